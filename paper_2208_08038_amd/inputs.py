@@ -1,0 +1,381 @@
+"""Seeded synthetic workloads shaped like the paper's test cases.
+
+This module only *describes* runs and draws their random initial states; it
+holds none of the method's arithmetic (no push, shape, deposit, field
+update or initial momentum split).  Both the HIP library binding and the
+FP64 oracle consume the objects defined here, and nothing else is shared
+between them.
+
+Units are the normalised ones of the library: c = eps0 = e = m_e = 1 and
+laser angular frequency 1, so the laser wavelength is 2 pi, densities are
+in units of the critical density and E in units of m_e c omega / e (a plane
+wave of normalised amplitude a0 has |E| = a0).
+
+Workloads (the paper's cases as restated for this project):
+  neutral_medium_1d   laser in a neutral bound-electron medium, Sec. 3.1
+  bragg_2d            x-ray Bragg scattering from a rotated lattice, Sec. 3.2
+  ionised_slab_3d     3D partially ionised slab with free electrons
+  mixed_precision_3d  Bragg-geometry 3D slab, 4 ions per cell
+  neutral_slab_2d     2D neutral slab (the differentiation workload's forward run)
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+PERIODIC, OPEN, LASER = 0, 1, 2
+POINT, TWO_BODY = 0, 1
+
+# physical constants (CODATA 2018)
+ME_C2_EV = 510998.95            # electron rest energy, eV
+AMU_IN_ME = 1822.888486209      # atomic mass unit in electron masses
+AU_MASS_AMU = 196.966570        # gold
+R_E_M = 2.8179403262e-15        # classical electron radius, m
+HC_EV_NM = 1239.84198           # h c in eV nm
+
+TWO_PI = 2.0 * math.pi
+BASE_SEED = 20220808
+
+
+@dataclass
+class Laser:
+    """Laser entering through x-min: E_inc = a0 sin^2(pi t'/t_env) sin(omega t' + phase),
+    t' = t - t_delay - x, times exp(-r_perp^2 / waist^2) when waist > 0."""
+    a0: float = 0.0
+    omega: float = 1.0
+    t_env: float = 0.0
+    waist: float = 0.0
+    yc: float = 0.0
+    zc: float = 0.0
+    phase: float = 0.0
+    t_delay: float = 0.0
+    pol: int = 1  # 1: E along y, 2: E along z
+
+
+@dataclass
+class Grid:
+    ndim: int
+    n: Tuple[int, int, int]
+    dx: Tuple[float, float, float]
+    dt: float
+    bc_lo: Tuple[int, int, int] = (PERIODIC, PERIODIC, PERIODIC)
+    bc_hi: Tuple[int, int, int] = (PERIODIC, PERIODIC, PERIODIC)
+    pad: int = 3
+    laser: Laser = field(default_factory=Laser)
+    re_norm: float = 0.0  # 2 pi r_e / lambda_laser, for a_c = 0 species
+
+    @property
+    def ncell(self) -> int:
+        return int(np.prod(self.n[: self.ndim]))
+
+
+@dataclass
+class Species:
+    """Real-particle charges/masses (units e, m_e).  A point species uses q1, m1.
+    a_c: softening length; 0 derives it from omega_c and the grid's re_norm;
+    math.inf selects the exact harmonic bond."""
+    kind: int
+    q1: float
+    m1: float
+    q2: float = 0.0
+    m2: float = 0.0
+    weight: float = 1.0
+    omega_c: float = 0.0
+    a_c: float = 0.0
+    nu: float = 0.0
+    nu_per_omega: float = 0.0
+    name: str = ""
+
+
+@dataclass
+class Particles:
+    x: np.ndarray                       # (n, ndim) positions, centre of mass for two-body
+    u1: np.ndarray                      # (n, 3) momentum per mass (centre of mass if u2 is None)
+    delta: Optional[np.ndarray] = None  # (n, 3) r1 - r2
+    u2: Optional[np.ndarray] = None     # (n, 3)
+    omega_c: Optional[np.ndarray] = None
+    weight: Optional[np.ndarray] = None
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[0])
+
+
+@dataclass
+class Workload:
+    name: str
+    grid: Grid
+    species: List[Tuple[Species, Particles]]
+    steps: int
+    precision: int = 64
+    probes: List[Tuple[int, Tuple[int, int, int]]] = field(default_factory=list)
+    notes: str = ""
+
+    @property
+    def n_particles(self) -> int:
+        return sum(p.n for _, p in self.species)
+
+
+def rng_for(config_id: int, stream: int = 0) -> np.random.Generator:
+    """Counter-based Philox stream keyed by (seed + config id, stream)."""
+    return np.random.Generator(np.random.Philox(key=[BASE_SEED + config_id, stream]))
+
+
+def gold_ion(z_bound: int, q_c: float):
+    """Two-body gold macro-ion charges/masses: q2 = -Z_b, m2 = Z_b, q1 = q_c - q2, m1 = m_c - m2."""
+    m_c = AU_MASS_AMU * AMU_IN_ME
+    q2, m2 = -float(z_bound), float(z_bound)
+    return q_c - q2, m_c - m2, q2, m2
+
+
+def bound_plasma_density(q1, m1, q2, m2, omega_pb):
+    """Ion density for which the bound-oscillator plasma frequency
+    omega_pb^2 = n q_r^2 / m_r takes the requested value (workload recipe)."""
+    mc = m1 + m2
+    m_r = m1 * m2 / mc
+    q_r = (q1 * m2 - q2 * m1) / mc
+    return omega_pb ** 2 * m_r / q_r ** 2
+
+
+def thermal_sigma(t_ev: float, mass_me: float) -> float:
+    """Standard deviation of u = p/(m c) per component for temperature t_ev."""
+    return math.sqrt(t_ev / (mass_me * ME_C2_EV))
+
+
+def stratified_positions(rng, lo, hi, ppc, dx, ndim):
+    """ppc particles per cell over cells lo..hi-1 (per dimension), cells
+    enumerated x fastest; each particle uniform within its own sub-stratum
+    along x (ppc slices) and uniform along the other dimensions."""
+    counts = [hi[d] - lo[d] for d in range(ndim)]
+    ncell = int(np.prod(counts))
+    n = ncell * ppc
+    idx = np.arange(ncell, dtype=np.int64)
+    cell = np.empty((ncell, ndim), dtype=np.int64)
+    rem = idx.copy()
+    for d in range(ndim):
+        cell[:, d] = lo[d] + rem % counts[d]
+        rem //= counts[d]
+    cell = np.repeat(cell, ppc, axis=0)
+    sub = np.tile(np.arange(ppc, dtype=np.float64), ncell)
+    x = np.empty((n, ndim), dtype=np.float64)
+    ux = rng.random(n)
+    x[:, 0] = (cell[:, 0] + (sub + ux) / ppc) * dx[0]
+    for d in range(1, ndim):
+        x[:, d] = (cell[:, d] + rng.random(n)) * dx[d]
+    return x
+
+
+def _probe_list(ndim, comp, cells):
+    out = []
+    for c in cells:
+        idx = [0, 0, 0]
+        for d in range(ndim):
+            idx[d] = int(c[d]) if isinstance(c, (tuple, list)) else (int(c) if d == 0 else 0)
+        out.append((comp, tuple(idx)))
+    return out
+
+
+# --------------------------------------------------------------------------
+# Case 1: laser in a neutral bound-electron medium (Sec. 3.1), 1D, FP64
+# --------------------------------------------------------------------------
+
+def neutral_medium_1d(cells: int = 2048, ppc: int = 8, steps: int = 1000,
+                      omega_c: float = 3.0, omega_pb: float = 0.9, a0: float = 1e-3,
+                      t_ev: float = 1.0, cycles: int = 10, a_c: float = 0.0,
+                      probes=(32, 224), config_id: int = 1) -> Workload:
+    dx = TWO_PI / 64.0
+    dt = 0.98 * dx
+    lam_m = 12.4e-9  # 0.1 keV photons, as in Sec. 3.1
+    laser = Laser(a0=a0, omega=1.0, t_env=cycles * TWO_PI, pol=1)
+    grid = Grid(1, (cells, 1, 1), (dx, 1.0, 1.0), dt, (LASER, PERIODIC, PERIODIC),
+                (OPEN, PERIODIC, PERIODIC), pad=3, laser=laser,
+                re_norm=TWO_PI * R_E_M / lam_m)
+    q1, m1, q2, m2 = gold_ion(78, 0.0)
+    n_ion = bound_plasma_density(q1, m1, q2, m2, omega_pb)
+    w = n_ion * dx / ppc
+    sp = Species(TWO_BODY, q1, m1, q2, m2, weight=w, omega_c=omega_c, a_c=a_c, name="Au_Zb78")
+    rng = rng_for(config_id)
+    pad = grid.pad
+    x = stratified_positions(rng, [pad], [cells - pad], ppc, grid.dx, 1)
+    n = x.shape[0]
+    sig = thermal_sigma(t_ev, m1 + m2)
+    uc = rng.normal(0.0, sig, size=(n, 3))
+    parts = Particles(x=x, u1=uc)
+    return Workload("neutral_medium_1d", grid, [(sp, parts)], steps, 64,
+                    probes=_probe_list(1, 1, list(probes)),
+                    notes=f"{n} two-body ions, omega_c={omega_c}, omega_pb={omega_pb}")
+
+
+# --------------------------------------------------------------------------
+# Case 2: Bragg scattering from a rotated square lattice (Sec. 3.2), 2D
+# --------------------------------------------------------------------------
+
+def bragg_2d(cells: int = 4096, slab: int = 1024, steps: int = 4000, d_over_lambda: float = 1.5,
+             omega_c: float = 0.5, a0: float = 1e-4, cycles: int = 20,
+             waist_lambda: float = 12.0, jitter: float = 0.01, precision: int = 64,
+             weight_scale: float = 1.0, config_id: int = 2) -> Workload:
+    dx = TWO_PI / 32.0
+    dt = 0.98 * dx / math.sqrt(2.0)
+    lam = TWO_PI
+    d = d_over_lambda * lam
+    # gold lattice constant d = n^{-1/3} = 0.2569 nm fixes the laser wavelength
+    d_m = (5.9e28) ** (-1.0 / 3.0)
+    lam_m = d_m / d_over_lambda
+    re_norm = TWO_PI * R_E_M / lam_m
+    theta_b = math.asin(lam / (2.0 * d))
+    Ly = cells * dx
+    laser = Laser(a0=a0, omega=1.0, t_env=cycles * TWO_PI, waist=waist_lambda * lam,
+                  yc=0.5 * Ly, pol=1)
+    grid = Grid(2, (cells, cells, 1), (dx, dx, 1.0), dt, (LASER, OPEN, PERIODIC),
+                (OPEN, OPEN, PERIODIC), pad=3, laser=laser, re_norm=re_norm)
+    q1, m1, q2, m2 = gold_ion(78, 0.0)
+    # one site = one column of atoms along z with spacing d: 1/d atoms per unit
+    # length, i.e. 4 pi re_norm / d in units of n_c (c/omega)^2
+    w = weight_scale * 4.0 * math.pi * re_norm / d
+    sp = Species(TWO_BODY, q1, m1, q2, m2, weight=w, omega_c=omega_c, a_c=0.0, name="Au_lattice")
+    rng = rng_for(config_id)
+    c0 = 0.5 * cells * dx
+    half = 0.5 * slab * dx
+    m = int(math.ceil(2.0 * half * math.sqrt(2.0) / d)) + 2
+    ii, jj = np.meshgrid(np.arange(-m, m + 1), np.arange(-m, m + 1), indexing="ij")
+    a = ii.ravel() * d
+    b = jj.ravel() * d
+    ct, st = math.cos(theta_b), math.sin(theta_b)
+    xs = c0 + a * ct - b * st
+    ys = c0 + a * st + b * ct
+    keep = (np.abs(xs - c0) < half) & (np.abs(ys - c0) < half)
+    xs, ys = xs[keep], ys[keep]
+    n = xs.size
+    xs = xs + rng.normal(0.0, jitter * d, n)
+    ys = ys + rng.normal(0.0, jitter * d, n)
+    x = np.stack([xs, ys], axis=1)
+    parts = Particles(x=x, u1=np.zeros((n, 3)))
+    return Workload("bragg_2d", grid, [(sp, parts)], steps, precision,
+                    notes=f"{n} lattice sites, d={d_over_lambda} lambda, theta_B={theta_b:.6f}")
+
+
+# --------------------------------------------------------------------------
+# Case 3: 3D partially ionised slab with free electrons
+# --------------------------------------------------------------------------
+
+def ionised_slab_3d(n=(512, 256, 256), ppc: int = 8, steps: int = 500, precision: int = 32,
+                    omega_pb: float = 0.9, a0: float = 0.05, waist_lambda: float = 8.0,
+                    cycles: int = 10, wc_range=(1.5, 4.0), nu_per_omega: float = 0.01,
+                    t_ion_ev: float = 1.0, t_e_ev: float = 10.0, electrons: bool = True,
+                    config_id: int = 3) -> Workload:
+    dx = TWO_PI / 24.0
+    dt = 0.98 * dx / math.sqrt(3.0)
+    lam_m = 12.4e-9
+    ny, nz = n[1], n[2]
+    laser = Laser(a0=a0, omega=1.0, t_env=cycles * TWO_PI, waist=waist_lambda * TWO_PI,
+                  yc=0.5 * ny * dx, zc=0.5 * nz * dx, pol=1)
+    grid = Grid(3, tuple(n), (dx, dx, dx), dt, (LASER, PERIODIC, PERIODIC),
+                (OPEN, PERIODIC, PERIODIC), pad=3, laser=laser,
+                re_norm=TWO_PI * R_E_M / lam_m)
+    q1, m1, q2, m2 = gold_ion(78, 1.0)
+    n_ion = bound_plasma_density(q1, m1, q2, m2, omega_pb)
+    dv = dx ** 3
+    w = n_ion * dv / ppc
+    ion = Species(TWO_BODY, q1, m1, q2, m2, weight=w, omega_c=0.5 * sum(wc_range), a_c=0.0,
+                  nu_per_omega=nu_per_omega, name="Au_q1")
+    rng_i = rng_for(config_id, 0)
+    lo = [grid.pad, 0, 0]
+    hi = [n[0] - grid.pad, ny, nz]
+    xi = stratified_positions(rng_i, lo, hi, ppc, grid.dx, 3)
+    ni = xi.shape[0]
+    uci = rng_i.normal(0.0, thermal_sigma(t_ion_ev, m1 + m2), size=(ni, 3))
+    wci = rng_i.uniform(wc_range[0], wc_range[1], size=ni)
+    species = [(ion, Particles(x=xi, u1=uci, omega_c=wci))]
+    if electrons:
+        ele = Species(POINT, -1.0, 1.0, weight=w, name="e")
+        rng_e = rng_for(config_id, 1)
+        xe = stratified_positions(rng_e, lo, hi, ppc, grid.dx, 3)
+        ue = rng_e.normal(0.0, thermal_sigma(t_e_ev, 1.0), size=(xe.shape[0], 3))
+        species.append((ele, Particles(x=xe, u1=ue)))
+    return Workload("ionised_slab_3d", grid, species, steps, precision,
+                    notes=f"{ni} two-body ions (+{ni if electrons else 0} electrons)")
+
+
+# --------------------------------------------------------------------------
+# Case 4: mixed-precision study, Bragg geometry in 3D, 4 ions per cell
+# --------------------------------------------------------------------------
+
+def mixed_precision_3d(n=(1024, 1024, 512), slab=(384, 640), ppc: int = 4, steps: int = 2000,
+                       omega_c: float = 0.5, d_over_lambda: float = 1.5, sigma_site: float = 0.1,
+                       a0: float = 1e-4, cycles: int = 20, precision: int = 32,
+                       config_id: int = 4) -> Workload:
+    dx = TWO_PI / 32.0
+    dt = 0.98 * dx / math.sqrt(3.0)
+    lam = TWO_PI
+    d = d_over_lambda * lam
+    d_m = (5.9e28) ** (-1.0 / 3.0)
+    lam_m = d_m / d_over_lambda
+    re_norm = TWO_PI * R_E_M / lam_m
+    theta_b = math.asin(lam / (2.0 * d))
+    laser = Laser(a0=a0, omega=1.0, t_env=cycles * TWO_PI, waist=12.0 * lam,
+                  yc=0.5 * n[1] * dx, zc=0.5 * n[2] * dx, pol=1)
+    grid = Grid(3, tuple(n), (dx, dx, dx), dt, (LASER, PERIODIC, PERIODIC),
+                (OPEN, PERIODIC, PERIODIC), pad=3, laser=laser, re_norm=re_norm)
+    q1, m1, q2, m2 = gold_ion(78, 0.0)
+    # mean density one atom per d^3 = 4 pi re_norm / d^3 in units of n_c, modulated
+    # by Gaussian sites of the rotated lattice so the Bragg structure survives
+    n_mean = 4.0 * math.pi * re_norm / d ** 3
+    dv = dx ** 3
+    sp = Species(TWO_BODY, q1, m1, q2, m2, weight=n_mean * dv / ppc, omega_c=omega_c, a_c=0.0,
+                 name="Au_lattice3d")
+    rng = rng_for(config_id)
+    lo = [max(slab[0], grid.pad), 0, 0]
+    hi = [min(slab[1], n[0] - grid.pad), n[1], n[2]]
+    x = stratified_positions(rng, lo, hi, ppc, grid.dx, 3)
+    ct, st = math.cos(theta_b), math.sin(theta_b)
+    a = x[:, 0] * ct + x[:, 1] * st
+    b = -x[:, 0] * st + x[:, 1] * ct
+    da = (a / d) - np.round(a / d)
+    db = (b / d) - np.round(b / d)
+    mod = np.exp(-(da ** 2 + db ** 2) / (2.0 * sigma_site ** 2))
+    wts = sp.weight * mod / mod.mean()
+    parts = Particles(x=x, u1=np.zeros((x.shape[0], 3)), weight=wts)
+    return Workload("mixed_precision_3d", grid, [(sp, parts)], steps, precision,
+                    notes=f"{x.shape[0]} two-body ions, lattice-modulated weights")
+
+
+# --------------------------------------------------------------------------
+# Case 5: 2D neutral slab (forward run of the differentiation workload)
+# --------------------------------------------------------------------------
+
+def neutral_slab_2d(n=(2048, 1024), slab=(512, 1536), ppc: int = 16, steps: int = 1024,
+                    omega_c: float = 3.0, omega_pb: float = 0.9, nu_per_omega: float = 0.01,
+                    a0: float = 1e-3, cycles: int = 20, precision: int = 32,
+                    config_id: int = 5) -> Workload:
+    dx = TWO_PI / 32.0
+    dt = 0.98 * dx / math.sqrt(2.0)
+    lam_m = 12.4e-9
+    laser = Laser(a0=a0, omega=1.0, t_env=cycles * TWO_PI, waist=0.25 * n[1] * dx,
+                  yc=0.5 * n[1] * dx, pol=1)
+    grid = Grid(2, (n[0], n[1], 1), (dx, dx, 1.0), dt, (LASER, PERIODIC, PERIODIC),
+                (OPEN, PERIODIC, PERIODIC), pad=3, laser=laser,
+                re_norm=TWO_PI * R_E_M / lam_m)
+    q1, m1, q2, m2 = gold_ion(78, 0.0)
+    n_ion = bound_plasma_density(q1, m1, q2, m2, omega_pb)
+    w = n_ion * dx * dx / ppc
+    sp = Species(TWO_BODY, q1, m1, q2, m2, weight=w, omega_c=omega_c, a_c=0.0,
+                 nu_per_omega=nu_per_omega, name="Au_slab2d")
+    rng = rng_for(config_id)
+    lo = [max(slab[0], grid.pad), 0]
+    hi = [min(slab[1], n[0] - grid.pad), n[1]]
+    x = stratified_positions(rng, lo, hi, ppc, grid.dx, 2)
+    parts = Particles(x=x, u1=rng.normal(0.0, thermal_sigma(1.0, m1 + m2), size=(x.shape[0], 3)))
+    return Workload("neutral_slab_2d", grid, [(sp, parts)], steps, precision,
+                    notes=f"{x.shape[0]} two-body ions")
+
+
+WORKLOADS = {
+    "neutral_medium_1d": neutral_medium_1d,
+    "bragg_2d": bragg_2d,
+    "ionised_slab_3d": ionised_slab_3d,
+    "mixed_precision_3d": mixed_precision_3d,
+    "neutral_slab_2d": neutral_slab_2d,
+}

@@ -1,0 +1,667 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle through an independent route (closed forms,
+invariants, paper-printed numbers, potential minimisation, moments of the
+B-spline), so that a dropped term, wrong sign, wrong stagger or transposed
+operand in the oracle fails at least one of them.  CPU only.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2208_08038_amd.inputs import (
+    LASER, OPEN, PERIODIC, POINT, TWO_BODY, Grid, Laser, Particles, Species, neutral_medium_1d)
+from oracle import Oracle, ac_from_omega, split_momentum
+from oracle.oracle import CHARGE_CHECK, FROZEN_FIELDS, NO_DEPOSIT
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_numbers.json")
+INF = math.inf
+
+
+def _grid(ndim, n, dx, dt, bc=PERIODIC, **kw):
+    n3 = tuple(list(n) + [1] * (3 - len(n)))
+    dx3 = tuple(list(dx) + [1.0] * (3 - len(dx)))
+    bcs = tuple([bc] * ndim + [PERIODIC] * (3 - ndim))
+    return Grid(ndim, n3, dx3, dt, bcs, bcs, **kw)
+
+
+def _uniform(o, E0=(0, 0, 0), B0=(0, 0, 0)):
+    E = np.tile(np.asarray(E0, float)[:, None], (1, o.ncell))
+    B = np.tile(np.asarray(B0, float)[:, None], (1, o.ncell))
+    o.load_fields(E, B)
+
+
+def _pos(o, sid, p=0):
+    st = o.particles(sid)
+    return (st["cell"][p] + st["off"][p]) * np.asarray(o.grid.dx[: o.ndim]), st
+
+
+# ---------------------------------------------------------------- Yee (T1)
+
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_yee_discrete_eigenmode(oracle_built, ndim):
+    """Vacuum Yee: a standing mode with B = 0 evolves as cos(w_d n dt) with
+    sin(w_d dt/2) = dt sqrt(sum_d (sin(k_d dx_d/2)/dx_d)^2)."""
+    n = {1: (24,), 2: (20, 12), 3: (12, 10, 8)}[ndim]
+    dx = {1: (0.3,), 2: (0.3, 0.25), 3: (0.3, 0.25, 0.2)}[ndim]
+    cfl = 1.0 / math.sqrt(sum(1.0 / d ** 2 for d in dx))
+    dt = 0.9 * cfl
+    g = _grid(ndim, n, dx, dt)
+    o = Oracle(g)
+    kd = min(ndim, 2)  # the mode varies along x (and y); E_z is uniform along z
+    modes = (3, 2)[:kd]
+    k = [2 * math.pi * modes[d] / (n[d] * dx[d]) for d in range(kd)]
+    shape = tuple(list(n) + [1] * (3 - ndim))
+    ii = np.meshgrid(*[np.arange(s) for s in shape], indexing="ij")
+    E = np.zeros((3,) + shape)
+    if ndim == 1:
+        comp, phase = 1, k[0] * ii[0] * dx[0]          # E_y at x = i dx
+    else:
+        comp = 2                                         # E_z at (i dx, j dy)
+        phase = sum(k[d] * ii[d] * dx[d] for d in range(2))
+    E[comp] = np.cos(phase)
+    Ef = E.transpose(0, 3, 2, 1).reshape(3, -1)         # x fastest
+    o.load_fields(Ef, np.zeros_like(Ef))
+    Om2 = sum((2.0 / dx[d] * math.sin(k[d] * dx[d] / 2)) ** 2 for d in range(kd))
+    wd = 2.0 / dt * math.asin(dt * math.sqrt(Om2) / 2)
+    nsteps = 157
+    o.step(nsteps)
+    E1, B1, _ = o.fields()
+    expect = math.cos(wd * nsteps * dt) * Ef[comp]
+    assert np.max(np.abs(E1[comp] - expect)) < 1e-11
+    # the continuum frequency c|k| is measurably wrong at this resolution
+    wc = math.sqrt(sum(kk * kk for kk in k))
+    assert np.max(np.abs(math.cos(wc * nsteps * dt) * Ef[comp] - E1[comp])) > 1e-4
+    # other E components stay zero
+    for c in range(3):
+        if c != comp:
+            assert np.max(np.abs(E1[c])) < 1e-12
+
+
+def test_vacuum_energy_bounded(oracle_built):
+    """Periodic vacuum box: discrete field energy stays bounded (no drift)."""
+    g = _grid(2, (16, 16), (0.2, 0.2), 0.1)
+    o = Oracle(g)
+    rng = np.random.default_rng(7)
+    E = rng.normal(size=(3, 256)) * 1e-2
+    E[0] = 0.0
+    E[1] = 0.0
+    o.load_fields(E, np.zeros_like(E))
+    e0 = o.diagnostics()["field_energy"]
+    es = []
+    for _ in range(40):
+        o.step(25)
+        es.append(o.diagnostics()["field_energy"])
+    es = np.array(es)
+    assert np.all(np.abs(es / e0 - 1.0) < 0.3)
+    assert abs(es[-10:].mean() / es[:10].mean() - 1.0) < 0.05
+
+
+# -------------------------------------------------------------- gather
+
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_gather_reproduces_linear_fields_with_stagger(oracle_built, ndim):
+    """The quadratic B-spline reproduces constants and linear functions
+    exactly; each component is sampled at its own Yee stagger."""
+    n = (10, 9, 8)[:ndim]
+    dx = (0.5, 0.4, 0.3)[:ndim]
+    g = _grid(ndim, n, dx, 0.05)
+    o = Oracle(g)
+    shape = tuple(list(n) + [1] * (3 - ndim))
+    ii = np.meshgrid(*[np.arange(s, dtype=float) for s in shape], indexing="ij")
+    stag_e = [(1, 0, 0), (0, 1, 0), (0, 0, 1)]
+    stag_b = [(0, 1, 1), (1, 0, 1), (1, 1, 0)]
+    coef = np.array([[0.7, -1.3, 0.4], [1.1, 0.2, -0.6], [-0.5, 0.9, 1.7],
+                     [0.3, 0.8, -1.1], [-0.9, 0.1, 0.6], [1.4, -0.7, 0.2]])
+    consts = np.array([0.1, -0.2, 0.3, 0.05, -0.15, 0.25])
+
+    def lin(c, st):
+        v = np.full(shape, consts[c])
+        for d in range(ndim):
+            v = v + coef[c, d] * (ii[d] + 0.5 * st[d]) * dx[d]
+        return v.transpose(2, 1, 0).ravel()
+
+    E = np.stack([lin(a, stag_e[a]) for a in range(3)])
+    B = np.stack([lin(3 + a, stag_b[a]) for a in range(3)])
+    o.load_fields(E, B)
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        cell = [int(rng.integers(3, n[d] - 3)) for d in range(ndim)]
+        off = rng.random(ndim)
+        e, b = o.gather(cell, off)
+        pos = [(cell[d] + off[d]) * dx[d] for d in range(ndim)]
+        for a in range(3):
+            ee = consts[a] + sum(coef[a, d] * pos[d] for d in range(ndim))
+            bb = consts[3 + a] + sum(coef[3 + a, d] * pos[d] for d in range(ndim))
+            assert abs(e[a] - ee) < 1e-13
+            assert abs(b[a] - bb) < 1e-13
+
+
+def test_gather_quadratic_moment(oracle_built):
+    """Second moment of the quadratic B-spline: sum_i S(xi - i) i^2 = xi^2 + 1/4."""
+    g = _grid(1, (12,), (1.0,), 0.1)
+    o = Oracle(g)
+    i = np.arange(12, dtype=float)
+    E = np.zeros((3, 12))
+    E[1] = i ** 2            # E_y on integer nodes
+    o.load_fields(E, np.zeros_like(E))
+    for xi in [4.0, 4.25, 4.5, 4.75, 5.9999]:
+        c = int(math.floor(xi))
+        e, _ = o.gather([c], [xi - c])
+        assert abs(e[1] - (xi * xi + 0.25)) < 1e-12
+
+
+# ------------------------------------------------------------- Boris (T2)
+
+def _one_point(grid, q, m, x, u, flags=FROZEN_FIELDS | NO_DEPOSIT):
+    o = Oracle(grid, flags=flags)
+    sid = o.add_species(Species(POINT, q, m, weight=1.0), 1)
+    o.load_particles(sid, Particles(x=np.array([x], float), u1=np.array([u], float)))
+    return o, sid
+
+
+def test_boris_pure_electric(oracle_built):
+    """B = 0: u^{n+1/2} = u^{-1/2} + (n+1) dt (q/m) E exactly, and the position
+    advances by dt u/gamma each step (Sec. 2 update with t = s = 0)."""
+    g = _grid(1, (64,), (0.5,), 0.2)
+    E0 = np.array([2e-3, -1e-3, 5e-4])
+    q, m = -1.0, 1.0
+    o, sid = _one_point(g, q, m, [10.3], [0, 0, 0])
+    _uniform(o, E0)
+    x = 10.3
+    for n in range(60):
+        o.step(1)
+        st = o.particles(sid)
+        u = st["u1"][0]
+        uexp = (n + 1) * g.dt * (q / m) * E0
+        assert np.allclose(u, uexp, rtol=1e-13, atol=1e-18)
+        x += g.dt * uexp[0] / math.sqrt(1.0 + uexp @ uexp)
+        xn = (st["cell"][0, 0] + st["off"][0, 0]) * g.dx[0]
+        assert abs(xn - x) < 1e-12
+
+
+def test_boris_pure_magnetic_rotation(oracle_built):
+    """E = 0: |u| is conserved and u turns by 2 atan(|t|) per step,
+    t = (q dt/2m) B / gamma, in the sense of q v x B."""
+    g = _grid(1, (64,), (0.5,), 0.3)
+    B0 = np.array([0.0, 0.0, 1.7])
+    q, m = -1.0, 1.0
+    u0 = np.array([0.4, 0.0, 0.1])
+    o, sid = _one_point(g, q, m, [10.0], u0)
+    _uniform(o, (0, 0, 0), B0)
+    gam = math.sqrt(1 + u0 @ u0)
+    tmag = abs(q / m * 0.5 * g.dt * B0[2] / gam)
+    ang = 2 * math.atan(tmag)
+    prev = u0
+    for _ in range(30):
+        o.step(1)
+        u = o.particles(sid)["u1"][0]
+        assert abs(np.linalg.norm(u) - np.linalg.norm(u0)) < 1e-14
+        assert abs(u[2] - u0[2]) < 1e-15
+        a0 = math.atan2(prev[1], prev[0])
+        a1 = math.atan2(u[1], u[0])
+        d = (a1 - a0 + math.pi) % (2 * math.pi) - math.pi
+        # q < 0 and B along +z: v x B for v = +x points to -y, times q < 0 -> +y
+        assert abs(d - ang) < 1e-13
+        prev = u
+
+
+def test_boris_exb_drift(oracle_built):
+    """Crossed E and B: a particle launched at the drift velocity E x B / B^2
+    keeps it (Boris is exact for the drift in the non-relativistic limit)."""
+    g = _grid(1, (4096,), (0.5,), 0.1)
+    E0, B0 = 1e-5, 0.2
+    vd = E0 / B0     # along +x for E along y, B along z
+    o, sid = _one_point(g, 1.0, 1.0, [100.0], [vd / math.sqrt(1 - vd * vd), 0, 0])
+    _uniform(o, (0, E0, 0), (0, 0, B0))
+    o.step(2000)
+    x1, st = _pos(o, sid)
+    assert abs((x1[0] - 100.0) / (2000 * g.dt) - vd) < 1e-6 * vd + 1e-14
+    assert abs(st["u1"][0][1]) < 1e-9
+
+
+# --------------------------------------------- bound oscillator (T3, T4)
+
+def _one_ion(grid, sp, x, u1=(0, 0, 0), u2=None, flags=FROZEN_FIELDS | NO_DEPOSIT, delta=None):
+    o = Oracle(grid, flags=flags)
+    sid = o.add_species(sp, 1)
+    u2a = None if u2 is None else np.array([u2], float)
+    da = None if delta is None else np.array([delta], float)
+    o.load_particles(sid, Particles(x=np.array([x], float), u1=np.array([u1], float),
+                                   u2=u2a, delta=da))
+    return o, sid
+
+
+def test_static_field_harmonic_oscillator(oracle_built):
+    """Harmonic bond (a_c -> inf), static E0: relative displacement follows
+    delta_n = d*[1 - cos(W n dt) + tan(W dt/2) sin(W n dt)] with
+    sin(W dt/2) = w_c dt/2 and d* = (q_r/m_r) E0 / w_c^2 (Sec. 3.1, w -> 0)."""
+    g = _grid(1, (32,), (0.1,), 0.05)
+    q1, m1, q2, m2 = 3.0, 50.0, -2.0, 2.0
+    wc = 2.0
+    sp = Species(TWO_BODY, q1, m1, q2, m2, weight=1.0, omega_c=wc, a_c=INF)
+    o, sid = _one_ion(g, sp, [1.234], u2=(0, 0, 0))
+    E0 = 1e-8
+    _uniform(o, (0, E0, 0))
+    mc = m1 + m2
+    qr_over_mr = (q1 * m2 - q2 * m1) / mc / (m1 * m2 / mc)
+    dstar = qr_over_mr * E0 / wc ** 2
+    W = 2.0 / g.dt * math.asin(wc * g.dt / 2)
+    for n in range(1, 401):
+        o.step(1)
+        st = o.particles(sid)
+        dn = dstar * (1 - math.cos(W * n * g.dt) + math.tan(W * g.dt / 2) * math.sin(W * n * g.dt))
+        assert abs(st["delta"][0, 1] - dn) < 1e-9 * dstar
+        # total momentum grows as (q1 + q2) E0 t
+        p = m1 * st["u1"][0, 1] + m2 * st["u2"][0, 1]
+        assert abs(p - (q1 + q2) * E0 * n * g.dt) < 1e-13 * abs((q1 + q2) * E0 * n * g.dt) + 1e-25
+
+
+def test_softened_bond_equilibrium_minimises_potential(oracle_built):
+    """Damped bond in a static field settles where the paper's potential
+    V_M = q1 q2 r_e / sqrt(r^2 + a_c^2) minus the field work q_r E r is
+    minimal; a_c derives from w_c through w_c^2 = |q1 q2| r_e/(m_r a_c^3)."""
+    from scipy.optimize import minimize_scalar
+    re = 1e-3
+    g = _grid(1, (32,), (1.0,), 0.05, re_norm=re)
+    q1, m1, q2, m2 = 3.0, 50.0, -2.0, 2.0
+    wc, nu = 2.0, 1.0
+    sp = Species(TWO_BODY, q1, m1, q2, m2, weight=1.0, omega_c=wc, a_c=0.0, nu=nu)
+    mc = m1 + m2
+    mr = m1 * m2 / mc
+    a_c = (abs(q1 * q2) * re / (mr * wc ** 2)) ** (1.0 / 3.0)
+    q_r = (q1 * m2 - q2 * m1) / mc
+    # a field below the softened bond's maximum restoring force puts the
+    # minimum near 0.42 a_c, where the bond is far from harmonic
+    E0 = 0.33 * abs(q1 * q2) * re / (q_r * a_c ** 2)
+
+    def U(r):
+        return q1 * q2 * re / math.sqrt(r * r + a_c * a_c) - q_r * E0 * r
+
+    # the bound state is the local minimum inside the inflection point a_c/sqrt(2)
+    r_eq = minimize_scalar(U, bounds=(0.0, a_c / math.sqrt(2.0)), method="bounded",
+                           options={"xatol": 1e-14}).x
+    assert 0.3 * a_c < r_eq < 0.6 * a_c
+    o, sid = _one_ion(g, sp, [10.5], u2=(0, 0, 0))
+    _uniform(o, (0, E0, 0))
+    o.step(2000)
+    d = o.particles(sid)["delta"][0, 1]
+    assert abs(d - r_eq) < 1e-7 * a_c
+    # the harmonic (linearised) bond would sit visibly elsewhere
+    assert abs(q_r * E0 / (mr * wc ** 2) - r_eq) > 0.05 * a_c
+
+
+def test_driven_damped_oscillator_response(oracle_built):
+    """Uniform drive E0 cos(w t): after the transient, the nucleus and the
+    cloud follow the Sec. 3.1 response
+      r1 = [-q_c/(m_c W^2) + (m2/m_c) q_r/(m_r D)] E,
+      r2 = [-q_c/(m_c W^2) - (m1/m_c) q_r/(m_r D)] E,
+    with the leapfrog frequency W = (2/dt) sin(w dt/2) and
+    D = w_c^2 - W^2 + i nu sin(w dt)/dt (the time-centred friction);
+    D -> w_c^2 - w^2 as dt -> 0 and nu -> 0."""
+    g = _grid(1, (64,), (1.0,), 0.05)
+    q1, m1, q2, m2 = 4.0, 60.0, -3.0, 3.0      # charged ion, q_c = 1
+    wc, nu, w = 2.0, 0.4, 1.3
+    sp = Species(TWO_BODY, q1, m1, q2, m2, weight=1.0, omega_c=wc, a_c=INF, nu=nu)
+    mc, qc = m1 + m2, q1 + q2
+    mr = m1 * m2 / mc
+    qr = (q1 * m2 - q2 * m1) / mc
+    dt = g.dt
+    W2 = (2.0 / dt * math.sin(w * dt / 2)) ** 2
+    D = wc ** 2 - W2 + 1j * nu * math.sin(w * dt) / dt
+    E0 = 1e-7
+    K = qc / mc * E0 / W2
+    x0 = 30.0
+    # launch the centre of mass on its periodic orbit: R_n = x0 - K cos(w n dt)
+    uc = -K * (1.0 - math.cos(w * dt)) / dt
+    o, sid = _one_ion(g, sp, [x0 - K], u1=(uc, 0, 0))
+    c1 = -qc / (mc * W2) + (m2 / mc) * qr / (mr * D)
+    c2 = -qc / (mc * W2) - (m1 / mc) * qr / (mr * D)
+    err1 = err2 = 0.0
+    nsteps = 4000
+    for n in range(nsteps):
+        E = E0 * math.cos(w * n * dt)
+        _uniform(o, (E, 0, 0))
+        o.step(1)
+        if n > nsteps - 200:
+            x, st = _pos(o, sid)
+            R = x[0]
+            dl = st["delta"][0, 0]
+            r1 = R + (m2 / mc) * dl
+            r2 = R - (m1 / mc) * dl
+            ph = np.exp(1j * w * (n + 1) * dt)
+            err1 = max(err1, abs(r1 - x0 - (c1 * E0 * ph).real))
+            err2 = max(err2, abs(r2 - x0 - (c2 * E0 * ph).real))
+    amp = abs(c2) * E0
+    assert err1 < 1e-6 * amp
+    assert err2 < 1e-6 * amp
+
+
+def test_split_initial_momentum(oracle_built):
+    """Sec. 2 initial condition: p1 + p2 = p_c and q1 v1 + q2 v2 = 0,
+    including a relativistic centre-of-mass momentum; p_c = 0 gives rest."""
+    q1, m1, q2, m2 = 79.0, 359000.0, -78.0, 78.0
+    for uc in [np.array([0.3, -0.2, 0.1]), np.array([1e-6, 2e-6, -3e-6]), np.zeros(3)]:
+        u1, u2 = split_momentum(q1, m1, q2, m2, uc)
+        v1 = u1 / math.sqrt(1 + u1 @ u1)
+        v2 = u2 / math.sqrt(1 + u2 @ u2)
+        pc = (m1 + m2) * uc
+        assert np.allclose(m1 * u1 + m2 * u2, pc, rtol=1e-12, atol=1e-300)
+        assert np.allclose(q1 * v1 + q2 * v2, 0.0, atol=1e-12 * max(1e-300, np.abs(q1 * v1).max()))
+    u1, u2 = split_momentum(1.0, 5.0, -1.0, 1.0, np.array([0.2, 0.0, 0.0]))
+    assert np.allclose(u1, [0.2, 0, 0]) and np.allclose(u2, [0.2, 0, 0])
+
+
+def test_isolated_pair_invariants(oracle_built):
+    """No external field: total momentum is conserved to round-off (also
+    with friction), and without friction the pair energy
+    sum m (gamma - 1) + V_M stays bounded."""
+    re = 1e-2
+    g = _grid(3, (12, 12, 12), (1.0, 1.0, 1.0), 0.05, re_norm=re)
+    q1, m1, q2, m2 = 2.0, 40.0, -1.0, 1.0
+    mc = m1 + m2
+    for nu in [0.0, 0.3]:
+        sp = Species(TWO_BODY, q1, m1, q2, m2, weight=1.0, omega_c=1.5, a_c=0.0, nu=nu)
+        a_c = ac_from_omega(q1, m1, q2, m2, 1.5, re)
+        o, sid = _one_ion(g, sp, [5.5, 6.1, 5.9], u1=(0.01, -0.02, 0.005),
+                          u2=(-0.05, 0.08, 0.02), delta=(0.05, -0.03, 0.02))
+        st = o.particles(sid)
+        p0 = m1 * st["u1"][0] + m2 * st["u2"][0]
+
+        def energy(st):
+            u1, u2, dl = st["u1"][0], st["u2"][0], st["delta"][0]
+            k = m1 * (math.sqrt(1 + u1 @ u1) - 1) + m2 * (math.sqrt(1 + u2 @ u2) - 1)
+            return k + q1 * q2 * re / math.sqrt(dl @ dl + a_c * a_c)
+
+        e0 = energy(st)
+        es = []
+        for _ in range(50):
+            o.step(20)
+            st = o.particles(sid)
+            p = m1 * st["u1"][0] + m2 * st["u2"][0]
+            assert np.allclose(p, p0, rtol=1e-13, atol=1e-15)
+            es.append(energy(st))
+        if nu == 0.0:
+            # kinetic (half step) and potential (full step) terms are sampled
+            # half a step apart, so the sum wobbles at O(dt); it must not drift
+            es = np.array(es)
+            scale = abs(e0 - q1 * q2 * re / a_c)
+            assert np.max(np.abs(es - e0)) < 0.05 * scale
+            assert abs(es[-10:].mean() - es[:10].mean()) < 0.01 * scale
+
+
+# ------------------------------------------ Esirkepov deposit (T5, T8)
+
+def _random_state(rng, ndim, n, shape, dx, pad=0, vmax=0.8):
+    lo = np.array([pad] * ndim, float)
+    hi = np.array([s - pad for s in shape[:ndim]], float)
+    x = (lo + (hi - lo) * rng.random((n, ndim))) * np.array(dx[:ndim])
+    u = rng.normal(size=(n, 3))
+    u *= (vmax / np.linalg.norm(u, axis=1))[:, None] * rng.random((n, 1))
+    u = u / np.sqrt(1 - np.sum(u * u, axis=1))[:, None]
+    return x, u
+
+
+@pytest.mark.parametrize("ndim,bc", [(1, PERIODIC), (2, PERIODIC), (3, PERIODIC), (1, OPEN),
+                                     (2, OPEN), (3, OPEN)])
+def test_charge_continuity_random_particles(oracle_built, ndim, bc):
+    """(rho^{n+1} - rho^n)/dt + div J^{n+1/2} = 0 to round-off for random
+    two-body ions and free particles, including cell crossings, wall
+    reflections and field-driven acceleration."""
+    rng = np.random.default_rng(11 + ndim + 10 * bc)
+    shape = (14, 12, 10)[:ndim]
+    dx = (0.3, 0.25, 0.2)[:ndim]
+    cfl = 1.0 / math.sqrt(sum(1.0 / d ** 2 for d in dx))
+    g = _grid(ndim, shape, dx, 0.95 * cfl, bc=bc, re_norm=1e-3)
+    o = Oracle(g, flags=FROZEN_FIELDS | CHARGE_CHECK)
+    nio, nel = 60, 40
+    pad = 3 if bc == OPEN else 0
+    xi, ui = _random_state(rng, ndim, nio, shape, dx, pad=pad, vmax=0.6)
+    sp = Species(TWO_BODY, 5.0, 30.0, -3.0, 3.0, weight=0.7, omega_c=0.5, a_c=0.0, nu=0.1)
+    sid = o.add_species(sp, nio)
+    delta = rng.uniform(-0.15, 0.15, size=(nio, 3)) * min(dx)
+    o.load_particles(sid, Particles(x=xi, u1=ui, u2=ui * 0.99, delta=delta,
+                                    omega_c=rng.uniform(0.5, 2, nio),
+                                    weight=rng.uniform(0.5, 1.5, nio)))
+    xe, ue = _random_state(rng, ndim, nel, shape, dx, pad=pad, vmax=0.95)
+    sid2 = o.add_species(Species(POINT, -1.0, 1.0, weight=1.3), nel)
+    o.load_particles(sid2, Particles(x=xe, u1=ue))
+    ncell = int(np.prod(shape))
+    o.load_fields(rng.normal(size=(3, ncell)) * 0.05, rng.normal(size=(3, ncell)) * 0.05)
+    for _ in range(3):
+        o.step(1)
+        d = o.diagnostics()
+        assert d["error_word"] == 0
+        assert d["rho_l2"] > 0
+        assert d["div_max"] < 1e-13 * d["rho_l2"]
+
+
+def _single_deposit(ndim, x, u, shape=(12, 12, 12), dx=(0.3, 0.3, 0.3), dt=0.1, q=-1.0, w=1.0):
+    g = _grid(ndim, shape[:ndim], dx[:ndim], dt)
+    o = Oracle(g, flags=FROZEN_FIELDS)
+    sid = o.add_species(Species(POINT, q, 1.0, weight=w), 1)
+    o.load_particles(sid, Particles(x=np.array([x], float), u1=np.array([u], float)))
+    x0, _ = _pos(o, sid)
+    o.step(1)
+    x1, _ = _pos(o, sid)
+    _, _, J = o.fields()
+    return J.reshape((3,) + tuple(reversed(shape[:ndim]))), x0, x1, o
+
+
+def test_esirkepov_total_current_is_charge_times_velocity():
+    """First moment of the shape: sum over nodes of J dV equals Q (x1 - x0)/dt
+    for each resolved component and Q v for unresolved ones."""
+    for ndim in (1, 2, 3):
+        u = np.array([0.31, -0.22, 0.17])
+        J, x0, x1, o = _single_deposit(ndim, [1.7, 1.9, 2.1][:ndim], u)
+        dV = 0.3 ** ndim
+        gam = math.sqrt(1 + u @ u)
+        for a in range(3):
+            tot = J[a].sum() * dV
+            if a < ndim:
+                expect = -1.0 * (x1[a] - x0[a]) / 0.1
+            else:
+                expect = -1.0 * u[a] / gam
+            assert abs(tot - expect) < 1e-13
+
+
+def test_esirkepov_axis_motion_and_symmetry():
+    """Motion along x alone gives no transverse current; exchanging the
+    x and y axes of the motion exchanges J_x and J_y (3D)."""
+    J, _, _, _ = _single_deposit(3, [1.7, 1.9, 2.1], [0.5, 0.0, 0.0])
+    assert np.abs(J[1]).max() == 0.0 and np.abs(J[2]).max() == 0.0
+    assert np.abs(J[0]).max() > 0
+    Ja, *_ = _single_deposit(3, [1.62, 1.93, 2.11], [0.4, -0.3, 0.2])
+    Jb, *_ = _single_deposit(3, [1.93, 1.62, 2.11], [-0.3, 0.4, 0.2])
+    # arrays are (comp, z, y, x); swapping x <-> y transposes the last two axes
+    assert np.allclose(Ja[0], Jb[1].transpose(0, 2, 1), atol=1e-14)
+    assert np.allclose(Ja[2], Jb[2].transpose(0, 2, 1), atol=1e-14)
+    J0, *_ = _single_deposit(3, [1.7, 1.9, 2.1], [0.0, 0.0, 0.0])
+    assert np.abs(J0).max() == 0.0
+
+
+# ------------------------------------------------ laser and boundaries
+
+def test_laser_injection_and_open_boundary(oracle_built):
+    """Vacuum: the field at a probe follows the incident waveform
+    E_inc(t - x) (up to Yee dispersion) and leaves through the far Mur face."""
+    cells = 1200
+    dx = 2 * math.pi / 64
+    dt = 0.98 * dx
+    las = Laser(a0=1.0, omega=1.0, t_env=4 * 2 * math.pi, pol=1)
+    g = Grid(1, (cells, 1, 1), (dx, 1, 1), dt, (LASER, 0, 0), (OPEN, 0, 0), laser=las)
+    o = Oracle(g, max_probe_steps=2200)
+    o.set_probes([(1, (100, 0, 0)), (5, (100, 0, 0))])
+    emax = 0.0
+    for _ in range(22):
+        o.step(100)
+        emax = max(emax, o.diagnostics()["field_energy"])
+    pr = o.probes()
+    t = (np.arange(pr.shape[1]) + 1) * dt
+    tau = t - 100 * dx
+    env = np.where((tau >= 0) & (tau <= las.t_env), np.sin(np.pi * tau / las.t_env) ** 2, 0.0)
+    einc = env * np.sin(tau)
+    assert np.max(np.abs(pr[0] - einc)) < 3e-3
+    # B_z at (100.5) dx, half a step later in the staggered sense: same wave
+    tau_b = t - 100.5 * dx
+    env_b = np.where((tau_b >= 0) & (tau_b <= las.t_env),
+                     np.sin(np.pi * tau_b / las.t_env) ** 2, 0.0)
+    assert np.max(np.abs(pr[1] - env_b * np.sin(tau_b))) < 3e-3
+    assert o.diagnostics()["field_energy"] < 1e-5 * emax
+
+
+# ------------------------------------------ coupled: dispersion (T6)
+
+@pytest.mark.slow
+def test_lorentz_dispersion_neutral_medium(oracle_built):
+    """Full 1D neutral-medium case: the phase velocity measured from the DFT
+    at w_L of E_y at two probes 3 lambda apart matches the medium's index
+    n^2 = 1 + w_pb^2/(w_c^2 - w^2) (Sec. 3.1 permittivity, neutral ions)."""
+    wl = neutral_medium_1d()
+    o = Oracle.from_workload(wl, max_probe_steps=wl.steps)
+    o.step(wl.steps)
+    pr = o.probes()
+    dt = wl.grid.dt
+    t = (np.arange(pr.shape[1]) + 1) * dt
+    F = (pr * np.exp(-1j * t)[None, :]).sum(axis=1)
+    (_, c0), (_, c1) = wl.probes
+    dist = (c1[0] - c0[0]) * wl.grid.dx[0]
+    dphi = (np.angle(F[0]) - np.angle(F[1])) % (2 * math.pi)
+    ncyc = math.floor(dist / (2 * math.pi))
+    n_meas = (dphi + 2 * math.pi * ncyc) / dist
+    n_theory = math.sqrt(1 + 0.81 / (9.0 - 1.0))
+    assert abs(n_meas - n_theory) < 2e-4
+    # a medium without the bound response (plain ions) would give n ~ 1
+    assert n_meas - 1.0 > 0.04
+    d = o.diagnostics()
+    assert d["error_word"] == 0
+
+
+# ------------------------------------------ paper-printed numbers (T10)
+
+def test_paper_printed_numbers(oracle_built):
+    gold = json.load(open(GOLDEN))
+    # resonance softening length: w_c = w_L at a_c ~ 9.5e-11 m (Sec. 3.1)
+    r = gold["resonance_softening_length"]
+    lam = r["lambda_m"]
+    re_norm = 2 * math.pi * 2.8179403262e-15 / lam
+    m_c = 196.96657 * 1822.888486209
+    q2, m2 = -float(r["z_bound"]), float(r["z_bound"])
+    q1, m1 = r["q_c"] - q2, m_c - m2
+    a_norm = ac_from_omega(q1, m1, q2, m2, 1.0, re_norm)
+    a_m = a_norm * lam / (2 * math.pi)
+    assert round(a_m / 1e-11, 1) == 9.5
+    # photon energy 0.1 keV for 12.4 nm
+    p = gold["photon_energy"]
+    assert round(1239.84198 / (p["lambda_m"] * 1e9) / 1000, 1) == p["energy_ev"] / 1000
+    # lattice constant d = n^{-1/3}
+    gd = gold["gold_density"]
+    d_nm = (gd["n_cm3"] * 1e6) ** (-1 / 3) * 1e9
+    assert round(d_nm, 2) == gd["d_nm"]
+    # peak field <-> normalised amplitude a = e E lambda / (2 pi m c^2)
+    bf = gold["bragg_field"]
+    a0 = bf["e_peak_v_m"] * bf["lambda_nm"] * 1e-9 / (2 * math.pi * 510998.95)
+    assert round(a0 / 1e-6, 1) == bf["a0"] / 1e-6
+    ba = gold["bragg_angle"]
+    assert abs(math.asin(ba["lambda_over_d"] / 2) - ba["theta_b_rad"]) < 1e-15
+
+
+# ------------------------------------- Gauss law, Mur faces, time centring
+
+def _div_e(E, shape, dx):
+    """Discrete divergence at the integer nodes of a periodic Yee grid."""
+    ndim = len(shape)
+    Es = [E[a].reshape(tuple(reversed(shape))) for a in range(3)]   # (z, y, x) order
+    div = np.zeros(tuple(reversed(shape)))
+    for d in range(ndim):
+        ax = ndim - 1 - d
+        div += (Es[d] - np.roll(Es[d], 1, axis=ax)) / dx[d]
+    return div.ravel()
+
+
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_gauss_law_preserved(oracle_built, ndim):
+    """With the Esirkepov current and the Yee update, div E - rho does not
+    change from step to step (to round-off): the deposited J enters Ampere's
+    law with the right sign and at the right stagger for every component."""
+    rng = np.random.default_rng(100 + ndim)
+    shape = (12, 10, 8)[:ndim]
+    dx = (0.3, 0.25, 0.2)[:ndim]
+    cfl = 1.0 / math.sqrt(sum(1.0 / d ** 2 for d in dx))
+    g = _grid(ndim, shape, dx, 0.9 * cfl, re_norm=1e-3)
+    o = Oracle(g)
+    n = 50
+    x, u = _random_state(rng, ndim, n, shape, dx, vmax=0.7)
+    sid = o.add_species(Species(TWO_BODY, 4.0, 20.0, -3.0, 3.0, weight=0.1, omega_c=3.0,
+                                a_c=0.0), n)
+    o.load_particles(sid, Particles(x=x, u1=u, u2=u, delta=rng.uniform(-0.02, 0.02, (n, 3))))
+    xe, ue = _random_state(rng, ndim, n, shape, dx, vmax=0.9)
+    sid2 = o.add_species(Species(POINT, -1.0, 1.0, weight=0.1), n)
+    o.load_particles(sid2, Particles(x=xe, u1=ue))
+
+    def gauss():
+        E, _, _ = o.fields()
+        return _div_e(E, shape, dx) - o.rho()
+
+    g0 = gauss()
+    scale = np.abs(o.rho()).max()
+    for _ in range(5):
+        o.step(1)
+        assert np.abs(gauss() - g0).max() < 1e-12 * scale
+    assert o.diagnostics()["error_word"] == 0
+
+
+@pytest.mark.parametrize("direction", [-1, 1])
+def test_mur_faces_absorb_outgoing_pulses(oracle_built, direction):
+    """A vacuum pulse travelling toward either open face leaves the box:
+    the first-order Mur conditions absorb normal incidence almost fully."""
+    cells = 400
+    dx = 0.1
+    dt = 0.5 * dx
+    g = Grid(1, (cells, 1, 1), (dx, 1, 1), dt, (OPEN, 0, 0), (OPEN, 0, 0))
+    o = Oracle(g)
+    xe = np.arange(cells) * dx                 # E_y at i dx
+    xb = (np.arange(cells) + 0.5) * dx         # B_z at (i + 1/2) dx, same time level
+    x0 = 0.5 * cells * dx
+
+    def f(x):
+        return np.exp(-((x - x0) / (15 * dx)) ** 2)
+
+    E = np.zeros((3, cells))
+    B = np.zeros((3, cells))
+    E[1] = f(xe)
+    # B_z = direction * E_y for a wave travelling along +-x
+    B[2] = direction * f(xb)
+    o.load_fields(E, B)
+    e0 = o.diagnostics()["field_energy"]
+    o.step(int(1.5 * cells * dx / dt))
+    assert o.diagnostics()["field_energy"] < 2e-5 * e0
+
+
+def test_out_of_plane_current_is_time_centred():
+    """Components along unresolved dimensions carry the shape averaged over
+    the straight path: their first moments equal Q v times the mean
+    position (1D: (x0 + x1)/2; 2D: also the xy moment, which fixes the 1/3
+    term x0 y0 + (x0 dy + y0 dx)/2 + dx dy/3)."""
+    u = np.array([0.35, -0.3, 0.25])
+    gam = math.sqrt(1 + u @ u)
+    J, x0, x1, _ = _single_deposit(1, [1.7], u)
+    dx = 0.3
+    xs = np.arange(12) * dx
+    m1 = (J[1] * xs).sum() * dx
+    assert abs(m1 - (-1.0) * u[1] / gam * 0.5 * (x0[0] + x1[0])) < 1e-13
+    J, x0, x1, _ = _single_deposit(2, [1.7, 1.9], u)
+    X, Y = np.meshgrid(np.arange(12) * dx, np.arange(12) * dx, indexing="xy")
+    dV = dx * dx
+    vz = u[2] / gam
+    mx = (J[2] * X).sum() * dV
+    my = (J[2] * Y).sum() * dV
+    mxy = (J[2] * X * Y).sum() * dV
+    ddx, ddy = x1[0] - x0[0], x1[1] - x0[1]
+    assert abs(mx - (-vz) * (x0[0] + 0.5 * ddx)) < 1e-13
+    assert abs(my - (-vz) * (x0[1] + 0.5 * ddy)) < 1e-13
+    exy = x0[0] * x0[1] + 0.5 * (x0[0] * ddy + x0[1] * ddx) + ddx * ddy / 3.0
+    assert abs(mxy - (-vz) * exy) < 1e-13
