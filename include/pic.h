@@ -1,0 +1,215 @@
+/*
+ * pic.h -- C ABI of libpic, the MI355X (gfx950) hot path of the two-body
+ * macro-ion particle-in-cell method of An, Chen, Sheng and Zhang,
+ * "Modeling of bound electron effects in particle-in-cell simulation"
+ * (arXiv 2208.08038).
+ *
+ * One library call advances the whole per-step cycle on one GPU:
+ *   tile sort -> field gather -> internal force + relativistic Boris push
+ *   -> move -> Esirkepov current deposit -> Yee update with open (Mur)
+ *   faces and laser injection -> optional FP64 diagnostics.
+ *
+ * Conventions shared by every entry point
+ *  - Units are normalised: c = eps0 = e = m_e = 1 and laser angular
+ *    frequency 1.  Lengths in c/omega, time in 1/omega, E in m_e c omega/e,
+ *    B in m_e omega/e, charge in e, mass in m_e, momentum per mass u = p/(m c).
+ *  - Every call returns pic_status (0 = PIC_OK, < 0 = error).  No C++
+ *    exception crosses the ABI.  pic_last_error() returns a text for the
+ *    last failure on a context (or of the last failed pic_create when ctx is
+ *    NULL).
+ *  - Host arrays passed in are read during the call and never retained;
+ *    the caller keeps ownership.  Host arrays passed out are written during
+ *    the call (the call synchronises the stream first).
+ *  - All device memory comes from the caller's allocator (pic_allocator);
+ *    with a NULL allocator the library uses hipMalloc/hipFree.  Memory is
+ *    released by pic_destroy.
+ *  - Work is enqueued on the HIP stream given to pic_create.  pic_step is
+ *    asynchronous; errors found on the device (non-finite state, particle
+ *    out of range) surface at the next pic_diagnostics.  A context is not
+ *    thread-safe; two contexts may run concurrently on different streams.
+ *  - Field arrays exchanged with the host are FP64, component-major
+ *    (3 planes of prod(n) interior values, x fastest, then y, then z).
+ *    Component a of E sits half a cell up along axis a; component a of B
+ *    sits half a cell up along the two other axes (Yee).
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PIC_OK = 0,
+  PIC_EINVAL = -1,  /* bad argument, shape, CFL violation, unsupported size */
+  PIC_ENOMEM = -2,  /* allocator returned NULL or capacity exceeded */
+  PIC_EHIP = -3,    /* HIP runtime error (text in pic_last_error) */
+  PIC_ESTATE = -4,  /* call order misuse (e.g. particles before species) */
+  PIC_ERANGE = -5,  /* particle outside the domain or |delta_d| >= dx_d / 2 */
+  PIC_ENAN = -6     /* non-finite particle state */
+} pic_status;
+
+/* boundary kinds per face */
+#define PIC_BC_PERIODIC 0
+#define PIC_BC_OPEN 1  /* first-order Mur absorbing face; particles reflect `pad` cells inside */
+#define PIC_BC_LASER 2 /* open face that also injects the laser (x-min only) */
+
+/* configuration flags */
+#define PIC_FLAG_FROZEN_FIELDS 1u /* skip the Maxwell update (fields stay as loaded) */
+#define PIC_FLAG_NO_DEPOSIT 2u    /* push without depositing current */
+#define PIC_FLAG_CHARGE_CHECK 4u  /* continuity residual of the last step of each pic_step */
+#define PIC_FLAG_TRACK_IDS 8u     /* keep each particle's load index through sorts */
+#define PIC_FLAG_TIMING 16u       /* time the particle kernels with HIP events */
+
+/* species kinds */
+#define PIC_POINT 0
+#define PIC_TWO_BODY 1
+
+/* device error word bits (pic_diag.error_word) */
+#define PIC_ERR_NAN 1u
+#define PIC_ERR_RANGE 2u
+
+typedef struct {
+  void* (*alloc)(size_t bytes, void* user); /* must return device memory aligned to 256 B */
+  void (*free)(void* ptr, void* user);
+  void* user;
+} pic_allocator;
+
+/* Laser entering through x-min (Sec. 3: x-ray pulse along +x):
+   E_inc(x, t) = a0 sin^2(pi t'/t_env) sin(omega t' + phase) * G(y, z),
+   t' = t - t_delay - x, nonzero for 0 <= t' <= t_env, G = exp(-r^2/waist^2)
+   about (yc, zc) if waist > 0 else 1; pol 1 drives E_y (B_z = E_y),
+   pol 2 drives E_z (B_y = -E_z). */
+typedef struct {
+  double a0, omega, t_env, waist, yc, zc, phase, t_delay;
+  int32_t pol, reserved;
+} pic_laser;
+
+typedef struct {
+  int32_t ndim;        /* 1, 2 or 3 resolved dimensions (x, x-y, x-y-z) */
+  int32_t precision;   /* 32 or 64: particle state, fields and push arithmetic */
+  int32_t pad;         /* particle walls sit pad (>= 3) cells inside non-periodic faces */
+  int32_t max_probe_steps;
+  int64_t n[3];        /* cells per resolved dimension; the packed cell index
+                          needs sum_d ceil(log2 n_d) <= 31 */
+  double dx[3];        /* cell sizes (resolved dimensions) */
+  double dt;           /* must satisfy dt < 1/sqrt(sum_d dx_d^-2) */
+  int32_t bc_lo[3], bc_hi[3];
+  int32_t tile[3];     /* tile shape in cells for sorting (0: library default) */
+  int32_t sort_every;  /* re-sort particles by tile every this many steps (0: default) */
+  uint32_t flags;
+  int32_t reserved;
+  double re_norm;      /* normalised classical electron radius 2 pi r_e / lambda */
+  pic_laser laser;
+} pic_config;
+
+/* Species (Sec. 2).  Charges/masses are those of ONE real particle:
+   two-body: nucleus q1, m1 and combined bound electron q2 = -Z_b, m2 = Z_b
+   (q1 = q_c - q2, m1 = m_c - m2); point: q1, m1 only.  weight = real
+   particles per macro-particle (in units of n_c (c/omega)^ndim); it scales
+   only the deposited current, never the internal force.  omega_c is the
+   restoring frequency of Sec. 3.1; a_c the softening length
+   (0: derive a_c^3 = |q1 q2| re_norm / (m_r omega_c^2); +inf: harmonic
+   bond).  Friction on the relative momentum: nu + nu_per_omega * omega_c. */
+typedef struct {
+  int32_t kind, reserved;
+  double q1, m1, q2, m2;
+  double weight, omega_c, a_c, nu, nu_per_omega;
+  int64_t capacity;    /* maximum number of macro-particles */
+} pic_species_desc;
+
+typedef struct {
+  int64_t step;
+  double time;
+  double field_energy;   /* 1/2 sum (E^2 + B^2) dV over interior nodes, FP64 compensated */
+  double kinetic_energy; /* sum W m (gamma - 1) over bodies */
+  double momentum[3];    /* sum W (m1 u1 + m2 u2) */
+  double div_l2, div_max; /* (rho^{n+1} - rho^n)/dt + div J^{n+1/2} of the last step (CHARGE_CHECK) */
+  double rho_l2;          /* L2 norm of (rho^{n+1} - rho^n)/dt */
+  int64_t n_particles;
+  uint32_t error_word, reserved;
+} pic_diag;
+
+typedef struct pic_ctx pic_ctx;
+
+/* Create a simulation context.  cfg: grid, time step, boundaries, laser,
+   flags.  alloc: device allocator (NULL: hipMalloc).  hip_stream: a
+   hipStream_t (NULL: the null stream).  *out receives the context.
+   Validates the CFL limit, sizes and boundary kinds (PIC_EINVAL). */
+int pic_create(const pic_config* cfg, const pic_allocator* alloc, void* hip_stream,
+               pic_ctx** out);
+
+/* Add a species (Sec. 2 two-body macro-ion or point particle) with room for
+   desc->capacity macro-particles; *species_id receives its id. */
+int pic_add_species(pic_ctx* ctx, const pic_species_desc* desc, int32_t* species_id);
+
+/* Append n particles from HOST FP64 arrays:
+   x      n x ndim physical positions (centre of mass r_c for two-body)
+   delta  n x 3 relative displacement r1 - r2 (NULL: zero, the Sec. 2 start)
+   u1     n x 3 momenta per mass; for a two-body species with u2 == NULL,
+          u1 is the centre-of-mass momentum per mass u_c and the bodies get
+          the Sec. 2 split p1 + p2 = m_c u_c, q1 v1 + q2 v2 = 0
+   u2     n x 3 or NULL
+   omega_c, weight: n values or NULL (species values)
+   Positions are converted to (cell, offset) as xi = x/dx, cell = floor(xi),
+   offset = xi - cell, then rounded to the context precision.  Particles
+   are ordered by tile (stable).  PIC_ERANGE if outside the domain or the
+   walls, PIC_ENAN if non-finite, PIC_ENOMEM beyond capacity. */
+int pic_load_particles(pic_ctx* ctx, int32_t species_id, int64_t n, const double* x,
+                       const double* delta, const double* u1, const double* u2,
+                       const double* omega_c, const double* weight);
+
+/* Replace E and B from HOST FP64 interior arrays (layout above; NULL: zero). */
+int pic_load_fields(pic_ctx* ctx, const double* E, const double* B);
+
+/* Advance nsteps steps, asynchronously on the context stream. */
+int pic_step(pic_ctx* ctx, int32_t nsteps);
+
+/* FP64 diagnostics of the present state (synchronises).  Returns PIC_ENAN or
+   PIC_ERANGE if the device error word is set (out is still filled). */
+int pic_diagnostics(pic_ctx* ctx, pic_diag* out);
+
+/* Copy E, B and the last step's J to HOST FP64 interior arrays (any may be NULL). */
+int pic_read_fields(pic_ctx* ctx, double* E, double* B, double* J);
+
+/* Number of particles in a species. */
+int pic_count(pic_ctx* ctx, int32_t species_id, int64_t* n);
+
+/* Copy a species' state to HOST arrays in the current device order:
+   cell n x 3 int32 (per dimension, unused dims 0), offset n x 3, delta,
+   u1, u2 n x 3 (delta/u2 two-body only), id n int64 load indices
+   (PIC_FLAG_TRACK_IDS only).  Any pointer may be NULL. */
+int pic_read_particles(pic_ctx* ctx, int32_t species_id, int32_t* cell, double* offset,
+                       double* delta, double* u1, double* u2, int64_t* id);
+
+/* Charge density at the integer nodes of the present state (HOST FP64, prod(n)). */
+int pic_rho(pic_ctx* ctx, double* rho);
+
+/* Field probes: component 0..5 (Ex, Ey, Ez, Bx, By, Bz) at interior node
+   index (i, j, k), sampled after every step into a device buffer of
+   max_probe_steps entries per probe.  Setting probes resets the record. */
+int pic_set_probes(pic_ctx* ctx, int32_t nprobe, const int32_t* comp, const int64_t* ijk);
+/* out: nprobe x nrecorded HOST FP64 (NULL: query *nrecorded only). */
+int pic_read_probes(pic_ctx* ctx, double* out, int64_t* nrecorded);
+
+/* Particle-kernel timing (PIC_FLAG_TIMING): total milliseconds and launch
+   count of the particle cycle kernels since the last reset, measured with
+   HIP events on the context stream.  Synchronises. */
+int pic_timing(pic_ctx* ctx, double* total_ms, int64_t* launches, int32_t reset);
+
+/* Text of the last error on ctx (or of the last failed pic_create if NULL). */
+const char* pic_last_error(const pic_ctx* ctx);
+
+/* Release the context and all its device memory (synchronises first). */
+void pic_destroy(pic_ctx* ctx);
+
+/* Library version string. */
+const char* pic_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PIC_H */

@@ -1,0 +1,960 @@
+// api.hip -- host implementation of the C ABI declared in include/pic.h:
+// context and memory plan, particle loading (position -> cell + offset,
+// Sec. 2 initial momentum split, tile ordering), the per-step launch
+// schedule, diagnostics and read-back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "pic.h"
+#include "pic_internal.h"
+#include "sort.h"
+
+using pic::GridInfo;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct SpeciesHost {
+  pic_species_desc d{};
+  double a_c = 0.0;  // effective softening length (inf: harmonic)
+  int64_t n = 0, cap = 0;
+  bool has_wc = false, has_w = false;
+  void* cell = nullptr;
+  void* off[3] = {nullptr, nullptr, nullptr};
+  void* dl[3] = {nullptr, nullptr, nullptr};
+  void* u1[3] = {nullptr, nullptr, nullptr};
+  void* u2[3] = {nullptr, nullptr, nullptr};
+  void* wc = nullptr;
+  void* w = nullptr;
+  pic::SortBuffers sort{};
+  int64_t* ids = nullptr;  // device load indices (TRACK_IDS)
+};
+
+}  // namespace
+
+struct pic_ctx {
+  pic_config cfg{};
+  pic_allocator alloc{};
+  bool use_hip_malloc = true;
+  hipStream_t stream = nullptr;
+  GridInfo g{};
+  int prec = 64;
+  size_t rsize = 8;
+  void* fields = nullptr;  // 9 planes
+  void* mur_b[3][2] = {};
+  void* mur_e[3][2] = {};
+  uint32_t* err = nullptr;
+  double* partials = nullptr;
+  double* dout = nullptr;  // 32 doubles: [0..3] scratch, [4..6] residual, ...
+  double* rho0 = nullptr;
+  double* rho1 = nullptr;
+  int nprobe = 0;
+  int* probe_comp = nullptr;
+  int64_t* probe_idx = nullptr;
+  void* probe_buf = nullptr;
+  int64_t probe_rec = 0;
+  std::vector<std::unique_ptr<SpeciesHost>> sp;
+  std::vector<void*> allocs;
+  int64_t step = 0;
+  int64_t steps_since_sort = 0;
+  int tile[3] = {1, 1, 1};
+  int ntiles[3] = {1, 1, 1};
+  int sort_every = 4;
+  std::string error;
+  bool residual_valid = false;
+  // timing
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;
+  int64_t launches = 0;
+};
+
+namespace {
+
+int fail(pic_ctx* c, int code, const std::string& msg) {
+  if (c)
+    c->error = msg;
+  else
+    g_create_error = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, expr)                                                           \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return fail(ctx, PIC_EHIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+void* dev_alloc(pic_ctx* c, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  bytes = (bytes + 255) & ~size_t(255);
+  void* p = nullptr;
+  if (c->use_hip_malloc) {
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  } else {
+    p = c->alloc.alloc(bytes, c->alloc.user);
+  }
+  if (p) c->allocs.push_back(p);
+  return p;
+}
+
+void dev_free_all(pic_ctx* c) {
+  for (void* p : c->allocs) {
+    if (c->use_hip_malloc)
+      (void)hipFree(p);
+    else
+      c->alloc.free(p, c->alloc.user);
+  }
+  c->allocs.clear();
+}
+
+int ceil_log2(int64_t n) {
+  int b = 0;
+  while ((int64_t(1) << b) < n) b++;
+  return b;
+}
+
+bool is_periodic(const pic_config& c, int d) {
+  return c.bc_lo[d] == PIC_BC_PERIODIC && c.bc_hi[d] == PIC_BC_PERIODIC;
+}
+
+template <typename Real>
+pic::FieldPtrs<Real> field_ptrs(pic_ctx* c) {
+  pic::FieldPtrs<Real> f;
+  Real* base = static_cast<Real*>(c->fields);
+  for (int a = 0; a < 3; a++) {
+    f.E[a] = base + (0 + a) * c->g.plane;
+    f.B[a] = base + (3 + a) * c->g.plane;
+    f.J[a] = base + (6 + a) * c->g.plane;
+  }
+  return f;
+}
+
+template <typename Real>
+pic::SpeciesDev<Real> species_dev(const SpeciesHost& s) {
+  pic::SpeciesDev<Real> d;
+  d.cell = static_cast<uint32_t*>(s.cell);
+  for (int a = 0; a < 3; a++) {
+    d.off[a] = static_cast<Real*>(s.off[a]);
+    d.dl[a] = static_cast<Real*>(s.dl[a]);
+    d.u1[a] = static_cast<Real*>(s.u1[a]);
+    d.u2[a] = static_cast<Real*>(s.u2[a]);
+  }
+  d.wc = s.has_wc ? static_cast<Real*>(s.wc) : nullptr;
+  d.w = s.has_w ? static_cast<Real*>(s.w) : nullptr;
+  d.n = s.n;
+  return d;
+}
+
+template <typename Real>
+pic::PushConst<Real> push_const(const pic_ctx* c, const SpeciesHost& s) {
+  pic::PushConst<Real> k{};
+  const pic_species_desc& d = s.d;
+  double dt = c->cfg.dt;
+  bool two = d.kind == PIC_TWO_BODY;
+  double m1 = d.m1, m2 = two ? d.m2 : 0.0, mc = m1 + m2;
+  k.dt = (Real)dt;
+  k.half_dt = (Real)(0.5 * dt);
+  double dv = 1.0;
+  for (int a = 0; a < 3; a++) {
+    k.idx[a] = a < c->g.nd ? (Real)(1.0 / c->cfg.dx[a]) : Real(0);
+    if (a < c->g.nd) dv *= c->cfg.dx[a];
+  }
+  k.a1 = (Real)(0.5 * dt * d.q1 / d.m1);
+  k.a2 = two ? (Real)(0.5 * dt * d.q2 / d.m2) : Real(0);
+  k.m1 = (Real)m1;
+  k.m2 = (Real)m2;
+  k.inv_mc = (Real)(1.0 / mc);
+  k.f1 = two ? (Real)(m2 / mc) : Real(0);
+  k.f2 = two ? (Real)(m1 / mc) : Real(1);
+  k.mr = two ? (Real)(m1 * m2 / mc) : Real(0);
+  k.inv_q1 = (Real)(1.0 / d.q1);
+  k.inv_q2 = two ? (Real)(1.0 / d.q2) : Real(0);
+  k.inv_ac2 = std::isinf(s.a_c) ? Real(0) : (Real)(1.0 / (s.a_c * s.a_c));
+  k.omega_c = (Real)d.omega_c;
+  k.nu = (Real)d.nu;
+  k.nu_per_omega = (Real)d.nu_per_omega;
+  k.qw1 = (Real)(d.q1 * d.weight);
+  k.qw2 = two ? (Real)(d.q2 * d.weight) : Real(0);
+  k.weight = (Real)d.weight;
+  k.q1 = (Real)d.q1;
+  k.q2 = two ? (Real)d.q2 : Real(0);
+  for (int a = 0; a < 3; a++) k.jf[a] = a < c->g.nd ? (Real)(-c->cfg.dx[a] / (dt * dv)) : Real(0);
+  k.inv_dv = (Real)(1.0 / dv);
+  k.two_body = two ? 1 : 0;
+  k.deposit = (c->cfg.flags & PIC_FLAG_NO_DEPOSIT) ? 0 : 1;
+  return k;
+}
+
+// Sec. 2 initial split: m1 u1 + m2 u2 = m_c u_c with q1 v1 + q2 v2 = 0.
+// Both velocities are parallel to u_c and v1 = alpha v2, alpha = -q2/q1;
+// the speed s of body 2 solves g(s) = m1 alpha s gamma(alpha s) +
+// m2 s gamma(s) - m_c |u_c| = 0, solved here by safeguarded Newton steps.
+void split_momentum(double q1, double m1, double q2, double m2, const double* uc, double* u1,
+                    double* u2) {
+  double mc = m1 + m2;
+  double p = std::sqrt(uc[0] * uc[0] + uc[1] * uc[1] + uc[2] * uc[2]);
+  if (p == 0.0) {
+    for (int a = 0; a < 3; a++) u1[a] = u2[a] = 0.0;
+    return;
+  }
+  if (q1 + q2 == 0.0) {
+    for (int a = 0; a < 3; a++) u1[a] = u2[a] = uc[a];
+    return;
+  }
+  double al = -q2 / q1;
+  double smax = std::fabs(al) > 1.0 ? 1.0 / std::fabs(al) : 1.0;
+  double target = mc * p;
+  double lo = 0.0, hi = smax;
+  double s = std::min(target / (m1 * al + m2), 0.5 * smax);
+  for (int it = 0; it < 100; it++) {
+    double g1 = 1.0 / std::sqrt(1.0 - al * al * s * s), g2 = 1.0 / std::sqrt(1.0 - s * s);
+    double gval = m1 * al * s * g1 + m2 * s * g2 - target;
+    if (gval < 0)
+      lo = s;
+    else
+      hi = s;
+    double dg = m1 * al * g1 * g1 * g1 + m2 * g2 * g2 * g2;  // d/ds of s gamma(c s) = gamma^3
+    double sn = s - gval / dg;
+    if (!(sn > lo && sn < hi)) sn = 0.5 * (lo + hi);
+    if (sn == s) break;
+    s = sn;
+  }
+  double g2 = 1.0 / std::sqrt(1.0 - s * s);
+  double g1 = 1.0 / std::sqrt(1.0 - al * al * s * s);
+  for (int a = 0; a < 3; a++) {
+    double e = uc[a] / p;
+    u2[a] = g2 * s * e;
+    u1[a] = g1 * al * s * e;
+  }
+}
+
+template <typename Real>
+int upload(pic_ctx* c, void* dst, const std::vector<Real>& v, int64_t at) {
+  if (v.empty()) return PIC_OK;
+  HIPCHK(c, hipMemcpyAsync(static_cast<Real*>(dst) + at, v.data(), v.size() * sizeof(Real),
+                           hipMemcpyHostToDevice, c->stream));
+  return PIC_OK;
+}
+
+template <typename Real>
+int load_particles_t(pic_ctx* c, SpeciesHost& s, int64_t n, const double* x, const double* delta,
+                     const double* u1, const double* u2, const double* wc, const double* w) {
+  const int nd = c->g.nd;
+  const bool two = s.d.kind == PIC_TWO_BODY;
+  std::vector<uint32_t> cell(n);
+  std::vector<int64_t> key(n);
+  std::vector<double> off(n * 3, 0.0), du1(n * 3), du2(two ? n * 3 : 0), ddl(two ? n * 3 : 0);
+  for (int64_t p = 0; p < n; p++) {
+    int ci[3] = {0, 0, 0};
+    for (int d = 0; d < nd; d++) {
+      double xv = x[p * nd + d];
+      if (!std::isfinite(xv)) return fail(c, PIC_ENAN, "non-finite particle position");
+      double xi = xv / c->cfg.dx[d];
+      double f = std::floor(xi);
+      if (f < 0 || f >= (double)c->g.n[d])
+        return fail(c, PIC_ERANGE, "particle position outside the grid");
+      ci[d] = (int)f;
+      double o = xi - f;
+      if (!is_periodic(c->cfg, d)) {
+        double pos = f + o;
+        if (pos < (double)c->g.pad || pos > (double)(c->g.n[d] - c->g.pad))
+          return fail(c, PIC_ERANGE, "particle outside the reflecting walls");
+      }
+      // round the offset to the working precision; an offset that rounds
+      // up to 1 moves to the next cell (crossing rule)
+      Real orr = (Real)o;
+      if (orr >= Real(1)) {
+        orr -= Real(1);
+        ci[d] += 1;
+        if (ci[d] >= c->g.n[d]) {
+          if (is_periodic(c->cfg, d))
+            ci[d] -= c->g.n[d];
+          else
+            return fail(c, PIC_ERANGE, "particle on the upper grid edge");
+        }
+      }
+      off[p * 3 + d] = (double)orr;
+    }
+    uint32_t pk = (uint32_t)ci[0];
+    if (nd > 1) pk |= (uint32_t)ci[1] << c->g.bits[0];
+    if (nd > 2) pk |= (uint32_t)ci[2] << (c->g.bits[0] + c->g.bits[1]);
+    cell[p] = pk;
+    key[p] = (ci[0] / c->tile[0]) +
+             (int64_t)c->ntiles[0] * ((ci[1] / c->tile[1]) + (int64_t)c->ntiles[1] * (ci[2] / c->tile[2]));
+    const double* uu = u1 + 3 * p;
+    for (int a = 0; a < 3; a++)
+      if (!std::isfinite(uu[a])) return fail(c, PIC_ENAN, "non-finite momentum");
+    if (two) {
+      if (u2) {
+        for (int a = 0; a < 3; a++) {
+          du1[p * 3 + a] = uu[a];
+          du2[p * 3 + a] = u2[3 * p + a];
+          if (!std::isfinite(u2[3 * p + a])) return fail(c, PIC_ENAN, "non-finite momentum");
+        }
+      } else {
+        split_momentum(s.d.q1, s.d.m1, s.d.q2, s.d.m2, uu, &du1[p * 3], &du2[p * 3]);
+      }
+      for (int a = 0; a < 3; a++) {
+        double v = delta ? delta[3 * p + a] : 0.0;
+        if (!std::isfinite(v)) return fail(c, PIC_ENAN, "non-finite delta");
+        if (a < nd && !(std::fabs(v) < 0.5 * c->cfg.dx[a]))
+          return fail(c, PIC_ERANGE, "|delta| must stay below half a cell");
+        ddl[p * 3 + a] = v;
+      }
+    } else {
+      for (int a = 0; a < 3; a++) du1[p * 3 + a] = uu[a];
+    }
+  }
+  // stable order by tile (counting sort on the host)
+  std::vector<int64_t> perm(n);
+  {
+    int64_t nt = (int64_t)c->ntiles[0] * c->ntiles[1] * c->ntiles[2];
+    std::vector<int64_t> cnt(nt + 1, 0);
+    for (int64_t p = 0; p < n; p++) cnt[key[p] + 1]++;
+    for (int64_t t = 0; t < nt; t++) cnt[t + 1] += cnt[t];
+    for (int64_t p = 0; p < n; p++) perm[cnt[key[p]]++] = p;
+  }
+  int64_t at = s.n;
+  std::vector<uint32_t> hc(n);
+  for (int64_t q = 0; q < n; q++) hc[q] = cell[perm[q]];
+  HIPCHK(c, hipMemcpyAsync(static_cast<uint32_t*>(s.cell) + at, hc.data(), n * sizeof(uint32_t),
+                           hipMemcpyHostToDevice, c->stream));
+  std::vector<Real> buf(n);
+  auto put = [&](void* dst, const std::vector<double>& src, int comp) -> int {
+    for (int64_t q = 0; q < n; q++) buf[q] = (Real)src[perm[q] * 3 + comp];
+    int rc = upload<Real>(c, dst, buf, at);
+    if (rc) return rc;
+    return hipStreamSynchronize(c->stream) == hipSuccess ? PIC_OK
+                                                         : fail(c, PIC_EHIP, "sync failed");
+  };
+  int rc;
+  for (int d = 0; d < nd; d++)
+    if ((rc = put(s.off[d], off, d))) return rc;
+  for (int a = 0; a < 3; a++) {
+    if ((rc = put(s.u1[a], du1, a))) return rc;
+    if (two) {
+      if ((rc = put(s.u2[a], du2, a))) return rc;
+      if ((rc = put(s.dl[a], ddl, a))) return rc;
+    }
+  }
+  auto put1 = [&](void* dst, const double* src) -> int {
+    for (int64_t q = 0; q < n; q++) buf[q] = (Real)src[perm[q]];
+    int r = upload<Real>(c, dst, buf, at);
+    if (r) return r;
+    return hipStreamSynchronize(c->stream) == hipSuccess ? PIC_OK
+                                                         : fail(c, PIC_EHIP, "sync failed");
+  };
+  if (wc || s.has_wc) {
+    std::vector<double> tmp(n, s.d.omega_c);
+    if (wc)
+      for (int64_t p = 0; p < n; p++) tmp[p] = wc[p];
+    if (!s.wc) return fail(c, PIC_ESTATE, "per-particle omega_c must come with the first load");
+    if ((rc = put1(s.wc, tmp.data()))) return rc;
+  }
+  if (w || s.has_w) {
+    std::vector<double> tmp(n, s.d.weight);
+    if (w)
+      for (int64_t p = 0; p < n; p++) tmp[p] = w[p];
+    if (!s.w) return fail(c, PIC_ESTATE, "per-particle weight must come with the first load");
+    if ((rc = put1(s.w, tmp.data()))) return rc;
+  }
+  if (s.ids) {
+    std::vector<int64_t> ids(n);
+    for (int64_t q = 0; q < n; q++) ids[q] = at + perm[q];
+    HIPCHK(c, hipMemcpyAsync(s.ids + at, ids.data(), n * sizeof(int64_t), hipMemcpyHostToDevice,
+                             c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  s.n += n;
+  return PIC_OK;
+}
+
+// ------------------------------------------------------------ stepping
+
+template <typename Real>
+void record_event(pic_ctx* c) {
+  if (!(c->cfg.flags & PIC_FLAG_TIMING)) return;
+  if (c->ev_used >= c->ev.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    c->ev.push_back(e);
+  }
+  (void)hipEventRecord(c->ev[c->ev_used++], c->stream);
+}
+
+template <typename Real>
+void deposit_rho(pic_ctx* c, double* rho) {
+  pic::launch_zero<double>(rho, c->g.plane, c->stream);
+  for (auto& s : c->sp)
+    pic::launch_rho<Real>(c->g, species_dev<Real>(*s), push_const<Real>(c, *s), rho, c->stream);
+  pic::launch_fold_periodic_f64(c->g, rho, c->stream);
+}
+
+template <typename Real>
+int step_t(pic_ctx* c, int nsteps) {
+  const GridInfo& g = c->g;
+  pic::FieldPtrs<Real> f = field_ptrs<Real>(c);
+  Real* eb[6] = {f.E[0], f.E[1], f.E[2], f.B[0], f.B[1], f.B[2]};
+  Real* jj[3] = {f.J[0], f.J[1], f.J[2]};
+  const bool frozen = (c->cfg.flags & PIC_FLAG_FROZEN_FIELDS) != 0;
+  pic::LaserDev las{};
+  las.a0 = c->cfg.laser.a0;
+  las.omega = c->cfg.laser.omega;
+  las.t_env = c->cfg.laser.t_env;
+  las.waist = c->cfg.laser.waist;
+  las.yc = c->cfg.laser.yc;
+  las.zc = c->cfg.laser.zc;
+  las.phase = c->cfg.laser.phase;
+  las.t_delay = c->cfg.laser.t_delay;
+  las.pol = c->cfg.laser.pol;
+  las.on = (c->cfg.bc_lo[0] == PIC_BC_LASER && c->cfg.laser.a0 != 0.0) ? 1 : 0;
+  for (int it = 0; it < nsteps; it++) {
+    const bool check = (c->cfg.flags & PIC_FLAG_CHARGE_CHECK) && it == nsteps - 1;
+    // tile sort on its cadence
+    if (c->sort_every > 0 && c->steps_since_sort >= c->sort_every) {
+      for (auto& s : c->sp) {
+        int rc = pic::sort_by_tile(g, c->tile, c->ntiles, s->sort, s->n, c->stream);
+        if (rc) return fail(c, PIC_EHIP, "tile sort launch failed");
+      }
+      c->steps_since_sort = 0;
+    }
+    pic::launch_fill_periodic<Real>(g, eb, 6, c->stream);
+    pic::launch_zero<Real>(f.J[0], 3 * g.plane, c->stream);
+    if (check) deposit_rho<Real>(c, c->rho0);
+    for (auto& s : c->sp) {
+      record_event<Real>(c);
+      pic::launch_push<Real>(g, f, species_dev<Real>(*s), push_const<Real>(c, *s), c->err,
+                             c->stream);
+      record_event<Real>(c);
+      c->launches++;
+    }
+    pic::launch_fold_periodic<Real>(g, jj, 3, c->stream);
+    if (check) {
+      deposit_rho<Real>(c, c->rho1);
+      pic::launch_residual<Real>(g, f, c->rho0, c->rho1, c->partials, pic::reduce_blocks(),
+                                 c->dout + 4, c->stream);
+      c->residual_valid = true;
+    }
+    if (!frozen) {
+      pic::launch_b_half<Real>(g, f, c->stream);
+      pic::launch_fill_periodic<Real>(g, eb + 3, 3, c->stream);
+      for (int d = 0; d < g.nd; d++)
+        if (!g.periodic[d])
+          pic::launch_mur_low_b<Real>(g, f, d, static_cast<Real*>(c->mur_b[d][0]),
+                                      static_cast<Real*>(c->mur_b[d][1]), las, c->step,
+                                      c->stream);
+      for (int d = 0; d < g.nd; d++)
+        if (!g.periodic[d])
+          pic::launch_save_high_e<Real>(g, f, d, static_cast<Real*>(c->mur_e[d][0]),
+                                        static_cast<Real*>(c->mur_e[d][1]), c->stream);
+      pic::launch_e_full<Real>(g, f, c->stream);
+      pic::launch_fill_periodic<Real>(g, eb, 3, c->stream);
+      for (int d = 0; d < g.nd; d++)
+        if (!g.periodic[d])
+          pic::launch_mur_high_e<Real>(g, f, d, static_cast<Real*>(c->mur_e[d][0]),
+                                       static_cast<Real*>(c->mur_e[d][1]), c->stream);
+      pic::launch_b_half<Real>(g, f, c->stream);
+    }
+    c->step++;
+    c->steps_since_sort++;
+    if (c->nprobe > 0 && c->probe_rec < c->cfg.max_probe_steps) {
+      pic::launch_probes<Real>(g, f, c->nprobe, c->probe_comp, c->probe_idx,
+                               static_cast<Real*>(c->probe_buf), c->cfg.max_probe_steps,
+                               c->probe_rec, c->stream);
+      c->probe_rec++;
+    }
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, PIC_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  return PIC_OK;
+}
+
+template <typename Real>
+int diagnostics_t(pic_ctx* c, pic_diag* out) {
+  pic::FieldPtrs<Real> f = field_ptrs<Real>(c);
+  int nb = pic::reduce_blocks();
+  pic::launch_field_energy<Real>(c->g, f, c->partials, nb, c->dout + 0, c->stream);
+  double host[8];
+  HIPCHK(c, hipMemcpyAsync(host, c->dout, 8 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  double dv = 1.0;
+  for (int d = 0; d < c->g.nd; d++) dv *= c->cfg.dx[d];
+  std::memset(out, 0, sizeof(*out));
+  out->field_energy = 0.5 * host[0] * dv;
+  if (c->residual_valid) {
+    out->div_l2 = std::sqrt(host[4]);
+    out->div_max = host[5];
+    out->rho_l2 = std::sqrt(host[6]);
+  }
+  double ke = 0.0, pm[3] = {0, 0, 0};
+  int64_t np = 0;
+  for (auto& sp : c->sp) {
+    const SpeciesHost& s = *sp;
+    np += s.n;
+    if (s.n == 0) continue;
+    pic::launch_kinetic<Real>(species_dev<Real>(s), push_const<Real>(c, s), c->partials, nb,
+                              c->dout + 0, c->stream);
+    double k4[4];
+    HIPCHK(c, hipMemcpyAsync(k4, c->dout, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    ke += k4[0];
+    for (int a = 0; a < 3; a++) pm[a] += k4[1 + a];
+  }
+  uint32_t ew = 0;
+  HIPCHK(c, hipMemcpyAsync(&ew, c->err, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  out->step = c->step;
+  out->time = (double)c->step * c->cfg.dt;
+  out->kinetic_energy = ke;
+  for (int a = 0; a < 3; a++) out->momentum[a] = pm[a];
+  out->n_particles = np;
+  out->error_word = ew;
+  if (ew & PIC_ERR_NAN) return fail(c, PIC_ENAN, "non-finite particle state on the device");
+  if (ew & PIC_ERR_RANGE) return fail(c, PIC_ERANGE, "particle out of range on the device");
+  return PIC_OK;
+}
+
+template <typename Real>
+int read_fields_t(pic_ctx* c, double* E, double* B, double* J) {
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const GridInfo& g = c->g;
+  std::vector<Real> plane(g.plane);
+  int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  double* outs[9] = {E, E ? E + ncell : nullptr, E ? E + 2 * ncell : nullptr,
+                     B, B ? B + ncell : nullptr, B ? B + 2 * ncell : nullptr,
+                     J, J ? J + ncell : nullptr, J ? J + 2 * ncell : nullptr};
+  for (int comp = 0; comp < 9; comp++) {
+    if (!outs[comp]) continue;
+    HIPCHK(c, hipMemcpy(plane.data(), static_cast<Real*>(c->fields) + comp * g.plane,
+                        g.plane * sizeof(Real), hipMemcpyDeviceToHost));
+    for (int k = 0; k < g.n[2]; k++)
+      for (int j = 0; j < g.n[1]; j++)
+        for (int i = 0; i < g.n[0]; i++)
+          outs[comp][i + (int64_t)g.n[0] * (j + (int64_t)g.n[1] * k)] =
+              (double)plane[g.origin + i + j * g.sy + k * g.sz];
+  }
+  return PIC_OK;
+}
+
+template <typename Real>
+int load_fields_t(pic_ctx* c, const double* E, const double* B) {
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const GridInfo& g = c->g;
+  std::vector<Real> plane(g.plane);
+  int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  for (int comp = 0; comp < 6; comp++) {
+    const double* src = comp < 3 ? (E ? E + comp * ncell : nullptr)
+                                 : (B ? B + (comp - 3) * ncell : nullptr);
+    std::fill(plane.begin(), plane.end(), Real(0));
+    if (src)
+      for (int k = 0; k < g.n[2]; k++)
+        for (int j = 0; j < g.n[1]; j++)
+          for (int i = 0; i < g.n[0]; i++)
+            plane[g.origin + i + j * g.sy + k * g.sz] =
+                (Real)src[i + (int64_t)g.n[0] * (j + (int64_t)g.n[1] * k)];
+    HIPCHK(c, hipMemcpy(static_cast<Real*>(c->fields) + comp * g.plane, plane.data(),
+                        g.plane * sizeof(Real), hipMemcpyHostToDevice));
+  }
+  return PIC_OK;
+}
+
+template <typename Real>
+int read_particles_t(pic_ctx* c, SpeciesHost& s, int32_t* cell, double* off, double* delta,
+                     double* u1, double* u2, int64_t* id) {
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const int64_t n = s.n;
+  const int nd = c->g.nd;
+  if (n == 0) return PIC_OK;
+  if (cell) {
+    std::vector<uint32_t> pk(n);
+    HIPCHK(c, hipMemcpy(pk.data(), s.cell, n * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    for (int64_t p = 0; p < n; p++) {
+      uint32_t v = pk[p];
+      int ci[3] = {0, 0, 0};
+      ci[0] = v & ((1u << c->g.bits[0]) - 1u);
+      if (nd > 1) ci[1] = (v >> c->g.bits[0]) & ((1u << c->g.bits[1]) - 1u);
+      if (nd > 2) ci[2] = v >> (c->g.bits[0] + c->g.bits[1]);
+      for (int d = 0; d < 3; d++) cell[p * 3 + d] = ci[d];
+    }
+  }
+  std::vector<Real> buf(n);
+  auto get = [&](void* src, double* dst, int comp) -> int {
+    HIPCHK(c, hipMemcpy(buf.data(), src, n * sizeof(Real), hipMemcpyDeviceToHost));
+    for (int64_t p = 0; p < n; p++) dst[p * 3 + comp] = (double)buf[p];
+    return PIC_OK;
+  };
+  int rc;
+  if (off) {
+    for (int64_t p = 0; p < 3 * n; p++) off[p] = 0.0;
+    for (int d = 0; d < nd; d++)
+      if ((rc = get(s.off[d], off, d))) return rc;
+  }
+  for (int a = 0; a < 3; a++) {
+    if (u1 && (rc = get(s.u1[a], u1, a))) return rc;
+    if (s.d.kind == PIC_TWO_BODY) {
+      if (u2 && (rc = get(s.u2[a], u2, a))) return rc;
+      if (delta && (rc = get(s.dl[a], delta, a))) return rc;
+    }
+  }
+  if (id) {
+    if (!s.ids) return fail(c, PIC_ESTATE, "ids need PIC_FLAG_TRACK_IDS");
+    HIPCHK(c, hipMemcpy(id, s.ids, n * sizeof(int64_t), hipMemcpyDeviceToHost));
+  }
+  return PIC_OK;
+}
+
+template <typename Real>
+int rho_t(pic_ctx* c, double* rho) {
+  deposit_rho<Real>(c, c->rho0);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const GridInfo& g = c->g;
+  std::vector<double> plane(g.plane);
+  HIPCHK(c, hipMemcpy(plane.data(), c->rho0, g.plane * sizeof(double), hipMemcpyDeviceToHost));
+  for (int k = 0; k < g.n[2]; k++)
+    for (int j = 0; j < g.n[1]; j++)
+      for (int i = 0; i < g.n[0]; i++)
+        rho[i + (int64_t)g.n[0] * (j + (int64_t)g.n[1] * k)] = plane[g.origin + i + j * g.sy + k * g.sz];
+  return PIC_OK;
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+
+extern "C" {
+
+const char* pic_version(void) { return "libpic 0.1 (gfx950)"; }
+
+const char* pic_last_error(const pic_ctx* ctx) {
+  return ctx ? ctx->error.c_str() : g_create_error.c_str();
+}
+
+int pic_create(const pic_config* cfg, const pic_allocator* alloc, void* hip_stream,
+               pic_ctx** out) {
+  if (!cfg || !out) return fail(nullptr, PIC_EINVAL, "null argument");
+  *out = nullptr;
+  if (cfg->ndim < 1 || cfg->ndim > 3) return fail(nullptr, PIC_EINVAL, "ndim must be 1, 2 or 3");
+  if (cfg->precision != 32 && cfg->precision != 64)
+    return fail(nullptr, PIC_EINVAL, "precision must be 32 or 64");
+  if (!(cfg->dt > 0)) return fail(nullptr, PIC_EINVAL, "dt must be positive");
+  double inv2 = 0.0;
+  int bits = 0;
+  for (int d = 0; d < cfg->ndim; d++) {
+    if (cfg->n[d] < 1 || !(cfg->dx[d] > 0)) return fail(nullptr, PIC_EINVAL, "bad grid size");
+    inv2 += 1.0 / (cfg->dx[d] * cfg->dx[d]);
+    bits += ceil_log2(cfg->n[d]);
+    bool pl = cfg->bc_lo[d] == PIC_BC_PERIODIC, ph = cfg->bc_hi[d] == PIC_BC_PERIODIC;
+    if (pl != ph) return fail(nullptr, PIC_EINVAL, "periodic faces come in pairs");
+    if (cfg->bc_hi[d] == PIC_BC_LASER || (d > 0 && cfg->bc_lo[d] == PIC_BC_LASER))
+      return fail(nullptr, PIC_EINVAL, "the laser enters through x-min only");
+    if (pl && cfg->n[d] < 2 * pic::kGuard)
+      return fail(nullptr, PIC_EINVAL, "periodic dimensions need at least 6 cells");
+    if (!pl && cfg->pad < 3) return fail(nullptr, PIC_EINVAL, "pad must be >= 3 with open faces");
+    if (!pl && cfg->n[d] < 2 * cfg->pad + 1)
+      return fail(nullptr, PIC_EINVAL, "grid too small for the particle walls");
+  }
+  if (bits > 31) return fail(nullptr, PIC_EINVAL, "grid too large for the packed cell index");
+  if (!(cfg->dt * std::sqrt(inv2) < 1.0))
+    return fail(nullptr, PIC_EINVAL, "time step violates the CFL limit");
+
+  pic_ctx* c = new pic_ctx();
+  c->cfg = *cfg;
+  if (alloc && alloc->alloc && alloc->free) {
+    c->alloc = *alloc;
+    c->use_hip_malloc = false;
+  }
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->prec = cfg->precision;
+  c->rsize = cfg->precision == 32 ? 4 : 8;
+  GridInfo& g = c->g;
+  g.nd = cfg->ndim;
+  g.plane = 1;
+  g.pad = cfg->pad;
+  for (int d = 0; d < 3; d++) {
+    bool r = d < g.nd;
+    g.n[d] = r ? (int)cfg->n[d] : 1;
+    g.g[d] = r ? pic::kGuard : 0;
+    g.st[d] = g.n[d] + 2 * g.g[d];
+    g.periodic[d] = r ? (is_periodic(*cfg, d) ? 1 : 0) : 1;
+    g.bits[d] = r ? ceil_log2(cfg->n[d]) : 0;
+    g.dx[d] = r ? cfg->dx[d] : 1.0;
+    g.plane *= g.st[d];
+  }
+  g.dt = cfg->dt;
+  g.sy = g.st[0];
+  g.sz = (int64_t)g.st[0] * g.st[1];
+  g.origin = g.g[0] + g.g[1] * g.sy + g.g[2] * g.sz;
+  // tiles
+  const int def3[3] = {8, 8, 8}, def2[3] = {16, 16, 1}, def1[3] = {256, 1, 1};
+  const int* def = g.nd == 3 ? def3 : (g.nd == 2 ? def2 : def1);
+  for (int d = 0; d < 3; d++) {
+    int t = d < g.nd ? (cfg->tile[d] > 0 ? cfg->tile[d] : def[d]) : 1;
+    if (d < g.nd) t = std::min(t, g.n[d]);
+    c->tile[d] = std::max(t, 1);
+    c->ntiles[d] = (g.n[d] + c->tile[d] - 1) / c->tile[d];
+  }
+  c->sort_every = cfg->sort_every > 0 ? cfg->sort_every : 4;
+
+  size_t rs = c->rsize;
+  c->fields = dev_alloc(c, 9 * g.plane * rs);
+  c->err = static_cast<uint32_t*>(dev_alloc(c, 256));
+  c->partials = static_cast<double*>(dev_alloc(c, 8 * pic::reduce_blocks() * sizeof(double)));
+  c->dout = static_cast<double*>(dev_alloc(c, 32 * sizeof(double)));
+  c->rho0 = static_cast<double*>(dev_alloc(c, g.plane * sizeof(double)));
+  c->rho1 = static_cast<double*>(dev_alloc(c, g.plane * sizeof(double)));
+  if (!c->fields || !c->err || !c->partials || !c->dout || !c->rho0 || !c->rho1) {
+    dev_free_all(c);
+    delete c;
+    return fail(nullptr, PIC_ENOMEM, "device allocation failed");
+  }
+  for (int d = 0; d < g.nd; d++) {
+    if (g.periodic[d]) continue;
+    int a_dim = d == 0 ? 1 : 0, b_dim = d == 2 ? 1 : 2;
+    size_t np = (size_t)g.n[a_dim] * g.n[b_dim];
+    for (int t = 0; t < 2; t++) {
+      c->mur_b[d][t] = dev_alloc(c, np * rs);
+      c->mur_e[d][t] = dev_alloc(c, np * rs);
+      if (!c->mur_b[d][t] || !c->mur_e[d][t]) {
+        dev_free_all(c);
+        delete c;
+        return fail(nullptr, PIC_ENOMEM, "device allocation failed");
+      }
+    }
+  }
+  hipError_t e = hipMemsetAsync(c->fields, 0, 9 * g.plane * rs, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->err, 0, 256, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->dout, 0, 32 * sizeof(double), c->stream);
+  for (int d = 0; d < g.nd && e == hipSuccess; d++) {
+    if (g.periodic[d]) continue;
+    int a_dim = d == 0 ? 1 : 0, b_dim = d == 2 ? 1 : 2;
+    size_t np = (size_t)g.n[a_dim] * g.n[b_dim];
+    for (int t = 0; t < 2 && e == hipSuccess; t++) {
+      e = hipMemsetAsync(c->mur_b[d][t], 0, np * rs, c->stream);
+      if (e == hipSuccess) e = hipMemsetAsync(c->mur_e[d][t], 0, np * rs, c->stream);
+    }
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    std::string msg = std::string("HIP: ") + hipGetErrorString(e);
+    dev_free_all(c);
+    delete c;
+    return fail(nullptr, PIC_EHIP, msg);
+  }
+  *out = c;
+  return PIC_OK;
+}
+
+int pic_add_species(pic_ctx* c, const pic_species_desc* d, int32_t* sid) {
+  if (!c || !d || !sid) return fail(c, PIC_EINVAL, "null argument");
+  if (d->kind != PIC_POINT && d->kind != PIC_TWO_BODY) return fail(c, PIC_EINVAL, "bad kind");
+  if (d->capacity < 0 || d->capacity >= (int64_t(1) << 31))
+    return fail(c, PIC_EINVAL, "capacity must be below 2^31");
+  if (!(d->m1 > 0) || d->q1 == 0.0) return fail(c, PIC_EINVAL, "bad charge or mass");
+  auto holder = std::make_unique<SpeciesHost>();
+  SpeciesHost& s = *holder;
+  s.d = *d;
+  s.cap = std::max<int64_t>(d->capacity, 1);
+  const bool two = d->kind == PIC_TWO_BODY;
+  if (two) {
+    if (!(d->m2 > 0) || d->q2 == 0.0) return fail(c, PIC_EINVAL, "bad bound-electron charge/mass");
+    if (!(d->omega_c > 0)) return fail(c, PIC_EINVAL, "omega_c must be positive");
+    double mr = d->m1 * d->m2 / (d->m1 + d->m2);
+    if (std::isinf(d->a_c))
+      s.a_c = std::numeric_limits<double>::infinity();
+    else if (d->a_c > 0)
+      s.a_c = d->a_c;
+    else {
+      // Sec. 3.1: w_c^2 = |q1 q2| (Coulomb constant) / (m_r a_c^3), the
+      // Coulomb constant being re_norm in these units
+      if (!(c->cfg.re_norm > 0)) return fail(c, PIC_EINVAL, "a_c = 0 needs re_norm > 0");
+      s.a_c = std::cbrt(std::fabs(d->q1 * d->q2) * c->cfg.re_norm / (mr * d->omega_c * d->omega_c));
+    }
+  }
+  size_t rs = c->rsize, n = (size_t)s.cap;
+  s.cell = dev_alloc(c, n * 4);
+  bool ok = s.cell != nullptr;
+  for (int a = 0; a < c->g.nd; a++) ok = ok && (s.off[a] = dev_alloc(c, n * rs));
+  for (int a = 0; a < 3; a++) {
+    ok = ok && (s.u1[a] = dev_alloc(c, n * rs));
+    if (two) {
+      ok = ok && (s.u2[a] = dev_alloc(c, n * rs));
+      ok = ok && (s.dl[a] = dev_alloc(c, n * rs));
+    }
+  }
+  if (c->cfg.flags & PIC_FLAG_TRACK_IDS)
+    ok = ok && (s.ids = static_cast<int64_t*>(dev_alloc(c, n * sizeof(int64_t))));
+  if (!ok) return fail(c, PIC_ENOMEM, "device allocation failed");
+  pic::AllocFn af = [c](size_t b) { return dev_alloc(c, b); };
+  int rc = pic::sort_alloc(c->g, c->ntiles, s.cap, af, s.sort);
+  rc = rc || pic::sort_add_attr(s.sort, &s.cell, 4, af);
+  for (int a = 0; a < c->g.nd && !rc; a++) rc = pic::sort_add_attr(s.sort, &s.off[a], rs, af);
+  for (int a = 0; a < 3 && !rc; a++) {
+    rc = pic::sort_add_attr(s.sort, &s.u1[a], rs, af);
+    if (two && !rc) rc = pic::sort_add_attr(s.sort, &s.u2[a], rs, af);
+    if (two && !rc) rc = pic::sort_add_attr(s.sort, &s.dl[a], rs, af);
+  }
+  if (s.ids && !rc) rc = pic::sort_add_attr(s.sort, reinterpret_cast<void**>(&s.ids), 8, af);
+  if (rc) return fail(c, PIC_ENOMEM, "device allocation failed (sort buffers)");
+  c->sp.push_back(std::move(holder));
+  *sid = (int32_t)(c->sp.size() - 1);
+  return PIC_OK;
+}
+
+int pic_load_particles(pic_ctx* c, int32_t sid, int64_t n, const double* x, const double* delta,
+                       const double* u1, const double* u2, const double* omega_c,
+                       const double* weight) {
+  if (!c) return PIC_EINVAL;
+  if (sid < 0 || sid >= (int32_t)c->sp.size()) return fail(c, PIC_ESTATE, "unknown species");
+  if (n < 0 || (n > 0 && (!x || !u1))) return fail(c, PIC_EINVAL, "null particle arrays");
+  SpeciesHost& s = *c->sp[sid];
+  if (s.n + n > s.cap) return fail(c, PIC_ENOMEM, "species capacity exceeded");
+  if (n == 0) return PIC_OK;
+  size_t rs = c->rsize, cap = (size_t)s.cap;
+  pic::AllocFn af = [c](size_t b) { return dev_alloc(c, b); };
+  if (omega_c && !s.wc) {
+    if (s.n > 0) return fail(c, PIC_ESTATE, "per-particle omega_c must come with the first load");
+    if (!(s.wc = dev_alloc(c, cap * rs))) return fail(c, PIC_ENOMEM, "device allocation failed");
+    if (pic::sort_add_attr(s.sort, &s.wc, rs, af))
+      return fail(c, PIC_ENOMEM, "device allocation failed");
+    s.has_wc = true;
+  }
+  if (weight && !s.w) {
+    if (s.n > 0) return fail(c, PIC_ESTATE, "per-particle weight must come with the first load");
+    if (!(s.w = dev_alloc(c, cap * rs))) return fail(c, PIC_ENOMEM, "device allocation failed");
+    if (pic::sort_add_attr(s.sort, &s.w, rs, af))
+      return fail(c, PIC_ENOMEM, "device allocation failed");
+    s.has_w = true;
+  }
+  if (c->prec == 32) return load_particles_t<float>(c, s, n, x, delta, u1, u2, omega_c, weight);
+  return load_particles_t<double>(c, s, n, x, delta, u1, u2, omega_c, weight);
+}
+
+int pic_load_fields(pic_ctx* c, const double* E, const double* B) {
+  if (!c) return PIC_EINVAL;
+  return c->prec == 32 ? load_fields_t<float>(c, E, B) : load_fields_t<double>(c, E, B);
+}
+
+int pic_step(pic_ctx* c, int32_t nsteps) {
+  if (!c || nsteps < 0) return c ? fail(c, PIC_EINVAL, "nsteps < 0") : PIC_EINVAL;
+  return c->prec == 32 ? step_t<float>(c, nsteps) : step_t<double>(c, nsteps);
+}
+
+int pic_diagnostics(pic_ctx* c, pic_diag* out) {
+  if (!c || !out) return PIC_EINVAL;
+  return c->prec == 32 ? diagnostics_t<float>(c, out) : diagnostics_t<double>(c, out);
+}
+
+int pic_read_fields(pic_ctx* c, double* E, double* B, double* J) {
+  if (!c) return PIC_EINVAL;
+  return c->prec == 32 ? read_fields_t<float>(c, E, B, J) : read_fields_t<double>(c, E, B, J);
+}
+
+int pic_count(pic_ctx* c, int32_t sid, int64_t* n) {
+  if (!c || !n) return PIC_EINVAL;
+  if (sid < 0 || sid >= (int32_t)c->sp.size()) return fail(c, PIC_ESTATE, "unknown species");
+  *n = c->sp[sid]->n;
+  return PIC_OK;
+}
+
+int pic_read_particles(pic_ctx* c, int32_t sid, int32_t* cell, double* offset, double* delta,
+                       double* u1, double* u2, int64_t* id) {
+  if (!c) return PIC_EINVAL;
+  if (sid < 0 || sid >= (int32_t)c->sp.size()) return fail(c, PIC_ESTATE, "unknown species");
+  SpeciesHost& s = *c->sp[sid];
+  return c->prec == 32 ? read_particles_t<float>(c, s, cell, offset, delta, u1, u2, id)
+                       : read_particles_t<double>(c, s, cell, offset, delta, u1, u2, id);
+}
+
+int pic_rho(pic_ctx* c, double* rho) {
+  if (!c || !rho) return PIC_EINVAL;
+  return c->prec == 32 ? rho_t<float>(c, rho) : rho_t<double>(c, rho);
+}
+
+int pic_set_probes(pic_ctx* c, int32_t nprobe, const int32_t* comp, const int64_t* ijk) {
+  if (!c || nprobe < 0 || (nprobe > 0 && (!comp || !ijk))) return PIC_EINVAL;
+  if (nprobe > 0 && c->cfg.max_probe_steps <= 0)
+    return fail(c, PIC_EINVAL, "max_probe_steps must be positive to record probes");
+  if (nprobe > c->nprobe) {
+    c->probe_comp = static_cast<int*>(dev_alloc(c, nprobe * sizeof(int)));
+    c->probe_idx = static_cast<int64_t*>(dev_alloc(c, nprobe * sizeof(int64_t)));
+    c->probe_buf = dev_alloc(c, (size_t)nprobe * c->cfg.max_probe_steps * c->rsize);
+    if (!c->probe_comp || !c->probe_idx || !c->probe_buf)
+      return fail(c, PIC_ENOMEM, "device allocation failed");
+  }
+  std::vector<int> hc(nprobe);
+  std::vector<int64_t> hi(nprobe);
+  for (int p = 0; p < nprobe; p++) {
+    if (comp[p] < 0 || comp[p] > 5) return fail(c, PIC_EINVAL, "probe component must be 0..5");
+    int64_t ix[3];
+    for (int d = 0; d < 3; d++) {
+      ix[d] = ijk[3 * p + d];
+      if (ix[d] < 0 || ix[d] >= c->g.n[d]) return fail(c, PIC_EINVAL, "probe outside the grid");
+    }
+    hc[p] = comp[p];
+    hi[p] = c->g.origin + ix[0] + ix[1] * c->g.sy + ix[2] * c->g.sz;
+  }
+  if (nprobe > 0) {
+    HIPCHK(c, hipMemcpy(c->probe_comp, hc.data(), nprobe * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->probe_idx, hi.data(), nprobe * sizeof(int64_t), hipMemcpyHostToDevice));
+  }
+  c->nprobe = nprobe;
+  c->probe_rec = 0;
+  return PIC_OK;
+}
+
+int pic_read_probes(pic_ctx* c, double* out, int64_t* nrec) {
+  if (!c) return PIC_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (nrec) *nrec = c->probe_rec;
+  if (!out || c->nprobe == 0 || c->probe_rec == 0) return PIC_OK;
+  size_t total = (size_t)c->nprobe * c->cfg.max_probe_steps;
+  if (c->prec == 32) {
+    std::vector<float> b(total);
+    HIPCHK(c, hipMemcpy(b.data(), c->probe_buf, total * 4, hipMemcpyDeviceToHost));
+    for (int p = 0; p < c->nprobe; p++)
+      for (int64_t t = 0; t < c->probe_rec; t++)
+        out[p * c->probe_rec + t] = b[(size_t)p * c->cfg.max_probe_steps + t];
+  } else {
+    std::vector<double> b(total);
+    HIPCHK(c, hipMemcpy(b.data(), c->probe_buf, total * 8, hipMemcpyDeviceToHost));
+    for (int p = 0; p < c->nprobe; p++)
+      for (int64_t t = 0; t < c->probe_rec; t++)
+        out[p * c->probe_rec + t] = b[(size_t)p * c->cfg.max_probe_steps + t];
+  }
+  return PIC_OK;
+}
+
+int pic_timing(pic_ctx* c, double* total_ms, int64_t* launches, int32_t reset) {
+  if (!c) return PIC_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  double tot = 0.0;
+  for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
+    tot += ms;
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = (int64_t)(c->ev_used / 2);
+  if (reset) c->ev_used = 0;
+  return PIC_OK;
+}
+
+void pic_destroy(pic_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  dev_free_all(c);
+  delete c;
+}
+
+}  // extern "C"

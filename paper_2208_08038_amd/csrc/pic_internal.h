@@ -1,0 +1,148 @@
+// pic_internal.h -- device-side data layout and kernel launchers of libpic.
+//
+// HBM layout (one context):
+//   fields   9 component planes (E, B, J), each (n_x + 2G)(n_y + 2G)(n_z + 2G)
+//            values of the context precision, x fastest; G = 3 guard layers
+//            on each side of every resolved dimension (unresolved: none).
+//            Index of interior node (i, j, k): origin + i + j*sy + k*sz.
+//   species  structure of arrays: packed cell (uint32: i | j << bx | k << (bx+by)),
+//            offset[ndim], delta[3], u1[3], u2[3] (two-body), optional
+//            omega_c and weight, all of the context precision; particles
+//            grouped by tile.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "pic.h"
+
+namespace pic {
+
+constexpr int kGuard = 3;
+
+// Grid geometry shared by every kernel (passed by value).
+struct GridInfo {
+  int nd;
+  int n[3];         // interior cells per dim (1 if unresolved)
+  int g[3];         // guard layers per dim (kGuard if resolved, else 0)
+  int st[3];        // storage extent per dim
+  int64_t sy, sz;   // strides of y and z in the storage
+  int64_t origin;   // storage index of interior node (0,0,0)
+  int64_t plane;    // values per component plane
+  int periodic[3];  // 1 if both faces periodic
+  int pad;          // particle wall distance from non-periodic faces
+  int bits[3];      // packed cell bits per dim
+  double dx[3];
+  double dt;
+};
+
+template <typename Real>
+struct FieldPtrs {
+  Real* E[3];
+  Real* B[3];
+  Real* J[3];
+};
+
+// One species' particle arrays (device pointers) and constants.
+template <typename Real>
+struct SpeciesDev {
+  uint32_t* cell;
+  Real* off[3];
+  Real* dl[3];
+  Real* u1[3];
+  Real* u2[3];
+  Real* wc;  // per-particle omega_c or nullptr
+  Real* w;   // per-particle weight or nullptr
+  int64_t n;
+};
+
+// Constants of the push of one species, precomputed on the host in FP64
+// and rounded once to Real.
+template <typename Real>
+struct PushConst {
+  Real dt, half_dt;
+  Real idx[3];     // 1/dx
+  Real a1, a2;     // (dt/2) q/m of body 1 and body 2
+  Real m1, m2, inv_mc;
+  Real f1, f2;     // m2/mc, m1/mc: body offsets from the centre of mass
+  Real mr;         // reduced mass
+  Real inv_q1, inv_q2;
+  Real inv_ac2;    // 1/a_c^2, 0 for the harmonic bond
+  Real omega_c, nu, nu_per_omega;
+  Real qw1, qw2;   // q1 * weight, q2 * weight (species weight)
+  Real weight;
+  Real q1, q2;
+  Real jf[3];      // -dx_d / (dt dV): Esirkepov prefactor per unit charge
+  Real inv_dv;
+  int two_body;
+  int deposit;
+};
+
+// Launchers (host).  All take the stream to launch on.
+template <typename Real>
+void launch_push(const GridInfo& g, const FieldPtrs<Real>& f, const SpeciesDev<Real>& s,
+                 const PushConst<Real>& c, uint32_t* err, hipStream_t st);
+
+template <typename Real>
+void launch_zero(Real* p, int64_t n, hipStream_t st);
+
+template <typename Real>
+void launch_fill_periodic(const GridInfo& g, Real* const* comps, int ncomp, hipStream_t st);
+
+template <typename Real>
+void launch_fold_periodic(const GridInfo& g, Real* const* comps, int ncomp, hipStream_t st);
+
+template <typename Real>
+void launch_b_half(const GridInfo& g, const FieldPtrs<Real>& f, hipStream_t st);
+
+template <typename Real>
+void launch_e_full(const GridInfo& g, const FieldPtrs<Real>& f, hipStream_t st);
+
+struct LaserDev {
+  double a0, omega, t_env, waist, yc, zc, phase, t_delay;
+  int pol;
+  int on;
+};
+
+template <typename Real>
+void launch_mur_low_b(const GridInfo& g, const FieldPtrs<Real>& f, int d, Real* prev0,
+                      Real* prev1, const LaserDev& las, int64_t step, hipStream_t st);
+
+template <typename Real>
+void launch_save_high_e(const GridInfo& g, const FieldPtrs<Real>& f, int d, Real* save0,
+                        Real* save1, hipStream_t st);
+
+template <typename Real>
+void launch_mur_high_e(const GridInfo& g, const FieldPtrs<Real>& f, int d, const Real* save0,
+                       const Real* save1, hipStream_t st);
+
+// diagnostics
+template <typename Real>
+void launch_rho(const GridInfo& g, const SpeciesDev<Real>& s, const PushConst<Real>& c,
+                double* rho, hipStream_t st);
+
+void launch_fold_periodic_f64(const GridInfo& g, double* rho, hipStream_t st);
+
+// FP64 compensated reductions; each writes its results into out[] (device)
+template <typename Real>
+void launch_field_energy(const GridInfo& g, const FieldPtrs<Real>& f, double* partials,
+                         int nblocks, double* out, hipStream_t st);
+
+template <typename Real>
+void launch_kinetic(const SpeciesDev<Real>& s, const PushConst<Real>& c, double* partials,
+                    int nblocks, double* out /* 4: energy, px, py, pz */, hipStream_t st);
+
+template <typename Real>
+void launch_residual(const GridInfo& g, const FieldPtrs<Real>& f, const double* rho0,
+                     const double* rho1, double* partials, int nblocks,
+                     double* out /* 3: sum res^2, max |res|, sum drho^2 */, hipStream_t st);
+
+template <typename Real>
+void launch_probes(const GridInfo& g, const FieldPtrs<Real>& f, int nprobe, const int* comp,
+                   const int64_t* index, Real* buf, int64_t max_steps, int64_t rec,
+                   hipStream_t st);
+
+int reduce_blocks();
+
+}  // namespace pic

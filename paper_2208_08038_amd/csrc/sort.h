@@ -1,0 +1,49 @@
+// sort.h -- stable on-device ordering of particles by tile.
+//
+// Key = tile id of the particle's (centre-of-mass) cell.  The order is a
+// stable LSD radix sort over 8-bit digits of the key: within a tile the
+// particles keep their previous relative order, so the permutation is
+// unique and reproducible.  Every attribute array is then gathered through
+// the permutation into an alternate buffer and the buffers are swapped.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <functional>
+
+#include "pic_internal.h"
+
+namespace pic {
+
+constexpr int kMaxAttr = 24;
+
+struct SortBuffers {
+  uint32_t* key[2] = {nullptr, nullptr};
+  uint32_t* idx[2] = {nullptr, nullptr};
+  uint32_t* hist = nullptr;     // 256 x blocks, digit-major
+  uint32_t* scan_tmp = nullptr; // block sums of the scan levels
+  uint32_t* tile_off = nullptr; // ntiles + 1 offsets of the sorted order
+  int64_t ntiles = 0;
+  int64_t cap = 0;
+  int nattr = 0;
+  void** attr[kMaxAttr] = {};   // pointers to the species' attribute pointers
+  size_t elem[kMaxAttr] = {};   // element sizes
+  void* alt[kMaxAttr] = {};     // alternate buffers
+};
+
+using AllocFn = std::function<void*(size_t)>;
+
+// Allocate key/index/histogram buffers and tile offsets for `cap` particles.
+int sort_alloc(const GridInfo& g, const int ntiles[3], int64_t cap, const AllocFn& alloc,
+               SortBuffers& sb);
+
+// Register one attribute array (pointer to the species' pointer) and
+// allocate its alternate buffer.
+int sort_add_attr(SortBuffers& sb, void** ptr, size_t elem, const AllocFn& alloc);
+
+// Sort n particles by tile; swaps the registered attribute pointers.
+int sort_by_tile(const GridInfo& g, const int tile[3], const int ntiles[3], SortBuffers& sb,
+                 int64_t n, hipStream_t st);
+
+}  // namespace pic

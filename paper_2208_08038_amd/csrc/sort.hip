@@ -1,0 +1,216 @@
+// sort.hip -- stable LSD radix sort of particles by tile id (8-bit digits).
+//
+// Pass structure (per digit): block histograms over chunks of 4096 keys,
+// an exclusive scan of the digit-major histogram table, and a stable
+// block scatter in which each wavefront ranks equal digits with ballots.
+// The resulting permutation gathers every attribute array once.
+#include "sort.h"
+
+namespace pic {
+
+namespace {
+
+constexpr int SB = 256;          // threads per block
+constexpr int ROUNDS = 16;       // items per thread
+constexpr int CHUNK = SB * ROUNDS;
+constexpr int SCAN_ITEMS = 1024; // per scan block (4 per thread)
+
+__global__ void k_keys(GridInfo g, int tx, int ty, int tz, int ntx, int nty, const uint32_t* cell,
+                       int64_t n, uint32_t* key) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  uint32_t v = cell[p];
+  uint32_t i = v & ((1u << g.bits[0]) - 1u);
+  uint32_t j = g.nd > 1 ? (v >> g.bits[0]) & ((1u << g.bits[1]) - 1u) : 0u;
+  uint32_t k = g.nd > 2 ? v >> (g.bits[0] + g.bits[1]) : 0u;
+  key[p] = i / tx + (uint32_t)ntx * (j / ty + (uint32_t)nty * (k / tz));
+}
+
+__global__ void __launch_bounds__(SB) k_hist(const uint32_t* key, int64_t n, int shift,
+                                             uint32_t* hist, int nb) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t base = (int64_t)blockIdx.x * CHUNK;
+  for (int r = 0; r < ROUNDS; r++) {
+    int64_t i = base + (int64_t)r * SB + threadIdx.x;
+    if (i < n) atomicAdd(&h[(key[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+// in-place exclusive scan of 1024-element blocks; block totals -> sums[b]
+__global__ void __launch_bounds__(SB) k_scan_block(uint32_t* a, int64_t L, uint32_t* sums) {
+  __shared__ uint32_t s[SB];
+  int64_t base = (int64_t)blockIdx.x * SCAN_ITEMS + (int64_t)threadIdx.x * 4;
+  uint32_t v[4], t = 0;
+  for (int q = 0; q < 4; q++) {
+    v[q] = (base + q < L) ? a[base + q] : 0u;
+    t += v[q];
+  }
+  s[threadIdx.x] = t;
+  __syncthreads();
+  for (int off = 1; off < SB; off <<= 1) {
+    uint32_t add = threadIdx.x >= (unsigned)off ? s[threadIdx.x - off] : 0u;
+    __syncthreads();
+    s[threadIdx.x] += add;
+    __syncthreads();
+  }
+  uint32_t run = s[threadIdx.x] - t;  // exclusive prefix of this thread
+  for (int q = 0; q < 4; q++) {
+    if (base + q < L) a[base + q] = run;
+    run += v[q];
+  }
+  if (threadIdx.x == SB - 1) sums[blockIdx.x] = s[SB - 1];
+}
+
+__global__ void k_scan_add(uint32_t* a, int64_t L, const uint32_t* sums) {
+  int64_t i = (int64_t)blockIdx.x * SCAN_ITEMS + threadIdx.x;
+  uint32_t add = sums[blockIdx.x];
+  for (int q = 0; q < 4; q++, i += SB)
+    if (i < L) a[i] += add;
+}
+
+void scan_exclusive(uint32_t* a, int64_t L, uint32_t* tmp, hipStream_t st) {
+  int64_t nb = (L + SCAN_ITEMS - 1) / SCAN_ITEMS;
+  hipLaunchKernelGGL(k_scan_block, dim3((unsigned)nb), SB, 0, st, a, L, tmp);
+  if (nb > 1) {
+    scan_exclusive(tmp, nb, tmp + nb, st);
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), SB, 0, st, a, L, tmp);
+  }
+}
+
+__global__ void __launch_bounds__(SB) k_scatter(const uint32_t* kin, const uint32_t* iin,
+                                                uint32_t* kout, uint32_t* iout,
+                                                const uint32_t* offs, int shift, int64_t n,
+                                                int nb) {
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t wc[SB / 64][256];
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  run[t] = offs[(int64_t)t * nb + blockIdx.x];
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  int64_t base = (int64_t)blockIdx.x * CHUNK;
+  for (int r = 0; r < ROUNDS; r++) {
+    for (int q = 0; q < SB / 64; q++) wc[q][t] = 0;
+    __syncthreads();
+    int64_t i = base + (int64_t)r * SB + t;
+    bool valid = i < n;
+    uint32_t key = valid ? kin[i] : 0u;
+    uint32_t dig = (key >> shift) & 255u;
+    uint64_t m = __ballot(valid);
+    for (int b = 0; b < 8; b++) {
+      bool bit = (dig >> b) & 1u;
+      uint64_t bb = __ballot(valid && bit);
+      m &= bit ? bb : ~bb;
+    }
+    uint32_t rank = (uint32_t)__popcll(m & lt);
+    if (valid && rank == 0) wc[wave][dig] = (uint32_t)__popcll(m);
+    __syncthreads();
+    uint32_t pos = 0;
+    if (valid) {
+      pos = run[dig] + rank;
+      for (int q = 0; q < wave; q++) pos += wc[q][dig];
+    }
+    __syncthreads();
+    uint32_t tot = 0;
+    for (int q = 0; q < SB / 64; q++) tot += wc[q][t];
+    run[t] += tot;
+    if (valid) {
+      kout[pos] = key;
+      iout[pos] = iin ? iin[i] : (uint32_t)i;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_tile_off(const uint32_t* key, int64_t n, int64_t ntiles, uint32_t* off) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > n) return;
+  int64_t lo = i == 0 ? -1 : min((int64_t)key[i - 1], ntiles);
+  int64_t hi = i == n ? ntiles : min((int64_t)key[i], ntiles);
+  for (int64_t t = lo + 1; t <= hi; t++) off[t] = (uint32_t)i;
+}
+
+template <typename T>
+__global__ void k_gather(const T* __restrict__ src, T* __restrict__ dst,
+                         const uint32_t* __restrict__ idx, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[idx[i]];
+}
+
+inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+int sort_alloc(const GridInfo&, const int ntiles[3], int64_t cap, const AllocFn& alloc,
+               SortBuffers& sb) {
+  sb.cap = cap;
+  sb.ntiles = (int64_t)ntiles[0] * ntiles[1] * ntiles[2];
+  int64_t nb = (cap + CHUNK - 1) / CHUNK;
+  int64_t hist = 256 * nb;
+  int64_t tmp = hist / 512 + 4096;
+  for (int b = 0; b < 2; b++) {
+    sb.key[b] = static_cast<uint32_t*>(alloc(cap * 4));
+    sb.idx[b] = static_cast<uint32_t*>(alloc(cap * 4));
+    if (!sb.key[b] || !sb.idx[b]) return -1;
+  }
+  sb.hist = static_cast<uint32_t*>(alloc(hist * 4));
+  sb.scan_tmp = static_cast<uint32_t*>(alloc(tmp * 4));
+  sb.tile_off = static_cast<uint32_t*>(alloc((sb.ntiles + 1) * 4));
+  if (!sb.hist || !sb.scan_tmp || !sb.tile_off) return -1;
+  return 0;
+}
+
+int sort_add_attr(SortBuffers& sb, void** ptr, size_t elem, const AllocFn& alloc) {
+  if (sb.nattr >= kMaxAttr) return -1;
+  void* a = alloc(sb.cap * elem);
+  if (!a) return -1;
+  sb.attr[sb.nattr] = ptr;
+  sb.elem[sb.nattr] = elem;
+  sb.alt[sb.nattr] = a;
+  sb.nattr++;
+  return 0;
+}
+
+int sort_by_tile(const GridInfo& g, const int tile[3], const int ntiles[3], SortBuffers& sb,
+                 int64_t n, hipStream_t st) {
+  if (n <= 0) return 0;
+  uint32_t* cell = static_cast<uint32_t*>(*sb.attr[0]);
+  hipLaunchKernelGGL(k_keys, nblk(n, 256), 256, 0, st, g, tile[0], tile[1], tile[2], ntiles[0],
+                     ntiles[1], cell, n, sb.key[0]);
+  int bits = 0;
+  while ((int64_t(1) << bits) < sb.ntiles) bits++;
+  int passes = (bits + 7) / 8;
+  int nb = (int)((n + CHUNK - 1) / CHUNK);
+  int cur = 0;
+  const uint32_t* idx_in = nullptr;
+  for (int p = 0; p < passes; p++) {
+    int shift = 8 * p;
+    hipLaunchKernelGGL(k_hist, dim3(nb), SB, 0, st, sb.key[cur], n, shift, sb.hist, nb);
+    scan_exclusive(sb.hist, (int64_t)256 * nb, sb.scan_tmp, st);
+    hipLaunchKernelGGL(k_scatter, dim3(nb), SB, 0, st, sb.key[cur], idx_in, sb.key[1 - cur],
+                       sb.idx[1 - cur], sb.hist, shift, n, nb);
+    idx_in = sb.idx[1 - cur];
+    cur = 1 - cur;
+  }
+  hipLaunchKernelGGL(k_tile_off, nblk(n + 1, 256), 256, 0, st, sb.key[cur], n, sb.ntiles,
+                     sb.tile_off);
+  if (passes == 0) return 0;  // a single tile: order unchanged
+  const uint32_t* perm = sb.idx[cur];
+  for (int a = 0; a < sb.nattr; a++) {
+    void* src = *sb.attr[a];
+    void* dst = sb.alt[a];
+    if (sb.elem[a] == 4)
+      hipLaunchKernelGGL(k_gather<uint32_t>, nblk(n, 256), 256, 0, st,
+                         static_cast<const uint32_t*>(src), static_cast<uint32_t*>(dst), perm, n);
+    else
+      hipLaunchKernelGGL(k_gather<uint64_t>, nblk(n, 256), 256, 0, st,
+                         static_cast<const uint64_t*>(src), static_cast<uint64_t*>(dst), perm, n);
+    *sb.attr[a] = dst;
+    sb.alt[a] = src;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace pic
