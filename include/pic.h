@@ -162,6 +162,16 @@ int pic_load_particles(pic_ctx* ctx, int32_t species_id, int64_t n, const double
                        const double* delta, const double* u1, const double* u2,
                        const double* omega_c, const double* weight);
 
+/* Same contract as pic_load_particles, but every array is FP64 DEVICE
+   memory on the context's device (read in stream order; the call
+   synchronises before returning, after which the caller may free them).
+   Conversion, the Sec. 2 split and the range checks run on the device; the
+   whole species is then re-ordered by tile on the device (stable).  On an
+   invalid particle nothing is appended and PIC_ERANGE / PIC_ENAN returns. */
+int pic_load_particles_device(pic_ctx* ctx, int32_t species_id, int64_t n, const double* x,
+                              const double* delta, const double* u1, const double* u2,
+                              const double* omega_c, const double* weight);
+
 /* Replace E and B from HOST FP64 interior arrays (layout above; NULL: zero). */
 int pic_load_fields(pic_ctx* ctx, const double* E, const double* B);
 
@@ -196,9 +206,11 @@ int pic_set_probes(pic_ctx* ctx, int32_t nprobe, const int32_t* comp, const int6
 int pic_read_probes(pic_ctx* ctx, double* out, int64_t* nrecorded);
 
 /* Particle-kernel timing (PIC_FLAG_TIMING): total milliseconds and launch
-   count of the particle cycle kernels since the last reset, measured with
-   HIP events on the context stream.  Synchronises. */
-int pic_timing(pic_ctx* ctx, double* total_ms, int64_t* launches, int32_t reset);
+   count of the particle-cycle kernel launches of one species (species_id
+   >= 0) or of all species (-1) since the last reset, measured with HIP
+   events recorded on the context stream around each launch.  Synchronises. */
+int pic_timing(pic_ctx* ctx, int32_t species_id, double* total_ms, int64_t* launches,
+               int32_t reset);
 
 /* Text of the last error on ctx (or of the last failed pic_create if NULL). */
 const char* pic_last_error(const pic_ctx* ctx);

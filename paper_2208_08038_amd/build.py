@@ -15,7 +15,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpic.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "particles.hip", "fields.hip", "diag.hip", "sort.hip", "tiled.hip"]
+SOURCES = ["api.hip", "particles.hip", "fields.hip", "diag.hip", "sort.hip", "load.hip",
+           "tiled.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -16,6 +16,7 @@
 #include "pic.h"
 #include "pic_internal.h"
 #include "sort.h"
+#include "load.h"
 
 using pic::GridInfo;
 
@@ -53,6 +54,7 @@ struct pic_ctx {
   void* mur_b[3][2] = {};
   void* mur_e[3][2] = {};
   uint32_t* err = nullptr;
+  uint32_t* load_err = nullptr;
   double* partials = nullptr;
   double* dout = nullptr;  // 32 doubles: [0..3] scratch, [4..6] residual, ...
   double* rho0 = nullptr;
@@ -73,6 +75,7 @@ struct pic_ctx {
   bool residual_valid = false;
   // timing
   std::vector<hipEvent_t> ev;
+  std::vector<int> ev_species;  // species of each (start, stop) pair
   size_t ev_used = 0;
   int64_t launches = 0;
 };
@@ -381,15 +384,21 @@ int load_particles_t(pic_ctx* c, SpeciesHost& s, int64_t n, const double* x, con
 
 // ------------------------------------------------------------ stepping
 
-template <typename Real>
-void record_event(pic_ctx* c) {
-  if (!(c->cfg.flags & PIC_FLAG_TIMING)) return;
+// start/stop events around one particle-kernel launch (PIC_FLAG_TIMING)
+constexpr size_t kMaxEvents = 1 << 16;
+bool record_event(pic_ctx* c, int species, bool start) {
+  if (!(c->cfg.flags & PIC_FLAG_TIMING)) return false;
+  if (start && c->ev_used + 2 > kMaxEvents) return false;
   if (c->ev_used >= c->ev.size()) {
     hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return;
+    if (hipEventCreate(&e) != hipSuccess) return false;
     c->ev.push_back(e);
   }
-  (void)hipEventRecord(c->ev[c->ev_used++], c->stream);
+  if (start) {
+    if (c->ev_species.size() < c->ev_used / 2 + 1) c->ev_species.resize(c->ev_used / 2 + 1);
+    c->ev_species[c->ev_used / 2] = species;
+  }
+  return hipEventRecord(c->ev[c->ev_used++], c->stream) == hipSuccess;
 }
 
 template <typename Real>
@@ -431,11 +440,12 @@ int step_t(pic_ctx* c, int nsteps) {
     pic::launch_fill_periodic<Real>(g, eb, 6, c->stream);
     pic::launch_zero<Real>(f.J[0], 3 * g.plane, c->stream);
     if (check) deposit_rho<Real>(c, c->rho0);
-    for (auto& s : c->sp) {
-      record_event<Real>(c);
+    for (size_t si = 0; si < c->sp.size(); si++) {
+      auto& s = c->sp[si];
+      bool timed = record_event(c, (int)si, true);
       pic::launch_push<Real>(g, f, species_dev<Real>(*s), push_const<Real>(c, *s), c->err,
                              c->stream);
-      record_event<Real>(c);
+      if (timed) record_event(c, (int)si, false);
       c->launches++;
     }
     pic::launch_fold_periodic<Real>(g, jj, 3, c->stream);
@@ -627,6 +637,27 @@ int rho_t(pic_ctx* c, double* rho) {
   return PIC_OK;
 }
 
+// allocate the optional per-particle arrays on the first load that brings them
+int prepare_optional(pic_ctx* c, SpeciesHost& s, bool want_wc, bool want_w) {
+  size_t rs = c->rsize, cap = (size_t)s.cap;
+  pic::AllocFn af = [c](size_t b) { return dev_alloc(c, b); };
+  if (want_wc && !s.wc) {
+    if (s.n > 0) return fail(c, PIC_ESTATE, "per-particle omega_c must come with the first load");
+    if (!(s.wc = dev_alloc(c, cap * rs))) return fail(c, PIC_ENOMEM, "device allocation failed");
+    if (pic::sort_add_attr(s.sort, &s.wc, rs, af))
+      return fail(c, PIC_ENOMEM, "device allocation failed");
+    s.has_wc = true;
+  }
+  if (want_w && !s.w) {
+    if (s.n > 0) return fail(c, PIC_ESTATE, "per-particle weight must come with the first load");
+    if (!(s.w = dev_alloc(c, cap * rs))) return fail(c, PIC_ENOMEM, "device allocation failed");
+    if (pic::sort_add_attr(s.sort, &s.w, rs, af))
+      return fail(c, PIC_ENOMEM, "device allocation failed");
+    s.has_w = true;
+  }
+  return PIC_OK;
+}
+
 }  // namespace
 
 // ================================================================ C ABI
@@ -708,11 +739,12 @@ int pic_create(const pic_config* cfg, const pic_allocator* alloc, void* hip_stre
   size_t rs = c->rsize;
   c->fields = dev_alloc(c, 9 * g.plane * rs);
   c->err = static_cast<uint32_t*>(dev_alloc(c, 256));
+  c->load_err = static_cast<uint32_t*>(dev_alloc(c, 256));
   c->partials = static_cast<double*>(dev_alloc(c, 8 * pic::reduce_blocks() * sizeof(double)));
   c->dout = static_cast<double*>(dev_alloc(c, 32 * sizeof(double)));
   c->rho0 = static_cast<double*>(dev_alloc(c, g.plane * sizeof(double)));
   c->rho1 = static_cast<double*>(dev_alloc(c, g.plane * sizeof(double)));
-  if (!c->fields || !c->err || !c->partials || !c->dout || !c->rho0 || !c->rho1) {
+  if (!c->fields || !c->err || !c->load_err || !c->partials || !c->dout || !c->rho0 || !c->rho1) {
     dev_free_all(c);
     delete c;
     return fail(nullptr, PIC_ENOMEM, "device allocation failed");
@@ -819,24 +851,43 @@ int pic_load_particles(pic_ctx* c, int32_t sid, int64_t n, const double* x, cons
   SpeciesHost& s = *c->sp[sid];
   if (s.n + n > s.cap) return fail(c, PIC_ENOMEM, "species capacity exceeded");
   if (n == 0) return PIC_OK;
-  size_t rs = c->rsize, cap = (size_t)s.cap;
-  pic::AllocFn af = [c](size_t b) { return dev_alloc(c, b); };
-  if (omega_c && !s.wc) {
-    if (s.n > 0) return fail(c, PIC_ESTATE, "per-particle omega_c must come with the first load");
-    if (!(s.wc = dev_alloc(c, cap * rs))) return fail(c, PIC_ENOMEM, "device allocation failed");
-    if (pic::sort_add_attr(s.sort, &s.wc, rs, af))
-      return fail(c, PIC_ENOMEM, "device allocation failed");
-    s.has_wc = true;
-  }
-  if (weight && !s.w) {
-    if (s.n > 0) return fail(c, PIC_ESTATE, "per-particle weight must come with the first load");
-    if (!(s.w = dev_alloc(c, cap * rs))) return fail(c, PIC_ENOMEM, "device allocation failed");
-    if (pic::sort_add_attr(s.sort, &s.w, rs, af))
-      return fail(c, PIC_ENOMEM, "device allocation failed");
-    s.has_w = true;
-  }
+  int rc = prepare_optional(c, s, omega_c != nullptr, weight != nullptr);
+  if (rc) return rc;
   if (c->prec == 32) return load_particles_t<float>(c, s, n, x, delta, u1, u2, omega_c, weight);
   return load_particles_t<double>(c, s, n, x, delta, u1, u2, omega_c, weight);
+}
+
+int pic_load_particles_device(pic_ctx* c, int32_t sid, int64_t n, const double* x,
+                              const double* delta, const double* u1, const double* u2,
+                              const double* omega_c, const double* weight) {
+  if (!c) return PIC_EINVAL;
+  if (sid < 0 || sid >= (int32_t)c->sp.size()) return fail(c, PIC_ESTATE, "unknown species");
+  if (n < 0 || (n > 0 && (!x || !u1))) return fail(c, PIC_EINVAL, "null particle arrays");
+  SpeciesHost& s = *c->sp[sid];
+  if (s.n + n > s.cap) return fail(c, PIC_ENOMEM, "species capacity exceeded");
+  if (n == 0) return PIC_OK;
+  int rc = prepare_optional(c, s, omega_c != nullptr, weight != nullptr);
+  if (rc) return rc;
+  pic::LoadSrc src{x, delta, u1, u2, omega_c, weight, n};
+  pic::LoadSplit sp{s.d.q1, s.d.m1, s.d.q2, s.d.m2, s.d.omega_c, s.d.weight};
+  const bool two = s.d.kind == PIC_TWO_BODY;
+  HIPCHK(c, hipMemsetAsync(c->load_err, 0, sizeof(uint32_t), c->stream));
+  if (c->prec == 32)
+    pic::launch_load<float>(c->g, src, species_dev<float>(s), s.n, s.ids, sp, two, c->load_err,
+                            c->stream);
+  else
+    pic::launch_load<double>(c->g, src, species_dev<double>(s), s.n, s.ids, sp, two, c->load_err,
+                             c->stream);
+  uint32_t bad = 0;
+  HIPCHK(c, hipMemcpyAsync(&bad, c->load_err, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (bad & PIC_ERR_NAN) return fail(c, PIC_ENAN, "non-finite particle state");
+  if (bad & PIC_ERR_RANGE) return fail(c, PIC_ERANGE, "particle outside the grid, walls or bond range");
+  s.n += n;
+  if (pic::sort_by_tile(c->g, c->tile, c->ntiles, s.sort, s.n, c->stream))
+    return fail(c, PIC_EHIP, "tile sort failed");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PIC_OK;
 }
 
 int pic_load_fields(pic_ctx* c, const double* E, const double* B) {
@@ -934,17 +985,21 @@ int pic_read_probes(pic_ctx* c, double* out, int64_t* nrec) {
   return PIC_OK;
 }
 
-int pic_timing(pic_ctx* c, double* total_ms, int64_t* launches, int32_t reset) {
+int pic_timing(pic_ctx* c, int32_t species_id, double* total_ms, int64_t* launches,
+               int32_t reset) {
   if (!c) return PIC_EINVAL;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   double tot = 0.0;
+  int64_t cnt = 0;
   for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+    if (species_id >= 0 && c->ev_species[i / 2] != species_id) continue;
     float ms = 0.f;
     HIPCHK(c, hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
     tot += ms;
+    cnt++;
   }
   if (total_ms) *total_ms = tot;
-  if (launches) *launches = (int64_t)(c->ev_used / 2);
+  if (launches) *launches = cnt;
   if (reset) c->ev_used = 0;
   return PIC_OK;
 }

@@ -149,22 +149,21 @@ def stratified_positions(rng, lo, hi, ppc, dx, ndim):
     """ppc particles per cell over cells lo..hi-1 (per dimension), cells
     enumerated x fastest; each particle uniform within its own sub-stratum
     along x (ppc slices) and uniform along the other dimensions."""
-    counts = [hi[d] - lo[d] for d in range(ndim)]
+    counts = [int(hi[d] - lo[d]) for d in range(ndim)]
     ncell = int(np.prod(counts))
     n = ncell * ppc
-    idx = np.arange(ncell, dtype=np.int64)
-    cell = np.empty((ncell, ndim), dtype=np.int64)
-    rem = idx.copy()
-    for d in range(ndim):
-        cell[:, d] = lo[d] + rem % counts[d]
-        rem //= counts[d]
-    cell = np.repeat(cell, ppc, axis=0)
-    sub = np.tile(np.arange(ppc, dtype=np.float64), ncell)
     x = np.empty((n, ndim), dtype=np.float64)
-    ux = rng.random(n)
-    x[:, 0] = (cell[:, 0] + (sub + ux) / ppc) * dx[0]
-    for d in range(1, ndim):
-        x[:, d] = (cell[:, d] + rng.random(n)) * dx[d]
+    # particle p lives in cell p // ppc, sub-stratum p % ppc
+    cidx = np.arange(n, dtype=np.int64) // ppc
+    sub = (np.arange(n, dtype=np.int64) % ppc).astype(np.float64)
+    rem = cidx
+    for d in range(ndim):
+        cd = (rem % counts[d]).astype(np.float64) + lo[d]
+        rem = rem // counts[d]
+        if d == 0:
+            x[:, 0] = (cd + (sub + rng.random(n)) / ppc) * dx[0]
+        else:
+            x[:, d] = (cd + rng.random(n)) * dx[d]
     return x
 
 
@@ -265,7 +264,10 @@ def ionised_slab_3d(n=(512, 256, 256), ppc: int = 8, steps: int = 500, precision
                     omega_pb: float = 0.9, a0: float = 0.05, waist_lambda: float = 8.0,
                     cycles: int = 10, wc_range=(1.5, 4.0), nu_per_omega: float = 0.01,
                     t_ion_ev: float = 1.0, t_e_ev: float = 10.0, electrons: bool = True,
-                    config_id: int = 3) -> Workload:
+                    x_cells=None, chunk: int = 0, config_id: int = 3) -> Workload:
+    """Medium filling the box between the particle walls.  x_cells = (lo, hi)
+    restricts the generated particles to those x planes (chunked loading of
+    the full-size case); each chunk draws from its own Philox streams."""
     dx = TWO_PI / 24.0
     dt = 0.98 * dx / math.sqrt(3.0)
     lam_m = 12.4e-9
@@ -281,9 +283,10 @@ def ionised_slab_3d(n=(512, 256, 256), ppc: int = 8, steps: int = 500, precision
     w = n_ion * dv / ppc
     ion = Species(TWO_BODY, q1, m1, q2, m2, weight=w, omega_c=0.5 * sum(wc_range), a_c=0.0,
                   nu_per_omega=nu_per_omega, name="Au_q1")
-    rng_i = rng_for(config_id, 0)
-    lo = [grid.pad, 0, 0]
-    hi = [n[0] - grid.pad, ny, nz]
+    xlo, xhi = (grid.pad, n[0] - grid.pad) if x_cells is None else x_cells
+    lo = [xlo, 0, 0]
+    hi = [xhi, ny, nz]
+    rng_i = rng_for(config_id, 2 * chunk)
     xi = stratified_positions(rng_i, lo, hi, ppc, grid.dx, 3)
     ni = xi.shape[0]
     uci = rng_i.normal(0.0, thermal_sigma(t_ion_ev, m1 + m2), size=(ni, 3))
@@ -291,12 +294,17 @@ def ionised_slab_3d(n=(512, 256, 256), ppc: int = 8, steps: int = 500, precision
     species = [(ion, Particles(x=xi, u1=uci, omega_c=wci))]
     if electrons:
         ele = Species(POINT, -1.0, 1.0, weight=w, name="e")
-        rng_e = rng_for(config_id, 1)
+        rng_e = rng_for(config_id, 2 * chunk + 1)
         xe = stratified_positions(rng_e, lo, hi, ppc, grid.dx, 3)
         ue = rng_e.normal(0.0, thermal_sigma(t_e_ev, 1.0), size=(xe.shape[0], 3))
         species.append((ele, Particles(x=xe, u1=ue)))
     return Workload("ionised_slab_3d", grid, species, steps, precision,
                     notes=f"{ni} two-body ions (+{ni if electrons else 0} electrons)")
+
+
+def ionised_slab_3d_count(n=(512, 256, 256), ppc: int = 8, pad: int = 3) -> int:
+    """Macro-ions (and, separately, free electrons) of the full slab."""
+    return (n[0] - 2 * pad) * n[1] * n[2] * ppc
 
 
 # --------------------------------------------------------------------------
@@ -379,3 +387,51 @@ WORKLOADS = {
     "mixed_precision_3d": mixed_precision_3d,
     "neutral_slab_2d": neutral_slab_2d,
 }
+
+
+# --------------------------------------------------------------------------
+# Device-side generation of the full-size 3D slab (benchmark inputs)
+# --------------------------------------------------------------------------
+
+def ionised_slab_3d_device_chunk(n=(512, 256, 256), ppc: int = 8, x_cells=(3, 35),
+                                 chunk: int = 0, device="cuda", wc_range=(1.5, 4.0),
+                                 t_ion_ev: float = 1.0, t_e_ev: float = 10.0,
+                                 config_id: int = 3):
+    """Same recipe as ionised_slab_3d for the x planes x_cells, drawn with
+    torch's Philox generator on the GPU (seed = base seed + config id, offset
+    by the chunk), returned as FP64 device tensors:
+    (x_ion, u_c_ion, omega_c_ion, x_e, u_e).  Holds no method arithmetic."""
+    import torch
+    dx = TWO_PI / 24.0
+    q1, m1, q2, m2 = gold_ion(78, 1.0)
+    ny, nz = n[1], n[2]
+    out = []
+    for sp in range(2):
+        g = torch.Generator(device=device)
+        g.manual_seed((BASE_SEED + config_id) * 1000003 + 2 * chunk + sp)
+        nxc = x_cells[1] - x_cells[0]
+        m = nxc * ny * nz * ppc
+        p = torch.arange(m, device=device, dtype=torch.int64)
+        cell = p // ppc
+        sub = (p % ppc).to(torch.float64)
+        cx = (cell % nxc).to(torch.float64) + x_cells[0]
+        rem = cell // nxc
+        cy = (rem % ny).to(torch.float64)
+        cz = (rem // ny).to(torch.float64)
+        x = torch.empty((m, 3), device=device, dtype=torch.float64)
+        x[:, 0] = (cx + (sub + torch.rand(m, generator=g, device=device,
+                                          dtype=torch.float64)) / ppc) * dx
+        x[:, 1] = (cy + torch.rand(m, generator=g, device=device, dtype=torch.float64)) * dx
+        x[:, 2] = (cz + torch.rand(m, generator=g, device=device, dtype=torch.float64)) * dx
+        del p, cell, sub, cx, cy, cz, rem
+        if sp == 0:
+            u = torch.randn((m, 3), generator=g, device=device, dtype=torch.float64)
+            u *= thermal_sigma(t_ion_ev, m1 + m2)
+            wc = torch.rand(m, generator=g, device=device, dtype=torch.float64)
+            wc = wc_range[0] + (wc_range[1] - wc_range[0]) * wc
+            out += [x, u, wc]
+        else:
+            u = torch.randn((m, 3), generator=g, device=device, dtype=torch.float64)
+            u *= thermal_sigma(t_e_ev, 1.0)
+            out += [x, u]
+    return tuple(out)

@@ -76,6 +76,7 @@ SIGNATURES = [
     ("pic_create", C.c_int, [C.POINTER(PicConfig), C.POINTER(PicAllocator), _P, C.POINTER(_P)]),
     ("pic_add_species", C.c_int, [_P, C.POINTER(PicSpeciesDesc), C.POINTER(C.c_int32)]),
     ("pic_load_particles", C.c_int, [_P, C.c_int32, C.c_int64, _D, _D, _D, _D, _D, _D]),
+    ("pic_load_particles_device", C.c_int, [_P, C.c_int32, C.c_int64, _P, _P, _P, _P, _P, _P]),
     ("pic_load_fields", C.c_int, [_P, _D, _D]),
     ("pic_step", C.c_int, [_P, C.c_int32]),
     ("pic_diagnostics", C.c_int, [_P, C.POINTER(PicDiag)]),
@@ -86,7 +87,7 @@ SIGNATURES = [
     ("pic_rho", C.c_int, [_P, _D]),
     ("pic_set_probes", C.c_int, [_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
     ("pic_read_probes", C.c_int, [_P, _D, C.POINTER(C.c_int64)]),
-    ("pic_timing", C.c_int, [_P, _D, C.POINTER(C.c_int64), C.c_int32]),
+    ("pic_timing", C.c_int, [_P, C.c_int32, _D, C.POINTER(C.c_int64), C.c_int32]),
     ("pic_last_error", C.c_char_p, [_P]),
     ("pic_destroy", None, [_P]),
     ("pic_version", C.c_char_p, []),
@@ -231,6 +232,28 @@ class Simulation:
         self._check(self.lib.pic_load_particles(self.ctx, sid, n, _dp(x), _dp(delta), _dp(u1),
                                                 _dp(u2), _dp(wc), _dp(w)))
 
+    def load_particles_device(self, sid: int, x, u1, delta=None, u2=None, omega_c=None,
+                              weight=None) -> None:
+        """Append particles from FP64 torch tensors on the context's device."""
+        import torch
+        n = int(x.shape[0])
+        keep = []
+
+        def ptr(t, cols):
+            if t is None:
+                return None
+            t = t.to(device=self.device, dtype=torch.float64).contiguous()
+            if t.numel() != n * cols:
+                raise ValueError("particle array has the wrong size")
+            keep.append(t)
+            return C.c_void_p(t.data_ptr())
+
+        args = [ptr(x, self.ndim), ptr(delta, 3), ptr(u1, 3), ptr(u2, 3), ptr(omega_c, 1),
+                ptr(weight, 1)]
+        torch.cuda.current_stream(self.device).synchronize()
+        self._check(self.lib.pic_load_particles_device(self.ctx, sid, n, *args))
+        del keep
+
     @classmethod
     def from_workload(cls, wl, precision: Optional[int] = None, flags: int = 0, **kw):
         sim = cls(wl.grid, precision=precision or wl.precision, flags=flags, **kw)
@@ -310,8 +333,10 @@ class Simulation:
         self._check(self.lib.pic_read_probes(self.ctx, _dp(out), C.byref(n)))
         return out
 
-    def timing(self, reset: bool = True):
+    def timing(self, species: int = -1, reset: bool = True):
+        """(total ms, launches) of the particle kernels of one species (-1: all)."""
         ms = C.c_double()
         nl = C.c_int64()
-        self._check(self.lib.pic_timing(self.ctx, C.byref(ms), C.byref(nl), int(reset)))
+        self._check(self.lib.pic_timing(self.ctx, int(species), C.byref(ms), C.byref(nl),
+                                        int(reset)))
         return ms.value, nl.value

@@ -259,3 +259,34 @@ def test_timing_events(pic):
     s.step(3)
     ms, n = s.timing()
     assert n == 6 and ms > 0
+
+
+def test_device_loader_matches_host_loader(pic):
+    """Loading the same FP64 arrays from device memory gives the same state
+    as the host loader: cells, offsets and delta bit-identical, momenta
+    (through the Sec. 2 split of a charged ion's momentum) to round-off."""
+    import torch
+    _say("case: device loader vs host loader")
+    for prec in (64, 32):
+        wl = random_workload(3, 2000, 1000, seed=91)
+        sp, parts = wl.species[0]
+        parts.u2 = None          # exercise the split
+        parts.delta = None
+        a = pic.Simulation.from_workload(wl, precision=prec, flags=pic.TRACK_IDS)
+        b = pic.Simulation(wl.grid, precision=prec, flags=pic.TRACK_IDS)
+        for s_, p_ in wl.species:
+            sid = b.add_species(s_, p_.n)
+            t = lambda v: None if v is None else torch.from_numpy(v).cuda()
+            b.load_particles_device(sid, t(p_.x), t(p_.u1), delta=t(p_.delta), u2=t(p_.u2),
+                                    omega_c=t(p_.omega_c), weight=t(p_.weight))
+        for sid in range(2):
+            ga = a.particles(sid, ids=True)
+            gb = b.particles(sid, ids=True)
+            ga = match_by_id(ga, ga["id"])
+            gb = match_by_id(gb, gb["id"])
+            for k in ("cell", "off", "delta"):
+                assert np.array_equal(ga[k], gb[k]), (prec, sid, k)
+            # the split's Newton iteration may contract multiply-adds differently
+            for k in ("u1", "u2"):
+                scale = max(np.abs(ga[k]).max(), 1e-300)
+                assert np.abs(ga[k] - gb[k]).max() <= 2e-15 * scale * (1 if prec == 64 else 1e9)
