@@ -63,6 +63,8 @@ typedef enum {
 #define PIC_FLAG_CHARGE_CHECK 4u  /* continuity residual of the last step of each pic_step */
 #define PIC_FLAG_TRACK_IDS 8u     /* keep each particle's load index through sorts */
 #define PIC_FLAG_TIMING 16u       /* time the particle kernels with HIP events */
+#define PIC_FLAG_GLOBAL_KERNEL 32u /* advance particles from HBM with global atomics
+                                      instead of the LDS-tiled kernel */
 
 /* species kinds */
 #define PIC_POINT 0
@@ -131,6 +133,7 @@ typedef struct {
   double rho_l2;          /* L2 norm of (rho^{n+1} - rho^n)/dt */
   int64_t n_particles;
   uint32_t error_word, reserved;
+  int64_t n_outside_tile; /* particles of the last step advanced outside their tile */
 } pic_diag;
 
 typedef struct pic_ctx pic_ctx;

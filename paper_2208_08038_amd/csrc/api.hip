@@ -17,6 +17,7 @@
 #include "pic_internal.h"
 #include "sort.h"
 #include "load.h"
+#include "tiled.h"
 
 using pic::GridInfo;
 
@@ -38,6 +39,8 @@ struct SpeciesHost {
   void* w = nullptr;
   pic::SortBuffers sort{};
   int64_t* ids = nullptr;  // device load indices (TRACK_IDS)
+  uint32_t* outside = nullptr;  // particles listed as outside their tile (tiled kernel)
+  bool needs_sort = true;  // tile offsets stale (after a load)
 };
 
 }  // namespace
@@ -55,6 +58,9 @@ struct pic_ctx {
   void* mur_e[3][2] = {};
   uint32_t* err = nullptr;
   uint32_t* load_err = nullptr;
+  uint32_t* nslow = nullptr;   // [0]: list length scratch, [1]: listed this step
+  bool tiled = false;
+  pic::TileGeom tg{};
   double* partials = nullptr;
   double* dout = nullptr;  // 32 doubles: [0..3] scratch, [4..6] residual, ...
   double* rho0 = nullptr;
@@ -379,6 +385,7 @@ int load_particles_t(pic_ctx* c, SpeciesHost& s, int64_t n, const double* x, con
   }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   s.n += n;
+  s.needs_sort = true;
   return PIC_OK;
 }
 
@@ -429,22 +436,33 @@ int step_t(pic_ctx* c, int nsteps) {
   las.on = (c->cfg.bc_lo[0] == PIC_BC_LASER && c->cfg.laser.a0 != 0.0) ? 1 : 0;
   for (int it = 0; it < nsteps; it++) {
     const bool check = (c->cfg.flags & PIC_FLAG_CHARGE_CHECK) && it == nsteps - 1;
-    // tile sort on its cadence
-    if (c->sort_every > 0 && c->steps_since_sort >= c->sort_every) {
-      for (auto& s : c->sp) {
-        int rc = pic::sort_by_tile(g, c->tile, c->ntiles, s->sort, s->n, c->stream);
-        if (rc) return fail(c, PIC_EHIP, "tile sort launch failed");
-      }
-      c->steps_since_sort = 0;
+    // tile sort on its cadence, and always after a load
+    const bool cadence = c->sort_every > 0 && c->steps_since_sort >= c->sort_every;
+    for (auto& s : c->sp) {
+      if (!(cadence || s->needs_sort)) continue;
+      int rc = pic::sort_by_tile(g, c->tile, c->ntiles, s->sort, s->n, c->stream);
+      if (rc) return fail(c, PIC_EHIP, "tile sort launch failed");
+      s->needs_sort = false;
     }
+    if (cadence) c->steps_since_sort = 0;
     pic::launch_fill_periodic<Real>(g, eb, 6, c->stream);
     pic::launch_zero<Real>(f.J[0], 3 * g.plane, c->stream);
     if (check) deposit_rho<Real>(c, c->rho0);
+    if (c->tiled) HIPCHK(c, hipMemsetAsync(c->nslow + 1, 0, sizeof(uint32_t), c->stream));
     for (size_t si = 0; si < c->sp.size(); si++) {
       auto& s = c->sp[si];
       bool timed = record_event(c, (int)si, true);
-      pic::launch_push<Real>(g, f, species_dev<Real>(*s), push_const<Real>(c, *s), c->err,
-                             c->stream);
+      if (c->tiled) {
+        hipError_t e = pic::launch_push_tiled<Real>(g, f, species_dev<Real>(*s),
+                                                    push_const<Real>(c, *s), c->tg,
+                                                    s->sort.tile_off, s->outside, c->nslow,
+                                                    c->nslow + 1, c->err, c->stream);
+        if (e != hipSuccess)
+          return fail(c, PIC_EHIP, std::string("tiled particle kernel: ") + hipGetErrorString(e));
+      } else {
+        pic::launch_push<Real>(g, f, species_dev<Real>(*s), push_const<Real>(c, *s), c->err,
+                               c->stream);
+      }
       if (timed) record_event(c, (int)si, false);
       c->launches++;
     }
@@ -520,8 +538,9 @@ int diagnostics_t(pic_ctx* c, pic_diag* out) {
     ke += k4[0];
     for (int a = 0; a < 3; a++) pm[a] += k4[1 + a];
   }
-  uint32_t ew = 0;
+  uint32_t ew = 0, ns = 0;
   HIPCHK(c, hipMemcpyAsync(&ew, c->err, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(&ns, c->nslow + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   out->step = c->step;
   out->time = (double)c->step * c->cfg.dt;
@@ -529,6 +548,7 @@ int diagnostics_t(pic_ctx* c, pic_diag* out) {
   for (int a = 0; a < 3; a++) out->momentum[a] = pm[a];
   out->n_particles = np;
   out->error_word = ew;
+  out->n_outside_tile = c->tiled ? (int64_t)ns : 0;
   if (ew & PIC_ERR_NAN) return fail(c, PIC_ENAN, "non-finite particle state on the device");
   if (ew & PIC_ERR_RANGE) return fail(c, PIC_ERANGE, "particle out of range on the device");
   return PIC_OK;
@@ -695,6 +715,12 @@ int pic_create(const pic_config* cfg, const pic_allocator* alloc, void* hip_stre
       return fail(nullptr, PIC_EINVAL, "grid too small for the particle walls");
   }
   if (bits > 31) return fail(nullptr, PIC_EINVAL, "grid too large for the packed cell index");
+  {
+    int64_t plane = 1;
+    for (int d = 0; d < cfg->ndim; d++) plane *= cfg->n[d] + 2 * pic::kGuard;
+    if (plane >= (int64_t(1) << 31))
+      return fail(nullptr, PIC_EINVAL, "field plane exceeds 2^31 values (32-bit indexing)");
+  }
   if (!(cfg->dt * std::sqrt(inv2) < 1.0))
     return fail(nullptr, PIC_EINVAL, "time step violates the CFL limit");
 
@@ -735,16 +761,19 @@ int pic_create(const pic_config* cfg, const pic_allocator* alloc, void* hip_stre
     c->ntiles[d] = (g.n[d] + c->tile[d] - 1) / c->tile[d];
   }
   c->sort_every = cfg->sort_every > 0 ? cfg->sort_every : 4;
+  c->tg = pic::make_tile_geom(g, c->tile, c->ntiles);
+  c->tiled = !(cfg->flags & PIC_FLAG_GLOBAL_KERNEL) && pic::tiled_supported(g, c->tg, c->rsize);
 
   size_t rs = c->rsize;
   c->fields = dev_alloc(c, 9 * g.plane * rs);
   c->err = static_cast<uint32_t*>(dev_alloc(c, 256));
   c->load_err = static_cast<uint32_t*>(dev_alloc(c, 256));
+  c->nslow = static_cast<uint32_t*>(dev_alloc(c, 256));
   c->partials = static_cast<double*>(dev_alloc(c, 8 * pic::reduce_blocks() * sizeof(double)));
   c->dout = static_cast<double*>(dev_alloc(c, 32 * sizeof(double)));
   c->rho0 = static_cast<double*>(dev_alloc(c, g.plane * sizeof(double)));
   c->rho1 = static_cast<double*>(dev_alloc(c, g.plane * sizeof(double)));
-  if (!c->fields || !c->err || !c->load_err || !c->partials || !c->dout || !c->rho0 || !c->rho1) {
+  if (!c->fields || !c->err || !c->load_err || !c->nslow || !c->partials || !c->dout || !c->rho0 || !c->rho1) {
     dev_free_all(c);
     delete c;
     return fail(nullptr, PIC_ENOMEM, "device allocation failed");
@@ -765,6 +794,7 @@ int pic_create(const pic_config* cfg, const pic_allocator* alloc, void* hip_stre
   }
   hipError_t e = hipMemsetAsync(c->fields, 0, 9 * g.plane * rs, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->err, 0, 256, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->nslow, 0, 256, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->dout, 0, 32 * sizeof(double), c->stream);
   for (int d = 0; d < g.nd && e == hipSuccess; d++) {
     if (g.periodic[d]) continue;
@@ -825,6 +855,7 @@ int pic_add_species(pic_ctx* c, const pic_species_desc* d, int32_t* sid) {
   }
   if (c->cfg.flags & PIC_FLAG_TRACK_IDS)
     ok = ok && (s.ids = static_cast<int64_t*>(dev_alloc(c, n * sizeof(int64_t))));
+  if (c->tiled) ok = ok && (s.outside = static_cast<uint32_t*>(dev_alloc(c, n * 4)));
   if (!ok) return fail(c, PIC_ENOMEM, "device allocation failed");
   pic::AllocFn af = [c](size_t b) { return dev_alloc(c, b); };
   int rc = pic::sort_alloc(c->g, c->ntiles, s.cap, af, s.sort);
@@ -886,6 +917,7 @@ int pic_load_particles_device(pic_ctx* c, int32_t sid, int64_t n, const double* 
   s.n += n;
   if (pic::sort_by_tile(c->g, c->tile, c->ntiles, s.sort, s.n, c->stream))
     return fail(c, PIC_EHIP, "tile sort failed");
+  s.needs_sort = false;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return PIC_OK;
 }

@@ -1,0 +1,582 @@
+// cycle.h -- device code of one particle cycle, shared by the global and the
+// LDS-tiled particle kernels: quadratic B-spline gather at the Yee
+// staggers, softened bond force between nucleus and bound-electron cloud
+// (An, Chen, Sheng, Zhang, arXiv 2208.08038, Sec. 2 and Sec. 3.1),
+// optional friction on the relative momentum, relativistic Boris push of
+// each body (Sec. 2), move of centre of mass and relative displacement,
+// reflecting walls, integer cell crossing, Esirkepov current deposit.
+//
+// Indices into field planes and LDS patches are 32-bit (a plane holds
+// fewer than 2^31 values; the host checks it), which keeps address
+// arithmetic in single VGPRs.
+#pragma once
+
+#include "pic_internal.h"
+
+namespace pic {
+
+template <typename Real>
+struct Weights {
+  int i0;  // first node, relative to the particle's cell
+  Real w0, w1, w2;
+};
+
+// Quadratic B-spline weights on the integer-staggered nodes: nearest node
+// i_n = floor(x + 1/2), d = x - i_n, weights at i_n-1, i_n, i_n+1.
+template <typename Real>
+__device__ __forceinline__ Weights<Real> weights_int(Real x) {
+  Weights<Real> r;
+  Real f = floor(x + Real(0.5));
+  Real d = x - f;
+  Real a = Real(0.5) - d, b = Real(0.5) + d;
+  r.i0 = static_cast<int>(f) - 1;
+  r.w0 = Real(0.5) * a * a;
+  r.w1 = Real(0.75) - d * d;
+  r.w2 = Real(0.5) * b * b;
+  return r;
+}
+
+// Same on the half-staggered nodes (positions i + 1/2, storage index i):
+// nearest i_h = floor(x), d = x - i_h - 1/2.
+template <typename Real>
+__device__ __forceinline__ Weights<Real> weights_half(Real x) {
+  Weights<Real> r;
+  Real f = floor(x);
+  Real d = x - f - Real(0.5);
+  Real a = Real(0.5) - d, b = Real(0.5) + d;
+  r.i0 = static_cast<int>(f) - 1;
+  r.w0 = Real(0.5) * a * a;
+  r.w1 = Real(0.75) - d * d;
+  r.w2 = Real(0.5) * b * b;
+  return r;
+}
+
+template <typename Real>
+__device__ __forceinline__ Weights<Real> unit_weights() {
+  Weights<Real> r;
+  r.i0 = 0;
+  r.w0 = Real(1);
+  r.w1 = Real(0);
+  r.w2 = Real(0);
+  return r;
+}
+
+template <typename Real>
+__device__ __forceinline__ Real row3(const Real* p, const Weights<Real>& wx) {
+  return wx.w0 * p[0] + wx.w1 * p[1] + wx.w2 * p[2];
+}
+
+template <typename Real, int ND>
+__device__ __forceinline__ Real interp(const Real* __restrict__ F, int base, int sy, int sz,
+                                       const Weights<Real>& wx, const Weights<Real>& wy,
+                                       const Weights<Real>& wz) {
+  const Real* p = F + base + wx.i0;
+  if constexpr (ND == 1) {
+    return row3(p, wx);
+  } else if constexpr (ND == 2) {
+    p += wy.i0 * sy;
+    return wy.w0 * row3(p, wx) + wy.w1 * row3(p + sy, wx) + wy.w2 * row3(p + 2 * sy, wx);
+  } else {
+    p += wy.i0 * sy + wz.i0 * sz;
+    Real s = 0;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      const Real* q = p + c * sz;
+      Real t = wy.w0 * row3(q, wx) + wy.w1 * row3(q + sy, wx) + wy.w2 * row3(q + 2 * sy, wx);
+      s += (c == 0 ? wz.w0 : (c == 1 ? wz.w1 : wz.w2)) * t;
+    }
+    return s;
+  }
+}
+
+// Gather E and B at a position x (cell units, relative to the cell whose
+// index is `base`).  E_a is half-staggered along a; B_a along the two
+// other axes.
+template <typename Real, int ND>
+__device__ __forceinline__ void gather(const FieldPtrs<Real>& f, int base, int sy, int sz,
+                                       const Real x[3], Real E[3], Real B[3]) {
+  Weights<Real> n0 = weights_int(x[0]), h0 = weights_half(x[0]);
+  Weights<Real> n1 = unit_weights<Real>(), h1 = unit_weights<Real>();
+  Weights<Real> n2 = unit_weights<Real>(), h2 = unit_weights<Real>();
+  if constexpr (ND > 1) {
+    n1 = weights_int(x[1]);
+    h1 = weights_half(x[1]);
+  }
+  if constexpr (ND > 2) {
+    n2 = weights_int(x[2]);
+    h2 = weights_half(x[2]);
+  }
+  E[0] = interp<Real, ND>(f.E[0], base, sy, sz, h0, n1, n2);
+  E[1] = interp<Real, ND>(f.E[1], base, sy, sz, n0, h1, n2);
+  E[2] = interp<Real, ND>(f.E[2], base, sy, sz, n0, n1, h2);
+  B[0] = interp<Real, ND>(f.B[0], base, sy, sz, n0, h1, h2);
+  B[1] = interp<Real, ND>(f.B[1], base, sy, sz, h0, n1, h2);
+  B[2] = interp<Real, ND>(f.B[2], base, sy, sz, h0, h1, n2);
+}
+
+// Shape of a body at its old (x0) and new (x1) position on a common
+// 4-node window starting at node `lo` (relative to the cell).  Returns
+// false if the two nearest nodes are more than one node apart.
+template <typename Real>
+struct Window {
+  int lo;
+  Real S0[4], DS[4];
+};
+
+template <typename Real>
+__device__ __forceinline__ bool window(Real x0, Real x1, Window<Real>& win) {
+  Real f0 = floor(x0 + Real(0.5)), f1 = floor(x1 + Real(0.5));
+  Real d0 = x0 - f0, d1 = x1 - f1;
+  int i0 = static_cast<int>(f0), i1 = static_cast<int>(f1);
+  int lo = min(i0, i1);
+  int s0 = i0 - lo, s1 = i1 - lo;
+  if (s0 > 1 || s1 > 1) return false;
+  Real a0 = Real(0.5) - d0, b0 = Real(0.5) + d0;
+  Real a1 = Real(0.5) - d1, b1 = Real(0.5) + d1;
+  Real w00 = Real(0.5) * a0 * a0, w01 = Real(0.75) - d0 * d0, w02 = Real(0.5) * b0 * b0;
+  Real w10 = Real(0.5) * a1 * a1, w11 = Real(0.75) - d1 * d1, w12 = Real(0.5) * b1 * b1;
+  Real S0[4], S1[4];
+  S0[0] = s0 ? Real(0) : w00;
+  S0[1] = s0 ? w00 : w01;
+  S0[2] = s0 ? w01 : w02;
+  S0[3] = s0 ? w02 : Real(0);
+  S1[0] = s1 ? Real(0) : w10;
+  S1[1] = s1 ? w10 : w11;
+  S1[2] = s1 ? w11 : w12;
+  S1[3] = s1 ? w12 : Real(0);
+  win.lo = lo - 1;
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    win.S0[k] = S0[k];
+    win.DS[k] = S1[k] - S0[k];
+  }
+  return true;
+}
+
+// Floating-point add into the current (accumulator type JT, which may be
+// wider than the arithmetic type): LDS patches take every term, global
+// planes skip exact zeros (fewer atomics).
+template <bool GLOBAL, typename JT, typename Real>
+__device__ __forceinline__ void jadd(JT* p, Real v) {
+  if constexpr (GLOBAL) {
+    if (v != Real(0)) unsafeAtomicAdd(p, (JT)v);
+  } else {
+    unsafeAtomicAdd(p, (JT)v);
+  }
+}
+
+// Esirkepov deposit of one body with charge Q (= q * weight) moving from
+// x0 to x1 (cell units relative to the cell at index `base`).  The current
+// along a resolved axis is the running sum of the decomposition
+// W_a = DS_a * (shape of the other axes averaged over the straight path);
+// along an unresolved axis it is Q v times the path-averaged shape.
+template <typename Real, int ND, bool GLOBAL, typename JT>
+__device__ __forceinline__ bool deposit(JT* const J[3], int base, int sy, int sz,
+                                        const Real x0[3], const Real x1[3], Real Q,
+                                        const Real v[3], const PushConst<Real>& c) {
+  const Real third = Real(1) / Real(3);
+  if constexpr (ND == 1) {
+    Window<Real> wx;
+    if (!window(x0[0], x1[0], wx)) return false;
+    Real fx = Q * c.jf[0];
+    Real fy = Q * v[1] * c.inv_dv, fz = Q * v[2] * c.inv_dv;
+    Real C = 0;
+    const int o = base + wx.lo;
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      Real A = wx.S0[r] + Real(0.5) * wx.DS[r];
+      if (r < 3) {
+        C += wx.DS[r];
+        jadd<GLOBAL>(J[0] + o + r, fx * C);
+      }
+      jadd<GLOBAL>(J[1] + o + r, fy * A);
+      jadd<GLOBAL>(J[2] + o + r, fz * A);
+    }
+  } else if constexpr (ND == 2) {
+    Window<Real> wx, wy;
+    if (!window(x0[0], x1[0], wx) || !window(x0[1], x1[1], wy)) return false;
+    Real fx = Q * c.jf[0], fy = Q * c.jf[1], fz = Q * v[2] * c.inv_dv;
+    const int o = base + wx.lo + wy.lo * sy;
+    // J_x = f_x C_x(r) (S0y + DSy/2)(s)
+    {
+      Real C = 0;
+#pragma unroll
+      for (int r = 0; r < 3; r++) {
+        C += wx.DS[r];
+        Real a = fx * C;
+#pragma unroll
+        for (int s = 0; s < 4; s++)
+          jadd<GLOBAL>(J[0] + o + r + s * sy, a * (wy.S0[s] + Real(0.5) * wy.DS[s]));
+      }
+    }
+    // J_y = f_y C_y(s) (S0x + DSx/2)(r)
+    {
+      Real C = 0;
+#pragma unroll
+      for (int s = 0; s < 3; s++) {
+        C += wy.DS[s];
+        Real a = fy * C;
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+          jadd<GLOBAL>(J[1] + o + r + s * sy, a * (wx.S0[r] + Real(0.5) * wx.DS[r]));
+      }
+    }
+    // J_z = f_z [S0x (S0y + DSy/2) + DSx (S0y/2 + DSy/3)]
+#pragma unroll
+    for (int s = 0; s < 4; s++) {
+      Real ay = wy.S0[s] + Real(0.5) * wy.DS[s];
+      Real by = Real(0.5) * wy.S0[s] + third * wy.DS[s];
+#pragma unroll
+      for (int r = 0; r < 4; r++)
+        jadd<GLOBAL>(J[2] + o + r + s * sy, fz * (wx.S0[r] * ay + wx.DS[r] * by));
+    }
+  } else {
+    Window<Real> wx, wy, wz;
+    if (!window(x0[0], x1[0], wx) || !window(x0[1], x1[1], wy) || !window(x0[2], x1[2], wz))
+      return false;
+    const int o = base + wx.lo + wy.lo * sy + wz.lo * sz;
+    // J_x = f_x C_x(r) [S0y (S0z + DSz/2) + DSy (S0z/2 + DSz/3)](s, t)
+    {
+      Real fx = Q * c.jf[0];
+      Real C0 = wx.DS[0], C1 = C0 + wx.DS[1], C2 = C1 + wx.DS[2];
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        Real az = wz.S0[t] + Real(0.5) * wz.DS[t];
+        Real bz = Real(0.5) * wz.S0[t] + third * wz.DS[t];
+#pragma unroll
+        for (int s = 0; s < 4; s++) {
+          Real T = fx * (wy.S0[s] * az + wy.DS[s] * bz);
+          JT* p = J[0] + o + s * sy + t * sz;
+          jadd<GLOBAL>(p, C0 * T);
+          jadd<GLOBAL>(p + 1, C1 * T);
+          jadd<GLOBAL>(p + 2, C2 * T);
+        }
+      }
+    }
+    // J_y = f_y C_y(s) [S0x (S0z + DSz/2) + DSx (S0z/2 + DSz/3)](r, t)
+    {
+      Real fy = Q * c.jf[1];
+      Real C0 = wy.DS[0], C1 = C0 + wy.DS[1], C2 = C1 + wy.DS[2];
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        Real az = wz.S0[t] + Real(0.5) * wz.DS[t];
+        Real bz = Real(0.5) * wz.S0[t] + third * wz.DS[t];
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          Real T = fy * (wx.S0[r] * az + wx.DS[r] * bz);
+          JT* p = J[1] + o + r + t * sz;
+          jadd<GLOBAL>(p, C0 * T);
+          jadd<GLOBAL>(p + sy, C1 * T);
+          jadd<GLOBAL>(p + 2 * sy, C2 * T);
+        }
+      }
+    }
+    // J_z = f_z C_z(t) [S0x (S0y + DSy/2) + DSx (S0y/2 + DSy/3)](r, s)
+    {
+      Real fz = Q * c.jf[2];
+      Real C0 = wz.DS[0], C1 = C0 + wz.DS[1], C2 = C1 + wz.DS[2];
+#pragma unroll
+      for (int s = 0; s < 4; s++) {
+        Real ay = wy.S0[s] + Real(0.5) * wy.DS[s];
+        Real by = Real(0.5) * wy.S0[s] + third * wy.DS[s];
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          Real T = fz * (wx.S0[r] * ay + wx.DS[r] * by);
+          JT* p = J[2] + o + r + s * sy;
+          jadd<GLOBAL>(p, C0 * T);
+          jadd<GLOBAL>(p + sz, C1 * T);
+          jadd<GLOBAL>(p + 2 * sz, C2 * T);
+        }
+      }
+    }
+  }
+  return true;
+}
+
+template <typename Real>
+__device__ __forceinline__ void boris_rotate_kick(const Real um[3], Real a, const Real E[3],
+                                                  const Real B[3], Real out[3]) {
+  Real gm = sqrt(Real(1) + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
+  Real k = a / gm;
+  Real t0 = k * B[0], t1 = k * B[1], t2 = k * B[2];
+  Real tt = t0 * t0 + t1 * t1 + t2 * t2;
+  Real sk = Real(2) / (Real(1) + tt);
+  Real s0 = sk * t0, s1 = sk * t1, s2 = sk * t2;
+  Real w0 = um[0] + (um[1] * t2 - um[2] * t1);
+  Real w1 = um[1] + (um[2] * t0 - um[0] * t2);
+  Real w2 = um[2] + (um[0] * t1 - um[1] * t0);
+  out[0] = um[0] + (w1 * s2 - w2 * s1) + a * E[0];
+  out[1] = um[1] + (w2 * s0 - w0 * s2) + a * E[1];
+  out[2] = um[2] + (w0 * s1 - w1 * s0) + a * E[2];
+}
+
+// Reflecting walls `pad` cells inside non-periodic faces.  off: new offset
+// relative to the old cell index ci (before the crossing rule).
+template <typename Real>
+__device__ __forceinline__ bool reflect(int periodic, int ci, int n, int pad, Real& off) {
+  if (periodic) return false;
+  int wl = pad, wr = n - pad;
+  if (ci == wl && off < Real(0)) {
+    off = -off;
+    return true;
+  }
+  if (ci == wr - 1 && off > Real(1)) {
+    off = Real(2) - off;
+    return true;
+  }
+  if (ci == wr && off > Real(0)) {
+    off = -off;
+    return true;
+  }
+  return false;
+}
+
+// Integer cell-crossing rule; returns false if the new cell would leave
+// the grid along a non-periodic axis.
+template <typename Real>
+__device__ __forceinline__ bool cross(int periodic, int n, int& ci, Real& off) {
+  if (off >= Real(1)) {
+    ci += 1;
+    off -= Real(1);
+  } else if (off < Real(0)) {
+    ci -= 1;
+    off += Real(1);
+  }
+  if (periodic) {
+    if (ci >= n) ci -= n;
+    if (ci < 0) ci += n;
+    return true;
+  }
+  return ci >= 0 && ci < n;
+}
+
+template <typename Real>
+__device__ __forceinline__ bool finite3(const Real v[3]) {
+  return isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]);
+}
+
+// Decode the packed cell index (i | j << bx | k << (bx + by)).
+template <int ND>
+__device__ __forceinline__ void decode_cell(const GridInfo& g, uint32_t packed, int ci[3]) {
+  ci[0] = packed & ((1u << g.bits[0]) - 1u);
+  ci[1] = ND > 1 ? (packed >> g.bits[0]) & ((1u << g.bits[1]) - 1u) : 0;
+  ci[2] = ND > 2 ? (packed >> (g.bits[0] + g.bits[1])) : 0;
+}
+
+template <int ND>
+__device__ __forceinline__ uint32_t encode_cell(const GridInfo& g, const int cn[3]) {
+  uint32_t pk = (uint32_t)cn[0];
+  if (ND > 1) pk |= (uint32_t)cn[1] << g.bits[0];
+  if (ND > 2) pk |= (uint32_t)cn[2] << (g.bits[0] + g.bits[1]);
+  return pk;
+}
+
+// Advance macro-particle p through one full cycle.  Gather reads E, B
+// through `fg` at index `fbase` of the particle's cell (strides fsy, fsz);
+// the deposit adds into J at `jbase` (strides jsy, jsz).  GLOBAL selects
+// the HBM form of the deposit (atomics, zero terms skipped).
+template <typename Real, int ND, bool TWO, bool GLOBAL, typename JT = Real>
+__device__ __forceinline__ void advance_particle(const GridInfo& g, const SpeciesDev<Real>& s,
+                                                 const PushConst<Real>& c, int64_t p,
+                                                 const int ci[3], const FieldPtrs<Real>& fg,
+                                                 int fbase, int fsy, int fsz, JT* const J[3],
+                                                 int jbase, int jsy, int jsz, uint32_t* err) {
+  Real off[3] = {0, 0, 0};
+#pragma unroll
+  for (int d = 0; d < ND; d++) off[d] = s.off[d][p];
+  Real u1[3], u2[3] = {0, 0, 0}, dl[3] = {0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < 3; q++) u1[q] = s.u1[q][p];
+  if constexpr (TWO) {
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+      u2[q] = s.u2[q][p];
+      dl[q] = s.dl[q][p];
+    }
+  }
+  const Real W = s.w ? s.w[p] : Real(1);
+
+  // body positions (cell units, relative to the cell)
+  Real x1[3] = {0, 0, 0}, x2[3] = {0, 0, 0};
+  bool finite = finite3(u1) && finite3(u2) && finite3(dl);
+  bool inside = true;
+#pragma unroll
+  for (int d = 0; d < ND; d++) {
+    finite = finite && isfinite(off[d]);
+    inside = inside && (off[d] >= Real(0)) && (off[d] <= Real(1));
+    if constexpr (TWO) {
+      Real sd = dl[d] * c.idx[d];
+      inside = inside && (fabs(sd) < Real(0.5));
+      x1[d] = off[d] + c.f1 * sd;
+      x2[d] = off[d] - c.f2 * sd;
+    } else {
+      x1[d] = off[d];
+    }
+  }
+  if (!finite || !inside) {
+    // a particle that cannot be gathered safely is left untouched
+    atomicOr(err, finite ? PIC_ERR_RANGE : PIC_ERR_NAN);
+    return;
+  }
+
+  if constexpr (TWO) {
+    const Real wc = s.wc ? s.wc[p] : c.omega_c;
+    // softened Coulomb bond: F1 = -m_r w_c^2 delta (1 + |delta|^2/a_c^2)^{-3/2}
+    Real r2 = dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2];
+    Real soft = Real(1);
+    if (c.inv_ac2 != Real(0)) {
+      Real rq = Real(1) / sqrt(Real(1) + r2 * c.inv_ac2);
+      soft = rq * rq * rq;
+    }
+    const Real kf = -c.mr * wc * wc * soft;
+    // one body at a time (loop not unrolled: a single copy of the gather
+    // keeps the live register set small); E and B are kept per body for
+    // the second half kick
+    Real E1[3], B1[3], E2[3], B2[3];
+#pragma unroll 1
+    for (int body = 0; body < 2; body++) {
+      Real xb[3], Eb[3], Bb[3];
+#pragma unroll
+      for (int d = 0; d < 3; d++) xb[d] = body == 0 ? x1[d] : x2[d];
+      gather<Real, ND>(fg, fbase, fsy, fsz, xb, Eb, Bb);
+#pragma unroll
+      for (int q = 0; q < 3; q++) {
+        E1[q] = body == 0 ? Eb[q] : E1[q];
+        B1[q] = body == 0 ? Bb[q] : B1[q];
+        E2[q] = body == 0 ? E2[q] : Eb[q];
+        B2[q] = body == 0 ? B2[q] : Bb[q];
+      }
+    }
+    Real um1[3], um2[3];
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+      Real F = kf * dl[q];
+      E1[q] += F * c.inv_q1;
+      E2[q] -= F * c.inv_q2;
+      um1[q] = u1[q] + c.a1 * E1[q];
+      um2[q] = u2[q] + c.a2 * E2[q];
+    }
+    const Real nu = c.nu + c.nu_per_omega * wc;
+    if (nu > Real(0)) {
+      // time-centred friction on the relative momentum; m1 u1 + m2 u2 kept
+      Real D = (Real(1) - nu * c.half_dt) / (Real(1) + nu * c.half_dt);
+#pragma unroll
+      for (int q = 0; q < 3; q++) {
+        Real V = (c.m1 * um1[q] + c.m2 * um2[q]) * c.inv_mc;
+        Real w = (um1[q] - um2[q]) * D;
+        um1[q] = V + c.f1 * w;
+        um2[q] = V - c.f2 * w;
+      }
+    }
+    Real n1[3], n2[3];
+    boris_rotate_kick(um1, c.a1, E1, B1, n1);
+    boris_rotate_kick(um2, c.a2, E2, B2, n2);
+    Real ig1 = Real(1) / sqrt(Real(1) + n1[0] * n1[0] + n1[1] * n1[1] + n1[2] * n1[2]);
+    Real ig2 = Real(1) / sqrt(Real(1) + n2[0] * n2[0] + n2[1] * n2[1] + n2[2] * n2[2]);
+    Real v1[3], v2[3];
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+      v1[q] = n1[q] * ig1;
+      v2[q] = n2[q] * ig2;
+      dl[q] = dl[q] + c.dt * (v1[q] - v2[q]);
+    }
+    // move: R += dt (m1 v1 + m2 v2)/m_c, delta += dt (v1 - v2)
+    Real offn[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < ND; d++) {
+      offn[d] = off[d] + c.dt * (c.m1 * v1[d] + c.m2 * v2[d]) * c.inv_mc * c.idx[d];
+      if (reflect(g.periodic[d], ci[d], g.n[d], g.pad, offn[d])) {
+        n1[d] = -n1[d];
+        n2[d] = -n2[d];
+        dl[d] = -dl[d];
+      }
+    }
+    bool range_ok = true;
+    if (c.deposit) {
+      const Real qw1 = s.w ? c.q1 * W : c.qw1;
+      const Real qw2 = s.w ? c.q2 * W : c.qw2;
+#pragma unroll 1
+      for (int body = 0; body < 2; body++) {
+        Real xa[3], y[3] = {0, 0, 0}, vb[3];
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+          xa[d] = body == 0 ? x1[d] : x2[d];
+          vb[d] = body == 0 ? v1[d] : v2[d];
+        }
+#pragma unroll
+        for (int d = 0; d < ND; d++) {
+          Real sd = dl[d] * c.idx[d];
+          y[d] = body == 0 ? offn[d] + c.f1 * sd : offn[d] - c.f2 * sd;
+        }
+        range_ok = deposit<Real, ND, GLOBAL, JT>(J, jbase, jsy, jsz, xa, y, body == 0 ? qw1 : qw2,
+                                             vb, c) && range_ok;
+      }
+    }
+    int cn[3] = {ci[0], ci[1], ci[2]};
+#pragma unroll
+    for (int d = 0; d < ND; d++) {
+      range_ok = range_ok && (fabs(dl[d] * c.idx[d]) < Real(0.5));
+      int keep = cn[d];
+      Real o = offn[d];
+      if (cross(g.periodic[d], g.n[d], cn[d], o)) {
+        offn[d] = o;
+      } else {
+        cn[d] = keep;
+        range_ok = false;
+      }
+    }
+    if (!range_ok) atomicOr(err, PIC_ERR_RANGE);
+    if (!(finite3(n1) && finite3(n2) && finite3(dl))) atomicOr(err, PIC_ERR_NAN);
+    s.cell[p] = encode_cell<ND>(g, cn);
+#pragma unroll
+    for (int d = 0; d < ND; d++) s.off[d][p] = offn[d];
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+      s.u1[q][p] = n1[q];
+      s.u2[q][p] = n2[q];
+      s.dl[q][p] = dl[q];
+    }
+  } else {
+    Real E1[3], B1[3];
+    gather<Real, ND>(fg, fbase, fsy, fsz, x1, E1, B1);
+    Real um[3], n1[3], v1[3];
+#pragma unroll
+    for (int q = 0; q < 3; q++) um[q] = u1[q] + c.a1 * E1[q];
+    boris_rotate_kick(um, c.a1, E1, B1, n1);
+    Real ig = Real(1) / sqrt(Real(1) + n1[0] * n1[0] + n1[1] * n1[1] + n1[2] * n1[2]);
+#pragma unroll
+    for (int q = 0; q < 3; q++) v1[q] = n1[q] * ig;
+    Real y1[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < ND; d++) {
+      y1[d] = off[d] + c.dt * v1[d] * c.idx[d];
+      if (reflect(g.periodic[d], ci[d], g.n[d], g.pad, y1[d])) n1[d] = -n1[d];
+    }
+    bool range_ok = true;
+    if (c.deposit) {
+      const Real qw1 = s.w ? c.q1 * W : c.qw1;
+      range_ok = deposit<Real, ND, GLOBAL, JT>(J, jbase, jsy, jsz, x1, y1, qw1, v1, c);
+    }
+    int cn[3] = {ci[0], ci[1], ci[2]};
+#pragma unroll
+    for (int d = 0; d < ND; d++) {
+      int keep = cn[d];
+      Real o = y1[d];
+      if (cross(g.periodic[d], g.n[d], cn[d], o)) {
+        y1[d] = o;
+      } else {
+        cn[d] = keep;
+        range_ok = false;
+      }
+    }
+    if (!range_ok) atomicOr(err, PIC_ERR_RANGE);
+    if (!finite3(n1)) atomicOr(err, PIC_ERR_NAN);
+    s.cell[p] = encode_cell<ND>(g, cn);
+#pragma unroll
+    for (int d = 0; d < ND; d++) s.off[d][p] = y1[d];
+#pragma unroll
+    for (int q = 0; q < 3; q++) s.u1[q][p] = n1[q];
+  }
+}
+
+}  // namespace pic

@@ -85,6 +85,11 @@ void launch_push(const GridInfo& g, const FieldPtrs<Real>& f, const SpeciesDev<R
                  const PushConst<Real>& c, uint32_t* err, hipStream_t st);
 
 template <typename Real>
+void launch_push_list(const GridInfo& g, const FieldPtrs<Real>& f, const SpeciesDev<Real>& s,
+                      const PushConst<Real>& c, const uint32_t* list, const uint32_t* count,
+                      uint32_t* total, uint32_t* err, hipStream_t st);
+
+template <typename Real>
 void launch_zero(Real* p, int64_t n, hipStream_t st);
 
 template <typename Real>

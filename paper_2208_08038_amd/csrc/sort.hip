@@ -159,6 +159,8 @@ int sort_alloc(const GridInfo&, const int ntiles[3], int64_t cap, const AllocFn&
   sb.scan_tmp = static_cast<uint32_t*>(alloc(tmp * 4));
   sb.tile_off = static_cast<uint32_t*>(alloc((sb.ntiles + 1) * 4));
   if (!sb.hist || !sb.scan_tmp || !sb.tile_off) return -1;
+  // until the first sort every tile is empty
+  if (hipMemset(sb.tile_off, 0, (sb.ntiles + 1) * 4) != hipSuccess) return -1;
   return 0;
 }
 

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpic.so")
 
 PIC_OK, PIC_EINVAL, PIC_ENOMEM, PIC_EHIP, PIC_ESTATE, PIC_ERANGE, PIC_ENAN = 0, -1, -2, -3, -4, -5, -6
-FROZEN_FIELDS, NO_DEPOSIT, CHARGE_CHECK, TRACK_IDS, TIMING = 1, 2, 4, 8, 16
+FROZEN_FIELDS, NO_DEPOSIT, CHARGE_CHECK, TRACK_IDS, TIMING, GLOBAL_KERNEL = 1, 2, 4, 8, 16, 32
 ERR_NAN, ERR_RANGE = 1, 2
 
 _NAMES = {PIC_EINVAL: "PIC_EINVAL", PIC_ENOMEM: "PIC_ENOMEM", PIC_EHIP: "PIC_EHIP",
@@ -57,7 +57,8 @@ class PicDiag(C.Structure):
     _fields_ = [("step", C.c_int64), ("time", C.c_double), ("field_energy", C.c_double),
                 ("kinetic_energy", C.c_double), ("momentum", C.c_double * 3),
                 ("div_l2", C.c_double), ("div_max", C.c_double), ("rho_l2", C.c_double),
-                ("n_particles", C.c_int64), ("error_word", C.c_uint32), ("reserved", C.c_uint32)]
+                ("n_particles", C.c_int64), ("error_word", C.c_uint32), ("reserved", C.c_uint32),
+                ("n_outside_tile", C.c_int64)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -289,7 +290,8 @@ class Simulation:
         return {"step": d.step, "time": d.time, "field_energy": d.field_energy,
                 "kinetic_energy": d.kinetic_energy, "momentum": list(d.momentum),
                 "div_l2": d.div_l2, "div_max": d.div_max, "rho_l2": d.rho_l2,
-                "n_particles": d.n_particles, "error_word": d.error_word, "status": rc}
+                "n_particles": d.n_particles, "error_word": d.error_word,
+                "n_outside_tile": d.n_outside_tile, "status": rc}
 
     def fields(self):
         E = np.zeros((3, self.ncell))

@@ -290,3 +290,35 @@ def test_device_loader_matches_host_loader(pic):
             for k in ("u1", "u2"):
                 scale = max(np.abs(ga[k]).max(), 1e-300)
                 assert np.abs(ga[k] - gb[k]).max() <= 2e-15 * scale * (1 if prec == 64 else 1e9)
+
+
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_particles_outside_their_tile(pic, ndim):
+    """Fast electrons with a long sort interval leave their tiles; those
+    particles take the HBM path and the result still matches the oracle."""
+    _say(f"case: drift out of tiles ndim={ndim}")
+    wl = random_workload(ndim, 200, 600, seed=140 + ndim, shape=(40, 24, 20)[:ndim],
+                         vmax_el=0.95)
+    o, s = _both(wl, pic, 64, sort_every=1000, tile=(8, 8, 8)[:ndim])
+    o.step(12)
+    s.step(12)
+    d = s.diagnostics()
+    assert d["n_outside_tile"] > 0
+    assert o.diagnostics()["error_word"] == 0
+    Eo, Bo, Jo = o.fields()
+    Eg, Bg, Jg = s.fields()
+    assert rel_l2(Eg, Eo) < 1e-12
+    assert rel_l2(Jg, Jo) < 1e-12
+    _compare_particles(o, s, wl, 1e-11)
+
+
+def test_global_kernel_option(pic):
+    """The HBM-gather / global-atomic kernel (PIC_FLAG_GLOBAL_KERNEL) agrees
+    with the oracle too."""
+    _say("case: global kernel option 3d")
+    wl = random_workload(3, 300, 300, seed=150)
+    o, s = _both(wl, pic, 64, pflags=pic.GLOBAL_KERNEL)
+    o.step(8)
+    s.step(8)
+    assert rel_l2(s.fields()[0], o.fields()[0]) < 1e-12
+    _compare_particles(o, s, wl, 1e-11)
