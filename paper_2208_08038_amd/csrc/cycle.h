@@ -114,6 +114,74 @@ __device__ __forceinline__ void gather(const FieldPtrs<Real>& f, int base, int s
   B[2] = interp<Real, ND>(f.B[2], base, sy, sz, h0, h1, n2);
 }
 
+// Two positions whose stencils coincide (same first node for every
+// stagger): one pass over the nodes accumulates both interpolants.
+template <typename Real, int ND>
+__device__ __forceinline__ void interp2(const Real* __restrict__ F, int base, int sy, int sz,
+                                        const Weights<Real>& xa, const Weights<Real>& ya,
+                                        const Weights<Real>& za, const Weights<Real>& xb,
+                                        const Weights<Real>& yb, const Weights<Real>& zb,
+                                        Real& ra, Real& rb) {
+  const Real* p = F + base + xa.i0;
+  if constexpr (ND > 1) p += ya.i0 * sy;
+  if constexpr (ND > 2) p += za.i0 * sz;
+  Real sa = 0, sb = 0;
+  constexpr int NZ = ND > 2 ? 3 : 1, NY = ND > 1 ? 3 : 1;
+#pragma unroll
+  for (int cz = 0; cz < NZ; cz++) {
+    Real ta = 0, tb = 0;
+#pragma unroll
+    for (int cy = 0; cy < NY; cy++) {
+      const Real* q = p + cy * sy + cz * sz;
+      Real v0 = q[0], v1 = q[1], v2 = q[2];
+      Real wa = cy == 0 ? ya.w0 : (cy == 1 ? ya.w1 : ya.w2);
+      Real wb = cy == 0 ? yb.w0 : (cy == 1 ? yb.w1 : yb.w2);
+      ta += wa * (xa.w0 * v0 + xa.w1 * v1 + xa.w2 * v2);
+      tb += wb * (xb.w0 * v0 + xb.w1 * v1 + xb.w2 * v2);
+    }
+    sa += (cz == 0 ? za.w0 : (cz == 1 ? za.w1 : za.w2)) * ta;
+    sb += (cz == 0 ? zb.w0 : (cz == 1 ? zb.w1 : zb.w2)) * tb;
+  }
+  ra = sa;
+  rb = sb;
+}
+
+// True when positions a and b have the same nearest integer and
+// half-integer node along every resolved dimension.
+template <typename Real, int ND>
+__device__ __forceinline__ bool same_stencil(const Real xa[3], const Real xb[3]) {
+  bool same = true;
+#pragma unroll
+  for (int d = 0; d < ND; d++)
+    same = same && floor(xa[d] + Real(0.5)) == floor(xb[d] + Real(0.5)) &&
+           floor(xa[d]) == floor(xb[d]);
+  return same;
+}
+
+template <typename Real, int ND>
+__device__ __forceinline__ void gather2(const FieldPtrs<Real>& f, int base, int sy, int sz,
+                                        const Real xa[3], const Real xb[3], Real Ea[3],
+                                        Real Ba[3], Real Eb[3], Real Bb[3]) {
+  Weights<Real> na[3], ha[3], nb[3], hb[3];
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    if (d < ND) {
+      na[d] = weights_int(xa[d]);
+      ha[d] = weights_half(xa[d]);
+      nb[d] = weights_int(xb[d]);
+      hb[d] = weights_half(xb[d]);
+    } else {
+      na[d] = ha[d] = nb[d] = hb[d] = unit_weights<Real>();
+    }
+  }
+  interp2<Real, ND>(f.E[0], base, sy, sz, ha[0], na[1], na[2], hb[0], nb[1], nb[2], Ea[0], Eb[0]);
+  interp2<Real, ND>(f.E[1], base, sy, sz, na[0], ha[1], na[2], nb[0], hb[1], nb[2], Ea[1], Eb[1]);
+  interp2<Real, ND>(f.E[2], base, sy, sz, na[0], na[1], ha[2], nb[0], nb[1], hb[2], Ea[2], Eb[2]);
+  interp2<Real, ND>(f.B[0], base, sy, sz, na[0], ha[1], ha[2], nb[0], hb[1], hb[2], Ba[0], Bb[0]);
+  interp2<Real, ND>(f.B[1], base, sy, sz, ha[0], na[1], ha[2], hb[0], nb[1], hb[2], Ba[1], Bb[1]);
+  interp2<Real, ND>(f.B[2], base, sy, sz, ha[0], ha[1], na[2], hb[0], hb[1], nb[2], Ba[2], Bb[2]);
+}
+
 // Shape of a body at its old (x0) and new (x1) position on a common
 // 4-node window starting at node `lo` (relative to the cell).  Returns
 // false if the two nearest nodes are more than one node apart.
@@ -293,6 +361,230 @@ __device__ __forceinline__ bool deposit(JT* const J[3], int base, int sy, int sz
   return true;
 }
 
+// Quadratic B-spline weights of a position x on the three nodes n-1, n, n+1.
+template <typename Real>
+__device__ __forceinline__ void shape3(Real x, int n, Real w[3]) {
+  Real d = x - Real(n);
+  Real a = Real(0.5) - d, b = Real(0.5) + d;
+  w[0] = Real(0.5) * a * a;
+  w[1] = Real(0.75) - d * d;
+  w[2] = Real(0.5) * b * b;
+}
+
+// Old and new shapes of a body on the 3-node window [n-1, n+1].
+template <typename Real, int ND>
+struct Win3 {
+  Real S0[ND][3], DS[ND][3];
+};
+
+template <typename Real, int ND>
+__device__ __forceinline__ void win3(const Real x0[3], const Real x1[3], const int nn[3],
+                                     Win3<Real, ND>& w) {
+#pragma unroll
+  for (int d = 0; d < ND; d++) {
+    Real s1[3];
+    shape3(x0[d], nn[d], w.S0[d]);
+    shape3(x1[d], nn[d], s1);
+#pragma unroll
+    for (int k = 0; k < 3; k++) w.DS[d][k] = s1[k] - w.S0[d][k];
+  }
+}
+
+// Esirkepov deposit when the nearest node does not change during the step
+// (old and new positions of every body share the node n per dimension):
+// the window is three nodes wide and the running sum along the motion has
+// two non-zero terms (the third is the sum of the shape change, zero).
+// With PAIR the two bodies of an ion share the window and their terms are
+// added in registers before one add per node.
+template <typename Real, int ND, bool GLOBAL, typename JT, bool PAIR>
+__device__ __forceinline__ void deposit3(JT* const J[3], int base, int sy, int sz,
+                                         const int nn[3], const Real xa0[3], const Real xa1[3],
+                                         Real Qa, const Real va[3], const Real xb0[3],
+                                         const Real xb1[3], Real Qb, const Real vb[3],
+                                         const PushConst<Real>& c) {
+  const Real third = Real(1) / Real(3);
+  Win3<Real, ND> a, b;
+  win3<Real, ND>(xa0, xa1, nn, a);
+  if constexpr (PAIR) win3<Real, ND>(xb0, xb1, nn, b);
+  int o = base + nn[0] - 1;
+  if constexpr (ND > 1) o += (nn[1] - 1) * sy;
+  if constexpr (ND > 2) o += (nn[2] - 1) * sz;
+  if constexpr (ND == 1) {
+    Real fxa = Qa * c.jf[0], fya = Qa * va[1] * c.inv_dv, fza = Qa * va[2] * c.inv_dv;
+    Real fxb = 0, fyb = 0, fzb = 0;
+    if constexpr (PAIR) {
+      fxb = Qb * c.jf[0];
+      fyb = Qb * vb[1] * c.inv_dv;
+      fzb = Qb * vb[2] * c.inv_dv;
+    }
+    Real Ca = 0, Cb = 0;
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+      Real Aa = a.S0[0][r] + Real(0.5) * a.DS[0][r];
+      Real Ab = 0;
+      if constexpr (PAIR) Ab = b.S0[0][r] + Real(0.5) * b.DS[0][r];
+      if (r < 2) {
+        Ca += a.DS[0][r];
+        if constexpr (PAIR) Cb += b.DS[0][r];
+        jadd<GLOBAL>(J[0] + o + r, PAIR ? fxa * Ca + fxb * Cb : fxa * Ca);
+      }
+      jadd<GLOBAL>(J[1] + o + r, PAIR ? fya * Aa + fyb * Ab : fya * Aa);
+      jadd<GLOBAL>(J[2] + o + r, PAIR ? fza * Aa + fzb * Ab : fza * Aa);
+    }
+  } else if constexpr (ND == 2) {
+    Real fxa = Qa * c.jf[0], fya = Qa * c.jf[1], fza = Qa * va[2] * c.inv_dv;
+    Real fxb = 0, fyb = 0, fzb = 0;
+    if constexpr (PAIR) {
+      fxb = Qb * c.jf[0];
+      fyb = Qb * c.jf[1];
+      fzb = Qb * vb[2] * c.inv_dv;
+    }
+    Real Cxa0 = a.DS[0][0], Cxa1 = Cxa0 + a.DS[0][1];
+    Real Cya0 = a.DS[1][0], Cya1 = Cya0 + a.DS[1][1];
+    Real Cxb0 = 0, Cxb1 = 0, Cyb0 = 0, Cyb1 = 0;
+    if constexpr (PAIR) {
+      Cxb0 = b.DS[0][0];
+      Cxb1 = Cxb0 + b.DS[0][1];
+      Cyb0 = b.DS[1][0];
+      Cyb1 = Cyb0 + b.DS[1][1];
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < 3; s2++) {
+      Real Aya = a.S0[1][s2] + Real(0.5) * a.DS[1][s2];
+      Real Bya = Real(0.5) * a.S0[1][s2] + third * a.DS[1][s2];
+      Real Ayb = 0, Byb = 0;
+      if constexpr (PAIR) {
+        Ayb = b.S0[1][s2] + Real(0.5) * b.DS[1][s2];
+        Byb = Real(0.5) * b.S0[1][s2] + third * b.DS[1][s2];
+      }
+      // J_x = f_x C_x(r) (S0y + DSy/2)(s)
+      JT* px = J[0] + o + s2 * sy;
+      jadd<GLOBAL>(px, PAIR ? fxa * Cxa0 * Aya + fxb * Cxb0 * Ayb : fxa * Cxa0 * Aya);
+      jadd<GLOBAL>(px + 1, PAIR ? fxa * Cxa1 * Aya + fxb * Cxb1 * Ayb : fxa * Cxa1 * Aya);
+#pragma unroll
+      for (int r = 0; r < 3; r++) {
+        Real Axa = a.S0[0][r] + Real(0.5) * a.DS[0][r];
+        Real Axb = 0;
+        if constexpr (PAIR) Axb = b.S0[0][r] + Real(0.5) * b.DS[0][r];
+        // J_y = f_y C_y(s) (S0x + DSx/2)(r), for s < 2
+        if (s2 < 2) {
+          Real cya = s2 == 0 ? Cya0 : Cya1, cyb = s2 == 0 ? Cyb0 : Cyb1;
+          jadd<GLOBAL>(J[1] + o + r + s2 * sy, PAIR ? fya * cya * Axa + fyb * cyb * Axb
+                                                     : fya * cya * Axa);
+        }
+        // J_z = f_z [S0x (S0y + DSy/2) + DSx (S0y/2 + DSy/3)]
+        Real za = fza * (a.S0[0][r] * Aya + a.DS[0][r] * Bya);
+        Real zb = 0;
+        if constexpr (PAIR) zb = fzb * (b.S0[0][r] * Ayb + b.DS[0][r] * Byb);
+        jadd<GLOBAL>(J[2] + o + r + s2 * sy, PAIR ? za + zb : za);
+      }
+    }
+  } else {
+    // J_x: running sum along x of DS_x, times [S0y (S0z + DSz/2) + DSy (S0z/2 + DSz/3)]
+    {
+      Real fa = Qa * c.jf[0], fb = PAIR ? Qb * c.jf[0] : Real(0);
+      Real Ca0 = a.DS[0][0], Ca1 = Ca0 + a.DS[0][1];
+      Real Cb0 = 0, Cb1 = 0;
+      if constexpr (PAIR) {
+        Cb0 = b.DS[0][0];
+        Cb1 = Cb0 + b.DS[0][1];
+      }
+#pragma unroll
+      for (int t = 0; t < 3; t++) {
+        Real aza = a.S0[2][t] + Real(0.5) * a.DS[2][t];
+        Real bza = Real(0.5) * a.S0[2][t] + third * a.DS[2][t];
+        Real azb = 0, bzb = 0;
+        if constexpr (PAIR) {
+          azb = b.S0[2][t] + Real(0.5) * b.DS[2][t];
+          bzb = Real(0.5) * b.S0[2][t] + third * b.DS[2][t];
+        }
+#pragma unroll
+        for (int s2 = 0; s2 < 3; s2++) {
+          Real Ta = fa * (a.S0[1][s2] * aza + a.DS[1][s2] * bza);
+          Real Tb = 0;
+          if constexpr (PAIR) Tb = fb * (b.S0[1][s2] * azb + b.DS[1][s2] * bzb);
+          JT* p = J[0] + o + s2 * sy + t * sz;
+          jadd<GLOBAL>(p, PAIR ? Ca0 * Ta + Cb0 * Tb : Ca0 * Ta);
+          jadd<GLOBAL>(p + 1, PAIR ? Ca1 * Ta + Cb1 * Tb : Ca1 * Ta);
+        }
+      }
+    }
+    // J_y: running sum along y of DS_y, times [S0x (S0z + DSz/2) + DSx (S0z/2 + DSz/3)]
+    {
+      Real fa = Qa * c.jf[1], fb = PAIR ? Qb * c.jf[1] : Real(0);
+      Real Ca0 = a.DS[1][0], Ca1 = Ca0 + a.DS[1][1];
+      Real Cb0 = 0, Cb1 = 0;
+      if constexpr (PAIR) {
+        Cb0 = b.DS[1][0];
+        Cb1 = Cb0 + b.DS[1][1];
+      }
+#pragma unroll
+      for (int t = 0; t < 3; t++) {
+        Real aza = a.S0[2][t] + Real(0.5) * a.DS[2][t];
+        Real bza = Real(0.5) * a.S0[2][t] + third * a.DS[2][t];
+        Real azb = 0, bzb = 0;
+        if constexpr (PAIR) {
+          azb = b.S0[2][t] + Real(0.5) * b.DS[2][t];
+          bzb = Real(0.5) * b.S0[2][t] + third * b.DS[2][t];
+        }
+#pragma unroll
+        for (int r = 0; r < 3; r++) {
+          Real Ta = fa * (a.S0[0][r] * aza + a.DS[0][r] * bza);
+          Real Tb = 0;
+          if constexpr (PAIR) Tb = fb * (b.S0[0][r] * azb + b.DS[0][r] * bzb);
+          JT* p = J[1] + o + r + t * sz;
+          jadd<GLOBAL>(p, PAIR ? Ca0 * Ta + Cb0 * Tb : Ca0 * Ta);
+          jadd<GLOBAL>(p + sy, PAIR ? Ca1 * Ta + Cb1 * Tb : Ca1 * Ta);
+        }
+      }
+    }
+    // J_z: running sum along z of DS_z, times [S0x (S0y + DSy/2) + DSx (S0y/2 + DSy/3)]
+    {
+      Real fa = Qa * c.jf[2], fb = PAIR ? Qb * c.jf[2] : Real(0);
+      Real Ca0 = a.DS[2][0], Ca1 = Ca0 + a.DS[2][1];
+      Real Cb0 = 0, Cb1 = 0;
+      if constexpr (PAIR) {
+        Cb0 = b.DS[2][0];
+        Cb1 = Cb0 + b.DS[2][1];
+      }
+#pragma unroll
+      for (int s2 = 0; s2 < 3; s2++) {
+        Real aya = a.S0[1][s2] + Real(0.5) * a.DS[1][s2];
+        Real bya = Real(0.5) * a.S0[1][s2] + third * a.DS[1][s2];
+        Real ayb = 0, byb = 0;
+        if constexpr (PAIR) {
+          ayb = b.S0[1][s2] + Real(0.5) * b.DS[1][s2];
+          byb = Real(0.5) * b.S0[1][s2] + third * b.DS[1][s2];
+        }
+#pragma unroll
+        for (int r = 0; r < 3; r++) {
+          Real Ta = fa * (a.S0[0][r] * aya + a.DS[0][r] * bya);
+          Real Tb = 0;
+          if constexpr (PAIR) Tb = fb * (b.S0[0][r] * ayb + b.DS[0][r] * byb);
+          JT* p = J[2] + o + r + s2 * sy;
+          jadd<GLOBAL>(p, PAIR ? Ca0 * Ta + Cb0 * Tb : Ca0 * Ta);
+          jadd<GLOBAL>(p + sz, PAIR ? Ca1 * Ta + Cb1 * Tb : Ca1 * Ta);
+        }
+      }
+    }
+  }
+}
+
+// Nearest node per dimension shared by all the given positions, if any.
+template <typename Real, int ND>
+__device__ __forceinline__ bool common_node(const Real* const* xs, int nx, int nn[3]) {
+  bool same = true;
+#pragma unroll
+  for (int d = 0; d < 3; d++) nn[d] = 0;
+#pragma unroll
+  for (int d = 0; d < ND; d++) {
+    Real f = floor(xs[0][d] + Real(0.5));
+    for (int k = 1; k < nx; k++) same = same && floor(xs[k][d] + Real(0.5)) == f;
+    nn[d] = static_cast<int>(f);
+  }
+  return same;
+}
+
 template <typename Real>
 __device__ __forceinline__ void boris_rotate_kick(const Real um[3], Real a, const Real E[3],
                                                   const Real B[3], Real out[3]) {
@@ -433,6 +725,10 @@ __device__ __forceinline__ void advance_particle(const GridInfo& g, const Specie
     // keeps the live register set small); E and B are kept per body for
     // the second half kick
     Real E1[3], B1[3], E2[3], B2[3];
+    if (same_stencil<Real, ND>(x1, x2)) {
+      // both bodies on the same nodes (the usual case: |delta| << dx)
+      gather2<Real, ND>(fg, fbase, fsy, fsz, x1, x2, E1, B1, E2, B2);
+    } else {
 #pragma unroll 1
     for (int body = 0; body < 2; body++) {
       Real xb[3], Eb[3], Bb[3];
@@ -446,6 +742,7 @@ __device__ __forceinline__ void advance_particle(const GridInfo& g, const Specie
         E2[q] = body == 0 ? E2[q] : Eb[q];
         B2[q] = body == 0 ? B2[q] : Bb[q];
       }
+    }
     }
     Real um1[3], um2[3];
 #pragma unroll
@@ -495,6 +792,21 @@ __device__ __forceinline__ void advance_particle(const GridInfo& g, const Specie
     if (c.deposit) {
       const Real qw1 = s.w ? c.q1 * W : c.qw1;
       const Real qw2 = s.w ? c.q2 * W : c.qw2;
+      Real y1[3] = {0, 0, 0}, y2[3] = {0, 0, 0};
+#pragma unroll
+      for (int d = 0; d < ND; d++) {
+        Real sd = dl[d] * c.idx[d];
+        y1[d] = offn[d] + c.f1 * sd;
+        y2[d] = offn[d] - c.f2 * sd;
+      }
+      const Real* xs[4] = {x1, x2, y1, y2};
+      int nn[3];
+      const bool pair = common_node<Real, ND>(xs, 4, nn);
+      if (pair) {
+        // both bodies keep one nearest node: merged three-node deposit
+        deposit3<Real, ND, GLOBAL, JT, true>(J, jbase, jsy, jsz, nn, x1, y1, qw1, v1, x2, y2,
+                                             qw2, v2, c);
+      } else {
 #pragma unroll 1
       for (int body = 0; body < 2; body++) {
         Real xa[3], y[3] = {0, 0, 0}, vb[3];
@@ -510,6 +822,7 @@ __device__ __forceinline__ void advance_particle(const GridInfo& g, const Specie
         }
         range_ok = deposit<Real, ND, GLOBAL, JT>(J, jbase, jsy, jsz, xa, y, body == 0 ? qw1 : qw2,
                                              vb, c) && range_ok;
+      }
       }
     }
     int cn[3] = {ci[0], ci[1], ci[2]};
@@ -555,7 +868,15 @@ __device__ __forceinline__ void advance_particle(const GridInfo& g, const Specie
     bool range_ok = true;
     if (c.deposit) {
       const Real qw1 = s.w ? c.q1 * W : c.qw1;
-      range_ok = deposit<Real, ND, GLOBAL, JT>(J, jbase, jsy, jsz, x1, y1, qw1, v1, c);
+      const Real* xs[2] = {x1, y1};
+      int nn[3];
+      const bool keep = common_node<Real, ND>(xs, 2, nn);
+      // per lane: most particles keep their nearest node
+      if (keep)
+        deposit3<Real, ND, GLOBAL, JT, false>(J, jbase, jsy, jsz, nn, x1, y1, qw1, v1, x1, y1,
+                                              Real(0), v1, c);
+      else
+        range_ok = deposit<Real, ND, GLOBAL, JT>(J, jbase, jsy, jsz, x1, y1, qw1, v1, c);
     }
     int cn[3] = {ci[0], ci[1], ci[2]};
 #pragma unroll

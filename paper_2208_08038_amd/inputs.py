@@ -396,7 +396,7 @@ WORKLOADS = {
 def ionised_slab_3d_device_chunk(n=(512, 256, 256), ppc: int = 8, x_cells=(3, 35),
                                  chunk: int = 0, device="cuda", wc_range=(1.5, 4.0),
                                  t_ion_ev: float = 1.0, t_e_ev: float = 10.0,
-                                 interleave: bool = False, config_id: int = 3):
+                                 interleave: bool = True, config_id: int = 3):
     """Same recipe as ionised_slab_3d for the x planes x_cells, drawn with
     torch's Philox generator on the GPU (seed = base seed + config id, offset
     by the chunk), returned as FP64 device tensors:
