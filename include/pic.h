@@ -208,10 +208,13 @@ int pic_set_probes(pic_ctx* ctx, int32_t nprobe, const int32_t* comp, const int6
 /* out: nprobe x nrecorded HOST FP64 (NULL: query *nrecorded only). */
 int pic_read_probes(pic_ctx* ctx, double* out, int64_t* nrecorded);
 
-/* Particle-kernel timing (PIC_FLAG_TIMING): total milliseconds and launch
-   count of the particle-cycle kernel launches of one species (species_id
-   >= 0) or of all species (-1) since the last reset, measured with HIP
-   events recorded on the context stream around each launch.  Synchronises. */
+/* Particle-kernel timing (PIC_FLAG_TIMING): total milliseconds and number
+   of dispatches of the main particle-cycle kernel of one species
+   (species_id >= 0) or of all species (-1) since the last reset, measured
+   with HIP events recorded on the context stream around each dispatch.
+   With the tiled kernel a species takes 2^ndim dispatches per step (one
+   per tile colour), each timed on its own; the small kernel that advances
+   particles found outside their tile is not included.  Synchronises. */
 int pic_timing(pic_ctx* ctx, int32_t species_id, double* total_ms, int64_t* launches,
                int32_t reset);
 

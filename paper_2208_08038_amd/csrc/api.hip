@@ -408,6 +408,24 @@ bool record_event(pic_ctx* c, int species, bool start) {
   return hipEventRecord(c->ev[c->ev_used++], c->stream) == hipSuccess;
 }
 
+// timing events around each dispatch of the main particle kernel of one
+// species (every colour of the tiled kernel; the outside-tile list kernel
+// is not timed)
+struct TimedDispatch {
+  pic_ctx* c;
+  int species;
+  bool open;
+  static void hook(void* arg, bool start) {
+    auto* t = static_cast<TimedDispatch*>(arg);
+    if (start) {
+      t->open = record_event(t->c, t->species, true);
+    } else if (t->open) {
+      record_event(t->c, t->species, false);
+      t->open = false;
+    }
+  }
+};
+
 template <typename Real>
 void deposit_rho(pic_ctx* c, double* rho) {
   pic::launch_zero<double>(rho, c->g.plane, c->stream);
@@ -451,19 +469,22 @@ int step_t(pic_ctx* c, int nsteps) {
     if (c->tiled) HIPCHK(c, hipMemsetAsync(c->nslow + 1, 0, sizeof(uint32_t), c->stream));
     for (size_t si = 0; si < c->sp.size(); si++) {
       auto& s = c->sp[si];
-      bool timed = record_event(c, (int)si, true);
+      TimedDispatch td{c, (int)si, false};
       if (c->tiled) {
+        pic::DispatchHook hook;
+        if (c->cfg.flags & PIC_FLAG_TIMING) hook = {&TimedDispatch::hook, &td};
         hipError_t e = pic::launch_push_tiled<Real>(g, f, species_dev<Real>(*s),
                                                     push_const<Real>(c, *s), c->tg,
                                                     s->sort.tile_off, s->outside, c->nslow,
-                                                    c->nslow + 1, c->err, c->stream);
+                                                    c->nslow + 1, c->err, c->stream, hook);
         if (e != hipSuccess)
           return fail(c, PIC_EHIP, std::string("tiled particle kernel: ") + hipGetErrorString(e));
       } else {
+        TimedDispatch::hook(&td, true);
         pic::launch_push<Real>(g, f, species_dev<Real>(*s), push_const<Real>(c, *s), c->err,
                                c->stream);
+        TimedDispatch::hook(&td, false);
       }
-      if (timed) record_event(c, (int)si, false);
       c->launches++;
     }
     pic::launch_fold_periodic<Real>(g, jj, 3, c->stream);

@@ -21,6 +21,13 @@ TileGeom make_tile_geom(const GridInfo& g, const int tile[3], const int ntiles[3
 size_t tiled_lds_bytes(const TileGeom& t, size_t rsize);
 bool tiled_supported(const GridInfo& g, const TileGeom& t, size_t rsize);
 
+// Called on the host just before (start = true) and after (false) each
+// colour dispatch is enqueued, e.g. to record timing events.
+struct DispatchHook {
+  void (*fn)(void* arg, bool start) = nullptr;
+  void* arg = nullptr;
+};
+
 // Launch the 2^ndim colours of the tiled kernel for one species, then the
 // kernel for the particles they listed as outside their tile.  `list`
 // holds room for every particle of the species; `nlist` is a scratch
@@ -29,6 +36,6 @@ template <typename Real>
 hipError_t launch_push_tiled(const GridInfo& g, const FieldPtrs<Real>& f, const SpeciesDev<Real>& s,
                              const PushConst<Real>& c, const TileGeom& t, const uint32_t* tile_off,
                              uint32_t* list, uint32_t* nlist, uint32_t* nlist_total,
-                             uint32_t* err, hipStream_t st);
+                             uint32_t* err, hipStream_t st, DispatchHook hook = {});
 
 }  // namespace pic

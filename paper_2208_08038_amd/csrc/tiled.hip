@@ -233,13 +233,14 @@ template <typename Real>
 hipError_t launch_push_tiled(const GridInfo& g, const FieldPtrs<Real>& f, const SpeciesDev<Real>& s,
                              const PushConst<Real>& c, const TileGeom& t, const uint32_t* tile_off,
                              uint32_t* list, uint32_t* nlist, uint32_t* nlist_total,
-                             uint32_t* err, hipStream_t st) {
+                             uint32_t* err, hipStream_t st, DispatchHook hook) {
   if (s.n == 0) return hipSuccess;
   size_t lds = tiled_lds_bytes(t, sizeof(Real));
   hipError_t e = hipMemsetAsync(nlist, 0, sizeof(uint32_t), st);
   if (e != hipSuccess) return e;
   int ncol = 1 << g.nd;
   for (int color = 0; color < ncol; color++) {
+    if (hook.fn) hook.fn(hook.arg, true);
     if (c.two_body) {
       if (g.nd == 1) e = launch_colour<Real, 1, true>(g, f, s, c, t, tile_off, color, list, nlist, err, lds, st);
       if (g.nd == 2) e = launch_colour<Real, 2, true>(g, f, s, c, t, tile_off, color, list, nlist, err, lds, st);
@@ -250,6 +251,7 @@ hipError_t launch_push_tiled(const GridInfo& g, const FieldPtrs<Real>& f, const 
       if (g.nd == 3) e = launch_colour<Real, 3, false>(g, f, s, c, t, tile_off, color, list, nlist, err, lds, st);
     }
     if (e != hipSuccess) return e;
+    if (hook.fn) hook.fn(hook.arg, false);
   }
   launch_push_list<Real>(g, f, s, c, list, nlist, nlist_total, err, st);
   return hipGetLastError();
@@ -258,10 +260,12 @@ hipError_t launch_push_tiled(const GridInfo& g, const FieldPtrs<Real>& f, const 
 template hipError_t launch_push_tiled<float>(const GridInfo&, const FieldPtrs<float>&,
                                              const SpeciesDev<float>&, const PushConst<float>&,
                                              const TileGeom&, const uint32_t*, uint32_t*,
-                                             uint32_t*, uint32_t*, uint32_t*, hipStream_t);
+                                             uint32_t*, uint32_t*, uint32_t*, hipStream_t,
+                                             DispatchHook);
 template hipError_t launch_push_tiled<double>(const GridInfo&, const FieldPtrs<double>&,
                                               const SpeciesDev<double>&, const PushConst<double>&,
                                               const TileGeom&, const uint32_t*, uint32_t*,
-                                              uint32_t*, uint32_t*, uint32_t*, hipStream_t);
+                                              uint32_t*, uint32_t*, uint32_t*, hipStream_t,
+                                             DispatchHook);
 
 }  // namespace pic

@@ -336,7 +336,8 @@ class Simulation:
         return out
 
     def timing(self, species: int = -1, reset: bool = True):
-        """(total ms, launches) of the particle kernels of one species (-1: all)."""
+        """(total ms, dispatches) of the main particle kernel of one species
+        (-1: all); the tiled kernel counts one dispatch per tile colour."""
         ms = C.c_double()
         nl = C.c_int64()
         self._check(self.lib.pic_timing(self.ctx, int(species), C.byref(ms), C.byref(nl),

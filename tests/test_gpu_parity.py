@@ -255,7 +255,14 @@ def test_device_error_word(pic):
 def test_timing_events(pic):
     _say("case: timing")
     wl = random_workload(3, 1000, 1000, seed=80)
+    # tiled kernel: one timed dispatch per tile colour (2^3), species and step
     s = pic.Simulation.from_workload(wl, precision=32, flags=pic.TIMING)
+    s.step(3)
+    ms0, n0 = s.timing(species=0, reset=False)
+    ms, n = s.timing()
+    assert n0 == 3 * 8 and n == 2 * n0 and ms >= ms0 > 0
+    # global kernel: one dispatch per species and step
+    s = pic.Simulation.from_workload(wl, precision=32, flags=pic.TIMING | pic.GLOBAL_KERNEL)
     s.step(3)
     ms, n = s.timing()
     assert n == 6 and ms > 0
