@@ -92,7 +92,8 @@ def run_gpu(args, precision):
     grid = meta.grid
     ion_sp, ele_sp = meta.species[0][0], meta.species[1][0]
     total = I.ionised_slab_3d_count(n, args.ppc, grid.pad)
-    sim = pic.Simulation(grid, precision=precision, flags=pic.TIMING, sort_every=args.sort_every)
+    sim = pic.Simulation(grid, precision=precision, flags=pic.TIMING, sort_every=args.sort_every,
+                         tile=args.tile)
     sid_i = sim.add_species(ion_sp, total)
     sid_e = sim.add_species(ele_sp, total)
     planes = max(1, int(args.chunk_particles // (n[1] * n[2] * args.ppc)))
@@ -179,6 +180,9 @@ def main():
     ap.add_argument("--cells", type=int, nargs=3, default=[512, 256, 256])
     ap.add_argument("--ppc", type=int, default=8)
     ap.add_argument("--sort-every", type=int, default=4)
+    ap.add_argument("--tile", type=int, nargs=3, default=None,
+                    help="cells per tile of the LDS-tiled particle kernel "
+                         "(default: the library's, 8x8x6 for FP32 and 8x8x8 for FP64)")
     ap.add_argument("--chunk-particles", type=float, default=3.4e7)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 run")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -219,7 +223,8 @@ def main():
         "data": "synthetic (seeded, generated in HBM)",
         "config": {"workload": "ionised_slab_3d", "cells": list(args.cells),
                    "two_body_ions": r32["n_ion"], "free_electrons": r32["n_el"],
-                   "ppc": args.ppc, "sort_every": args.sort_every, "precision": "fp32",
+                   "ppc": args.ppc, "sort_every": args.sort_every, "tile": list(args.tile) if args.tile else [8, 8, 6],
+                   "precision": "fp32",
                    "parallelism": "1 GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -773,7 +773,11 @@ int pic_create(const pic_config* cfg, const pic_allocator* alloc, void* hip_stre
   g.sz = (int64_t)g.st[0] * g.st[1];
   g.origin = g.g[0] + g.g[1] * g.sy + g.g[2] * g.sz;
   // tiles
-  const int def3[3] = {8, 8, 8}, def2[3] = {16, 16, 1}, def1[3] = {256, 1, 1};
+  // default tiles: in 3D FP32 an 8x8x6 tile lets two workgroups share a CU
+  // (LDS under 80 KB); FP64 fields need the larger 8^3 tile's one per CU
+  const int def3f[3] = {8, 8, 6}, def3d[3] = {8, 8, 8};
+  const int def2[3] = {16, 16, 1}, def1[3] = {256, 1, 1};
+  const int* def3 = cfg->precision == 32 ? def3f : def3d;
   const int* def = g.nd == 3 ? def3 : (g.nd == 2 ? def2 : def1);
   for (int d = 0; d < 3; d++) {
     int t = d < g.nd ? (cfg->tile[d] > 0 ? cfg->tile[d] : def[d]) : 1;
@@ -782,7 +786,7 @@ int pic_create(const pic_config* cfg, const pic_allocator* alloc, void* hip_stre
     c->ntiles[d] = (g.n[d] + c->tile[d] - 1) / c->tile[d];
   }
   c->sort_every = cfg->sort_every > 0 ? cfg->sort_every : 4;
-  c->tg = pic::make_tile_geom(g, c->tile, c->ntiles);
+  c->tg = pic::make_tile_geom(g, c->tile, c->ntiles, c->rsize);
   c->tiled = !(cfg->flags & PIC_FLAG_GLOBAL_KERNEL) && pic::tiled_supported(g, c->tg, c->rsize);
 
   size_t rs = c->rsize;

@@ -663,30 +663,73 @@ __device__ __forceinline__ uint32_t encode_cell(const GridInfo& g, const int cn[
   return pk;
 }
 
+// Sink for the general (four-node) deposit of one body, which a body
+// needs only when its nearest node changes during the step.  The HBM
+// kernels deposit at once (this sink takes nothing); the tiled kernel
+// queues such bodies in LDS and deposits them after its particle loop, so
+// that a wavefront does not run the long path for one or two lanes.
+struct DepositNow {
+  template <typename Real>
+  __device__ __forceinline__ bool operator()(int, const Real*, const Real*, Real,
+                                             const Real*) const {
+    return false;
+  }
+};
+
+// Stored state of one macro-particle: packed cell, offsets in the cell,
+// momenta, relative displacement, per-particle omega_c and weight (when
+// the species carries them).  Loaded ahead of its cycle so that the
+// tiled kernel can fetch the next particle while advancing this one.
+template <typename Real>
+struct PState {
+  uint32_t cell;
+  Real off[3], u1[3], u2[3], dl[3], wc, w;
+};
+
+template <typename Real, int ND, bool TWO>
+__device__ __forceinline__ void load_state(const SpeciesDev<Real>& s, const PushConst<Real>& c,
+                                           int64_t p, PState<Real>& st) {
+  st.cell = s.cell[p];
+#pragma unroll
+  for (int d = 0; d < 3; d++) st.off[d] = d < ND ? s.off[d][p] : Real(0);
+#pragma unroll
+  for (int q = 0; q < 3; q++) {
+    st.u1[q] = s.u1[q][p];
+    st.u2[q] = TWO ? s.u2[q][p] : Real(0);
+    st.dl[q] = TWO ? s.dl[q][p] : Real(0);
+  }
+  st.wc = TWO && s.wc ? s.wc[p] : c.omega_c;
+  st.w = s.w ? s.w[p] : Real(1);
+}
+
 // Advance macro-particle p through one full cycle.  Gather reads E, B
 // through `fg` at index `fbase` of the particle's cell (strides fsy, fsz);
 // the deposit adds into J at `jbase` (strides jsy, jsz).  GLOBAL selects
-// the HBM form of the deposit (atomics, zero terms skipped).
-template <typename Real, int ND, bool TWO, bool GLOBAL, typename JT = Real>
+// the HBM form of the deposit (atomics, zero terms skipped).  `later`
+// may take over a body's general deposit (returns true if it did).
+template <typename Real, int ND, bool TWO, bool GLOBAL, typename JT = Real,
+          typename Later = DepositNow>
 __device__ __forceinline__ void advance_particle(const GridInfo& g, const SpeciesDev<Real>& s,
                                                  const PushConst<Real>& c, int64_t p,
-                                                 const int ci[3], const FieldPtrs<Real>& fg,
-                                                 int fbase, int fsy, int fsz, JT* const J[3],
-                                                 int jbase, int jsy, int jsz, uint32_t* err) {
+                                                 const PState<Real>& st, const int ci[3],
+                                                 const FieldPtrs<Real>& fg, int fbase, int fsy,
+                                                 int fsz, JT* const J[3], int jbase, int jsy,
+                                                 int jsz, uint32_t* err,
+                                                 const Later& later = Later{}) {
   Real off[3] = {0, 0, 0};
 #pragma unroll
-  for (int d = 0; d < ND; d++) off[d] = s.off[d][p];
+  for (int d = 0; d < ND; d++) off[d] = st.off[d];
   Real u1[3], u2[3] = {0, 0, 0}, dl[3] = {0, 0, 0};
 #pragma unroll
-  for (int q = 0; q < 3; q++) u1[q] = s.u1[q][p];
+  for (int q = 0; q < 3; q++) u1[q] = st.u1[q];
   if constexpr (TWO) {
 #pragma unroll
     for (int q = 0; q < 3; q++) {
-      u2[q] = s.u2[q][p];
-      dl[q] = s.dl[q][p];
+      u2[q] = st.u2[q];
+      dl[q] = st.dl[q];
     }
   }
-  const Real W = s.w ? s.w[p] : Real(1);
+  const Real W = st.w;
 
   // body positions (cell units, relative to the cell)
   Real x1[3] = {0, 0, 0}, x2[3] = {0, 0, 0};
@@ -712,7 +755,7 @@ __device__ __forceinline__ void advance_particle(const GridInfo& g, const Specie
   }
 
   if constexpr (TWO) {
-    const Real wc = s.wc ? s.wc[p] : c.omega_c;
+    const Real wc = st.wc;
     // softened Coulomb bond: F1 = -m_r w_c^2 delta (1 + |delta|^2/a_c^2)^{-3/2}
     Real r2 = dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2];
     Real soft = Real(1);
@@ -820,8 +863,9 @@ __device__ __forceinline__ void advance_particle(const GridInfo& g, const Specie
           Real sd = dl[d] * c.idx[d];
           y[d] = body == 0 ? offn[d] + c.f1 * sd : offn[d] - c.f2 * sd;
         }
-        range_ok = deposit<Real, ND, GLOBAL, JT>(J, jbase, jsy, jsz, xa, y, body == 0 ? qw1 : qw2,
-                                             vb, c) && range_ok;
+        const Real qb = body == 0 ? qw1 : qw2;
+        if (!later(jbase, xa, y, qb, vb))
+          range_ok = deposit<Real, ND, GLOBAL, JT>(J, jbase, jsy, jsz, xa, y, qb, vb, c) && range_ok;
       }
       }
     }
@@ -875,7 +919,7 @@ __device__ __forceinline__ void advance_particle(const GridInfo& g, const Specie
       if (keep)
         deposit3<Real, ND, GLOBAL, JT, false>(J, jbase, jsy, jsz, nn, x1, y1, qw1, v1, x1, y1,
                                               Real(0), v1, c);
-      else
+      else if (!later(jbase, x1, y1, qw1, v1))
         range_ok = deposit<Real, ND, GLOBAL, JT>(J, jbase, jsy, jsz, x1, y1, qw1, v1, c);
     }
     int cn[3] = {ci[0], ci[1], ci[2]};

@@ -16,11 +16,13 @@ __global__ void __launch_bounds__(256) k_push(GridInfo g, FieldPtrs<Real> f, Spe
                                               PushConst<Real> c, uint32_t* err) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= s.n) return;
+  PState<Real> st;
+  load_state<Real, ND, TWO>(s, c, p, st);
   int ci[3];
-  decode_cell<ND>(g, s.cell[p], ci);
+  decode_cell<ND>(g, st.cell, ci);
   const int base = (int)g.origin + ci[0] + ci[1] * (int)g.sy + ci[2] * (int)g.sz;
-  advance_particle<Real, ND, TWO, true>(g, s, c, p, ci, f, base, (int)g.sy, (int)g.sz, f.J, base,
-                                        (int)g.sy, (int)g.sz, err);
+  advance_particle<Real, ND, TWO, true>(g, s, c, p, st, ci, f, base, (int)g.sy, (int)g.sz, f.J,
+                                        base, (int)g.sy, (int)g.sz, err);
 }
 
 // Particles listed by the tiled kernel (outside their tile since the last
@@ -35,11 +37,13 @@ __global__ void __launch_bounds__(256) k_push_list(GridInfo g, FieldPtrs<Real> f
   if (blockIdx.x == 0 && threadIdx.x == 0 && n) atomicAdd(total, n);
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     int64_t p = list[i];
+    PState<Real> st;
+    load_state<Real, ND, TWO>(s, c, p, st);
     int ci[3];
-    decode_cell<ND>(g, s.cell[p], ci);
+    decode_cell<ND>(g, st.cell, ci);
     const int base = (int)g.origin + ci[0] + ci[1] * (int)g.sy + ci[2] * (int)g.sz;
-    advance_particle<Real, ND, TWO, true>(g, s, c, p, ci, f, base, (int)g.sy, (int)g.sz, f.J,
-                                          base, (int)g.sy, (int)g.sz, err);
+    advance_particle<Real, ND, TWO, true>(g, s, c, p, st, ci, f, base, (int)g.sy, (int)g.sz,
+                                          f.J, base, (int)g.sy, (int)g.sz, err);
   }
 }
 

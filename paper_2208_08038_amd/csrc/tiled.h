@@ -7,6 +7,7 @@ namespace pic {
 
 constexpr int kTiledThreads = 512;
 constexpr size_t kTiledMaxLds = 160 * 1024;  // LDS per CU on gfx950
+constexpr int kQueueMax = 1024;              // queued general deposits per tile
 
 // Tile geometry (per dimension; unresolved dimensions are 1).
 struct TileGeom {
@@ -15,9 +16,15 @@ struct TileGeom {
   int nc[3];  // tiles of one colour per dimension (upper bound)
   int F[3];   // field patch extent: T + 4 (2-node apron each side)
   int Jd[3];  // current patch extent: T + 5 (2 below, 3 above)
+  int qcap;   // LDS queue capacity for general (four-node) deposits
+  int nd;     // resolved dimensions
 };
 
-TileGeom make_tile_geom(const GridInfo& g, const int tile[3], const int ntiles[3]);
+// Values per queued deposit: old and new position (resolved axes), charge,
+// velocity along the unresolved axes.
+constexpr int queue_vals(int nd) { return nd + 4; }
+
+TileGeom make_tile_geom(const GridInfo& g, const int tile[3], const int ntiles[3], size_t rsize);
 size_t tiled_lds_bytes(const TileGeom& t, size_t rsize);
 bool tiled_supported(const GridInfo& g, const TileGeom& t, size_t rsize);
 

@@ -5,7 +5,9 @@
 //   2. clears an LDS current patch covering the tile plus the 2-node
 //      (below) / 3-node (above) reach of the order-2 Esirkepov window,
 //   3. advances every particle of the tile, gathering from LDS and
-//      depositing with LDS floating-point atomics,
+//      depositing with LDS floating-point atomics; a body whose nearest
+//      node changes needs the longer four-node deposit, which is queued in
+//      LDS and run after the loop by consecutive threads,
 //   4. adds the patch into the global current with plain loads and stores.
 // Tiles are launched in 2^ndim colours (parity of the tile coordinates):
 // patches of tiles of one colour never overlap (patch extent T + 5 <= 2T),
@@ -13,6 +15,8 @@
 // particle that has drifted out of its tile since the last sort is only
 // listed here; a second kernel advances the listed particles from HBM
 // after the last colour, adding their current with global atomics.
+#include <algorithm>
+
 #include "cycle.h"
 #include "tiled.h"
 
@@ -26,7 +30,45 @@ namespace {
 // per-tile reduction.
 using PatchT = double;
 
-template <typename Real, int ND, bool TWO>
+// LDS queue of general deposits (structure of arrays, `cap` entries).
+template <typename Real, int ND>
+struct LdsQueue {
+  Real* val;        // queue_vals(ND) rows of cap values
+  int* base;        // patch index of the body's cell
+  uint32_t* count;  // entries requested (may exceed cap)
+  int cap;
+  __device__ __forceinline__ bool operator()(int jb, const Real* x0, const Real* x1, Real q,
+                                             const Real* v) const {
+    const uint32_t i = atomicAdd(count, 1u);
+    if (i >= (uint32_t)cap) return false;  // full: the caller deposits at once
+    base[i] = jb;
+    int k = 0;
+#pragma unroll
+    for (int d = 0; d < ND; d++) val[(k++) * cap + i] = x0[d];
+#pragma unroll
+    for (int d = 0; d < ND; d++) val[(k++) * cap + i] = x1[d];
+    val[(k++) * cap + i] = q;
+#pragma unroll
+    for (int d = ND; d < 3; d++) val[(k++) * cap + i] = v[d];
+    return true;
+  }
+  __device__ __forceinline__ void load(int i, int& jb, Real x0[3], Real x1[3], Real& q,
+                                       Real v[3]) const {
+    jb = base[i];
+    int k = 0;
+#pragma unroll
+    for (int d = 0; d < 3; d++) x0[d] = x1[d] = v[d] = Real(0);
+#pragma unroll
+    for (int d = 0; d < ND; d++) x0[d] = val[(k++) * cap + i];
+#pragma unroll
+    for (int d = 0; d < ND; d++) x1[d] = val[(k++) * cap + i];
+    q = val[(k++) * cap + i];
+#pragma unroll
+    for (int d = ND; d < 3; d++) v[d] = val[(k++) * cap + i];
+  }
+};
+
+template <typename Real, int ND, bool TWO, bool PREFETCH>
 __device__ __forceinline__ void tiled_body(const GridInfo& g, const FieldPtrs<Real>& f,
                                            const SpeciesDev<Real>& s, const PushConst<Real>& c,
                                            const TileGeom& t, const uint32_t* tile_off, int color,
@@ -58,7 +100,8 @@ __device__ __forceinline__ void tiled_body(const GridInfo& g, const FieldPtrs<Re
   const int nf = FX * FY * FZ, nj = JX * JY * JZ;
   FieldPtrs<Real> fl;
   PatchT* jl[3];
-  // the FP64 patch comes first (8-byte aligned), the fields after it
+  // the FP64 patch comes first (8-byte aligned), the fields after it,
+  // then the deposit queue
   PatchT* pbase = reinterpret_cast<PatchT*>(smem_raw);
   Real* fbase_l = reinterpret_cast<Real*>(pbase + 3 * nj);
   for (int a = 0; a < 3; a++) {
@@ -67,6 +110,11 @@ __device__ __forceinline__ void tiled_body(const GridInfo& g, const FieldPtrs<Re
     fl.B[a] = fbase_l + (3 + a) * nf;
     fl.J[a] = nullptr;
   }
+  LdsQueue<Real, ND> queue;
+  queue.cap = t.qcap;
+  queue.val = fbase_l + 6 * nf;
+  queue.base = reinterpret_cast<int*>(queue.val + queue_vals(ND) * t.qcap);
+  queue.count = reinterpret_cast<uint32_t*>(queue.base + t.qcap);
   // patch origins in storage: field patch starts 2 nodes below the tile,
   // current patch likewise (it extends 3 nodes above)
   int64_t forg = g.origin;
@@ -89,6 +137,7 @@ __device__ __forceinline__ void tiled_body(const GridInfo& g, const FieldPtrs<Re
     }
   }
   for (int q = threadIdx.x; q < 3 * nj; q += blockDim.x) jl[0][q] = PatchT(0);
+  if (threadIdx.x == 0) *queue.count = 0u;
   __syncthreads();
 
   // 3. particles of the tile
@@ -96,13 +145,25 @@ __device__ __forceinline__ void tiled_body(const GridInfo& g, const FieldPtrs<Re
   const int jsy = JX, jsz = JX * JY;
   const int lane = threadIdx.x & 63;
   const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  // the state of a thread's next particle is loaded while it advances the
+  // present one
+  // (PREFETCH; costs the registers of one more state)
+  PState<Real> next;
+  if (PREFETCH && p0 + threadIdx.x < p1) load_state<Real, ND, TWO>(s, c, p0 + threadIdx.x, next);
   for (int64_t p0w = p0; p0w < p1; p0w += blockDim.x) {
     const int64_t p = p0w + threadIdx.x;
     const bool valid = p < p1;
+    PState<Real> st;
+    if (PREFETCH) {
+      st = next;
+      if (p + blockDim.x < p1) load_state<Real, ND, TWO>(s, c, p + blockDim.x, next);
+    } else if (valid) {
+      load_state<Real, ND, TWO>(s, c, p, st);
+    }
     int ci[3] = {0, 0, 0};
     bool inside = false;
     if (valid) {
-      decode_cell<ND>(g, s.cell[p], ci);
+      decode_cell<ND>(g, st.cell, ci);
       inside = true;
 #pragma unroll
       for (int d = 0; d < ND; d++) inside = inside && ci[d] >= lo[d] && ci[d] < hi[d];
@@ -128,9 +189,20 @@ __device__ __forceinline__ void tiled_body(const GridInfo& g, const FieldPtrs<Re
         lf += (ci[2] - lo[2] + 2) * fsz;
         lj += (ci[2] - lo[2] + 2) * jsz;
       }
-      advance_particle<Real, ND, TWO, false, PatchT>(g, s, c, p, ci, fl, lf, fsy, fsz, jl, lj,
-                                                     jsy, jsz, err);
+      advance_particle<Real, ND, TWO, false, PatchT>(g, s, c, p, st, ci, fl, lf, fsy, fsz, jl,
+                                                     lj, jsy, jsz, err, queue);
     }
+  }
+  __syncthreads();
+
+  // 3b. the queued general deposits, one per thread
+  const int nq = min((int)*queue.count, t.qcap);
+  for (int e = threadIdx.x; e < nq; e += blockDim.x) {
+    int jb;
+    Real x0[3], x1[3], v[3], q;
+    queue.load(e, jb, x0, x1, q, v);
+    if (!deposit<Real, ND, false, PatchT>(jl, jb, jsy, jsz, x0, x1, q, v, c))
+      atomicOr(err, PIC_ERR_RANGE);
   }
   __syncthreads();
 
@@ -157,28 +229,30 @@ __device__ __forceinline__ void tiled_body(const GridInfo& g, const FieldPtrs<Re
 }
 
 // FP32 fields with the FP64 current patch of an 8^3 tile take 94 KB of LDS
-// (one workgroup per CU); FP64 fields take 136 KB.  With one workgroup of
-// 8 waves per CU each wave may use up to 256 VGPRs.
-template <int ND, bool TWO>
-__global__ void __launch_bounds__(kTiledThreads) __attribute__((amdgpu_waves_per_eu(2)))
+// (one workgroup of 8 waves per CU: each wave may use up to 256 VGPRs);
+// an 8x8x6 tile takes under 80 KB, so two workgroups fit when each wave
+// keeps to 128 VGPRs (WPE = 4 waves per SIMD).
+template <int ND, bool TWO, int WPE>
+__global__ void __launch_bounds__(kTiledThreads) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_push_tiled_f32(GridInfo g, FieldPtrs<float> f, SpeciesDev<float> s, PushConst<float> c,
                  TileGeom t, const uint32_t* tile_off, int color, uint32_t* list,
                  uint32_t* nlist, uint32_t* err) {
-  tiled_body<float, ND, TWO>(g, f, s, c, t, tile_off, color, list, nlist, err);
+  tiled_body<float, ND, TWO, (WPE < 4 || !TWO)>(g, f, s, c, t, tile_off, color, list, nlist, err);
 }
 
-template <int ND, bool TWO>
-__global__ void __launch_bounds__(kTiledThreads) __attribute__((amdgpu_waves_per_eu(2)))
+template <int ND, bool TWO, int WPE>
+__global__ void __launch_bounds__(kTiledThreads) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_push_tiled_f64(GridInfo g, FieldPtrs<double> f, SpeciesDev<double> s, PushConst<double> c,
                  TileGeom t, const uint32_t* tile_off, int color, uint32_t* list,
                  uint32_t* nlist, uint32_t* err) {
-  tiled_body<double, ND, TWO>(g, f, s, c, t, tile_off, color, list, nlist, err);
+  tiled_body<double, ND, TWO, (WPE < 4 || !TWO)>(g, f, s, c, t, tile_off, color, list, nlist, err);
 }
 
 }  // namespace
 
-TileGeom make_tile_geom(const GridInfo& g, const int tile[3], const int ntiles[3]) {
+TileGeom make_tile_geom(const GridInfo& g, const int tile[3], const int ntiles[3], size_t rsize) {
   TileGeom t{};
+  t.nd = g.nd;
   for (int d = 0; d < 3; d++) {
     bool r = d < g.nd;
     t.T[d] = r ? tile[d] : 1;
@@ -187,13 +261,26 @@ TileGeom make_tile_geom(const GridInfo& g, const int tile[3], const int ntiles[3
     t.F[d] = r ? tile[d] + 4 : 1;
     t.Jd[d] = r ? tile[d] + 5 : 1;
   }
+  // the queue takes what LDS is left, up to kQueueMax entries; when the
+  // patches leave room for 64 entries within half the LDS, it stops there
+  // so that two workgroups can share a CU
+  t.qcap = 0;
+  size_t fixed = tiled_lds_bytes(t, rsize);
+  size_t entry = (size_t)queue_vals(g.nd) * rsize + sizeof(int);
+  size_t limit = fixed + 64 * entry <= kTiledMaxLds / 2 ? kTiledMaxLds / 2 : kTiledMaxLds;
+  if (fixed < limit) {
+    size_t room = (limit - fixed) / entry;
+    t.qcap = (int)std::min<size_t>(room, kQueueMax) & ~63;
+  }
   return t;
 }
 
+// patch, fields, queue (values, cell indices) and the queue counter
 size_t tiled_lds_bytes(const TileGeom& t, size_t rsize) {
   size_t nf = (size_t)t.F[0] * t.F[1] * t.F[2];
   size_t nj = (size_t)t.Jd[0] * t.Jd[1] * t.Jd[2];
-  return 6 * nf * rsize + 3 * nj * sizeof(double);
+  size_t queue = (size_t)t.qcap * ((size_t)queue_vals(t.nd) * rsize + sizeof(int));
+  return 3 * nj * sizeof(double) + 6 * nf * rsize + queue + 16;
 }
 
 bool tiled_supported(const GridInfo& g, const TileGeom& t, size_t rsize) {
@@ -202,17 +289,17 @@ bool tiled_supported(const GridInfo& g, const TileGeom& t, size_t rsize) {
   return tiled_lds_bytes(t, rsize) <= kTiledMaxLds;
 }
 
-template <typename Real, int ND, bool TWO>
-static hipError_t launch_colour(const GridInfo& g, const FieldPtrs<Real>& f,
-                                const SpeciesDev<Real>& s, const PushConst<Real>& c,
-                                const TileGeom& t, const uint32_t* tile_off, int color,
-                                uint32_t* list, uint32_t* nlist, uint32_t* err, size_t lds,
-                                hipStream_t st) {
+template <typename Real, int ND, bool TWO, int WPE>
+static hipError_t launch_colour_wpe(const GridInfo& g, const FieldPtrs<Real>& f,
+                                    const SpeciesDev<Real>& s, const PushConst<Real>& c,
+                                    const TileGeom& t, const uint32_t* tile_off, int color,
+                                    uint32_t* list, uint32_t* nlist, uint32_t* err, size_t lds,
+                                    hipStream_t st) {
   const void* fn;
   if constexpr (sizeof(Real) == 4)
-    fn = (const void*)k_push_tiled_f32<ND, TWO>;
+    fn = (const void*)k_push_tiled_f32<ND, TWO, WPE>;
   else
-    fn = (const void*)k_push_tiled_f64<ND, TWO>;
+    fn = (const void*)k_push_tiled_f64<ND, TWO, WPE>;
   static size_t attr_lds = 0;
   if (lds > 64 * 1024 && lds > attr_lds) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -221,12 +308,44 @@ static hipError_t launch_colour(const GridInfo& g, const FieldPtrs<Real>& f,
   }
   unsigned blocks = (unsigned)((int64_t)t.nc[0] * t.nc[1] * t.nc[2]);
   if constexpr (sizeof(Real) == 4)
-    hipLaunchKernelGGL((k_push_tiled_f32<ND, TWO>), dim3(blocks), dim3(kTiledThreads), lds, st, g,
-                       f, s, c, t, tile_off, color, list, nlist, err);
+    hipLaunchKernelGGL((k_push_tiled_f32<ND, TWO, WPE>), dim3(blocks), dim3(kTiledThreads), lds,
+                       st, g, f, s, c, t, tile_off, color, list, nlist, err);
   else
-    hipLaunchKernelGGL((k_push_tiled_f64<ND, TWO>), dim3(blocks), dim3(kTiledThreads), lds, st, g,
-                       f, s, c, t, tile_off, color, list, nlist, err);
+    hipLaunchKernelGGL((k_push_tiled_f64<ND, TWO, WPE>), dim3(blocks), dim3(kTiledThreads), lds,
+                       st, g, f, s, c, t, tile_off, color, list, nlist, err);
   return hipGetLastError();
+}
+
+// True if the 4-waves-per-SIMD build of the kernel keeps everything in
+// registers (no scratch).
+template <typename Real, int ND, bool TWO>
+static bool wpe4_without_spill() {
+  static int ok = -1;
+  if (ok < 0) {
+    hipFuncAttributes a{};
+    const void* fn;
+    if constexpr (sizeof(Real) == 4)
+      fn = (const void*)k_push_tiled_f32<ND, TWO, 4>;
+    else
+      fn = (const void*)k_push_tiled_f64<ND, TWO, 4>;
+    ok = hipFuncGetAttributes(&a, fn) == hipSuccess && a.localSizeBytes == 0 ? 1 : 0;
+  }
+  return ok == 1;
+}
+
+// two workgroups per CU when their LDS fits and the smaller register
+// budget needs no spills, else one with the larger register budget
+template <typename Real, int ND, bool TWO>
+static hipError_t launch_colour(const GridInfo& g, const FieldPtrs<Real>& f,
+                                const SpeciesDev<Real>& s, const PushConst<Real>& c,
+                                const TileGeom& t, const uint32_t* tile_off, int color,
+                                uint32_t* list, uint32_t* nlist, uint32_t* err, size_t lds,
+                                hipStream_t st) {
+  if (2 * lds <= kTiledMaxLds && wpe4_without_spill<Real, ND, TWO>())
+    return launch_colour_wpe<Real, ND, TWO, 4>(g, f, s, c, t, tile_off, color, list, nlist, err,
+                                               lds, st);
+  return launch_colour_wpe<Real, ND, TWO, 2>(g, f, s, c, t, tile_off, color, list, nlist, err,
+                                             lds, st);
 }
 
 template <typename Real>

@@ -116,6 +116,28 @@ def test_coupled_periodic_fp64(pic, ndim):
     assert s.diagnostics()["error_word"] == 0
 
 
+@pytest.mark.parametrize("tile", [(8, 8, 8), (8, 8, 6), (6, 8, 8), (5, 5, 5), (16, 8, 6)])
+def test_tile_shapes(pic, tile):
+    """Other tile shapes (partial tiles at the upper faces, two workgroups
+    per CU where the LDS footprint allows): FP64 follows the oracle,
+    FP32 within its tolerance."""
+    _say(f"case: tile shape {tile}")
+    wl = random_workload(3, 300, 300, seed=24)
+    o, s = _both(wl, pic, 64, sort_every=3, tile=tile)
+    o.step(10)
+    s.step(10)
+    assert o.diagnostics()["error_word"] == 0, "oracle run left the valid range"
+    Eo, Bo, Jo = o.fields()
+    Eg, Bg, Jg = s.fields()
+    assert rel_l2(Eg, Eo) < 1e-12 and rel_l2(Bg, Bo) < 1e-12 and rel_l2(Jg, Jo) < 1e-12
+    _compare_particles(o, s, wl, 1e-11)
+    s32 = pic.Simulation.from_workload(wl, precision=32, sort_every=3, tile=tile)
+    s32.step(10)
+    Eg, Bg, _ = s32.fields()
+    assert rel_l2(Eg, Eo) < 2e-5 and rel_l2(Bg, Bo) < 2e-5
+    assert s.diagnostics()["error_word"] == 0 and s32.diagnostics()["error_word"] == 0
+
+
 def test_open_faces_laser_walls_fp64(pic):
     """2D box with Mur faces, a Gaussian laser entering at x-min, reflecting
     particle walls: fields and particles follow the oracle."""
