@@ -9,15 +9,59 @@ constexpr int kTiledThreads = 512;
 constexpr size_t kTiledMaxLds = 160 * 1024;  // LDS per CU on gfx950
 constexpr int kQueueMax = 1024;              // queued general deposits per tile
 
+// LDS row pitch (in values) for rows of `width` values such that a
+// wavefront whose 64 lanes sit in `tx` consecutive cells of 64 / tx rows of
+// one layer touches 64 distinct banks when they read the same relative
+// node: the pitch is tx times an odd number (tx a divisor of 64 below 64;
+// otherwise rows are packed).
+constexpr int bank_pitch(int width, int tx) {
+  if (tx <= 0 || tx >= 64 || 64 % tx != 0) return width;
+  int m = (width + tx - 1) / tx;
+  if (m % 2 == 0) m++;
+  return tx * m;
+}
+
+// LDS layout of a tile's patches.  Field components are stored in pairs
+// (Ex Ey | Ez Bx | By Bz) with the two rows of a pair side by side, which
+// fills the row pitch that the bank rule asks for (24 values for an 8-cell
+// tile row) with data instead of padding.  The three FP64 current
+// components share each row, packed: padding those rows to the bank rule
+// measured slower on the 512x256x256 slab.
+struct PatchLayout {
+  int F[3];    // field patch extent: T + 4 (2-node apron each side)
+  int Jd[3];   // current patch extent: T + 5 (2 below, 3 above)
+  int fpitch;  // field row pitch (2 components)
+  int fplane;  // fpitch * F[1]
+  int fpair;   // values of one component pair: fplane * F[2]
+  int jpitch;  // current row pitch (3 components, packed)
+  int jplane;  // jpitch * Jd[1]
+  int nj;      // values of the current patch: jplane * Jd[2]
+};
+
+constexpr PatchLayout patch_layout(int tx, int ty, int tz, int nd) {
+  PatchLayout L{};
+  const int T[3] = {tx, ty, tz};
+  for (int d = 0; d < 3; d++) {
+    L.F[d] = d < nd ? T[d] + 4 : 1;
+    L.Jd[d] = d < nd ? T[d] + 5 : 1;
+  }
+  L.fpitch = nd > 1 ? bank_pitch(2 * L.F[0], tx) : 2 * L.F[0];
+  L.fplane = L.fpitch * L.F[1];
+  L.fpair = L.fplane * L.F[2];
+  L.jpitch = 3 * L.Jd[0];
+  L.jplane = L.jpitch * L.Jd[1];
+  L.nj = L.jplane * L.Jd[2];
+  return L;
+}
+
 // Tile geometry (per dimension; unresolved dimensions are 1).
 struct TileGeom {
-  int T[3];   // tile shape in cells
-  int nt[3];  // tiles per dimension
-  int nc[3];  // tiles of one colour per dimension (upper bound)
-  int F[3];   // field patch extent: T + 4 (2-node apron each side)
-  int Jd[3];  // current patch extent: T + 5 (2 below, 3 above)
-  int qcap;   // LDS queue capacity for general (four-node) deposits
-  int nd;     // resolved dimensions
+  int T[3];       // tile shape in cells
+  int nt[3];      // tiles per dimension
+  int nc[3];      // tiles of one colour per dimension (upper bound)
+  PatchLayout L;  // LDS layout of the patches
+  int qcap;       // LDS queue capacity for general (four-node) deposits
+  int nd;         // resolved dimensions
 };
 
 // Values per queued deposit: old and new position (resolved axes), charge,

@@ -68,7 +68,10 @@ struct LdsQueue {
   }
 };
 
-template <typename Real, int ND, bool TWO, bool PREFETCH>
+// TX, TY, TZ > 0 fix the tile shape at compile time (patch strides become
+// constants, so LDS addresses fold into instruction offsets); 0 takes the
+// shape from `t`.
+template <typename Real, int ND, bool TWO, bool PREFETCH, int TX, int TY, int TZ>
 __device__ __forceinline__ void tiled_body(const GridInfo& g, const FieldPtrs<Real>& f,
                                            const SpeciesDev<Real>& s, const PushConst<Real>& c,
                                            const TileGeom& t, const uint32_t* tile_off, int color,
@@ -86,33 +89,41 @@ __device__ __forceinline__ void tiled_body(const GridInfo& g, const FieldPtrs<Re
   if (ND > 2) tc[2] = 2 * b + ((color >> 2) & 1);
   for (int d = 0; d < ND; d++)
     if (tc[d] >= t.nt[d]) return;  // whole block leaves before any barrier
+  const int TT[3] = {TX ? TX : t.T[0], TY ? TY : t.T[1], TZ ? TZ : t.T[2]};
   int lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
   for (int d = 0; d < ND; d++) {
-    lo[d] = tc[d] * t.T[d];
-    hi[d] = min(lo[d] + t.T[d], g.n[d]);
+    lo[d] = tc[d] * TT[d];
+    hi[d] = min(lo[d] + TT[d], g.n[d]);
   }
   const int64_t tile = tc[0] + (int64_t)t.nt[0] * (tc[1] + (int64_t)t.nt[1] * tc[2]);
   const int64_t p0 = tile_off[tile], p1 = tile_off[tile + 1];
 
-  // LDS layout: E[3], B[3] on the field patch, then J[3] on the current patch
-  const int FX = t.F[0], FY = t.F[1], FZ = t.F[2];
-  const int JX = t.Jd[0], JY = t.Jd[1], JZ = t.Jd[2];
-  const int nf = FX * FY * FZ, nj = JX * JY * JZ;
+  // LDS layout: the FP64 current patch first (8-byte aligned), then the
+  // field pairs, then the deposit queue
+  PatchLayout L;
+  if constexpr (TX > 0) {
+    constexpr PatchLayout Lc = patch_layout(TX, TY, TZ, ND);
+    L = Lc;
+  } else {
+    L = t.L;
+  }
   FieldPtrs<Real> fl;
   PatchT* jl[3];
-  // the FP64 patch comes first (8-byte aligned), the fields after it,
-  // then the deposit queue
   PatchT* pbase = reinterpret_cast<PatchT*>(smem_raw);
-  Real* fbase_l = reinterpret_cast<Real*>(pbase + 3 * nj);
+  Real* fbase_l = reinterpret_cast<Real*>(pbase + L.nj);
   for (int a = 0; a < 3; a++) {
-    jl[a] = pbase + a * nj;
-    fl.E[a] = fbase_l + a * nf;
-    fl.B[a] = fbase_l + (3 + a) * nf;
+    jl[a] = pbase + a * L.Jd[0];
     fl.J[a] = nullptr;
+  }
+  Real* fc[6];
+  for (int cmp = 0; cmp < 6; cmp++) fc[cmp] = fbase_l + (cmp >> 1) * L.fpair + (cmp & 1) * L.F[0];
+  for (int a = 0; a < 3; a++) {
+    fl.E[a] = fc[a];
+    fl.B[a] = fc[3 + a];
   }
   LdsQueue<Real, ND> queue;
   queue.cap = t.qcap;
-  queue.val = fbase_l + 6 * nf;
+  queue.val = fbase_l + 3 * L.fpair;
   queue.base = reinterpret_cast<int*>(queue.val + queue_vals(ND) * t.qcap);
   queue.count = reinterpret_cast<uint32_t*>(queue.base + t.qcap);
   // patch origins in storage: field patch starts 2 nodes below the tile,
@@ -125,24 +136,26 @@ __device__ __forceinline__ void tiled_body(const GridInfo& g, const FieldPtrs<Re
   // 1-2. stage fields (only the part a partial tile needs), clear the patch
   int fext[3] = {1, 1, 1};
   for (int d = 0; d < ND; d++) fext[d] = (hi[d] - lo[d]) + 4;
+  const int nf = L.F[0] * L.F[1] * L.F[2];
   for (int q = threadIdx.x; q < nf; q += blockDim.x) {
-    int a = q % FX, r = q / FX;
-    int bb = r % FY, cc = r / FY;
+    int a = q % L.F[0], r = q / L.F[0];
+    int bb = r % L.F[1], cc = r / L.F[1];
     if (a >= fext[0] || bb >= fext[1] || cc >= fext[2]) continue;
     int64_t go = forg + a + (int64_t)bb * g.sy + (int64_t)cc * g.sz;
+    const int li = a + bb * L.fpitch + cc * L.fplane;
 #pragma unroll
     for (int comp = 0; comp < 3; comp++) {
-      fl.E[comp][q] = f.E[comp][go];
-      fl.B[comp][q] = f.B[comp][go];
+      fl.E[comp][li] = f.E[comp][go];
+      fl.B[comp][li] = f.B[comp][go];
     }
   }
-  for (int q = threadIdx.x; q < 3 * nj; q += blockDim.x) jl[0][q] = PatchT(0);
+  for (int q = threadIdx.x; q < L.nj; q += blockDim.x) pbase[q] = PatchT(0);
   if (threadIdx.x == 0) *queue.count = 0u;
   __syncthreads();
 
   // 3. particles of the tile
-  const int fsy = FX, fsz = FX * FY;
-  const int jsy = JX, jsz = JX * JY;
+  const int fsy = L.fpitch, fsz = L.fplane;
+  const int jsy = L.jpitch, jsz = L.jplane;
   const int lane = threadIdx.x & 63;
   const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   // the state of a thread's next particle is loaded while it advances the
@@ -215,14 +228,16 @@ __device__ __forceinline__ void tiled_body(const GridInfo& g, const FieldPtrs<Re
     jorg += (int64_t)(lo[d] - 2) * sd;
     jext[d] = (hi[d] - lo[d]) + 5;
   }
-  for (int q = threadIdx.x; q < nj; q += blockDim.x) {
-    int a = q % JX, r = q / JX;
-    int bb = r % JY, cc = r / JY;
+  const int njn = L.Jd[0] * L.Jd[1] * L.Jd[2];
+  for (int q = threadIdx.x; q < njn; q += blockDim.x) {
+    int a = q % L.Jd[0], r = q / L.Jd[0];
+    int bb = r % L.Jd[1], cc = r / L.Jd[1];
     if (a >= jext[0] || bb >= jext[1] || cc >= jext[2]) continue;
     int64_t go = jorg + a + (int64_t)bb * g.sy + (int64_t)cc * g.sz;
+    const int li = a + bb * L.jpitch + cc * L.jplane;
 #pragma unroll
     for (int comp = 0; comp < 3; comp++) {
-      PatchT v = jl[comp][q];
+      PatchT v = jl[comp][li];
       if (v != PatchT(0)) f.J[comp][go] = (Real)((PatchT)f.J[comp][go] + v);
     }
   }
@@ -232,20 +247,22 @@ __device__ __forceinline__ void tiled_body(const GridInfo& g, const FieldPtrs<Re
 // (one workgroup of 8 waves per CU: each wave may use up to 256 VGPRs);
 // an 8x8x6 tile takes under 80 KB, so two workgroups fit when each wave
 // keeps to 128 VGPRs (WPE = 4 waves per SIMD).
-template <int ND, bool TWO, int WPE>
+template <int ND, bool TWO, int WPE, int TX, int TY, int TZ>
 __global__ void __launch_bounds__(kTiledThreads) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_push_tiled_f32(GridInfo g, FieldPtrs<float> f, SpeciesDev<float> s, PushConst<float> c,
                  TileGeom t, const uint32_t* tile_off, int color, uint32_t* list,
                  uint32_t* nlist, uint32_t* err) {
-  tiled_body<float, ND, TWO, (WPE < 4 || !TWO)>(g, f, s, c, t, tile_off, color, list, nlist, err);
+  tiled_body<float, ND, TWO, (WPE < 4 || !TWO), TX, TY, TZ>(g, f, s, c, t, tile_off, color, list,
+                                                            nlist, err);
 }
 
-template <int ND, bool TWO, int WPE>
+template <int ND, bool TWO, int WPE, int TX, int TY, int TZ>
 __global__ void __launch_bounds__(kTiledThreads) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_push_tiled_f64(GridInfo g, FieldPtrs<double> f, SpeciesDev<double> s, PushConst<double> c,
                  TileGeom t, const uint32_t* tile_off, int color, uint32_t* list,
                  uint32_t* nlist, uint32_t* err) {
-  tiled_body<double, ND, TWO, (WPE < 4 || !TWO)>(g, f, s, c, t, tile_off, color, list, nlist, err);
+  tiled_body<double, ND, TWO, (WPE < 4 || !TWO), TX, TY, TZ>(g, f, s, c, t, tile_off, color, list,
+                                                             nlist, err);
 }
 
 }  // namespace
@@ -258,29 +275,27 @@ TileGeom make_tile_geom(const GridInfo& g, const int tile[3], const int ntiles[3
     t.T[d] = r ? tile[d] : 1;
     t.nt[d] = r ? ntiles[d] : 1;
     t.nc[d] = r ? (ntiles[d] + 1) / 2 : 1;
-    t.F[d] = r ? tile[d] + 4 : 1;
-    t.Jd[d] = r ? tile[d] + 5 : 1;
   }
+  t.L = patch_layout(t.T[0], t.T[1], t.T[2], g.nd);
   // the queue takes what LDS is left, up to kQueueMax entries; when the
-  // patches leave room for 64 entries within half the LDS, it stops there
-  // so that two workgroups can share a CU
+  // patches leave room for 32 entries within half the LDS, it stops there
+  // so that two workgroups can share a CU (a full queue only sends the
+  // overflow down the direct path)
   t.qcap = 0;
   size_t fixed = tiled_lds_bytes(t, rsize);
   size_t entry = (size_t)queue_vals(g.nd) * rsize + sizeof(int);
-  size_t limit = fixed + 64 * entry <= kTiledMaxLds / 2 ? kTiledMaxLds / 2 : kTiledMaxLds;
+  size_t limit = fixed + 32 * entry <= kTiledMaxLds / 2 ? kTiledMaxLds / 2 : kTiledMaxLds;
   if (fixed < limit) {
     size_t room = (limit - fixed) / entry;
-    t.qcap = (int)std::min<size_t>(room, kQueueMax) & ~63;
+    t.qcap = (int)std::min<size_t>(room, kQueueMax) & ~31;
   }
   return t;
 }
 
 // patch, fields, queue (values, cell indices) and the queue counter
 size_t tiled_lds_bytes(const TileGeom& t, size_t rsize) {
-  size_t nf = (size_t)t.F[0] * t.F[1] * t.F[2];
-  size_t nj = (size_t)t.Jd[0] * t.Jd[1] * t.Jd[2];
   size_t queue = (size_t)t.qcap * ((size_t)queue_vals(t.nd) * rsize + sizeof(int));
-  return 3 * nj * sizeof(double) + 6 * nf * rsize + queue + 16;
+  return (size_t)t.L.nj * sizeof(double) + 3 * (size_t)t.L.fpair * rsize + queue + 16;
 }
 
 bool tiled_supported(const GridInfo& g, const TileGeom& t, size_t rsize) {
@@ -289,63 +304,85 @@ bool tiled_supported(const GridInfo& g, const TileGeom& t, size_t rsize) {
   return tiled_lds_bytes(t, rsize) <= kTiledMaxLds;
 }
 
-template <typename Real, int ND, bool TWO, int WPE>
+template <typename Real, int ND, bool TWO, int WPE, int TX, int TY, int TZ>
+static const void* tiled_kernel() {
+  if constexpr (sizeof(Real) == 4)
+    return (const void*)k_push_tiled_f32<ND, TWO, WPE, TX, TY, TZ>;
+  else
+    return (const void*)k_push_tiled_f64<ND, TWO, WPE, TX, TY, TZ>;
+}
+
+template <typename Real, int ND, bool TWO, int WPE, int TX, int TY, int TZ>
 static hipError_t launch_colour_wpe(const GridInfo& g, const FieldPtrs<Real>& f,
                                     const SpeciesDev<Real>& s, const PushConst<Real>& c,
                                     const TileGeom& t, const uint32_t* tile_off, int color,
                                     uint32_t* list, uint32_t* nlist, uint32_t* err, size_t lds,
                                     hipStream_t st) {
-  const void* fn;
-  if constexpr (sizeof(Real) == 4)
-    fn = (const void*)k_push_tiled_f32<ND, TWO, WPE>;
-  else
-    fn = (const void*)k_push_tiled_f64<ND, TWO, WPE>;
   static size_t attr_lds = 0;
   if (lds > 64 * 1024 && lds > attr_lds) {
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute(tiled_kernel<Real, ND, TWO, WPE, TX, TY, TZ>(),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     attr_lds = lds;
   }
   unsigned blocks = (unsigned)((int64_t)t.nc[0] * t.nc[1] * t.nc[2]);
   if constexpr (sizeof(Real) == 4)
-    hipLaunchKernelGGL((k_push_tiled_f32<ND, TWO, WPE>), dim3(blocks), dim3(kTiledThreads), lds,
-                       st, g, f, s, c, t, tile_off, color, list, nlist, err);
+    hipLaunchKernelGGL((k_push_tiled_f32<ND, TWO, WPE, TX, TY, TZ>), dim3(blocks),
+                       dim3(kTiledThreads), lds, st, g, f, s, c, t, tile_off, color, list, nlist,
+                       err);
   else
-    hipLaunchKernelGGL((k_push_tiled_f64<ND, TWO, WPE>), dim3(blocks), dim3(kTiledThreads), lds,
-                       st, g, f, s, c, t, tile_off, color, list, nlist, err);
+    hipLaunchKernelGGL((k_push_tiled_f64<ND, TWO, WPE, TX, TY, TZ>), dim3(blocks),
+                       dim3(kTiledThreads), lds, st, g, f, s, c, t, tile_off, color, list, nlist,
+                       err);
   return hipGetLastError();
 }
 
 // True if the 4-waves-per-SIMD build of the kernel keeps everything in
 // registers (no scratch).
-template <typename Real, int ND, bool TWO>
+template <typename Real, int ND, bool TWO, int TX, int TY, int TZ>
 static bool wpe4_without_spill() {
   static int ok = -1;
   if (ok < 0) {
     hipFuncAttributes a{};
-    const void* fn;
-    if constexpr (sizeof(Real) == 4)
-      fn = (const void*)k_push_tiled_f32<ND, TWO, 4>;
-    else
-      fn = (const void*)k_push_tiled_f64<ND, TWO, 4>;
-    ok = hipFuncGetAttributes(&a, fn) == hipSuccess && a.localSizeBytes == 0 ? 1 : 0;
+    ok = hipFuncGetAttributes(&a, tiled_kernel<Real, ND, TWO, 4, TX, TY, TZ>()) == hipSuccess &&
+                 a.localSizeBytes == 0
+             ? 1
+             : 0;
   }
   return ok == 1;
 }
 
 // two workgroups per CU when their LDS fits and the smaller register
 // budget needs no spills, else one with the larger register budget
+template <typename Real, int ND, bool TWO, int TX, int TY, int TZ>
+static hipError_t launch_colour_shape(const GridInfo& g, const FieldPtrs<Real>& f,
+                                      const SpeciesDev<Real>& s, const PushConst<Real>& c,
+                                      const TileGeom& t, const uint32_t* tile_off, int color,
+                                      uint32_t* list, uint32_t* nlist, uint32_t* err, size_t lds,
+                                      hipStream_t st) {
+  if (2 * lds <= kTiledMaxLds && wpe4_without_spill<Real, ND, TWO, TX, TY, TZ>())
+    return launch_colour_wpe<Real, ND, TWO, 4, TX, TY, TZ>(g, f, s, c, t, tile_off, color, list,
+                                                           nlist, err, lds, st);
+  return launch_colour_wpe<Real, ND, TWO, 2, TX, TY, TZ>(g, f, s, c, t, tile_off, color, list,
+                                                         nlist, err, lds, st);
+}
+
+// the default 3D tiles (8x8x6 for FP32, 8x8x8 for FP64) have builds with
+// compile-time strides; any other shape runs the generic build
 template <typename Real, int ND, bool TWO>
 static hipError_t launch_colour(const GridInfo& g, const FieldPtrs<Real>& f,
                                 const SpeciesDev<Real>& s, const PushConst<Real>& c,
                                 const TileGeom& t, const uint32_t* tile_off, int color,
                                 uint32_t* list, uint32_t* nlist, uint32_t* err, size_t lds,
                                 hipStream_t st) {
-  if (2 * lds <= kTiledMaxLds && wpe4_without_spill<Real, ND, TWO>())
-    return launch_colour_wpe<Real, ND, TWO, 4>(g, f, s, c, t, tile_off, color, list, nlist, err,
-                                               lds, st);
-  return launch_colour_wpe<Real, ND, TWO, 2>(g, f, s, c, t, tile_off, color, list, nlist, err,
-                                             lds, st);
+  if constexpr (ND == 3) {
+    constexpr int TZ = sizeof(Real) == 4 ? 6 : 8;
+    if (t.T[0] == 8 && t.T[1] == 8 && t.T[2] == TZ)
+      return launch_colour_shape<Real, ND, TWO, 8, 8, TZ>(g, f, s, c, t, tile_off, color, list,
+                                                          nlist, err, lds, st);
+  }
+  return launch_colour_shape<Real, ND, TWO, 0, 0, 0>(g, f, s, c, t, tile_off, color, list, nlist,
+                                                     err, lds, st);
 }
 
 template <typename Real>
