@@ -81,33 +81,46 @@ def copy_calibration(mib):
     return 0 if ok else 1
 
 
-def run_gpu(args, precision):
+def ionised_slab_simulation(cells, ppc, precision, flags, sort_every=4, tile=None,
+                            chunk_particles=3.4e7):
+    """The partially ionised slab in HBM: (sim, workload description (grid,
+    species), ion id, electron id, load seconds).  Particles are generated
+    on the device in x-plane chunks and loaded from device memory."""
     import torch
 
     from paper_2208_08038_amd import inputs as I
     from paper_2208_08038_amd import pic
 
-    n = tuple(args.cells)
-    meta = I.ionised_slab_3d(n=n, ppc=args.ppc, precision=precision, x_cells=(3, 3))
+    n = tuple(cells)
+    meta = I.ionised_slab_3d(n=n, ppc=ppc, precision=precision, x_cells=(3, 3))
     grid = meta.grid
     ion_sp, ele_sp = meta.species[0][0], meta.species[1][0]
-    total = I.ionised_slab_3d_count(n, args.ppc, grid.pad)
-    sim = pic.Simulation(grid, precision=precision, flags=pic.TIMING, sort_every=args.sort_every,
-                         tile=args.tile)
+    total = I.ionised_slab_3d_count(n, ppc, grid.pad)
+    sim = pic.Simulation(grid, precision=precision, flags=flags, sort_every=sort_every, tile=tile)
     sid_i = sim.add_species(ion_sp, total)
     sid_e = sim.add_species(ele_sp, total)
-    planes = max(1, int(args.chunk_particles // (n[1] * n[2] * args.ppc)))
+    planes = max(1, int(chunk_particles // (n[1] * n[2] * ppc)))
     x0, chunk = grid.pad, 0
     t_load = time.perf_counter()
     while x0 < n[0] - grid.pad:
         x1 = min(x0 + planes, n[0] - grid.pad)
-        xi, ui, wci, xe, ue = I.ionised_slab_3d_device_chunk(n, args.ppc, (x0, x1), chunk)
+        xi, ui, wci, xe, ue = I.ionised_slab_3d_device_chunk(n, ppc, (x0, x1), chunk)
         sim.load_particles_device(sid_i, xi, ui, omega_c=wci)
         sim.load_particles_device(sid_e, xe, ue)
         del xi, ui, wci, xe, ue
         x0, chunk = x1, chunk + 1
     torch.cuda.synchronize()
-    t_load = time.perf_counter() - t_load
+    return sim, meta, sid_i, sid_e, time.perf_counter() - t_load
+
+
+def run_gpu(args, precision):
+    import torch
+
+    from paper_2208_08038_amd import pic
+
+    n = tuple(args.cells)
+    sim, _, sid_i, sid_e, t_load = ionised_slab_simulation(
+        n, args.ppc, precision, pic.TIMING, args.sort_every, args.tile, args.chunk_particles)
     n_ion, n_el = sim.count(sid_i), sim.count(sid_e)
     print(f"[bench] fp{precision}: loaded {n_ion} ions + {n_el} electrons in {t_load:.1f} s",
           file=sys.stderr, flush=True)

@@ -199,6 +199,16 @@ int pic_count(pic_ctx* ctx, int32_t species_id, int64_t* n);
 int pic_read_particles(pic_ctx* ctx, int32_t species_id, int32_t* cell, double* offset,
                        double* delta, double* u1, double* u2, int64_t* id);
 
+/* The particles start .. start + count - 1 of a species in the library's
+   present storage order (tile order after a sort; unchanged by a step that
+   does not sort), same layouts as pic_read_particles, plus omega_c and
+   weight (n each; the species value, resp. 1, where the species carries
+   none).  Any pointer may be NULL.  PIC_EINVAL if the range is not inside
+   the species.  Synchronises. */
+int pic_read_particles_range(pic_ctx* ctx, int32_t species_id, int64_t start, int64_t count,
+                             int32_t* cell, double* offset, double* delta, double* u1,
+                             double* u2, double* omega_c, double* weight, int64_t* id);
+
 /* Charge density at the integer nodes of the present state (HOST FP64, prod(n)). */
 int pic_rho(pic_ctx* ctx, double* rho);
 

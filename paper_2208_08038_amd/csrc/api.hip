@@ -619,16 +619,19 @@ int load_fields_t(pic_ctx* c, const double* E, const double* B) {
   return PIC_OK;
 }
 
+// Particles [start, start + cnt) of the species in storage order.
 template <typename Real>
-int read_particles_t(pic_ctx* c, SpeciesHost& s, int32_t* cell, double* off, double* delta,
-                     double* u1, double* u2, int64_t* id) {
+int read_particles_t(pic_ctx* c, SpeciesHost& s, int64_t start, int64_t cnt, int32_t* cell,
+                     double* off, double* delta, double* u1, double* u2, double* wc, double* w,
+                     int64_t* id) {
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  const int64_t n = s.n;
+  const int64_t n = cnt;
   const int nd = c->g.nd;
   if (n == 0) return PIC_OK;
   if (cell) {
     std::vector<uint32_t> pk(n);
-    HIPCHK(c, hipMemcpy(pk.data(), s.cell, n * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(pk.data(), static_cast<uint32_t*>(s.cell) + start, n * sizeof(uint32_t),
+                        hipMemcpyDeviceToHost));
     for (int64_t p = 0; p < n; p++) {
       uint32_t v = pk[p];
       int ci[3] = {0, 0, 0};
@@ -639,27 +642,43 @@ int read_particles_t(pic_ctx* c, SpeciesHost& s, int32_t* cell, double* off, dou
     }
   }
   std::vector<Real> buf(n);
-  auto get = [&](void* src, double* dst, int comp) -> int {
-    HIPCHK(c, hipMemcpy(buf.data(), src, n * sizeof(Real), hipMemcpyDeviceToHost));
-    for (int64_t p = 0; p < n; p++) dst[p * 3 + comp] = (double)buf[p];
+  // component `comp` of an n x `stride` host array from a device array
+  auto get = [&](void* src, double* dst, int comp, int stride) -> int {
+    HIPCHK(c, hipMemcpy(buf.data(), static_cast<Real*>(src) + start, n * sizeof(Real),
+                        hipMemcpyDeviceToHost));
+    for (int64_t p = 0; p < n; p++) dst[p * stride + comp] = (double)buf[p];
     return PIC_OK;
   };
   int rc;
   if (off) {
     for (int64_t p = 0; p < 3 * n; p++) off[p] = 0.0;
     for (int d = 0; d < nd; d++)
-      if ((rc = get(s.off[d], off, d))) return rc;
+      if ((rc = get(s.off[d], off, d, 3))) return rc;
   }
   for (int a = 0; a < 3; a++) {
-    if (u1 && (rc = get(s.u1[a], u1, a))) return rc;
+    if (u1 && (rc = get(s.u1[a], u1, a, 3))) return rc;
     if (s.d.kind == PIC_TWO_BODY) {
-      if (u2 && (rc = get(s.u2[a], u2, a))) return rc;
-      if (delta && (rc = get(s.dl[a], delta, a))) return rc;
+      if (u2 && (rc = get(s.u2[a], u2, a, 3))) return rc;
+      if (delta && (rc = get(s.dl[a], delta, a, 3))) return rc;
+    }
+  }
+  if (wc) {
+    if (s.has_wc) {
+      if ((rc = get(s.wc, wc, 0, 1))) return rc;
+    } else {
+      for (int64_t p = 0; p < n; p++) wc[p] = s.d.omega_c;
+    }
+  }
+  if (w) {
+    if (s.has_w) {
+      if ((rc = get(s.w, w, 0, 1))) return rc;
+    } else {
+      for (int64_t p = 0; p < n; p++) w[p] = 1.0;
     }
   }
   if (id) {
     if (!s.ids) return fail(c, PIC_ESTATE, "ids need PIC_FLAG_TRACK_IDS");
-    HIPCHK(c, hipMemcpy(id, s.ids, n * sizeof(int64_t), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(id, s.ids + start, n * sizeof(int64_t), hipMemcpyDeviceToHost));
   }
   return PIC_OK;
 }
@@ -979,8 +998,25 @@ int pic_read_particles(pic_ctx* c, int32_t sid, int32_t* cell, double* offset, d
   if (!c) return PIC_EINVAL;
   if (sid < 0 || sid >= (int32_t)c->sp.size()) return fail(c, PIC_ESTATE, "unknown species");
   SpeciesHost& s = *c->sp[sid];
-  return c->prec == 32 ? read_particles_t<float>(c, s, cell, offset, delta, u1, u2, id)
-                       : read_particles_t<double>(c, s, cell, offset, delta, u1, u2, id);
+  return c->prec == 32
+             ? read_particles_t<float>(c, s, 0, s.n, cell, offset, delta, u1, u2, nullptr,
+                                       nullptr, id)
+             : read_particles_t<double>(c, s, 0, s.n, cell, offset, delta, u1, u2, nullptr,
+                                        nullptr, id);
+}
+
+int pic_read_particles_range(pic_ctx* c, int32_t sid, int64_t start, int64_t count,
+                             int32_t* cell, double* offset, double* delta, double* u1, double* u2,
+                             double* omega_c, double* weight, int64_t* id) {
+  if (!c) return PIC_EINVAL;
+  if (sid < 0 || sid >= (int32_t)c->sp.size()) return fail(c, PIC_ESTATE, "unknown species");
+  SpeciesHost& s = *c->sp[sid];
+  if (start < 0 || count < 0 || start > s.n || count > s.n - start)
+    return fail(c, PIC_EINVAL, "particle range outside the species");
+  return c->prec == 32 ? read_particles_t<float>(c, s, start, count, cell, offset, delta, u1, u2,
+                                                 omega_c, weight, id)
+                       : read_particles_t<double>(c, s, start, count, cell, offset, delta, u1,
+                                                  u2, omega_c, weight, id);
 }
 
 int pic_rho(pic_ctx* c, double* rho) {

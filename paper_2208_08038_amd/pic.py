@@ -85,6 +85,9 @@ SIGNATURES = [
     ("pic_count", C.c_int, [_P, C.c_int32, C.POINTER(C.c_int64)]),
     ("pic_read_particles", C.c_int, [_P, C.c_int32, C.POINTER(C.c_int32), _D, _D, _D, _D,
                                      C.POINTER(C.c_int64)]),
+    ("pic_read_particles_range", C.c_int, [_P, C.c_int32, C.c_int64, C.c_int64,
+                                           C.POINTER(C.c_int32), _D, _D, _D, _D, _D, _D,
+                                           C.POINTER(C.c_int64)]),
     ("pic_rho", C.c_int, [_P, _D]),
     ("pic_set_probes", C.c_int, [_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
     ("pic_read_probes", C.c_int, [_P, _D, C.POINTER(C.c_int64)]),
@@ -319,6 +322,24 @@ class Simulation:
         nd = self.ndim
         out = {"cell": cell[:, :nd].copy(), "off": off[:, :nd].copy(), "delta": delta,
                "u1": u1, "u2": u2}
+        if ids:
+            out["id"] = idv
+        return out
+
+    def particles_range(self, sid: int, start: int, count: int, ids: bool = False) -> dict:
+        """Particles start .. start+count-1 in storage order (see
+        pic_read_particles_range), with omega_c and weight."""
+        cell = np.zeros((count, 3), dtype=np.int32)
+        off, delta, u1, u2 = (np.zeros((count, 3)) for _ in range(4))
+        wc, w = np.zeros(count), np.zeros(count)
+        idv = np.zeros(count, dtype=np.int64) if ids else None
+        self._check(self.lib.pic_read_particles_range(
+            self.ctx, sid, int(start), int(count), cell.ctypes.data_as(C.POINTER(C.c_int32)),
+            _dp(off), _dp(delta), _dp(u1), _dp(u2), _dp(wc), _dp(w),
+            idv.ctypes.data_as(C.POINTER(C.c_int64)) if ids else None))
+        nd = self.ndim
+        out = {"cell": cell[:, :nd].copy(), "off": off[:, :nd].copy(), "delta": delta,
+               "u1": u1, "u2": u2, "omega_c": wc, "weight": w}
         if ids:
             out["id"] = idv
         return out
