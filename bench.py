@@ -32,7 +32,7 @@ sys.path.insert(0, ROOT)
 METRIC = "particle-steps/sec (push+gather+deposit) and % HBM roofline, FP32 vs FP64, 1 GPU"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "push_tiled_two_body_3d_fp32_traffic.json")
-ION_KERNEL = "k_push_tiled_f32<3, true>"
+ION_KERNEL = "k_push_tiled_f32<3, true, 4, 8, 8, 6>"
 
 
 
