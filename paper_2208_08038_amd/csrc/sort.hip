@@ -1,9 +1,12 @@
-// sort.hip -- stable LSD radix sort of particles by tile id (8-bit digits).
+// sort.hip -- stable LSD radix sort of particles by tile id.
 //
+// Digits of up to 9 bits (a key of b bits takes ceil(b / 9) passes, the
+// digit width spread evenly over them: 17-bit tile ids of a 512x256x256
+// grid in 8x8x6 tiles sort in two passes of 9 bits).
 // Pass structure (per digit): block histograms over chunks of 4096 keys,
 // an exclusive scan of the digit-major histogram table, and a stable
 // block scatter in which each wavefront ranks equal digits with ballots.
-// The resulting permutation gathers every attribute array once.
+// The resulting permutation gathers every attribute array in one kernel.
 #include "sort.h"
 
 namespace pic {
@@ -14,6 +17,8 @@ constexpr int SB = 256;          // threads per block
 constexpr int ROUNDS = 16;       // items per thread
 constexpr int CHUNK = SB * ROUNDS;
 constexpr int SCAN_ITEMS = 1024; // per scan block (4 per thread)
+constexpr int MAXBITS = 9;       // widest digit
+constexpr int MAXBINS = 1 << MAXBITS;
 
 __global__ void k_keys(GridInfo g, int tx, int ty, int tz, int ntx, int nty, const uint32_t* cell,
                        int64_t n, uint32_t* key) {
@@ -27,17 +32,19 @@ __global__ void k_keys(GridInfo g, int tx, int ty, int tz, int ntx, int nty, con
 }
 
 __global__ void __launch_bounds__(SB) k_hist(const uint32_t* key, int64_t n, int shift,
-                                             uint32_t* hist, int nb) {
-  __shared__ uint32_t h[256];
-  h[threadIdx.x] = 0;
+                                             int nbits, uint32_t* hist, int nb) {
+  __shared__ uint32_t h[MAXBINS];
+  const int bins = 1 << nbits;
+  const uint32_t mask = (uint32_t)bins - 1u;
+  for (int d = threadIdx.x; d < bins; d += SB) h[d] = 0;
   __syncthreads();
   int64_t base = (int64_t)blockIdx.x * CHUNK;
   for (int r = 0; r < ROUNDS; r++) {
     int64_t i = base + (int64_t)r * SB + threadIdx.x;
-    if (i < n) atomicAdd(&h[(key[i] >> shift) & 255u], 1u);
+    if (i < n) atomicAdd(&h[(key[i] >> shift) & mask], 1u);
   }
   __syncthreads();
-  hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+  for (int d = threadIdx.x; d < bins; d += SB) hist[(int64_t)d * nb + blockIdx.x] = h[d];
 }
 
 // in-place exclusive scan of 1024-element blocks; block totals -> sums[b]
@@ -83,23 +90,27 @@ void scan_exclusive(uint32_t* a, int64_t L, uint32_t* tmp, hipStream_t st) {
 
 __global__ void __launch_bounds__(SB) k_scatter(const uint32_t* kin, const uint32_t* iin,
                                                 uint32_t* kout, uint32_t* iout,
-                                                const uint32_t* offs, int shift, int64_t n,
-                                                int nb) {
-  __shared__ uint32_t run[256];
-  __shared__ uint32_t wc[SB / 64][256];
+                                                const uint32_t* offs, int shift, int nbits,
+                                                int64_t n, int nb) {
+  __shared__ uint32_t run[MAXBINS];
+  __shared__ uint32_t wc[SB / 64][MAXBINS];
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
-  run[t] = offs[(int64_t)t * nb + blockIdx.x];
+  const int bins = 1 << nbits;
+  const uint32_t mask = (uint32_t)bins - 1u;
+  for (int d = t; d < bins; d += SB) run[d] = offs[(int64_t)d * nb + blockIdx.x];
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   int64_t base = (int64_t)blockIdx.x * CHUNK;
   for (int r = 0; r < ROUNDS; r++) {
-    for (int q = 0; q < SB / 64; q++) wc[q][t] = 0;
+    for (int d = t; d < bins; d += SB)
+      for (int q = 0; q < SB / 64; q++) wc[q][d] = 0;
     __syncthreads();
     int64_t i = base + (int64_t)r * SB + t;
     bool valid = i < n;
     uint32_t key = valid ? kin[i] : 0u;
-    uint32_t dig = (key >> shift) & 255u;
+    uint32_t dig = (key >> shift) & mask;
+    // lanes of this wavefront with the same digit, by ballots over its bits
     uint64_t m = __ballot(valid);
-    for (int b = 0; b < 8; b++) {
+    for (int b = 0; b < nbits; b++) {
       bool bit = (dig >> b) & 1u;
       uint64_t bb = __ballot(valid && bit);
       m &= bit ? bb : ~bb;
@@ -113,9 +124,11 @@ __global__ void __launch_bounds__(SB) k_scatter(const uint32_t* kin, const uint3
       for (int q = 0; q < wave; q++) pos += wc[q][dig];
     }
     __syncthreads();
-    uint32_t tot = 0;
-    for (int q = 0; q < SB / 64; q++) tot += wc[q][t];
-    run[t] += tot;
+    for (int d = t; d < bins; d += SB) {
+      uint32_t tot = 0;
+      for (int q = 0; q < SB / 64; q++) tot += wc[q][d];
+      run[d] += tot;
+    }
     if (valid) {
       kout[pos] = key;
       iout[pos] = iin ? iin[i] : (uint32_t)i;
@@ -132,11 +145,38 @@ __global__ void k_tile_off(const uint32_t* key, int64_t n, int64_t ntiles, uint3
   for (int64_t t = lo + 1; t <= hi; t++) off[t] = (uint32_t)i;
 }
 
-template <typename T>
-__global__ void k_gather(const T* __restrict__ src, T* __restrict__ dst,
-                         const uint32_t* __restrict__ idx, int64_t n) {
+// Every attribute of element i gathered through one read of the
+// permutation: up to kMaxAttr arrays of 4- or 8-byte elements.
+struct GatherSet {
+  const void* src[kMaxAttr];
+  void* dst[kMaxAttr];
+  int wide[kMaxAttr];  // 8-byte elements
+  int n;
+};
+
+__global__ void __launch_bounds__(256) k_gather_all(GatherSet gs,
+                                                    const uint32_t* __restrict__ idx,
+                                                    int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = src[idx[i]];
+  if (i >= n) return;
+  const uint32_t j = idx[i];
+  // all loads first (independent, in flight together), then the stores
+  uint64_t v[kMaxAttr];
+#pragma unroll
+  for (int a = 0; a < kMaxAttr; a++) {
+    if (a < gs.n)
+      v[a] = gs.wide[a] ? static_cast<const uint64_t*>(gs.src[a])[j]
+                        : (uint64_t) static_cast<const uint32_t*>(gs.src[a])[j];
+  }
+#pragma unroll
+  for (int a = 0; a < kMaxAttr; a++) {
+    if (a < gs.n) {
+      if (gs.wide[a])
+        static_cast<uint64_t*>(gs.dst[a])[i] = v[a];
+      else
+        static_cast<uint32_t*>(gs.dst[a])[i] = (uint32_t)v[a];
+    }
+  }
 }
 
 inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -148,7 +188,7 @@ int sort_alloc(const GridInfo&, const int ntiles[3], int64_t cap, const AllocFn&
   sb.cap = cap;
   sb.ntiles = (int64_t)ntiles[0] * ntiles[1] * ntiles[2];
   int64_t nb = (cap + CHUNK - 1) / CHUNK;
-  int64_t hist = 256 * nb;
+  int64_t hist = (int64_t)MAXBINS * nb;
   int64_t tmp = hist / 512 + 4096;
   for (int b = 0; b < 2; b++) {
     sb.key[b] = static_cast<uint32_t*>(alloc(cap * 4));
@@ -183,16 +223,17 @@ int sort_by_tile(const GridInfo& g, const int tile[3], const int ntiles[3], Sort
                      ntiles[1], cell, n, sb.key[0]);
   int bits = 0;
   while ((int64_t(1) << bits) < sb.ntiles) bits++;
-  int passes = (bits + 7) / 8;
+  const int passes = (bits + MAXBITS - 1) / MAXBITS;
+  const int dbits = passes ? (bits + passes - 1) / passes : 0;
   int nb = (int)((n + CHUNK - 1) / CHUNK);
   int cur = 0;
   const uint32_t* idx_in = nullptr;
   for (int p = 0; p < passes; p++) {
-    int shift = 8 * p;
-    hipLaunchKernelGGL(k_hist, dim3(nb), SB, 0, st, sb.key[cur], n, shift, sb.hist, nb);
-    scan_exclusive(sb.hist, (int64_t)256 * nb, sb.scan_tmp, st);
+    int shift = dbits * p;
+    hipLaunchKernelGGL(k_hist, dim3(nb), SB, 0, st, sb.key[cur], n, shift, dbits, sb.hist, nb);
+    scan_exclusive(sb.hist, ((int64_t)1 << dbits) * nb, sb.scan_tmp, st);
     hipLaunchKernelGGL(k_scatter, dim3(nb), SB, 0, st, sb.key[cur], idx_in, sb.key[1 - cur],
-                       sb.idx[1 - cur], sb.hist, shift, n, nb);
+                       sb.idx[1 - cur], sb.hist, shift, dbits, n, nb);
     idx_in = sb.idx[1 - cur];
     cur = 1 - cur;
   }
@@ -200,16 +241,17 @@ int sort_by_tile(const GridInfo& g, const int tile[3], const int ntiles[3], Sort
                      sb.tile_off);
   if (passes == 0) return 0;  // a single tile: order unchanged
   const uint32_t* perm = sb.idx[cur];
+  GatherSet gs{};
+  gs.n = sb.nattr;
+  for (int a = 0; a < sb.nattr; a++) {
+    gs.src[a] = *sb.attr[a];
+    gs.dst[a] = sb.alt[a];
+    gs.wide[a] = sb.elem[a] == 8;
+  }
+  hipLaunchKernelGGL(k_gather_all, nblk(n, 256), 256, 0, st, gs, perm, n);
   for (int a = 0; a < sb.nattr; a++) {
     void* src = *sb.attr[a];
-    void* dst = sb.alt[a];
-    if (sb.elem[a] == 4)
-      hipLaunchKernelGGL(k_gather<uint32_t>, nblk(n, 256), 256, 0, st,
-                         static_cast<const uint32_t*>(src), static_cast<uint32_t*>(dst), perm, n);
-    else
-      hipLaunchKernelGGL(k_gather<uint64_t>, nblk(n, 256), 256, 0, st,
-                         static_cast<const uint64_t*>(src), static_cast<uint64_t*>(dst), perm, n);
-    *sb.attr[a] = dst;
+    *sb.attr[a] = sb.alt[a];
     sb.alt[a] = src;
   }
   return hipGetLastError() == hipSuccess ? 0 : -1;

@@ -186,20 +186,25 @@ def test_fp32_against_fp64_oracle(pic):
     assert rel_l2(Bg, Bo) < 2e-5
 
 
-def test_stable_tile_sort_permutation(pic):
+@pytest.mark.parametrize("shape,tile,n", [((24, 16, 16), (4, 4, 4), 3000),
+                                          ((160, 160, 80), (5, 5, 5), 60000),
+                                          ((320, 320, 160), (5, 5, 5), 200000)])
+def test_stable_tile_sort_permutation(pic, shape, tile, n):
     """The device sort orders particles by tile, stably: the new order is
-    the stable argsort of the tile keys of the previous order."""
-    _say("case: tile sort permutation")
-    wl = random_workload(3, 3000, 0, seed=61, shape=(24, 16, 16), vmax_ion=0.9)
+    the stable argsort of the tile keys of the previous order (one radix
+    pass for 96 tiles, two 7-bit passes for 16384, two 9-bit passes for
+    131072)."""
+    _say(f"case: tile sort permutation {shape} tile {tile}")
+    wl = random_workload(3, n, 0, seed=61, shape=shape, vmax_ion=0.9)
     s = pic.Simulation.from_workload(wl, precision=64, flags=pic.TRACK_IDS, sort_every=1,
-                                     tile=(4, 4, 4))
+                                     tile=tile)
     s.step(1)                       # no sort on the first step after a load
     before = s.particles(0, ids=True)
     s.step(1)                       # sorts by the cells of `before`, then pushes
     after = s.particles(0, ids=True)
     c = before["cell"]
-    nt = (24 // 4, 16 // 4, 16 // 4)
-    key = c[:, 0] // 4 + nt[0] * (c[:, 1] // 4 + nt[1] * (c[:, 2] // 4))
+    nt = tuple(-(-shape[d] // tile[d]) for d in range(3))
+    key = c[:, 0] // tile[0] + nt[0] * (c[:, 1] // tile[1] + nt[1] * (c[:, 2] // tile[2]))
     expect = before["id"][np.argsort(key, kind="stable")]
     assert np.array_equal(after["id"], expect)
 
