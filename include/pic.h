@@ -70,7 +70,14 @@ typedef enum {
 #define PIC_POINT 0
 #define PIC_TWO_BODY 1
 
-/* device error word bits (pic_diag.error_word) */
+/* Device error word bits (pic_diag.error_word).  A macro-particle whose
+   state is non-finite (NAN) or outside the representable range (RANGE: an
+   offset outside [0, 1], or a two-body ion with |delta_d| >= dx_d / 2) at
+   the start of its cycle is left unchanged -- not advanced, no current --
+   and the bit is set.  One that leaves the range during its cycle (|delta_d|
+   reaching dx_d / 2, a jump of more than one node, a step out of the grid
+   along a non-periodic axis) is advanced and flagged; it stops at its next
+   cycle.  The bits stay set until the context is destroyed. */
 #define PIC_ERR_NAN 1u
 #define PIC_ERR_RANGE 2u
 
@@ -102,7 +109,7 @@ typedef struct {
   int32_t bc_lo[3], bc_hi[3];
   int32_t tile[3];     /* tile shape in cells (0: library default: 8x8x6 in 3D FP32,
                           8x8x8 in 3D FP64, 16x16 in 2D, 256 in 1D) */
-  int32_t sort_every;  /* re-sort particles by tile every this many steps (0: default) */
+  int32_t sort_every;  /* re-sort particles by tile every this many steps (0: default 8) */
   uint32_t flags;
   int32_t reserved;
   double re_norm;      /* normalised classical electron radius 2 pi r_e / lambda */

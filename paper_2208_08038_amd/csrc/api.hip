@@ -804,7 +804,7 @@ int pic_create(const pic_config* cfg, const pic_allocator* alloc, void* hip_stre
     c->tile[d] = std::max(t, 1);
     c->ntiles[d] = (g.n[d] + c->tile[d] - 1) / c->tile[d];
   }
-  c->sort_every = cfg->sort_every > 0 ? cfg->sort_every : 4;
+  c->sort_every = cfg->sort_every > 0 ? cfg->sort_every : 8;
   c->tg = pic::make_tile_geom(g, c->tile, c->ntiles, c->rsize);
   c->tiled = !(cfg->flags & PIC_FLAG_GLOBAL_KERNEL) && pic::tiled_supported(g, c->tg, c->rsize);
 
