@@ -26,6 +26,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -113,7 +115,7 @@ def ionised_slab_simulation(cells, ppc, precision, flags, sort_every=8, tile=Non
     return sim, meta, sid_i, sid_e, time.perf_counter() - t_load
 
 
-def run_gpu(args, precision):
+def run_gpu(args, precision, keep_fields=False):
     import torch
 
     from paper_2208_08038_amd import pic
@@ -159,7 +161,10 @@ def run_gpu(args, precision):
         "bytes_per_electron": pp_e, "bytes_per_cell": pc, "load_seconds": t_load,
         "outside_tile_last_step": diag["n_outside_tile"],
         "error_word": diag["error_word"], "field_energy": diag["field_energy"],
+        "kinetic_energy": diag["kinetic_energy"],
     }
+    if keep_fields:  # final E, B, J for the FP32-against-FP64 comparison
+        res["fields"] = sim.fields()
     sim.close()
     del sim
     torch.cuda.empty_cache()
@@ -193,8 +198,8 @@ def main():
     ap.add_argument("--cells", type=int, nargs=3, default=[512, 256, 256])
     ap.add_argument("--ppc", type=int, default=8)
     ap.add_argument("--sort-every", type=int, default=8,
-                    help="steps between tile sorts (particles that leave their tile in
-                    between are advanced by the outside-tile kernel)")
+                    help="steps between tile sorts (particles that leave their tile in "
+                         "between are advanced by the outside-tile kernel)")
     ap.add_argument("--tile", type=int, nargs=3, default=None,
                     help="cells per tile of the LDS-tiled particle kernel "
                          "(default: the library's, 8x8x6 for FP32 and 8x8x8 for FP64)")
@@ -217,8 +222,21 @@ def main():
     if args.copy_calibration:
         sys.exit(copy_calibration(args.copy_calibration))
 
-    r32 = run_gpu(args, 32)
-    r64 = None if args.no_fp64 else run_gpu(args, 64)
+    r32 = run_gpu(args, 32, keep_fields=not args.no_fp64)
+    r64 = None if args.no_fp64 else run_gpu(args, 64, keep_fields=True)
+    fp32_err = None
+    if r64 is not None:
+        # same seeded inputs and steps in both precisions: FP32 error against
+        # the FP64 run (relative L2 over the grid)
+        def rel(a, b):
+            return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+        f32, f64 = r32.pop("fields"), r64.pop("fields")
+        fp32_err = {"E_rel_l2": rel(f32[0], f64[0]), "B_rel_l2": rel(f32[1], f64[1]),
+                    "J_rel_l2": rel(f32[2], f64[2]),
+                    "field_energy_rel": abs(r32["field_energy"] / r64["field_energy"] - 1.0),
+                    "kinetic_energy_rel": abs(r32["kinetic_energy"] / r64["kinetic_energy"] - 1.0),
+                    "after_steps": args.warmup + args.steps}
+        del f32, f64
     key = f"ionised_slab_3d {args.cells} ppc={args.ppc} fp32"
     traffic = measured_traffic(key)
     achieved = r32["ion_kernel_gbs"]
@@ -254,6 +272,7 @@ def main():
             "ion_push_ms": r64["ion_push_ms"], "electron_push_ms": r64["electron_push_ms"],
             "ion_kernel_gbs": r64["ion_kernel_gbs"],
             "frac": r64["ion_kernel_gbs"] / HBM_PEAK_GBS if r64["ion_kernel_gbs"] else None},
+        "fp32_vs_fp64": fp32_err,
         "error_word": r32["error_word"],
     }
     print(json.dumps(out), flush=True)

@@ -371,22 +371,29 @@ __device__ __forceinline__ void shape3(Real x, int n, Real w[3]) {
   w[2] = Real(0.5) * b * b;
 }
 
-// Old and new shapes of a body on the 3-node window [n-1, n+1].
+// Old shape and shape change of a body on the 3-node window [n-1, n+1],
+// from its old position x0 and its displacement dx.  The change of each
+// quadratic B-spline weight factors through the displacement D (with
+// d0 = x0 - n and s = d0 + d1 = 2 d0 + D):
+//   S(n-1): -D (1 - s)/2,   S(n): -D s,   S(n+1): D (1 + s)/2,
+// so a displacement much smaller than a cell keeps its relative precision
+// (the difference of two nearly equal weights would lose it in FP32).
 template <typename Real, int ND>
 struct Win3 {
   Real S0[ND][3], DS[ND][3];
 };
 
 template <typename Real, int ND>
-__device__ __forceinline__ void win3(const Real x0[3], const Real x1[3], const int nn[3],
+__device__ __forceinline__ void win3(const Real x0[3], const Real dx[3], const int nn[3],
                                      Win3<Real, ND>& w) {
 #pragma unroll
   for (int d = 0; d < ND; d++) {
-    Real s1[3];
     shape3(x0[d], nn[d], w.S0[d]);
-    shape3(x1[d], nn[d], s1);
-#pragma unroll
-    for (int k = 0; k < 3; k++) w.DS[d][k] = s1[k] - w.S0[d][k];
+    const Real D = dx[d];
+    const Real sum = Real(2) * (x0[d] - Real(nn[d])) + D;
+    w.DS[d][0] = Real(-0.5) * D * (Real(1) - sum);
+    w.DS[d][1] = -D * sum;
+    w.DS[d][2] = Real(0.5) * D * (Real(1) + sum);
   }
 }
 
@@ -394,18 +401,19 @@ __device__ __forceinline__ void win3(const Real x0[3], const Real x1[3], const i
 // (old and new positions of every body share the node n per dimension):
 // the window is three nodes wide and the running sum along the motion has
 // two non-zero terms (the third is the sum of the shape change, zero).
-// With PAIR the two bodies of an ion share the window and their terms are
+// Bodies are given by old position and displacement (see win3).  With
+// PAIR the two bodies of an ion share the window and their terms are
 // added in registers before one add per node.
 template <typename Real, int ND, bool GLOBAL, typename JT, bool PAIR>
 __device__ __forceinline__ void deposit3(JT* const J[3], int base, int sy, int sz,
-                                         const int nn[3], const Real xa0[3], const Real xa1[3],
+                                         const int nn[3], const Real xa0[3], const Real da[3],
                                          Real Qa, const Real va[3], const Real xb0[3],
-                                         const Real xb1[3], Real Qb, const Real vb[3],
+                                         const Real db[3], Real Qb, const Real vb[3],
                                          const PushConst<Real>& c) {
   const Real third = Real(1) / Real(3);
   Win3<Real, ND> a, b;
-  win3<Real, ND>(xa0, xa1, nn, a);
-  if constexpr (PAIR) win3<Real, ND>(xb0, xb1, nn, b);
+  win3<Real, ND>(xa0, da, nn, a);
+  if constexpr (PAIR) win3<Real, ND>(xb0, db, nn, b);
   int o = base + nn[0] - 1;
   if constexpr (ND > 1) o += (nn[1] - 1) * sy;
   if constexpr (ND > 2) o += (nn[2] - 1) * sz;
@@ -846,8 +854,19 @@ __device__ __forceinline__ void advance_particle(const GridInfo& g, const Specie
       int nn[3];
       const bool pair = common_node<Real, ND>(xs, 4, nn);
       if (pair) {
-        // both bodies keep one nearest node: merged three-node deposit
-        deposit3<Real, ND, GLOBAL, JT, true>(J, jbase, jsy, jsz, nn, x1, y1, qw1, v1, x2, y2,
+        // both bodies keep one nearest node: merged three-node deposit.
+        // Displacements from the stored quantities (centre-of-mass offset,
+        // delta), whose differences over a step are exact in the working
+        // precision, not from the rounded body positions.
+        Real d1[3] = {0, 0, 0}, d2[3] = {0, 0, 0};
+#pragma unroll
+        for (int d = 0; d < ND; d++) {
+          const Real dR = offn[d] - off[d];
+          const Real dd = (dl[d] - st.dl[d]) * c.idx[d];
+          d1[d] = dR + c.f1 * dd;
+          d2[d] = dR - c.f2 * dd;
+        }
+        deposit3<Real, ND, GLOBAL, JT, true>(J, jbase, jsy, jsz, nn, x1, d1, qw1, v1, x2, d2,
                                              qw2, v2, c);
       } else {
 #pragma unroll 1
@@ -916,9 +935,13 @@ __device__ __forceinline__ void advance_particle(const GridInfo& g, const Specie
       int nn[3];
       const bool keep = common_node<Real, ND>(xs, 2, nn);
       // per lane: most particles keep their nearest node
-      if (keep)
-        deposit3<Real, ND, GLOBAL, JT, false>(J, jbase, jsy, jsz, nn, x1, y1, qw1, v1, x1, y1,
+      if (keep) {
+        Real d1[3] = {0, 0, 0};
+#pragma unroll
+        for (int d = 0; d < ND; d++) d1[d] = y1[d] - x1[d];
+        deposit3<Real, ND, GLOBAL, JT, false>(J, jbase, jsy, jsz, nn, x1, d1, qw1, v1, x1, d1,
                                               Real(0), v1, c);
+      }
       else if (!later(jbase, x1, y1, qw1, v1))
         range_ok = deposit<Real, ND, GLOBAL, JT>(J, jbase, jsy, jsz, x1, y1, qw1, v1, c);
     }

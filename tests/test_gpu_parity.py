@@ -209,6 +209,39 @@ def test_stable_tile_sort_permutation(pic, shape, tile, n):
     assert np.array_equal(after["id"], expect)
 
 
+def test_bragg_case_fp64_fp32(pic):
+    """Reduced Bragg case (Sec. 3.2 geometry, 512^2 cells, 700 steps): GPU
+    fields match the oracle (FP64 1e-12, FP32 2e-5 relative L2); the FP32
+    scattered field (run with ions minus run without) against the oracle's
+    is reported and keeps the Bragg direction 2 theta_B."""
+    import math
+    from _bragg import bragg_case, scattered_direction
+    _say("case: bragg 2d reduced")
+    wl = bragg_case(1.5)
+    ovac = Oracle(wl.grid)
+    ovac.step(wl.steps)
+    omed = Oracle.from_workload(wl)
+    omed.step(wl.steps)
+    Eo = omed.fields()[0]
+    es_ref = Eo[2] - ovac.fields()[0][2]
+    for prec, tol in ((64, 1e-12), (32, 2e-5)):
+        vac = pic.Simulation(wl.grid, precision=prec)
+        vac.step(wl.steps)
+        med = pic.Simulation.from_workload(wl, precision=prec)
+        med.step(wl.steps)
+        Eg = med.fields()[0]
+        assert rel_l2(Eg, Eo) < tol
+        es = Eg[2] - vac.fields()[0][2]
+        err = rel_l2(es, es_ref)
+        angle, kmean, contrast = scattered_direction(wl, es)
+        _say(f"bragg fp{prec}: field rel L2 {rel_l2(Eg, Eo):.2e}, scattered field rel L2 "
+             f"{err:.2e}, direction {angle:.2f} deg")
+        assert err < (1e-10 if prec == 64 else 2e-4)
+        expect = 2 * math.degrees(math.asin(1.0 / 3.0))
+        assert abs(angle - expect) < math.degrees(1.0 / 16.0)
+        assert med.diagnostics()["error_word"] == 0
+
+
 def test_neutral_medium_case_fp64(pic):
     """The full 1D neutral-medium case (2048 cells, 16k two-body ions,
     1000 steps): fields and probes match the oracle."""

@@ -12,6 +12,7 @@ import os
 import numpy as np
 import pytest
 
+from _bragg import bragg_case, scattered_direction
 from paper_2208_08038_amd.inputs import (
     LASER, OPEN, PERIODIC, POINT, TWO_BODY, Grid, Laser, Particles, Species, neutral_medium_1d)
 from oracle import Oracle, ac_from_omega, split_momentum
@@ -538,6 +539,35 @@ def test_lorentz_dispersion_neutral_medium(oracle_built):
     assert n_meas - 1.0 > 0.04
     d = o.diagnostics()
     assert d["error_word"] == 0
+
+
+# ------------------------------------------ coupled: Bragg scattering (T7)
+
+def _bragg_scattered_direction(d_over_lambda):
+    """Scattered field of the reduced Bragg case on the oracle: the run with
+    ions minus the run without (the response is linear at a0 = 1e-4)."""
+    wl = bragg_case(d_over_lambda)
+    vac = Oracle(wl.grid)
+    vac.step(wl.steps)
+    med = Oracle.from_workload(wl)
+    med.step(wl.steps)
+    assert med.diagnostics()["error_word"] == 0
+    return scattered_direction(wl, med.fields()[0][2] - vac.fields()[0][2])
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("d_over_lambda", [1.5, 2.0])
+def test_bragg_scattered_peak_angle(oracle_built, d_over_lambda):
+    """Bragg law 2 d sin(theta) = lambda (Sec. 3.2): with the lattice planes
+    at theta_B to the beam, the scattered wave leaves at 2 theta_B from the
+    beam, elastically (|k| = omega), and not on the mirror side.  Two
+    lattice constants, so the angle follows d.  Tolerance: one angular bin
+    of the spectrum, lambda / L = 1/16 rad."""
+    angle, kmean, contrast = _bragg_scattered_direction(d_over_lambda)
+    expect = 2 * math.degrees(math.asin(1.0 / (2.0 * d_over_lambda)))
+    assert abs(angle - expect) < math.degrees(1.0 / 16.0), (angle, expect)
+    assert abs(kmean - 1.0) < 0.03
+    assert contrast > 3.0
 
 
 # ------------------------------------------ paper-printed numbers (T10)
