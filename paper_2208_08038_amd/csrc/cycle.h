@@ -593,14 +593,22 @@ __device__ __forceinline__ bool common_node(const Real* const* xs, int nx, int n
   return same;
 }
 
+// Reciprocal and reciprocal square root of arguments >= 1 (Lorentz factors,
+// softening and rotation denominators).  FP32 uses the hardware
+// approximations (within 1 ulp) instead of the correctly rounded
+// division and square-root sequences; FP64 keeps the correctly rounded ones.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rsqrt1(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt1(double x) { return 1.0 / sqrt(x); }
+
 template <typename Real>
 __device__ __forceinline__ void boris_rotate_kick(const Real um[3], Real a, const Real E[3],
                                                   const Real B[3], Real out[3]) {
-  Real gm = sqrt(Real(1) + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
-  Real k = a / gm;
+  Real k = a * rsqrt1(Real(1) + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
   Real t0 = k * B[0], t1 = k * B[1], t2 = k * B[2];
   Real tt = t0 * t0 + t1 * t1 + t2 * t2;
-  Real sk = Real(2) / (Real(1) + tt);
+  Real sk = Real(2) * recip(Real(1) + tt);
   Real s0 = sk * t0, s1 = sk * t1, s2 = sk * t2;
   Real w0 = um[0] + (um[1] * t2 - um[2] * t1);
   Real w1 = um[1] + (um[2] * t0 - um[0] * t2);
@@ -768,7 +776,7 @@ __device__ __forceinline__ void advance_particle(const GridInfo& g, const Specie
     Real r2 = dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2];
     Real soft = Real(1);
     if (c.inv_ac2 != Real(0)) {
-      Real rq = Real(1) / sqrt(Real(1) + r2 * c.inv_ac2);
+      Real rq = rsqrt1(Real(1) + r2 * c.inv_ac2);
       soft = rq * rq * rq;
     }
     const Real kf = -c.mr * wc * wc * soft;
@@ -807,7 +815,7 @@ __device__ __forceinline__ void advance_particle(const GridInfo& g, const Specie
     const Real nu = c.nu + c.nu_per_omega * wc;
     if (nu > Real(0)) {
       // time-centred friction on the relative momentum; m1 u1 + m2 u2 kept
-      Real D = (Real(1) - nu * c.half_dt) / (Real(1) + nu * c.half_dt);
+      Real D = (Real(1) - nu * c.half_dt) * recip(Real(1) + nu * c.half_dt);
 #pragma unroll
       for (int q = 0; q < 3; q++) {
         Real V = (c.m1 * um1[q] + c.m2 * um2[q]) * c.inv_mc;
@@ -819,8 +827,8 @@ __device__ __forceinline__ void advance_particle(const GridInfo& g, const Specie
     Real n1[3], n2[3];
     boris_rotate_kick(um1, c.a1, E1, B1, n1);
     boris_rotate_kick(um2, c.a2, E2, B2, n2);
-    Real ig1 = Real(1) / sqrt(Real(1) + n1[0] * n1[0] + n1[1] * n1[1] + n1[2] * n1[2]);
-    Real ig2 = Real(1) / sqrt(Real(1) + n2[0] * n2[0] + n2[1] * n2[1] + n2[2] * n2[2]);
+    Real ig1 = rsqrt1(Real(1) + n1[0] * n1[0] + n1[1] * n1[1] + n1[2] * n1[2]);
+    Real ig2 = rsqrt1(Real(1) + n2[0] * n2[0] + n2[1] * n2[1] + n2[2] * n2[2]);
     Real v1[3], v2[3];
 #pragma unroll
     for (int q = 0; q < 3; q++) {
@@ -919,7 +927,7 @@ __device__ __forceinline__ void advance_particle(const GridInfo& g, const Specie
 #pragma unroll
     for (int q = 0; q < 3; q++) um[q] = u1[q] + c.a1 * E1[q];
     boris_rotate_kick(um, c.a1, E1, B1, n1);
-    Real ig = Real(1) / sqrt(Real(1) + n1[0] * n1[0] + n1[1] * n1[1] + n1[2] * n1[2]);
+    Real ig = rsqrt1(Real(1) + n1[0] * n1[0] + n1[1] * n1[1] + n1[2] * n1[2]);
 #pragma unroll
     for (int q = 0; q < 3; q++) v1[q] = n1[q] * ig;
     Real y1[3] = {0, 0, 0};
