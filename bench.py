@@ -83,7 +83,7 @@ def copy_calibration(mib):
     return 0 if ok else 1
 
 
-def ionised_slab_simulation(cells, ppc, precision, flags, sort_every=8, tile=None,
+def ionised_slab_simulation(cells, ppc, precision, flags, sort_every=0, tile=None,
                             chunk_particles=3.4e7):
     """The partially ionised slab in HBM: (sim, workload description (grid,
     species), ion id, electron id, load seconds).  Particles are generated
@@ -197,9 +197,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cells", type=int, nargs=3, default=[512, 256, 256])
     ap.add_argument("--ppc", type=int, default=8)
-    ap.add_argument("--sort-every", type=int, default=8,
-                    help="steps between tile sorts (particles that leave their tile in "
-                         "between are advanced by the outside-tile kernel)")
+    ap.add_argument("--sort-every", type=int, default=0,
+                    help="steps between tile sorts (0: the library's adaptive policy; "
+                         "particles that leave their tile in between are advanced by the "
+                         "outside-tile kernel)")
     ap.add_argument("--tile", type=int, nargs=3, default=None,
                     help="cells per tile of the LDS-tiled particle kernel "
                          "(default: the library's, 8x8x6 for FP32 and 8x8x8 for FP64)")
@@ -256,7 +257,8 @@ def main():
         "data": "synthetic (seeded, generated in HBM)",
         "config": {"workload": "ionised_slab_3d", "cells": list(args.cells),
                    "two_body_ions": r32["n_ion"], "free_electrons": r32["n_el"],
-                   "ppc": args.ppc, "sort_every": args.sort_every,
+                   "ppc": args.ppc,
+                   "sort_every": args.sort_every if args.sort_every > 0 else "adaptive",
                    "tile": list(args.tile) if args.tile else [8, 8, 6],
                    "precision": "fp32",
                    "parallelism": "1 GPU"},

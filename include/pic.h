@@ -109,7 +109,9 @@ typedef struct {
   int32_t bc_lo[3], bc_hi[3];
   int32_t tile[3];     /* tile shape in cells (0: library default: 8x8x6 in 3D FP32,
                           8x8x8 in 3D FP64, 16x16 in 2D, 256 in 1D) */
-  int32_t sort_every;  /* re-sort particles by tile every this many steps (0: default 8) */
+  int32_t sort_every;  /* > 0: re-sort particles by tile every this many steps; 0: per
+                          species, once the particles advanced outside their tile since
+                          its last sort reach 1/200 of the species, or after 64 steps */
   uint32_t flags;
   int32_t reserved;
   double re_norm;      /* normalised classical electron radius 2 pi r_e / lambda */

@@ -41,7 +41,14 @@ struct SpeciesHost {
   int64_t* ids = nullptr;  // device load indices (TRACK_IDS)
   uint32_t* outside = nullptr;  // particles listed as outside their tile (tiled kernel)
   bool needs_sort = true;  // tile offsets stale (after a load)
+  // adaptive sort policy: particles advanced outside their tile since the
+  // species' last sort, and steps since then
+  double listed_since_sort = 0.0;
+  int64_t steps_since_sort = 0;
 };
+
+// Species slots of the per-step outside-tile counters (device nslow[2 + s]).
+constexpr int kMaxSpecies = 62;
 
 }  // namespace
 
@@ -58,7 +65,10 @@ struct pic_ctx {
   void* mur_e[3][2] = {};
   uint32_t* err = nullptr;
   uint32_t* load_err = nullptr;
-  uint32_t* nslow = nullptr;   // [0]: list length scratch, [1]: listed this step
+  uint32_t* nslow = nullptr;   // [0]: list length scratch, [2 + s]: species s listed this step
+  uint32_t* host_counts = nullptr;  // pinned: 2 slots of the per-species counts
+  hipEvent_t ev_counts[2] = {nullptr, nullptr};
+  int counts_pending = -1;          // slot whose copy is in flight, or -1
   bool tiled = false;
   pic::TileGeom tg{};
   double* partials = nullptr;
@@ -76,7 +86,7 @@ struct pic_ctx {
   int64_t steps_since_sort = 0;
   int tile[3] = {1, 1, 1};
   int ntiles[3] = {1, 1, 1};
-  int sort_every = 4;
+  int sort_every = 0;  // > 0: fixed cadence; 0: adaptive per species
   std::string error;
   bool residual_valid = false;
   // timing
@@ -114,6 +124,16 @@ void* dev_alloc(pic_ctx* c, size_t bytes) {
   }
   if (p) c->allocs.push_back(p);
   return p;
+}
+
+// pinned host buffer and events of the sort policy
+void release_host(pic_ctx* c) {
+  if (c->host_counts) (void)hipHostFree(c->host_counts);
+  c->host_counts = nullptr;
+  for (int t = 0; t < 2; t++) {
+    if (c->ev_counts[t]) (void)hipEventDestroy(c->ev_counts[t]);
+    c->ev_counts[t] = nullptr;
+  }
 }
 
 void dev_free_all(pic_ctx* c) {
@@ -426,6 +446,17 @@ struct TimedDispatch {
   }
 };
 
+// Add the outside-tile counts of the last enqueued step (waits for that
+// step's particle kernels; the field update of the step may still run).
+void harvest_counts(pic_ctx* c) {
+  if (c->counts_pending < 0) return;
+  const int slot = c->counts_pending;
+  c->counts_pending = -1;
+  if (hipEventSynchronize(c->ev_counts[slot]) != hipSuccess) return;
+  for (size_t si = 0; si < c->sp.size(); si++)
+    c->sp[si]->listed_since_sort += (double)c->host_counts[64 * slot + si];
+}
+
 template <typename Real>
 void deposit_rho(pic_ctx* c, double* rho) {
   pic::launch_zero<double>(rho, c->g.plane, c->stream);
@@ -454,19 +485,34 @@ int step_t(pic_ctx* c, int nsteps) {
   las.on = (c->cfg.bc_lo[0] == PIC_BC_LASER && c->cfg.laser.a0 != 0.0) ? 1 : 0;
   for (int it = 0; it < nsteps; it++) {
     const bool check = (c->cfg.flags & PIC_FLAG_CHARGE_CHECK) && it == nsteps - 1;
-    // tile sort on its cadence, and always after a load
+    // tile sort: always after a load; then on a fixed cadence, or per
+    // species when the particles it advanced outside their tile since its
+    // last sort reach kSortRatio of the species (the outside-tile kernel
+    // costs about 1 / kSortRatio as much per particle as a sort does; the
+    // rule spends on sorting what the detour cost, so stays within twice
+    // the best cadence), or after kSortMaxSteps steps (keeps the order of
+    // particles within tiles close to the interleaved load order)
+    constexpr double kSortRatio = 1.0 / 200.0;
+    constexpr int64_t kSortMaxSteps = 64;
+    if (c->sort_every == 0) harvest_counts(c);
     const bool cadence = c->sort_every > 0 && c->steps_since_sort >= c->sort_every;
     for (auto& s : c->sp) {
-      if (!(cadence || s->needs_sort)) continue;
+      bool due = cadence || s->needs_sort;
+      if (c->sort_every == 0)
+        due = due || s->listed_since_sort >= kSortRatio * (double)s->n ||
+              s->steps_since_sort >= kSortMaxSteps;
+      if (!due) continue;
       int rc = pic::sort_by_tile(g, c->tile, c->ntiles, s->sort, s->n, c->stream);
       if (rc) return fail(c, PIC_EHIP, "tile sort launch failed");
       s->needs_sort = false;
+      s->listed_since_sort = 0.0;
+      s->steps_since_sort = 0;
     }
     if (cadence) c->steps_since_sort = 0;
     pic::launch_fill_periodic<Real>(g, eb, 6, c->stream);
     pic::launch_zero<Real>(f.J[0], 3 * g.plane, c->stream);
     if (check) deposit_rho<Real>(c, c->rho0);
-    if (c->tiled) HIPCHK(c, hipMemsetAsync(c->nslow + 1, 0, sizeof(uint32_t), c->stream));
+    if (c->tiled) HIPCHK(c, hipMemsetAsync(c->nslow + 1, 0, 63 * sizeof(uint32_t), c->stream));
     for (size_t si = 0; si < c->sp.size(); si++) {
       auto& s = c->sp[si];
       TimedDispatch td{c, (int)si, false};
@@ -476,7 +522,7 @@ int step_t(pic_ctx* c, int nsteps) {
         hipError_t e = pic::launch_push_tiled<Real>(g, f, species_dev<Real>(*s),
                                                     push_const<Real>(c, *s), c->tg,
                                                     s->sort.tile_off, s->outside, c->nslow,
-                                                    c->nslow + 1, c->err, c->stream, hook);
+                                                    c->nslow + 2 + si, c->err, c->stream, hook);
         if (e != hipSuccess)
           return fail(c, PIC_EHIP, std::string("tiled particle kernel: ") + hipGetErrorString(e));
       } else {
@@ -486,6 +532,17 @@ int step_t(pic_ctx* c, int nsteps) {
         TimedDispatch::hook(&td, false);
       }
       c->launches++;
+      s->steps_since_sort++;
+    }
+    // the step's outside-tile counts go to pinned host memory, read before
+    // the next step is enqueued
+    if (c->tiled && c->sort_every == 0 && !c->sp.empty()) {
+      const int slot = (int)(c->step & 1);
+      HIPCHK(c, hipMemcpyAsync(c->host_counts + 64 * slot, c->nslow + 2,
+                               c->sp.size() * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                               c->stream));
+      HIPCHK(c, hipEventRecord(c->ev_counts[slot], c->stream));
+      c->counts_pending = slot;
     }
     pic::launch_fold_periodic<Real>(g, jj, 3, c->stream);
     if (check) {
@@ -559,10 +616,13 @@ int diagnostics_t(pic_ctx* c, pic_diag* out) {
     ke += k4[0];
     for (int a = 0; a < 3; a++) pm[a] += k4[1 + a];
   }
-  uint32_t ew = 0, ns = 0;
+  uint32_t ew = 0, nsl[kMaxSpecies] = {};
   HIPCHK(c, hipMemcpyAsync(&ew, c->err, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipMemcpyAsync(&ns, c->nslow + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(nsl, c->nslow + 2, kMaxSpecies * sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  int64_t ns = 0;
+  for (size_t si = 0; si < c->sp.size(); si++) ns += nsl[si];
   out->step = c->step;
   out->time = (double)c->step * c->cfg.dt;
   out->kinetic_energy = ke;
@@ -804,7 +864,7 @@ int pic_create(const pic_config* cfg, const pic_allocator* alloc, void* hip_stre
     c->tile[d] = std::max(t, 1);
     c->ntiles[d] = (g.n[d] + c->tile[d] - 1) / c->tile[d];
   }
-  c->sort_every = cfg->sort_every > 0 ? cfg->sort_every : 8;
+  c->sort_every = cfg->sort_every > 0 ? cfg->sort_every : 0;
   c->tg = pic::make_tile_geom(g, c->tile, c->ntiles, c->rsize);
   c->tiled = !(cfg->flags & PIC_FLAG_GLOBAL_KERNEL) && pic::tiled_supported(g, c->tg, c->rsize);
 
@@ -849,9 +909,12 @@ int pic_create(const pic_config* cfg, const pic_allocator* alloc, void* hip_stre
       if (e == hipSuccess) e = hipMemsetAsync(c->mur_e[d][t], 0, np * rs, c->stream);
     }
   }
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->host_counts, 2 * 64 * sizeof(uint32_t));
+  for (int t = 0; t < 2 && e == hipSuccess; t++) e = hipEventCreate(&c->ev_counts[t]);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     std::string msg = std::string("HIP: ") + hipGetErrorString(e);
+    release_host(c);
     dev_free_all(c);
     delete c;
     return fail(nullptr, PIC_EHIP, msg);
@@ -863,6 +926,7 @@ int pic_create(const pic_config* cfg, const pic_allocator* alloc, void* hip_stre
 int pic_add_species(pic_ctx* c, const pic_species_desc* d, int32_t* sid) {
   if (!c || !d || !sid) return fail(c, PIC_EINVAL, "null argument");
   if (d->kind != PIC_POINT && d->kind != PIC_TWO_BODY) return fail(c, PIC_EINVAL, "bad kind");
+  if ((int)c->sp.size() >= kMaxSpecies) return fail(c, PIC_EINVAL, "too many species");
   if (d->capacity < 0 || d->capacity >= (int64_t(1) << 31))
     return fail(c, PIC_EINVAL, "capacity must be below 2^31");
   if (!(d->m1 > 0) || d->q1 == 0.0) return fail(c, PIC_EINVAL, "bad charge or mass");
@@ -1101,6 +1165,7 @@ void pic_destroy(pic_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  release_host(c);
   dev_free_all(c);
   delete c;
 }

@@ -379,6 +379,25 @@ def test_particles_outside_their_tile(pic, ndim):
     _compare_particles(o, s, wl, 1e-11)
 
 
+def test_adaptive_sort_policy(pic):
+    """Default sort policy with hot electrons: the species is re-sorted once
+    enough of it was advanced outside its tile (the storage order changes),
+    and the coupled run still follows the oracle."""
+    _say("case: adaptive sort policy")
+    wl = random_workload(3, 400, 3000, seed=91, shape=(24, 24, 16), vmax_el=0.95)
+    o, s = _both(wl, pic, 64)
+    first = s.particles(1, ids=True)["id"].copy()
+    o.step(12)
+    s.step(12)
+    assert o.diagnostics()["error_word"] == 0, "oracle run left the valid range"
+    later = s.particles(1, ids=True)["id"]
+    assert not np.array_equal(first, later), "no sort of the electrons in 12 steps"
+    Eo, Bo, Jo = o.fields()
+    Eg, Bg, Jg = s.fields()
+    assert rel_l2(Eg, Eo) < 1e-12 and rel_l2(Bg, Bo) < 1e-12
+    _compare_particles(o, s, wl, 1e-11)
+
+
 def test_global_kernel_option(pic):
     """The HBM-gather / global-atomic kernel (PIC_FLAG_GLOBAL_KERNEL) agrees
     with the oracle too."""
