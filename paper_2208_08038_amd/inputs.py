@@ -208,6 +208,31 @@ def neutral_medium_1d(cells: int = 2048, ppc: int = 8, steps: int = 1000,
                     notes=f"{n} two-body ions, omega_c={omega_c}, omega_pb={omega_pb}")
 
 
+def bound_slab_1d(cells: int = 1536, x_cells=(256, 1536), ppc: int = 4, steps: int = 2200,
+                  omega_c: float = 3.0, omega_pb: float = 0.9, a0: float = 1e-4,
+                  cycles: int = 10, dx_per_lambda: int = 64, config_id: int = 11) -> Workload:
+    """Neutral bound-electron medium filling x_cells (cells) after a vacuum
+    gap, for the observables of Sec. 3.1 (group velocity, reflection phase):
+    cold two-body gold ions (delta = 0, at rest), plane wave polarised along
+    y entering at x-min.  The medium's far end is the particle wall
+    (x_cells[1] may reach cells - pad)."""
+    dx = TWO_PI / float(dx_per_lambda)
+    dt = 0.98 * dx
+    laser = Laser(a0=a0, omega=1.0, t_env=cycles * TWO_PI, pol=1)
+    grid = Grid(1, (cells, 1, 1), (dx, 1.0, 1.0), dt, (LASER, PERIODIC, PERIODIC),
+                (OPEN, PERIODIC, PERIODIC), pad=3, laser=laser,
+                re_norm=TWO_PI * R_E_M / 12.4e-9)
+    q1, m1, q2, m2 = gold_ion(78, 0.0)
+    n_ion = bound_plasma_density(q1, m1, q2, m2, omega_pb)
+    sp = Species(TWO_BODY, q1, m1, q2, m2, weight=n_ion * dx / ppc, omega_c=omega_c,
+                 a_c=math.inf, name="Au_Zb78_cold")
+    lo, hi = x_cells[0], min(x_cells[1], cells - grid.pad)
+    x = stratified_positions(rng_for(config_id), [lo], [hi], ppc, grid.dx, 1)
+    parts = Particles(x=x, u1=np.zeros((x.shape[0], 3)))
+    return Workload("bound_slab_1d", grid, [(sp, parts)], steps, 64,
+                    notes=f"medium cells {lo}..{hi}, omega_c={omega_c}, omega_pb={omega_pb}")
+
+
 # --------------------------------------------------------------------------
 # Case 2: Bragg scattering from a rotated square lattice (Sec. 3.2), 2D
 # --------------------------------------------------------------------------

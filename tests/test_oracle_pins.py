@@ -12,6 +12,7 @@ import os
 import numpy as np
 import pytest
 
+import _sec31 as S31
 from _bragg import bragg_case, scattered_direction
 from paper_2208_08038_amd.inputs import (
     LASER, OPEN, PERIODIC, POINT, TWO_BODY, Grid, Laser, Particles, Species, neutral_medium_1d)
@@ -568,6 +569,53 @@ def test_bragg_scattered_peak_angle(oracle_built, d_over_lambda):
     assert abs(angle - expect) < math.degrees(1.0 / 16.0), (angle, expect)
     assert abs(kmean - 1.0) < 0.03
     assert contrast > 3.0
+
+
+# ------------------------------------------ Sec. 3.1 observables (NEXT-2)
+
+def _oracle_series(wl, probes, with_medium):
+    o = Oracle.from_workload(wl, max_probe_steps=wl.steps) if with_medium else \
+        Oracle(wl.grid, max_probe_steps=wl.steps)
+    o.set_probes([(1, (p, 0, 0)) for p in probes])
+    o.step(wl.steps)
+    assert o.diagnostics()["error_word"] == 0
+    return o.probes()
+
+
+@pytest.mark.slow
+def test_group_velocity_scan(oracle_built):
+    """Sec. 3.1: the group velocity of a pulse in the bound-electron medium
+    follows v_g = (k/w + w^2/(2k) d eps_r/dw)^-1 and falls as w_c approaches
+    the laser frequency (three restoring frequencies, within 1e-3)."""
+    vg = []
+    for wc in (3.0, 2.5, 2.0):
+        wl, probes = S31.group_velocity_case(wc)
+        v = S31.measured_group_velocity(wl, probes, _oracle_series(wl, probes, True))
+        assert abs(v / S31.group_velocity_theory(wc) - 1.0) < 1e-3, (wc, v)
+        vg.append(v)
+    assert vg[0] > vg[1] > vg[2]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("omega_c", [0.8, 0.7, 3.0])
+def test_reflection_phase(oracle_built, omega_c):
+    """Sec. 3.1: reflection at the medium's surface, r = (1 - beta)/(1 + beta),
+    beta = sqrt(eps_r).  Opaque medium (eps_r < 0, beta = i Gamma): |r| = 1
+    and phase atan(-2 Gamma/(1 - Gamma^2)) within 0.01 rad; transparent
+    medium (w_c = 3): |r| within 2 % and a phase of pi within 0.1 rad."""
+    wl, (p,) = S31.reflection_case(omega_c)
+    vac = _oracle_series(wl, (p,), False)[0]
+    med = _oracle_series(wl, (p,), True)[0]
+    r = S31.measured_reflection(wl, p, vac, med)
+    rt = S31.reflection_theory(omega_c)
+    if S31.eps_r(omega_c) < 0:
+        assert abs(abs(r) - 1.0) < 0.01
+        assert abs(np.angle(r) - np.angle(rt)) < 0.01, (np.angle(r), np.angle(rt))
+        gamma = math.sqrt(-S31.eps_r(omega_c))
+        assert abs(math.atan2(-2 * gamma, 1 - gamma ** 2) - np.angle(rt)) < 1e-12
+    else:
+        assert abs(abs(r) / abs(rt) - 1.0) < 0.02
+        assert abs(abs(np.angle(r)) - math.pi) < 0.1
 
 
 # ------------------------------------------ paper-printed numbers (T10)
