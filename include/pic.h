@@ -91,10 +91,16 @@ typedef struct {
    E_inc(x, t) = a0 sin^2(pi t'/t_env) sin(omega t' + phase) * G(y, z),
    t' = t - t_delay - x, nonzero for 0 <= t' <= t_env, G = exp(-r^2/waist^2)
    about (yc, zc) if waist > 0 else 1; pol 1 drives E_y (B_z = E_y),
-   pol 2 drives E_z (B_y = -E_z). */
+   pol 2 drives E_z (B_y = -E_z).  angle != 0 (2D/3D, waist 0 only): a plane
+   wave travelling at `angle` from +x toward +y, t' = t - t_delay -
+   x cos(angle) - (y - yc) sin(angle); pol 1 keeps E in the x-y plane
+   (B_z = |E|), pol 2 has E along z (B_y = -cos(angle) E_z).  With a periodic
+   y axis the wave is periodic only if sin(angle) n_y dx_y omega / (2 pi) is
+   an integer (the caller's choice). */
 typedef struct {
   double a0, omega, t_env, waist, yc, zc, phase, t_delay;
   int32_t pol, reserved;
+  double angle;
 } pic_laser;
 
 typedef struct {

@@ -114,6 +114,8 @@ static double b2(double d) {
 
 or_ctx* or_create(const or_config* cfg) {
   if (!cfg || cfg->ndim < 1 || cfg->ndim > 3) return NULL;
+  /* an oblique wave is a plane wave in a resolved x-y plane */
+  if (cfg->angle != 0.0 && (cfg->ndim < 2 || cfg->waist > 0.0)) return NULL;
   or_ctx* c = (or_ctx*)calloc(1, sizeof(or_ctx));
   c->g = *cfg;
   c->nd = cfg->ndim;
@@ -812,14 +814,23 @@ static double laser_time(const or_config* g, double tau) {
   return g->a0 * s * s * sin(g->omega * tau + g->phase);
 }
 
-/* Incident magnetic field of the laser (a wave travelling along +x, E_y = B_z
-   and E_z = -B_y) for component a of B at storage index (i, j, k). */
+/* Incident magnetic field of the laser for component a of B at storage index
+   (i, j, k).  A plane wave with unit direction n and electric field e has
+   B = n x e (c = 1): along +x, E_y gives B_z = E_y and E_z gives B_y = -E_z;
+   at an angle theta toward +y, the in-plane E (pol 1) gives B_z = |E| and
+   E_z (pol 2) gives B_y = -cos(theta) E_z. */
 static double b_incident(const or_ctx* c, int a, int64_t i, int64_t j, int64_t k, double t) {
   const or_config* g = &c->g;
   if (g->a0 == 0.0) return 0.0;
   int want = g->pol == 2 ? 1 : 2; /* pol y drives B_z, pol z drives B_y */
   if (a != want) return 0.0;
   double x = ((double)i + 0.5 * STAG_B[a][0]) * g->dx[0];
+  if (g->angle != 0.0) {
+    double y = c->nd > 1 ? ((double)j + 0.5 * STAG_B[a][1]) * g->dx[1] - g->yc : 0.0;
+    double tau = t - g->t_delay - (x * cos(g->angle) + y * sin(g->angle));
+    double e = laser_time(g, tau);
+    return a == 2 ? e : -cos(g->angle) * e;
+  }
   double prof = 1.0;
   if (g->waist > 0.0) {
     double r2 = 0.0;

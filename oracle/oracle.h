@@ -55,8 +55,11 @@ typedef struct {
   uint32_t flags, reserved;
   /* laser entering at x-min: E_inc(t) = a0 * sin^2(pi t'/t_env) * sin(omega t' + phase),
      t' = t - t_delay - x, for 0 <= t' <= t_env; transverse Gaussian exp(-r^2/waist^2)
-     about (yc, zc) when waist > 0, plane wave otherwise. */
-  double a0, omega, t_env, waist, yc, zc, phase, t_delay;
+     about (yc, zc) when waist > 0, plane wave otherwise.  angle != 0 (2D and
+     3D, plane wave only): the wave travels at `angle` from +x toward +y,
+     t' = t - t_delay - x cos(angle) - (y - yc) sin(angle); pol 1 keeps E in
+     the x-y plane (B along z), pol 2 has E along z. */
+  double a0, omega, t_env, waist, yc, zc, phase, t_delay, angle;
 } or_config;
 
 typedef struct {

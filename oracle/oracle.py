@@ -29,7 +29,7 @@ class _Config(C.Structure):
         ("flags", C.c_uint32), ("reserved", C.c_uint32),
         ("a0", C.c_double), ("omega", C.c_double), ("t_env", C.c_double),
         ("waist", C.c_double), ("yc", C.c_double), ("zc", C.c_double),
-        ("phase", C.c_double), ("t_delay", C.c_double),
+        ("phase", C.c_double), ("t_delay", C.c_double), ("angle", C.c_double),
     ]
 
 
@@ -134,6 +134,7 @@ class Oracle:
         cfg.a0, cfg.omega, cfg.t_env = las.a0, las.omega, las.t_env
         cfg.waist, cfg.yc, cfg.zc = las.waist, las.yc, las.zc
         cfg.phase, cfg.t_delay = las.phase, las.t_delay
+        cfg.angle = getattr(las, "angle", 0.0)
         self.cfg = cfg
         self.grid = grid
         self.ndim = grid.ndim

@@ -483,6 +483,9 @@ int step_t(pic_ctx* c, int nsteps) {
   las.t_delay = c->cfg.laser.t_delay;
   las.pol = c->cfg.laser.pol;
   las.on = (c->cfg.bc_lo[0] == PIC_BC_LASER && c->cfg.laser.a0 != 0.0) ? 1 : 0;
+  las.oblique = c->cfg.laser.angle != 0.0 ? 1 : 0;
+  las.cos_a = std::cos(c->cfg.laser.angle);
+  las.sin_a = std::sin(c->cfg.laser.angle);
   for (int it = 0; it < nsteps; it++) {
     const bool check = (c->cfg.flags & PIC_FLAG_CHARGE_CHECK) && it == nsteps - 1;
     // tile sort: always after a load; then on a fixed cadence, or per
@@ -808,6 +811,8 @@ int pic_create(const pic_config* cfg, const pic_allocator* alloc, void* hip_stre
     if (pl != ph) return fail(nullptr, PIC_EINVAL, "periodic faces come in pairs");
     if (cfg->bc_hi[d] == PIC_BC_LASER || (d > 0 && cfg->bc_lo[d] == PIC_BC_LASER))
       return fail(nullptr, PIC_EINVAL, "the laser enters through x-min only");
+    if (d == 0 && cfg->laser.angle != 0.0 && (cfg->ndim < 2 || cfg->laser.waist > 0.0))
+      return fail(nullptr, PIC_EINVAL, "an oblique laser is a plane wave in 2D or 3D");
     if (pl && cfg->n[d] < 2 * pic::kGuard)
       return fail(nullptr, PIC_EINVAL, "periodic dimensions need at least 6 cells");
     if (!pl && cfg->pad < 3) return fail(nullptr, PIC_EINVAL, "pad must be >= 3 with open faces");

@@ -180,6 +180,13 @@ __device__ __forceinline__ double b_incident(const GridInfo& g, const LaserDev& 
   // B_a is half-staggered along the two axes other than a
   double sx = 0.5, sy = a == 1 ? 0.0 : 0.5, sz = a == 2 ? 0.0 : 0.5;
   double x = ((double)i + sx) * g.dx[0];
+  if (L.oblique) {
+    // plane wave travelling at an angle toward +y: B = n x E (c = 1), so the
+    // in-plane E gives B_z = |E| and E_z gives B_y = -cos(angle) E_z
+    double y = g.nd > 1 ? ((double)j + sy) * g.dx[1] - L.yc : 0.0;
+    double e = laser_time(L, t - L.t_delay - (x * L.cos_a + y * L.sin_a));
+    return a == 2 ? e : -L.cos_a * e;
+  }
   double prof = 1.0;
   if (L.waist > 0.0) {
     double r2 = 0.0;

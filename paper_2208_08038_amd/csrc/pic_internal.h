@@ -106,8 +106,10 @@ void launch_e_full(const GridInfo& g, const FieldPtrs<Real>& f, hipStream_t st);
 
 struct LaserDev {
   double a0, omega, t_env, waist, yc, zc, phase, t_delay;
+  double cos_a, sin_a;  // direction of travel in the x-y plane
   int pol;
   int on;
+  int oblique;
 };
 
 template <typename Real>

@@ -52,7 +52,8 @@ class Laser:
     zc: float = 0.0
     phase: float = 0.0
     t_delay: float = 0.0
-    pol: int = 1  # 1: E along y, 2: E along z
+    pol: int = 1  # 1: E along y (in the x-y plane), 2: E along z
+    angle: float = 0.0  # direction of travel from +x toward +y (plane waves only)
 
 
 @dataclass

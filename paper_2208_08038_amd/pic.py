@@ -35,7 +35,7 @@ class PicLaser(C.Structure):
     _fields_ = [("a0", C.c_double), ("omega", C.c_double), ("t_env", C.c_double),
                 ("waist", C.c_double), ("yc", C.c_double), ("zc", C.c_double),
                 ("phase", C.c_double), ("t_delay", C.c_double),
-                ("pol", C.c_int32), ("reserved", C.c_int32)]
+                ("pol", C.c_int32), ("reserved", C.c_int32), ("angle", C.c_double)]
 
 
 class PicConfig(C.Structure):
@@ -185,7 +185,7 @@ class Simulation:
         cfg.re_norm = float(grid.re_norm)
         las = grid.laser
         cfg.laser = PicLaser(las.a0, las.omega, las.t_env, las.waist, las.yc, las.zc, las.phase,
-                             las.t_delay, int(las.pol), 0)
+                             las.t_delay, int(las.pol), 0, float(getattr(las, "angle", 0.0)))
         self.cfg = cfg
         self.grid = grid
         self.ndim = grid.ndim

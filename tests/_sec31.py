@@ -13,7 +13,9 @@ import math
 
 import numpy as np
 
-from paper_2208_08038_amd.inputs import bound_slab_1d
+from paper_2208_08038_amd.inputs import (LASER, PERIODIC, OPEN, R_E_M, TWO_BODY, Grid, Laser,
+                                         Particles, Species, Workload, bound_plasma_density,
+                                         bound_slab_1d, gold_ion, rng_for, stratified_positions)
 
 OMEGA_PB = 0.9
 
@@ -67,3 +69,37 @@ def measured_reflection(wl, probe, vacuum, medium, interface_cell=256):
     fr = ((medium - vacuum) * ph).sum()
     L = (interface_cell - probe) * wl.grid.dx[0]
     return fr / fi * np.exp(-2j * L)
+
+
+def refraction_case(omega_c=2.0, angle=math.pi / 6):
+    """2D, lambda/32 cells, 256 x 64 (periodic in y: the 30-degree wave's
+    phase advances by one wavelength over the 2-lambda height); cold medium
+    from cell 96 to the wall; plane wave polarised along z entering at x-min
+    at `angle` to +x; 12-cycle envelope.  Probes on the line y = 32: in the
+    vacuum gap and in the medium."""
+    two_pi = 2 * math.pi
+    dx = two_pi / 32.0
+    dt = 0.98 * dx / math.sqrt(2.0)
+    nx, ny = 256, 64
+    las = Laser(a0=1e-4, omega=1.0, t_env=12 * two_pi, pol=2, angle=angle)
+    g = Grid(2, (nx, ny, 1), (dx, dx, 1.0), dt, (LASER, PERIODIC, PERIODIC),
+             (OPEN, PERIODIC, PERIODIC), pad=3, laser=las, re_norm=two_pi * R_E_M / 12.4e-9)
+    q1, m1, q2, m2 = gold_ion(78, 0.0)
+    n_ion = bound_plasma_density(q1, m1, q2, m2, OMEGA_PB)
+    sp = Species(TWO_BODY, q1, m1, q2, m2, weight=n_ion * dx * dx, omega_c=omega_c,
+                 a_c=math.inf)
+    x = stratified_positions(rng_for(12), [96, 0], [nx - 3, ny], 1, g.dx, 2)
+    parts = Particles(x=x, u1=np.zeros((x.shape[0], 3)))
+    steps = int((12 * two_pi + nx * dx * 1.2) / dt)
+    wl = Workload("refraction_2d", g, [(sp, parts)], steps, 64)
+    vac_cells = list(range(12, 84, 4))
+    med_cells = list(range(112, 232, 4))
+    return wl, vac_cells, med_cells
+
+
+def measured_kx(wl, cells, series):
+    """x component of the wave vector at w = 1 along a probe line: slope of
+    the unwrapped DFT phase against x."""
+    t = (np.arange(series.shape[1]) + 1) * wl.grid.dt
+    ph = np.unwrap(np.angle((series * np.exp(1j * t)[None, :]).sum(axis=1)))
+    return np.polyfit(np.asarray(cells) * wl.grid.dx[0], ph, 1)[0]

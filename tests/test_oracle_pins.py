@@ -618,6 +618,29 @@ def test_reflection_phase(oracle_built, omega_c):
         assert abs(abs(np.angle(r)) - math.pi) < 0.1
 
 
+@pytest.mark.slow
+def test_refraction_angle(oracle_built):
+    """Sec. 3.1 refraction check: a plane wave entering the medium at 30
+    degrees (its k_y fixed by the surface) refracts to sin(theta_t) =
+    sin(theta_i)/n, n = sqrt(eps_r): k_x measured along a probe line is
+    cos(theta_i) in vacuum (0.5 %) and sqrt(n^2 - sin^2 theta_i) in the medium,
+    and the refraction angle matches Snell's law within 0.2 degrees (it
+    differs from the incidence angle by 3.7)."""
+    wl, vac, med = S31.refraction_case(2.0)
+    o = Oracle.from_workload(wl, max_probe_steps=wl.steps)
+    o.set_probes([(2, (x, 32, 0)) for x in vac + med])
+    o.step(wl.steps)
+    assert o.diagnostics()["error_word"] == 0
+    pr = o.probes()
+    kv = S31.measured_kx(wl, vac, pr[:len(vac)])
+    km = S31.measured_kx(wl, med, pr[len(vac):])
+    n = math.sqrt(S31.eps_r(2.0))
+    assert abs(kv / math.cos(math.pi / 6) - 1.0) < 5e-3, kv
+    assert abs(km / math.sqrt(n ** 2 - 0.25) - 1.0) < 5e-3, km
+    theta_t = math.degrees(math.atan2(0.5, km))
+    assert abs(theta_t - math.degrees(math.asin(0.5 / n))) < 0.2, theta_t
+
+
 # ------------------------------------------ paper-printed numbers (T10)
 
 def test_paper_printed_numbers(oracle_built):
