@@ -242,6 +242,78 @@ def test_bragg_case_fp64_fp32(pic):
         assert med.diagnostics()["error_word"] == 0
 
 
+def _gpu_series(pic, wl, probes, with_medium, prec):
+    if with_medium:
+        s = pic.Simulation.from_workload(wl, precision=prec, max_probe_steps=wl.steps)
+    else:
+        s = pic.Simulation(wl.grid, precision=prec, max_probe_steps=wl.steps)
+    s.set_probes([(1, (p, 0, 0)) for p in probes])
+    s.step(wl.steps)
+    assert s.diagnostics()["error_word"] == 0
+    return s.probes()
+
+
+def test_sec31_observables_gpu(pic):
+    """Group velocity (w_c = 2.5) and reflection phase (opaque medium,
+    w_c = 0.8) on the GPU: probe series against the oracle's (FP64 relative
+    L2 1e-12, FP32 2e-5) and the observables against the Sec. 3.1 closed
+    forms (as for the oracle pins)."""
+    import _sec31 as S31
+    _say("case: sec 3.1 group velocity and reflection")
+    wl, probes = S31.group_velocity_case(2.5)
+    ref = Oracle.from_workload(wl, max_probe_steps=wl.steps)
+    ref.set_probes([(1, (p, 0, 0)) for p in probes])
+    ref.step(wl.steps)
+    pr_o = ref.probes()
+    wr, (pp,) = S31.reflection_case(0.8)
+    rv = Oracle(wr.grid, max_probe_steps=wr.steps)
+    rm = Oracle.from_workload(wr, max_probe_steps=wr.steps)
+    for o in (rv, rm):
+        o.set_probes([(1, (pp, 0, 0))])
+        o.step(wr.steps)
+    for prec, tol in ((64, 1e-12), (32, 2e-5)):
+        pr = _gpu_series(pic, wl, probes, True, prec)
+        assert rel_l2(pr, pr_o) < tol
+        v = S31.measured_group_velocity(wl, probes, pr)
+        assert abs(v / S31.group_velocity_theory(2.5) - 1.0) < 1e-3
+        vac = _gpu_series(pic, wr, (pp,), False, prec)[0]
+        med = _gpu_series(pic, wr, (pp,), True, prec)[0]
+        assert rel_l2(med, rm.probes()[0]) < tol and rel_l2(vac, rv.probes()[0]) < tol
+        r = S31.measured_reflection(wr, pp, vac, med)
+        assert abs(np.angle(r) - np.angle(S31.reflection_theory(0.8))) < 0.01
+        _say(f"fp{prec}: v_g {v:.5f} (theory {S31.group_velocity_theory(2.5):.5f}), "
+             f"reflection phase {np.angle(r):.4f} (theory "
+             f"{np.angle(S31.reflection_theory(0.8)):.4f})")
+
+
+def test_refraction_gpu(pic):
+    """Oblique plane wave (30 degrees, E along z) into the medium, 2D: GPU
+    probe series against the oracle's (FP64 1e-12, FP32 2e-5) and the
+    refraction angle against Snell's law (0.2 degrees), as for the oracle."""
+    import math
+    import _sec31 as S31
+    _say("case: refraction 2d")
+    wl, vac, med = S31.refraction_case(2.0)
+    probes = [(2, (x, 32, 0)) for x in vac + med]
+    o = Oracle.from_workload(wl, max_probe_steps=wl.steps)
+    o.set_probes(probes)
+    o.step(wl.steps)
+    pr_o = o.probes()
+    n = math.sqrt(S31.eps_r(2.0))
+    for prec, tol in ((64, 1e-12), (32, 2e-5)):
+        s = pic.Simulation.from_workload(wl, precision=prec, max_probe_steps=wl.steps)
+        s.set_probes(probes)
+        s.step(wl.steps)
+        assert s.diagnostics()["error_word"] == 0
+        pr = s.probes()
+        assert rel_l2(pr, pr_o) < tol
+        km = S31.measured_kx(wl, med, pr[len(vac):])
+        theta_t = math.degrees(math.atan2(0.5, km))
+        _say(f"fp{prec}: refraction angle {theta_t:.3f} deg (Snell "
+             f"{math.degrees(math.asin(0.5 / n)):.3f}), probes rel L2 {rel_l2(pr, pr_o):.2e}")
+        assert abs(theta_t - math.degrees(math.asin(0.5 / n))) < 0.2
+
+
 def test_neutral_medium_case_fp64(pic):
     """The full 1D neutral-medium case (2048 cells, 16k two-body ions,
     1000 steps): fields and probes match the oracle."""
