@@ -30,6 +30,7 @@ struct SpeciesHost {
   double a_c = 0.0;  // effective softening length (inf: harmonic)
   int64_t n = 0, cap = 0;
   bool has_wc = false, has_w = false;
+  double max_w = 0.0;  // largest |per-particle weight| loaded (has_w)
   void* cell = nullptr;
   void* off[3] = {nullptr, nullptr, nullptr};
   void* dl[3] = {nullptr, nullptr, nullptr};
@@ -219,6 +220,20 @@ pic::PushConst<Real> push_const(const pic_ctx* c, const SpeciesHost& s) {
   k.q2 = two ? (Real)d.q2 : Real(0);
   for (int a = 0; a < 3; a++) k.jf[a] = a < c->g.nd ? (Real)(-c->cfg.dx[a] / (dt * dv)) : Real(0);
   k.inv_dv = (Real)(1.0 / dv);
+  // Bound on one deposit term: charge x prefactor x shape factors.  The
+  // running sum C of shape changes lies in [-1, 1]; the transverse factor
+  // S0 (S0 + DS/2) + DS (S0/2 + DS/3) is at most 1 + 1/2; out-of-plane terms
+  // carry |v| < c = 1 instead of C.  A merged pair adds both bodies.
+  {
+    const double wmax = s.has_w ? s.max_w : std::fabs(d.weight);
+    const double qsum = (std::fabs(d.q1) + (two ? std::fabs(d.q2) : 0.0)) * wmax;
+    double fmax = c->g.nd < 3 ? 1.0 / dv : 0.0;
+    for (int a = 0; a < c->g.nd; a++) fmax = std::max(fmax, c->cfg.dx[a] / (dt * dv));
+    const double bound = 1.5 * qsum * fmax;
+    int e = bound > 0.0 ? (int)std::floor(46.0 - std::log2(bound)) : 0;
+    e = std::max(-120, std::min(120, e));
+    k.jscale = (Real)std::ldexp(1.0, e);
+  }
   k.two_body = two ? 1 : 0;
   k.deposit = (c->cfg.flags & PIC_FLAG_NO_DEPOSIT) ? 0 : 1;
   return k;
@@ -394,6 +409,7 @@ int load_particles_t(pic_ctx* c, SpeciesHost& s, int64_t n, const double* x, con
     std::vector<double> tmp(n, s.d.weight);
     if (w)
       for (int64_t p = 0; p < n; p++) tmp[p] = w[p];
+    for (int64_t p = 0; p < n; p++) s.max_w = std::max(s.max_w, std::fabs(tmp[p]));
     if (!s.w) return fail(c, PIC_ESTATE, "per-particle weight must come with the first load");
     if ((rc = put1(s.w, tmp.data()))) return rc;
   }
@@ -1015,16 +1031,23 @@ int pic_load_particles_device(pic_ctx* c, int32_t sid, int64_t n, const double* 
   pic::LoadSrc src{x, delta, u1, u2, omega_c, weight, n};
   pic::LoadSplit sp{s.d.q1, s.d.m1, s.d.q2, s.d.m2, s.d.omega_c, s.d.weight};
   const bool two = s.d.kind == PIC_TWO_BODY;
-  HIPCHK(c, hipMemsetAsync(c->load_err, 0, sizeof(uint32_t), c->stream));
+  HIPCHK(c, hipMemsetAsync(c->load_err, 0, 16, c->stream));
   if (c->prec == 32)
     pic::launch_load<float>(c->g, src, species_dev<float>(s), s.n, s.ids, sp, two, c->load_err,
                             c->stream);
   else
     pic::launch_load<double>(c->g, src, species_dev<double>(s), s.n, s.ids, sp, two, c->load_err,
                              c->stream);
-  uint32_t bad = 0;
-  HIPCHK(c, hipMemcpyAsync(&bad, c->load_err, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+  uint32_t lw[4] = {0, 0, 0, 0};
+  HIPCHK(c, hipMemcpyAsync(lw, c->load_err, 16, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  const uint32_t bad = lw[0];
+  if (s.has_w) {  // bytes 8..15: bits of the largest |weight| of this load
+    uint64_t bits = (uint64_t)lw[2] | ((uint64_t)lw[3] << 32);
+    double wm;
+    std::memcpy(&wm, &bits, sizeof(wm));
+    s.max_w = std::max(s.max_w, wm);
+  }
   if (bad & PIC_ERR_NAN) return fail(c, PIC_ENAN, "non-finite particle state");
   if (bad & PIC_ERR_RANGE) return fail(c, PIC_ERANGE, "particle outside the grid, walls or bond range");
   s.n += n;

@@ -11,6 +11,8 @@
 // arithmetic in single VGPRs.
 #pragma once
 
+#include <type_traits>
+
 #include "pic_internal.h"
 
 namespace pic {
@@ -221,12 +223,27 @@ __device__ __forceinline__ bool window(Real x0, Real x1, Window<Real>& win) {
   return true;
 }
 
-// Floating-point add into the current (accumulator type JT, which may be
-// wider than the arithmetic type): LDS patches take every term, global
-// planes skip exact zeros (fewer atomics).
+// Add into the current (accumulator type JT, which may be wider than the
+// arithmetic type): LDS patches take every term, global planes skip exact
+// zeros (fewer atomics).  An integer JT is a 64-bit fixed-point LDS patch: v * scale rounded to an
+// integer (scale a power of two chosen by the host so that every term stays
+// below 2^46 in magnitude).  Integer adds are exact, so the patch sum does
+// not depend on the order of the atomics, and 64-bit integer LDS atomics
+// issue faster than FP64 ones on gfx950.
+__device__ __forceinline__ long long to_fixed(double v, double scale) {
+  // v * scale + 1.5 * 2^52 has a unit ulp: its low mantissa bits hold the
+  // rounded integer (valid for |v * scale| < 2^51)
+  const double magic = 6755399441055744.0;
+  const double d = __builtin_fma(v, scale, magic);
+  return __builtin_bit_cast(long long, d) - __builtin_bit_cast(long long, magic);
+}
+
 template <bool GLOBAL, typename JT, typename Real>
-__device__ __forceinline__ void jadd(JT* p, Real v) {
-  if constexpr (GLOBAL) {
+__device__ __forceinline__ void jadd(JT* p, Real v, Real scale) {
+  if constexpr (std::is_integral<JT>::value) {
+    atomicAdd(reinterpret_cast<unsigned long long*>(p),
+              static_cast<unsigned long long>(to_fixed((double)v, (double)scale)));
+  } else if constexpr (GLOBAL) {
     if (v != Real(0)) unsafeAtomicAdd(p, (JT)v);
   } else {
     unsafeAtomicAdd(p, (JT)v);
@@ -255,10 +272,10 @@ __device__ __forceinline__ bool deposit(JT* const J[3], int base, int sy, int sz
       Real A = wx.S0[r] + Real(0.5) * wx.DS[r];
       if (r < 3) {
         C += wx.DS[r];
-        jadd<GLOBAL>(J[0] + o + r, fx * C);
+        jadd<GLOBAL>(J[0] + o + r, fx * C, c.jscale);
       }
-      jadd<GLOBAL>(J[1] + o + r, fy * A);
-      jadd<GLOBAL>(J[2] + o + r, fz * A);
+      jadd<GLOBAL>(J[1] + o + r, fy * A, c.jscale);
+      jadd<GLOBAL>(J[2] + o + r, fz * A, c.jscale);
     }
   } else if constexpr (ND == 2) {
     Window<Real> wx, wy;
@@ -274,7 +291,7 @@ __device__ __forceinline__ bool deposit(JT* const J[3], int base, int sy, int sz
         Real a = fx * C;
 #pragma unroll
         for (int s = 0; s < 4; s++)
-          jadd<GLOBAL>(J[0] + o + r + s * sy, a * (wy.S0[s] + Real(0.5) * wy.DS[s]));
+          jadd<GLOBAL>(J[0] + o + r + s * sy, a * (wy.S0[s] + Real(0.5) * wy.DS[s]), c.jscale);
       }
     }
     // J_y = f_y C_y(s) (S0x + DSx/2)(r)
@@ -286,7 +303,7 @@ __device__ __forceinline__ bool deposit(JT* const J[3], int base, int sy, int sz
         Real a = fy * C;
 #pragma unroll
         for (int r = 0; r < 4; r++)
-          jadd<GLOBAL>(J[1] + o + r + s * sy, a * (wx.S0[r] + Real(0.5) * wx.DS[r]));
+          jadd<GLOBAL>(J[1] + o + r + s * sy, a * (wx.S0[r] + Real(0.5) * wx.DS[r]), c.jscale);
       }
     }
     // J_z = f_z [S0x (S0y + DSy/2) + DSx (S0y/2 + DSy/3)]
@@ -296,7 +313,7 @@ __device__ __forceinline__ bool deposit(JT* const J[3], int base, int sy, int sz
       Real by = Real(0.5) * wy.S0[s] + third * wy.DS[s];
 #pragma unroll
       for (int r = 0; r < 4; r++)
-        jadd<GLOBAL>(J[2] + o + r + s * sy, fz * (wx.S0[r] * ay + wx.DS[r] * by));
+        jadd<GLOBAL>(J[2] + o + r + s * sy, fz * (wx.S0[r] * ay + wx.DS[r] * by), c.jscale);
     }
   } else {
     Window<Real> wx, wy, wz;
@@ -315,9 +332,9 @@ __device__ __forceinline__ bool deposit(JT* const J[3], int base, int sy, int sz
         for (int s = 0; s < 4; s++) {
           Real T = fx * (wy.S0[s] * az + wy.DS[s] * bz);
           JT* p = J[0] + o + s * sy + t * sz;
-          jadd<GLOBAL>(p, C0 * T);
-          jadd<GLOBAL>(p + 1, C1 * T);
-          jadd<GLOBAL>(p + 2, C2 * T);
+          jadd<GLOBAL>(p, C0 * T, c.jscale);
+          jadd<GLOBAL>(p + 1, C1 * T, c.jscale);
+          jadd<GLOBAL>(p + 2, C2 * T, c.jscale);
         }
       }
     }
@@ -333,9 +350,9 @@ __device__ __forceinline__ bool deposit(JT* const J[3], int base, int sy, int sz
         for (int r = 0; r < 4; r++) {
           Real T = fy * (wx.S0[r] * az + wx.DS[r] * bz);
           JT* p = J[1] + o + r + t * sz;
-          jadd<GLOBAL>(p, C0 * T);
-          jadd<GLOBAL>(p + sy, C1 * T);
-          jadd<GLOBAL>(p + 2 * sy, C2 * T);
+          jadd<GLOBAL>(p, C0 * T, c.jscale);
+          jadd<GLOBAL>(p + sy, C1 * T, c.jscale);
+          jadd<GLOBAL>(p + 2 * sy, C2 * T, c.jscale);
         }
       }
     }
@@ -351,9 +368,9 @@ __device__ __forceinline__ bool deposit(JT* const J[3], int base, int sy, int sz
         for (int r = 0; r < 4; r++) {
           Real T = fz * (wx.S0[r] * ay + wx.DS[r] * by);
           JT* p = J[2] + o + r + s * sy;
-          jadd<GLOBAL>(p, C0 * T);
-          jadd<GLOBAL>(p + sz, C1 * T);
-          jadd<GLOBAL>(p + 2 * sz, C2 * T);
+          jadd<GLOBAL>(p, C0 * T, c.jscale);
+          jadd<GLOBAL>(p + sz, C1 * T, c.jscale);
+          jadd<GLOBAL>(p + 2 * sz, C2 * T, c.jscale);
         }
       }
     }
@@ -434,10 +451,10 @@ __device__ __forceinline__ void deposit3(JT* const J[3], int base, int sy, int s
       if (r < 2) {
         Ca += a.DS[0][r];
         if constexpr (PAIR) Cb += b.DS[0][r];
-        jadd<GLOBAL>(J[0] + o + r, PAIR ? fxa * Ca + fxb * Cb : fxa * Ca);
+        jadd<GLOBAL>(J[0] + o + r, PAIR ? fxa * Ca + fxb * Cb : fxa * Ca, c.jscale);
       }
-      jadd<GLOBAL>(J[1] + o + r, PAIR ? fya * Aa + fyb * Ab : fya * Aa);
-      jadd<GLOBAL>(J[2] + o + r, PAIR ? fza * Aa + fzb * Ab : fza * Aa);
+      jadd<GLOBAL>(J[1] + o + r, PAIR ? fya * Aa + fyb * Ab : fya * Aa, c.jscale);
+      jadd<GLOBAL>(J[2] + o + r, PAIR ? fza * Aa + fzb * Ab : fza * Aa, c.jscale);
     }
   } else if constexpr (ND == 2) {
     Real fxa = Qa * c.jf[0], fya = Qa * c.jf[1], fza = Qa * va[2] * c.inv_dv;
@@ -467,8 +484,8 @@ __device__ __forceinline__ void deposit3(JT* const J[3], int base, int sy, int s
       }
       // J_x = f_x C_x(r) (S0y + DSy/2)(s)
       JT* px = J[0] + o + s2 * sy;
-      jadd<GLOBAL>(px, PAIR ? fxa * Cxa0 * Aya + fxb * Cxb0 * Ayb : fxa * Cxa0 * Aya);
-      jadd<GLOBAL>(px + 1, PAIR ? fxa * Cxa1 * Aya + fxb * Cxb1 * Ayb : fxa * Cxa1 * Aya);
+      jadd<GLOBAL>(px, PAIR ? fxa * Cxa0 * Aya + fxb * Cxb0 * Ayb : fxa * Cxa0 * Aya, c.jscale);
+      jadd<GLOBAL>(px + 1, PAIR ? fxa * Cxa1 * Aya + fxb * Cxb1 * Ayb : fxa * Cxa1 * Aya, c.jscale);
 #pragma unroll
       for (int r = 0; r < 3; r++) {
         Real Axa = a.S0[0][r] + Real(0.5) * a.DS[0][r];
@@ -478,13 +495,13 @@ __device__ __forceinline__ void deposit3(JT* const J[3], int base, int sy, int s
         if (s2 < 2) {
           Real cya = s2 == 0 ? Cya0 : Cya1, cyb = s2 == 0 ? Cyb0 : Cyb1;
           jadd<GLOBAL>(J[1] + o + r + s2 * sy, PAIR ? fya * cya * Axa + fyb * cyb * Axb
-                                                     : fya * cya * Axa);
+                                                     : fya * cya * Axa, c.jscale);
         }
         // J_z = f_z [S0x (S0y + DSy/2) + DSx (S0y/2 + DSy/3)]
         Real za = fza * (a.S0[0][r] * Aya + a.DS[0][r] * Bya);
         Real zb = 0;
         if constexpr (PAIR) zb = fzb * (b.S0[0][r] * Ayb + b.DS[0][r] * Byb);
-        jadd<GLOBAL>(J[2] + o + r + s2 * sy, PAIR ? za + zb : za);
+        jadd<GLOBAL>(J[2] + o + r + s2 * sy, PAIR ? za + zb : za, c.jscale);
       }
     }
   } else {
@@ -512,8 +529,8 @@ __device__ __forceinline__ void deposit3(JT* const J[3], int base, int sy, int s
           Real Tb = 0;
           if constexpr (PAIR) Tb = fb * (b.S0[1][s2] * azb + b.DS[1][s2] * bzb);
           JT* p = J[0] + o + s2 * sy + t * sz;
-          jadd<GLOBAL>(p, PAIR ? Ca0 * Ta + Cb0 * Tb : Ca0 * Ta);
-          jadd<GLOBAL>(p + 1, PAIR ? Ca1 * Ta + Cb1 * Tb : Ca1 * Ta);
+          jadd<GLOBAL>(p, PAIR ? Ca0 * Ta + Cb0 * Tb : Ca0 * Ta, c.jscale);
+          jadd<GLOBAL>(p + 1, PAIR ? Ca1 * Ta + Cb1 * Tb : Ca1 * Ta, c.jscale);
         }
       }
     }
@@ -541,8 +558,8 @@ __device__ __forceinline__ void deposit3(JT* const J[3], int base, int sy, int s
           Real Tb = 0;
           if constexpr (PAIR) Tb = fb * (b.S0[0][r] * azb + b.DS[0][r] * bzb);
           JT* p = J[1] + o + r + t * sz;
-          jadd<GLOBAL>(p, PAIR ? Ca0 * Ta + Cb0 * Tb : Ca0 * Ta);
-          jadd<GLOBAL>(p + sy, PAIR ? Ca1 * Ta + Cb1 * Tb : Ca1 * Ta);
+          jadd<GLOBAL>(p, PAIR ? Ca0 * Ta + Cb0 * Tb : Ca0 * Ta, c.jscale);
+          jadd<GLOBAL>(p + sy, PAIR ? Ca1 * Ta + Cb1 * Tb : Ca1 * Ta, c.jscale);
         }
       }
     }
@@ -570,8 +587,8 @@ __device__ __forceinline__ void deposit3(JT* const J[3], int base, int sy, int s
           Real Tb = 0;
           if constexpr (PAIR) Tb = fb * (b.S0[0][r] * ayb + b.DS[0][r] * byb);
           JT* p = J[2] + o + r + s2 * sy;
-          jadd<GLOBAL>(p, PAIR ? Ca0 * Ta + Cb0 * Tb : Ca0 * Ta);
-          jadd<GLOBAL>(p + sz, PAIR ? Ca1 * Ta + Cb1 * Tb : Ca1 * Ta);
+          jadd<GLOBAL>(p, PAIR ? Ca0 * Ta + Cb0 * Tb : Ca0 * Ta, c.jscale);
+          jadd<GLOBAL>(p + sz, PAIR ? Ca1 * Ta + Cb1 * Tb : Ca1 * Ta, c.jscale);
         }
       }
     }

@@ -24,5 +24,7 @@ struct LoadSplit {
 template <typename Real>
 void launch_load(const GridInfo& g, const LoadSrc& src, const SpeciesDev<Real>& s, int64_t at,
                  int64_t* ids, const LoadSplit& sp, bool two, uint32_t* err, hipStream_t st);
+// err: 16 bytes, zeroed by the caller: [0] error bits (PIC_ERR_*), bytes
+// 8..15 the bits of the largest |weight| loaded (a non-negative double).
 
 }  // namespace pic

@@ -136,7 +136,14 @@ __global__ void __launch_bounds__(256) k_load(GridInfo g, LoadSrc src, SpeciesDe
     }
   }
   if (s.wc) s.wc[q] = (Real)(src.wc ? src.wc[p] : sp.omega_c);
-  if (s.w) s.w[q] = (Real)(src.w ? src.w[p] : sp.weight);
+  if (s.w) {
+    const double w = src.w ? src.w[p] : sp.weight;
+    s.w[q] = (Real)w;
+    // largest |weight| of the load (bit order of non-negative doubles is
+    // their numeric order), in bytes 8..15 of the error buffer
+    atomicMax(reinterpret_cast<unsigned long long*>(err + 2),
+              __builtin_bit_cast(unsigned long long, fabs(w)));
+  }
   if (ids) ids[q] = q;
 }
 

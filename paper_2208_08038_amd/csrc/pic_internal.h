@@ -75,6 +75,9 @@ struct PushConst {
   Real q1, q2;
   Real jf[3];      // -dx_d / (dt dV): Esirkepov prefactor per unit charge
   Real inv_dv;
+  // power-of-two scale of the fixed-point LDS current patch: every deposit
+  // term of this species times jscale is below 2^46 in magnitude
+  Real jscale;
   int two_body;
   int deposit;
 };

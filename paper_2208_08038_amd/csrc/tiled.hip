@@ -5,9 +5,10 @@
 //   2. clears an LDS current patch covering the tile plus the 2-node
 //      (below) / 3-node (above) reach of the order-2 Esirkepov window,
 //   3. advances every particle of the tile, gathering from LDS and
-//      depositing with LDS floating-point atomics; a body whose nearest
-//      node changes needs the longer four-node deposit, which is queued in
-//      LDS and run after the loop by consecutive threads,
+//      depositing with LDS atomics (64-bit fixed point for FP32 work, FP64
+//      otherwise); a body whose nearest node changes needs the longer
+//      four-node deposit, which is queued in LDS and run after the loop by
+//      consecutive threads,
 //   4. adds the patch into the global current with plain loads and stores.
 // Tiles are launched in 2^ndim colours (parity of the tile coordinates):
 // patches of tiles of one colour never overlap (patch extent T + 5 <= 2T),
@@ -16,6 +17,7 @@
 // listed here; a second kernel advances the listed particles from HBM
 // after the last colour, adding their current with global atomics.
 #include <algorithm>
+#include <type_traits>
 
 #include "cycle.h"
 #include "tiled.h"
@@ -24,11 +26,16 @@ namespace pic {
 
 namespace {
 
-// The LDS current patch accumulates in FP64 whatever the working precision:
-// on gfx950 FP32 LDS atomic adds issue far slower than FP64 ones (measured
-// with SQ_WAIT_INST_LDS), and the wider sum also drops the rounding of the
-// per-tile reduction.
-using PatchT = double;
+// LDS current patch: FP64 for FP64 work; for FP32 work 64-bit fixed point
+// (exact, order-independent sums, and 64-bit integer LDS atomics issue
+// faster than FP64 ones; FP32 LDS atomic adds issue slowest of all on
+// gfx950).  The per-species scale keeps a term below 2^46 (host side), so
+// 2^16 terms per node cannot overflow: a workgroup advances at most kChunk
+// particles (two bodies each) and lists any further ones for the
+// outside-tile kernel.
+template <typename Real>
+using PatchOf = std::conditional_t<sizeof(Real) == 4, long long, double>;
+constexpr int64_t kChunk = 32768;
 
 // LDS queue of general deposits (structure of arrays, `cap` entries).
 template <typename Real, int ND>
@@ -76,6 +83,7 @@ __device__ __forceinline__ void tiled_body(const GridInfo& g, const FieldPtrs<Re
                                            const SpeciesDev<Real>& s, const PushConst<Real>& c,
                                            const TileGeom& t, const uint32_t* tile_off, int color,
                                            uint32_t* list, uint32_t* nlist, uint32_t* err) {
+  using PatchT = PatchOf<Real>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   // tile of this block within the colour
   int b = blockIdx.x;
@@ -153,14 +161,16 @@ __device__ __forceinline__ void tiled_body(const GridInfo& g, const FieldPtrs<Re
   if (threadIdx.x == 0) *queue.count = 0u;
   __syncthreads();
 
-  // 3. particles of the tile
+  // 3. particles of the tile; the state of a thread's next particle is
+  //    loaded while it advances the present one (PREFETCH; costs the
+  //    registers of one more state).  Beyond kChunk particles (a tile far
+  //    more crowded than the mean) the rest is listed like particles
+  //    outside the tile, which bounds the number of terms per patch node.
   const int fsy = L.fpitch, fsz = L.fplane;
   const int jsy = L.jpitch, jsz = L.jplane;
   const int lane = threadIdx.x & 63;
   const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  // the state of a thread's next particle is loaded while it advances the
-  // present one
-  // (PREFETCH; costs the registers of one more state)
+  const int64_t pk = p0 + kChunk;
   PState<Real> next;
   if (PREFETCH && p0 + threadIdx.x < p1) load_state<Real, ND, TWO>(s, c, p0 + threadIdx.x, next);
   for (int64_t p0w = p0; p0w < p1; p0w += blockDim.x) {
@@ -177,7 +187,7 @@ __device__ __forceinline__ void tiled_body(const GridInfo& g, const FieldPtrs<Re
     bool inside = false;
     if (valid) {
       decode_cell<ND>(g, st.cell, ci);
-      inside = true;
+      inside = p < pk;
 #pragma unroll
       for (int d = 0; d < ND; d++) inside = inside && ci[d] >= lo[d] && ci[d] < hi[d];
     }
@@ -228,6 +238,7 @@ __device__ __forceinline__ void tiled_body(const GridInfo& g, const FieldPtrs<Re
     jorg += (int64_t)(lo[d] - 2) * sd;
     jext[d] = (hi[d] - lo[d]) + 5;
   }
+  const double inv_scale = std::is_integral<PatchT>::value ? 1.0 / (double)c.jscale : 1.0;
   const int njn = L.Jd[0] * L.Jd[1] * L.Jd[2];
   for (int q = threadIdx.x; q < njn; q += blockDim.x) {
     int a = q % L.Jd[0], r = q / L.Jd[0];
@@ -238,7 +249,7 @@ __device__ __forceinline__ void tiled_body(const GridInfo& g, const FieldPtrs<Re
 #pragma unroll
     for (int comp = 0; comp < 3; comp++) {
       PatchT v = jl[comp][li];
-      if (v != PatchT(0)) f.J[comp][go] = (Real)((PatchT)f.J[comp][go] + v);
+      if (v != PatchT(0)) f.J[comp][go] = (Real)((double)f.J[comp][go] + (double)v * inv_scale);
     }
   }
 }

@@ -470,6 +470,41 @@ def test_adaptive_sort_policy(pic):
     _compare_particles(o, s, wl, 1e-11)
 
 
+def test_fp32_current_patch_fixed_point(pic):
+    """FP32 work accumulates each tile's current in 64-bit fixed point: the
+    sum does not depend on the order of the LDS atomics, so two identical
+    FP32 steps give bit-identical J (no particle leaves its tile in a first
+    step after a load, so no global atomics are involved); a tile with more
+    than 32768 particles (the rest go to the outside-tile kernel) still
+    follows the oracle."""
+    _say("case: fp32 fixed-point patch")
+    wl = random_workload(3, 600, 600, seed=101)
+    J = []
+    for _ in range(2):
+        s = pic.Simulation.from_workload(wl, precision=32)
+        s.step(1)
+        assert s.diagnostics()["n_outside_tile"] == 0
+        J.append(s.fields()[2])
+    assert np.array_equal(J[0], J[1])
+    # crowded tile: 40000 electrons in the first 8x8x6 tile
+    g = small_grid(3, (16, 16, 12), (0.3, 0.25, 0.2))
+    rng = np.random.default_rng(7)
+    n = 40000
+    x = rng.random((n, 3)) * np.array([8 * 0.3, 8 * 0.25, 6 * 0.2])
+    parts = Particles(x=x, u1=rng.normal(0.0, 0.05, (n, 3)))
+    sp = Species(POINT, -1.0, 1.0, 0.0, 0.0, weight=1e-4)
+    from paper_2208_08038_amd.inputs import Workload
+    wc = Workload("crowded", g, [(sp, parts)], 2, 32)
+    o = Oracle.from_workload(wc)
+    s = pic.Simulation.from_workload(wc, precision=32)
+    o.step(2)
+    s.step(2)
+    assert s.diagnostics()["error_word"] == 0
+    Eo, Bo, Jo = o.fields()
+    Eg, Bg, Jg = s.fields()
+    assert rel_l2(Eg, Eo) < 2e-5 and rel_l2(Jg, Jo) < 2e-5
+
+
 def test_global_kernel_option(pic):
     """The HBM-gather / global-atomic kernel (PIC_FLAG_GLOBAL_KERNEL) agrees
     with the oracle too."""
