@@ -96,11 +96,18 @@ typedef struct {
    x cos(angle) - (y - yc) sin(angle); pol 1 keeps E in the x-y plane
    (B_z = |E|), pol 2 has E along z (B_y = -cos(angle) E_z).  With a periodic
    y axis the wave is periodic only if sin(angle) n_y dx_y omega / (2 pi) is
-   an integer (the caller's choice). */
+   an integer (the caller's choice).  n_env > 0 (at most PIC_MAX_ENV)
+   replaces sin^2(pi t'/t_env) by the spline envelope
+   sum_{k < n_env} env[k] N3(t'/h - k), h = t_env / (n_env + 3), N3 the
+   cardinal cubic B-spline on [0, 4] (the envelope whose coefficients the
+   gradient run differentiates). */
+#define PIC_MAX_ENV 64
 typedef struct {
   double a0, omega, t_env, waist, yc, zc, phase, t_delay;
   int32_t pol, reserved;
   double angle;
+  int32_t n_env, reserved2;
+  double env[PIC_MAX_ENV];
 } pic_laser;
 
 typedef struct {
@@ -243,6 +250,49 @@ int pic_read_probes(pic_ctx* ctx, double* out, int64_t* nrecorded);
    particles found outside their tile is not included.  Synchronises. */
 int pic_timing(pic_ctx* ctx, int32_t species_id, double* total_ms, int64_t* launches,
                int32_t reset);
+
+/* Gradient run: the adjoint of the step (1D and 2D grids, both species
+   kinds, FP32 and FP64), the differentiation axis that the bound-electron
+   model of Sec. 2 / Sec. 3.1 opens: how a transmitted or reflected pulse
+   depends on the restoring frequency omega_c, the friction rate and the
+   laser's temporal envelope.
+
+   pic_grad_forward advances the context by nsteps exactly as pic_step
+   does, except that no tile sort runs during the run (the particles keep
+   their storage order; a pending sort after a load runs first), recording
+   the probes after every step, and keeps a device snapshot of the whole
+   state every checkpoint_every steps (memory: ceil(nsteps / K) + K + 1
+   snapshots, each the particle state plus E, B and the Mur history).
+   Fails with PIC_EINVAL in 3D, with PIC_FLAG_FROZEN_FIELDS or
+   PIC_FLAG_NO_DEPOSIT, or when the probe record has no room for nsteps
+   more steps.
+
+   pic_grad_backward takes the cotangent of the probe values recorded by
+   that run, dprobe[p * nsteps + n] = dL / d(probe p after step n of the
+   run) (HOST FP64, nprobe x nsteps), and returns dL/d(parameter) for the
+   parameters below, by re-running each checkpoint segment and reversing
+   its steps (transposed Yee, Mur and guard operations; adjoint particle
+   cycle).  Gradients with respect to omega_c are taken at fixed a_c (a
+   derived a_c keeps the value fixed at pic_add_species); a species with
+   per-particle omega_c gets the derivative with respect to a common shift
+   of all of them; d_omega_c includes the nu_per_omega * omega_c part of
+   the friction rate.  The context is left in the state at the end of the
+   forward run.  NULL outputs are skipped.  Synchronises. */
+typedef struct {
+  double* d_omega_c;  /* [number of species] */
+  double* d_nu;       /* [number of species]: d/d(nu), the species' constant rate */
+  double* d_env;      /* [laser.n_env]: d/d(env[k]) of the spline envelope */
+  double* d_E;        /* 3 x ncell HOST FP64, layout of pic_load_fields: d/d(E at run start) */
+  double* d_B;        /* same for B */
+} pic_grad;
+int pic_grad_forward(pic_ctx* ctx, int32_t nsteps, int32_t checkpoint_every);
+int pic_grad_backward(pic_ctx* ctx, const double* dprobe, pic_grad* out);
+/* After pic_grad_backward: dL/d(initial particle state) of one species in
+   storage order (as pic_read_particles at the start of the run): d_x
+   (n x ndim, d/d position), d_delta, d_u1, d_u2 (n x 3; two-body only for
+   delta and u2).  HOST FP64; NULL outputs are skipped. */
+int pic_read_grad_particles(pic_ctx* ctx, int32_t species_id, double* d_x, double* d_delta,
+                            double* d_u1, double* d_u2);
 
 /* Text of the last error on ctx (or of the last failed pic_create if NULL). */
 const char* pic_last_error(const pic_ctx* ctx);

@@ -116,6 +116,7 @@ or_ctx* or_create(const or_config* cfg) {
   if (!cfg || cfg->ndim < 1 || cfg->ndim > 3) return NULL;
   /* an oblique wave is a plane wave in a resolved x-y plane */
   if (cfg->angle != 0.0 && (cfg->ndim < 2 || cfg->waist > 0.0)) return NULL;
+  if (cfg->n_env < 0 || cfg->n_env > OR_MAX_ENV) return NULL;
   or_ctx* c = (or_ctx*)calloc(1, sizeof(or_ctx));
   c->g = *cfg;
   c->nd = cfg->ndim;
@@ -808,10 +809,32 @@ static void tangential(int d, int* t0, int* t1) {
   *t1 = d == 2 ? 1 : 2;
 }
 
+/* Cardinal cubic B-spline: the fourfold convolution of the unit box,
+   supported on [0, 4], one cubic piece per unit interval (de Boor). */
+static double cubic_bspline(double s) {
+  if (s <= 0.0 || s >= 4.0) return 0.0;
+  if (s < 1.0) return s * s * s / 6.0;
+  if (s < 2.0) return (-3.0 * s * s * s + 12.0 * s * s - 12.0 * s + 4.0) / 6.0;
+  if (s < 3.0) return (3.0 * s * s * s - 24.0 * s * s + 60.0 * s - 44.0) / 6.0;
+  return (4.0 - s) * (4.0 - s) * (4.0 - s) / 6.0;
+}
+
+/* Temporal envelope of the laser: sin^2 over [0, t_env], or the sum of the
+   n_env spline coefficients times their basis functions. */
+static double envelope(const or_config* g, double tau) {
+  if (g->n_env <= 0) {
+    double s = sin(OR_PI * tau / g->t_env);
+    return s * s;
+  }
+  double h = g->t_env / (double)(g->n_env + 3);
+  double e = 0.0;
+  for (int k = 0; k < g->n_env; k++) e += g->env[k] * cubic_bspline(tau / h - (double)k);
+  return e;
+}
+
 static double laser_time(const or_config* g, double tau) {
   if (tau < 0.0 || tau > g->t_env) return 0.0;
-  double s = sin(OR_PI * tau / g->t_env);
-  return g->a0 * s * s * sin(g->omega * tau + g->phase);
+  return g->a0 * envelope(g, tau) * sin(g->omega * tau + g->phase);
 }
 
 /* Incident magnetic field of the laser for component a of B at storage index

@@ -36,6 +36,8 @@ extern "C" {
 #define OR_NO_DEPOSIT 2u    /* particles are pushed but deposit no current */
 #define OR_CHARGE_CHECK 4u  /* compute rho before/after the last step of each or_step */
 
+#define OR_MAX_ENV 64 /* largest number of envelope spline coefficients */
+
 #define OR_POINT 0
 #define OR_TWO_BODY 1
 
@@ -58,8 +60,13 @@ typedef struct {
      about (yc, zc) when waist > 0, plane wave otherwise.  angle != 0 (2D and
      3D, plane wave only): the wave travels at `angle` from +x toward +y,
      t' = t - t_delay - x cos(angle) - (y - yc) sin(angle); pol 1 keeps E in
-     the x-y plane (B along z), pol 2 has E along z. */
+     the x-y plane (B along z), pol 2 has E along z.
+     n_env > 0 replaces sin^2(pi t'/t_env) by the spline envelope
+     sum_{k < n_env} env[k] N3(t'/h - k), h = t_env / (n_env + 3), with N3 the
+     cardinal cubic B-spline supported on [0, 4]. */
   double a0, omega, t_env, waist, yc, zc, phase, t_delay, angle;
+  int32_t n_env, reserved2;
+  double env[OR_MAX_ENV];
 } or_config;
 
 typedef struct {

@@ -30,6 +30,7 @@ class _Config(C.Structure):
         ("a0", C.c_double), ("omega", C.c_double), ("t_env", C.c_double),
         ("waist", C.c_double), ("yc", C.c_double), ("zc", C.c_double),
         ("phase", C.c_double), ("t_delay", C.c_double), ("angle", C.c_double),
+        ("n_env", C.c_int32), ("reserved2", C.c_int32), ("env", C.c_double * 64),
     ]
 
 
@@ -135,6 +136,12 @@ class Oracle:
         cfg.waist, cfg.yc, cfg.zc = las.waist, las.yc, las.zc
         cfg.phase, cfg.t_delay = las.phase, las.t_delay
         cfg.angle = getattr(las, "angle", 0.0)
+        env = tuple(getattr(las, "env", ()) or ())
+        if len(env) > 64:
+            raise ValueError("oracle: at most 64 envelope coefficients")
+        cfg.n_env = len(env)
+        for k, v in enumerate(env):
+            cfg.env[k] = float(v)
         self.cfg = cfg
         self.grid = grid
         self.ndim = grid.ndim

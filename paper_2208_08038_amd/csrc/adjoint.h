@@ -1,0 +1,25 @@
+// adjoint.h -- launcher of the reverse-mode particle cycle (gradient run).
+#pragma once
+
+#include "pic_internal.h"
+
+namespace pic {
+
+// Particle arrays of one species as the adjoint kernel sees them: the
+// stored state at the start of a step (cell, offsets, delta, u1, u2, and
+// the species' per-particle omega_c and weight), or the adjoint of that
+// state (offsets, delta, u1, u2 only).
+template <typename Real>
+using AdjState = SpeciesDev<Real>;
+
+// Reverse the particle cycle of one step for one species (1D and 2D
+// grids): reads the stored state `st`, the fields f (E, B at the start of
+// the step, guards filled) and the adjoint current l.J; updates the
+// particle adjoint `lp` in place, adds the gather's transpose into l.E and
+// l.B, and adds d/d(omega_c) and d/d(friction rate) to dparam[0], dparam[1].
+template <typename Real>
+void launch_adjoint_push(const GridInfo& g, const FieldPtrs<Real>& f, const AdjState<Real>& st,
+                         const PushConst<Real>& c, const AdjState<Real>& lp,
+                         const FieldPtrs<Real>& l, double* dparam, hipStream_t stream);
+
+}  // namespace pic

@@ -1,0 +1,662 @@
+// adjoint.hip -- reverse-mode (adjoint) particle cycle of the gradient run,
+// 1D and 2D grids, two-body ions and point particles.
+//
+// One thread per macro-particle.  The thread recomputes the forward cycle
+// of its particle from the stored state at the start of the step (the
+// same arithmetic as the forward kernels: quadratic B-spline gather,
+// softened bond force, time-centred friction, relativistic Boris push of
+// each body, move, walls, Esirkepov deposit; Sec. 2 and Sec. 3.1) and then
+// applies its transpose:
+//   * the deposit's adjoint reads the adjoint current lJ on the deposit
+//     window and yields derivatives with respect to the old and new body
+//     positions (through the B-spline weights and their derivatives) and
+//     to the out-of-plane velocity;
+//   * move, Lorentz factor, Boris rotation, friction and kicks are
+//     differentiated in reverse order;
+//   * the gather's adjoint scatters lambda_E, lambda_B of each body onto the
+//     nodes with the gather weights (atomics into lE, lB) and adds the
+//     position derivative of the interpolant.
+// The particle's adjoint state (offsets, delta, u1, u2) is updated in
+// place; the derivatives with respect to omega_c and the friction rate are
+// reduced per block and added to two FP64 accumulators.
+#include "adjoint.h"
+
+namespace pic {
+
+namespace {
+
+// Quadratic B-spline weights and their derivatives with respect to the
+// position at the nearest node n = floor(x + 1/2) (integer stagger) or
+// n = floor(x) (half stagger, node i at i + 1/2): nodes n-1, n, n+1.
+template <typename Real>
+struct Shape {
+  int i0;  // first node relative to the cell
+  Real w[3], dw[3];
+};
+
+template <typename Real>
+__device__ __forceinline__ Shape<Real> shape_at(Real x, bool half) {
+  Shape<Real> s;
+  const Real f = half ? floor(x) : floor(x + Real(0.5));
+  const Real d = half ? x - f - Real(0.5) : x - f;
+  const Real a = Real(0.5) - d, b = Real(0.5) + d;
+  s.i0 = static_cast<int>(f) - 1;
+  s.w[0] = Real(0.5) * a * a;
+  s.w[1] = Real(0.75) - d * d;
+  s.w[2] = Real(0.5) * b * b;
+  s.dw[0] = -a;
+  s.dw[1] = Real(-2) * d;
+  s.dw[2] = b;
+  return s;
+}
+
+template <typename Real>
+__device__ __forceinline__ Shape<Real> unit_shape() {
+  Shape<Real> s;
+  s.i0 = 0;
+  s.w[0] = Real(1);
+  s.w[1] = s.w[2] = Real(0);
+  s.dw[0] = s.dw[1] = s.dw[2] = Real(0);
+  return s;
+}
+
+// Interpolant of one field component and its gradient (cell units).
+template <typename Real, int ND>
+__device__ __forceinline__ Real interp_grad(const Real* __restrict__ F, int64_t base, int64_t sy,
+                                            const Shape<Real>& sx, const Shape<Real>& syy,
+                                            Real grad[2]) {
+  Real v = 0, gx = 0, gy = 0;
+  const int ny = ND > 1 ? 3 : 1;
+  for (int s = 0; s < ny; s++) {
+    const Real* row = F + base + sx.i0 + (ND > 1 ? (int64_t)(syy.i0 + s) * sy : 0);
+    const Real r0 = row[0], r1 = row[1], r2 = row[2];
+    const Real rv = sx.w[0] * r0 + sx.w[1] * r1 + sx.w[2] * r2;
+    const Real rd = sx.dw[0] * r0 + sx.dw[1] * r1 + sx.dw[2] * r2;
+    const Real wy = ND > 1 ? syy.w[s] : Real(1);
+    const Real dy = ND > 1 ? syy.dw[s] : Real(0);
+    v += wy * rv;
+    gx += wy * rd;
+    gy += dy * rv;
+  }
+  grad[0] = gx;
+  grad[1] = gy;
+  return v;
+}
+
+// Transpose of the interpolation: F(node) += lam * weight(node).
+template <typename Real, int ND>
+__device__ __forceinline__ void scatter(Real* F, int64_t base, int64_t sy, const Shape<Real>& sx,
+                                        const Shape<Real>& syy, Real lam) {
+  if (lam == Real(0)) return;
+  const int ny = ND > 1 ? 3 : 1;
+  for (int s = 0; s < ny; s++) {
+    Real* row = F + base + sx.i0 + (ND > 1 ? (int64_t)(syy.i0 + s) * sy : 0);
+    const Real wy = ND > 1 ? syy.w[s] : Real(1);
+#pragma unroll
+    for (int r = 0; r < 3; r++) unsafeAtomicAdd(row + r, lam * wy * sx.w[r]);
+  }
+}
+
+// Field values and position gradients of E and B at one body position x
+// (cell units relative to the cell at `base`).
+template <typename Real, int ND>
+struct Probe {
+  Shape<Real> n[2], h[2];  // integer / half stagger per resolved dim
+  Real E[3], B[3], gE[3][2], gB[3][2];
+};
+
+template <typename Real, int ND>
+__device__ __forceinline__ void probe_fields(const FieldPtrs<Real>& f, int64_t base, int64_t sy,
+                                             const Real x[3], Probe<Real, ND>& p) {
+  for (int d = 0; d < 2; d++) {
+    if (d < ND) {
+      p.n[d] = shape_at(x[d], false);
+      p.h[d] = shape_at(x[d], true);
+    } else {
+      p.n[d] = p.h[d] = unit_shape<Real>();
+    }
+  }
+  // E_a half-staggered along a; B_a along the other axes (z unresolved)
+  p.E[0] = interp_grad<Real, ND>(f.E[0], base, sy, p.h[0], p.n[1], p.gE[0]);
+  p.E[1] = interp_grad<Real, ND>(f.E[1], base, sy, p.n[0], p.h[1], p.gE[1]);
+  p.E[2] = interp_grad<Real, ND>(f.E[2], base, sy, p.n[0], p.n[1], p.gE[2]);
+  p.B[0] = interp_grad<Real, ND>(f.B[0], base, sy, p.n[0], p.h[1], p.gB[0]);
+  p.B[1] = interp_grad<Real, ND>(f.B[1], base, sy, p.h[0], p.n[1], p.gB[1]);
+  p.B[2] = interp_grad<Real, ND>(f.B[2], base, sy, p.h[0], p.h[1], p.gB[2]);
+}
+
+// Scatter lambda_E, lambda_B of one body and return d/dx of the
+// interpolated fields contracted with them.
+template <typename Real, int ND>
+__device__ __forceinline__ void gather_adjoint(const FieldPtrs<Real>& l, int64_t base, int64_t sy,
+                                               const Probe<Real, ND>& p, const Real lE[3],
+                                               const Real lB[3], Real lx[2]) {
+  scatter<Real, ND>(l.E[0], base, sy, p.h[0], p.n[1], lE[0]);
+  scatter<Real, ND>(l.E[1], base, sy, p.n[0], p.h[1], lE[1]);
+  scatter<Real, ND>(l.E[2], base, sy, p.n[0], p.n[1], lE[2]);
+  scatter<Real, ND>(l.B[0], base, sy, p.n[0], p.h[1], lB[0]);
+  scatter<Real, ND>(l.B[1], base, sy, p.h[0], p.n[1], lB[1]);
+  scatter<Real, ND>(l.B[2], base, sy, p.h[0], p.h[1], lB[2]);
+  for (int d = 0; d < ND; d++) {
+    Real s = 0;
+    for (int a = 0; a < 3; a++) s += lE[a] * p.gE[a][d] + lB[a] * p.gB[a][d];
+    lx[d] = s;
+  }
+}
+
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+
+template <typename Real>
+__device__ __forceinline__ void cross(const Real a[3], const Real b[3], Real c[3]) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// Boris rotation and second half kick: out = um + (um + um x t) x s + a E,
+// t = a B / gamma(um), s = 2 t / (1 + t^2).  Reverse mode: given lout,
+// adds to lum, lE, lB.
+template <typename Real>
+__device__ __forceinline__ void boris_forward(const Real um[3], Real a, const Real E[3],
+                                              const Real B[3], Real out[3]) {
+  const Real g = rsq(Real(1) + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
+  const Real k = a * g;
+  Real t[3] = {k * B[0], k * B[1], k * B[2]};
+  const Real sk = Real(2) * rcp(Real(1) + t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+  Real s[3] = {sk * t[0], sk * t[1], sk * t[2]};
+  Real c[3], w[3], ws[3];
+  cross(um, t, c);
+  for (int q = 0; q < 3; q++) w[q] = um[q] + c[q];
+  cross(w, s, ws);
+  for (int q = 0; q < 3; q++) out[q] = um[q] + ws[q] + a * E[q];
+}
+
+template <typename Real>
+__device__ __forceinline__ void boris_adjoint(const Real um[3], Real a, const Real B[3],
+                                              const Real lout[3], Real lum[3], Real lE[3],
+                                              Real lB[3]) {
+  const Real g = rsq(Real(1) + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
+  const Real k = a * g;
+  Real t[3] = {k * B[0], k * B[1], k * B[2]};
+  const Real sk = Real(2) * rcp(Real(1) + t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+  Real s[3] = {sk * t[0], sk * t[1], sk * t[2]};
+  Real c[3], w[3];
+  cross(um, t, c);
+  for (int q = 0; q < 3; q++) w[q] = um[q] + c[q];
+  // out = um + w x s + a E
+  Real lw[3], ls[3], lt[3], tmp[3];
+  cross(s, lout, lw);   // lambda . (w x s) = w . (s x lambda)
+  cross(lout, w, ls);   //                 = s . (lambda x w)
+  for (int q = 0; q < 3; q++) {
+    lum[q] += lout[q] + lw[q];
+    lE[q] += a * lout[q];
+  }
+  // w = um + um x t
+  cross(t, lw, tmp);
+  for (int q = 0; q < 3; q++) lum[q] += tmp[q];
+  cross(lw, um, lt);
+  // s = sk t, sk = 2 / (1 + t.t)
+  const Real lsk = t[0] * ls[0] + t[1] * ls[1] + t[2] * ls[2];
+  const Real ltt = -Real(0.5) * sk * sk * lsk;
+  for (int q = 0; q < 3; q++) lt[q] += sk * ls[q] + Real(2) * t[q] * ltt;
+  // t = a g B
+  Real lk = 0;
+  for (int q = 0; q < 3; q++) {
+    lB[q] += k * lt[q];
+    lk += B[q] * lt[q];
+  }
+  const Real lg = a * lk;
+  const Real g3 = g * g * g;
+  for (int q = 0; q < 3; q++) lum[q] -= g3 * um[q] * lg;
+}
+
+// v = n / sqrt(1 + n^2): lambda_n += g lv - g^3 n (n . lv)
+template <typename Real>
+__device__ __forceinline__ void velocity_adjoint(const Real n[3], const Real lv[3], Real ln[3]) {
+  const Real g = rsq(Real(1) + n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+  const Real nl = n[0] * lv[0] + n[1] * lv[1] + n[2] * lv[2];
+  const Real g3 = g * g * g;
+  for (int q = 0; q < 3; q++) ln[q] += g * lv[q] - g3 * n[q] * nl;
+}
+
+// Shapes of one body on the four-node deposit window of one dimension:
+// old (S0) and new (S1) weights and their position derivatives.
+template <typename Real>
+struct Win4 {
+  int lo;
+  Real S0[4], S1[4], D0[4], D1[4];
+};
+
+template <typename Real>
+__device__ __forceinline__ bool win4(Real x0, Real x1, Win4<Real>& w) {
+  const Shape<Real> a = shape_at(x0, false), b = shape_at(x1, false);
+  const int lo = min(a.i0, b.i0);
+  const int sa = a.i0 - lo, sb = b.i0 - lo;
+  if (sa > 1 || sb > 1) return false;
+  w.lo = lo;
+  for (int r = 0; r < 4; r++) {
+    const int ra = r - sa, rb = r - sb;
+    w.S0[r] = (ra >= 0 && ra < 3) ? a.w[ra] : Real(0);
+    w.D0[r] = (ra >= 0 && ra < 3) ? a.dw[ra] : Real(0);
+    w.S1[r] = (rb >= 0 && rb < 3) ? b.w[rb] : Real(0);
+    w.D1[r] = (rb >= 0 && rb < 3) ? b.dw[rb] : Real(0);
+  }
+  return true;
+}
+
+// Adjoint of the Esirkepov deposit of one body (charge Q, from x0 to x1,
+// velocity v for the out-of-plane components): with lJ the adjoint current,
+// Phi = sum lJ . J; returns dPhi/dx0, dPhi/dx1 (resolved dims) and
+// dPhi/dv (unresolved components).  The running sum along an axis turns
+// into a suffix sum of lJ.
+template <typename Real, int ND>
+__device__ __forceinline__ bool deposit_adjoint(const FieldPtrs<Real>& l, int64_t base, int64_t sy,
+                                                const Real x0[3], const Real x1[3], Real Q,
+                                                const Real v[3], const PushConst<Real>& c,
+                                                Real g0[2], Real g1[2], Real gv[3]) {
+  const Real third = Real(1) / Real(3), sixth = Real(1) / Real(6);
+  g0[0] = g0[1] = g1[0] = g1[1] = Real(0);
+  gv[0] = gv[1] = gv[2] = Real(0);
+  if constexpr (ND == 1) {
+    Win4<Real> wx;
+    if (!win4(x0[0], x1[0], wx)) return false;
+    const int64_t o = base + wx.lo;
+    const Real fx = Q * c.jf[0], fv = Q * c.inv_dv;
+    // J_x(r) = fx C(r), r < 3; J_y,z(r) = fv v_{y,z} (S0 + S1)(r) / 2
+    Real L[4];
+    L[3] = Real(0);
+    Real acc = 0;
+    for (int r = 2; r >= 0; r--) {
+      acc += l.J[0][o + r];
+      L[r] = acc;
+    }
+    for (int r = 0; r < 4; r++) {
+      const Real ly = l.J[1][o + r], lz = l.J[2][o + r];
+      const Real A = Real(0.5) * (wx.S0[r] + wx.S1[r]);
+      gv[1] += fv * ly * A;
+      gv[2] += fv * lz * A;
+      const Real t = Real(0.5) * fv * (v[1] * ly + v[2] * lz);
+      const Real dS1 = fx * L[r] + t, dS0 = -fx * L[r] + t;
+      g0[0] += dS0 * wx.D0[r];
+      g1[0] += dS1 * wx.D1[r];
+    }
+    return true;
+  } else {
+    Win4<Real> wx, wy;
+    if (!win4(x0[0], x1[0], wx) || !win4(x0[1], x1[1], wy)) return false;
+    const int64_t o = base + wx.lo + (int64_t)wy.lo * sy;
+    const Real fx = Q * c.jf[0], fy = Q * c.jf[1], fz = Q * v[2] * c.inv_dv;
+    Real G0x[4] = {0, 0, 0, 0}, G1x[4] = {0, 0, 0, 0}, G0y[4] = {0, 0, 0, 0},
+         G1y[4] = {0, 0, 0, 0};
+    Real Ax[4], Ay[4], DSx[4], DSy[4];
+    for (int r = 0; r < 4; r++) {
+      Ax[r] = Real(0.5) * (wx.S0[r] + wx.S1[r]);
+      Ay[r] = Real(0.5) * (wy.S0[r] + wy.S1[r]);
+      DSx[r] = wx.S1[r] - wx.S0[r];
+      DSy[r] = wy.S1[r] - wy.S0[r];
+    }
+    // J_x(r, s) = fx Cx(r) Ay(s), r < 3: Lx(r, s) suffix sums along x
+    for (int s = 0; s < 4; s++) {
+      Real acc = 0, Lx[4];
+      Lx[3] = Real(0);
+      for (int r = 2; r >= 0; r--) {
+        acc += l.J[0][o + r + s * sy];
+        Lx[r] = acc;
+      }
+      Real sumDL = 0;
+      for (int r = 0; r < 4; r++) {
+        const Real t = fx * Ay[s] * Lx[r];
+        G1x[r] += t;
+        G0x[r] -= t;
+        sumDL += DSx[r] * Lx[r];
+      }
+      G0y[s] += Real(0.5) * fx * sumDL;
+      G1y[s] += Real(0.5) * fx * sumDL;
+    }
+    // J_y(r, s) = fy Cy(s) Ax(r), s < 3: Ly(r, s) suffix sums along y
+    for (int r = 0; r < 4; r++) {
+      Real acc = 0, Ly[4];
+      Ly[3] = Real(0);
+      for (int s = 2; s >= 0; s--) {
+        acc += l.J[1][o + r + s * sy];
+        Ly[s] = acc;
+      }
+      Real sumDL = 0;
+      for (int s = 0; s < 4; s++) {
+        const Real t = fy * Ax[r] * Ly[s];
+        G1y[s] += t;
+        G0y[s] -= t;
+        sumDL += DSy[s] * Ly[s];
+      }
+      G0x[r] += Real(0.5) * fy * sumDL;
+      G1x[r] += Real(0.5) * fy * sumDL;
+    }
+    // J_z(r, s) = fz W(r, s), W = S0x S0y/3 + S0x S1y/6 + S1x S0y/6 + S1x S1y/3
+    for (int s = 0; s < 4; s++)
+      for (int r = 0; r < 4; r++) {
+        const Real lz = l.J[2][o + r + s * sy];
+        if (lz == Real(0)) continue;
+        const Real W = third * wx.S0[r] * wy.S0[s] + sixth * wx.S0[r] * wy.S1[s] +
+                       sixth * wx.S1[r] * wy.S0[s] + third * wx.S1[r] * wy.S1[s];
+        gv[2] += Q * c.inv_dv * lz * W;
+        const Real t = fz * lz;
+        G0x[r] += t * (third * wy.S0[s] + sixth * wy.S1[s]);
+        G1x[r] += t * (sixth * wy.S0[s] + third * wy.S1[s]);
+        G0y[s] += t * (third * wx.S0[r] + sixth * wx.S1[r]);
+        G1y[s] += t * (sixth * wx.S0[r] + third * wx.S1[r]);
+      }
+    for (int r = 0; r < 4; r++) {
+      g0[0] += G0x[r] * wx.D0[r];
+      g1[0] += G1x[r] * wx.D1[r];
+      g0[1] += G0y[r] * wy.D0[r];
+      g1[1] += G1y[r] * wy.D1[r];
+    }
+    return true;
+  }
+}
+
+// Wall reflection as in the forward cycle; returns true if it reflected.
+template <typename Real>
+__device__ __forceinline__ bool reflect_wall(int periodic, int ci, int n, int pad, Real& off) {
+  if (periodic) return false;
+  const int wl = pad, wr = n - pad;
+  if (ci == wl && off < Real(0)) {
+    off = -off;
+    return true;
+  }
+  if (ci == wr - 1 && off > Real(1)) {
+    off = Real(2) - off;
+    return true;
+  }
+  if (ci == wr && off > Real(0)) {
+    off = -off;
+    return true;
+  }
+  return false;
+}
+
+template <typename Real>
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); w++) t += sh[w];
+  __syncthreads();
+  return t;
+}
+
+template <typename Real, int ND, bool TWO>
+__global__ void __launch_bounds__(256)
+    k_adjoint_push(GridInfo g, FieldPtrs<Real> f, AdjState<Real> st, PushConst<Real> c,
+                   AdjState<Real> lp, FieldPtrs<Real> l, double* dparam) {
+  __shared__ double sh[4];
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double d_wc = 0.0, d_nu = 0.0;
+  if (p < st.n) {
+    do {
+      // ---- stored state at the start of the step
+      int ci[3] = {0, 0, 0};
+      const uint32_t pk = st.cell[p];
+      ci[0] = pk & ((1u << g.bits[0]) - 1u);
+      if (ND > 1) ci[1] = (pk >> g.bits[0]) & ((1u << g.bits[1]) - 1u);
+      Real off[3] = {0, 0, 0}, u1[3], u2[3] = {0, 0, 0}, dl[3] = {0, 0, 0};
+      for (int d = 0; d < ND; d++) off[d] = st.off[d][p];
+      for (int q = 0; q < 3; q++) {
+        u1[q] = st.u1[q][p];
+        if (TWO) {
+          u2[q] = st.u2[q][p];
+          dl[q] = st.dl[q][p];
+        }
+      }
+      const Real wc = TWO ? (st.wc ? st.wc[p] : c.omega_c) : Real(0);
+      const Real W = st.w ? st.w[p] : Real(1);
+      bool ok = true;
+      Real x1[3] = {0, 0, 0}, x2[3] = {0, 0, 0};
+      for (int d = 0; d < ND; d++) {
+        ok = ok && isfinite(off[d]) && off[d] >= Real(0) && off[d] <= Real(1);
+        const Real sd = dl[d] * c.idx[d];
+        if (TWO) ok = ok && fabs(sd) < Real(0.5);
+        x1[d] = off[d] + (TWO ? c.f1 * sd : Real(0));
+        x2[d] = off[d] - (TWO ? c.f2 * sd : Real(0));
+      }
+      for (int q = 0; q < 3; q++) ok = ok && isfinite(u1[q]) && isfinite(u2[q]) && isfinite(dl[q]);
+      if (!ok) break;  // the forward cycle left it unchanged: identity
+      const int64_t base = g.origin + ci[0] + (ND > 1 ? (int64_t)ci[1] * g.sy : 0);
+
+      // ---- forward recomputation
+      Probe<Real, ND> P1, P2;
+      probe_fields<Real, ND>(f, base, g.sy, x1, P1);
+      if (TWO) probe_fields<Real, ND>(f, base, g.sy, x2, P2);
+      Real E1[3], E2[3] = {0, 0, 0}, um1[3], um2[3] = {0, 0, 0};
+      Real r2 = 0, rq = 1, soft = 1, kf = 0;
+      if (TWO) {
+        r2 = dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2];
+        if (c.inv_ac2 != Real(0)) {
+          rq = rsq(Real(1) + r2 * c.inv_ac2);
+          soft = rq * rq * rq;
+        }
+        kf = -c.mr * wc * wc * soft;
+      }
+      for (int q = 0; q < 3; q++) {
+        const Real F = kf * dl[q];
+        E1[q] = P1.E[q] + (TWO ? F * c.inv_q1 : Real(0));
+        um1[q] = u1[q] + c.a1 * E1[q];
+        if (TWO) {
+          E2[q] = P2.E[q] - F * c.inv_q2;
+          um2[q] = u2[q] + c.a2 * E2[q];
+        }
+      }
+      // friction on the relative momentum (identity when nu = 0)
+      const Real nu = TWO ? c.nu + c.nu_per_omega * wc : Real(0);
+      const Real Dn = (Real(1) - nu * c.half_dt) * rcp(Real(1) + nu * c.half_dt);
+      Real vm1[3], vm2[3] = {0, 0, 0};
+      for (int q = 0; q < 3; q++) {
+        if (TWO) {
+          const Real V = (c.m1 * um1[q] + c.m2 * um2[q]) * c.inv_mc;
+          const Real w = (um1[q] - um2[q]) * Dn;
+          vm1[q] = V + c.f1 * w;
+          vm2[q] = V - c.f2 * w;
+        } else {
+          vm1[q] = um1[q];
+        }
+      }
+      Real n1[3], n2[3] = {0, 0, 0}, v1[3], v2[3] = {0, 0, 0};
+      boris_forward(vm1, c.a1, E1, P1.B, n1);
+      if (TWO) boris_forward(vm2, c.a2, E2, P2.B, n2);
+      {
+        const Real i1 = rsq(Real(1) + n1[0] * n1[0] + n1[1] * n1[1] + n1[2] * n1[2]);
+        const Real i2 = rsq(Real(1) + n2[0] * n2[0] + n2[1] * n2[1] + n2[2] * n2[2]);
+        for (int q = 0; q < 3; q++) {
+          v1[q] = n1[q] * i1;
+          v2[q] = n2[q] * i2;
+        }
+      }
+      Real dln[3], offn[3] = {0, 0, 0};
+      for (int q = 0; q < 3; q++) dln[q] = TWO ? dl[q] + c.dt * (v1[q] - v2[q]) : Real(0);
+      bool refl[3] = {false, false, false};
+      for (int d = 0; d < ND; d++) {
+        const Real vc = TWO ? (c.m1 * v1[d] + c.m2 * v2[d]) * c.inv_mc : v1[d];
+        offn[d] = off[d] + c.dt * vc * c.idx[d];
+        refl[d] = reflect_wall(g.periodic[d], ci[d], g.n[d], g.pad, offn[d]);
+        if (refl[d]) dln[d] = -dln[d];
+      }
+      Real y1[3] = {0, 0, 0}, y2[3] = {0, 0, 0};
+      for (int d = 0; d < ND; d++) {
+        const Real sd = dln[d] * c.idx[d];
+        y1[d] = offn[d] + (TWO ? c.f1 * sd : Real(0));
+        y2[d] = offn[d] - (TWO ? c.f2 * sd : Real(0));
+      }
+
+      // ---- reverse
+      Real l_off[3] = {0, 0, 0}, l_dl[3] = {0, 0, 0}, l_u1[3] = {0, 0, 0}, l_u2[3] = {0, 0, 0};
+      Real l_offn[3] = {0, 0, 0}, l_dln[3] = {0, 0, 0}, l_n1[3], l_n2[3] = {0, 0, 0};
+      for (int d = 0; d < ND; d++) l_offn[d] = lp.off[d][p];
+      for (int q = 0; q < 3; q++) {
+        l_n1[q] = lp.u1[q][p];
+        if (TWO) {
+          l_n2[q] = lp.u2[q][p];
+          l_dln[q] = lp.dl[q][p];
+        }
+      }
+      Real l_v1[3] = {0, 0, 0}, l_v2[3] = {0, 0, 0};
+      if (c.deposit) {
+        const Real Q1 = st.w ? c.q1 * W : c.qw1;
+        Real g0[2], g1[2], gv[3];
+        if (deposit_adjoint<Real, ND>(l, base, g.sy, x1, y1, Q1, v1, c, g0, g1, gv)) {
+          for (int d = 0; d < ND; d++) {
+            l_offn[d] += g1[d];
+            l_off[d] += g0[d];
+            if (TWO) {
+              l_dln[d] += c.f1 * c.idx[d] * g1[d];
+              l_dl[d] += c.f1 * c.idx[d] * g0[d];
+            }
+          }
+          for (int q = ND; q < 3; q++) l_v1[q] += gv[q];
+        }
+        if (TWO) {
+          const Real Q2 = st.w ? c.q2 * W : c.qw2;
+          if (deposit_adjoint<Real, ND>(l, base, g.sy, x2, y2, Q2, v2, c, g0, g1, gv)) {
+            for (int d = 0; d < ND; d++) {
+              l_offn[d] += g1[d];
+              l_off[d] += g0[d];
+              l_dln[d] -= c.f2 * c.idx[d] * g1[d];
+              l_dl[d] -= c.f2 * c.idx[d] * g0[d];
+            }
+            for (int q = ND; q < 3; q++) l_v2[q] += gv[q];
+          }
+        }
+      }
+      // walls: the reflected components change sign
+      for (int d = 0; d < ND; d++)
+        if (refl[d]) {
+          l_offn[d] = -l_offn[d];
+          l_dln[d] = -l_dln[d];
+          l_n1[d] = -l_n1[d];
+          l_n2[d] = -l_n2[d];
+        }
+      // move
+      for (int d = 0; d < ND; d++) {
+        l_off[d] += l_offn[d];
+        const Real k = c.dt * c.idx[d] * l_offn[d];
+        if (TWO) {
+          l_v1[d] += k * c.m1 * c.inv_mc;
+          l_v2[d] += k * c.m2 * c.inv_mc;
+        } else {
+          l_v1[d] += k;
+        }
+      }
+      if (TWO)
+        for (int q = 0; q < 3; q++) {
+          l_dl[q] += l_dln[q];
+          l_v1[q] += c.dt * l_dln[q];
+          l_v2[q] -= c.dt * l_dln[q];
+        }
+      velocity_adjoint(n1, l_v1, l_n1);
+      if (TWO) velocity_adjoint(n2, l_v2, l_n2);
+      // Boris
+      Real l_vm1[3] = {0, 0, 0}, l_vm2[3] = {0, 0, 0};
+      Real l_E1[3] = {0, 0, 0}, l_E2[3] = {0, 0, 0}, l_B1[3] = {0, 0, 0}, l_B2[3] = {0, 0, 0};
+      boris_adjoint(vm1, c.a1, P1.B, l_n1, l_vm1, l_E1, l_B1);
+      if (TWO) boris_adjoint(vm2, c.a2, P2.B, l_n2, l_vm2, l_E2, l_B2);
+      // friction
+      Real l_um1[3], l_um2[3] = {0, 0, 0};
+      if (TWO) {
+        const Real dD = Real(-2) * c.half_dt * rcp((Real(1) + nu * c.half_dt) *
+                                                   (Real(1) + nu * c.half_dt));
+        for (int q = 0; q < 3; q++) {
+          const Real lV = l_vm1[q] + l_vm2[q];
+          const Real lw = c.f1 * l_vm1[q] - c.f2 * l_vm2[q];
+          l_um1[q] = c.m1 * c.inv_mc * lV + Dn * lw;
+          l_um2[q] = c.m2 * c.inv_mc * lV - Dn * lw;
+          d_nu += (double)(lw * (um1[q] - um2[q]) * dD);
+        }
+      } else {
+        for (int q = 0; q < 3; q++) l_um1[q] = l_vm1[q];
+      }
+      // half kicks
+      for (int q = 0; q < 3; q++) {
+        l_u1[q] += l_um1[q];
+        l_E1[q] += c.a1 * l_um1[q];
+        if (TWO) {
+          l_u2[q] += l_um2[q];
+          l_E2[q] += c.a2 * l_um2[q];
+        }
+      }
+      // bond force: E1 = E(x1) + F / q1, E2 = E(x2) - F / q2, F = kf delta
+      if (TWO) {
+        Real lkf = 0;
+        for (int q = 0; q < 3; q++) {
+          const Real lF = c.inv_q1 * l_E1[q] - c.inv_q2 * l_E2[q];
+          l_dl[q] += kf * lF;
+          lkf += lF * dl[q];
+        }
+        d_wc += (double)(lkf * Real(-2) * c.mr * wc * soft);
+        if (c.inv_ac2 != Real(0)) {
+          // soft = (1 + r2 / a_c^2)^{-3/2}
+          const Real lsoft = lkf * (-c.mr * wc * wc);
+          const Real dsoft = Real(-1.5) * c.inv_ac2 * rq * rq * rq * rq * rq;
+          for (int q = 0; q < 3; q++) l_dl[q] += Real(2) * dl[q] * lsoft * dsoft;
+        }
+      }
+      // gather
+      Real lx1[2] = {0, 0}, lx2[2] = {0, 0};
+      gather_adjoint<Real, ND>(l, base, g.sy, P1, l_E1, l_B1, lx1);
+      if (TWO) gather_adjoint<Real, ND>(l, base, g.sy, P2, l_E2, l_B2, lx2);
+      for (int d = 0; d < ND; d++) {
+        l_off[d] += lx1[d] + lx2[d];
+        if (TWO) l_dl[d] += c.idx[d] * (c.f1 * lx1[d] - c.f2 * lx2[d]);
+      }
+      // adjoint state at the start of the step
+      for (int d = 0; d < ND; d++) lp.off[d][p] = l_off[d];
+      for (int q = 0; q < 3; q++) {
+        lp.u1[q][p] = l_u1[q];
+        if (TWO) {
+          lp.u2[q][p] = l_u2[q];
+          lp.dl[q][p] = l_dl[q];
+        }
+      }
+    } while (false);
+  }
+  const double s_wc = block_sum<Real>(d_wc, sh);
+  const double s_nu = block_sum<Real>(d_nu, sh);
+  if (threadIdx.x == 0) {
+    if (s_wc != 0.0) atomicAdd(&dparam[0], s_wc);
+    if (s_nu != 0.0) atomicAdd(&dparam[1], s_nu);
+  }
+}
+
+}  // namespace
+
+template <typename Real>
+void launch_adjoint_push(const GridInfo& g, const FieldPtrs<Real>& f, const AdjState<Real>& st,
+                         const PushConst<Real>& c, const AdjState<Real>& lp,
+                         const FieldPtrs<Real>& l, double* dparam, hipStream_t stream) {
+  if (st.n <= 0) return;
+  dim3 grid((unsigned)((st.n + 255) / 256));
+  const bool two = c.two_body != 0;
+  if (g.nd == 1 && two)
+    hipLaunchKernelGGL((k_adjoint_push<Real, 1, true>), grid, 256, 0, stream, g, f, st, c, lp, l, dparam);
+  if (g.nd == 1 && !two)
+    hipLaunchKernelGGL((k_adjoint_push<Real, 1, false>), grid, 256, 0, stream, g, f, st, c, lp, l, dparam);
+  if (g.nd == 2 && two)
+    hipLaunchKernelGGL((k_adjoint_push<Real, 2, true>), grid, 256, 0, stream, g, f, st, c, lp, l, dparam);
+  if (g.nd == 2 && !two)
+    hipLaunchKernelGGL((k_adjoint_push<Real, 2, false>), grid, 256, 0, stream, g, f, st, c, lp, l, dparam);
+}
+
+template void launch_adjoint_push<float>(const GridInfo&, const FieldPtrs<float>&,
+                                         const AdjState<float>&, const PushConst<float>&,
+                                         const AdjState<float>&, const FieldPtrs<float>&, double*,
+                                         hipStream_t);
+template void launch_adjoint_push<double>(const GridInfo&, const FieldPtrs<double>&,
+                                          const AdjState<double>&, const PushConst<double>&,
+                                          const AdjState<double>&, const FieldPtrs<double>&,
+                                          double*, hipStream_t);
+
+}  // namespace pic

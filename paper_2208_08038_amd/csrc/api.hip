@@ -13,91 +13,14 @@
 #include <string>
 #include <vector>
 
-#include "pic.h"
-#include "pic_internal.h"
-#include "sort.h"
+#include "ctx.h"
 #include "load.h"
-#include "tiled.h"
-
-using pic::GridInfo;
 
 namespace {
 
 thread_local std::string g_create_error;
 
-struct SpeciesHost {
-  pic_species_desc d{};
-  double a_c = 0.0;  // effective softening length (inf: harmonic)
-  int64_t n = 0, cap = 0;
-  bool has_wc = false, has_w = false;
-  double max_w = 0.0;  // largest |per-particle weight| loaded (has_w)
-  void* cell = nullptr;
-  void* off[3] = {nullptr, nullptr, nullptr};
-  void* dl[3] = {nullptr, nullptr, nullptr};
-  void* u1[3] = {nullptr, nullptr, nullptr};
-  void* u2[3] = {nullptr, nullptr, nullptr};
-  void* wc = nullptr;
-  void* w = nullptr;
-  pic::SortBuffers sort{};
-  int64_t* ids = nullptr;  // device load indices (TRACK_IDS)
-  uint32_t* outside = nullptr;  // particles listed as outside their tile (tiled kernel)
-  bool needs_sort = true;  // tile offsets stale (after a load)
-  // adaptive sort policy: particles advanced outside their tile since the
-  // species' last sort, and steps since then
-  double listed_since_sort = 0.0;
-  int64_t steps_since_sort = 0;
-};
-
-// Species slots of the per-step outside-tile counters (device nslow[2 + s]).
-constexpr int kMaxSpecies = 62;
-
 }  // namespace
-
-struct pic_ctx {
-  pic_config cfg{};
-  pic_allocator alloc{};
-  bool use_hip_malloc = true;
-  hipStream_t stream = nullptr;
-  GridInfo g{};
-  int prec = 64;
-  size_t rsize = 8;
-  void* fields = nullptr;  // 9 planes
-  void* mur_b[3][2] = {};
-  void* mur_e[3][2] = {};
-  uint32_t* err = nullptr;
-  uint32_t* load_err = nullptr;
-  uint32_t* nslow = nullptr;   // [0]: list length scratch, [2 + s]: species s listed this step
-  uint32_t* host_counts = nullptr;  // pinned: 2 slots of the per-species counts
-  hipEvent_t ev_counts[2] = {nullptr, nullptr};
-  int counts_pending = -1;          // slot whose copy is in flight, or -1
-  bool tiled = false;
-  pic::TileGeom tg{};
-  double* partials = nullptr;
-  double* dout = nullptr;  // 32 doubles: [0..3] scratch, [4..6] residual, ...
-  double* rho0 = nullptr;
-  double* rho1 = nullptr;
-  int nprobe = 0;
-  int* probe_comp = nullptr;
-  int64_t* probe_idx = nullptr;
-  void* probe_buf = nullptr;
-  int64_t probe_rec = 0;
-  std::vector<std::unique_ptr<SpeciesHost>> sp;
-  std::vector<void*> allocs;
-  int64_t step = 0;
-  int64_t steps_since_sort = 0;
-  int tile[3] = {1, 1, 1};
-  int ntiles[3] = {1, 1, 1};
-  int sort_every = 0;  // > 0: fixed cadence; 0: adaptive per species
-  std::string error;
-  bool residual_valid = false;
-  // timing
-  std::vector<hipEvent_t> ev;
-  std::vector<int> ev_species;  // species of each (start, stop) pair
-  size_t ev_used = 0;
-  int64_t launches = 0;
-};
-
-namespace {
 
 int fail(pic_ctx* c, int code, const std::string& msg) {
   if (c)
@@ -106,13 +29,6 @@ int fail(pic_ctx* c, int code, const std::string& msg) {
     g_create_error = msg;
   return code;
 }
-
-#define HIPCHK(ctx, expr)                                                           \
-  do {                                                                              \
-    hipError_t e_ = (expr);                                                         \
-    if (e_ != hipSuccess)                                                           \
-      return fail(ctx, PIC_EHIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
-  } while (0)
 
 void* dev_alloc(pic_ctx* c, size_t bytes) {
   if (bytes == 0) bytes = 256;
@@ -126,6 +42,8 @@ void* dev_alloc(pic_ctx* c, size_t bytes) {
   if (p) c->allocs.push_back(p);
   return p;
 }
+
+namespace {
 
 // pinned host buffer and events of the sort policy
 void release_host(pic_ctx* c) {
@@ -151,92 +69,6 @@ int ceil_log2(int64_t n) {
   int b = 0;
   while ((int64_t(1) << b) < n) b++;
   return b;
-}
-
-bool is_periodic(const pic_config& c, int d) {
-  return c.bc_lo[d] == PIC_BC_PERIODIC && c.bc_hi[d] == PIC_BC_PERIODIC;
-}
-
-template <typename Real>
-pic::FieldPtrs<Real> field_ptrs(pic_ctx* c) {
-  pic::FieldPtrs<Real> f;
-  Real* base = static_cast<Real*>(c->fields);
-  for (int a = 0; a < 3; a++) {
-    f.E[a] = base + (0 + a) * c->g.plane;
-    f.B[a] = base + (3 + a) * c->g.plane;
-    f.J[a] = base + (6 + a) * c->g.plane;
-  }
-  return f;
-}
-
-template <typename Real>
-pic::SpeciesDev<Real> species_dev(const SpeciesHost& s) {
-  pic::SpeciesDev<Real> d;
-  d.cell = static_cast<uint32_t*>(s.cell);
-  for (int a = 0; a < 3; a++) {
-    d.off[a] = static_cast<Real*>(s.off[a]);
-    d.dl[a] = static_cast<Real*>(s.dl[a]);
-    d.u1[a] = static_cast<Real*>(s.u1[a]);
-    d.u2[a] = static_cast<Real*>(s.u2[a]);
-  }
-  d.wc = s.has_wc ? static_cast<Real*>(s.wc) : nullptr;
-  d.w = s.has_w ? static_cast<Real*>(s.w) : nullptr;
-  d.n = s.n;
-  return d;
-}
-
-template <typename Real>
-pic::PushConst<Real> push_const(const pic_ctx* c, const SpeciesHost& s) {
-  pic::PushConst<Real> k{};
-  const pic_species_desc& d = s.d;
-  double dt = c->cfg.dt;
-  bool two = d.kind == PIC_TWO_BODY;
-  double m1 = d.m1, m2 = two ? d.m2 : 0.0, mc = m1 + m2;
-  k.dt = (Real)dt;
-  k.half_dt = (Real)(0.5 * dt);
-  double dv = 1.0;
-  for (int a = 0; a < 3; a++) {
-    k.idx[a] = a < c->g.nd ? (Real)(1.0 / c->cfg.dx[a]) : Real(0);
-    if (a < c->g.nd) dv *= c->cfg.dx[a];
-  }
-  k.a1 = (Real)(0.5 * dt * d.q1 / d.m1);
-  k.a2 = two ? (Real)(0.5 * dt * d.q2 / d.m2) : Real(0);
-  k.m1 = (Real)m1;
-  k.m2 = (Real)m2;
-  k.inv_mc = (Real)(1.0 / mc);
-  k.f1 = two ? (Real)(m2 / mc) : Real(0);
-  k.f2 = two ? (Real)(m1 / mc) : Real(1);
-  k.mr = two ? (Real)(m1 * m2 / mc) : Real(0);
-  k.inv_q1 = (Real)(1.0 / d.q1);
-  k.inv_q2 = two ? (Real)(1.0 / d.q2) : Real(0);
-  k.inv_ac2 = std::isinf(s.a_c) ? Real(0) : (Real)(1.0 / (s.a_c * s.a_c));
-  k.omega_c = (Real)d.omega_c;
-  k.nu = (Real)d.nu;
-  k.nu_per_omega = (Real)d.nu_per_omega;
-  k.qw1 = (Real)(d.q1 * d.weight);
-  k.qw2 = two ? (Real)(d.q2 * d.weight) : Real(0);
-  k.weight = (Real)d.weight;
-  k.q1 = (Real)d.q1;
-  k.q2 = two ? (Real)d.q2 : Real(0);
-  for (int a = 0; a < 3; a++) k.jf[a] = a < c->g.nd ? (Real)(-c->cfg.dx[a] / (dt * dv)) : Real(0);
-  k.inv_dv = (Real)(1.0 / dv);
-  // Bound on one deposit term: charge x prefactor x shape factors.  The
-  // running sum C of shape changes lies in [-1, 1]; the transverse factor
-  // S0 (S0 + DS/2) + DS (S0/2 + DS/3) is at most 1 + 1/2; out-of-plane terms
-  // carry |v| < c = 1 instead of C.  A merged pair adds both bodies.
-  {
-    const double wmax = s.has_w ? s.max_w : std::fabs(d.weight);
-    const double qsum = (std::fabs(d.q1) + (two ? std::fabs(d.q2) : 0.0)) * wmax;
-    double fmax = c->g.nd < 3 ? 1.0 / dv : 0.0;
-    for (int a = 0; a < c->g.nd; a++) fmax = std::max(fmax, c->cfg.dx[a] / (dt * dv));
-    const double bound = 1.5 * qsum * fmax;
-    int e = bound > 0.0 ? (int)std::floor(46.0 - std::log2(bound)) : 0;
-    e = std::max(-120, std::min(120, e));
-    k.jscale = (Real)std::ldexp(1.0, e);
-  }
-  k.two_body = two ? 1 : 0;
-  k.deposit = (c->cfg.flags & PIC_FLAG_NO_DEPOSIT) ? 0 : 1;
-  return k;
 }
 
 // Sec. 2 initial split: m1 u1 + m2 u2 = m_c u_c with q1 v1 + q2 v2 = 0.
@@ -481,123 +313,136 @@ void deposit_rho(pic_ctx* c, double* rho) {
   pic::launch_fold_periodic_f64(c->g, rho, c->stream);
 }
 
+// Tile sort of each species that needs one: always after a load; then on
+// a fixed cadence, or per species when the particles it advanced outside
+// their tile since its last sort reach kSortRatio of the species (the
+// outside-tile kernel costs about 1 / kSortRatio as much per particle as a
+// sort does; the rule spends on sorting what the detour cost, so stays
+// within twice the best cadence), or after kSortMaxSteps steps (keeps the
+// order of particles within tiles close to the interleaved load order).
+int sort_due(pic_ctx* c) {
+  constexpr double kSortRatio = 1.0 / 200.0;
+  constexpr int64_t kSortMaxSteps = 64;
+  if (c->sort_every == 0) harvest_counts(c);
+  const bool cadence = c->sort_every > 0 && c->steps_since_sort >= c->sort_every;
+  for (auto& s : c->sp) {
+    bool due = cadence || s->needs_sort;
+    if (c->sort_every == 0)
+      due = due || s->listed_since_sort >= kSortRatio * (double)s->n ||
+            s->steps_since_sort >= kSortMaxSteps;
+    if (!due) continue;
+    int rc = pic::sort_by_tile(c->g, c->tile, c->ntiles, s->sort, s->n, c->stream);
+    if (rc) return fail(c, PIC_EHIP, "tile sort launch failed");
+    s->needs_sort = false;
+    s->listed_since_sort = 0.0;
+    s->steps_since_sort = 0;
+  }
+  if (cadence) c->steps_since_sort = 0;
+  return PIC_OK;
+}
+
+}  // namespace
+
 template <typename Real>
-int step_t(pic_ctx* c, int nsteps) {
+int advance_one(pic_ctx* c, const pic::LaserDev& las, const StepOpts& o,
+                void (*save)(pic_ctx*, void*), void* save_arg) {
   const GridInfo& g = c->g;
   pic::FieldPtrs<Real> f = field_ptrs<Real>(c);
   Real* eb[6] = {f.E[0], f.E[1], f.E[2], f.B[0], f.B[1], f.B[2]};
   Real* jj[3] = {f.J[0], f.J[1], f.J[2]};
   const bool frozen = (c->cfg.flags & PIC_FLAG_FROZEN_FIELDS) != 0;
-  pic::LaserDev las{};
-  las.a0 = c->cfg.laser.a0;
-  las.omega = c->cfg.laser.omega;
-  las.t_env = c->cfg.laser.t_env;
-  las.waist = c->cfg.laser.waist;
-  las.yc = c->cfg.laser.yc;
-  las.zc = c->cfg.laser.zc;
-  las.phase = c->cfg.laser.phase;
-  las.t_delay = c->cfg.laser.t_delay;
-  las.pol = c->cfg.laser.pol;
-  las.on = (c->cfg.bc_lo[0] == PIC_BC_LASER && c->cfg.laser.a0 != 0.0) ? 1 : 0;
-  las.oblique = c->cfg.laser.angle != 0.0 ? 1 : 0;
-  las.cos_a = std::cos(c->cfg.laser.angle);
-  las.sin_a = std::sin(c->cfg.laser.angle);
+  const bool check = o.check;
+  pic::launch_fill_periodic<Real>(g, eb, 6, c->stream);
+  if (save) save(c, save_arg);
+  pic::launch_zero<Real>(f.J[0], 3 * g.plane, c->stream);
+  if (check) deposit_rho<Real>(c, c->rho0);
+  if (c->tiled) HIPCHK(c, hipMemsetAsync(c->nslow + 1, 0, 63 * sizeof(uint32_t), c->stream));
+  for (size_t si = 0; si < c->sp.size(); si++) {
+    auto& s = c->sp[si];
+    TimedDispatch td{c, (int)si, false};
+    if (c->tiled) {
+      pic::DispatchHook hook;
+      if (c->cfg.flags & PIC_FLAG_TIMING) hook = {&TimedDispatch::hook, &td};
+      hipError_t e = pic::launch_push_tiled<Real>(g, f, species_dev<Real>(*s),
+                                                  push_const<Real>(c, *s), c->tg,
+                                                  s->sort.tile_off, s->outside, c->nslow,
+                                                  c->nslow + 2 + si, c->err, c->stream, hook);
+      if (e != hipSuccess)
+        return fail(c, PIC_EHIP, std::string("tiled particle kernel: ") + hipGetErrorString(e));
+    } else {
+      TimedDispatch::hook(&td, true);
+      pic::launch_push<Real>(g, f, species_dev<Real>(*s), push_const<Real>(c, *s), c->err,
+                             c->stream);
+      TimedDispatch::hook(&td, false);
+    }
+    c->launches++;
+    s->steps_since_sort++;
+  }
+  // the step's outside-tile counts go to pinned host memory, read before
+  // the next step is enqueued
+  if (c->tiled && c->sort_every == 0 && !c->sp.empty()) {
+    const int slot = (int)(c->step & 1);
+    HIPCHK(c, hipMemcpyAsync(c->host_counts + 64 * slot, c->nslow + 2,
+                             c->sp.size() * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipEventRecord(c->ev_counts[slot], c->stream));
+    c->counts_pending = slot;
+  }
+  pic::launch_fold_periodic<Real>(g, jj, 3, c->stream);
+  if (check) {
+    deposit_rho<Real>(c, c->rho1);
+    pic::launch_residual<Real>(g, f, c->rho0, c->rho1, c->partials, pic::reduce_blocks(),
+                               c->dout + 4, c->stream);
+    c->residual_valid = true;
+  }
+  if (!frozen) {
+    pic::launch_b_half<Real>(g, f, c->stream);
+    pic::launch_fill_periodic<Real>(g, eb + 3, 3, c->stream);
+    for (int d = 0; d < g.nd; d++)
+      if (!g.periodic[d])
+        pic::launch_mur_low_b<Real>(g, f, d, static_cast<Real*>(c->mur_b[d][0]),
+                                    static_cast<Real*>(c->mur_b[d][1]), las, c->step,
+                                    c->stream);
+    for (int d = 0; d < g.nd; d++)
+      if (!g.periodic[d])
+        pic::launch_save_high_e<Real>(g, f, d, static_cast<Real*>(c->mur_e[d][0]),
+                                      static_cast<Real*>(c->mur_e[d][1]), c->stream);
+    pic::launch_e_full<Real>(g, f, c->stream);
+    pic::launch_fill_periodic<Real>(g, eb, 3, c->stream);
+    for (int d = 0; d < g.nd; d++)
+      if (!g.periodic[d])
+        pic::launch_mur_high_e<Real>(g, f, d, static_cast<Real*>(c->mur_e[d][0]),
+                                     static_cast<Real*>(c->mur_e[d][1]), c->stream);
+    pic::launch_b_half<Real>(g, f, c->stream);
+  }
+  c->step++;
+  c->steps_since_sort++;
+  if (o.record && c->nprobe > 0 && c->probe_rec < c->cfg.max_probe_steps) {
+    pic::launch_probes<Real>(g, f, c->nprobe, c->probe_comp, c->probe_idx,
+                             static_cast<Real*>(c->probe_buf), c->cfg.max_probe_steps,
+                             c->probe_rec, c->stream);
+    c->probe_rec++;
+  }
+  return PIC_OK;
+}
+
+template int advance_one<float>(pic_ctx*, const pic::LaserDev&, const StepOpts&,
+                                void (*)(pic_ctx*, void*), void*);
+template int advance_one<double>(pic_ctx*, const pic::LaserDev&, const StepOpts&,
+                                 void (*)(pic_ctx*, void*), void*);
+
+namespace {
+
+template <typename Real>
+int step_t(pic_ctx* c, int nsteps) {
+  const pic::LaserDev las = laser_dev(c);
   for (int it = 0; it < nsteps; it++) {
-    const bool check = (c->cfg.flags & PIC_FLAG_CHARGE_CHECK) && it == nsteps - 1;
-    // tile sort: always after a load; then on a fixed cadence, or per
-    // species when the particles it advanced outside their tile since its
-    // last sort reach kSortRatio of the species (the outside-tile kernel
-    // costs about 1 / kSortRatio as much per particle as a sort does; the
-    // rule spends on sorting what the detour cost, so stays within twice
-    // the best cadence), or after kSortMaxSteps steps (keeps the order of
-    // particles within tiles close to the interleaved load order)
-    constexpr double kSortRatio = 1.0 / 200.0;
-    constexpr int64_t kSortMaxSteps = 64;
-    if (c->sort_every == 0) harvest_counts(c);
-    const bool cadence = c->sort_every > 0 && c->steps_since_sort >= c->sort_every;
-    for (auto& s : c->sp) {
-      bool due = cadence || s->needs_sort;
-      if (c->sort_every == 0)
-        due = due || s->listed_since_sort >= kSortRatio * (double)s->n ||
-              s->steps_since_sort >= kSortMaxSteps;
-      if (!due) continue;
-      int rc = pic::sort_by_tile(g, c->tile, c->ntiles, s->sort, s->n, c->stream);
-      if (rc) return fail(c, PIC_EHIP, "tile sort launch failed");
-      s->needs_sort = false;
-      s->listed_since_sort = 0.0;
-      s->steps_since_sort = 0;
-    }
-    if (cadence) c->steps_since_sort = 0;
-    pic::launch_fill_periodic<Real>(g, eb, 6, c->stream);
-    pic::launch_zero<Real>(f.J[0], 3 * g.plane, c->stream);
-    if (check) deposit_rho<Real>(c, c->rho0);
-    if (c->tiled) HIPCHK(c, hipMemsetAsync(c->nslow + 1, 0, 63 * sizeof(uint32_t), c->stream));
-    for (size_t si = 0; si < c->sp.size(); si++) {
-      auto& s = c->sp[si];
-      TimedDispatch td{c, (int)si, false};
-      if (c->tiled) {
-        pic::DispatchHook hook;
-        if (c->cfg.flags & PIC_FLAG_TIMING) hook = {&TimedDispatch::hook, &td};
-        hipError_t e = pic::launch_push_tiled<Real>(g, f, species_dev<Real>(*s),
-                                                    push_const<Real>(c, *s), c->tg,
-                                                    s->sort.tile_off, s->outside, c->nslow,
-                                                    c->nslow + 2 + si, c->err, c->stream, hook);
-        if (e != hipSuccess)
-          return fail(c, PIC_EHIP, std::string("tiled particle kernel: ") + hipGetErrorString(e));
-      } else {
-        TimedDispatch::hook(&td, true);
-        pic::launch_push<Real>(g, f, species_dev<Real>(*s), push_const<Real>(c, *s), c->err,
-                               c->stream);
-        TimedDispatch::hook(&td, false);
-      }
-      c->launches++;
-      s->steps_since_sort++;
-    }
-    // the step's outside-tile counts go to pinned host memory, read before
-    // the next step is enqueued
-    if (c->tiled && c->sort_every == 0 && !c->sp.empty()) {
-      const int slot = (int)(c->step & 1);
-      HIPCHK(c, hipMemcpyAsync(c->host_counts + 64 * slot, c->nslow + 2,
-                               c->sp.size() * sizeof(uint32_t), hipMemcpyDeviceToHost,
-                               c->stream));
-      HIPCHK(c, hipEventRecord(c->ev_counts[slot], c->stream));
-      c->counts_pending = slot;
-    }
-    pic::launch_fold_periodic<Real>(g, jj, 3, c->stream);
-    if (check) {
-      deposit_rho<Real>(c, c->rho1);
-      pic::launch_residual<Real>(g, f, c->rho0, c->rho1, c->partials, pic::reduce_blocks(),
-                                 c->dout + 4, c->stream);
-      c->residual_valid = true;
-    }
-    if (!frozen) {
-      pic::launch_b_half<Real>(g, f, c->stream);
-      pic::launch_fill_periodic<Real>(g, eb + 3, 3, c->stream);
-      for (int d = 0; d < g.nd; d++)
-        if (!g.periodic[d])
-          pic::launch_mur_low_b<Real>(g, f, d, static_cast<Real*>(c->mur_b[d][0]),
-                                      static_cast<Real*>(c->mur_b[d][1]), las, c->step,
-                                      c->stream);
-      for (int d = 0; d < g.nd; d++)
-        if (!g.periodic[d])
-          pic::launch_save_high_e<Real>(g, f, d, static_cast<Real*>(c->mur_e[d][0]),
-                                        static_cast<Real*>(c->mur_e[d][1]), c->stream);
-      pic::launch_e_full<Real>(g, f, c->stream);
-      pic::launch_fill_periodic<Real>(g, eb, 3, c->stream);
-      for (int d = 0; d < g.nd; d++)
-        if (!g.periodic[d])
-          pic::launch_mur_high_e<Real>(g, f, d, static_cast<Real*>(c->mur_e[d][0]),
-                                       static_cast<Real*>(c->mur_e[d][1]), c->stream);
-      pic::launch_b_half<Real>(g, f, c->stream);
-    }
-    c->step++;
-    c->steps_since_sort++;
-    if (c->nprobe > 0 && c->probe_rec < c->cfg.max_probe_steps) {
-      pic::launch_probes<Real>(g, f, c->nprobe, c->probe_comp, c->probe_idx,
-                               static_cast<Real*>(c->probe_buf), c->cfg.max_probe_steps,
-                               c->probe_rec, c->stream);
-      c->probe_rec++;
-    }
+    int rc = sort_due(c);
+    if (rc) return rc;
+    StepOpts o;
+    o.check = (c->cfg.flags & PIC_FLAG_CHARGE_CHECK) && it == nsteps - 1;
+    rc = advance_one<Real>(c, las, o);
+    if (rc) return rc;
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(c, PIC_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
@@ -835,6 +680,8 @@ int pic_create(const pic_config* cfg, const pic_allocator* alloc, void* hip_stre
     if (!pl && cfg->n[d] < 2 * cfg->pad + 1)
       return fail(nullptr, PIC_EINVAL, "grid too small for the particle walls");
   }
+  if (cfg->laser.n_env < 0 || cfg->laser.n_env > PIC_MAX_ENV)
+    return fail(nullptr, PIC_EINVAL, "n_env must be in [0, PIC_MAX_ENV]");
   if (bits > 31) return fail(nullptr, PIC_EINVAL, "grid too large for the packed cell index");
   {
     int64_t plane = 1;
@@ -1193,6 +1040,7 @@ void pic_destroy(pic_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  grad_release(c);
   release_host(c);
   dev_free_all(c);
   delete c;

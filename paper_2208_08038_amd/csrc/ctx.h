@@ -1,0 +1,234 @@
+// ctx.h -- host-side context of the library (shared by the C-ABI
+// implementation and the gradient driver): species storage, the context
+// struct, and the helpers that turn them into kernel arguments.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "pic.h"
+#include "pic_internal.h"
+#include "sort.h"
+#include "tiled.h"
+
+using pic::GridInfo;
+
+struct GradState;  // gradient run: checkpoints, adjoint arrays (grad.hip)
+
+struct SpeciesHost {
+  pic_species_desc d{};
+  double a_c = 0.0;  // effective softening length (inf: harmonic)
+  int64_t n = 0, cap = 0;
+  bool has_wc = false, has_w = false;
+  double max_w = 0.0;  // largest |per-particle weight| loaded (has_w)
+  void* cell = nullptr;
+  void* off[3] = {nullptr, nullptr, nullptr};
+  void* dl[3] = {nullptr, nullptr, nullptr};
+  void* u1[3] = {nullptr, nullptr, nullptr};
+  void* u2[3] = {nullptr, nullptr, nullptr};
+  void* wc = nullptr;
+  void* w = nullptr;
+  pic::SortBuffers sort{};
+  int64_t* ids = nullptr;  // device load indices (TRACK_IDS)
+  uint32_t* outside = nullptr;  // particles listed as outside their tile (tiled kernel)
+  bool needs_sort = true;  // tile offsets stale (after a load)
+  // adaptive sort policy: particles advanced outside their tile since the
+  // species' last sort, and steps since then
+  double listed_since_sort = 0.0;
+  int64_t steps_since_sort = 0;
+};
+
+// Species slots of the per-step outside-tile counters (device nslow[2 + s]).
+constexpr int kMaxSpecies = 62;
+
+struct pic_ctx {
+  pic_config cfg{};
+  pic_allocator alloc{};
+  bool use_hip_malloc = true;
+  hipStream_t stream = nullptr;
+  GridInfo g{};
+  int prec = 64;
+  size_t rsize = 8;
+  void* fields = nullptr;  // 9 planes
+  void* mur_b[3][2] = {};
+  void* mur_e[3][2] = {};
+  uint32_t* err = nullptr;
+  uint32_t* load_err = nullptr;
+  uint32_t* nslow = nullptr;   // [0]: list length scratch, [2 + s]: species s listed this step
+  uint32_t* host_counts = nullptr;  // pinned: 2 slots of the per-species counts
+  hipEvent_t ev_counts[2] = {nullptr, nullptr};
+  int counts_pending = -1;          // slot whose copy is in flight, or -1
+  bool tiled = false;
+  pic::TileGeom tg{};
+  double* partials = nullptr;
+  double* dout = nullptr;  // 32 doubles: [0..3] scratch, [4..6] residual, ...
+  double* rho0 = nullptr;
+  double* rho1 = nullptr;
+  int nprobe = 0;
+  int* probe_comp = nullptr;
+  int64_t* probe_idx = nullptr;
+  void* probe_buf = nullptr;
+  int64_t probe_rec = 0;
+  std::vector<std::unique_ptr<SpeciesHost>> sp;
+  std::vector<void*> allocs;
+  int64_t step = 0;
+  int64_t steps_since_sort = 0;
+  int tile[3] = {1, 1, 1};
+  int ntiles[3] = {1, 1, 1};
+  int sort_every = 0;  // > 0: fixed cadence; 0: adaptive per species
+  std::string error;
+  bool residual_valid = false;
+  // timing
+  std::vector<hipEvent_t> ev;
+  std::vector<int> ev_species;  // species of each (start, stop) pair
+  size_t ev_used = 0;
+  int64_t launches = 0;
+  // gradient run (checkpoints and adjoint arrays), created on first use
+  GradState* grad = nullptr;
+};
+
+// Free the gradient run's host bookkeeping (its device buffers are in the
+// context's allocation list).
+void grad_release(pic_ctx* c);
+
+// Record `msg` as the context's (or, without one, the creating thread's)
+// last error and return `code`.
+int fail(pic_ctx* c, int code, const std::string& msg);
+
+#define HIPCHK(ctx, expr)                                                           \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return fail(ctx, PIC_EHIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+// Device memory from the caller's allocator (or hipMalloc), released at
+// pic_destroy.
+void* dev_alloc(pic_ctx* c, size_t bytes);
+
+inline bool is_periodic(const pic_config& c, int d) {
+  return c.bc_lo[d] == PIC_BC_PERIODIC && c.bc_hi[d] == PIC_BC_PERIODIC;
+}
+
+template <typename Real>
+pic::FieldPtrs<Real> field_ptrs(const pic_ctx* c) {
+  pic::FieldPtrs<Real> f;
+  Real* base = static_cast<Real*>(c->fields);
+  for (int a = 0; a < 3; a++) {
+    f.E[a] = base + (0 + a) * c->g.plane;
+    f.B[a] = base + (3 + a) * c->g.plane;
+    f.J[a] = base + (6 + a) * c->g.plane;
+  }
+  return f;
+}
+
+template <typename Real>
+pic::SpeciesDev<Real> species_dev(const SpeciesHost& s) {
+  pic::SpeciesDev<Real> d;
+  d.cell = static_cast<uint32_t*>(s.cell);
+  for (int a = 0; a < 3; a++) {
+    d.off[a] = static_cast<Real*>(s.off[a]);
+    d.dl[a] = static_cast<Real*>(s.dl[a]);
+    d.u1[a] = static_cast<Real*>(s.u1[a]);
+    d.u2[a] = static_cast<Real*>(s.u2[a]);
+  }
+  d.wc = s.has_wc ? static_cast<Real*>(s.wc) : nullptr;
+  d.w = s.has_w ? static_cast<Real*>(s.w) : nullptr;
+  d.n = s.n;
+  return d;
+}
+
+template <typename Real>
+pic::PushConst<Real> push_const(const pic_ctx* c, const SpeciesHost& s) {
+  pic::PushConst<Real> k{};
+  const pic_species_desc& d = s.d;
+  double dt = c->cfg.dt;
+  bool two = d.kind == PIC_TWO_BODY;
+  double m1 = d.m1, m2 = two ? d.m2 : 0.0, mc = m1 + m2;
+  k.dt = (Real)dt;
+  k.half_dt = (Real)(0.5 * dt);
+  double dv = 1.0;
+  for (int a = 0; a < 3; a++) {
+    k.idx[a] = a < c->g.nd ? (Real)(1.0 / c->cfg.dx[a]) : Real(0);
+    if (a < c->g.nd) dv *= c->cfg.dx[a];
+  }
+  k.a1 = (Real)(0.5 * dt * d.q1 / d.m1);
+  k.a2 = two ? (Real)(0.5 * dt * d.q2 / d.m2) : Real(0);
+  k.m1 = (Real)m1;
+  k.m2 = (Real)m2;
+  k.inv_mc = (Real)(1.0 / mc);
+  k.f1 = two ? (Real)(m2 / mc) : Real(0);
+  k.f2 = two ? (Real)(m1 / mc) : Real(1);
+  k.mr = two ? (Real)(m1 * m2 / mc) : Real(0);
+  k.inv_q1 = (Real)(1.0 / d.q1);
+  k.inv_q2 = two ? (Real)(1.0 / d.q2) : Real(0);
+  k.inv_ac2 = std::isinf(s.a_c) ? Real(0) : (Real)(1.0 / (s.a_c * s.a_c));
+  k.omega_c = (Real)d.omega_c;
+  k.nu = (Real)d.nu;
+  k.nu_per_omega = (Real)d.nu_per_omega;
+  k.qw1 = (Real)(d.q1 * d.weight);
+  k.qw2 = two ? (Real)(d.q2 * d.weight) : Real(0);
+  k.weight = (Real)d.weight;
+  k.q1 = (Real)d.q1;
+  k.q2 = two ? (Real)d.q2 : Real(0);
+  for (int a = 0; a < 3; a++) k.jf[a] = a < c->g.nd ? (Real)(-c->cfg.dx[a] / (dt * dv)) : Real(0);
+  k.inv_dv = (Real)(1.0 / dv);
+  // Bound on one deposit term: charge x prefactor x shape factors.  The
+  // running sum C of shape changes lies in [-1, 1]; the transverse factor
+  // S0 (S0 + DS/2) + DS (S0/2 + DS/3) is at most 1 + 1/2; out-of-plane terms
+  // carry |v| < c = 1 instead of C.  A merged pair adds both bodies.
+  {
+    const double wmax = s.has_w ? s.max_w : std::fabs(d.weight);
+    const double qsum = (std::fabs(d.q1) + (two ? std::fabs(d.q2) : 0.0)) * wmax;
+    double fmax = c->g.nd < 3 ? 1.0 / dv : 0.0;
+    for (int a = 0; a < c->g.nd; a++) fmax = std::max(fmax, c->cfg.dx[a] / (dt * dv));
+    const double bound = 1.5 * qsum * fmax;
+    int e = bound > 0.0 ? (int)std::floor(46.0 - std::log2(bound)) : 0;
+    e = std::max(-120, std::min(120, e));
+    k.jscale = (Real)std::ldexp(1.0, e);
+  }
+  k.two_body = two ? 1 : 0;
+  k.deposit = (c->cfg.flags & PIC_FLAG_NO_DEPOSIT) ? 0 : 1;
+  return k;
+}
+
+// Laser description for the field kernels.
+inline pic::LaserDev laser_dev(const pic_ctx* c) {
+  const pic_laser& L = c->cfg.laser;
+  pic::LaserDev las{};
+  las.a0 = L.a0;
+  las.omega = L.omega;
+  las.t_env = L.t_env;
+  las.waist = L.waist;
+  las.yc = L.yc;
+  las.zc = L.zc;
+  las.phase = L.phase;
+  las.t_delay = L.t_delay;
+  las.pol = L.pol;
+  las.on = (c->cfg.bc_lo[0] == PIC_BC_LASER && L.a0 != 0.0) ? 1 : 0;
+  las.oblique = L.angle != 0.0 ? 1 : 0;
+  las.cos_a = std::cos(L.angle);
+  las.sin_a = std::sin(L.angle);
+  las.n_env = L.n_env;
+  las.h_env = L.n_env > 0 ? L.t_env / (double)(L.n_env + 3) : 0.0;
+  for (int k = 0; k < 64; k++) las.env[k] = k < L.n_env ? L.env[k] : 0.0;
+  return las;
+}
+
+// What one step does besides advancing the state.
+struct StepOpts {
+  bool check = false;   // charge-continuity residual of this step
+  bool record = true;   // record the probes after the step
+};
+
+// Advance every species and the fields by one step (no tile sort); the
+// state after the field guard fill and before the particle push is handed
+// to `save` when given.
+template <typename Real>
+int advance_one(pic_ctx* c, const pic::LaserDev& las, const StepOpts& o,
+                void (*save)(pic_ctx*, void*) = nullptr, void* save_arg = nullptr);

@@ -164,19 +164,55 @@ __device__ __forceinline__ int64_t face_node(const GridInfo& g, int d, int p, in
   return g.origin + i + (int64_t)j * g.sy + (int64_t)k * g.sz;
 }
 
-__device__ __forceinline__ double laser_time(const LaserDev& L, double tau) {
-  if (tau < 0.0 || tau > L.t_env) return 0.0;
-  double s = sin(3.14159265358979323846 * tau / L.t_env);
-  return L.a0 * s * s * sin(L.omega * tau + L.phase);
+// The four uniform cubic B-spline basis functions that are non-zero on one
+// knot interval, at the local coordinate u in [0, 1): weights of the
+// coefficients m-3 .. m of the interval [m h, (m+1) h).
+__device__ __forceinline__ void spline_segment(double u, double w[4]) {
+  const double v = 1.0 - u;
+  w[0] = v * v * v / 6.0;
+  w[1] = (3.0 * u * u * u - 6.0 * u * u + 4.0) / 6.0;
+  w[2] = (-3.0 * u * u * u + 3.0 * u * u + 3.0 * u + 1.0) / 6.0;
+  w[3] = u * u * u / 6.0;
 }
 
-// incident B of the laser (wave along +x) for component a at interior
-// index (i, j, k) with the B stagger of that component
-__device__ __forceinline__ double b_incident(const GridInfo& g, const LaserDev& L, int a, int i,
-                                             int j, int k, double t) {
-  if (!L.on) return 0.0;
+// Envelope of the laser at t' = tau in [0, t_env]: sin^2(pi tau / t_env),
+// or the cubic B-spline series of the n_env coefficients (knots h apart).
+__device__ __forceinline__ double envelope(const LaserDev& L, double tau) {
+  if (L.n_env <= 0) {
+    double s = sin(3.14159265358979323846 * tau / L.t_env);
+    return s * s;
+  }
+  const double x = tau / L.h_env;
+  const int m = (int)floor(x);
+  double w[4];
+  spline_segment(x - (double)m, w);
+  double e = 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; r++) {
+    const int k = m - 3 + r;
+    if (k >= 0 && k < L.n_env) e += L.env[k] * w[r];
+  }
+  return e;
+}
+
+__device__ __forceinline__ double laser_time(const LaserDev& L, double tau) {
+  if (tau < 0.0 || tau > L.t_env) return 0.0;
+  return L.a0 * envelope(L, tau) * sin(L.omega * tau + L.phase);
+}
+
+// Incident B of the laser (wave along +x, or oblique) for component a at
+// interior index (i, j, k) with the B stagger of that component, as
+// amp * laser_time(tau): amp holds the polarisation sign and the transverse
+// profile (0 for the component the laser does not drive), tau the retarded
+// time.
+__device__ __forceinline__ void incident_parts(const GridInfo& g, const LaserDev& L, int a, int i,
+                                               int j, int k, double t, double& amp,
+                                               double& tau) {
+  amp = 0.0;
+  tau = -1.0;
+  if (!L.on) return;
   int want = L.pol == 2 ? 1 : 2;
-  if (a != want) return 0.0;
+  if (a != want) return;
   // B_a is half-staggered along the two axes other than a
   double sx = 0.5, sy = a == 1 ? 0.0 : 0.5, sz = a == 2 ? 0.0 : 0.5;
   double x = ((double)i + sx) * g.dx[0];
@@ -184,8 +220,9 @@ __device__ __forceinline__ double b_incident(const GridInfo& g, const LaserDev& 
     // plane wave travelling at an angle toward +y: B = n x E (c = 1), so the
     // in-plane E gives B_z = |E| and E_z gives B_y = -cos(angle) E_z
     double y = g.nd > 1 ? ((double)j + sy) * g.dx[1] - L.yc : 0.0;
-    double e = laser_time(L, t - L.t_delay - (x * L.cos_a + y * L.sin_a));
-    return a == 2 ? e : -L.cos_a * e;
+    tau = t - L.t_delay - (x * L.cos_a + y * L.sin_a);
+    amp = a == 2 ? 1.0 : -L.cos_a;
+    return;
   }
   double prof = 1.0;
   if (L.waist > 0.0) {
@@ -200,8 +237,35 @@ __device__ __forceinline__ double b_incident(const GridInfo& g, const LaserDev& 
     }
     prof = exp(-r2 / (L.waist * L.waist));
   }
-  double e = prof * laser_time(L, t - L.t_delay - x);
-  return a == 2 ? e : -e;
+  tau = t - L.t_delay - x;
+  amp = a == 2 ? prof : -prof;
+}
+
+__device__ __forceinline__ double b_incident(const GridInfo& g, const LaserDev& L, int a, int i,
+                                             int j, int k, double t) {
+  double amp, tau;
+  incident_parts(g, L, a, i, j, k, t, amp, tau);
+  return amp == 0.0 ? 0.0 : amp * laser_time(L, tau);
+}
+
+// Add coef * d(b_incident)/d(env[m]) to acc[m] for the (at most four)
+// spline coefficients that the incident field at (i, j, k, t) depends on.
+__device__ __forceinline__ void b_incident_grad(const GridInfo& g, const LaserDev& L, int a, int i,
+                                                int j, int k, double t, double coef,
+                                                double* acc) {
+  double amp, tau;
+  incident_parts(g, L, a, i, j, k, t, amp, tau);
+  if (amp == 0.0 || L.n_env <= 0 || tau < 0.0 || tau > L.t_env) return;
+  const double base = coef * amp * L.a0 * sin(L.omega * tau + L.phase);
+  const double x = tau / L.h_env;
+  const int m = (int)floor(x);
+  double w[4];
+  spline_segment(x - (double)m, w);
+#pragma unroll
+  for (int r = 0; r < 4; r++) {
+    const int kk = m - 3 + r;
+    if (kk >= 0 && kk < L.n_env) atomicAdd(&acc[kk], base * w[r]);
+  }
 }
 
 // Mur condition on the scattered tangential B at the ghost half a cell
@@ -286,6 +350,225 @@ __global__ void k_probes(GridInfo g, FieldPtrs<Real> f, int nprobe, const int* c
   buf[(int64_t)p * max_steps + rec] = F[index[p]];
 }
 
+// ------------------------------------------------- adjoint (transposed) operators
+//
+// Each kernel below applies the transpose of one linear field operation of
+// the step to the adjoint fields lE, lB (same layout as E, B).  They run
+// over the nodes whose adjoint value changes and gather the contributions
+// from the nodes that the forward operation wrote, so no atomics are
+// needed.
+
+// Node (i, j, k) of the range [lo, lo + n + 1) in each resolved dimension
+// (one extra layer): returns false past the end.
+__device__ __forceinline__ bool ext_ijk(const GridInfo& g, int64_t t, int lo, int& i, int& j,
+                                        int& k) {
+  const int ex = g.n[0] + 1, ey = g.nd > 1 ? g.n[1] + 1 : 1, ez = g.nd > 2 ? g.n[2] + 1 : 1;
+  if (t >= (int64_t)ex * ey * ez) return false;
+  i = (int)(t % ex) + lo;
+  int64_t r = t / ex;
+  j = g.nd > 1 ? (int)(r % ey) + lo : 0;
+  k = g.nd > 2 ? (int)(r / ey) + lo : 0;
+  return true;
+}
+
+__device__ __forceinline__ bool interior(const GridInfo& g, int i, int j, int k) {
+  return i >= 0 && i < g.n[0] && j >= 0 && j < g.n[1] && k >= 0 && k < g.n[2];
+}
+
+// Transpose of B -= h curl E on the interior: lE += -h curl^T lB, over the
+// E nodes that the curl reads (interior plus one layer above it).
+template <typename Real, int ND>
+__global__ void __launch_bounds__(256) k_b_half_adj(GridInfo g, FieldPtrs<Real> l, Real h,
+                                                    Real ix, Real iy, Real iz) {
+  int i, j, k;
+  if (!ext_ijk(g, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, 0, i, j, k)) return;
+  const int64_t o = g.origin + i + j * g.sy + k * g.sz;
+  const bool in0 = interior(g, i, j, k);
+  const bool inx = interior(g, i - 1, j, k);
+  const bool iny = ND > 1 && interior(g, i, j - 1, k);
+  const bool inz = ND > 2 && interior(g, i, j, k - 1);
+  const Real *Bx = l.B[0], *By = l.B[1], *Bz = l.B[2];
+  Real ax = 0, ay = 0, az = 0;
+  // from B_y -= h [-(Ez[o+1] - Ez[o]) ix + (Ex[o+sz] - Ex[o]) iz]
+  // and B_z -= h [(Ey[o+1] - Ey[o]) ix - (Ex[o+sy] - Ex[o]) iy]
+  // and B_x -= h [(Ez[o+sy] - Ez[o]) iy - (Ey[o+sz] - Ey[o]) iz]
+  if (in0) {
+    az -= h * ix * By[o];
+    ay += h * ix * Bz[o];
+    if (ND > 1) {
+      ax -= h * iy * Bz[o];
+      az += h * iy * Bx[o];
+    }
+    if (ND > 2) {
+      ax += h * iz * By[o];
+      ay -= h * iz * Bx[o];
+    }
+  }
+  if (inx) {
+    az += h * ix * By[o - 1];
+    ay -= h * ix * Bz[o - 1];
+  }
+  if (iny) {
+    ax += h * iy * Bz[o - g.sy];
+    az -= h * iy * Bx[o - g.sy];
+  }
+  if (inz) {
+    ax -= h * iz * By[o - g.sz];
+    ay += h * iz * Bx[o - g.sz];
+  }
+  l.E[0][o] += ax;
+  l.E[1][o] += ay;
+  l.E[2][o] += az;
+}
+
+// Transpose of E += dt (curl B - J) on the interior: lB += dt curl^T lE over
+// the B nodes that the curl reads (interior plus one layer below it), and
+// lJ = -dt lE on the interior.
+template <typename Real, int ND>
+__global__ void __launch_bounds__(256) k_e_full_adj(GridInfo g, FieldPtrs<Real> l, Real dt,
+                                                    Real ix, Real iy, Real iz) {
+  int i, j, k;
+  if (!ext_ijk(g, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, -1, i, j, k)) return;
+  const int64_t o = g.origin + i + j * g.sy + k * g.sz;
+  const bool in0 = interior(g, i, j, k);
+  const bool inx = interior(g, i + 1, j, k);
+  const bool iny = ND > 1 && interior(g, i, j + 1, k);
+  const bool inz = ND > 2 && interior(g, i, j, k + 1);
+  const Real *Ex = l.E[0], *Ey = l.E[1], *Ez = l.E[2];
+  Real bx = 0, by = 0, bz = 0;
+  // E_x += dt [(Bz[o] - Bz[o-sy]) iy - (By[o] - By[o-sz]) iz]
+  // E_y += dt [-(Bz[o] - Bz[o-1]) ix + (Bx[o] - Bx[o-sz]) iz]
+  // E_z += dt [(By[o] - By[o-1]) ix - (Bx[o] - Bx[o-sy]) iy]
+  if (in0) {
+    bz -= dt * ix * Ey[o];
+    by += dt * ix * Ez[o];
+    if (ND > 1) {
+      bz += dt * iy * Ex[o];
+      bx -= dt * iy * Ez[o];
+    }
+    if (ND > 2) {
+      by -= dt * iz * Ex[o];
+      bx += dt * iz * Ey[o];
+    }
+    l.J[0][o] = -dt * Ex[o];
+    l.J[1][o] = -dt * Ey[o];
+    l.J[2][o] = -dt * Ez[o];
+  }
+  if (inx) {
+    bz += dt * ix * Ey[o + 1];
+    by -= dt * ix * Ez[o + 1];
+  }
+  if (iny) {
+    bz -= dt * iy * Ex[o + g.sy];
+    bx += dt * iy * Ez[o + g.sy];
+  }
+  if (inz) {
+    by += dt * iz * Ex[o + g.sz];
+    bx -= dt * iz * Ey[o + g.sz];
+  }
+  l.B[0][o] += bx;
+  l.B[1][o] += by;
+  l.B[2][o] += bz;
+}
+
+// Transpose of the Mur update of the ghost B at the low face of dim d
+// (k_mur_low_b): Bg' = prev - i1m + kc (B1 - i1p - Bg + igm) + igp,
+// prev' = B1.  lprev holds the adjoint of prev' on entry and of prev on
+// exit; the laser's incident terms add their coefficient gradients to
+// genv (one FP64 value per spline coefficient).
+template <typename Real>
+__global__ void k_mur_low_b_adj(GridInfo g, FieldPtrs<Real> l, int d, Real* lprev0,
+                                Real* lprev1, LaserDev L, int64_t step, double* genv) {
+  __shared__ double acc[64];
+  for (int q = threadIdx.x; q < 64; q += blockDim.x) acc[q] = 0.0;
+  __syncthreads();
+  int a_dim = d == 0 ? 1 : 0, b_dim = d == 2 ? 1 : 2;
+  int64_t np = (int64_t)g.n[a_dim] * g.n[b_dim];
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < 2 * np) {
+    int q = (int)(t / np);
+    int64_t pi = t % np;
+    int a, b, na;
+    face_ab(g, d, pi, a, b, na);
+    int comp = q == 0 ? (d == 0 ? 1 : 0) : (d == 2 ? 1 : 2);
+    Real* lB = l.B[comp];
+    Real* lprev = q == 0 ? lprev0 : lprev1;
+    const double kc = (g.dt - g.dx[d]) / (g.dt + g.dx[d]);
+    const int64_t fg = face_node(g, d, -1, a, b), f1 = face_node(g, d, 0, a, b);
+    const double lg = (double)lB[fg];
+    const double lp_new = (double)lprev[pi];
+    lprev[pi] = (Real)lg;
+    lB[f1] = (Real)((double)lB[f1] + kc * lg + lp_new);
+    lB[fg] = (Real)(-kc * lg);
+    if (d == 0 && L.on && L.n_env > 0 && lg != 0.0) {
+      const double tn = (double)step * g.dt;
+      const int jj = a, kk = b;
+      b_incident_grad(g, L, comp, -1, jj, kk, tn + 0.5 * g.dt, lg, acc);
+      b_incident_grad(g, L, comp, -1, jj, kk, tn - 0.5 * g.dt, kc * lg, acc);
+      b_incident_grad(g, L, comp, 0, jj, kk, tn - 0.5 * g.dt, -lg, acc);
+      b_incident_grad(g, L, comp, 0, jj, kk, tn + 0.5 * g.dt, -kc * lg, acc);
+    }
+  }
+  __syncthreads();
+  if (d == 0 && L.on && L.n_env > 0)
+    for (int q = threadIdx.x; q < L.n_env; q += blockDim.x)
+      if (acc[q] != 0.0) atomicAdd(&genv[q], acc[q]);
+}
+
+// Transpose of saving the tangential E of the last interior layer.
+template <typename Real>
+__global__ void k_save_high_e_adj(GridInfo g, FieldPtrs<Real> l, int d, Real* ls0, Real* ls1) {
+  int a_dim = d == 0 ? 1 : 0, b_dim = d == 2 ? 1 : 2;
+  int64_t np = (int64_t)g.n[a_dim] * g.n[b_dim];
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * np) return;
+  int q = (int)(t / np);
+  int64_t pi = t % np;
+  int a, b, na;
+  face_ab(g, d, pi, a, b, na);
+  int comp = q == 0 ? (d == 0 ? 1 : 0) : (d == 2 ? 1 : 2);
+  Real* ls = q == 0 ? ls0 : ls1;
+  const int64_t f1 = face_node(g, d, g.n[d] - 1, a, b);
+  l.E[comp][f1] += ls[pi];
+  ls[pi] = Real(0);
+}
+
+// Transpose of the Mur update of the ghost E at the high face of dim d
+// (k_mur_high_e): Eg' = s + kc (E1 - Eg).
+template <typename Real>
+__global__ void k_mur_high_e_adj(GridInfo g, FieldPtrs<Real> l, int d, Real* ls0, Real* ls1) {
+  int a_dim = d == 0 ? 1 : 0, b_dim = d == 2 ? 1 : 2;
+  int64_t np = (int64_t)g.n[a_dim] * g.n[b_dim];
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * np) return;
+  int q = (int)(t / np);
+  int64_t pi = t % np;
+  int a, b, na;
+  face_ab(g, d, pi, a, b, na);
+  int comp = q == 0 ? (d == 0 ? 1 : 0) : (d == 2 ? 1 : 2);
+  Real* ls = q == 0 ? ls0 : ls1;
+  const double kc = (g.dt - g.dx[d]) / (g.dt + g.dx[d]);
+  Real* lE = l.E[comp];
+  const int64_t fg = face_node(g, d, g.n[d], a, b), f1 = face_node(g, d, g.n[d] - 1, a, b);
+  const double lg = (double)lE[fg];
+  ls[pi] = (Real)lg;
+  lE[f1] = (Real)((double)lE[f1] + kc * lg);
+  lE[fg] = (Real)(-kc * lg);
+}
+
+// Adjoint of the probe recording of one step: l(field at probe p) +=
+// cot[p * nsteps + rec].
+template <typename Real>
+__global__ void k_probe_seed(FieldPtrs<Real> l, int nprobe, const int* comp, const int64_t* index,
+                             const double* cot, int64_t nsteps, int64_t rec) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nprobe) return;
+  const int c = comp[p];
+  Real* F = c < 3 ? l.E[c] : l.B[c - 3];
+  const double v = cot[(int64_t)p * nsteps + rec];
+  if (v != 0.0) atomicAdd(&F[index[p]], (Real)v);
+}
+
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -299,8 +582,10 @@ void launch_zero(Real* p, int64_t n, hipStream_t st) {
 }
 
 template <typename Real>
-void launch_fill_periodic(const GridInfo& g, Real* const* comps, int ncomp, hipStream_t st) {
-  for (int d = 0; d < g.nd; d++) {
+void launch_fill_periodic(const GridInfo& g, Real* const* comps, int ncomp, hipStream_t st,
+                          bool reverse) {
+  for (int it = 0; it < g.nd; it++) {
+    const int d = reverse ? g.nd - 1 - it : it;
     if (!g.periodic[d]) continue;
     int a_dim = d == 0 ? 1 : 0, b_dim = d == 2 ? 1 : 2;
     int64_t total = (int64_t)g.st[a_dim] * g.st[b_dim] * 2 * kGuard;
@@ -314,8 +599,10 @@ void launch_fill_periodic(const GridInfo& g, Real* const* comps, int ncomp, hipS
 }
 
 template <typename Real>
-void launch_fold_periodic(const GridInfo& g, Real* const* comps, int ncomp, hipStream_t st) {
-  for (int d = 0; d < g.nd; d++) {
+void launch_fold_periodic(const GridInfo& g, Real* const* comps, int ncomp, hipStream_t st,
+                          bool reverse) {
+  for (int it = 0; it < g.nd; it++) {
+    const int d = reverse ? g.nd - 1 - it : it;
     if (!g.periodic[d]) continue;
     int a_dim = d == 0 ? 1 : 0, b_dim = d == 2 ? 1 : 2;
     int64_t total = (int64_t)g.st[a_dim] * g.st[b_dim] * 2 * kGuard;
@@ -330,7 +617,7 @@ void launch_fold_periodic(const GridInfo& g, Real* const* comps, int ncomp, hipS
 
 void launch_fold_periodic_f64(const GridInfo& g, double* rho, hipStream_t st) {
   double* c[1] = {rho};
-  launch_fold_periodic<double>(g, c, 1, st);
+  launch_fold_periodic<double>(g, c, 1, st, false);
 }
 
 template <typename Real>
@@ -395,10 +682,72 @@ void launch_probes(const GridInfo& g, const FieldPtrs<Real>& f, int nprobe, cons
                      buf, max_steps, rec);
 }
 
+template <typename Real>
+static unsigned ext_blocks(const GridInfo& g) {
+  int64_t n = (int64_t)(g.n[0] + 1) * (g.nd > 1 ? g.n[1] + 1 : 1) * (g.nd > 2 ? g.n[2] + 1 : 1);
+  return blocks_for(n, 256);
+}
+
+template <typename Real>
+void launch_b_half_adj(const GridInfo& g, const FieldPtrs<Real>& l, hipStream_t st) {
+  Real h = (Real)(0.5 * g.dt);
+  Real ix = (Real)(1.0 / g.dx[0]);
+  Real iy = g.nd > 1 ? (Real)(1.0 / g.dx[1]) : Real(0);
+  Real iz = g.nd > 2 ? (Real)(1.0 / g.dx[2]) : Real(0);
+  unsigned nb = ext_blocks<Real>(g);
+  if (g.nd == 1) hipLaunchKernelGGL((k_b_half_adj<Real, 1>), nb, 256, 0, st, g, l, h, ix, iy, iz);
+  if (g.nd == 2) hipLaunchKernelGGL((k_b_half_adj<Real, 2>), nb, 256, 0, st, g, l, h, ix, iy, iz);
+  if (g.nd == 3) hipLaunchKernelGGL((k_b_half_adj<Real, 3>), nb, 256, 0, st, g, l, h, ix, iy, iz);
+}
+
+template <typename Real>
+void launch_e_full_adj(const GridInfo& g, const FieldPtrs<Real>& l, hipStream_t st) {
+  Real dt = (Real)g.dt;
+  Real ix = (Real)(1.0 / g.dx[0]);
+  Real iy = g.nd > 1 ? (Real)(1.0 / g.dx[1]) : Real(0);
+  Real iz = g.nd > 2 ? (Real)(1.0 / g.dx[2]) : Real(0);
+  unsigned nb = ext_blocks<Real>(g);
+  if (g.nd == 1) hipLaunchKernelGGL((k_e_full_adj<Real, 1>), nb, 256, 0, st, g, l, dt, ix, iy, iz);
+  if (g.nd == 2) hipLaunchKernelGGL((k_e_full_adj<Real, 2>), nb, 256, 0, st, g, l, dt, ix, iy, iz);
+  if (g.nd == 3) hipLaunchKernelGGL((k_e_full_adj<Real, 3>), nb, 256, 0, st, g, l, dt, ix, iy, iz);
+}
+
+template <typename Real>
+void launch_mur_low_b_adj(const GridInfo& g, const FieldPtrs<Real>& l, int d, Real* lprev0,
+                          Real* lprev1, const LaserDev& las, int64_t step, double* genv,
+                          hipStream_t st) {
+  int64_t np = 2 * face_count(g, d);
+  hipLaunchKernelGGL(k_mur_low_b_adj<Real>, blocks_for(np, 256), 256, 0, st, g, l, d, lprev0,
+                     lprev1, las, step, genv);
+}
+
+template <typename Real>
+void launch_save_high_e_adj(const GridInfo& g, const FieldPtrs<Real>& l, int d, Real* ls0,
+                            Real* ls1, hipStream_t st) {
+  int64_t np = 2 * face_count(g, d);
+  hipLaunchKernelGGL(k_save_high_e_adj<Real>, blocks_for(np, 256), 256, 0, st, g, l, d, ls0, ls1);
+}
+
+template <typename Real>
+void launch_mur_high_e_adj(const GridInfo& g, const FieldPtrs<Real>& l, int d, Real* ls0,
+                           Real* ls1, hipStream_t st) {
+  int64_t np = 2 * face_count(g, d);
+  hipLaunchKernelGGL(k_mur_high_e_adj<Real>, blocks_for(np, 256), 256, 0, st, g, l, d, ls0, ls1);
+}
+
+template <typename Real>
+void launch_probe_seed(const FieldPtrs<Real>& l, int nprobe, const int* comp,
+                       const int64_t* index, const double* cot, int64_t nsteps, int64_t rec,
+                       hipStream_t st) {
+  if (nprobe <= 0) return;
+  hipLaunchKernelGGL(k_probe_seed<Real>, blocks_for(nprobe, 64), 64, 0, st, l, nprobe, comp,
+                     index, cot, nsteps, rec);
+}
+
 #define PIC_INST(R)                                                                              \
   template void launch_zero<R>(R*, int64_t, hipStream_t);                                        \
-  template void launch_fill_periodic<R>(const GridInfo&, R* const*, int, hipStream_t);           \
-  template void launch_fold_periodic<R>(const GridInfo&, R* const*, int, hipStream_t);           \
+  template void launch_fill_periodic<R>(const GridInfo&, R* const*, int, hipStream_t, bool);     \
+  template void launch_fold_periodic<R>(const GridInfo&, R* const*, int, hipStream_t, bool);     \
   template void launch_b_half<R>(const GridInfo&, const FieldPtrs<R>&, hipStream_t);             \
   template void launch_e_full<R>(const GridInfo&, const FieldPtrs<R>&, hipStream_t);             \
   template void launch_mur_low_b<R>(const GridInfo&, const FieldPtrs<R>&, int, R*, R*,           \
@@ -408,7 +757,17 @@ void launch_probes(const GridInfo& g, const FieldPtrs<Real>& f, int nprobe, cons
   template void launch_mur_high_e<R>(const GridInfo&, const FieldPtrs<R>&, int, const R*,        \
                                      const R*, hipStream_t);                                     \
   template void launch_probes<R>(const GridInfo&, const FieldPtrs<R>&, int, const int*,          \
-                                 const int64_t*, R*, int64_t, int64_t, hipStream_t);
+                                 const int64_t*, R*, int64_t, int64_t, hipStream_t);                   \
+  template void launch_b_half_adj<R>(const GridInfo&, const FieldPtrs<R>&, hipStream_t);         \
+  template void launch_e_full_adj<R>(const GridInfo&, const FieldPtrs<R>&, hipStream_t);         \
+  template void launch_mur_low_b_adj<R>(const GridInfo&, const FieldPtrs<R>&, int, R*, R*,       \
+                                        const LaserDev&, int64_t, double*, hipStream_t);         \
+  template void launch_save_high_e_adj<R>(const GridInfo&, const FieldPtrs<R>&, int, R*, R*,     \
+                                          hipStream_t);                                          \
+  template void launch_mur_high_e_adj<R>(const GridInfo&, const FieldPtrs<R>&, int, R*, R*,      \
+                                         hipStream_t);                                           \
+  template void launch_probe_seed<R>(const FieldPtrs<R>&, int, const int*, const int64_t*,       \
+                                     const double*, int64_t, int64_t, hipStream_t);
 
 PIC_INST(float)
 PIC_INST(double)

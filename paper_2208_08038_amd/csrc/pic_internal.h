@@ -96,10 +96,12 @@ template <typename Real>
 void launch_zero(Real* p, int64_t n, hipStream_t st);
 
 template <typename Real>
-void launch_fill_periodic(const GridInfo& g, Real* const* comps, int ncomp, hipStream_t st);
+void launch_fill_periodic(const GridInfo& g, Real* const* comps, int ncomp, hipStream_t st,
+                          bool reverse = false);
 
 template <typename Real>
-void launch_fold_periodic(const GridInfo& g, Real* const* comps, int ncomp, hipStream_t st);
+void launch_fold_periodic(const GridInfo& g, Real* const* comps, int ncomp, hipStream_t st,
+                          bool reverse = false);
 
 template <typename Real>
 void launch_b_half(const GridInfo& g, const FieldPtrs<Real>& f, hipStream_t st);
@@ -113,6 +115,9 @@ struct LaserDev {
   int pol;
   int on;
   int oblique;
+  int n_env;            // 0: sin^2 envelope; else cubic B-spline coefficients
+  double h_env;         // knot spacing t_env / (n_env + 3)
+  double env[64];
 };
 
 template <typename Real>
@@ -128,6 +133,27 @@ void launch_mur_high_e(const GridInfo& g, const FieldPtrs<Real>& f, int d, const
                        const Real* save1, hipStream_t st);
 
 // diagnostics
+// Adjoint (transposed) field operators of the gradient run; lE, lB, lJ in
+// a FieldPtrs with the layout of the fields.
+template <typename Real>
+void launch_b_half_adj(const GridInfo& g, const FieldPtrs<Real>& l, hipStream_t st);
+template <typename Real>
+void launch_e_full_adj(const GridInfo& g, const FieldPtrs<Real>& l, hipStream_t st);
+template <typename Real>
+void launch_mur_low_b_adj(const GridInfo& g, const FieldPtrs<Real>& l, int d, Real* lprev0,
+                          Real* lprev1, const LaserDev& las, int64_t step, double* genv,
+                          hipStream_t st);
+template <typename Real>
+void launch_save_high_e_adj(const GridInfo& g, const FieldPtrs<Real>& l, int d, Real* ls0,
+                            Real* ls1, hipStream_t st);
+template <typename Real>
+void launch_mur_high_e_adj(const GridInfo& g, const FieldPtrs<Real>& l, int d, Real* ls0,
+                           Real* ls1, hipStream_t st);
+template <typename Real>
+void launch_probe_seed(const FieldPtrs<Real>& l, int nprobe, const int* comp,
+                       const int64_t* index, const double* cot, int64_t nsteps, int64_t rec,
+                       hipStream_t st);
+
 template <typename Real>
 void launch_rho(const GridInfo& g, const SpeciesDev<Real>& s, const PushConst<Real>& c,
                 double* rho, hipStream_t st);

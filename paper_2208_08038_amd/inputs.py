@@ -43,7 +43,9 @@ BASE_SEED = 20220808
 @dataclass
 class Laser:
     """Laser entering through x-min: E_inc = a0 sin^2(pi t'/t_env) sin(omega t' + phase),
-    t' = t - t_delay - x, times exp(-r_perp^2 / waist^2) when waist > 0."""
+    t' = t - t_delay - x, times exp(-r_perp^2 / waist^2) when waist > 0.  A non-empty
+    `env` replaces sin^2 by sum_k env[k] N3(t'/h - k), h = t_env / (len(env) + 3),
+    N3 the cardinal cubic B-spline on [0, 4]."""
     a0: float = 0.0
     omega: float = 1.0
     t_env: float = 0.0
@@ -54,6 +56,7 @@ class Laser:
     t_delay: float = 0.0
     pol: int = 1  # 1: E along y (in the x-y plane), 2: E along z
     angle: float = 0.0  # direction of travel from +x toward +y (plane waves only)
+    env: Tuple[float, ...] = ()  # spline envelope coefficients (at most 64)
 
 
 @dataclass
@@ -232,6 +235,54 @@ def bound_slab_1d(cells: int = 1536, x_cells=(256, 1536), ppc: int = 4, steps: i
     parts = Particles(x=x, u1=np.zeros((x.shape[0], 3)))
     return Workload("bound_slab_1d", grid, [(sp, parts)], steps, 64,
                     notes=f"medium cells {lo}..{hi}, omega_c={omega_c}, omega_pb={omega_pb}")
+
+
+def adjoint_slab(ndim: int = 2, cells=(2048, 1024), slab=(64, 448), probe_x: int = 512,
+                 ppc: int = 16, steps: int = 1024, omega_c: float = 3.0, omega_pb: float = 0.9,
+                 nu: float = 0.03, a_c: float = math.inf, n_env: int = 64, cycles: float = 4.0,
+                 a0: float = 1e-4, waist_frac: float = 0.3, dx_per_lambda: int = 32,
+                 config_id: int = 5) -> Workload:
+    """Gradient-run case: a neutral bound-electron slab (cold two-body gold
+    ions, Z_b = 78, ppc per cell over x cells slab[0]..slab[1] and every y)
+    crossed by a pulse from x-min whose temporal envelope is a cubic
+    B-spline series of n_env coefficients over `cycles` laser periods
+    (initial coefficients: sin^2 sampled at the basis centres); y periodic,
+    a wide Gaussian profile (waist = waist_frac * L_y; plane wave in 1D).
+    Probes on the plane x = probe_x behind the slab: E_y at (probe_x, j)
+    and B_z at (probe_x - 1, j), (probe_x, j) for every j, in that order
+    (the transmitted Poynting flux and phase)."""
+    dx = TWO_PI / float(dx_per_lambda)
+    dt = 0.98 * dx / math.sqrt(float(ndim))
+    nx = int(cells[0])
+    ny = int(cells[1]) if ndim > 1 else 1
+    t_env = cycles * TWO_PI
+    h = t_env / (n_env + 3)
+    env = tuple(math.sin(math.pi * (k + 2) * h / t_env) ** 2 for k in range(n_env))
+    Ly = ny * dx
+    laser = Laser(a0=a0, omega=1.0, t_env=t_env, pol=1, env=env,
+                  waist=waist_frac * Ly if ndim > 1 else 0.0, yc=0.5 * Ly if ndim > 1 else 0.0)
+    if ndim == 1:
+        grid = Grid(1, (nx, 1, 1), (dx, 1.0, 1.0), dt, (LASER, PERIODIC, PERIODIC),
+                    (OPEN, PERIODIC, PERIODIC), pad=3, laser=laser,
+                    re_norm=TWO_PI * R_E_M / 12.4e-9)
+    else:
+        grid = Grid(2, (nx, ny, 1), (dx, dx, 1.0), dt, (LASER, PERIODIC, PERIODIC),
+                    (OPEN, PERIODIC, PERIODIC), pad=3, laser=laser,
+                    re_norm=TWO_PI * R_E_M / 12.4e-9)
+    q1, m1, q2, m2 = gold_ion(78, 0.0)
+    n_ion = bound_plasma_density(q1, m1, q2, m2, omega_pb)
+    cell_vol = dx ** ndim
+    sp = Species(TWO_BODY, q1, m1, q2, m2, weight=n_ion * cell_vol / ppc, omega_c=omega_c,
+                 a_c=a_c, nu=nu, name="Au_Zb78_cold")
+    lo = [slab[0]] + ([0] if ndim > 1 else [])
+    hi = [min(slab[1], nx - grid.pad)] + ([ny] if ndim > 1 else [])
+    x = stratified_positions(rng_for(config_id), lo, hi, ppc, grid.dx, ndim)
+    parts = Particles(x=x, u1=np.zeros((x.shape[0], 3)))
+    probes = ([(1, (probe_x, j, 0)) for j in range(ny)] +
+              [(5, (probe_x - 1, j, 0)) for j in range(ny)] +
+              [(5, (probe_x, j, 0)) for j in range(ny)])
+    return Workload("adjoint_slab", grid, [(sp, parts)], steps, 64, probes=probes,
+                    notes=f"slab {slab}, probe plane x={probe_x}, omega_c={omega_c}, nu={nu}")
 
 
 # --------------------------------------------------------------------------

@@ -35,7 +35,8 @@ class PicLaser(C.Structure):
     _fields_ = [("a0", C.c_double), ("omega", C.c_double), ("t_env", C.c_double),
                 ("waist", C.c_double), ("yc", C.c_double), ("zc", C.c_double),
                 ("phase", C.c_double), ("t_delay", C.c_double),
-                ("pol", C.c_int32), ("reserved", C.c_int32), ("angle", C.c_double)]
+                ("pol", C.c_int32), ("reserved", C.c_int32), ("angle", C.c_double),
+                ("n_env", C.c_int32), ("reserved2", C.c_int32), ("env", C.c_double * 64)]
 
 
 class PicConfig(C.Structure):
@@ -73,6 +74,10 @@ _lib = None
 
 # (name, restype, argtypes) of every entry point in include/pic.h
 _P, _D = C.c_void_p, C.POINTER(C.c_double)
+class PicGrad(C.Structure):
+    _fields_ = [("d_omega_c", _D), ("d_nu", _D), ("d_env", _D), ("d_E", _D), ("d_B", _D)]
+
+
 SIGNATURES = [
     ("pic_create", C.c_int, [C.POINTER(PicConfig), C.POINTER(PicAllocator), _P, C.POINTER(_P)]),
     ("pic_add_species", C.c_int, [_P, C.POINTER(PicSpeciesDesc), C.POINTER(C.c_int32)]),
@@ -92,6 +97,9 @@ SIGNATURES = [
     ("pic_set_probes", C.c_int, [_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
     ("pic_read_probes", C.c_int, [_P, _D, C.POINTER(C.c_int64)]),
     ("pic_timing", C.c_int, [_P, C.c_int32, _D, C.POINTER(C.c_int64), C.c_int32]),
+    ("pic_grad_forward", C.c_int, [_P, C.c_int32, C.c_int32]),
+    ("pic_grad_backward", C.c_int, [_P, _D, C.POINTER(PicGrad)]),
+    ("pic_read_grad_particles", C.c_int, [_P, C.c_int32, _D, _D, _D, _D]),
     ("pic_last_error", C.c_char_p, [_P]),
     ("pic_destroy", None, [_P]),
     ("pic_version", C.c_char_p, []),
@@ -186,6 +194,12 @@ class Simulation:
         las = grid.laser
         cfg.laser = PicLaser(las.a0, las.omega, las.t_env, las.waist, las.yc, las.zc, las.phase,
                              las.t_delay, int(las.pol), 0, float(getattr(las, "angle", 0.0)))
+        env = tuple(getattr(las, "env", ()) or ())
+        if len(env) > 64:
+            raise ValueError("at most 64 envelope coefficients")
+        cfg.laser.n_env = len(env)
+        for k, v in enumerate(env):
+            cfg.laser.env[k] = float(v)
         self.cfg = cfg
         self.grid = grid
         self.ndim = grid.ndim
@@ -200,6 +214,7 @@ class Simulation:
             raise PicError(rc, self.lib.pic_last_error(None).decode())
         self.ctx = ctx
         self.nprobe = 0
+        self.species = []
 
     def _check(self, rc):
         if rc != PIC_OK:
@@ -223,6 +238,7 @@ class Simulation:
                            int(capacity))
         sid = C.c_int32()
         self._check(self.lib.pic_add_species(self.ctx, C.byref(d), C.byref(sid)))
+        self.species.append(sp)
         return sid.value
 
     def load_particles(self, sid: int, parts) -> None:
@@ -354,6 +370,44 @@ class Simulation:
         self._check(self.lib.pic_read_probes(self.ctx, None, C.byref(n)))
         out = np.zeros((self.nprobe, n.value))
         self._check(self.lib.pic_read_probes(self.ctx, _dp(out), C.byref(n)))
+        return out
+
+    # ------------------------------------------------------- gradient run
+    def grad_forward(self, nsteps: int, checkpoint_every: int) -> None:
+        """Advance nsteps as step() does (no tile sorts), recording the
+        probes and keeping a checkpoint every `checkpoint_every` steps."""
+        self._grad_steps = int(nsteps)
+        self._check(self.lib.pic_grad_forward(self.ctx, int(nsteps), int(checkpoint_every)))
+
+    def grad_backward(self, dprobe, fields: bool = False) -> dict:
+        """Gradients from the cotangent of the probe values of the last
+        grad_forward run (nprobe x nsteps): d_omega_c, d_nu per species,
+        d_env per envelope coefficient, and (fields=True) d_E, d_B at the
+        start of the run (3 x ncell each)."""
+        ns = len(self.species)
+        dp = _f64(dprobe, (self.nprobe, self._grad_steps)) if self.nprobe else None
+        out = {"d_omega_c": np.zeros(ns), "d_nu": np.zeros(ns),
+               "d_env": np.zeros(max(int(self.cfg.laser.n_env), 0))}
+        if fields:
+            out["d_E"] = np.zeros((3, self.ncell))
+            out["d_B"] = np.zeros((3, self.ncell))
+        g = PicGrad(_dp(out["d_omega_c"]), _dp(out["d_nu"]),
+                    _dp(out["d_env"]) if out["d_env"].size else None,
+                    _dp(out.get("d_E")), _dp(out.get("d_B")))
+        self._check(self.lib.pic_grad_backward(self.ctx, _dp(dp), C.byref(g)))
+        return out
+
+    def grad_particles(self, sid: int) -> dict:
+        """dL/d(state at the start of the run) of one species, storage order."""
+        n = self.count(sid)
+        two = self.species[sid].kind == 1  # two-body
+        out = {"x": np.zeros((n, self.ndim)), "u1": np.zeros((n, 3))}
+        if two:
+            out["delta"] = np.zeros((n, 3))
+            out["u2"] = np.zeros((n, 3))
+        self._check(self.lib.pic_read_grad_particles(self.ctx, int(sid), _dp(out["x"]),
+                                                     _dp(out.get("delta")), _dp(out["u1"]),
+                                                     _dp(out.get("u2"))))
         return out
 
     def timing(self, species: int = -1, reset: bool = True):

@@ -1,0 +1,99 @@
+"""Cases and helpers of the gradient-run tests: small 1D / 2D versions of
+`inputs.adjoint_slab`, parameter perturbations, losses, central finite
+differences on the oracle and on the library's FP64 forward."""
+import dataclasses
+import math
+
+import numpy as np
+
+from paper_2208_08038_amd.inputs import Grid, Laser, adjoint_slab, OPEN, LASER, PERIODIC
+
+TWO_PI = 2.0 * math.pi
+
+
+def small_case(ndim, steps=None, a0=1e-4, nu=0.03, omega_c=3.0, a_c=math.inf, ppc=4,
+               thermal=0.0, seed=7):
+    """1D: 128 cells of lambda/16, slab 16..64, probe plane 80, 3-cycle
+    envelope of 8 coefficients, 210 steps.  2D: 96 x 16 cells, slab 16..48,
+    probe plane 56, 2-cycle envelope, 150 steps.  `thermal` adds Gaussian
+    momenta of that spread to both bodies (independently)."""
+    if ndim == 1:
+        wl = adjoint_slab(1, (128, 1), (16, 64), 80, ppc=ppc, steps=steps or 210,
+                          omega_c=omega_c, nu=nu, a_c=a_c, n_env=8, cycles=3.0, a0=a0,
+                          dx_per_lambda=16)
+    else:
+        wl = adjoint_slab(2, (96, 16), (16, 48), 56, ppc=ppc, steps=steps or 150,
+                          omega_c=omega_c, nu=nu, a_c=a_c, n_env=8, cycles=2.0, a0=a0,
+                          dx_per_lambda=16)
+    if thermal > 0.0:
+        sp, parts = wl.species[0]
+        rng = np.random.default_rng(seed)
+        u1 = rng.normal(0.0, thermal, (parts.n, 3))
+        u2 = rng.normal(0.0, thermal, (parts.n, 3))
+        parts = dataclasses.replace(parts, u1=u1, u2=u2)
+        wl = dataclasses.replace(wl, species=[(sp, parts)])
+    return wl
+
+
+def with_params(wl, omega_c=None, nu=None, env=None):
+    sp, parts = wl.species[0]
+    sp = dataclasses.replace(sp, omega_c=sp.omega_c if omega_c is None else omega_c,
+                             nu=sp.nu if nu is None else nu)
+    grid = wl.grid
+    if env is not None:
+        grid = dataclasses.replace(grid, laser=dataclasses.replace(grid.laser, env=tuple(env)))
+    return dataclasses.replace(wl, grid=grid, species=[(sp, parts)])
+
+
+def with_particles(wl, **arrays):
+    sp, parts = wl.species[0]
+    return dataclasses.replace(wl, species=[(sp, dataclasses.replace(parts, **arrays))])
+
+
+def oracle_series(wl):
+    from oracle import Oracle
+    o = Oracle.from_workload(wl, max_probe_steps=wl.steps)
+    o.set_probes(wl.probes)
+    o.step(wl.steps)
+    d = o.diagnostics()
+    assert d["error_word"] == 0
+    out = o.probes()
+    o.close()
+    return out
+
+
+def gpu_series(pic, wl, precision=64, flags=0):
+    sim = pic.Simulation.from_workload(wl, precision=precision, flags=flags,
+                                       max_probe_steps=wl.steps)
+    sim.step(wl.steps)
+    d = sim.diagnostics()
+    assert d["error_word"] == 0, d
+    out = sim.probes()
+    sim.close()
+    return out
+
+
+def central_fd(series_fn, loss_fn, make, x0, h):
+    """(L(x0 + h) - L(x0 - h)) / (2 h) with L = loss_fn(series_fn(make(x)))."""
+    lp = loss_fn(series_fn(make(x0 + h)))
+    lm = loss_fn(series_fn(make(x0 - h)))
+    return (lp - lm) / (2.0 * h)
+
+
+def richardson_fd(series_fn, loss_fn, make, x0, h):
+    """Central differences at h and h/2 combined to cancel the h^2 term:
+    (4 D(h/2) - D(h)) / 3, error O(h^4)."""
+    d1 = central_fd(series_fn, loss_fn, make, x0, h)
+    d2 = central_fd(series_fn, loss_fn, make, x0, 0.5 * h)
+    return (4.0 * d2 - d1) / 3.0
+
+
+def vacuum_grid(ndim, laser=None):
+    """Open x faces (x-min injects `laser`), periodic y; lambda/16 cells."""
+    dx = TWO_PI / 16.0
+    if ndim == 1:
+        return Grid(1, (64, 1, 1), (dx, 1.0, 1.0), 0.98 * dx, (LASER, PERIODIC, PERIODIC),
+                    (OPEN, PERIODIC, PERIODIC), pad=3, laser=laser or Laser())
+    return Grid(2, (48, 16, 1), (dx, dx, 1.0), 0.98 * dx / math.sqrt(2.0),
+                (LASER, PERIODIC, PERIODIC), (OPEN, PERIODIC, PERIODIC), pad=3,
+                laser=laser or Laser())

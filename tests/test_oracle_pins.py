@@ -515,6 +515,41 @@ def test_laser_injection_and_open_boundary(oracle_built):
     assert o.diagnostics()["field_energy"] < 1e-5 * emax
 
 
+def test_laser_spline_envelope(oracle_built):
+    """The spline envelope of the gradient runs: E_inc = a0 env(t') sin(t'),
+    env = sum_k c_k N3(t'/h - k), h = t_env / (K + 3), with N3 the cardinal
+    cubic B-spline taken from scipy's B-spline basis element (knots 0..4).
+    The field at a vacuum probe follows it (up to Yee dispersion); equal
+    coefficients give a flat top (partition of unity)."""
+    from scipy.interpolate import BSpline
+    n3 = BSpline.basis_element(np.arange(5.0), extrapolate=False)
+    cells = 600
+    dx = 2 * math.pi / 64
+    dt = 0.98 * dx
+    rng = np.random.default_rng(4)
+    for coef in (rng.uniform(0.1, 1.0, 9), np.ones(9)):
+        t_env = 5 * 2 * math.pi
+        las = Laser(a0=1.0, omega=1.0, t_env=t_env, pol=1, env=tuple(coef))
+        g = Grid(1, (cells, 1, 1), (dx, 1, 1), dt, (LASER, 0, 0), (OPEN, 0, 0), laser=las)
+        o = Oracle(g, max_probe_steps=700)
+        o.set_probes([(1, (100, 0, 0))])
+        o.step(700)
+        pr = o.probes()[0]
+        o.close()
+        t = (np.arange(pr.shape[0]) + 1) * dt
+        tau = t - 100 * dx
+        h = t_env / (len(coef) + 3)
+        env = np.zeros_like(tau)
+        for k, ck in enumerate(coef):
+            env += ck * np.nan_to_num(n3(tau / h - k))
+        env[(tau < 0) | (tau > t_env)] = 0.0
+        assert np.max(np.abs(pr - env * np.sin(tau))) < 3e-3
+        if np.all(coef == 1.0):
+            flat = (tau > 3 * h) & (tau < t_env - 3 * h)
+            assert np.allclose(env[flat], 1.0, atol=1e-12)
+            assert np.max(np.abs(pr[flat] - np.sin(tau[flat]))) < 3e-3
+
+
 # ------------------------------------------ coupled: dispersion (T6)
 
 @pytest.mark.slow
