@@ -171,6 +171,70 @@ def run_gpu(args, precision, keep_fields=False):
     return res
 
 
+def run_adjoint(args):
+    """Gradient run on the adjoint workload (2D neutral bound-electron slab,
+    cells args.adjoint_cells, ppc args.adjoint_ppc in x cells 64..448, probe
+    plane x = 512, 64-coefficient spline envelope over 4 laser cycles),
+    FP32: checkpointed forward, transmitted-pulse loss, reverse sweep.  The
+    adjoint particle kernel is timed per reverse step with HIP events."""
+    import torch
+    from paper_2208_08038_amd import pic
+    from paper_2208_08038_amd.inputs import adjoint_slab
+    from paper_2208_08038_amd.objectives import transmitted_loss, transmitted_parts
+    nx, ny = args.adjoint_cells
+    wl = adjoint_slab(2, (nx, ny), steps=args.adjoint_steps, ppc=args.adjoint_ppc)
+    t0 = time.perf_counter()
+    sim = pic.Simulation.from_workload(wl, precision=32, flags=pic.TIMING,
+                                       max_probe_steps=wl.steps)
+    torch.cuda.synchronize()
+    t_load = time.perf_counter() - t0
+    n_ion = wl.species[0][1].n
+    t0 = time.perf_counter()
+    sim.grad_forward(wl.steps, args.checkpoint_every)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    print(f"adjoint leg: {n_ion} ions loaded in {t_load:.1f} s, forward {wl.steps} steps "
+          f"{t_fwd:.1f} s", file=sys.stderr, flush=True)
+    dt, dy = wl.grid.dt, wl.grid.dx[1]
+    series = torch.tensor(sim.probes(), requires_grad=True)
+    e_ref = float(transmitted_parts(series.detach(), ny, dt, dy)[0])
+    loss = transmitted_loss(series, ny, dt, dy, e_ref=e_ref)
+    (cot,) = torch.autograd.grad(loss, series)
+    sim.timing(-1, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = sim.grad_backward(cot.numpy())
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    print(f"adjoint leg: reverse sweep {t_bwd:.1f} s", file=sys.stderr, flush=True)
+    adj_ms, adj_n = sim.timing(pic.TIMING_ADJOINT + 0, reset=False)
+    fwd_ms, fwd_n = sim.timing(0, reset=True)
+    diag = sim.diagnostics()
+    sim.close()
+    slab_cells = (min(448, nx - 3) - 64) * ny
+    # per ion: stored state 48 B read, adjoint state 44 B read + 44 B written;
+    # per slab cell: E, B 24 B and adjoint J 12 B read, adjoint E, B 48 B
+    # read and written
+    bytes_launch = n_ion * (48 + 88) + slab_cells * 84
+    launch_ms = adj_ms / adj_n if adj_n else None
+    gbs = bytes_launch / (launch_ms * 1e-3) / 1e9 if launch_ms else None
+    return {
+        "workload": "adjoint_slab_2d", "cells": [nx, ny], "two_body_ions": n_ion,
+        "steps": wl.steps, "checkpoint_every": args.checkpoint_every, "precision": "fp32",
+        "loss": "E_T / E_T(base) + phase at the probe plane x = 512",
+        "load_s": t_load, "forward_s": t_fwd, "backward_s": t_bwd,
+        "particle_steps_per_s": n_ion * wl.steps / (t_fwd + t_bwd),
+        "adjoint_kernel": {"name": "k_adjoint_tiled<float, 2, true>", "launches": adj_n,
+                           "launch_ms": launch_ms, "algorithmic_bytes_per_launch": bytes_launch,
+                           "achieved_gbs": gbs,
+                           "frac_hbm": gbs / HBM_PEAK_GBS if gbs else None},
+        "forward_kernel_ms_per_dispatch": fwd_ms / fwd_n if fwd_n else None,
+        "grad": {"d_omega_c": float(g["d_omega_c"][0]), "d_nu": float(g["d_nu"][0]),
+                 "d_env_l2": float(np.linalg.norm(g["d_env"]))},
+        "error_word": diag["error_word"],
+    }
+
+
 def cpu_baseline(target_seconds):
     """The FP64 oracle as it stands, on a small sample of the same workload."""
     from oracle import Oracle
@@ -210,6 +274,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=float, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient-run leg")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only run the gradient-run leg (one JSON object)")
+    ap.add_argument("--adjoint-cells", type=int, nargs=2, default=[2048, 1024])
+    ap.add_argument("--adjoint-ppc", type=int, default=16)
+    ap.add_argument("--adjoint-steps", type=int, default=1024)
+    ap.add_argument("--checkpoint-every", type=int, default=32)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -223,6 +294,9 @@ def main():
     if args.copy_calibration:
         sys.exit(copy_calibration(args.copy_calibration))
 
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": run_adjoint(args)}), flush=True)
+        return
     r32 = run_gpu(args, 32, keep_fields=not args.no_fp64)
     r64 = None if args.no_fp64 else run_gpu(args, 64, keep_fields=True)
     fp32_err = None
@@ -249,6 +323,7 @@ def main():
                           f"one of the {ncol} tile-colour dispatches of a step",
                 "launch_ms": r32["ion_dispatch_ms"],
                 "algorithmic_bytes_per_launch": r32["bytes_ion_dispatch"]}
+    adj = None if args.no_adjoint else run_adjoint(args)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_seconds)
     out = {
         "metric": METRIC, "value": r32["value"], "unit": "particle-steps/s", "n_gpus": 1,
@@ -275,6 +350,7 @@ def main():
             "ion_kernel_gbs": r64["ion_kernel_gbs"],
             "frac": r64["ion_kernel_gbs"] / HBM_PEAK_GBS if r64["ion_kernel_gbs"] else None},
         "fp32_vs_fp64": fp32_err,
+        "adjoint": adj,
         "error_word": r32["error_word"],
     }
     print(json.dumps(out), flush=True)

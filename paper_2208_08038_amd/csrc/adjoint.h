@@ -17,9 +17,19 @@ using AdjState = SpeciesDev<Real>;
 // the step, guards filled) and the adjoint current l.J; updates the
 // particle adjoint `lp` in place, adds the gather's transpose into l.E and
 // l.B, and adds d/d(omega_c) and d/d(friction rate) to dparam[0], dparam[1].
+// Tiles of the sorted particle order (cells per tile, tiles per dim).
+struct AdjTiles {
+  int T[2];
+  int nt[2];
+};
+
+// With tile_off (the species' tile offsets of its last sort, which the
+// gradient run keeps) one workgroup per tile accumulates the scatter in LDS;
+// without, one thread per particle scatters with global atomics.
 template <typename Real>
 void launch_adjoint_push(const GridInfo& g, const FieldPtrs<Real>& f, const AdjState<Real>& st,
                          const PushConst<Real>& c, const AdjState<Real>& lp,
-                         const FieldPtrs<Real>& l, double* dparam, hipStream_t stream);
+                         const FieldPtrs<Real>& l, double* dparam, const uint32_t* tile_off,
+                         const AdjTiles& tt, hipStream_t stream);
 
 }  // namespace pic

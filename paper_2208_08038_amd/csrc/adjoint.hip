@@ -1,7 +1,8 @@
 // adjoint.hip -- reverse-mode (adjoint) particle cycle of the gradient run,
 // 1D and 2D grids, two-body ions and point particles.
 //
-// One thread per macro-particle.  The thread recomputes the forward cycle
+// One thread per macro-particle (one workgroup per tile of the sorted order
+// when the tile offsets are given).  The thread recomputes the forward cycle
 // of its particle from the stored state at the start of the step (the
 // same arithmetic as the forward kernels: quadratic B-spline gather,
 // softened bond force, time-centred friction, relativistic Boris push of
@@ -14,8 +15,9 @@
 //   * move, Lorentz factor, Boris rotation, friction and kicks are
 //     differentiated in reverse order;
 //   * the gather's adjoint scatters lambda_E, lambda_B of each body onto the
-//     nodes with the gather weights (atomics into lE, lB) and adds the
-//     position derivative of the interpolant.
+//     nodes with the gather weights (into an FP64 LDS patch of the tile, or
+//     with atomics into lE, lB) and adds the position derivative of the
+//     interpolant.
 // The particle's adjoint state (offsets, delta, u1, u2) is updated in
 // place; the derivatives with respect to omega_c and the friction rate are
 // reduced per block and added to two FP64 accumulators.
@@ -83,17 +85,54 @@ __device__ __forceinline__ Real interp_grad(const Real* __restrict__ F, int64_t 
   return v;
 }
 
-// Transpose of the interpolation: F(node) += lam * weight(node).
+// Destination of the gather's transpose for one particle: an FP64 LDS
+// patch of the workgroup's tile (component planes of `lplane` values, row
+// pitch `lsy`, the particle's cell at index `lbase`), or the global adjoint
+// planes with atomics (particles outside their tile).  Nodes are given
+// relative to the particle's cell.
+template <typename Real>
+struct Sink {
+  FieldPtrs<Real> l;
+  int64_t gbase, gsy;
+  double* lds;
+  int lbase, lsy, lplane;
+  __device__ __forceinline__ void add(int comp, int ix, int iy, Real v) const {
+    if (lds) {
+      atomicAdd(lds + comp * lplane + lbase + ix + iy * lsy, (double)v);
+    } else {
+      Real* F = comp < 3 ? l.E[comp] : l.B[comp - 3];
+      unsafeAtomicAdd(F + gbase + ix + iy * gsy, v);
+    }
+  }
+};
+
+// Transpose of the interpolation: node += lam * weight(node).
 template <typename Real, int ND>
-__device__ __forceinline__ void scatter(Real* F, int64_t base, int64_t sy, const Shape<Real>& sx,
+__device__ __forceinline__ void scatter(const Sink<Real>& k, int comp, const Shape<Real>& sx,
                                         const Shape<Real>& syy, Real lam) {
   if (lam == Real(0)) return;
   const int ny = ND > 1 ? 3 : 1;
   for (int s = 0; s < ny; s++) {
-    Real* row = F + base + sx.i0 + (ND > 1 ? (int64_t)(syy.i0 + s) * sy : 0);
     const Real wy = ND > 1 ? syy.w[s] : Real(1);
+    const int iy = ND > 1 ? syy.i0 + s : 0;
 #pragma unroll
-    for (int r = 0; r < 3; r++) unsafeAtomicAdd(row + r, lam * wy * sx.w[r]);
+    for (int r = 0; r < 3; r++) k.add(comp, sx.i0 + r, iy, lam * wy * sx.w[r]);
+  }
+}
+
+// Both bodies on the same nodes: one add per node with the two weights.
+template <typename Real, int ND>
+__device__ __forceinline__ void scatter2(const Sink<Real>& k, int comp, const Shape<Real>& ax,
+                                         const Shape<Real>& ay, Real la, const Shape<Real>& bx,
+                                         const Shape<Real>& by, Real lb) {
+  if (la == Real(0) && lb == Real(0)) return;
+  const int ny = ND > 1 ? 3 : 1;
+  for (int s = 0; s < ny; s++) {
+    const Real wa = ND > 1 ? la * ay.w[s] : la;
+    const Real wb = ND > 1 ? lb * by.w[s] : lb;
+    const int iy = ND > 1 ? ay.i0 + s : 0;
+#pragma unroll
+    for (int r = 0; r < 3; r++) k.add(comp, ax.i0 + r, iy, wa * ax.w[r] + wb * bx.w[r]);
   }
 }
 
@@ -125,23 +164,48 @@ __device__ __forceinline__ void probe_fields(const FieldPtrs<Real>& f, int64_t b
   p.B[2] = interp_grad<Real, ND>(f.B[2], base, sy, p.h[0], p.h[1], p.gB[2]);
 }
 
-// Scatter lambda_E, lambda_B of one body and return d/dx of the
-// interpolated fields contracted with them.
+// d/dx of one body's interpolated fields contracted with lambda_E, lambda_B.
 template <typename Real, int ND>
-__device__ __forceinline__ void gather_adjoint(const FieldPtrs<Real>& l, int64_t base, int64_t sy,
-                                               const Probe<Real, ND>& p, const Real lE[3],
-                                               const Real lB[3], Real lx[2]) {
-  scatter<Real, ND>(l.E[0], base, sy, p.h[0], p.n[1], lE[0]);
-  scatter<Real, ND>(l.E[1], base, sy, p.n[0], p.h[1], lE[1]);
-  scatter<Real, ND>(l.E[2], base, sy, p.n[0], p.n[1], lE[2]);
-  scatter<Real, ND>(l.B[0], base, sy, p.n[0], p.h[1], lB[0]);
-  scatter<Real, ND>(l.B[1], base, sy, p.h[0], p.n[1], lB[1]);
-  scatter<Real, ND>(l.B[2], base, sy, p.h[0], p.h[1], lB[2]);
+__device__ __forceinline__ void position_adjoint(const Probe<Real, ND>& p, const Real lE[3],
+                                                 const Real lB[3], Real lx[2]) {
   for (int d = 0; d < ND; d++) {
     Real s = 0;
     for (int a = 0; a < 3; a++) s += lE[a] * p.gE[a][d] + lB[a] * p.gB[a][d];
     lx[d] = s;
   }
+}
+
+// The gather's transpose for one body: scatter lambda_E, lambda_B with the
+// gather weights of every component's stagger.
+template <typename Real, int ND>
+__device__ __forceinline__ void scatter_body(const Sink<Real>& k, const Probe<Real, ND>& p,
+                                             const Real lE[3], const Real lB[3]) {
+  scatter<Real, ND>(k, 0, p.h[0], p.n[1], lE[0]);
+  scatter<Real, ND>(k, 1, p.n[0], p.h[1], lE[1]);
+  scatter<Real, ND>(k, 2, p.n[0], p.n[1], lE[2]);
+  scatter<Real, ND>(k, 3, p.n[0], p.h[1], lB[0]);
+  scatter<Real, ND>(k, 4, p.h[0], p.n[1], lB[1]);
+  scatter<Real, ND>(k, 5, p.h[0], p.h[1], lB[2]);
+}
+
+template <typename Real, int ND>
+__device__ __forceinline__ bool same_nodes(const Probe<Real, ND>& a, const Probe<Real, ND>& b) {
+  bool same = true;
+  for (int d = 0; d < ND; d++) same = same && a.n[d].i0 == b.n[d].i0 && a.h[d].i0 == b.h[d].i0;
+  return same;
+}
+
+template <typename Real, int ND>
+__device__ __forceinline__ void scatter_pair(const Sink<Real>& k, const Probe<Real, ND>& a,
+                                             const Real lEa[3], const Real lBa[3],
+                                             const Probe<Real, ND>& b, const Real lEb[3],
+                                             const Real lBb[3]) {
+  scatter2<Real, ND>(k, 0, a.h[0], a.n[1], lEa[0], b.h[0], b.n[1], lEb[0]);
+  scatter2<Real, ND>(k, 1, a.n[0], a.h[1], lEa[1], b.n[0], b.h[1], lEb[1]);
+  scatter2<Real, ND>(k, 2, a.n[0], a.n[1], lEa[2], b.n[0], b.n[1], lEb[2]);
+  scatter2<Real, ND>(k, 3, a.n[0], a.h[1], lBa[0], b.n[0], b.h[1], lBb[0]);
+  scatter2<Real, ND>(k, 4, a.h[0], a.n[1], lBa[1], b.h[0], b.n[1], lBb[1]);
+  scatter2<Real, ND>(k, 5, a.h[0], a.h[1], lBa[2], b.h[0], b.h[1], lBb[2]);
 }
 
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
@@ -391,6 +455,268 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;
 }
 
+// Tile of the workgroup in the tiled adjoint kernel: cells [x0, x0 + tx) x
+// [y0, y0 + ty) and the FP64 LDS patch of its nodes [x0 - 2, x0 + tx + 2) x
+// [y0 - 2, y0 + ty + 2), six component planes of `plane` values, row pitch
+// `pitch`.  lds == nullptr: every scatter goes to the global planes.
+struct TileBox {
+  double* lds;
+  int x0, y0, tx, ty, pitch, plane;
+};
+
+// Reverse the cycle of particle p (see the file comment).
+template <typename Real, int ND, bool TWO>
+__device__ __forceinline__ void adjoint_one(const GridInfo& g, const FieldPtrs<Real>& f,
+                                            const AdjState<Real>& st, const PushConst<Real>& c,
+                                            const AdjState<Real>& lp, const FieldPtrs<Real>& l,
+                                            int64_t p, const TileBox& box, double& d_wc,
+                                            double& d_nu) {
+  do {
+    // ---- stored state at the start of the step
+    int ci[3] = {0, 0, 0};
+    const uint32_t pk = st.cell[p];
+    ci[0] = pk & ((1u << g.bits[0]) - 1u);
+    if (ND > 1) ci[1] = (pk >> g.bits[0]) & ((1u << g.bits[1]) - 1u);
+    Real off[3] = {0, 0, 0}, u1[3], u2[3] = {0, 0, 0}, dl[3] = {0, 0, 0};
+    for (int d = 0; d < ND; d++) off[d] = st.off[d][p];
+    for (int q = 0; q < 3; q++) {
+      u1[q] = st.u1[q][p];
+      if (TWO) {
+        u2[q] = st.u2[q][p];
+        dl[q] = st.dl[q][p];
+      }
+    }
+    const Real wc = TWO ? (st.wc ? st.wc[p] : c.omega_c) : Real(0);
+    const Real W = st.w ? st.w[p] : Real(1);
+    bool ok = true;
+    Real x1[3] = {0, 0, 0}, x2[3] = {0, 0, 0};
+    for (int d = 0; d < ND; d++) {
+      ok = ok && isfinite(off[d]) && off[d] >= Real(0) && off[d] <= Real(1);
+      const Real sd = dl[d] * c.idx[d];
+      if (TWO) ok = ok && fabs(sd) < Real(0.5);
+      x1[d] = off[d] + (TWO ? c.f1 * sd : Real(0));
+      x2[d] = off[d] - (TWO ? c.f2 * sd : Real(0));
+    }
+    for (int q = 0; q < 3; q++) ok = ok && isfinite(u1[q]) && isfinite(u2[q]) && isfinite(dl[q]);
+    if (!ok) break;  // the forward cycle left it unchanged: identity
+    const int64_t base = g.origin + ci[0] + (ND > 1 ? (int64_t)ci[1] * g.sy : 0);
+
+    // ---- forward recomputation
+    Probe<Real, ND> P1, P2;
+    probe_fields<Real, ND>(f, base, g.sy, x1, P1);
+    if (TWO) probe_fields<Real, ND>(f, base, g.sy, x2, P2);
+    Real E1[3], E2[3] = {0, 0, 0}, um1[3], um2[3] = {0, 0, 0};
+    Real r2 = 0, rq = 1, soft = 1, kf = 0;
+    if (TWO) {
+      r2 = dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2];
+      if (c.inv_ac2 != Real(0)) {
+        rq = rsq(Real(1) + r2 * c.inv_ac2);
+        soft = rq * rq * rq;
+      }
+      kf = -c.mr * wc * wc * soft;
+    }
+    for (int q = 0; q < 3; q++) {
+      const Real F = kf * dl[q];
+      E1[q] = P1.E[q] + (TWO ? F * c.inv_q1 : Real(0));
+      um1[q] = u1[q] + c.a1 * E1[q];
+      if (TWO) {
+        E2[q] = P2.E[q] - F * c.inv_q2;
+        um2[q] = u2[q] + c.a2 * E2[q];
+      }
+    }
+    // friction on the relative momentum (identity when nu = 0)
+    const Real nu = TWO ? c.nu + c.nu_per_omega * wc : Real(0);
+    const Real Dn = (Real(1) - nu * c.half_dt) * rcp(Real(1) + nu * c.half_dt);
+    Real vm1[3], vm2[3] = {0, 0, 0};
+    for (int q = 0; q < 3; q++) {
+      if (TWO) {
+        const Real V = (c.m1 * um1[q] + c.m2 * um2[q]) * c.inv_mc;
+        const Real w = (um1[q] - um2[q]) * Dn;
+        vm1[q] = V + c.f1 * w;
+        vm2[q] = V - c.f2 * w;
+      } else {
+        vm1[q] = um1[q];
+      }
+    }
+    Real n1[3], n2[3] = {0, 0, 0}, v1[3], v2[3] = {0, 0, 0};
+    boris_forward(vm1, c.a1, E1, P1.B, n1);
+    if (TWO) boris_forward(vm2, c.a2, E2, P2.B, n2);
+    {
+      const Real i1 = rsq(Real(1) + n1[0] * n1[0] + n1[1] * n1[1] + n1[2] * n1[2]);
+      const Real i2 = rsq(Real(1) + n2[0] * n2[0] + n2[1] * n2[1] + n2[2] * n2[2]);
+      for (int q = 0; q < 3; q++) {
+        v1[q] = n1[q] * i1;
+        v2[q] = n2[q] * i2;
+      }
+    }
+    Real dln[3], offn[3] = {0, 0, 0};
+    for (int q = 0; q < 3; q++) dln[q] = TWO ? dl[q] + c.dt * (v1[q] - v2[q]) : Real(0);
+    bool refl[3] = {false, false, false};
+    for (int d = 0; d < ND; d++) {
+      const Real vc = TWO ? (c.m1 * v1[d] + c.m2 * v2[d]) * c.inv_mc : v1[d];
+      offn[d] = off[d] + c.dt * vc * c.idx[d];
+      refl[d] = reflect_wall(g.periodic[d], ci[d], g.n[d], g.pad, offn[d]);
+      if (refl[d]) dln[d] = -dln[d];
+    }
+    Real y1[3] = {0, 0, 0}, y2[3] = {0, 0, 0};
+    for (int d = 0; d < ND; d++) {
+      const Real sd = dln[d] * c.idx[d];
+      y1[d] = offn[d] + (TWO ? c.f1 * sd : Real(0));
+      y2[d] = offn[d] - (TWO ? c.f2 * sd : Real(0));
+    }
+
+    // ---- reverse
+    Real l_off[3] = {0, 0, 0}, l_dl[3] = {0, 0, 0}, l_u1[3] = {0, 0, 0}, l_u2[3] = {0, 0, 0};
+    Real l_offn[3] = {0, 0, 0}, l_dln[3] = {0, 0, 0}, l_n1[3], l_n2[3] = {0, 0, 0};
+    for (int d = 0; d < ND; d++) l_offn[d] = lp.off[d][p];
+    for (int q = 0; q < 3; q++) {
+      l_n1[q] = lp.u1[q][p];
+      if (TWO) {
+        l_n2[q] = lp.u2[q][p];
+        l_dln[q] = lp.dl[q][p];
+      }
+    }
+    Real l_v1[3] = {0, 0, 0}, l_v2[3] = {0, 0, 0};
+    if (c.deposit) {
+      const Real Q1 = st.w ? c.q1 * W : c.qw1;
+      Real g0[2], g1[2], gv[3];
+      if (deposit_adjoint<Real, ND>(l, base, g.sy, x1, y1, Q1, v1, c, g0, g1, gv)) {
+        for (int d = 0; d < ND; d++) {
+          l_offn[d] += g1[d];
+          l_off[d] += g0[d];
+          if (TWO) {
+            l_dln[d] += c.f1 * c.idx[d] * g1[d];
+            l_dl[d] += c.f1 * c.idx[d] * g0[d];
+          }
+        }
+        for (int q = ND; q < 3; q++) l_v1[q] += gv[q];
+      }
+      if (TWO) {
+        const Real Q2 = st.w ? c.q2 * W : c.qw2;
+        if (deposit_adjoint<Real, ND>(l, base, g.sy, x2, y2, Q2, v2, c, g0, g1, gv)) {
+          for (int d = 0; d < ND; d++) {
+            l_offn[d] += g1[d];
+            l_off[d] += g0[d];
+            l_dln[d] -= c.f2 * c.idx[d] * g1[d];
+            l_dl[d] -= c.f2 * c.idx[d] * g0[d];
+          }
+          for (int q = ND; q < 3; q++) l_v2[q] += gv[q];
+        }
+      }
+    }
+    // walls: the reflected components change sign
+    for (int d = 0; d < ND; d++)
+      if (refl[d]) {
+        l_offn[d] = -l_offn[d];
+        l_dln[d] = -l_dln[d];
+        l_n1[d] = -l_n1[d];
+        l_n2[d] = -l_n2[d];
+      }
+    // move
+    for (int d = 0; d < ND; d++) {
+      l_off[d] += l_offn[d];
+      const Real k = c.dt * c.idx[d] * l_offn[d];
+      if (TWO) {
+        l_v1[d] += k * c.m1 * c.inv_mc;
+        l_v2[d] += k * c.m2 * c.inv_mc;
+      } else {
+        l_v1[d] += k;
+      }
+    }
+    if (TWO)
+      for (int q = 0; q < 3; q++) {
+        l_dl[q] += l_dln[q];
+        l_v1[q] += c.dt * l_dln[q];
+        l_v2[q] -= c.dt * l_dln[q];
+      }
+    velocity_adjoint(n1, l_v1, l_n1);
+    if (TWO) velocity_adjoint(n2, l_v2, l_n2);
+    // Boris
+    Real l_vm1[3] = {0, 0, 0}, l_vm2[3] = {0, 0, 0};
+    Real l_E1[3] = {0, 0, 0}, l_E2[3] = {0, 0, 0}, l_B1[3] = {0, 0, 0}, l_B2[3] = {0, 0, 0};
+    boris_adjoint(vm1, c.a1, P1.B, l_n1, l_vm1, l_E1, l_B1);
+    if (TWO) boris_adjoint(vm2, c.a2, P2.B, l_n2, l_vm2, l_E2, l_B2);
+    // friction
+    Real l_um1[3], l_um2[3] = {0, 0, 0};
+    if (TWO) {
+      const Real dD = Real(-2) * c.half_dt * rcp((Real(1) + nu * c.half_dt) *
+                                                 (Real(1) + nu * c.half_dt));
+      for (int q = 0; q < 3; q++) {
+        const Real lV = l_vm1[q] + l_vm2[q];
+        const Real lw = c.f1 * l_vm1[q] - c.f2 * l_vm2[q];
+        l_um1[q] = c.m1 * c.inv_mc * lV + Dn * lw;
+        l_um2[q] = c.m2 * c.inv_mc * lV - Dn * lw;
+        d_nu += (double)(lw * (um1[q] - um2[q]) * dD);
+      }
+    } else {
+      for (int q = 0; q < 3; q++) l_um1[q] = l_vm1[q];
+    }
+    // half kicks
+    for (int q = 0; q < 3; q++) {
+      l_u1[q] += l_um1[q];
+      l_E1[q] += c.a1 * l_um1[q];
+      if (TWO) {
+        l_u2[q] += l_um2[q];
+        l_E2[q] += c.a2 * l_um2[q];
+      }
+    }
+    // bond force: E1 = E(x1) + F / q1, E2 = E(x2) - F / q2, F = kf delta
+    if (TWO) {
+      Real lkf = 0;
+      for (int q = 0; q < 3; q++) {
+        const Real lF = c.inv_q1 * l_E1[q] - c.inv_q2 * l_E2[q];
+        l_dl[q] += kf * lF;
+        lkf += lF * dl[q];
+      }
+      d_wc += (double)(lkf * Real(-2) * c.mr * wc * soft);
+      if (c.inv_ac2 != Real(0)) {
+        // soft = (1 + r2 / a_c^2)^{-3/2}
+        const Real lsoft = lkf * (-c.mr * wc * wc);
+        const Real dsoft = Real(-1.5) * c.inv_ac2 * rq * rq * rq * rq * rq;
+        for (int q = 0; q < 3; q++) l_dl[q] += Real(2) * dl[q] * lsoft * dsoft;
+      }
+    }
+    // gather
+    Real lx1[2] = {0, 0}, lx2[2] = {0, 0};
+    Sink<Real> k;
+    k.l = l;
+    k.gbase = base;
+    k.gsy = g.sy;
+    k.lds = nullptr;
+    k.lbase = k.lsy = k.lplane = 0;
+    if (box.lds) {
+      const int cx = ci[0] - box.x0, cy = ND > 1 ? ci[1] - box.y0 : 0;
+      if (cx >= 0 && cx < box.tx && cy >= 0 && cy < box.ty) {
+        k.lds = box.lds;
+        k.lbase = (cx + 2) + (ND > 1 ? (cy + 2) * box.pitch : 0);
+        k.lsy = box.pitch;
+        k.lplane = box.plane;
+      }
+    }
+    if (TWO && same_nodes<Real, ND>(P1, P2)) {
+      scatter_pair<Real, ND>(k, P1, l_E1, l_B1, P2, l_E2, l_B2);
+    } else {
+      scatter_body<Real, ND>(k, P1, l_E1, l_B1);
+      if (TWO) scatter_body<Real, ND>(k, P2, l_E2, l_B2);
+    }
+    position_adjoint<Real, ND>(P1, l_E1, l_B1, lx1);
+    if (TWO) position_adjoint<Real, ND>(P2, l_E2, l_B2, lx2);
+    for (int d = 0; d < ND; d++) {
+      l_off[d] += lx1[d] + lx2[d];
+      if (TWO) l_dl[d] += c.idx[d] * (c.f1 * lx1[d] - c.f2 * lx2[d]);
+    }
+    // adjoint state at the start of the step
+    for (int d = 0; d < ND; d++) lp.off[d][p] = l_off[d];
+    for (int q = 0; q < 3; q++) {
+      lp.u1[q][p] = l_u1[q];
+      if (TWO) {
+        lp.u2[q][p] = l_u2[q];
+        lp.dl[q][p] = l_dl[q];
+      }
+    }
+  } while (false);
+}
+
 template <typename Real, int ND, bool TWO>
 __global__ void __launch_bounds__(256)
     k_adjoint_push(GridInfo g, FieldPtrs<Real> f, AdjState<Real> st, PushConst<Real> c,
@@ -398,230 +724,58 @@ __global__ void __launch_bounds__(256)
   __shared__ double sh[4];
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double d_wc = 0.0, d_nu = 0.0;
-  if (p < st.n) {
-    do {
-      // ---- stored state at the start of the step
-      int ci[3] = {0, 0, 0};
-      const uint32_t pk = st.cell[p];
-      ci[0] = pk & ((1u << g.bits[0]) - 1u);
-      if (ND > 1) ci[1] = (pk >> g.bits[0]) & ((1u << g.bits[1]) - 1u);
-      Real off[3] = {0, 0, 0}, u1[3], u2[3] = {0, 0, 0}, dl[3] = {0, 0, 0};
-      for (int d = 0; d < ND; d++) off[d] = st.off[d][p];
-      for (int q = 0; q < 3; q++) {
-        u1[q] = st.u1[q][p];
-        if (TWO) {
-          u2[q] = st.u2[q][p];
-          dl[q] = st.dl[q][p];
-        }
-      }
-      const Real wc = TWO ? (st.wc ? st.wc[p] : c.omega_c) : Real(0);
-      const Real W = st.w ? st.w[p] : Real(1);
-      bool ok = true;
-      Real x1[3] = {0, 0, 0}, x2[3] = {0, 0, 0};
-      for (int d = 0; d < ND; d++) {
-        ok = ok && isfinite(off[d]) && off[d] >= Real(0) && off[d] <= Real(1);
-        const Real sd = dl[d] * c.idx[d];
-        if (TWO) ok = ok && fabs(sd) < Real(0.5);
-        x1[d] = off[d] + (TWO ? c.f1 * sd : Real(0));
-        x2[d] = off[d] - (TWO ? c.f2 * sd : Real(0));
-      }
-      for (int q = 0; q < 3; q++) ok = ok && isfinite(u1[q]) && isfinite(u2[q]) && isfinite(dl[q]);
-      if (!ok) break;  // the forward cycle left it unchanged: identity
-      const int64_t base = g.origin + ci[0] + (ND > 1 ? (int64_t)ci[1] * g.sy : 0);
+  TileBox box{};
+  if (p < st.n) adjoint_one<Real, ND, TWO>(g, f, st, c, lp, l, p, box, d_wc, d_nu);
+  const double s_wc = block_sum<Real>(d_wc, sh);
+  const double s_nu = block_sum<Real>(d_nu, sh);
+  if (threadIdx.x == 0) {
+    if (s_wc != 0.0) atomicAdd(&dparam[0], s_wc);
+    if (s_nu != 0.0) atomicAdd(&dparam[1], s_nu);
+  }
+}
 
-      // ---- forward recomputation
-      Probe<Real, ND> P1, P2;
-      probe_fields<Real, ND>(f, base, g.sy, x1, P1);
-      if (TWO) probe_fields<Real, ND>(f, base, g.sy, x2, P2);
-      Real E1[3], E2[3] = {0, 0, 0}, um1[3], um2[3] = {0, 0, 0};
-      Real r2 = 0, rq = 1, soft = 1, kf = 0;
-      if (TWO) {
-        r2 = dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2];
-        if (c.inv_ac2 != Real(0)) {
-          rq = rsq(Real(1) + r2 * c.inv_ac2);
-          soft = rq * rq * rq;
-        }
-        kf = -c.mr * wc * wc * soft;
-      }
-      for (int q = 0; q < 3; q++) {
-        const Real F = kf * dl[q];
-        E1[q] = P1.E[q] + (TWO ? F * c.inv_q1 : Real(0));
-        um1[q] = u1[q] + c.a1 * E1[q];
-        if (TWO) {
-          E2[q] = P2.E[q] - F * c.inv_q2;
-          um2[q] = u2[q] + c.a2 * E2[q];
-        }
-      }
-      // friction on the relative momentum (identity when nu = 0)
-      const Real nu = TWO ? c.nu + c.nu_per_omega * wc : Real(0);
-      const Real Dn = (Real(1) - nu * c.half_dt) * rcp(Real(1) + nu * c.half_dt);
-      Real vm1[3], vm2[3] = {0, 0, 0};
-      for (int q = 0; q < 3; q++) {
-        if (TWO) {
-          const Real V = (c.m1 * um1[q] + c.m2 * um2[q]) * c.inv_mc;
-          const Real w = (um1[q] - um2[q]) * Dn;
-          vm1[q] = V + c.f1 * w;
-          vm2[q] = V - c.f2 * w;
-        } else {
-          vm1[q] = um1[q];
-        }
-      }
-      Real n1[3], n2[3] = {0, 0, 0}, v1[3], v2[3] = {0, 0, 0};
-      boris_forward(vm1, c.a1, E1, P1.B, n1);
-      if (TWO) boris_forward(vm2, c.a2, E2, P2.B, n2);
-      {
-        const Real i1 = rsq(Real(1) + n1[0] * n1[0] + n1[1] * n1[1] + n1[2] * n1[2]);
-        const Real i2 = rsq(Real(1) + n2[0] * n2[0] + n2[1] * n2[1] + n2[2] * n2[2]);
-        for (int q = 0; q < 3; q++) {
-          v1[q] = n1[q] * i1;
-          v2[q] = n2[q] * i2;
-        }
-      }
-      Real dln[3], offn[3] = {0, 0, 0};
-      for (int q = 0; q < 3; q++) dln[q] = TWO ? dl[q] + c.dt * (v1[q] - v2[q]) : Real(0);
-      bool refl[3] = {false, false, false};
-      for (int d = 0; d < ND; d++) {
-        const Real vc = TWO ? (c.m1 * v1[d] + c.m2 * v2[d]) * c.inv_mc : v1[d];
-        offn[d] = off[d] + c.dt * vc * c.idx[d];
-        refl[d] = reflect_wall(g.periodic[d], ci[d], g.n[d], g.pad, offn[d]);
-        if (refl[d]) dln[d] = -dln[d];
-      }
-      Real y1[3] = {0, 0, 0}, y2[3] = {0, 0, 0};
-      for (int d = 0; d < ND; d++) {
-        const Real sd = dln[d] * c.idx[d];
-        y1[d] = offn[d] + (TWO ? c.f1 * sd : Real(0));
-        y2[d] = offn[d] - (TWO ? c.f2 * sd : Real(0));
-      }
-
-      // ---- reverse
-      Real l_off[3] = {0, 0, 0}, l_dl[3] = {0, 0, 0}, l_u1[3] = {0, 0, 0}, l_u2[3] = {0, 0, 0};
-      Real l_offn[3] = {0, 0, 0}, l_dln[3] = {0, 0, 0}, l_n1[3], l_n2[3] = {0, 0, 0};
-      for (int d = 0; d < ND; d++) l_offn[d] = lp.off[d][p];
-      for (int q = 0; q < 3; q++) {
-        l_n1[q] = lp.u1[q][p];
-        if (TWO) {
-          l_n2[q] = lp.u2[q][p];
-          l_dln[q] = lp.dl[q][p];
-        }
-      }
-      Real l_v1[3] = {0, 0, 0}, l_v2[3] = {0, 0, 0};
-      if (c.deposit) {
-        const Real Q1 = st.w ? c.q1 * W : c.qw1;
-        Real g0[2], g1[2], gv[3];
-        if (deposit_adjoint<Real, ND>(l, base, g.sy, x1, y1, Q1, v1, c, g0, g1, gv)) {
-          for (int d = 0; d < ND; d++) {
-            l_offn[d] += g1[d];
-            l_off[d] += g0[d];
-            if (TWO) {
-              l_dln[d] += c.f1 * c.idx[d] * g1[d];
-              l_dl[d] += c.f1 * c.idx[d] * g0[d];
-            }
-          }
-          for (int q = ND; q < 3; q++) l_v1[q] += gv[q];
-        }
-        if (TWO) {
-          const Real Q2 = st.w ? c.q2 * W : c.qw2;
-          if (deposit_adjoint<Real, ND>(l, base, g.sy, x2, y2, Q2, v2, c, g0, g1, gv)) {
-            for (int d = 0; d < ND; d++) {
-              l_offn[d] += g1[d];
-              l_off[d] += g0[d];
-              l_dln[d] -= c.f2 * c.idx[d] * g1[d];
-              l_dl[d] -= c.f2 * c.idx[d] * g0[d];
-            }
-            for (int q = ND; q < 3; q++) l_v2[q] += gv[q];
-          }
-        }
-      }
-      // walls: the reflected components change sign
-      for (int d = 0; d < ND; d++)
-        if (refl[d]) {
-          l_offn[d] = -l_offn[d];
-          l_dln[d] = -l_dln[d];
-          l_n1[d] = -l_n1[d];
-          l_n2[d] = -l_n2[d];
-        }
-      // move
-      for (int d = 0; d < ND; d++) {
-        l_off[d] += l_offn[d];
-        const Real k = c.dt * c.idx[d] * l_offn[d];
-        if (TWO) {
-          l_v1[d] += k * c.m1 * c.inv_mc;
-          l_v2[d] += k * c.m2 * c.inv_mc;
-        } else {
-          l_v1[d] += k;
-        }
-      }
-      if (TWO)
-        for (int q = 0; q < 3; q++) {
-          l_dl[q] += l_dln[q];
-          l_v1[q] += c.dt * l_dln[q];
-          l_v2[q] -= c.dt * l_dln[q];
-        }
-      velocity_adjoint(n1, l_v1, l_n1);
-      if (TWO) velocity_adjoint(n2, l_v2, l_n2);
-      // Boris
-      Real l_vm1[3] = {0, 0, 0}, l_vm2[3] = {0, 0, 0};
-      Real l_E1[3] = {0, 0, 0}, l_E2[3] = {0, 0, 0}, l_B1[3] = {0, 0, 0}, l_B2[3] = {0, 0, 0};
-      boris_adjoint(vm1, c.a1, P1.B, l_n1, l_vm1, l_E1, l_B1);
-      if (TWO) boris_adjoint(vm2, c.a2, P2.B, l_n2, l_vm2, l_E2, l_B2);
-      // friction
-      Real l_um1[3], l_um2[3] = {0, 0, 0};
-      if (TWO) {
-        const Real dD = Real(-2) * c.half_dt * rcp((Real(1) + nu * c.half_dt) *
-                                                   (Real(1) + nu * c.half_dt));
-        for (int q = 0; q < 3; q++) {
-          const Real lV = l_vm1[q] + l_vm2[q];
-          const Real lw = c.f1 * l_vm1[q] - c.f2 * l_vm2[q];
-          l_um1[q] = c.m1 * c.inv_mc * lV + Dn * lw;
-          l_um2[q] = c.m2 * c.inv_mc * lV - Dn * lw;
-          d_nu += (double)(lw * (um1[q] - um2[q]) * dD);
-        }
-      } else {
-        for (int q = 0; q < 3; q++) l_um1[q] = l_vm1[q];
-      }
-      // half kicks
-      for (int q = 0; q < 3; q++) {
-        l_u1[q] += l_um1[q];
-        l_E1[q] += c.a1 * l_um1[q];
-        if (TWO) {
-          l_u2[q] += l_um2[q];
-          l_E2[q] += c.a2 * l_um2[q];
-        }
-      }
-      // bond force: E1 = E(x1) + F / q1, E2 = E(x2) - F / q2, F = kf delta
-      if (TWO) {
-        Real lkf = 0;
-        for (int q = 0; q < 3; q++) {
-          const Real lF = c.inv_q1 * l_E1[q] - c.inv_q2 * l_E2[q];
-          l_dl[q] += kf * lF;
-          lkf += lF * dl[q];
-        }
-        d_wc += (double)(lkf * Real(-2) * c.mr * wc * soft);
-        if (c.inv_ac2 != Real(0)) {
-          // soft = (1 + r2 / a_c^2)^{-3/2}
-          const Real lsoft = lkf * (-c.mr * wc * wc);
-          const Real dsoft = Real(-1.5) * c.inv_ac2 * rq * rq * rq * rq * rq;
-          for (int q = 0; q < 3; q++) l_dl[q] += Real(2) * dl[q] * lsoft * dsoft;
-        }
-      }
-      // gather
-      Real lx1[2] = {0, 0}, lx2[2] = {0, 0};
-      gather_adjoint<Real, ND>(l, base, g.sy, P1, l_E1, l_B1, lx1);
-      if (TWO) gather_adjoint<Real, ND>(l, base, g.sy, P2, l_E2, l_B2, lx2);
-      for (int d = 0; d < ND; d++) {
-        l_off[d] += lx1[d] + lx2[d];
-        if (TWO) l_dl[d] += c.idx[d] * (c.f1 * lx1[d] - c.f2 * lx2[d]);
-      }
-      // adjoint state at the start of the step
-      for (int d = 0; d < ND; d++) lp.off[d][p] = l_off[d];
-      for (int q = 0; q < 3; q++) {
-        lp.u1[q][p] = l_u1[q];
-        if (TWO) {
-          lp.u2[q][p] = l_u2[q];
-          lp.dl[q][p] = l_dl[q];
-        }
-      }
-    } while (false);
+// One workgroup per tile of the sorted particle order: the gather's
+// transpose of the tile's particles accumulates in an FP64 LDS patch
+// (LDS atomics, 64-bit ones issue an order of magnitude faster than FP32
+// ones on gfx950), flushed to the global adjoint planes once; particles
+// that have left the tile since the sort scatter to the global planes
+// directly.
+template <typename Real, int ND, bool TWO>
+__global__ void __launch_bounds__(256)
+    k_adjoint_tiled(GridInfo g, FieldPtrs<Real> f, AdjState<Real> st, PushConst<Real> c,
+                    AdjState<Real> lp, FieldPtrs<Real> l, double* dparam,
+                    const uint32_t* tile_off, AdjTiles tt) {
+  extern __shared__ double patch[];
+  __shared__ double sh[4];
+  const int t = blockIdx.x;
+  const int64_t p0 = tile_off[t], p1 = tile_off[t + 1];
+  if (p0 == p1) return;  // uniform over the workgroup
+  TileBox box;
+  box.lds = patch;
+  box.tx = tt.T[0];
+  box.ty = ND > 1 ? tt.T[1] : 1;
+  box.x0 = (t % tt.nt[0]) * tt.T[0];
+  box.y0 = ND > 1 ? (t / tt.nt[0]) * tt.T[1] : 0;
+  box.pitch = box.tx + 4;
+  box.plane = box.pitch * (ND > 1 ? box.ty + 4 : 1);
+  for (int q = threadIdx.x; q < 6 * box.plane; q += blockDim.x) patch[q] = 0.0;
+  __syncthreads();
+  double d_wc = 0.0, d_nu = 0.0;
+  for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x)
+    adjoint_one<Real, ND, TWO>(g, f, st, c, lp, l, p, box, d_wc, d_nu);
+  __syncthreads();
+  // flush: patch node (px, py) is global node (x0 - 2 + px, y0 - 2 + py)
+  for (int q = threadIdx.x; q < 6 * box.plane; q += blockDim.x) {
+    const double v = patch[q];
+    if (v == 0.0) continue;
+    const int comp = q / box.plane, r = q % box.plane;
+    const int px = r % box.pitch, py = r / box.pitch;
+    const int gx = box.x0 - 2 + px, gy = box.y0 - 2 + py;
+    if (gx < -kGuard || gx >= g.n[0] + kGuard) continue;
+    if (ND > 1 && (gy < -kGuard || gy >= g.n[1] + kGuard)) continue;
+    const int64_t o = g.origin + (box.x0 - 2 + px) + (ND > 1 ? (int64_t)(box.y0 - 2 + py) * g.sy : 0);
+    Real* F = comp < 3 ? l.E[comp] : l.B[comp - 3];
+    unsafeAtomicAdd(F + o, (Real)v);
   }
   const double s_wc = block_sum<Real>(d_wc, sh);
   const double s_nu = block_sum<Real>(d_nu, sh);
@@ -636,10 +790,26 @@ __global__ void __launch_bounds__(256)
 template <typename Real>
 void launch_adjoint_push(const GridInfo& g, const FieldPtrs<Real>& f, const AdjState<Real>& st,
                          const PushConst<Real>& c, const AdjState<Real>& lp,
-                         const FieldPtrs<Real>& l, double* dparam, hipStream_t stream) {
+                         const FieldPtrs<Real>& l, double* dparam, const uint32_t* tile_off,
+                         const AdjTiles& tt, hipStream_t stream) {
   if (st.n <= 0) return;
-  dim3 grid((unsigned)((st.n + 255) / 256));
   const bool two = c.two_body != 0;
+  if (tile_off) {
+    const int ntile = tt.nt[0] * (g.nd > 1 ? tt.nt[1] : 1);
+    const size_t lds = 6 * sizeof(double) * (size_t)(tt.T[0] + 4) *
+                       (size_t)(g.nd > 1 ? tt.T[1] + 4 : 1);
+    dim3 grid((unsigned)ntile);
+#define PIC_ADJ_TILED(ND_, TWO_)                                                                 \
+    hipLaunchKernelGGL((k_adjoint_tiled<Real, ND_, TWO_>), grid, 256, lds, stream, g, f, st, c, lp, \
+                       l, dparam, tile_off, tt)
+    if (g.nd == 1 && two) PIC_ADJ_TILED(1, true);
+    if (g.nd == 1 && !two) PIC_ADJ_TILED(1, false);
+    if (g.nd == 2 && two) PIC_ADJ_TILED(2, true);
+    if (g.nd == 2 && !two) PIC_ADJ_TILED(2, false);
+#undef PIC_ADJ_TILED
+    return;
+  }
+  dim3 grid((unsigned)((st.n + 255) / 256));
   if (g.nd == 1 && two)
     hipLaunchKernelGGL((k_adjoint_push<Real, 1, true>), grid, 256, 0, stream, g, f, st, c, lp, l, dparam);
   if (g.nd == 1 && !two)
@@ -653,10 +823,10 @@ void launch_adjoint_push(const GridInfo& g, const FieldPtrs<Real>& f, const AdjS
 template void launch_adjoint_push<float>(const GridInfo&, const FieldPtrs<float>&,
                                          const AdjState<float>&, const PushConst<float>&,
                                          const AdjState<float>&, const FieldPtrs<float>&, double*,
-                                         hipStream_t);
+                                         const uint32_t*, const AdjTiles&, hipStream_t);
 template void launch_adjoint_push<double>(const GridInfo&, const FieldPtrs<double>&,
                                           const AdjState<double>&, const PushConst<double>&,
                                           const AdjState<double>&, const FieldPtrs<double>&,
-                                          double*, hipStream_t);
+                                          double*, const uint32_t*, const AdjTiles&, hipStream_t);
 
 }  // namespace pic

@@ -259,6 +259,8 @@ int load_particles_t(pic_ctx* c, SpeciesHost& s, int64_t n, const double* x, con
 
 // ------------------------------------------------------------ stepping
 
+}  // namespace
+
 // start/stop events around one particle-kernel launch (PIC_FLAG_TIMING)
 constexpr size_t kMaxEvents = 1 << 16;
 bool record_event(pic_ctx* c, int species, bool start) {
@@ -275,6 +277,8 @@ bool record_event(pic_ctx* c, int species, bool start) {
   }
   return hipEventRecord(c->ev[c->ev_used++], c->stream) == hipSuccess;
 }
+
+namespace {
 
 // timing events around each dispatch of the main particle kernel of one
 // species (every colour of the tiled kernel; the outside-tile list kernel

@@ -220,6 +220,11 @@ inline pic::LaserDev laser_dev(const pic_ctx* c) {
   return las;
 }
 
+// Record a start (or stop) event of a timed particle-kernel dispatch with
+// the given tag (species index; PIC_TIMING_ADJOINT + species for the
+// adjoint kernel) when PIC_FLAG_TIMING is set.
+bool record_event(pic_ctx* c, int tag, bool start);
+
 // What one step does besides advancing the state.
 struct StepOpts {
   bool check = false;   // charge-continuity residual of this step
