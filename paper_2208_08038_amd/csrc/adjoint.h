@@ -13,10 +13,12 @@ template <typename Real>
 using AdjState = SpeciesDev<Real>;
 
 // Reverse the particle cycle of one step for one species (1D and 2D
-// grids): reads the stored state `st`, the fields f (E, B at the start of
-// the step, guards filled) and the adjoint current l.J; updates the
-// particle adjoint `lp` in place, adds the gather's transpose into l.E and
-// l.B, and adds d/d(omega_c) and d/d(friction rate) to dparam[0], dparam[1].
+// grids): reads the stored state `st`, the fields (E, B planes at the start
+// of the step, guards filled, contiguous from `fields`, g.plane apart) and
+// the adjoint current (planes 6..8 of `lam`, whose planes 0..5 are the
+// adjoint E, B); updates the particle adjoint `lp` in place, adds the
+// gather's transpose into the adjoint E, B, and adds d/d(omega_c) and
+// d/d(friction rate) to dparam[0], dparam[1].
 // Tiles of the sorted particle order (cells per tile, tiles per dim).
 struct AdjTiles {
   int T[2];
@@ -27,9 +29,9 @@ struct AdjTiles {
 // gradient run keeps) one workgroup per tile accumulates the scatter in LDS;
 // without, one thread per particle scatters with global atomics.
 template <typename Real>
-void launch_adjoint_push(const GridInfo& g, const FieldPtrs<Real>& f, const AdjState<Real>& st,
-                         const PushConst<Real>& c, const AdjState<Real>& lp,
-                         const FieldPtrs<Real>& l, double* dparam, const uint32_t* tile_off,
-                         const AdjTiles& tt, hipStream_t stream);
+void launch_adjoint_push(const GridInfo& g, const Real* fields, const AdjState<Real>& st,
+                         const PushConst<Real>& c, const AdjState<Real>& lp, Real* lam,
+                         double* dparam, const uint32_t* tile_off, const AdjTiles& tt,
+                         hipStream_t stream);
 
 }  // namespace pic

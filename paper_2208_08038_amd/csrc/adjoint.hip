@@ -27,6 +27,18 @@ namespace pic {
 
 namespace {
 
+// Component planes of a field array stored contiguously (E0..E2, B0..B2,
+// J0..J2, `plane` values apart): one base pointer instead of nine keeps
+// the kernel arguments in few scalar registers.
+template <typename Real>
+struct Planes {
+  Real* base;
+  int64_t plane;
+  __device__ __forceinline__ Real* E(int a) const { return base + a * plane; }
+  __device__ __forceinline__ Real* B(int a) const { return base + (3 + a) * plane; }
+  __device__ __forceinline__ Real* J(int a) const { return base + (6 + a) * plane; }
+};
+
 // Quadratic B-spline weights and their derivatives with respect to the
 // position at the nearest node n = floor(x + 1/2) (integer stagger) or
 // n = floor(x) (half stagger, node i at i + 1/2): nodes n-1, n, n+1.
@@ -62,29 +74,6 @@ __device__ __forceinline__ Shape<Real> unit_shape() {
   return s;
 }
 
-// Interpolant of one field component and its gradient (cell units).
-template <typename Real, int ND>
-__device__ __forceinline__ Real interp_grad(const Real* __restrict__ F, int64_t base, int64_t sy,
-                                            const Shape<Real>& sx, const Shape<Real>& syy,
-                                            Real grad[2]) {
-  Real v = 0, gx = 0, gy = 0;
-  const int ny = ND > 1 ? 3 : 1;
-  for (int s = 0; s < ny; s++) {
-    const Real* row = F + base + sx.i0 + (ND > 1 ? (int64_t)(syy.i0 + s) * sy : 0);
-    const Real r0 = row[0], r1 = row[1], r2 = row[2];
-    const Real rv = sx.w[0] * r0 + sx.w[1] * r1 + sx.w[2] * r2;
-    const Real rd = sx.dw[0] * r0 + sx.dw[1] * r1 + sx.dw[2] * r2;
-    const Real wy = ND > 1 ? syy.w[s] : Real(1);
-    const Real dy = ND > 1 ? syy.dw[s] : Real(0);
-    v += wy * rv;
-    gx += wy * rd;
-    gy += dy * rv;
-  }
-  grad[0] = gx;
-  grad[1] = gy;
-  return v;
-}
-
 // Destination of the gather's transpose for one particle: an FP64 LDS
 // patch of the workgroup's tile (component planes of `lplane` values, row
 // pitch `lsy`, the particle's cell at index `lbase`), or the global adjoint
@@ -92,7 +81,7 @@ __device__ __forceinline__ Real interp_grad(const Real* __restrict__ F, int64_t 
 // relative to the particle's cell.
 template <typename Real>
 struct Sink {
-  FieldPtrs<Real> l;
+  Planes<Real> l;
   int64_t gbase, gsy;
   double* lds;
   int lbase, lsy, lplane;
@@ -100,112 +89,148 @@ struct Sink {
     if (lds) {
       atomicAdd(lds + comp * lplane + lbase + ix + iy * lsy, (double)v);
     } else {
-      Real* F = comp < 3 ? l.E[comp] : l.B[comp - 3];
+      Real* F = l.base + comp * l.plane;
       unsafeAtomicAdd(F + gbase + ix + iy * gsy, v);
     }
   }
 };
 
-// Transpose of the interpolation: node += lam * weight(node).
-template <typename Real, int ND>
-__device__ __forceinline__ void scatter(const Sink<Real>& k, int comp, const Shape<Real>& sx,
-                                        const Shape<Real>& syy, Real lam) {
-  if (lam == Real(0)) return;
-  const int ny = ND > 1 ? 3 : 1;
-  for (int s = 0; s < ny; s++) {
-    const Real wy = ND > 1 ? syy.w[s] : Real(1);
-    const int iy = ND > 1 ? syy.i0 + s : 0;
-#pragma unroll
-    for (int r = 0; r < 3; r++) k.add(comp, sx.i0 + r, iy, lam * wy * sx.w[r]);
-  }
-}
-
-// Both bodies on the same nodes: one add per node with the two weights.
-template <typename Real, int ND>
-__device__ __forceinline__ void scatter2(const Sink<Real>& k, int comp, const Shape<Real>& ax,
-                                         const Shape<Real>& ay, Real la, const Shape<Real>& bx,
-                                         const Shape<Real>& by, Real lb) {
-  if (la == Real(0) && lb == Real(0)) return;
-  const int ny = ND > 1 ? 3 : 1;
-  for (int s = 0; s < ny; s++) {
-    const Real wa = ND > 1 ? la * ay.w[s] : la;
-    const Real wb = ND > 1 ? lb * by.w[s] : lb;
-    const int iy = ND > 1 ? ay.i0 + s : 0;
-#pragma unroll
-    for (int r = 0; r < 3; r++) k.add(comp, ax.i0 + r, iy, wa * ax.w[r] + wb * bx.w[r]);
-  }
-}
-
-// Field values and position gradients of E and B at one body position x
-// (cell units relative to the cell at `base`).
-template <typename Real, int ND>
-struct Probe {
-  Shape<Real> n[2], h[2];  // integer / half stagger per resolved dim
-  Real E[3], B[3], gE[3][2], gB[3][2];
+// Quadratic B-spline shapes of one body at the integer (n) and half (h)
+// staggers of each resolved axis (unit shapes along unresolved ones).
+template <typename Real>
+struct Stencil {
+  Shape<Real> n[2], h[2];
 };
 
 template <typename Real, int ND>
-__device__ __forceinline__ void probe_fields(const FieldPtrs<Real>& f, int64_t base, int64_t sy,
-                                             const Real x[3], Probe<Real, ND>& p) {
+__device__ __forceinline__ Stencil<Real> stencil_at(const Real x[3]) {
+  Stencil<Real> s;
+#pragma unroll
   for (int d = 0; d < 2; d++) {
     if (d < ND) {
-      p.n[d] = shape_at(x[d], false);
-      p.h[d] = shape_at(x[d], true);
+      s.n[d] = shape_at(x[d], false);
+      s.h[d] = shape_at(x[d], true);
     } else {
-      p.n[d] = p.h[d] = unit_shape<Real>();
+      s.n[d] = s.h[d] = unit_shape<Real>();
     }
   }
-  // E_a half-staggered along a; B_a along the other axes (z unresolved)
-  p.E[0] = interp_grad<Real, ND>(f.E[0], base, sy, p.h[0], p.n[1], p.gE[0]);
-  p.E[1] = interp_grad<Real, ND>(f.E[1], base, sy, p.n[0], p.h[1], p.gE[1]);
-  p.E[2] = interp_grad<Real, ND>(f.E[2], base, sy, p.n[0], p.n[1], p.gE[2]);
-  p.B[0] = interp_grad<Real, ND>(f.B[0], base, sy, p.n[0], p.h[1], p.gB[0]);
-  p.B[1] = interp_grad<Real, ND>(f.B[1], base, sy, p.h[0], p.n[1], p.gB[1]);
-  p.B[2] = interp_grad<Real, ND>(f.B[2], base, sy, p.h[0], p.h[1], p.gB[2]);
+  return s;
 }
 
-// d/dx of one body's interpolated fields contracted with lambda_E, lambda_B.
 template <typename Real, int ND>
-__device__ __forceinline__ void position_adjoint(const Probe<Real, ND>& p, const Real lE[3],
-                                                 const Real lB[3], Real lx[2]) {
-  for (int d = 0; d < ND; d++) {
-    Real s = 0;
-    for (int a = 0; a < 3; a++) s += lE[a] * p.gE[a][d] + lB[a] * p.gB[a][d];
-    lx[d] = s;
+__device__ __forceinline__ Real interp_value(const Real* __restrict__ F, int64_t base, int64_t sy,
+                                             const Shape<Real>& sx, const Shape<Real>& syy) {
+  Real v = 0;
+  constexpr int NY = ND > 1 ? 3 : 1;
+#pragma unroll
+  for (int s = 0; s < NY; s++) {
+    const Real* row = F + base + sx.i0 + (ND > 1 ? (int64_t)(syy.i0 + s) * sy : 0);
+    const Real wy = ND > 1 ? syy.w[s] : Real(1);
+    v += wy * (sx.w[0] * row[0] + sx.w[1] * row[1] + sx.w[2] * row[2]);
+  }
+  return v;
+}
+
+// E and B at a body position (the gather of the forward cycle): E_a
+// half-staggered along a, B_a along the other axes (z unresolved).
+template <typename Real, int ND>
+__device__ __forceinline__ void gather_values(const Planes<Real>& f, int64_t base, int64_t sy,
+                                              const Real x[3], Real E[3], Real B[3]) {
+  const Stencil<Real> t = stencil_at<Real, ND>(x);
+  E[0] = interp_value<Real, ND>(f.E(0), base, sy, t.h[0], t.n[1]);
+  E[1] = interp_value<Real, ND>(f.E(1), base, sy, t.n[0], t.h[1]);
+  E[2] = interp_value<Real, ND>(f.E(2), base, sy, t.n[0], t.n[1]);
+  B[0] = interp_value<Real, ND>(f.B(0), base, sy, t.n[0], t.h[1]);
+  B[1] = interp_value<Real, ND>(f.B(1), base, sy, t.h[0], t.n[1]);
+  B[2] = interp_value<Real, ND>(f.B(2), base, sy, t.h[0], t.h[1]);
+}
+
+// Adjoint of one interpolated component for one body, in one pass over its
+// nodes: scatter lam * weight(node) and add lam * d(interpolant)/dx to lx.
+template <typename Real, int ND>
+__device__ __forceinline__ void comp_adjoint(const Real* __restrict__ F, int comp,
+                                             const Sink<Real>& k, int64_t base, int64_t sy,
+                                             const Shape<Real>& sx, const Shape<Real>& syy,
+                                             Real lam, Real lx[2]) {
+  if (lam == Real(0)) return;
+  constexpr int NY = ND > 1 ? 3 : 1;
+#pragma unroll
+  for (int s = 0; s < NY; s++) {
+    const int iy = ND > 1 ? syy.i0 + s : 0;
+    const Real* row = F + base + sx.i0 + (ND > 1 ? (int64_t)iy * sy : 0);
+    const Real r0 = row[0], r1 = row[1], r2 = row[2];
+    const Real wy = ND > 1 ? syy.w[s] : Real(1);
+    lx[0] += lam * wy * (sx.dw[0] * r0 + sx.dw[1] * r1 + sx.dw[2] * r2);
+    if (ND > 1) lx[1] += lam * syy.dw[s] * (sx.w[0] * r0 + sx.w[1] * r1 + sx.w[2] * r2);
+    const Real a = lam * wy;
+#pragma unroll
+    for (int r = 0; r < 3; r++) k.add(comp, sx.i0 + r, iy, a * sx.w[r]);
   }
 }
 
-// The gather's transpose for one body: scatter lambda_E, lambda_B with the
-// gather weights of every component's stagger.
+// Same for both bodies of an ion when their stencils share the nodes: one
+// add per node with both weights.
 template <typename Real, int ND>
-__device__ __forceinline__ void scatter_body(const Sink<Real>& k, const Probe<Real, ND>& p,
-                                             const Real lE[3], const Real lB[3]) {
-  scatter<Real, ND>(k, 0, p.h[0], p.n[1], lE[0]);
-  scatter<Real, ND>(k, 1, p.n[0], p.h[1], lE[1]);
-  scatter<Real, ND>(k, 2, p.n[0], p.n[1], lE[2]);
-  scatter<Real, ND>(k, 3, p.n[0], p.h[1], lB[0]);
-  scatter<Real, ND>(k, 4, p.h[0], p.n[1], lB[1]);
-  scatter<Real, ND>(k, 5, p.h[0], p.h[1], lB[2]);
+__device__ __forceinline__ void comp_adjoint2(const Real* __restrict__ F, int comp,
+                                              const Sink<Real>& k, int64_t base, int64_t sy,
+                                              const Shape<Real>& ax, const Shape<Real>& ay,
+                                              Real la, const Shape<Real>& bx,
+                                              const Shape<Real>& by, Real lb, Real lxa[2],
+                                              Real lxb[2]) {
+  if (la == Real(0) && lb == Real(0)) return;
+  constexpr int NY = ND > 1 ? 3 : 1;
+#pragma unroll
+  for (int s = 0; s < NY; s++) {
+    const int iy = ND > 1 ? ay.i0 + s : 0;
+    const Real* row = F + base + ax.i0 + (ND > 1 ? (int64_t)iy * sy : 0);
+    const Real r0 = row[0], r1 = row[1], r2 = row[2];
+    const Real wya = ND > 1 ? ay.w[s] : Real(1), wyb = ND > 1 ? by.w[s] : Real(1);
+    lxa[0] += la * wya * (ax.dw[0] * r0 + ax.dw[1] * r1 + ax.dw[2] * r2);
+    lxb[0] += lb * wyb * (bx.dw[0] * r0 + bx.dw[1] * r1 + bx.dw[2] * r2);
+    if (ND > 1) {
+      lxa[1] += la * ay.dw[s] * (ax.w[0] * r0 + ax.w[1] * r1 + ax.w[2] * r2);
+      lxb[1] += lb * by.dw[s] * (bx.w[0] * r0 + bx.w[1] * r1 + bx.w[2] * r2);
+    }
+    const Real a = la * wya, b = lb * wyb;
+#pragma unroll
+    for (int r = 0; r < 3; r++) k.add(comp, ax.i0 + r, iy, a * ax.w[r] + b * bx.w[r]);
+  }
+}
+
+// The gather's transpose for a body at x (or, with TWO_SHARED, for both
+// bodies of an ion whose stencils share the nodes).
+template <typename Real, int ND>
+__device__ __forceinline__ void gather_adjoint(const Planes<Real>& f, const Sink<Real>& k,
+                                               int64_t base, int64_t sy, const Stencil<Real>& t,
+                                               const Real lE[3], const Real lB[3], Real lx[2]) {
+  comp_adjoint<Real, ND>(f.E(0), 0, k, base, sy, t.h[0], t.n[1], lE[0], lx);
+  comp_adjoint<Real, ND>(f.E(1), 1, k, base, sy, t.n[0], t.h[1], lE[1], lx);
+  comp_adjoint<Real, ND>(f.E(2), 2, k, base, sy, t.n[0], t.n[1], lE[2], lx);
+  comp_adjoint<Real, ND>(f.B(0), 3, k, base, sy, t.n[0], t.h[1], lB[0], lx);
+  comp_adjoint<Real, ND>(f.B(1), 4, k, base, sy, t.h[0], t.n[1], lB[1], lx);
+  comp_adjoint<Real, ND>(f.B(2), 5, k, base, sy, t.h[0], t.h[1], lB[2], lx);
 }
 
 template <typename Real, int ND>
-__device__ __forceinline__ bool same_nodes(const Probe<Real, ND>& a, const Probe<Real, ND>& b) {
+__device__ __forceinline__ void gather_adjoint2(const Planes<Real>& f, const Sink<Real>& k,
+                                                int64_t base, int64_t sy, const Stencil<Real>& a,
+                                                const Real lEa[3], const Real lBa[3],
+                                                const Stencil<Real>& b, const Real lEb[3],
+                                                const Real lBb[3], Real lxa[2], Real lxb[2]) {
+  comp_adjoint2<Real, ND>(f.E(0), 0, k, base, sy, a.h[0], a.n[1], lEa[0], b.h[0], b.n[1], lEb[0], lxa, lxb);
+  comp_adjoint2<Real, ND>(f.E(1), 1, k, base, sy, a.n[0], a.h[1], lEa[1], b.n[0], b.h[1], lEb[1], lxa, lxb);
+  comp_adjoint2<Real, ND>(f.E(2), 2, k, base, sy, a.n[0], a.n[1], lEa[2], b.n[0], b.n[1], lEb[2], lxa, lxb);
+  comp_adjoint2<Real, ND>(f.B(0), 3, k, base, sy, a.n[0], a.h[1], lBa[0], b.n[0], b.h[1], lBb[0], lxa, lxb);
+  comp_adjoint2<Real, ND>(f.B(1), 4, k, base, sy, a.h[0], a.n[1], lBa[1], b.h[0], b.n[1], lBb[1], lxa, lxb);
+  comp_adjoint2<Real, ND>(f.B(2), 5, k, base, sy, a.h[0], a.h[1], lBa[2], b.h[0], b.h[1], lBb[2], lxa, lxb);
+}
+
+template <typename Real, int ND>
+__device__ __forceinline__ bool same_nodes(const Stencil<Real>& a, const Stencil<Real>& b) {
   bool same = true;
+#pragma unroll
   for (int d = 0; d < ND; d++) same = same && a.n[d].i0 == b.n[d].i0 && a.h[d].i0 == b.h[d].i0;
   return same;
-}
-
-template <typename Real, int ND>
-__device__ __forceinline__ void scatter_pair(const Sink<Real>& k, const Probe<Real, ND>& a,
-                                             const Real lEa[3], const Real lBa[3],
-                                             const Probe<Real, ND>& b, const Real lEb[3],
-                                             const Real lBb[3]) {
-  scatter2<Real, ND>(k, 0, a.h[0], a.n[1], lEa[0], b.h[0], b.n[1], lEb[0]);
-  scatter2<Real, ND>(k, 1, a.n[0], a.h[1], lEa[1], b.n[0], b.h[1], lEb[1]);
-  scatter2<Real, ND>(k, 2, a.n[0], a.n[1], lEa[2], b.n[0], b.n[1], lEb[2]);
-  scatter2<Real, ND>(k, 3, a.n[0], a.h[1], lBa[0], b.n[0], b.h[1], lBb[0]);
-  scatter2<Real, ND>(k, 4, a.h[0], a.n[1], lBa[1], b.h[0], b.n[1], lBb[1]);
-  scatter2<Real, ND>(k, 5, a.h[0], a.h[1], lBa[2], b.h[0], b.h[1], lBb[2]);
 }
 
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
@@ -233,8 +258,10 @@ __device__ __forceinline__ void boris_forward(const Real um[3], Real a, const Re
   Real s[3] = {sk * t[0], sk * t[1], sk * t[2]};
   Real c[3], w[3], ws[3];
   cross(um, t, c);
+#pragma unroll
   for (int q = 0; q < 3; q++) w[q] = um[q] + c[q];
   cross(w, s, ws);
+#pragma unroll
   for (int q = 0; q < 3; q++) out[q] = um[q] + ws[q] + a * E[q];
 }
 
@@ -249,31 +276,37 @@ __device__ __forceinline__ void boris_adjoint(const Real um[3], Real a, const Re
   Real s[3] = {sk * t[0], sk * t[1], sk * t[2]};
   Real c[3], w[3];
   cross(um, t, c);
+#pragma unroll
   for (int q = 0; q < 3; q++) w[q] = um[q] + c[q];
   // out = um + w x s + a E
   Real lw[3], ls[3], lt[3], tmp[3];
   cross(s, lout, lw);   // lambda . (w x s) = w . (s x lambda)
   cross(lout, w, ls);   //                 = s . (lambda x w)
+#pragma unroll
   for (int q = 0; q < 3; q++) {
     lum[q] += lout[q] + lw[q];
     lE[q] += a * lout[q];
   }
   // w = um + um x t
   cross(t, lw, tmp);
+#pragma unroll
   for (int q = 0; q < 3; q++) lum[q] += tmp[q];
   cross(lw, um, lt);
   // s = sk t, sk = 2 / (1 + t.t)
   const Real lsk = t[0] * ls[0] + t[1] * ls[1] + t[2] * ls[2];
   const Real ltt = -Real(0.5) * sk * sk * lsk;
+#pragma unroll
   for (int q = 0; q < 3; q++) lt[q] += sk * ls[q] + Real(2) * t[q] * ltt;
   // t = a g B
   Real lk = 0;
+#pragma unroll
   for (int q = 0; q < 3; q++) {
     lB[q] += k * lt[q];
     lk += B[q] * lt[q];
   }
   const Real lg = a * lk;
   const Real g3 = g * g * g;
+#pragma unroll
   for (int q = 0; q < 3; q++) lum[q] -= g3 * um[q] * lg;
 }
 
@@ -283,6 +316,7 @@ __device__ __forceinline__ void velocity_adjoint(const Real n[3], const Real lv[
   const Real g = rsq(Real(1) + n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
   const Real nl = n[0] * lv[0] + n[1] * lv[1] + n[2] * lv[2];
   const Real g3 = g * g * g;
+#pragma unroll
   for (int q = 0; q < 3; q++) ln[q] += g * lv[q] - g3 * n[q] * nl;
 }
 
@@ -301,13 +335,24 @@ __device__ __forceinline__ bool win4(Real x0, Real x1, Win4<Real>& w) {
   const int sa = a.i0 - lo, sb = b.i0 - lo;
   if (sa > 1 || sb > 1) return false;
   w.lo = lo;
-  for (int r = 0; r < 4; r++) {
-    const int ra = r - sa, rb = r - sb;
-    w.S0[r] = (ra >= 0 && ra < 3) ? a.w[ra] : Real(0);
-    w.D0[r] = (ra >= 0 && ra < 3) ? a.dw[ra] : Real(0);
-    w.S1[r] = (rb >= 0 && rb < 3) ? b.w[rb] : Real(0);
-    w.D1[r] = (rb >= 0 && rb < 3) ? b.dw[rb] : Real(0);
-  }
+  // the three weights sit at window nodes sa..sa+2 (sa = 0 or 1); selects,
+  // not a runtime index, keep them in registers
+  w.S0[0] = sa ? Real(0) : a.w[0];
+  w.S0[1] = sa ? a.w[0] : a.w[1];
+  w.S0[2] = sa ? a.w[1] : a.w[2];
+  w.S0[3] = sa ? a.w[2] : Real(0);
+  w.D0[0] = sa ? Real(0) : a.dw[0];
+  w.D0[1] = sa ? a.dw[0] : a.dw[1];
+  w.D0[2] = sa ? a.dw[1] : a.dw[2];
+  w.D0[3] = sa ? a.dw[2] : Real(0);
+  w.S1[0] = sb ? Real(0) : b.w[0];
+  w.S1[1] = sb ? b.w[0] : b.w[1];
+  w.S1[2] = sb ? b.w[1] : b.w[2];
+  w.S1[3] = sb ? b.w[2] : Real(0);
+  w.D1[0] = sb ? Real(0) : b.dw[0];
+  w.D1[1] = sb ? b.dw[0] : b.dw[1];
+  w.D1[2] = sb ? b.dw[1] : b.dw[2];
+  w.D1[3] = sb ? b.dw[2] : Real(0);
   return true;
 }
 
@@ -317,7 +362,7 @@ __device__ __forceinline__ bool win4(Real x0, Real x1, Win4<Real>& w) {
 // dPhi/dv (unresolved components).  The running sum along an axis turns
 // into a suffix sum of lJ.
 template <typename Real, int ND>
-__device__ __forceinline__ bool deposit_adjoint(const FieldPtrs<Real>& l, int64_t base, int64_t sy,
+__device__ __forceinline__ bool deposit_adjoint(const Planes<Real>& l, int64_t base, int64_t sy,
                                                 const Real x0[3], const Real x1[3], Real Q,
                                                 const Real v[3], const PushConst<Real>& c,
                                                 Real g0[2], Real g1[2], Real gv[3]) {
@@ -333,12 +378,14 @@ __device__ __forceinline__ bool deposit_adjoint(const FieldPtrs<Real>& l, int64_
     Real L[4];
     L[3] = Real(0);
     Real acc = 0;
+#pragma unroll
     for (int r = 2; r >= 0; r--) {
-      acc += l.J[0][o + r];
+      acc += l.J(0)[o + r];
       L[r] = acc;
     }
+#pragma unroll
     for (int r = 0; r < 4; r++) {
-      const Real ly = l.J[1][o + r], lz = l.J[2][o + r];
+      const Real ly = l.J(1)[o + r], lz = l.J(2)[o + r];
       const Real A = Real(0.5) * (wx.S0[r] + wx.S1[r]);
       gv[1] += fv * ly * A;
       gv[2] += fv * lz * A;
@@ -356,6 +403,7 @@ __device__ __forceinline__ bool deposit_adjoint(const FieldPtrs<Real>& l, int64_
     Real G0x[4] = {0, 0, 0, 0}, G1x[4] = {0, 0, 0, 0}, G0y[4] = {0, 0, 0, 0},
          G1y[4] = {0, 0, 0, 0};
     Real Ax[4], Ay[4], DSx[4], DSy[4];
+#pragma unroll
     for (int r = 0; r < 4; r++) {
       Ax[r] = Real(0.5) * (wx.S0[r] + wx.S1[r]);
       Ay[r] = Real(0.5) * (wy.S0[r] + wy.S1[r]);
@@ -363,14 +411,17 @@ __device__ __forceinline__ bool deposit_adjoint(const FieldPtrs<Real>& l, int64_
       DSy[r] = wy.S1[r] - wy.S0[r];
     }
     // J_x(r, s) = fx Cx(r) Ay(s), r < 3: Lx(r, s) suffix sums along x
+#pragma unroll
     for (int s = 0; s < 4; s++) {
       Real acc = 0, Lx[4];
       Lx[3] = Real(0);
+#pragma unroll
       for (int r = 2; r >= 0; r--) {
-        acc += l.J[0][o + r + s * sy];
+        acc += l.J(0)[o + r + s * sy];
         Lx[r] = acc;
       }
       Real sumDL = 0;
+#pragma unroll
       for (int r = 0; r < 4; r++) {
         const Real t = fx * Ay[s] * Lx[r];
         G1x[r] += t;
@@ -381,14 +432,17 @@ __device__ __forceinline__ bool deposit_adjoint(const FieldPtrs<Real>& l, int64_
       G1y[s] += Real(0.5) * fx * sumDL;
     }
     // J_y(r, s) = fy Cy(s) Ax(r), s < 3: Ly(r, s) suffix sums along y
+#pragma unroll
     for (int r = 0; r < 4; r++) {
       Real acc = 0, Ly[4];
       Ly[3] = Real(0);
+#pragma unroll
       for (int s = 2; s >= 0; s--) {
-        acc += l.J[1][o + r + s * sy];
+        acc += l.J(1)[o + r + s * sy];
         Ly[s] = acc;
       }
       Real sumDL = 0;
+#pragma unroll
       for (int s = 0; s < 4; s++) {
         const Real t = fy * Ax[r] * Ly[s];
         G1y[s] += t;
@@ -399,9 +453,11 @@ __device__ __forceinline__ bool deposit_adjoint(const FieldPtrs<Real>& l, int64_
       G1x[r] += Real(0.5) * fy * sumDL;
     }
     // J_z(r, s) = fz W(r, s), W = S0x S0y/3 + S0x S1y/6 + S1x S0y/6 + S1x S1y/3
+#pragma unroll
     for (int s = 0; s < 4; s++)
+#pragma unroll
       for (int r = 0; r < 4; r++) {
-        const Real lz = l.J[2][o + r + s * sy];
+        const Real lz = l.J(2)[o + r + s * sy];
         if (lz == Real(0)) continue;
         const Real W = third * wx.S0[r] * wy.S0[s] + sixth * wx.S0[r] * wy.S1[s] +
                        sixth * wx.S1[r] * wy.S0[s] + third * wx.S1[r] * wy.S1[s];
@@ -412,6 +468,7 @@ __device__ __forceinline__ bool deposit_adjoint(const FieldPtrs<Real>& l, int64_
         G0y[s] += t * (third * wx.S0[r] + sixth * wx.S1[r]);
         G1y[s] += t * (sixth * wx.S0[r] + third * wx.S1[r]);
       }
+#pragma unroll
     for (int r = 0; r < 4; r++) {
       g0[0] += G0x[r] * wx.D0[r];
       g1[0] += G1x[r] * wx.D1[r];
@@ -466,9 +523,9 @@ struct TileBox {
 
 // Reverse the cycle of particle p (see the file comment).
 template <typename Real, int ND, bool TWO>
-__device__ __forceinline__ void adjoint_one(const GridInfo& g, const FieldPtrs<Real>& f,
+__device__ __forceinline__ void adjoint_one(const GridInfo& g, const Planes<Real>& f,
                                             const AdjState<Real>& st, const PushConst<Real>& c,
-                                            const AdjState<Real>& lp, const FieldPtrs<Real>& l,
+                                            const AdjState<Real>& lp, const Planes<Real>& l,
                                             int64_t p, const TileBox& box, double& d_wc,
                                             double& d_nu) {
   do {
@@ -478,7 +535,9 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const FieldPtrs<R
     ci[0] = pk & ((1u << g.bits[0]) - 1u);
     if (ND > 1) ci[1] = (pk >> g.bits[0]) & ((1u << g.bits[1]) - 1u);
     Real off[3] = {0, 0, 0}, u1[3], u2[3] = {0, 0, 0}, dl[3] = {0, 0, 0};
+#pragma unroll
     for (int d = 0; d < ND; d++) off[d] = st.off[d][p];
+#pragma unroll
     for (int q = 0; q < 3; q++) {
       u1[q] = st.u1[q][p];
       if (TWO) {
@@ -490,6 +549,7 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const FieldPtrs<R
     const Real W = st.w ? st.w[p] : Real(1);
     bool ok = true;
     Real x1[3] = {0, 0, 0}, x2[3] = {0, 0, 0};
+#pragma unroll
     for (int d = 0; d < ND; d++) {
       ok = ok && isfinite(off[d]) && off[d] >= Real(0) && off[d] <= Real(1);
       const Real sd = dl[d] * c.idx[d];
@@ -497,14 +557,15 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const FieldPtrs<R
       x1[d] = off[d] + (TWO ? c.f1 * sd : Real(0));
       x2[d] = off[d] - (TWO ? c.f2 * sd : Real(0));
     }
+#pragma unroll
     for (int q = 0; q < 3; q++) ok = ok && isfinite(u1[q]) && isfinite(u2[q]) && isfinite(dl[q]);
     if (!ok) break;  // the forward cycle left it unchanged: identity
     const int64_t base = g.origin + ci[0] + (ND > 1 ? (int64_t)ci[1] * g.sy : 0);
 
     // ---- forward recomputation
-    Probe<Real, ND> P1, P2;
-    probe_fields<Real, ND>(f, base, g.sy, x1, P1);
-    if (TWO) probe_fields<Real, ND>(f, base, g.sy, x2, P2);
+    Real G1[3], B1[3], G2[3] = {0, 0, 0}, B2[3] = {0, 0, 0};
+    gather_values<Real, ND>(f, base, g.sy, x1, G1, B1);
+    if (TWO) gather_values<Real, ND>(f, base, g.sy, x2, G2, B2);
     Real E1[3], E2[3] = {0, 0, 0}, um1[3], um2[3] = {0, 0, 0};
     Real r2 = 0, rq = 1, soft = 1, kf = 0;
     if (TWO) {
@@ -515,12 +576,13 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const FieldPtrs<R
       }
       kf = -c.mr * wc * wc * soft;
     }
+#pragma unroll
     for (int q = 0; q < 3; q++) {
       const Real F = kf * dl[q];
-      E1[q] = P1.E[q] + (TWO ? F * c.inv_q1 : Real(0));
+      E1[q] = G1[q] + (TWO ? F * c.inv_q1 : Real(0));
       um1[q] = u1[q] + c.a1 * E1[q];
       if (TWO) {
-        E2[q] = P2.E[q] - F * c.inv_q2;
+        E2[q] = G2[q] - F * c.inv_q2;
         um2[q] = u2[q] + c.a2 * E2[q];
       }
     }
@@ -528,6 +590,7 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const FieldPtrs<R
     const Real nu = TWO ? c.nu + c.nu_per_omega * wc : Real(0);
     const Real Dn = (Real(1) - nu * c.half_dt) * rcp(Real(1) + nu * c.half_dt);
     Real vm1[3], vm2[3] = {0, 0, 0};
+#pragma unroll
     for (int q = 0; q < 3; q++) {
       if (TWO) {
         const Real V = (c.m1 * um1[q] + c.m2 * um2[q]) * c.inv_mc;
@@ -539,19 +602,22 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const FieldPtrs<R
       }
     }
     Real n1[3], n2[3] = {0, 0, 0}, v1[3], v2[3] = {0, 0, 0};
-    boris_forward(vm1, c.a1, E1, P1.B, n1);
-    if (TWO) boris_forward(vm2, c.a2, E2, P2.B, n2);
+    boris_forward(vm1, c.a1, E1, B1, n1);
+    if (TWO) boris_forward(vm2, c.a2, E2, B2, n2);
     {
       const Real i1 = rsq(Real(1) + n1[0] * n1[0] + n1[1] * n1[1] + n1[2] * n1[2]);
       const Real i2 = rsq(Real(1) + n2[0] * n2[0] + n2[1] * n2[1] + n2[2] * n2[2]);
+#pragma unroll
       for (int q = 0; q < 3; q++) {
         v1[q] = n1[q] * i1;
         v2[q] = n2[q] * i2;
       }
     }
     Real dln[3], offn[3] = {0, 0, 0};
+#pragma unroll
     for (int q = 0; q < 3; q++) dln[q] = TWO ? dl[q] + c.dt * (v1[q] - v2[q]) : Real(0);
     bool refl[3] = {false, false, false};
+#pragma unroll
     for (int d = 0; d < ND; d++) {
       const Real vc = TWO ? (c.m1 * v1[d] + c.m2 * v2[d]) * c.inv_mc : v1[d];
       offn[d] = off[d] + c.dt * vc * c.idx[d];
@@ -559,6 +625,7 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const FieldPtrs<R
       if (refl[d]) dln[d] = -dln[d];
     }
     Real y1[3] = {0, 0, 0}, y2[3] = {0, 0, 0};
+#pragma unroll
     for (int d = 0; d < ND; d++) {
       const Real sd = dln[d] * c.idx[d];
       y1[d] = offn[d] + (TWO ? c.f1 * sd : Real(0));
@@ -568,7 +635,9 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const FieldPtrs<R
     // ---- reverse
     Real l_off[3] = {0, 0, 0}, l_dl[3] = {0, 0, 0}, l_u1[3] = {0, 0, 0}, l_u2[3] = {0, 0, 0};
     Real l_offn[3] = {0, 0, 0}, l_dln[3] = {0, 0, 0}, l_n1[3], l_n2[3] = {0, 0, 0};
+#pragma unroll
     for (int d = 0; d < ND; d++) l_offn[d] = lp.off[d][p];
+#pragma unroll
     for (int q = 0; q < 3; q++) {
       l_n1[q] = lp.u1[q][p];
       if (TWO) {
@@ -581,6 +650,7 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const FieldPtrs<R
       const Real Q1 = st.w ? c.q1 * W : c.qw1;
       Real g0[2], g1[2], gv[3];
       if (deposit_adjoint<Real, ND>(l, base, g.sy, x1, y1, Q1, v1, c, g0, g1, gv)) {
+#pragma unroll
         for (int d = 0; d < ND; d++) {
           l_offn[d] += g1[d];
           l_off[d] += g0[d];
@@ -589,22 +659,26 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const FieldPtrs<R
             l_dl[d] += c.f1 * c.idx[d] * g0[d];
           }
         }
+#pragma unroll
         for (int q = ND; q < 3; q++) l_v1[q] += gv[q];
       }
       if (TWO) {
         const Real Q2 = st.w ? c.q2 * W : c.qw2;
         if (deposit_adjoint<Real, ND>(l, base, g.sy, x2, y2, Q2, v2, c, g0, g1, gv)) {
+#pragma unroll
           for (int d = 0; d < ND; d++) {
             l_offn[d] += g1[d];
             l_off[d] += g0[d];
             l_dln[d] -= c.f2 * c.idx[d] * g1[d];
             l_dl[d] -= c.f2 * c.idx[d] * g0[d];
           }
+#pragma unroll
           for (int q = ND; q < 3; q++) l_v2[q] += gv[q];
         }
       }
     }
     // walls: the reflected components change sign
+#pragma unroll
     for (int d = 0; d < ND; d++)
       if (refl[d]) {
         l_offn[d] = -l_offn[d];
@@ -613,6 +687,7 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const FieldPtrs<R
         l_n2[d] = -l_n2[d];
       }
     // move
+#pragma unroll
     for (int d = 0; d < ND; d++) {
       l_off[d] += l_offn[d];
       const Real k = c.dt * c.idx[d] * l_offn[d];
@@ -624,6 +699,7 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const FieldPtrs<R
       }
     }
     if (TWO)
+#pragma unroll
       for (int q = 0; q < 3; q++) {
         l_dl[q] += l_dln[q];
         l_v1[q] += c.dt * l_dln[q];
@@ -634,13 +710,14 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const FieldPtrs<R
     // Boris
     Real l_vm1[3] = {0, 0, 0}, l_vm2[3] = {0, 0, 0};
     Real l_E1[3] = {0, 0, 0}, l_E2[3] = {0, 0, 0}, l_B1[3] = {0, 0, 0}, l_B2[3] = {0, 0, 0};
-    boris_adjoint(vm1, c.a1, P1.B, l_n1, l_vm1, l_E1, l_B1);
-    if (TWO) boris_adjoint(vm2, c.a2, P2.B, l_n2, l_vm2, l_E2, l_B2);
+    boris_adjoint(vm1, c.a1, B1, l_n1, l_vm1, l_E1, l_B1);
+    if (TWO) boris_adjoint(vm2, c.a2, B2, l_n2, l_vm2, l_E2, l_B2);
     // friction
     Real l_um1[3], l_um2[3] = {0, 0, 0};
     if (TWO) {
       const Real dD = Real(-2) * c.half_dt * rcp((Real(1) + nu * c.half_dt) *
                                                  (Real(1) + nu * c.half_dt));
+#pragma unroll
       for (int q = 0; q < 3; q++) {
         const Real lV = l_vm1[q] + l_vm2[q];
         const Real lw = c.f1 * l_vm1[q] - c.f2 * l_vm2[q];
@@ -649,9 +726,11 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const FieldPtrs<R
         d_nu += (double)(lw * (um1[q] - um2[q]) * dD);
       }
     } else {
+#pragma unroll
       for (int q = 0; q < 3; q++) l_um1[q] = l_vm1[q];
     }
     // half kicks
+#pragma unroll
     for (int q = 0; q < 3; q++) {
       l_u1[q] += l_um1[q];
       l_E1[q] += c.a1 * l_um1[q];
@@ -663,6 +742,7 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const FieldPtrs<R
     // bond force: E1 = E(x1) + F / q1, E2 = E(x2) - F / q2, F = kf delta
     if (TWO) {
       Real lkf = 0;
+#pragma unroll
       for (int q = 0; q < 3; q++) {
         const Real lF = c.inv_q1 * l_E1[q] - c.inv_q2 * l_E2[q];
         l_dl[q] += kf * lF;
@@ -673,6 +753,7 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const FieldPtrs<R
         // soft = (1 + r2 / a_c^2)^{-3/2}
         const Real lsoft = lkf * (-c.mr * wc * wc);
         const Real dsoft = Real(-1.5) * c.inv_ac2 * rq * rq * rq * rq * rq;
+#pragma unroll
         for (int q = 0; q < 3; q++) l_dl[q] += Real(2) * dl[q] * lsoft * dsoft;
       }
     }
@@ -693,20 +774,27 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const FieldPtrs<R
         k.lplane = box.plane;
       }
     }
-    if (TWO && same_nodes<Real, ND>(P1, P2)) {
-      scatter_pair<Real, ND>(k, P1, l_E1, l_B1, P2, l_E2, l_B2);
+    const Stencil<Real> t1 = stencil_at<Real, ND>(x1);
+    if (TWO) {
+      const Stencil<Real> t2 = stencil_at<Real, ND>(x2);
+      if (same_nodes<Real, ND>(t1, t2)) {
+        gather_adjoint2<Real, ND>(f, k, base, g.sy, t1, l_E1, l_B1, t2, l_E2, l_B2, lx1, lx2);
+      } else {
+        gather_adjoint<Real, ND>(f, k, base, g.sy, t1, l_E1, l_B1, lx1);
+        gather_adjoint<Real, ND>(f, k, base, g.sy, t2, l_E2, l_B2, lx2);
+      }
     } else {
-      scatter_body<Real, ND>(k, P1, l_E1, l_B1);
-      if (TWO) scatter_body<Real, ND>(k, P2, l_E2, l_B2);
+      gather_adjoint<Real, ND>(f, k, base, g.sy, t1, l_E1, l_B1, lx1);
     }
-    position_adjoint<Real, ND>(P1, l_E1, l_B1, lx1);
-    if (TWO) position_adjoint<Real, ND>(P2, l_E2, l_B2, lx2);
+#pragma unroll
     for (int d = 0; d < ND; d++) {
       l_off[d] += lx1[d] + lx2[d];
       if (TWO) l_dl[d] += c.idx[d] * (c.f1 * lx1[d] - c.f2 * lx2[d]);
     }
     // adjoint state at the start of the step
+#pragma unroll
     for (int d = 0; d < ND; d++) lp.off[d][p] = l_off[d];
+#pragma unroll
     for (int q = 0; q < 3; q++) {
       lp.u1[q][p] = l_u1[q];
       if (TWO) {
@@ -719,8 +807,8 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const FieldPtrs<R
 
 template <typename Real, int ND, bool TWO>
 __global__ void __launch_bounds__(256)
-    k_adjoint_push(GridInfo g, FieldPtrs<Real> f, AdjState<Real> st, PushConst<Real> c,
-                   AdjState<Real> lp, FieldPtrs<Real> l, double* dparam) {
+    k_adjoint_push(GridInfo g, Planes<Real> f, AdjState<Real> st, PushConst<Real> c,
+                   AdjState<Real> lp, Planes<Real> l, double* dparam) {
   __shared__ double sh[4];
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double d_wc = 0.0, d_nu = 0.0;
@@ -742,8 +830,8 @@ __global__ void __launch_bounds__(256)
 // directly.
 template <typename Real, int ND, bool TWO>
 __global__ void __launch_bounds__(256)
-    k_adjoint_tiled(GridInfo g, FieldPtrs<Real> f, AdjState<Real> st, PushConst<Real> c,
-                    AdjState<Real> lp, FieldPtrs<Real> l, double* dparam,
+    k_adjoint_tiled(GridInfo g, Planes<Real> f, AdjState<Real> st, PushConst<Real> c,
+                    AdjState<Real> lp, Planes<Real> l, double* dparam,
                     const uint32_t* tile_off, AdjTiles tt) {
   extern __shared__ double patch[];
   __shared__ double sh[4];
@@ -774,7 +862,7 @@ __global__ void __launch_bounds__(256)
     if (gx < -kGuard || gx >= g.n[0] + kGuard) continue;
     if (ND > 1 && (gy < -kGuard || gy >= g.n[1] + kGuard)) continue;
     const int64_t o = g.origin + (box.x0 - 2 + px) + (ND > 1 ? (int64_t)(box.y0 - 2 + py) * g.sy : 0);
-    Real* F = comp < 3 ? l.E[comp] : l.B[comp - 3];
+    Real* F = l.base + comp * l.plane;
     unsafeAtomicAdd(F + o, (Real)v);
   }
   const double s_wc = block_sum<Real>(d_wc, sh);
@@ -788,11 +876,13 @@ __global__ void __launch_bounds__(256)
 }  // namespace
 
 template <typename Real>
-void launch_adjoint_push(const GridInfo& g, const FieldPtrs<Real>& f, const AdjState<Real>& st,
-                         const PushConst<Real>& c, const AdjState<Real>& lp,
-                         const FieldPtrs<Real>& l, double* dparam, const uint32_t* tile_off,
-                         const AdjTiles& tt, hipStream_t stream) {
+void launch_adjoint_push(const GridInfo& g, const Real* fields, const AdjState<Real>& st,
+                         const PushConst<Real>& c, const AdjState<Real>& lp, Real* lam,
+                         double* dparam, const uint32_t* tile_off, const AdjTiles& tt,
+                         hipStream_t stream) {
   if (st.n <= 0) return;
+  const Planes<Real> f{const_cast<Real*>(fields), g.plane};
+  const Planes<Real> l{lam, g.plane};
   const bool two = c.two_body != 0;
   if (tile_off) {
     const int ntile = tt.nt[0] * (g.nd > 1 ? tt.nt[1] : 1);
@@ -820,13 +910,12 @@ void launch_adjoint_push(const GridInfo& g, const FieldPtrs<Real>& f, const AdjS
     hipLaunchKernelGGL((k_adjoint_push<Real, 2, false>), grid, 256, 0, stream, g, f, st, c, lp, l, dparam);
 }
 
-template void launch_adjoint_push<float>(const GridInfo&, const FieldPtrs<float>&,
-                                         const AdjState<float>&, const PushConst<float>&,
-                                         const AdjState<float>&, const FieldPtrs<float>&, double*,
-                                         const uint32_t*, const AdjTiles&, hipStream_t);
-template void launch_adjoint_push<double>(const GridInfo&, const FieldPtrs<double>&,
-                                          const AdjState<double>&, const PushConst<double>&,
-                                          const AdjState<double>&, const FieldPtrs<double>&,
-                                          double*, const uint32_t*, const AdjTiles&, hipStream_t);
+template void launch_adjoint_push<float>(const GridInfo&, const float*, const AdjState<float>&,
+                                         const PushConst<float>&, const AdjState<float>&, float*,
+                                         double*, const uint32_t*, const AdjTiles&, hipStream_t);
+template void launch_adjoint_push<double>(const GridInfo&, const double*, const AdjState<double>&,
+                                          const PushConst<double>&, const AdjState<double>&,
+                                          double*, double*, const uint32_t*, const AdjTiles&,
+                                          hipStream_t);
 
 }  // namespace pic

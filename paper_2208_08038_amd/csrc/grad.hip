@@ -398,16 +398,17 @@ int grad_backward_t(pic_ctx* c, const double* dprobe, pic_grad* out) {
       // J guard fold, transposed: guards take the adjoint of their alias
       pic::launch_fill_periodic<Real>(g, lJ, 3, c->stream, true);
       // particle cycles
-      pic::FieldPtrs<Real> f = planes<Real>(static_cast<char*>(slot) + G.lay.fields, g.plane);
+      const Real* fslot = reinterpret_cast<const Real*>(static_cast<char*>(slot) + G.lay.fields);
       for (size_t si = 0; si < c->sp.size(); si++) {
         const SpeciesHost& s = *c->sp[si];
         if (s.n == 0) continue;
         const bool timed = record_event(c, PIC_TIMING_ADJOINT + (int)si, true);
         pic::AdjTiles tt{{c->tile[0], c->tile[1]}, {c->ntiles[0], c->ntiles[1]}};
         const uint32_t* toff = c->tiled ? s.sort.tile_off : nullptr;
-        pic::launch_adjoint_push<Real>(g, f, snap_state<Real>(c, slot, si), push_const<Real>(c, s),
-                                       lam_state<Real>(c, si), l, G.dgrad + 2 * si, toff, tt,
-                                       c->stream);
+        pic::launch_adjoint_push<Real>(g, fslot, snap_state<Real>(c, slot, si),
+                                       push_const<Real>(c, s), lam_state<Real>(c, si),
+                                       static_cast<Real*>(G.lam_fields), G.dgrad + 2 * si, toff,
+                                       tt, c->stream);
         if (timed) record_event(c, PIC_TIMING_ADJOINT + (int)si, false);
       }
       // E, B guard fill at the start of the step, transposed
