@@ -139,3 +139,47 @@ def test_full_size_sampled_particles_and_continuity(pic, precision):
          f"{27 * 8 * eps * gross:.3e}), rms {d['div_l2'] / math.sqrt(ncell):.3e} "
          f"(bound {eps * gross:.3e}), rho_l2 {d['rho_l2']:.3e}")
     o.close()
+
+
+def test_full_size_gradient_run(pic):
+    """The gradient run at the size bench.py measures (2D 2048 x 1024 cells,
+    6,291,456 two-body ions, 1024 steps, checkpoints every 32): FP32 adjoint
+    gradients of the transmitted-pulse loss with respect to omega_c, nu and
+    one envelope coefficient against central differences (h = 1e-3
+    relative) of the FP64 forward, within 1e-4."""
+    import torch
+    from paper_2208_08038_amd.inputs import adjoint_slab
+    from paper_2208_08038_amd.objectives import transmitted_loss, transmitted_parts
+    import _adjoint as A
+    wl = adjoint_slab(2, (2048, 1024))
+    ny, dt, dy = wl.grid.n[1], wl.grid.dt, wl.grid.dx[1]
+    _say(f"case: full-size gradient run, {wl.species[0][1].n} ions, {wl.steps} steps: fp32 adjoint")
+    sim = pic.Simulation.from_workload(wl, precision=32, max_probe_steps=wl.steps)
+    sim.grad_forward(wl.steps, 32)
+    series = torch.tensor(sim.probes(), requires_grad=True)
+    e_ref = float(transmitted_parts(series.detach(), ny, dt, dy)[0])
+    L = transmitted_loss(series, ny, dt, dy, e_ref=e_ref)
+    (cot,) = torch.autograd.grad(L, series)
+    g = sim.grad_backward(cot.numpy())
+    assert sim.diagnostics()["error_word"] == 0
+    sim.close()
+
+    def loss(s):
+        return float(transmitted_loss(s, ny, dt, dy, e_ref=e_ref))
+    sp = wl.species[0][0]
+    env = np.array(wl.grid.laser.env)
+    k = 32
+
+    def env_k(v):
+        e = env.copy()
+        e[k] = v
+        return A.with_params(wl, env=e)
+    for name, adj, make, x0 in (
+            ("omega_c", g["d_omega_c"][0], lambda v: A.with_params(wl, omega_c=v), sp.omega_c),
+            ("nu", g["d_nu"][0], lambda v: A.with_params(wl, nu=v), sp.nu),
+            (f"env[{k}]", g["d_env"][k], env_k, env[k])):
+        _say(f"case: full-size gradient run: fp64 central differences in {name}")
+        fd = A.central_fd(lambda w: A.gpu_series(pic, w), loss, make, x0, 1e-3 * abs(x0))
+        rel = abs(adj - fd) / abs(fd)
+        _say(f"full size d/d{name}: fp32 adjoint {adj:.8e}, fp64 FD {fd:.8e}, rel {rel:.2e}")
+        assert rel < 1e-4, name
