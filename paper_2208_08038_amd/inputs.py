@@ -16,7 +16,8 @@ Workloads (the paper's cases as restated for this project):
   bragg_2d            x-ray Bragg scattering from a rotated lattice, Sec. 3.2
   ionised_slab_3d     3D partially ionised slab with free electrons
   mixed_precision_3d  Bragg-geometry 3D slab, 4 ions per cell
-  neutral_slab_2d     2D neutral slab (the differentiation workload's forward run)
+  adjoint_slab        2D neutral slab crossed by a spline-envelope pulse (gradient runs)
+  bound_slab_1d       medium behind a vacuum gap (Sec. 3.1 observables)
 """
 from __future__ import annotations
 
@@ -427,42 +428,12 @@ def mixed_precision_3d(n=(1024, 1024, 512), slab=(384, 640), ppc: int = 4, steps
                     notes=f"{x.shape[0]} two-body ions, lattice-modulated weights")
 
 
-# --------------------------------------------------------------------------
-# Case 5: 2D neutral slab (forward run of the differentiation workload)
-# --------------------------------------------------------------------------
-
-def neutral_slab_2d(n=(2048, 1024), slab=(512, 1536), ppc: int = 16, steps: int = 1024,
-                    omega_c: float = 3.0, omega_pb: float = 0.9, nu_per_omega: float = 0.01,
-                    a0: float = 1e-3, cycles: int = 20, precision: int = 32,
-                    config_id: int = 5) -> Workload:
-    dx = TWO_PI / 32.0
-    dt = 0.98 * dx / math.sqrt(2.0)
-    lam_m = 12.4e-9
-    laser = Laser(a0=a0, omega=1.0, t_env=cycles * TWO_PI, waist=0.25 * n[1] * dx,
-                  yc=0.5 * n[1] * dx, pol=1)
-    grid = Grid(2, (n[0], n[1], 1), (dx, dx, 1.0), dt, (LASER, PERIODIC, PERIODIC),
-                (OPEN, PERIODIC, PERIODIC), pad=3, laser=laser,
-                re_norm=TWO_PI * R_E_M / lam_m)
-    q1, m1, q2, m2 = gold_ion(78, 0.0)
-    n_ion = bound_plasma_density(q1, m1, q2, m2, omega_pb)
-    w = n_ion * dx * dx / ppc
-    sp = Species(TWO_BODY, q1, m1, q2, m2, weight=w, omega_c=omega_c, a_c=0.0,
-                 nu_per_omega=nu_per_omega, name="Au_slab2d")
-    rng = rng_for(config_id)
-    lo = [max(slab[0], grid.pad), 0]
-    hi = [min(slab[1], n[0] - grid.pad), n[1]]
-    x = stratified_positions(rng, lo, hi, ppc, grid.dx, 2)
-    parts = Particles(x=x, u1=rng.normal(0.0, thermal_sigma(1.0, m1 + m2), size=(x.shape[0], 3)))
-    return Workload("neutral_slab_2d", grid, [(sp, parts)], steps, precision,
-                    notes=f"{x.shape[0]} two-body ions")
-
-
 WORKLOADS = {
     "neutral_medium_1d": neutral_medium_1d,
     "bragg_2d": bragg_2d,
     "ionised_slab_3d": ionised_slab_3d,
     "mixed_precision_3d": mixed_precision_3d,
-    "neutral_slab_2d": neutral_slab_2d,
+    "adjoint_slab": adjoint_slab,
 }
 
 

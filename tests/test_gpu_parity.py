@@ -515,3 +515,56 @@ def test_global_kernel_option(pic):
     s.step(8)
     assert rel_l2(s.fields()[0], o.fields()[0]) < 1e-12
     _compare_particles(o, s, wl, 1e-11)
+
+
+@pytest.fixture(scope="module")
+def mixed_case():
+    """The mixed-precision case (Bragg geometry in 3D, lattice-modulated
+    per-particle weights) at reduced size, and its FP64 oracle run."""
+    from paper_2208_08038_amd.inputs import mixed_precision_3d
+    wl = mixed_precision_3d(n=(80, 12, 12), slab=(20, 44), ppc=1, steps=220, cycles=2)
+    o = Oracle.from_workload(wl)
+    o.step(wl.steps)
+    assert o.diagnostics()["error_word"] == 0
+    ref = o.fields()
+    o.close()
+    return wl, ref
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_mixed_precision_case(pic, mixed_case, precision):
+    """Per-step charge-continuity residual (FP64 compensated reduction) and
+    the final fields, whole grid and the transmitted region behind the
+    slab, against the FP64 oracle."""
+    wl, (Eo, Bo, _) = mixed_case
+    _say(f"case: mixed-precision 3D fp{precision}, {wl.species[0][1].n} ions, {wl.steps} steps")
+    s = pic.Simulation.from_workload(wl, precision=precision, flags=pic.CHARGE_CHECK)
+    sp = wl.species[0][0]
+    dx = wl.grid.dx[0]
+    ncell = int(np.prod(wl.grid.n))
+    # rounding of the continuity residual scales with the largest charge
+    # rate of a cell: the site-modulated weights peak far above their mean
+    wmax = float(np.max(wl.species[0][1].weight))
+    gross = wmax * (abs(sp.q1) + abs(sp.q2)) / (dx ** 3 * wl.grid.dt)
+    eps = 2.0 ** -24 if precision == 32 else 2.0 ** -53
+    worst = 0.0
+    for _ in range(wl.steps):
+        s.step(1)
+        d = s.diagnostics()
+        assert d["error_word"] == 0
+        worst = max(worst, d["div_l2"] / math.sqrt(ncell))
+    assert worst < eps * gross, (worst, eps * gross)
+    Eg, Bg, _ = s.fields()
+    s.close()
+    tol = 1e-12 if precision == 64 else 2e-5
+    nx, ny, nz = wl.grid.n
+    behind = (slice(None), slice(None), slice(48, nx - 4))
+
+    def region(F):
+        return F.reshape(3, nz, ny, nx)[(slice(None),) + behind]
+    errs = {"E": rel_l2(Eg, Eo), "B": rel_l2(Bg, Bo),
+            "E transmitted": rel_l2(region(Eg), region(Eo))}
+    _say(f"fp{precision}: per-step residual RMS max {worst:.3e} (bound {eps * gross:.3e}); " +
+         ", ".join(f"{k} {v:.2e}" for k, v in errs.items()))
+    for k, v in errs.items():
+        assert v < tol, k
