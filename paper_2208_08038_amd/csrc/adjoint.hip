@@ -362,7 +362,8 @@ __device__ __forceinline__ bool win4(Real x0, Real x1, Win4<Real>& w) {
 // dPhi/dv (unresolved components).  The running sum along an axis turns
 // into a suffix sum of lJ.
 template <typename Real, int ND>
-__device__ __forceinline__ bool deposit_adjoint(const Planes<Real>& l, int64_t base, int64_t sy,
+__device__ __forceinline__ bool deposit_adjoint(const Real* J, int64_t jplane, int64_t base,
+                                                int64_t sy,
                                                 const Real x0[3], const Real x1[3], Real Q,
                                                 const Real v[3], const PushConst<Real>& c,
                                                 Real g0[2], Real g1[2], Real gv[3]) {
@@ -380,12 +381,12 @@ __device__ __forceinline__ bool deposit_adjoint(const Planes<Real>& l, int64_t b
     Real acc = 0;
 #pragma unroll
     for (int r = 2; r >= 0; r--) {
-      acc += l.J(0)[o + r];
+      acc += J[o + r];
       L[r] = acc;
     }
 #pragma unroll
     for (int r = 0; r < 4; r++) {
-      const Real ly = l.J(1)[o + r], lz = l.J(2)[o + r];
+      const Real ly = J[jplane + o + r], lz = J[2 * jplane + o + r];
       const Real A = Real(0.5) * (wx.S0[r] + wx.S1[r]);
       gv[1] += fv * ly * A;
       gv[2] += fv * lz * A;
@@ -417,7 +418,7 @@ __device__ __forceinline__ bool deposit_adjoint(const Planes<Real>& l, int64_t b
       Lx[3] = Real(0);
 #pragma unroll
       for (int r = 2; r >= 0; r--) {
-        acc += l.J(0)[o + r + s * sy];
+        acc += J[o + r + s * sy];
         Lx[r] = acc;
       }
       Real sumDL = 0;
@@ -438,7 +439,7 @@ __device__ __forceinline__ bool deposit_adjoint(const Planes<Real>& l, int64_t b
       Ly[3] = Real(0);
 #pragma unroll
       for (int s = 2; s >= 0; s--) {
-        acc += l.J(1)[o + r + s * sy];
+        acc += J[jplane + o + r + s * sy];
         Ly[s] = acc;
       }
       Real sumDL = 0;
@@ -457,7 +458,7 @@ __device__ __forceinline__ bool deposit_adjoint(const Planes<Real>& l, int64_t b
     for (int s = 0; s < 4; s++)
 #pragma unroll
       for (int r = 0; r < 4; r++) {
-        const Real lz = l.J(2)[o + r + s * sy];
+        const Real lz = J[2 * jplane + o + r + s * sy];
         if (lz == Real(0)) continue;
         const Real W = third * wx.S0[r] * wy.S0[s] + sixth * wx.S0[r] * wy.S1[s] +
                        sixth * wx.S1[r] * wy.S0[s] + third * wx.S1[r] * wy.S1[s];
@@ -513,20 +514,28 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 }
 
 // Tile of the workgroup in the tiled adjoint kernel: cells [x0, x0 + tx) x
-// [y0, y0 + ty) and the FP64 LDS patch of its nodes [x0 - 2, x0 + tx + 2) x
-// [y0 - 2, y0 + ty + 2), six component planes of `plane` values, row pitch
-// `pitch`.  lds == nullptr: every scatter goes to the global planes.
+// [y0, y0 + ty) and LDS copies of its nodes [x0 - 2, x0 + tx + 3) x
+// [y0 - 2, y0 + ty + 3) (the reach of the gather and of the deposit window
+// of a particle in the tile), `plane` values per component, row pitch
+// `pitch`: the FP64 accumulator of the gather's transpose (6 planes), the
+// fields E, B (6 planes) and the adjoint current (3 planes).
+template <typename Real>
 struct TileBox {
   double* lds;
+  Real* f;
+  Real* lj;
   int x0, y0, tx, ty, pitch, plane;
 };
 
 // Reverse the cycle of particle p (see the file comment).
-template <typename Real, int ND, bool TWO>
-__device__ __forceinline__ void adjoint_one(const GridInfo& g, const Planes<Real>& f,
+// IN_TILE: the particle's cell is in the workgroup's tile, so its fields,
+// adjoint current and scatter live in the tile's LDS copies (known LDS
+// addresses); otherwise everything goes through the global planes.
+template <typename Real, int ND, bool TWO, bool IN_TILE>
+__device__ __forceinline__ void adjoint_one(const GridInfo& g, const Planes<Real>& fg,
                                             const AdjState<Real>& st, const PushConst<Real>& c,
                                             const AdjState<Real>& lp, const Planes<Real>& l,
-                                            int64_t p, const TileBox& box, double& d_wc,
+                                            int64_t p, const TileBox<Real>& box, double& d_wc,
                                             double& d_nu) {
   do {
     // ---- stored state at the start of the step
@@ -560,12 +569,39 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const Planes<Real
 #pragma unroll
     for (int q = 0; q < 3; q++) ok = ok && isfinite(u1[q]) && isfinite(u2[q]) && isfinite(dl[q]);
     if (!ok) break;  // the forward cycle left it unchanged: identity
-    const int64_t base = g.origin + ci[0] + (ND > 1 ? (int64_t)ci[1] * g.sy : 0);
+    // where the fields, the adjoint current and the scatter live
+    Planes<Real> f;
+    const Real* LJ;
+    int64_t jplane, base, sy;
+    Sink<Real> k;
+    k.l = l;
+    k.gbase = g.origin + ci[0] + (ND > 1 ? (int64_t)ci[1] * g.sy : 0);
+    k.gsy = g.sy;
+    if constexpr (IN_TILE) {
+      const int cx = ci[0] - box.x0, cy = ND > 1 ? ci[1] - box.y0 : 0;
+      base = (cx + 2) + (ND > 1 ? (cy + 2) * box.pitch : 0);
+      sy = box.pitch;
+      f = Planes<Real>{box.f, box.plane};
+      LJ = box.lj;
+      jplane = box.plane;
+      k.lds = box.lds;
+      k.lbase = (int)base;
+      k.lsy = box.pitch;
+      k.lplane = box.plane;
+    } else {
+      base = k.gbase;
+      sy = g.sy;
+      f = fg;
+      LJ = l.J(0);
+      jplane = l.plane;
+      k.lds = nullptr;
+      k.lbase = k.lsy = k.lplane = 0;
+    }
 
     // ---- forward recomputation
     Real G1[3], B1[3], G2[3] = {0, 0, 0}, B2[3] = {0, 0, 0};
-    gather_values<Real, ND>(f, base, g.sy, x1, G1, B1);
-    if (TWO) gather_values<Real, ND>(f, base, g.sy, x2, G2, B2);
+    gather_values<Real, ND>(f, base, sy, x1, G1, B1);
+    if (TWO) gather_values<Real, ND>(f, base, sy, x2, G2, B2);
     Real E1[3], E2[3] = {0, 0, 0}, um1[3], um2[3] = {0, 0, 0};
     Real r2 = 0, rq = 1, soft = 1, kf = 0;
     if (TWO) {
@@ -649,7 +685,7 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const Planes<Real
     if (c.deposit) {
       const Real Q1 = st.w ? c.q1 * W : c.qw1;
       Real g0[2], g1[2], gv[3];
-      if (deposit_adjoint<Real, ND>(l, base, g.sy, x1, y1, Q1, v1, c, g0, g1, gv)) {
+      if (deposit_adjoint<Real, ND>(LJ, jplane, base, sy, x1, y1, Q1, v1, c, g0, g1, gv)) {
 #pragma unroll
         for (int d = 0; d < ND; d++) {
           l_offn[d] += g1[d];
@@ -664,7 +700,7 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const Planes<Real
       }
       if (TWO) {
         const Real Q2 = st.w ? c.q2 * W : c.qw2;
-        if (deposit_adjoint<Real, ND>(l, base, g.sy, x2, y2, Q2, v2, c, g0, g1, gv)) {
+        if (deposit_adjoint<Real, ND>(LJ, jplane, base, sy, x2, y2, Q2, v2, c, g0, g1, gv)) {
 #pragma unroll
           for (int d = 0; d < ND; d++) {
             l_offn[d] += g1[d];
@@ -759,32 +795,17 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const Planes<Real
     }
     // gather
     Real lx1[2] = {0, 0}, lx2[2] = {0, 0};
-    Sink<Real> k;
-    k.l = l;
-    k.gbase = base;
-    k.gsy = g.sy;
-    k.lds = nullptr;
-    k.lbase = k.lsy = k.lplane = 0;
-    if (box.lds) {
-      const int cx = ci[0] - box.x0, cy = ND > 1 ? ci[1] - box.y0 : 0;
-      if (cx >= 0 && cx < box.tx && cy >= 0 && cy < box.ty) {
-        k.lds = box.lds;
-        k.lbase = (cx + 2) + (ND > 1 ? (cy + 2) * box.pitch : 0);
-        k.lsy = box.pitch;
-        k.lplane = box.plane;
-      }
-    }
     const Stencil<Real> t1 = stencil_at<Real, ND>(x1);
     if (TWO) {
       const Stencil<Real> t2 = stencil_at<Real, ND>(x2);
       if (same_nodes<Real, ND>(t1, t2)) {
-        gather_adjoint2<Real, ND>(f, k, base, g.sy, t1, l_E1, l_B1, t2, l_E2, l_B2, lx1, lx2);
+        gather_adjoint2<Real, ND>(f, k, base, sy, t1, l_E1, l_B1, t2, l_E2, l_B2, lx1, lx2);
       } else {
-        gather_adjoint<Real, ND>(f, k, base, g.sy, t1, l_E1, l_B1, lx1);
-        gather_adjoint<Real, ND>(f, k, base, g.sy, t2, l_E2, l_B2, lx2);
+        gather_adjoint<Real, ND>(f, k, base, sy, t1, l_E1, l_B1, lx1);
+        gather_adjoint<Real, ND>(f, k, base, sy, t2, l_E2, l_B2, lx2);
       }
     } else {
-      gather_adjoint<Real, ND>(f, k, base, g.sy, t1, l_E1, l_B1, lx1);
+      gather_adjoint<Real, ND>(f, k, base, sy, t1, l_E1, l_B1, lx1);
     }
 #pragma unroll
     for (int d = 0; d < ND; d++) {
@@ -812,8 +833,8 @@ __global__ void __launch_bounds__(256)
   __shared__ double sh[4];
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double d_wc = 0.0, d_nu = 0.0;
-  TileBox box{};
-  if (p < st.n) adjoint_one<Real, ND, TWO>(g, f, st, c, lp, l, p, box, d_wc, d_nu);
+  TileBox<Real> box{};
+  if (p < st.n) adjoint_one<Real, ND, TWO, false>(g, f, st, c, lp, l, p, box, d_wc, d_nu);
   const double s_wc = block_sum<Real>(d_wc, sh);
   const double s_nu = block_sum<Real>(d_nu, sh);
   if (threadIdx.x == 0) {
@@ -838,19 +859,39 @@ __global__ void __launch_bounds__(256)
   const int t = blockIdx.x;
   const int64_t p0 = tile_off[t], p1 = tile_off[t + 1];
   if (p0 == p1) return;  // uniform over the workgroup
-  TileBox box;
-  box.lds = patch;
+  TileBox<Real> box;
   box.tx = tt.T[0];
   box.ty = ND > 1 ? tt.T[1] : 1;
   box.x0 = (t % tt.nt[0]) * tt.T[0];
   box.y0 = ND > 1 ? (t / tt.nt[0]) * tt.T[1] : 0;
-  box.pitch = box.tx + 4;
-  box.plane = box.pitch * (ND > 1 ? box.ty + 4 : 1);
-  for (int q = threadIdx.x; q < 6 * box.plane; q += blockDim.x) patch[q] = 0.0;
+  box.pitch = box.tx + 5;
+  box.plane = box.pitch * (ND > 1 ? box.ty + 5 : 1);
+  box.lds = patch;
+  box.f = reinterpret_cast<Real*>(patch + 6 * box.plane);
+  box.lj = box.f + 6 * box.plane;
+  // zero the accumulator; stage E, B and the adjoint current of the tile's
+  // reach (nodes beyond the guard layers, reachable only past a partial
+  // last tile, read as zero)
+  for (int q = threadIdx.x; q < 6 * box.plane; q += blockDim.x) {
+    patch[q] = 0.0;
+    const int comp = q / box.plane, r = q % box.plane;
+    const int gx = box.x0 - 2 + r % box.pitch, gy = box.y0 - 2 + r / box.pitch;
+    const bool in = gx < g.n[0] + kGuard && (ND == 1 || gy < g.n[1] + kGuard);
+    const int64_t o = g.origin + gx + (ND > 1 ? (int64_t)gy * g.sy : 0);
+    box.f[q] = in ? f.base[comp * f.plane + o] : Real(0);
+    if (comp < 3) box.lj[q] = in ? l.J(comp)[o] : Real(0);
+  }
   __syncthreads();
   double d_wc = 0.0, d_nu = 0.0;
-  for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x)
-    adjoint_one<Real, ND, TWO>(g, f, st, c, lp, l, p, box, d_wc, d_nu);
+  for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+    const uint32_t pk = st.cell[p];
+    const int cx = (int)(pk & ((1u << g.bits[0]) - 1u)) - box.x0;
+    const int cy = ND > 1 ? (int)((pk >> g.bits[0]) & ((1u << g.bits[1]) - 1u)) - box.y0 : 0;
+    if (cx >= 0 && cx < box.tx && cy >= 0 && cy < box.ty)
+      adjoint_one<Real, ND, TWO, true>(g, f, st, c, lp, l, p, box, d_wc, d_nu);
+    else
+      adjoint_one<Real, ND, TWO, false>(g, f, st, c, lp, l, p, box, d_wc, d_nu);
+  }
   __syncthreads();
   // flush: patch node (px, py) is global node (x0 - 2 + px, y0 - 2 + py)
   for (int q = threadIdx.x; q < 6 * box.plane; q += blockDim.x) {
@@ -886,8 +927,9 @@ void launch_adjoint_push(const GridInfo& g, const Real* fields, const AdjState<R
   const bool two = c.two_body != 0;
   if (tile_off) {
     const int ntile = tt.nt[0] * (g.nd > 1 ? tt.nt[1] : 1);
-    const size_t lds = 6 * sizeof(double) * (size_t)(tt.T[0] + 4) *
-                       (size_t)(g.nd > 1 ? tt.T[1] + 4 : 1);
+    // FP64 accumulator (6 planes) + fields (6) + adjoint current (3)
+    const size_t plane = (size_t)(tt.T[0] + 5) * (size_t)(g.nd > 1 ? tt.T[1] + 5 : 1);
+    const size_t lds = plane * (6 * sizeof(double) + 9 * sizeof(Real));
     dim3 grid((unsigned)ntile);
 #define PIC_ADJ_TILED(ND_, TWO_)                                                                 \
     hipLaunchKernelGGL((k_adjoint_tiled<Real, ND_, TWO_>), grid, 256, lds, stream, g, f, st, c, lp, \
