@@ -513,6 +513,39 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;
 }
 
+// What the reverse cycle of one particle reads from memory: its stored
+// state at the start of the step and the adjoint of its state at the end.
+// Loaded one particle ahead in the tiled kernel so that the loads overlap
+// the previous particle's arithmetic.
+template <typename Real>
+struct PIn {
+  uint32_t cell;
+  Real off[2], u1[3], u2[3], dl[3], wc, w;
+  Real loff[2], ldl[3], lu1[3], lu2[3];
+};
+
+template <typename Real, int ND, bool TWO>
+__device__ __forceinline__ void load_in(const AdjState<Real>& st, const AdjState<Real>& lp,
+                                        const PushConst<Real>& c, int64_t p, PIn<Real>& in) {
+  in.cell = st.cell[p];
+#pragma unroll
+  for (int d = 0; d < 2; d++) {
+    in.off[d] = d < ND ? st.off[d][p] : Real(0);
+    in.loff[d] = d < ND ? lp.off[d][p] : Real(0);
+  }
+#pragma unroll
+  for (int q = 0; q < 3; q++) {
+    in.u1[q] = st.u1[q][p];
+    in.lu1[q] = lp.u1[q][p];
+    in.u2[q] = TWO ? st.u2[q][p] : Real(0);
+    in.dl[q] = TWO ? st.dl[q][p] : Real(0);
+    in.lu2[q] = TWO ? lp.u2[q][p] : Real(0);
+    in.ldl[q] = TWO ? lp.dl[q][p] : Real(0);
+  }
+  in.wc = TWO ? (st.wc ? st.wc[p] : c.omega_c) : Real(0);
+  in.w = st.w ? st.w[p] : Real(1);
+}
+
 // Tile of the workgroup in the tiled adjoint kernel: cells [x0, x0 + tx) x
 // [y0, y0 + ty) and LDS copies of its nodes [x0 - 2, x0 + tx + 3) x
 // [y0 - 2, y0 + ty + 3) (the reach of the gather and of the deposit window
@@ -535,27 +568,28 @@ template <typename Real, int ND, bool TWO, bool IN_TILE>
 __device__ __forceinline__ void adjoint_one(const GridInfo& g, const Planes<Real>& fg,
                                             const AdjState<Real>& st, const PushConst<Real>& c,
                                             const AdjState<Real>& lp, const Planes<Real>& l,
-                                            int64_t p, const TileBox<Real>& box, double& d_wc,
+                                            int64_t p, const PIn<Real>& in,
+                                            const TileBox<Real>& box, double& d_wc,
                                             double& d_nu) {
   do {
     // ---- stored state at the start of the step
     int ci[3] = {0, 0, 0};
-    const uint32_t pk = st.cell[p];
+    const uint32_t pk = in.cell;
     ci[0] = pk & ((1u << g.bits[0]) - 1u);
     if (ND > 1) ci[1] = (pk >> g.bits[0]) & ((1u << g.bits[1]) - 1u);
     Real off[3] = {0, 0, 0}, u1[3], u2[3] = {0, 0, 0}, dl[3] = {0, 0, 0};
 #pragma unroll
-    for (int d = 0; d < ND; d++) off[d] = st.off[d][p];
+    for (int d = 0; d < ND; d++) off[d] = in.off[d];
 #pragma unroll
     for (int q = 0; q < 3; q++) {
-      u1[q] = st.u1[q][p];
+      u1[q] = in.u1[q];
       if (TWO) {
-        u2[q] = st.u2[q][p];
-        dl[q] = st.dl[q][p];
+        u2[q] = in.u2[q];
+        dl[q] = in.dl[q];
       }
     }
-    const Real wc = TWO ? (st.wc ? st.wc[p] : c.omega_c) : Real(0);
-    const Real W = st.w ? st.w[p] : Real(1);
+    const Real wc = in.wc;
+    const Real W = in.w;
     bool ok = true;
     Real x1[3] = {0, 0, 0}, x2[3] = {0, 0, 0};
 #pragma unroll
@@ -672,13 +706,13 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const Planes<Real
     Real l_off[3] = {0, 0, 0}, l_dl[3] = {0, 0, 0}, l_u1[3] = {0, 0, 0}, l_u2[3] = {0, 0, 0};
     Real l_offn[3] = {0, 0, 0}, l_dln[3] = {0, 0, 0}, l_n1[3], l_n2[3] = {0, 0, 0};
 #pragma unroll
-    for (int d = 0; d < ND; d++) l_offn[d] = lp.off[d][p];
+    for (int d = 0; d < ND; d++) l_offn[d] = in.loff[d];
 #pragma unroll
     for (int q = 0; q < 3; q++) {
-      l_n1[q] = lp.u1[q][p];
+      l_n1[q] = in.lu1[q];
       if (TWO) {
-        l_n2[q] = lp.u2[q][p];
-        l_dln[q] = lp.dl[q][p];
+        l_n2[q] = in.lu2[q];
+        l_dln[q] = in.ldl[q];
       }
     }
     Real l_v1[3] = {0, 0, 0}, l_v2[3] = {0, 0, 0};
@@ -834,7 +868,11 @@ __global__ void __launch_bounds__(256)
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double d_wc = 0.0, d_nu = 0.0;
   TileBox<Real> box{};
-  if (p < st.n) adjoint_one<Real, ND, TWO, false>(g, f, st, c, lp, l, p, box, d_wc, d_nu);
+  if (p < st.n) {
+    PIn<Real> in;
+    load_in<Real, ND, TWO>(st, lp, c, p, in);
+    adjoint_one<Real, ND, TWO, false>(g, f, st, c, lp, l, p, in, box, d_wc, d_nu);
+  }
   const double s_wc = block_sum<Real>(d_wc, sh);
   const double s_nu = block_sum<Real>(d_nu, sh);
   if (threadIdx.x == 0) {
@@ -883,14 +921,21 @@ __global__ void __launch_bounds__(256)
   }
   __syncthreads();
   double d_wc = 0.0, d_nu = 0.0;
-  for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
-    const uint32_t pk = st.cell[p];
+  PIn<Real> in;
+  int64_t p = p0 + threadIdx.x;
+  if (p < p1) load_in<Real, ND, TWO>(st, lp, c, p, in);
+  for (; p < p1; p += blockDim.x) {
+    // the next particle's loads are issued before this one's arithmetic
+    PIn<Real> nx = in;
+    if (p + blockDim.x < p1) load_in<Real, ND, TWO>(st, lp, c, p + blockDim.x, nx);
+    const uint32_t pk = in.cell;
     const int cx = (int)(pk & ((1u << g.bits[0]) - 1u)) - box.x0;
     const int cy = ND > 1 ? (int)((pk >> g.bits[0]) & ((1u << g.bits[1]) - 1u)) - box.y0 : 0;
     if (cx >= 0 && cx < box.tx && cy >= 0 && cy < box.ty)
-      adjoint_one<Real, ND, TWO, true>(g, f, st, c, lp, l, p, box, d_wc, d_nu);
+      adjoint_one<Real, ND, TWO, true>(g, f, st, c, lp, l, p, in, box, d_wc, d_nu);
     else
-      adjoint_one<Real, ND, TWO, false>(g, f, st, c, lp, l, p, box, d_wc, d_nu);
+      adjoint_one<Real, ND, TWO, false>(g, f, st, c, lp, l, p, in, box, d_wc, d_nu);
+    in = nx;
   }
   __syncthreads();
   // flush: patch node (px, py) is global node (x0 - 2 + px, y0 - 2 + py)
