@@ -216,6 +216,7 @@ class Simulation:
         self.ctx = ctx
         self.nprobe = 0
         self.species = []
+        self._grad_steps = 0  # steps of the last completed grad_forward
 
     def _check(self, rc):
         if rc != PIC_OK:
@@ -377,8 +378,9 @@ class Simulation:
     def grad_forward(self, nsteps: int, checkpoint_every: int) -> None:
         """Advance nsteps as step() does (no tile sorts), recording the
         probes and keeping a checkpoint every `checkpoint_every` steps."""
-        self._grad_steps = int(nsteps)
+        self._grad_steps = 0
         self._check(self.lib.pic_grad_forward(self.ctx, int(nsteps), int(checkpoint_every)))
+        self._grad_steps = int(nsteps)
 
     def grad_backward(self, dprobe, fields: bool = False) -> dict:
         """Gradients from the cotangent of the probe values of the last
@@ -386,7 +388,15 @@ class Simulation:
         d_env per envelope coefficient, and (fields=True) d_E, d_B at the
         start of the run (3 x ncell each)."""
         ns = len(self.species)
-        dp = _f64(dprobe, (self.nprobe, self._grad_steps)) if self.nprobe else None
+        dp = None
+        if self.nprobe:
+            dp = _f64(dprobe)
+            # the library reads nprobe x nsteps values of the last run (and
+            # refuses with PIC_ESTATE when there is none)
+            if self._grad_steps and dp.size != self.nprobe * self._grad_steps:
+                raise ValueError(f"dprobe must hold {self.nprobe} x {self._grad_steps} values")
+            if not self._grad_steps:
+                dp = np.zeros(self.nprobe)
         out = {"d_omega_c": np.zeros(ns), "d_nu": np.zeros(ns),
                "d_env": np.zeros(max(int(self.cfg.laser.n_env), 0))}
         if fields:

@@ -268,3 +268,41 @@ def test_autograd_bridge(pic):
     _say(f"autograd d/d env[{k}] {float(genv[k]):.10e}, FD {fde:.10e}")
     assert _rel(float(genv[k]), fde) < 2e-6
     assert math.isfinite(float(gnu))
+
+
+def test_gradient_run_errors(pic):
+    """Call-order and configuration errors of the gradient run come back as
+    error codes, and a failed call leaves the context usable."""
+    _say("case: gradient-run errors")
+    from paper_2208_08038_amd.inputs import Grid, OPEN, PERIODIC, LASER
+    dx = A.TWO_PI / 16.0
+    g3 = Grid(3, (16, 8, 8), (dx, dx, dx), 0.5 * dx, (LASER, PERIODIC, PERIODIC),
+              (OPEN, PERIODIC, PERIODIC), pad=3, laser=Laser())
+    s3 = pic.Simulation(g3, precision=32, max_probe_steps=8)
+    with pytest.raises(pic.PicError) as e:
+        s3.grad_forward(4, 2)
+    assert e.value.code == pic.PIC_EINVAL
+    s3.close()
+    s = pic.Simulation(A.vacuum_grid(1), precision=64, max_probe_steps=8)
+    s.set_probes([(1, (5, 0, 0))])
+    with pytest.raises(pic.PicError) as e:  # backward before any forward run
+        s.grad_backward(np.zeros((1, 4)))
+    assert e.value.code == pic.PIC_ESTATE
+    with pytest.raises(pic.PicError) as e:  # no room for 9 more probe records
+        s.grad_forward(9, 3)
+    assert e.value.code == pic.PIC_EINVAL
+    with pytest.raises(pic.PicError) as e:
+        s.grad_forward(4, 0)
+    assert e.value.code == pic.PIC_EINVAL
+    s.grad_forward(4, 2)
+    s.step(1)  # the context moved on: the run can no longer be reversed
+    with pytest.raises(pic.PicError) as e:
+        s.grad_backward(np.zeros((1, 4)))
+    assert e.value.code == pic.PIC_ESTATE
+    s.close()
+    sf = pic.Simulation(A.vacuum_grid(2), precision=32, flags=pic.FROZEN_FIELDS,
+                        max_probe_steps=8)
+    with pytest.raises(pic.PicError) as e:
+        sf.grad_forward(2, 1)
+    assert e.value.code == pic.PIC_EINVAL
+    sf.close()
