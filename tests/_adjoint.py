@@ -35,6 +35,19 @@ def small_case(ndim, steps=None, a0=1e-4, nu=0.03, omega_c=3.0, a_c=math.inf, pp
     return wl
 
 
+def with_electrons(wl, thermal=2e-3, seed=21):
+    """Ions of charge +1 (one bound electron fewer) and one free electron per
+    ion at the ion's position, Gaussian momenta of spread `thermal`: a
+    neutral two-species version of a case (species 0 ions, 1 electrons)."""
+    from paper_2208_08038_amd.inputs import POINT, Particles, Species
+    sp, parts = wl.species[0]
+    ion = dataclasses.replace(sp, q1=sp.q1 + 1.0)
+    el = Species(POINT, -1.0, 1.0, weight=sp.weight, name="e")
+    rng = np.random.default_rng(seed)
+    ep = Particles(x=np.array(parts.x, copy=True), u1=rng.normal(0.0, thermal, (parts.n, 3)))
+    return dataclasses.replace(wl, species=[(ion, parts), (el, ep)])
+
+
 def with_params(wl, omega_c=None, nu=None, env=None):
     sp, parts = wl.species[0]
     sp = dataclasses.replace(sp, omega_c=sp.omega_c if omega_c is None else omega_c,
@@ -42,12 +55,14 @@ def with_params(wl, omega_c=None, nu=None, env=None):
     grid = wl.grid
     if env is not None:
         grid = dataclasses.replace(grid, laser=dataclasses.replace(grid.laser, env=tuple(env)))
-    return dataclasses.replace(wl, grid=grid, species=[(sp, parts)])
+    return dataclasses.replace(wl, grid=grid, species=[(sp, parts)] + list(wl.species[1:]))
 
 
-def with_particles(wl, **arrays):
-    sp, parts = wl.species[0]
-    return dataclasses.replace(wl, species=[(sp, dataclasses.replace(parts, **arrays))])
+def with_particles(wl, species=0, **arrays):
+    sp = list(wl.species)
+    s, parts = sp[species]
+    sp[species] = (s, dataclasses.replace(parts, **arrays))
+    return dataclasses.replace(wl, species=sp)
 
 
 def oracle_series(wl):

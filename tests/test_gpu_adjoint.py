@@ -306,3 +306,51 @@ def test_gradient_run_errors(pic):
         sf.grad_forward(2, 1)
     assert e.value.code == pic.PIC_EINVAL
     sf.close()
+
+
+@pytest.mark.parametrize("ndim", [1, 2])
+def test_gradients_with_free_electrons(pic, ndim):
+    """Ions of charge +1 and warm free electrons (the point-particle adjoint
+    kernel): parameter gradients and one electron's initial momentum and
+    position against Richardson central differences of the FP64 forward."""
+    _say(f"case: gradients with free electrons {ndim}D")
+    wl = A.with_electrons(A.small_case(ndim, a0=3e-3))
+    rng = np.random.default_rng(17)
+    sim = pic.Simulation.from_workload(wl, precision=64, flags=pic.TRACK_IDS,
+                                       max_probe_steps=wl.steps)
+    sim.grad_forward(wl.steps, 40)
+    ids = sim.particles(1, ids=True)["id"]
+    y = sim.probes()
+    w = rng.normal(size=y.shape)
+    g = sim.grad_backward(w)
+    ge = sim.grad_particles(1)
+    sim.close()
+    loss = _loss_w(w)
+    series = lambda x: A.gpu_series(pic, x)
+    sp = wl.species[0][0]
+    env = np.array(wl.grid.laser.env)
+    checks = [("omega_c", g["d_omega_c"][0], lambda v: A.with_params(wl, omega_c=v), sp.omega_c, 1e-4),
+              ("env[4]", g["d_env"][4],
+               lambda v: A.with_params(wl, env=np.concatenate([env[:4], [v], env[5:]])), env[4], 1e-3)]
+    for name, adj, make, x0, hrel in checks:
+        fd = A.richardson_fd(series, loss, make, x0, hrel * abs(x0))
+        _say(f"{ndim}D {name}: adjoint {adj:.10e}, FD {fd:.10e}, rel {_rel(adj, fd):.2e}")
+        assert _rel(adj, fd) < 2e-7, name
+    parts = wl.species[1][1]
+    # each derivative on the electron where it matters most (a nearly
+    # cancelling derivative is not a fair finite-difference target: the
+    # B-spline is only C1 at the knots the electron crosses)
+    for key, comp, h in (("u1", 0, 1e-6), ("u1", 1, 1e-6), ("x", 0, 1e-5)):
+        slot = int(np.argmax(np.abs(ge[key][:, comp])))
+        pid = int(ids[slot])
+        arr = {"u1": parts.u1, "x": parts.x}[key]
+
+        def make(v, arr=arr, key=key, comp=comp):
+            a = np.array(arr, dtype=np.float64, copy=True)
+            a[pid, comp] = v
+            return A.with_particles(wl, species=1, **{key: a})
+        fd = A.richardson_fd(series, loss, make, float(arr[pid, comp]), h)
+        adj = float(ge[key][slot, comp])
+        _say(f"{ndim}D electron {pid} d/d{key}[{comp}]: adjoint {adj:.10e}, FD {fd:.10e}, "
+             f"rel {_rel(adj, fd):.2e}")
+        assert _rel(adj, fd) < 2e-6, (key, comp)
