@@ -247,7 +247,10 @@ int pic_read_probes(pic_ctx* ctx, double* out, int64_t* nrecorded);
    with HIP events recorded on the context stream around each dispatch.
    With the tiled kernel a species takes 2^ndim dispatches per step (one
    per tile colour), each timed on its own; the small kernel that advances
-   particles found outside their tile is not included.  Synchronises. */
+   particles found outside their tile is not included.  species_id =
+   PIC_TIMING_ADJOINT + s selects the adjoint particle kernel of species s
+   in gradient runs (one dispatch per reverse step).  Synchronises. */
+#define PIC_TIMING_ADJOINT 65536
 int pic_timing(pic_ctx* ctx, int32_t species_id, double* total_ms, int64_t* launches,
                int32_t reset);
 
@@ -277,7 +280,10 @@ int pic_timing(pic_ctx* ctx, int32_t species_id, double* total_ms, int64_t* laun
    per-particle omega_c gets the derivative with respect to a common shift
    of all of them; d_omega_c includes the nu_per_omega * omega_c part of
    the friction rate.  The context is left in the state at the end of the
-   forward run.  NULL outputs are skipped.  Synchronises. */
+   forward run, so pic_grad_backward may be called again with another
+   cotangent.  Fails with PIC_ESTATE without a completed forward run, or
+   once the context changed after it (pic_step, a load, new probes or
+   species).  NULL outputs are skipped.  Synchronises. */
 typedef struct {
   double* d_omega_c;  /* [number of species] */
   double* d_nu;       /* [number of species]: d/d(nu), the species' constant rate */

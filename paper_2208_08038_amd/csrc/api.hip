@@ -43,6 +43,17 @@ void* dev_alloc(pic_ctx* c, size_t bytes) {
   return p;
 }
 
+void dev_release(pic_ctx* c, void* p) {
+  if (!p) return;
+  auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
+  if (it == c->allocs.end()) return;
+  c->allocs.erase(it);
+  if (c->use_hip_malloc)
+    (void)hipFree(p);
+  else
+    c->alloc.free(p, c->alloc.user);
+}
+
 namespace {
 
 // pinned host buffer and events of the sort policy
@@ -797,6 +808,7 @@ int pic_create(const pic_config* cfg, const pic_allocator* alloc, void* hip_stre
 
 int pic_add_species(pic_ctx* c, const pic_species_desc* d, int32_t* sid) {
   if (!c || !d || !sid) return fail(c, PIC_EINVAL, "null argument");
+  c->version++;  // a gradient run started before this can no longer be reversed
   if (d->kind != PIC_POINT && d->kind != PIC_TWO_BODY) return fail(c, PIC_EINVAL, "bad kind");
   if ((int)c->sp.size() >= kMaxSpecies) return fail(c, PIC_EINVAL, "too many species");
   if (d->capacity < 0 || d->capacity >= (int64_t(1) << 31))
@@ -857,6 +869,7 @@ int pic_load_particles(pic_ctx* c, int32_t sid, int64_t n, const double* x, cons
                        const double* u1, const double* u2, const double* omega_c,
                        const double* weight) {
   if (!c) return PIC_EINVAL;
+  c->version++;  // a gradient run started before this can no longer be reversed
   if (sid < 0 || sid >= (int32_t)c->sp.size()) return fail(c, PIC_ESTATE, "unknown species");
   if (n < 0 || (n > 0 && (!x || !u1))) return fail(c, PIC_EINVAL, "null particle arrays");
   SpeciesHost& s = *c->sp[sid];
@@ -872,6 +885,7 @@ int pic_load_particles_device(pic_ctx* c, int32_t sid, int64_t n, const double* 
                               const double* delta, const double* u1, const double* u2,
                               const double* omega_c, const double* weight) {
   if (!c) return PIC_EINVAL;
+  c->version++;  // a gradient run started before this can no longer be reversed
   if (sid < 0 || sid >= (int32_t)c->sp.size()) return fail(c, PIC_ESTATE, "unknown species");
   if (n < 0 || (n > 0 && (!x || !u1))) return fail(c, PIC_EINVAL, "null particle arrays");
   SpeciesHost& s = *c->sp[sid];
@@ -911,11 +925,13 @@ int pic_load_particles_device(pic_ctx* c, int32_t sid, int64_t n, const double* 
 
 int pic_load_fields(pic_ctx* c, const double* E, const double* B) {
   if (!c) return PIC_EINVAL;
+  c->version++;  // a gradient run started before this can no longer be reversed
   return c->prec == 32 ? load_fields_t<float>(c, E, B) : load_fields_t<double>(c, E, B);
 }
 
 int pic_step(pic_ctx* c, int32_t nsteps) {
   if (!c || nsteps < 0) return c ? fail(c, PIC_EINVAL, "nsteps < 0") : PIC_EINVAL;
+  c->version++;  // a gradient run started before this can no longer be reversed
   return c->prec == 32 ? step_t<float>(c, nsteps) : step_t<double>(c, nsteps);
 }
 
@@ -969,6 +985,7 @@ int pic_rho(pic_ctx* c, double* rho) {
 
 int pic_set_probes(pic_ctx* c, int32_t nprobe, const int32_t* comp, const int64_t* ijk) {
   if (!c || nprobe < 0 || (nprobe > 0 && (!comp || !ijk))) return PIC_EINVAL;
+  c->version++;  // a gradient run started before this can no longer be reversed
   if (nprobe > 0 && c->cfg.max_probe_steps <= 0)
     return fail(c, PIC_EINVAL, "max_probe_steps must be positive to record probes");
   if (nprobe > c->nprobe) {

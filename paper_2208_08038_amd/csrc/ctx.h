@@ -90,6 +90,9 @@ struct pic_ctx {
   int64_t launches = 0;
   // gradient run (checkpoints and adjoint arrays), created on first use
   GradState* grad = nullptr;
+  // bumped by every call that changes the state from outside a step
+  // (loads, probes, species, pic_step); a gradient run records it
+  uint64_t version = 0;
 };
 
 // Free the gradient run's host bookkeeping (its device buffers are in the
@@ -108,8 +111,9 @@ int fail(pic_ctx* c, int code, const std::string& msg);
   } while (0)
 
 // Device memory from the caller's allocator (or hipMalloc), released at
-// pic_destroy.
+// pic_destroy, or earlier by dev_release (synchronise the stream first).
 void* dev_alloc(pic_ctx* c, size_t bytes);
+void dev_release(pic_ctx* c, void* p);
 
 inline bool is_periodic(const pic_config& c, int d) {
   return c.bc_lo[d] == PIC_BC_PERIODIC && c.bc_hi[d] == PIC_BC_PERIODIC;

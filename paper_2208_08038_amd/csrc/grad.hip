@@ -104,6 +104,7 @@ struct GradState {
   size_t dprobe_cap = 0;
   // buffers are kept for the next run when the state has the same size
   size_t alloc_bytes = 0;
+  uint64_t version = 0;           // context version at the end of the forward run
 };
 
 void grad_release(pic_ctx* c) {
@@ -169,13 +170,17 @@ int grad_buffers(pic_ctx* c, int64_t nsteps, int K) {
   std::vector<int64_t> sizes;
   for (auto& s : c->sp) sizes.push_back(s->n);
   if (L.bytes != G.alloc_bytes || sizes != G.sp_n) {
+    // a different state size: release the previous run's snapshots and
+    // particle adjoints (the field-sized buffers keep their size)
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (void* p : G.ck) dev_release(c, p);
+    for (void* p : G.slot) dev_release(c, p);
+    for (void* p : G.lam_sp) dev_release(c, p);
+    dev_release(c, G.final_state);
     G.ck.clear();
     G.slot.clear();
-    G.final_state = nullptr;
-    G.lam_fields = nullptr;
     G.lam_sp.clear();
-    std::memset(G.lam_mur_b, 0, sizeof(G.lam_mur_b));
-    std::memset(G.lam_mur_e, 0, sizeof(G.lam_mur_e));
+    G.final_state = nullptr;
     G.alloc_bytes = L.bytes;
   }
   G.lay = L;
@@ -310,6 +315,7 @@ int grad_forward_t(pic_ctx* c, int64_t nsteps, int K) {
   }
   if ((rc = snap_copy(c, G.final_state, true))) return rc;
   G.final_step = c->step;
+  G.version = c->version;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(c, PIC_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
   G.ready = true;
@@ -505,8 +511,8 @@ int pic_grad_backward(pic_ctx* c, const double* dprobe, pic_grad* out) {
   for (size_t si = 0; si < c->sp.size(); si++)
     if (si >= c->grad->sp_n.size() || c->sp[si]->n != c->grad->sp_n[si])
       return fail(c, PIC_ESTATE, "species changed since pic_grad_forward");
-  if (c->grad->final_step != c->step)
-    return fail(c, PIC_ESTATE, "the context was stepped since pic_grad_forward");
+  if (c->grad->final_step != c->step || c->grad->version != c->version)
+    return fail(c, PIC_ESTATE, "the context was stepped or changed since pic_grad_forward");
   return c->prec == 32 ? grad_backward_t<float>(c, dprobe, out)
                        : grad_backward_t<double>(c, dprobe, out);
 }

@@ -299,6 +299,11 @@ def test_gradient_run_errors(pic):
     with pytest.raises(pic.PicError) as e:
         s.grad_backward(np.zeros((1, 4)))
     assert e.value.code == pic.PIC_ESTATE
+    s.grad_forward(2, 1)
+    s.load_fields(np.zeros((3, s.ncell)), np.zeros((3, s.ncell)))  # so does a load
+    with pytest.raises(pic.PicError) as e:
+        s.grad_backward(np.zeros((1, 2)))
+    assert e.value.code == pic.PIC_ESTATE
     s.close()
     sf = pic.Simulation(A.vacuum_grid(2), precision=32, flags=pic.FROZEN_FIELDS,
                         max_probe_steps=8)
@@ -354,3 +359,26 @@ def test_gradients_with_free_electrons(pic, ndim):
         _say(f"{ndim}D electron {pid} d/d{key}[{comp}]: adjoint {adj:.10e}, FD {fd:.10e}, "
              f"rel {_rel(adj, fd):.2e}")
         assert _rel(adj, fd) < 2e-6, (key, comp)
+
+
+def test_backward_is_repeatable_and_linear(pic):
+    """One forward run, three reverse sweeps: the context is restored after
+    each, so the gradients are linear in the cotangent and the run can be
+    reversed again (2D case with ions, FP64)."""
+    _say("case: repeated reverse sweeps")
+    wl = A.small_case(2)
+    sim = pic.Simulation.from_workload(wl, precision=64, max_probe_steps=wl.steps)
+    sim.grad_forward(wl.steps, 32)
+    rng = np.random.default_rng(2)
+    y = sim.probes()
+    w1, w2 = rng.normal(size=y.shape), rng.normal(size=y.shape)
+    g1 = sim.grad_backward(w1, fields=True)
+    g2 = sim.grad_backward(w2, fields=True)
+    g12 = sim.grad_backward(w1 + 2.0 * w2, fields=True)
+    for k in ("d_omega_c", "d_nu", "d_env", "d_E", "d_B"):
+        ref = g1[k] + 2.0 * g2[k]
+        err = np.abs(g12[k] - ref).max() / max(np.abs(ref).max(), 1e-300)
+        _say(f"{k}: linearity error {err:.2e}")
+        assert err < 1e-11, k
+    assert sim.diagnostics()["step"] == wl.steps
+    sim.close()
