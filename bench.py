@@ -185,7 +185,7 @@ def run_adjoint(args):
     wl = adjoint_slab(2, (nx, ny), steps=args.adjoint_steps, ppc=args.adjoint_ppc)
     t0 = time.perf_counter()
     sim = pic.Simulation.from_workload(wl, precision=32, flags=pic.TIMING,
-                                       max_probe_steps=wl.steps)
+                                       max_probe_steps=wl.steps, tile=args.adjoint_tile)
     torch.cuda.synchronize()
     t_load = time.perf_counter() - t0
     n_ion = wl.species[0][1].n
@@ -220,6 +220,7 @@ def run_adjoint(args):
     gbs = bytes_launch / (launch_ms * 1e-3) / 1e9 if launch_ms else None
     return {
         "workload": "adjoint_slab_2d", "cells": [nx, ny], "two_body_ions": n_ion,
+        "tile": list(args.adjoint_tile) if args.adjoint_tile else "default",
         "steps": wl.steps, "checkpoint_every": args.checkpoint_every, "precision": "fp32",
         "loss": "E_T / E_T(base) + phase at the probe plane x = 512",
         "load_s": t_load, "forward_s": t_fwd, "backward_s": t_bwd,
@@ -281,6 +282,8 @@ def main():
     ap.add_argument("--adjoint-ppc", type=int, default=16)
     ap.add_argument("--adjoint-steps", type=int, default=1024)
     ap.add_argument("--checkpoint-every", type=int, default=32)
+    ap.add_argument("--adjoint-tile", type=int, nargs=2, default=None,
+                    help="cells per tile in the gradient-run leg (default: the library's)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "

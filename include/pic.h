@@ -121,7 +121,7 @@ typedef struct {
   double dt;           /* must satisfy dt < 1/sqrt(sum_d dx_d^-2) */
   int32_t bc_lo[3], bc_hi[3];
   int32_t tile[3];     /* tile shape in cells (0: library default: 8x8x6 in 3D FP32,
-                          8x8x8 in 3D FP64, 16x16 in 2D, 256 in 1D) */
+                          8x8x8 in 3D FP64, 12x12 in 2D, 256 in 1D) */
   int32_t sort_every;  /* > 0: re-sort particles by tile every this many steps; 0: per
                           species, once the particles advanced outside their tile since
                           its last sort reach 1/200 of the species, or after 64 steps */

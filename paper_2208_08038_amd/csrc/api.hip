@@ -738,7 +738,7 @@ int pic_create(const pic_config* cfg, const pic_allocator* alloc, void* hip_stre
   // default tiles: in 3D FP32 an 8x8x6 tile lets two workgroups share a CU
   // (LDS under 80 KB); FP64 fields need the larger 8^3 tile's one per CU
   const int def3f[3] = {8, 8, 6}, def3d[3] = {8, 8, 8};
-  const int def2[3] = {16, 16, 1}, def1[3] = {256, 1, 1};
+  const int def2[3] = {12, 12, 1}, def1[3] = {256, 1, 1};
   const int* def3 = cfg->precision == 32 ? def3f : def3d;
   const int* def = g.nd == 3 ? def3 : (g.nd == 2 ? def2 : def1);
   for (int d = 0; d < 3; d++) {
