@@ -122,7 +122,8 @@ def run_gpu(args, precision, keep_fields=False):
 
     n = tuple(args.cells)
     sim, _, sid_i, sid_e, t_load = ionised_slab_simulation(
-        n, args.ppc, precision, pic.TIMING, args.sort_every, args.tile, args.chunk_particles)
+        n, args.ppc, precision, pic.TIMING, args.sort_every,
+        args.tile if precision == 32 else args.tile64, args.chunk_particles)
     n_ion, n_el = sim.count(sid_i), sim.count(sid_e)
     print(f"[bench] fp{precision}: loaded {n_ion} ions + {n_el} electrons in {t_load:.1f} s",
           file=sys.stderr, flush=True)
@@ -269,8 +270,12 @@ def main():
     ap.add_argument("--tile", type=int, nargs=3, default=None,
                     help="cells per tile of the LDS-tiled particle kernel "
                          "(default: the library's, 8x8x6 for FP32 and 8x8x8 for FP64)")
+    ap.add_argument("--tile64", type=int, nargs=3, default=None,
+                    help="cells per tile of the FP64 run (default: the library's, 8x8x8)")
     ap.add_argument("--chunk-particles", type=float, default=3.4e7)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 run")
+    ap.add_argument("--fp64-only", action="store_true",
+                    help="only the FP64 run (one JSON object with its numbers)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=float, metavar="MIB",
@@ -299,6 +304,12 @@ def main():
 
     if args.adjoint_only:
         print(json.dumps({"adjoint": run_adjoint(args)}), flush=True)
+        return
+    if args.fp64_only:
+        r = run_gpu(args, 64)
+        r.pop("fields", None)
+        print(json.dumps({"fp64": {k: v for k, v in r.items() if not hasattr(v, "shape")},
+                          "tile64": args.tile64 or "default"}), flush=True)
         return
     r32 = run_gpu(args, 32, keep_fields=not args.no_fp64)
     r64 = None if args.no_fp64 else run_gpu(args, 64, keep_fields=True)
