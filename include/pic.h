@@ -254,8 +254,8 @@ int pic_read_probes(pic_ctx* ctx, double* out, int64_t* nrecorded);
 int pic_timing(pic_ctx* ctx, int32_t species_id, double* total_ms, int64_t* launches,
                int32_t reset);
 
-/* Gradient run: the adjoint of the step (1D and 2D grids, both species
-   kinds, FP32 and FP64), the differentiation axis that the bound-electron
+/* Gradient run: the adjoint of the step (1D, 2D and 3D grids, both
+   species kinds, FP32 and FP64), the differentiation axis that the bound-electron
    model of Sec. 2 / Sec. 3.1 opens: how a transmitted or reflected pulse
    depends on the restoring frequency omega_c, the friction rate and the
    laser's temporal envelope.
@@ -266,7 +266,7 @@ int pic_timing(pic_ctx* ctx, int32_t species_id, double* total_ms, int64_t* laun
    the probes after every step, and keeps a device snapshot of the whole
    state every checkpoint_every steps (memory: ceil(nsteps / K) + K + 1
    snapshots, each the particle state plus E, B and the Mur history).
-   Fails with PIC_EINVAL in 3D, with PIC_FLAG_FROZEN_FIELDS or
+   Fails with PIC_EINVAL with PIC_FLAG_FROZEN_FIELDS or
    PIC_FLAG_NO_DEPOSIT, or when the probe record has no room for nsteps
    more steps.
 

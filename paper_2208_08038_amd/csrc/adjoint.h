@@ -12,8 +12,8 @@ namespace pic {
 template <typename Real>
 using AdjState = SpeciesDev<Real>;
 
-// Reverse the particle cycle of one step for one species (1D and 2D
-// grids): reads the stored state `st`, the fields (E, B planes at the start
+// Reverse the particle cycle of one step for one species (1D, 2D
+// and 3D grids): reads the stored state `st`, the fields (E, B planes at the start
 // of the step, guards filled, contiguous from `fields`, g.plane apart) and
 // the adjoint current (planes 6..8 of `lam`, whose planes 0..5 are the
 // adjoint E, B); updates the particle adjoint `lp` in place, adds the
@@ -21,9 +21,14 @@ using AdjState = SpeciesDev<Real>;
 // d/d(friction rate) to dparam[0], dparam[1].
 // Tiles of the sorted particle order (cells per tile, tiles per dim).
 struct AdjTiles {
-  int T[2];
-  int nt[2];
+  int T[3];
+  int nt[3];
 };
+
+// Workgroups and LDS bytes of the tiled adjoint kernel (the launcher fails
+// if the LDS does not fit a workgroup; the host checks first).
+size_t adjoint_tiles(const GridInfo& g, const AdjTiles& tt);
+size_t adjoint_lds_bytes(const GridInfo& g, const AdjTiles& tt, size_t rsize);
 
 // With tile_off (the species' tile offsets of its last sort, which the
 // gradient run keeps) one workgroup per tile accumulates the scatter in LDS;

@@ -1,5 +1,5 @@
 // adjoint.hip -- reverse-mode (adjoint) particle cycle of the gradient run,
-// 1D and 2D grids, two-body ions and point particles.
+// 1D, 2D and 3D grids, two-body ions and point particles.
 //
 // One thread per macro-particle (one workgroup per tile of the sorted order
 // when the tile offsets are given).  The thread recomputes the forward cycle
@@ -75,22 +75,22 @@ __device__ __forceinline__ Shape<Real> unit_shape() {
 }
 
 // Destination of the gather's transpose for one particle: an FP64 LDS
-// patch of the workgroup's tile (component planes of `lplane` values, row
-// pitch `lsy`, the particle's cell at index `lbase`), or the global adjoint
-// planes with atomics (particles outside their tile).  Nodes are given
-// relative to the particle's cell.
+// patch of the workgroup's tile (component planes of `lplane` values,
+// strides lsy, lsz, the particle's cell at index `lbase`), or the global
+// adjoint planes with atomics (particles outside their tile).  Nodes are
+// given relative to the particle's cell.
 template <typename Real>
 struct Sink {
   Planes<Real> l;
-  int64_t gbase, gsy;
+  int64_t gbase, gsy, gsz;
   double* lds;
-  int lbase, lsy, lplane;
-  __device__ __forceinline__ void add(int comp, int ix, int iy, Real v) const {
+  int lbase, lsy, lsz, lplane;
+  __device__ __forceinline__ void add(int comp, int ix, int iy, int iz, Real v) const {
     if (lds) {
-      atomicAdd(lds + comp * lplane + lbase + ix + iy * lsy, (double)v);
+      atomicAdd(lds + comp * lplane + lbase + ix + iy * lsy + iz * lsz, (double)v);
     } else {
       Real* F = l.base + comp * l.plane;
-      unsafeAtomicAdd(F + gbase + ix + iy * gsy, v);
+      unsafeAtomicAdd(F + gbase + ix + iy * gsy + iz * gsz, v);
     }
   }
 };
@@ -99,14 +99,14 @@ struct Sink {
 // staggers of each resolved axis (unit shapes along unresolved ones).
 template <typename Real>
 struct Stencil {
-  Shape<Real> n[2], h[2];
+  Shape<Real> n[3], h[3];
 };
 
 template <typename Real, int ND>
 __device__ __forceinline__ Stencil<Real> stencil_at(const Real x[3]) {
   Stencil<Real> s;
 #pragma unroll
-  for (int d = 0; d < 2; d++) {
+  for (int d = 0; d < 3; d++) {
     if (d < ND) {
       s.n[d] = shape_at(x[d], false);
       s.h[d] = shape_at(x[d], true);
@@ -117,112 +117,106 @@ __device__ __forceinline__ Stencil<Real> stencil_at(const Real x[3]) {
   return s;
 }
 
+// Node offsets and strides of one interpolation: the base index of the
+// particle's cell and the y, z strides of the array read.
+struct Where3 {
+  int64_t base, sy, sz;
+};
+
 template <typename Real, int ND>
-__device__ __forceinline__ Real interp_value(const Real* __restrict__ F, int64_t base, int64_t sy,
-                                             const Shape<Real>& sx, const Shape<Real>& syy) {
+__device__ __forceinline__ Real interp_value(const Real* __restrict__ F, const Where3& w,
+                                             const Shape<Real>& sx, const Shape<Real>& syy,
+                                             const Shape<Real>& szz) {
   Real v = 0;
-  constexpr int NY = ND > 1 ? 3 : 1;
+  constexpr int NY = ND > 1 ? 3 : 1, NZ = ND > 2 ? 3 : 1;
 #pragma unroll
-  for (int s = 0; s < NY; s++) {
-    const Real* row = F + base + sx.i0 + (ND > 1 ? (int64_t)(syy.i0 + s) * sy : 0);
-    const Real wy = ND > 1 ? syy.w[s] : Real(1);
-    v += wy * (sx.w[0] * row[0] + sx.w[1] * row[1] + sx.w[2] * row[2]);
+  for (int t = 0; t < NZ; t++) {
+    Real vy = 0;
+#pragma unroll
+    for (int s = 0; s < NY; s++) {
+      const Real* row = F + w.base + sx.i0 + (ND > 1 ? (int64_t)(syy.i0 + s) * w.sy : 0) +
+                        (ND > 2 ? (int64_t)(szz.i0 + t) * w.sz : 0);
+      const Real wy = ND > 1 ? syy.w[s] : Real(1);
+      vy += wy * (sx.w[0] * row[0] + sx.w[1] * row[1] + sx.w[2] * row[2]);
+    }
+    v += (ND > 2 ? szz.w[t] : Real(1)) * vy;
   }
   return v;
 }
 
 // E and B at a body position (the gather of the forward cycle): E_a
-// half-staggered along a, B_a along the other axes (z unresolved).
+// half-staggered along a, B_a along the two other axes.
 template <typename Real, int ND>
-__device__ __forceinline__ void gather_values(const Planes<Real>& f, int64_t base, int64_t sy,
+__device__ __forceinline__ void gather_values(const Planes<Real>& f, const Where3& w,
                                               const Real x[3], Real E[3], Real B[3]) {
   const Stencil<Real> t = stencil_at<Real, ND>(x);
-  E[0] = interp_value<Real, ND>(f.E(0), base, sy, t.h[0], t.n[1]);
-  E[1] = interp_value<Real, ND>(f.E(1), base, sy, t.n[0], t.h[1]);
-  E[2] = interp_value<Real, ND>(f.E(2), base, sy, t.n[0], t.n[1]);
-  B[0] = interp_value<Real, ND>(f.B(0), base, sy, t.n[0], t.h[1]);
-  B[1] = interp_value<Real, ND>(f.B(1), base, sy, t.h[0], t.n[1]);
-  B[2] = interp_value<Real, ND>(f.B(2), base, sy, t.h[0], t.h[1]);
+  E[0] = interp_value<Real, ND>(f.E(0), w, t.h[0], t.n[1], t.n[2]);
+  E[1] = interp_value<Real, ND>(f.E(1), w, t.n[0], t.h[1], t.n[2]);
+  E[2] = interp_value<Real, ND>(f.E(2), w, t.n[0], t.n[1], t.h[2]);
+  B[0] = interp_value<Real, ND>(f.B(0), w, t.n[0], t.h[1], t.h[2]);
+  B[1] = interp_value<Real, ND>(f.B(1), w, t.h[0], t.n[1], t.h[2]);
+  B[2] = interp_value<Real, ND>(f.B(2), w, t.h[0], t.h[1], t.n[2]);
 }
 
-// Adjoint of one interpolated component for one body, in one pass over its
-// nodes: scatter lam * weight(node) and add lam * d(interpolant)/dx to lx.
-template <typename Real, int ND>
+// Adjoint of one interpolated component for one body (or, with two shapes,
+// for both bodies of an ion whose stencils share the nodes), in one pass
+// over its nodes: scatter lam * weight(node) and add lam * d(interp)/dx
+// to lx.
+template <typename Real, int ND, bool PAIR>
 __device__ __forceinline__ void comp_adjoint(const Real* __restrict__ F, int comp,
-                                             const Sink<Real>& k, int64_t base, int64_t sy,
-                                             const Shape<Real>& sx, const Shape<Real>& syy,
-                                             Real lam, Real lx[2]) {
-  if (lam == Real(0)) return;
-  constexpr int NY = ND > 1 ? 3 : 1;
+                                             const Sink<Real>& k, const Where3& w,
+                                             const Shape<Real>& ax, const Shape<Real>& ay,
+                                             const Shape<Real>& az, Real la,
+                                             const Shape<Real>& bx, const Shape<Real>& by,
+                                             const Shape<Real>& bz, Real lb, Real lxa[3],
+                                             Real lxb[3]) {
+  if (la == Real(0) && (!PAIR || lb == Real(0))) return;
+  constexpr int NY = ND > 1 ? 3 : 1, NZ = ND > 2 ? 3 : 1;
 #pragma unroll
-  for (int s = 0; s < NY; s++) {
-    const int iy = ND > 1 ? syy.i0 + s : 0;
-    const Real* row = F + base + sx.i0 + (ND > 1 ? (int64_t)iy * sy : 0);
-    const Real r0 = row[0], r1 = row[1], r2 = row[2];
-    const Real wy = ND > 1 ? syy.w[s] : Real(1);
-    lx[0] += lam * wy * (sx.dw[0] * r0 + sx.dw[1] * r1 + sx.dw[2] * r2);
-    if (ND > 1) lx[1] += lam * syy.dw[s] * (sx.w[0] * r0 + sx.w[1] * r1 + sx.w[2] * r2);
-    const Real a = lam * wy;
+  for (int t = 0; t < NZ; t++) {
+    const int iz = ND > 2 ? az.i0 + t : 0;
 #pragma unroll
-    for (int r = 0; r < 3; r++) k.add(comp, sx.i0 + r, iy, a * sx.w[r]);
-  }
-}
-
-// Same for both bodies of an ion when their stencils share the nodes: one
-// add per node with both weights.
-template <typename Real, int ND>
-__device__ __forceinline__ void comp_adjoint2(const Real* __restrict__ F, int comp,
-                                              const Sink<Real>& k, int64_t base, int64_t sy,
-                                              const Shape<Real>& ax, const Shape<Real>& ay,
-                                              Real la, const Shape<Real>& bx,
-                                              const Shape<Real>& by, Real lb, Real lxa[2],
-                                              Real lxb[2]) {
-  if (la == Real(0) && lb == Real(0)) return;
-  constexpr int NY = ND > 1 ? 3 : 1;
+    for (int s = 0; s < NY; s++) {
+      const int iy = ND > 1 ? ay.i0 + s : 0;
+      const Real* row = F + w.base + ax.i0 + (ND > 1 ? (int64_t)iy * w.sy : 0) +
+                        (ND > 2 ? (int64_t)iz * w.sz : 0);
+      const Real r0 = row[0], r1 = row[1], r2 = row[2];
+      const Real wza = ND > 2 ? az.w[t] : Real(1), wya = ND > 1 ? ay.w[s] : Real(1);
+      const Real va = ax.w[0] * r0 + ax.w[1] * r1 + ax.w[2] * r2;
+      lxa[0] += la * wza * wya * (ax.dw[0] * r0 + ax.dw[1] * r1 + ax.dw[2] * r2);
+      if (ND > 1) lxa[1] += la * wza * ay.dw[s] * va;
+      if (ND > 2) lxa[2] += la * az.dw[t] * wya * va;
+      const Real ca = la * wza * wya;
+      Real cb = 0;
+      if constexpr (PAIR) {
+        const Real wzb = ND > 2 ? bz.w[t] : Real(1), wyb = ND > 1 ? by.w[s] : Real(1);
+        const Real vb = bx.w[0] * r0 + bx.w[1] * r1 + bx.w[2] * r2;
+        lxb[0] += lb * wzb * wyb * (bx.dw[0] * r0 + bx.dw[1] * r1 + bx.dw[2] * r2);
+        if (ND > 1) lxb[1] += lb * wzb * by.dw[s] * vb;
+        if (ND > 2) lxb[2] += lb * bz.dw[t] * wyb * vb;
+        cb = lb * wzb * wyb;
+      }
 #pragma unroll
-  for (int s = 0; s < NY; s++) {
-    const int iy = ND > 1 ? ay.i0 + s : 0;
-    const Real* row = F + base + ax.i0 + (ND > 1 ? (int64_t)iy * sy : 0);
-    const Real r0 = row[0], r1 = row[1], r2 = row[2];
-    const Real wya = ND > 1 ? ay.w[s] : Real(1), wyb = ND > 1 ? by.w[s] : Real(1);
-    lxa[0] += la * wya * (ax.dw[0] * r0 + ax.dw[1] * r1 + ax.dw[2] * r2);
-    lxb[0] += lb * wyb * (bx.dw[0] * r0 + bx.dw[1] * r1 + bx.dw[2] * r2);
-    if (ND > 1) {
-      lxa[1] += la * ay.dw[s] * (ax.w[0] * r0 + ax.w[1] * r1 + ax.w[2] * r2);
-      lxb[1] += lb * by.dw[s] * (bx.w[0] * r0 + bx.w[1] * r1 + bx.w[2] * r2);
+      for (int r = 0; r < 3; r++)
+        k.add(comp, ax.i0 + r, iy, iz, PAIR ? ca * ax.w[r] + cb * bx.w[r] : ca * ax.w[r]);
     }
-    const Real a = la * wya, b = lb * wyb;
-#pragma unroll
-    for (int r = 0; r < 3; r++) k.add(comp, ax.i0 + r, iy, a * ax.w[r] + b * bx.w[r]);
   }
 }
 
-// The gather's transpose for a body at x (or, with TWO_SHARED, for both
-// bodies of an ion whose stencils share the nodes).
-template <typename Real, int ND>
+// The gather's transpose for one body, or for both bodies of an ion whose
+// stencils share the nodes (PAIR).
+template <typename Real, int ND, bool PAIR>
 __device__ __forceinline__ void gather_adjoint(const Planes<Real>& f, const Sink<Real>& k,
-                                               int64_t base, int64_t sy, const Stencil<Real>& t,
-                                               const Real lE[3], const Real lB[3], Real lx[2]) {
-  comp_adjoint<Real, ND>(f.E(0), 0, k, base, sy, t.h[0], t.n[1], lE[0], lx);
-  comp_adjoint<Real, ND>(f.E(1), 1, k, base, sy, t.n[0], t.h[1], lE[1], lx);
-  comp_adjoint<Real, ND>(f.E(2), 2, k, base, sy, t.n[0], t.n[1], lE[2], lx);
-  comp_adjoint<Real, ND>(f.B(0), 3, k, base, sy, t.n[0], t.h[1], lB[0], lx);
-  comp_adjoint<Real, ND>(f.B(1), 4, k, base, sy, t.h[0], t.n[1], lB[1], lx);
-  comp_adjoint<Real, ND>(f.B(2), 5, k, base, sy, t.h[0], t.h[1], lB[2], lx);
-}
-
-template <typename Real, int ND>
-__device__ __forceinline__ void gather_adjoint2(const Planes<Real>& f, const Sink<Real>& k,
-                                                int64_t base, int64_t sy, const Stencil<Real>& a,
-                                                const Real lEa[3], const Real lBa[3],
-                                                const Stencil<Real>& b, const Real lEb[3],
-                                                const Real lBb[3], Real lxa[2], Real lxb[2]) {
-  comp_adjoint2<Real, ND>(f.E(0), 0, k, base, sy, a.h[0], a.n[1], lEa[0], b.h[0], b.n[1], lEb[0], lxa, lxb);
-  comp_adjoint2<Real, ND>(f.E(1), 1, k, base, sy, a.n[0], a.h[1], lEa[1], b.n[0], b.h[1], lEb[1], lxa, lxb);
-  comp_adjoint2<Real, ND>(f.E(2), 2, k, base, sy, a.n[0], a.n[1], lEa[2], b.n[0], b.n[1], lEb[2], lxa, lxb);
-  comp_adjoint2<Real, ND>(f.B(0), 3, k, base, sy, a.n[0], a.h[1], lBa[0], b.n[0], b.h[1], lBb[0], lxa, lxb);
-  comp_adjoint2<Real, ND>(f.B(1), 4, k, base, sy, a.h[0], a.n[1], lBa[1], b.h[0], b.n[1], lBb[1], lxa, lxb);
-  comp_adjoint2<Real, ND>(f.B(2), 5, k, base, sy, a.h[0], a.h[1], lBa[2], b.h[0], b.h[1], lBb[2], lxa, lxb);
+                                               const Where3& w, const Stencil<Real>& a,
+                                               const Real lEa[3], const Real lBa[3],
+                                               const Stencil<Real>& b, const Real lEb[3],
+                                               const Real lBb[3], Real lxa[3], Real lxb[3]) {
+  comp_adjoint<Real, ND, PAIR>(f.E(0), 0, k, w, a.h[0], a.n[1], a.n[2], lEa[0], b.h[0], b.n[1], b.n[2], lEb[0], lxa, lxb);
+  comp_adjoint<Real, ND, PAIR>(f.E(1), 1, k, w, a.n[0], a.h[1], a.n[2], lEa[1], b.n[0], b.h[1], b.n[2], lEb[1], lxa, lxb);
+  comp_adjoint<Real, ND, PAIR>(f.E(2), 2, k, w, a.n[0], a.n[1], a.h[2], lEa[2], b.n[0], b.n[1], b.h[2], lEb[2], lxa, lxb);
+  comp_adjoint<Real, ND, PAIR>(f.B(0), 3, k, w, a.n[0], a.h[1], a.h[2], lBa[0], b.n[0], b.h[1], b.h[2], lBb[0], lxa, lxb);
+  comp_adjoint<Real, ND, PAIR>(f.B(1), 4, k, w, a.h[0], a.n[1], a.h[2], lBa[1], b.h[0], b.n[1], b.h[2], lBb[1], lxa, lxb);
+  comp_adjoint<Real, ND, PAIR>(f.B(2), 5, k, w, a.h[0], a.h[1], a.n[2], lBa[2], b.h[0], b.h[1], b.n[2], lBb[2], lxa, lxb);
 }
 
 template <typename Real, int ND>
@@ -360,16 +354,18 @@ __device__ __forceinline__ bool win4(Real x0, Real x1, Win4<Real>& w) {
 // velocity v for the out-of-plane components): with lJ the adjoint current,
 // Phi = sum lJ . J; returns dPhi/dx0, dPhi/dx1 (resolved dims) and
 // dPhi/dv (unresolved components).  The running sum along an axis turns
-// into a suffix sum of lJ.
+// into a suffix sum of lJ; the path-averaged transverse shape
+// M = S0 S0'/3 + S0 S1'/6 + S1 S0'/6 + S1 S1'/3 (two transverse axes) or
+// (S0 + S1)/2 (one) is differentiated by hand.
 template <typename Real, int ND>
-__device__ __forceinline__ bool deposit_adjoint(const Real* J, int64_t jplane, int64_t base,
-                                                int64_t sy,
+__device__ __forceinline__ bool deposit_adjoint(const Real* J, int64_t jplane, const Where3& wh,
                                                 const Real x0[3], const Real x1[3], Real Q,
                                                 const Real v[3], const PushConst<Real>& c,
-                                                Real g0[2], Real g1[2], Real gv[3]) {
+                                                Real g0[3], Real g1[3], Real gv[3]) {
   const Real third = Real(1) / Real(3), sixth = Real(1) / Real(6);
-  g0[0] = g0[1] = g1[0] = g1[1] = Real(0);
-  gv[0] = gv[1] = gv[2] = Real(0);
+  const int64_t base = wh.base, sy = wh.sy;
+#pragma unroll
+  for (int d = 0; d < 3; d++) g0[d] = g1[d] = gv[d] = Real(0);
   if constexpr (ND == 1) {
     Win4<Real> wx;
     if (!win4(x0[0], x1[0], wx)) return false;
@@ -396,7 +392,7 @@ __device__ __forceinline__ bool deposit_adjoint(const Real* J, int64_t jplane, i
       g1[0] += dS1 * wx.D1[r];
     }
     return true;
-  } else {
+  } else if constexpr (ND == 2) {
     Win4<Real> wx, wy;
     if (!win4(x0[0], x1[0], wx) || !win4(x0[1], x1[1], wy)) return false;
     const int64_t o = base + wx.lo + (int64_t)wy.lo * sy;
@@ -477,6 +473,61 @@ __device__ __forceinline__ bool deposit_adjoint(const Real* J, int64_t jplane, i
       g1[1] += G1y[r] * wy.D1[r];
     }
     return true;
+  } else {
+    Win4<Real> w[3];
+    if (!win4(x0[0], x1[0], w[0]) || !win4(x0[1], x1[1], w[1]) || !win4(x0[2], x1[2], w[2]))
+      return false;
+    const int64_t st[3] = {1, sy, wh.sz};
+    const int64_t o = base + w[0].lo + (int64_t)w[1].lo * sy + (int64_t)w[2].lo * wh.sz;
+    Real G0[3][4], G1[3][4];
+#pragma unroll
+    for (int d = 0; d < 3; d++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) G0[d][r] = G1[d][r] = Real(0);
+    // J_a(i_a, i_b, i_c) = Q jf_a C_a(i_a) M(i_b, i_c), C_a the running sum of
+    // the shape change along a, (b, c) the transverse axes
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      const int b = a == 0 ? 1 : 0, e = a == 2 ? 1 : 2;
+      const Real f = Q * c.jf[a];
+      const Real* Ja = J + a * jplane;
+#pragma unroll
+      for (int s = 0; s < 4; s++)
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+          const int64_t ob = o + s * st[b] + t * st[e];
+          Real L[4], acc = 0;
+          L[3] = Real(0);
+#pragma unroll
+          for (int r = 2; r >= 0; r--) {
+            acc += Ja[ob + r * st[a]];
+            L[r] = acc;
+          }
+          const Real M = third * w[b].S0[s] * w[e].S0[t] + sixth * w[b].S0[s] * w[e].S1[t] +
+                         sixth * w[b].S1[s] * w[e].S0[t] + third * w[b].S1[s] * w[e].S1[t];
+          Real P = 0;
+#pragma unroll
+          for (int r = 0; r < 4; r++) {
+            const Real q = f * M * L[r];
+            G1[a][r] += q;
+            G0[a][r] -= q;
+            P += (w[a].S1[r] - w[a].S0[r]) * L[r];
+          }
+          P *= f;
+          G0[b][s] += P * (third * w[e].S0[t] + sixth * w[e].S1[t]);
+          G1[b][s] += P * (sixth * w[e].S0[t] + third * w[e].S1[t]);
+          G0[e][t] += P * (third * w[b].S0[s] + sixth * w[b].S1[s]);
+          G1[e][t] += P * (sixth * w[b].S0[s] + third * w[b].S1[s]);
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < 3; d++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        g0[d] += G0[d][r] * w[d].D0[r];
+        g1[d] += G1[d][r] * w[d].D1[r];
+      }
+    return true;
   }
 }
 
@@ -520,8 +571,8 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 template <typename Real>
 struct PIn {
   uint32_t cell;
-  Real off[2], u1[3], u2[3], dl[3], wc, w;
-  Real loff[2], ldl[3], lu1[3], lu2[3];
+  Real off[3], u1[3], u2[3], dl[3], wc, w;
+  Real loff[3], ldl[3], lu1[3], lu2[3];
 };
 
 template <typename Real, int ND, bool TWO>
@@ -529,7 +580,7 @@ __device__ __forceinline__ void load_in(const AdjState<Real>& st, const AdjState
                                         const PushConst<Real>& c, int64_t p, PIn<Real>& in) {
   in.cell = st.cell[p];
 #pragma unroll
-  for (int d = 0; d < 2; d++) {
+  for (int d = 0; d < 3; d++) {
     in.off[d] = d < ND ? st.off[d][p] : Real(0);
     in.loff[d] = d < ND ? lp.off[d][p] : Real(0);
   }
@@ -555,9 +606,9 @@ __device__ __forceinline__ void load_in(const AdjState<Real>& st, const AdjState
 template <typename Real>
 struct TileBox {
   double* lds;
-  Real* f;
-  Real* lj;
-  int x0, y0, tx, ty, pitch, plane;
+  Real* f;   // staged E, B (1D and 2D)
+  Real* lj;  // staged adjoint current (1D and 2D)
+  int x0, y0, z0, tx, ty, tz, pitch, slab, plane;
 };
 
 // Reverse the cycle of particle p (see the file comment).
@@ -577,6 +628,7 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const Planes<Real
     const uint32_t pk = in.cell;
     ci[0] = pk & ((1u << g.bits[0]) - 1u);
     if (ND > 1) ci[1] = (pk >> g.bits[0]) & ((1u << g.bits[1]) - 1u);
+    if (ND > 2) ci[2] = pk >> (g.bits[0] + g.bits[1]);
     Real off[3] = {0, 0, 0}, u1[3], u2[3] = {0, 0, 0}, dl[3] = {0, 0, 0};
 #pragma unroll
     for (int d = 0; d < ND; d++) off[d] = in.off[d];
@@ -603,39 +655,44 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const Planes<Real
 #pragma unroll
     for (int q = 0; q < 3; q++) ok = ok && isfinite(u1[q]) && isfinite(u2[q]) && isfinite(dl[q]);
     if (!ok) break;  // the forward cycle left it unchanged: identity
-    // where the fields, the adjoint current and the scatter live
-    Planes<Real> f;
-    const Real* LJ;
-    int64_t jplane, base, sy;
+    // where the fields, the adjoint current and the scatter live: the
+    // tile's LDS copies for a particle in the tile (in 3D only the scatter,
+    // the fields and adjoint current being read from the global planes),
+    // else the global planes
+    Planes<Real> f = fg;
+    const Real* LJ = l.J(0);
+    int64_t jplane = l.plane;
     Sink<Real> k;
     k.l = l;
-    k.gbase = g.origin + ci[0] + (ND > 1 ? (int64_t)ci[1] * g.sy : 0);
+    k.gbase = g.origin + ci[0] + (ND > 1 ? (int64_t)ci[1] * g.sy : 0) +
+              (ND > 2 ? (int64_t)ci[2] * g.sz : 0);
     k.gsy = g.sy;
+    k.gsz = g.sz;
+    k.lds = nullptr;
+    k.lbase = k.lsy = k.lsz = k.lplane = 0;
+    Where3 wh{k.gbase, g.sy, g.sz};
     if constexpr (IN_TILE) {
       const int cx = ci[0] - box.x0, cy = ND > 1 ? ci[1] - box.y0 : 0;
-      base = (cx + 2) + (ND > 1 ? (cy + 2) * box.pitch : 0);
-      sy = box.pitch;
-      f = Planes<Real>{box.f, box.plane};
-      LJ = box.lj;
-      jplane = box.plane;
+      const int cz = ND > 2 ? ci[2] - box.z0 : 0;
+      const int lidx = (cx + 2) + (ND > 1 ? (cy + 2) * box.pitch : 0) +
+                       (ND > 2 ? (cz + 2) * box.slab : 0);
       k.lds = box.lds;
-      k.lbase = (int)base;
+      k.lbase = lidx;
       k.lsy = box.pitch;
+      k.lsz = box.slab;
       k.lplane = box.plane;
-    } else {
-      base = k.gbase;
-      sy = g.sy;
-      f = fg;
-      LJ = l.J(0);
-      jplane = l.plane;
-      k.lds = nullptr;
-      k.lbase = k.lsy = k.lplane = 0;
+      if constexpr (ND < 3) {
+        f = Planes<Real>{box.f, box.plane};
+        LJ = box.lj;
+        jplane = box.plane;
+        wh = Where3{lidx, box.pitch, box.slab};
+      }
     }
 
     // ---- forward recomputation
     Real G1[3], B1[3], G2[3] = {0, 0, 0}, B2[3] = {0, 0, 0};
-    gather_values<Real, ND>(f, base, sy, x1, G1, B1);
-    if (TWO) gather_values<Real, ND>(f, base, sy, x2, G2, B2);
+    gather_values<Real, ND>(f, wh, x1, G1, B1);
+    if (TWO) gather_values<Real, ND>(f, wh, x2, G2, B2);
     Real E1[3], E2[3] = {0, 0, 0}, um1[3], um2[3] = {0, 0, 0};
     Real r2 = 0, rq = 1, soft = 1, kf = 0;
     if (TWO) {
@@ -718,8 +775,8 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const Planes<Real
     Real l_v1[3] = {0, 0, 0}, l_v2[3] = {0, 0, 0};
     if (c.deposit) {
       const Real Q1 = st.w ? c.q1 * W : c.qw1;
-      Real g0[2], g1[2], gv[3];
-      if (deposit_adjoint<Real, ND>(LJ, jplane, base, sy, x1, y1, Q1, v1, c, g0, g1, gv)) {
+      Real g0[3], g1[3], gv[3];
+      if (deposit_adjoint<Real, ND>(LJ, jplane, wh, x1, y1, Q1, v1, c, g0, g1, gv)) {
 #pragma unroll
         for (int d = 0; d < ND; d++) {
           l_offn[d] += g1[d];
@@ -734,7 +791,7 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const Planes<Real
       }
       if (TWO) {
         const Real Q2 = st.w ? c.q2 * W : c.qw2;
-        if (deposit_adjoint<Real, ND>(LJ, jplane, base, sy, x2, y2, Q2, v2, c, g0, g1, gv)) {
+        if (deposit_adjoint<Real, ND>(LJ, jplane, wh, x2, y2, Q2, v2, c, g0, g1, gv)) {
 #pragma unroll
           for (int d = 0; d < ND; d++) {
             l_offn[d] += g1[d];
@@ -828,18 +885,18 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const Planes<Real
       }
     }
     // gather
-    Real lx1[2] = {0, 0}, lx2[2] = {0, 0};
+    Real lx1[3] = {0, 0, 0}, lx2[3] = {0, 0, 0};
     const Stencil<Real> t1 = stencil_at<Real, ND>(x1);
     if (TWO) {
       const Stencil<Real> t2 = stencil_at<Real, ND>(x2);
       if (same_nodes<Real, ND>(t1, t2)) {
-        gather_adjoint2<Real, ND>(f, k, base, sy, t1, l_E1, l_B1, t2, l_E2, l_B2, lx1, lx2);
+        gather_adjoint<Real, ND, true>(f, k, wh, t1, l_E1, l_B1, t2, l_E2, l_B2, lx1, lx2);
       } else {
-        gather_adjoint<Real, ND>(f, k, base, sy, t1, l_E1, l_B1, lx1);
-        gather_adjoint<Real, ND>(f, k, base, sy, t2, l_E2, l_B2, lx2);
+        gather_adjoint<Real, ND, false>(f, k, wh, t1, l_E1, l_B1, t1, l_E1, l_B1, lx1, lx1);
+        gather_adjoint<Real, ND, false>(f, k, wh, t2, l_E2, l_B2, t2, l_E2, l_B2, lx2, lx2);
       }
     } else {
-      gather_adjoint<Real, ND>(f, k, base, sy, t1, l_E1, l_B1, lx1);
+      gather_adjoint<Real, ND, false>(f, k, wh, t1, l_E1, l_B1, t1, l_E1, l_B1, lx1, lx1);
     }
 #pragma unroll
     for (int d = 0; d < ND; d++) {
@@ -900,24 +957,29 @@ __global__ void __launch_bounds__(256)
   TileBox<Real> box;
   box.tx = tt.T[0];
   box.ty = ND > 1 ? tt.T[1] : 1;
+  box.tz = ND > 2 ? tt.T[2] : 1;
   box.x0 = (t % tt.nt[0]) * tt.T[0];
-  box.y0 = ND > 1 ? (t / tt.nt[0]) * tt.T[1] : 0;
+  box.y0 = ND > 1 ? ((t / tt.nt[0]) % tt.nt[1]) * tt.T[1] : 0;
+  box.z0 = ND > 2 ? (t / (tt.nt[0] * tt.nt[1])) * tt.T[2] : 0;
   box.pitch = box.tx + 5;
-  box.plane = box.pitch * (ND > 1 ? box.ty + 5 : 1);
+  box.slab = box.pitch * (ND > 1 ? box.ty + 5 : 1);
+  box.plane = box.slab * (ND > 2 ? box.tz + 5 : 1);
   box.lds = patch;
   box.f = reinterpret_cast<Real*>(patch + 6 * box.plane);
   box.lj = box.f + 6 * box.plane;
-  // zero the accumulator; stage E, B and the adjoint current of the tile's
-  // reach (nodes beyond the guard layers, reachable only past a partial
-  // last tile, read as zero)
+  // zero the accumulator; in 1D and 2D stage E, B and the adjoint current of
+  // the tile's reach (nodes beyond the guard layers, reachable only past a
+  // partial last tile, read as zero)
   for (int q = threadIdx.x; q < 6 * box.plane; q += blockDim.x) {
     patch[q] = 0.0;
-    const int comp = q / box.plane, r = q % box.plane;
-    const int gx = box.x0 - 2 + r % box.pitch, gy = box.y0 - 2 + r / box.pitch;
-    const bool in = gx < g.n[0] + kGuard && (ND == 1 || gy < g.n[1] + kGuard);
-    const int64_t o = g.origin + gx + (ND > 1 ? (int64_t)gy * g.sy : 0);
-    box.f[q] = in ? f.base[comp * f.plane + o] : Real(0);
-    if (comp < 3) box.lj[q] = in ? l.J(comp)[o] : Real(0);
+    if constexpr (ND < 3) {
+      const int comp = q / box.plane, r = q % box.plane;
+      const int gx = box.x0 - 2 + r % box.pitch, gy = box.y0 - 2 + r / box.pitch;
+      const bool in = gx < g.n[0] + kGuard && (ND == 1 || gy < g.n[1] + kGuard);
+      const int64_t o = g.origin + gx + (ND > 1 ? (int64_t)gy * g.sy : 0);
+      box.f[q] = in ? f.base[comp * f.plane + o] : Real(0);
+      if (comp < 3) box.lj[q] = in ? l.J(comp)[o] : Real(0);
+    }
   }
   __syncthreads();
   double d_wc = 0.0, d_nu = 0.0;
@@ -931,23 +993,27 @@ __global__ void __launch_bounds__(256)
     const uint32_t pk = in.cell;
     const int cx = (int)(pk & ((1u << g.bits[0]) - 1u)) - box.x0;
     const int cy = ND > 1 ? (int)((pk >> g.bits[0]) & ((1u << g.bits[1]) - 1u)) - box.y0 : 0;
-    if (cx >= 0 && cx < box.tx && cy >= 0 && cy < box.ty)
+    const int cz = ND > 2 ? (int)(pk >> (g.bits[0] + g.bits[1])) - box.z0 : 0;
+    if (cx >= 0 && cx < box.tx && cy >= 0 && cy < box.ty && cz >= 0 && cz < box.tz)
       adjoint_one<Real, ND, TWO, true>(g, f, st, c, lp, l, p, in, box, d_wc, d_nu);
     else
       adjoint_one<Real, ND, TWO, false>(g, f, st, c, lp, l, p, in, box, d_wc, d_nu);
     in = nx;
   }
   __syncthreads();
-  // flush: patch node (px, py) is global node (x0 - 2 + px, y0 - 2 + py)
+  // flush: patch node (px, py, pz) is global node (x0 - 2 + px, ...)
   for (int q = threadIdx.x; q < 6 * box.plane; q += blockDim.x) {
     const double v = patch[q];
     if (v == 0.0) continue;
     const int comp = q / box.plane, r = q % box.plane;
-    const int px = r % box.pitch, py = r / box.pitch;
-    const int gx = box.x0 - 2 + px, gy = box.y0 - 2 + py;
+    const int px = r % box.pitch, py = (r / box.pitch) % (box.slab / box.pitch);
+    const int pz = r / box.slab;
+    const int gx = box.x0 - 2 + px, gy = box.y0 - 2 + py, gz = box.z0 - 2 + pz;
     if (gx < -kGuard || gx >= g.n[0] + kGuard) continue;
     if (ND > 1 && (gy < -kGuard || gy >= g.n[1] + kGuard)) continue;
-    const int64_t o = g.origin + (box.x0 - 2 + px) + (ND > 1 ? (int64_t)(box.y0 - 2 + py) * g.sy : 0);
+    if (ND > 2 && (gz < -kGuard || gz >= g.n[2] + kGuard)) continue;
+    const int64_t o = g.origin + gx + (ND > 1 ? (int64_t)gy * g.sy : 0) +
+                      (ND > 2 ? (int64_t)gz * g.sz : 0);
     Real* F = l.base + comp * l.plane;
     unsafeAtomicAdd(F + o, (Real)v);
   }
@@ -971,30 +1037,51 @@ void launch_adjoint_push(const GridInfo& g, const Real* fields, const AdjState<R
   const Planes<Real> l{lam, g.plane};
   const bool two = c.two_body != 0;
   if (tile_off) {
-    const int ntile = tt.nt[0] * (g.nd > 1 ? tt.nt[1] : 1);
-    // FP64 accumulator (6 planes) + fields (6) + adjoint current (3)
-    const size_t plane = (size_t)(tt.T[0] + 5) * (size_t)(g.nd > 1 ? tt.T[1] + 5 : 1);
-    const size_t lds = plane * (6 * sizeof(double) + 9 * sizeof(Real));
+    const size_t ntile = adjoint_tiles(g, tt);
+    const size_t lds = adjoint_lds_bytes(g, tt, sizeof(Real));
     dim3 grid((unsigned)ntile);
-#define PIC_ADJ_TILED(ND_, TWO_)                                                                 \
-    hipLaunchKernelGGL((k_adjoint_tiled<Real, ND_, TWO_>), grid, 256, lds, stream, g, f, st, c, lp, \
-                       l, dparam, tile_off, tt)
-    if (g.nd == 1 && two) PIC_ADJ_TILED(1, true);
-    if (g.nd == 1 && !two) PIC_ADJ_TILED(1, false);
-    if (g.nd == 2 && two) PIC_ADJ_TILED(2, true);
-    if (g.nd == 2 && !two) PIC_ADJ_TILED(2, false);
+#define PIC_ADJ_TILED(ND_, TWO_)                                                               \
+    {                                                                                          \
+      const void* fn = (const void*)k_adjoint_tiled<Real, ND_, TWO_>;                          \
+      (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);     \
+      hipLaunchKernelGGL((k_adjoint_tiled<Real, ND_, TWO_>), grid, 256, lds, stream, g, f, st,  \
+                         c, lp, l, dparam, tile_off, tt);                                      \
+    }
+    if (g.nd == 1 && two) PIC_ADJ_TILED(1, true)
+    if (g.nd == 1 && !two) PIC_ADJ_TILED(1, false)
+    if (g.nd == 2 && two) PIC_ADJ_TILED(2, true)
+    if (g.nd == 2 && !two) PIC_ADJ_TILED(2, false)
+    if (g.nd == 3 && two) PIC_ADJ_TILED(3, true)
+    if (g.nd == 3 && !two) PIC_ADJ_TILED(3, false)
 #undef PIC_ADJ_TILED
     return;
   }
   dim3 grid((unsigned)((st.n + 255) / 256));
-  if (g.nd == 1 && two)
-    hipLaunchKernelGGL((k_adjoint_push<Real, 1, true>), grid, 256, 0, stream, g, f, st, c, lp, l, dparam);
-  if (g.nd == 1 && !two)
-    hipLaunchKernelGGL((k_adjoint_push<Real, 1, false>), grid, 256, 0, stream, g, f, st, c, lp, l, dparam);
-  if (g.nd == 2 && two)
-    hipLaunchKernelGGL((k_adjoint_push<Real, 2, true>), grid, 256, 0, stream, g, f, st, c, lp, l, dparam);
-  if (g.nd == 2 && !two)
-    hipLaunchKernelGGL((k_adjoint_push<Real, 2, false>), grid, 256, 0, stream, g, f, st, c, lp, l, dparam);
+#define PIC_ADJ_GLOBAL(ND_, TWO_)                                                              \
+  hipLaunchKernelGGL((k_adjoint_push<Real, ND_, TWO_>), grid, 256, 0, stream, g, f, st, c, lp, l, \
+                     dparam)
+  if (g.nd == 1 && two) PIC_ADJ_GLOBAL(1, true);
+  if (g.nd == 1 && !two) PIC_ADJ_GLOBAL(1, false);
+  if (g.nd == 2 && two) PIC_ADJ_GLOBAL(2, true);
+  if (g.nd == 2 && !two) PIC_ADJ_GLOBAL(2, false);
+  if (g.nd == 3 && two) PIC_ADJ_GLOBAL(3, true);
+  if (g.nd == 3 && !two) PIC_ADJ_GLOBAL(3, false);
+#undef PIC_ADJ_GLOBAL
+}
+
+size_t adjoint_tiles(const GridInfo& g, const AdjTiles& tt) {
+  size_t n = 1;
+  for (int d = 0; d < g.nd; d++) n *= (size_t)tt.nt[d];
+  return n;
+}
+
+size_t adjoint_lds_bytes(const GridInfo& g, const AdjTiles& tt, size_t rsize) {
+  // patch nodes: the tile plus 2 nodes below and 3 above per resolved axis
+  size_t nodes = 1;
+  for (int d = 0; d < g.nd; d++) nodes *= (size_t)tt.T[d] + 5;
+  // FP64 accumulator (6 planes); in 1D and 2D also E, B (6) and the adjoint
+  // current (3) in the working precision
+  return nodes * (6 * sizeof(double) + (g.nd < 3 ? 9 * rsize : 0));
 }
 
 template void launch_adjoint_push<float>(const GridInfo&, const float*, const AdjState<float>&,

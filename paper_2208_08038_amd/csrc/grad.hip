@@ -272,7 +272,6 @@ pic::FieldPtrs<Real> planes(void* base, int64_t plane) {
 }
 
 int check_grad_ok(pic_ctx* c) {
-  if (c->g.nd > 2) return fail(c, PIC_EINVAL, "gradient runs support 1D and 2D grids");
   if (c->cfg.flags & (PIC_FLAG_FROZEN_FIELDS | PIC_FLAG_NO_DEPOSIT))
     return fail(c, PIC_EINVAL, "gradient runs need the coupled step (no frozen fields, deposit on)");
   if (c->sp.size() > 64) return fail(c, PIC_EINVAL, "gradient runs support at most 64 species");
@@ -409,8 +408,14 @@ int grad_backward_t(pic_ctx* c, const double* dprobe, pic_grad* out) {
         const SpeciesHost& s = *c->sp[si];
         if (s.n == 0) continue;
         const bool timed = record_event(c, PIC_TIMING_ADJOINT + (int)si, true);
-        pic::AdjTiles tt{{c->tile[0], c->tile[1]}, {c->ntiles[0], c->ntiles[1]}};
-        const uint32_t* toff = c->tiled ? s.sort.tile_off : nullptr;
+        pic::AdjTiles tt{{c->tile[0], c->tile[1], c->tile[2]},
+                         {c->ntiles[0], c->ntiles[1], c->ntiles[2]}};
+        // one workgroup per tile when its LDS patch fits, else one thread
+        // per particle with global atomics
+        constexpr size_t kMaxAdjointLds = 160 * 1024;
+        const bool tiled =
+            c->tiled && pic::adjoint_lds_bytes(g, tt, sizeof(Real)) <= kMaxAdjointLds;
+        const uint32_t* toff = tiled ? s.sort.tile_off : nullptr;
         pic::launch_adjoint_push<Real>(g, fslot, snap_state<Real>(c, slot, si),
                                        push_const<Real>(c, s), lam_state<Real>(c, si),
                                        static_cast<Real*>(G.lam_fields), G.dgrad + 2 * si, toff,

@@ -244,25 +244,32 @@ def adjoint_slab(ndim: int = 2, cells=(2048, 1024), slab=(64, 448), probe_x: int
                  a0: float = 1e-4, waist_frac: float = 0.3, dx_per_lambda: int = 32,
                  config_id: int = 5) -> Workload:
     """Gradient-run case: a neutral bound-electron slab (cold two-body gold
-    ions, Z_b = 78, ppc per cell over x cells slab[0]..slab[1] and every y)
-    crossed by a pulse from x-min whose temporal envelope is a cubic
+    ions, Z_b = 78, ppc per cell over x cells slab[0]..slab[1] and every y,
+    z) crossed by a pulse from x-min whose temporal envelope is a cubic
     B-spline series of n_env coefficients over `cycles` laser periods
-    (initial coefficients: sin^2 sampled at the basis centres); y periodic,
-    a wide Gaussian profile (waist = waist_frac * L_y; plane wave in 1D).
-    Probes on the plane x = probe_x behind the slab: E_y at (probe_x, j)
-    and B_z at (probe_x - 1, j), (probe_x, j) for every j, in that order
-    (the transmitted Poynting flux and phase)."""
+    (initial coefficients: sin^2 sampled at the basis centres); y (and z)
+    periodic, a wide Gaussian profile (waist = waist_frac * L_y; plane wave
+    in 1D).  Probes on the plane x = probe_x behind the slab: E_y at
+    (probe_x, j, k), then B_z at (probe_x - 1, j, k), then B_z at
+    (probe_x, j, k), each over every (j, k) with j fastest (the transmitted
+    Poynting flux and phase)."""
     dx = TWO_PI / float(dx_per_lambda)
     dt = 0.98 * dx / math.sqrt(float(ndim))
     nx = int(cells[0])
     ny = int(cells[1]) if ndim > 1 else 1
+    nz = int(cells[2]) if ndim > 2 else 1
     t_env = cycles * TWO_PI
     h = t_env / (n_env + 3)
     env = tuple(math.sin(math.pi * (k + 2) * h / t_env) ** 2 for k in range(n_env))
     Ly = ny * dx
     laser = Laser(a0=a0, omega=1.0, t_env=t_env, pol=1, env=env,
-                  waist=waist_frac * Ly if ndim > 1 else 0.0, yc=0.5 * Ly if ndim > 1 else 0.0)
-    if ndim == 1:
+                  waist=waist_frac * Ly if ndim > 1 else 0.0, yc=0.5 * Ly if ndim > 1 else 0.0,
+                  zc=0.5 * nz * dx if ndim > 2 else 0.0)
+    if ndim == 3:
+        grid = Grid(3, (nx, ny, nz), (dx, dx, dx), dt, (LASER, PERIODIC, PERIODIC),
+                    (OPEN, PERIODIC, PERIODIC), pad=3, laser=laser,
+                    re_norm=TWO_PI * R_E_M / 12.4e-9)
+    elif ndim == 1:
         grid = Grid(1, (nx, 1, 1), (dx, 1.0, 1.0), dt, (LASER, PERIODIC, PERIODIC),
                     (OPEN, PERIODIC, PERIODIC), pad=3, laser=laser,
                     re_norm=TWO_PI * R_E_M / 12.4e-9)
@@ -275,13 +282,14 @@ def adjoint_slab(ndim: int = 2, cells=(2048, 1024), slab=(64, 448), probe_x: int
     cell_vol = dx ** ndim
     sp = Species(TWO_BODY, q1, m1, q2, m2, weight=n_ion * cell_vol / ppc, omega_c=omega_c,
                  a_c=a_c, nu=nu, name="Au_Zb78_cold")
-    lo = [slab[0]] + ([0] if ndim > 1 else [])
-    hi = [min(slab[1], nx - grid.pad)] + ([ny] if ndim > 1 else [])
+    lo = [slab[0]] + [0] * (ndim - 1)
+    hi = [min(slab[1], nx - grid.pad)] + [ny, nz][:ndim - 1]
     x = stratified_positions(rng_for(config_id), lo, hi, ppc, grid.dx, ndim)
     parts = Particles(x=x, u1=np.zeros((x.shape[0], 3)))
-    probes = ([(1, (probe_x, j, 0)) for j in range(ny)] +
-              [(5, (probe_x - 1, j, 0)) for j in range(ny)] +
-              [(5, (probe_x, j, 0)) for j in range(ny)])
+    plane = [(j, k) for k in range(nz) for j in range(ny)]
+    probes = ([(1, (probe_x, j, k)) for j, k in plane] +
+              [(5, (probe_x - 1, j, k)) for j, k in plane] +
+              [(5, (probe_x, j, k)) for j, k in plane])
     return Workload("adjoint_slab", grid, [(sp, parts)], steps, 64, probes=probes,
                     notes=f"slab {slab}, probe plane x={probe_x}, omega_c={omega_c}, nu={nu}")
 

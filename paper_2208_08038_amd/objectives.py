@@ -1,7 +1,7 @@
 """Objective of the gradient run: the pulse transmitted through the probe
 plane behind the medium, from the probe series of `inputs.adjoint_slab`
-(rows: E_y(x_p, j), B_z(x_p - 1, j), B_z(x_p, j) for j = 0..n_y-1; one
-column per step).
+(rows: E_y(x_p, j), B_z(x_p - 1, j), B_z(x_p, j) over the ny points j of the
+plane (ny = n_y n_z in 3D, dy the area of one point); one column per step).
 
     L = E_T / E_ref + phi_T
     E_T   = sum_n sum_j E_y B_z dt dy     (Poynting flux through the plane,

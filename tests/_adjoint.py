@@ -15,11 +15,17 @@ def small_case(ndim, steps=None, a0=1e-4, nu=0.03, omega_c=3.0, a_c=math.inf, pp
                thermal=0.0, seed=7):
     """1D: 128 cells of lambda/16, slab 16..64, probe plane 80, 3-cycle
     envelope of 8 coefficients, 210 steps.  2D: 96 x 16 cells, slab 16..48,
-    probe plane 56, 2-cycle envelope, 150 steps.  `thermal` adds Gaussian
+    probe plane 56, 2-cycle envelope, 150 steps.  3D: 40 x 8 x 8 cells,
+    slab 8..24, probe plane 30, 1.5-cycle envelope of 6 coefficients, one
+    ion per cell (ppc / 4), 120 steps.  `thermal` adds Gaussian
     momenta of that spread to both bodies (independently)."""
     if ndim == 1:
         wl = adjoint_slab(1, (128, 1), (16, 64), 80, ppc=ppc, steps=steps or 210,
                           omega_c=omega_c, nu=nu, a_c=a_c, n_env=8, cycles=3.0, a0=a0,
+                          dx_per_lambda=16)
+    elif ndim == 3:
+        wl = adjoint_slab(3, (40, 8, 8), (8, 24), 30, ppc=max(ppc // 4, 1), steps=steps or 120,
+                          omega_c=omega_c, nu=nu, a_c=a_c, n_env=6, cycles=1.5, a0=a0,
                           dx_per_lambda=16)
     else:
         wl = adjoint_slab(2, (96, 16), (16, 48), 56, ppc=ppc, steps=steps or 150,
@@ -104,8 +110,12 @@ def richardson_fd(series_fn, loss_fn, make, x0, h):
 
 
 def vacuum_grid(ndim, laser=None):
-    """Open x faces (x-min injects `laser`), periodic y; lambda/16 cells."""
+    """Open x faces (x-min injects `laser`), periodic y (and z); lambda/16 cells."""
     dx = TWO_PI / 16.0
+    if ndim == 3:
+        return Grid(3, (24, 8, 8), (dx, dx, dx), 0.98 * dx / math.sqrt(3.0),
+                    (LASER, PERIODIC, PERIODIC), (OPEN, PERIODIC, PERIODIC), pad=3,
+                    laser=laser or Laser())
     if ndim == 1:
         return Grid(1, (64, 1, 1), (dx, 1.0, 1.0), 0.98 * dx, (LASER, PERIODIC, PERIODIC),
                     (OPEN, PERIODIC, PERIODIC), pad=3, laser=laser or Laser())
