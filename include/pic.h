@@ -293,8 +293,10 @@ typedef struct {
 } pic_grad;
 int pic_grad_forward(pic_ctx* ctx, int32_t nsteps, int32_t checkpoint_every);
 int pic_grad_backward(pic_ctx* ctx, const double* dprobe, pic_grad* out);
-/* After pic_grad_backward: dL/d(initial particle state) of one species in
-   storage order (as pic_read_particles at the start of the run): d_x
+/* After pic_grad_backward: dL/d(particle state at the start of the run)
+   of one species, in the storage order of the run (the order
+   pic_read_particles reports after pic_grad_forward; no sort runs during
+   the run, but a sort pending from a load runs at its start): d_x
    (n x ndim, d/d position), d_delta, d_u1, d_u2 (n x 3; two-body only for
    delta and u2).  HOST FP64; NULL outputs are skipped. */
 int pic_read_grad_particles(pic_ctx* ctx, int32_t species_id, double* d_x, double* d_delta,

@@ -409,7 +409,8 @@ class Simulation:
         return out
 
     def grad_particles(self, sid: int) -> dict:
-        """dL/d(state at the start of the run) of one species, storage order."""
+        """dL/d(state at the start of the run) of one species, in the run's
+        storage order (that of particles(sid) after grad_forward)."""
         n = self.count(sid)
         two = self.species[sid].kind == 1  # two-body
         out = {"x": np.zeros((n, self.ndim)), "u1": np.zeros((n, 3))}

@@ -164,8 +164,8 @@ def test_particle_state_gradient_matches_finite_differences(pic, ndim):
     wl = A.with_particles(wl, delta=parts.delta)
     sim = pic.Simulation.from_workload(wl, precision=64, flags=pic.TRACK_IDS,
                                        max_probe_steps=wl.steps)
-    ids = sim.particles(0, ids=True)["id"]
     sim.grad_forward(wl.steps, 40)
+    ids = sim.particles(0, ids=True)["id"]  # the run's storage order
     y = sim.probes()
     w = rng.normal(size=y.shape)
     sim.grad_backward(w)
