@@ -6,10 +6,10 @@ omega_c ~ U[1.5, 4] omega_L per ion, friction 0.01 omega_c) and 8 free
 electrons (10 eV) per cell filling the box between the particle walls,
 Gaussian laser (w0 = 8 lambda, a0 = 0.05) entering at x-min, FP32 state
 and arithmetic (FP64 diagnostics).  Inputs are seeded synthetic arrays
-generated directly in HBM (particles enumerated stratum by stratum: every
-cell's first particle, then every cell's second, ...; the library's stable
-tile sort keeps that order within each tile, so the lanes of a wavefront
-touch distinct cells); they are resident before timing starts.
+generated directly in HBM (particles enumerated cell by cell; the library's
+sort after each load orders every tile by rank within cell, so the lanes
+of a wavefront touch distinct cells); they are resident before timing
+starts.
 
 A step is one pass of the whole hot path: tile sort (on its cadence),
 particle cycle of both species (gather, bond force, Boris, move,

@@ -333,8 +333,9 @@ void deposit_rho(pic_ctx* c, double* rho) {
 // their tile since its last sort reach kSortRatio of the species (the
 // outside-tile kernel costs about 1 / kSortRatio as much per particle as a
 // sort does; the rule spends on sorting what the detour cost, so stays
-// within twice the best cadence), or after kSortMaxSteps steps (keeps the
-// order of particles within tiles close to the interleaved load order).
+// within twice the best cadence), or after kSortMaxSteps steps.  The sort
+// after a load also orders each tile by rank within cell; later sorts are
+// stable and keep that order for the particles that stayed.
 int sort_due(pic_ctx* c) {
   constexpr double kSortRatio = 1.0 / 200.0;
   constexpr int64_t kSortMaxSteps = 64;
@@ -346,7 +347,9 @@ int sort_due(pic_ctx* c) {
       due = due || s->listed_since_sort >= kSortRatio * (double)s->n ||
             s->steps_since_sort >= kSortMaxSteps;
     if (!due) continue;
-    int rc = pic::sort_by_tile(c->g, c->tile, c->ntiles, s->sort, s->n, c->stream);
+    // the first sort after a host load also rebuilds the order within tiles
+    int rc = pic::sort_by_tile(c->g, c->tile, c->ntiles, s->sort, s->n, c->stream,
+                               s->needs_sort);
     if (rc) return fail(c, PIC_EHIP, "tile sort launch failed");
     s->needs_sort = false;
     s->listed_since_sort = 0.0;
@@ -916,7 +919,7 @@ int pic_load_particles_device(pic_ctx* c, int32_t sid, int64_t n, const double* 
   if (bad & PIC_ERR_NAN) return fail(c, PIC_ENAN, "non-finite particle state");
   if (bad & PIC_ERR_RANGE) return fail(c, PIC_ERANGE, "particle outside the grid, walls or bond range");
   s.n += n;
-  if (pic::sort_by_tile(c->g, c->tile, c->ntiles, s.sort, s.n, c->stream))
+  if (pic::sort_by_tile(c->g, c->tile, c->ntiles, s.sort, s.n, c->stream, true))
     return fail(c, PIC_EHIP, "tile sort failed");
   s.needs_sort = false;
   HIPCHK(c, hipStreamSynchronize(c->stream));

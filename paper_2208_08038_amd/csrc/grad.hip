@@ -286,7 +286,7 @@ int grad_forward_t(pic_ctx* c, int64_t nsteps, int K) {
   // one sort now (after a load), none during the run
   for (auto& s : c->sp)
     if (s->needs_sort) {
-      if (pic::sort_by_tile(c->g, c->tile, c->ntiles, s->sort, s->n, c->stream))
+      if (pic::sort_by_tile(c->g, c->tile, c->ntiles, s->sort, s->n, c->stream, true))
         return fail(c, PIC_EHIP, "tile sort launch failed");
       s->needs_sort = false;
       s->listed_since_sort = 0.0;

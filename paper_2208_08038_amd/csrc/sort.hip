@@ -1,4 +1,4 @@
-// sort.hip -- stable LSD radix sort of particles by tile id.
+// sort.hip -- stable LSD radix sorts of particles by tile id.
 //
 // Digits of up to 9 bits (a key of b bits takes ceil(b / 9) passes, the
 // digit width spread evenly over them: 17-bit tile ids of a 512x256x256
@@ -29,6 +29,53 @@ __global__ void k_keys(GridInfo g, int tx, int ty, int tz, int ntx, int nty, con
   uint32_t j = g.nd > 1 ? (v >> g.bits[0]) & ((1u << g.bits[1]) - 1u) : 0u;
   uint32_t k = g.nd > 2 ? v >> (g.bits[0] + g.bits[1]) : 0u;
   key[p] = i / tx + (uint32_t)ntx * (j / ty + (uint32_t)nty * (k / tz));
+}
+
+// Key of the ordering sort after a load: tile id times the cells of a tile
+// plus the cell's index within its tile (x fastest).
+__global__ void k_cell_keys(GridInfo g, int tx, int ty, int tz, int ntx, int nty,
+                            const uint32_t* cell, int64_t n, uint32_t* key) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  uint32_t v = cell[p];
+  uint32_t i = v & ((1u << g.bits[0]) - 1u);
+  uint32_t j = g.nd > 1 ? (v >> g.bits[0]) & ((1u << g.bits[1]) - 1u) : 0u;
+  uint32_t k = g.nd > 2 ? v >> (g.bits[0] + g.bits[1]) : 0u;
+  uint32_t tile = i / tx + (uint32_t)ntx * (j / ty + (uint32_t)nty * (k / tz));
+  uint32_t local = i % tx + (uint32_t)tx * (j % ty + (uint32_t)ty * (k % tz));
+  key[p] = tile * (uint32_t)(tx * ty * tz) + local;
+}
+
+// Over keys sorted by (tile, cell): the rank of element i among the equal
+// keys before it (its rank within the cell, in the previous order), found
+// by a doubling search back to the start of the run and a bisection, then
+// the key (tile, rank) with the rank clamped to rmax.
+__global__ void k_rank_keys(const uint32_t* __restrict__ ck, int64_t n, uint32_t cpt, int rbits,
+                            uint32_t* __restrict__ rk) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t K = ck[i];
+  int64_t hi = i, lo = -1;  // ck[hi] == K; lo < 0 or ck[lo] < K
+  for (int64_t d = 1;; d <<= 1) {
+    const int64_t q = i - d;
+    if (q < 0) break;
+    if (ck[q] != K) {
+      lo = q;
+      break;
+    }
+    hi = q;
+  }
+  while (hi - lo > 1) {
+    const int64_t m = lo + (hi - lo) / 2;
+    if (ck[m] == K)
+      hi = m;
+    else
+      lo = m;
+  }
+  const uint32_t rmax = (1u << rbits) - 1u;
+  const int64_t r = i - hi;
+  const uint32_t rank = r < (int64_t)rmax ? (uint32_t)r : rmax;
+  rk[i] = ((K / cpt) << rbits) | rank;
 }
 
 __global__ void __launch_bounds__(SB) k_hist(const uint32_t* key, int64_t n, int shift,
@@ -137,11 +184,13 @@ __global__ void __launch_bounds__(SB) k_scatter(const uint32_t* kin, const uint3
   }
 }
 
-__global__ void k_tile_off(const uint32_t* key, int64_t n, int64_t ntiles, uint32_t* off) {
+// Offsets of the tiles in the sorted order; the tile id is key >> tshift.
+__global__ void k_tile_off(const uint32_t* key, int64_t n, int64_t ntiles, int tshift,
+                           uint32_t* off) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i > n) return;
-  int64_t lo = i == 0 ? -1 : min((int64_t)key[i - 1], ntiles);
-  int64_t hi = i == n ? ntiles : min((int64_t)key[i], ntiles);
+  int64_t lo = i == 0 ? -1 : min((int64_t)(key[i - 1] >> tshift), ntiles);
+  int64_t hi = i == n ? ntiles : min((int64_t)(key[i] >> tshift), ntiles);
   for (int64_t t = lo + 1; t <= hi; t++) off[t] = (uint32_t)i;
 }
 
@@ -215,32 +264,60 @@ int sort_add_attr(SortBuffers& sb, void** ptr, size_t elem, const AllocFn& alloc
   return 0;
 }
 
-int sort_by_tile(const GridInfo& g, const int tile[3], const int ntiles[3], SortBuffers& sb,
-                 int64_t n, hipStream_t st) {
-  if (n <= 0) return 0;
-  uint32_t* cell = static_cast<uint32_t*>(*sb.attr[0]);
-  hipLaunchKernelGGL(k_keys, nblk(n, 256), 256, 0, st, g, tile[0], tile[1], tile[2], ntiles[0],
-                     ntiles[1], cell, n, sb.key[0]);
-  int bits = 0;
-  while ((int64_t(1) << bits) < sb.ntiles) bits++;
+// Stable LSD radix sort of the n keys in sb.key[kc] (bits wide) carrying
+// the indices in sb.idx[ic] (identity when ic < 0); kc and ic name the
+// buffers that hold the result on return.
+static void radix_sort(SortBuffers& sb, int64_t n, int bits, int& kc, int& ic, hipStream_t st) {
   const int passes = (bits + MAXBITS - 1) / MAXBITS;
   const int dbits = passes ? (bits + passes - 1) / passes : 0;
-  int nb = (int)((n + CHUNK - 1) / CHUNK);
-  int cur = 0;
-  const uint32_t* idx_in = nullptr;
+  const int nb = (int)((n + CHUNK - 1) / CHUNK);
   for (int p = 0; p < passes; p++) {
-    int shift = dbits * p;
-    hipLaunchKernelGGL(k_hist, dim3(nb), SB, 0, st, sb.key[cur], n, shift, dbits, sb.hist, nb);
+    const int shift = dbits * p;
+    const int ko = 1 - kc, io = ic < 0 ? 0 : 1 - ic;
+    hipLaunchKernelGGL(k_hist, dim3(nb), SB, 0, st, sb.key[kc], n, shift, dbits, sb.hist, nb);
     scan_exclusive(sb.hist, ((int64_t)1 << dbits) * nb, sb.scan_tmp, st);
-    hipLaunchKernelGGL(k_scatter, dim3(nb), SB, 0, st, sb.key[cur], idx_in, sb.key[1 - cur],
-                       sb.idx[1 - cur], sb.hist, shift, dbits, n, nb);
-    idx_in = sb.idx[1 - cur];
-    cur = 1 - cur;
+    hipLaunchKernelGGL(k_scatter, dim3(nb), SB, 0, st, sb.key[kc], ic < 0 ? nullptr : sb.idx[ic],
+                       sb.key[ko], sb.idx[io], sb.hist, shift, dbits, n, nb);
+    kc = ko;
+    ic = io;
   }
-  hipLaunchKernelGGL(k_tile_off, nblk(n + 1, 256), 256, 0, st, sb.key[cur], n, sb.ntiles,
+}
+
+static int bits_for(uint64_t count) {
+  int b = 0;
+  while ((uint64_t(1) << b) < count) b++;
+  return b;
+}
+
+int sort_by_tile(const GridInfo& g, const int tile[3], const int ntiles[3], SortBuffers& sb,
+                 int64_t n, hipStream_t st, bool interleave) {
+  if (n <= 0) return 0;
+  uint32_t* cell = static_cast<uint32_t*>(*sb.attr[0]);
+  const uint64_t cpt = (uint64_t)tile[0] * tile[1] * tile[2];
+  const int tbits = bits_for((uint64_t)sb.ntiles);
+  const int rbits = 32 - tbits < 8 ? 32 - tbits : 8;
+  // the ordering sort needs (tile, cell) and (tile, rank) keys of 32 bits
+  interleave = interleave && cpt > 1 && rbits > 0 &&
+               (uint64_t)sb.ntiles * cpt <= (uint64_t)UINT32_MAX;
+  int kc = 0, ic = -1, tshift = 0;
+  if (interleave) {
+    hipLaunchKernelGGL(k_cell_keys, nblk(n, 256), 256, 0, st, g, tile[0], tile[1], tile[2],
+                       ntiles[0], ntiles[1], cell, n, sb.key[0]);
+    radix_sort(sb, n, bits_for((uint64_t)sb.ntiles * cpt), kc, ic, st);
+    hipLaunchKernelGGL(k_rank_keys, nblk(n, 256), 256, 0, st, sb.key[kc], n, (uint32_t)cpt, rbits,
+                       sb.key[1 - kc]);
+    kc = 1 - kc;
+    radix_sort(sb, n, tbits + rbits, kc, ic, st);
+    tshift = rbits;
+  } else {
+    hipLaunchKernelGGL(k_keys, nblk(n, 256), 256, 0, st, g, tile[0], tile[1], tile[2], ntiles[0],
+                       ntiles[1], cell, n, sb.key[0]);
+    radix_sort(sb, n, tbits, kc, ic, st);
+  }
+  hipLaunchKernelGGL(k_tile_off, nblk(n + 1, 256), 256, 0, st, sb.key[kc], n, sb.ntiles, tshift,
                      sb.tile_off);
-  if (passes == 0) return 0;  // a single tile: order unchanged
-  const uint32_t* perm = sb.idx[cur];
+  if (ic < 0) return hipGetLastError() == hipSuccess ? 0 : -1;  // a single tile: order unchanged
+  const uint32_t* perm = sb.idx[ic];
   GatherSet gs{};
   gs.n = sb.nattr;
   for (int a = 0; a < sb.nattr; a++) {

@@ -452,13 +452,12 @@ WORKLOADS = {
 def ionised_slab_3d_device_chunk(n=(512, 256, 256), ppc: int = 8, x_cells=(3, 35),
                                  chunk: int = 0, device="cuda", wc_range=(1.5, 4.0),
                                  t_ion_ev: float = 1.0, t_e_ev: float = 10.0,
-                                 interleave: bool = True, config_id: int = 3):
+                                 config_id: int = 3):
     """Same recipe as ionised_slab_3d for the x planes x_cells, drawn with
     torch's Philox generator on the GPU (seed = base seed + config id, offset
     by the chunk), returned as FP64 device tensors:
-    (x_ion, u_c_ion, omega_c_ion, x_e, u_e).  interleave=True enumerates the
-    particles stratum-major (every cell's first particle, then every cell's
-    second, ...) instead of cell-major.  Holds no method arithmetic."""
+    (x_ion, u_c_ion, omega_c_ion, x_e, u_e), particles enumerated cell by
+    cell (x fastest).  Holds no method arithmetic."""
     import torch
     dx = TWO_PI / 24.0
     q1, m1, q2, m2 = gold_ion(78, 1.0)
@@ -470,13 +469,8 @@ def ionised_slab_3d_device_chunk(n=(512, 256, 256), ppc: int = 8, x_cells=(3, 35
         nxc = x_cells[1] - x_cells[0]
         m = nxc * ny * nz * ppc
         p = torch.arange(m, device=device, dtype=torch.int64)
-        ncc = m // ppc
-        if interleave:
-            cell = p % ncc
-            sub = (p // ncc).to(torch.float64)
-        else:
-            cell = p // ppc
-            sub = (p % ppc).to(torch.float64)
+        cell = p // ppc
+        sub = (p % ppc).to(torch.float64)
         cx = (cell % nxc).to(torch.float64) + x_cells[0]
         rem = cell // nxc
         cy = (rem % ny).to(torch.float64)

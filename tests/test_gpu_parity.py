@@ -2,6 +2,7 @@
 identical seeded inputs.  Tolerances: integer state (cells, sort order)
 bit-exact; FP64 fields within relative L2 1e-12; FP32 fields within 2e-5.
 """
+import dataclasses
 import math
 import sys
 
@@ -207,6 +208,85 @@ def test_stable_tile_sort_permutation(pic, shape, tile, n):
     key = c[:, 0] // tile[0] + nt[0] * (c[:, 1] // tile[1] + nt[1] * (c[:, 2] // tile[2]))
     expect = before["id"][np.argsort(key, kind="stable")]
     assert np.array_equal(after["id"], expect)
+
+
+def _load_order(cells, prev_ids, tile, nt):
+    """Expected order after a load: by tile, then by the rank of the
+    particle within its cell in the previous order (clamped at 255), then
+    by the cell's index within the tile (x fastest), then stably."""
+    nd = cells.shape[1]
+    t = list(tile) + [1] * (3 - nd)
+    c = np.zeros((len(cells), 3), dtype=np.int64)
+    c[:, :nd] = cells
+    n_t = list(nt) + [1] * (3 - nd)
+    tid = c[:, 0] // t[0] + n_t[0] * (c[:, 1] // t[1] + n_t[1] * (c[:, 2] // t[2]))
+    local = c[:, 0] % t[0] + t[0] * (c[:, 1] % t[1] + t[1] * (c[:, 2] % t[2]))
+    ckey = tid * (t[0] * t[1] * t[2]) + local
+    order = np.argsort(ckey, kind="stable")
+    sk = ckey[order]
+    rank = np.empty(len(ckey), dtype=np.int64)
+    rank[order] = np.arange(len(sk)) - np.searchsorted(sk, sk, side="left")
+    rank = np.minimum(rank, 255)
+    return prev_ids[np.lexsort((np.arange(len(ckey)), local, rank, tid))]
+
+
+@pytest.mark.parametrize("ndim,shape,tile", [(3, (24, 16, 16), (8, 8, 6)),
+                                             (2, (48, 36), (12, 12)),
+                                             (1, (600,), (256,))])
+def test_load_order_within_tiles(pic, ndim, shape, tile):
+    """The first sort after a host load orders each tile by the particles'
+    rank within their cell (first particle of every cell, then every cell's
+    second, ...) and by cell within a rank, whatever the load order; 300
+    particles in one cell check the rank clamp at 255.  Later sorts keep
+    the order stable (test_stable_tile_sort_permutation)."""
+    _say(f"case: load order {ndim}d {shape} tile {tile}")
+    n = {3: 20000, 2: 15000, 1: 6000}[ndim]
+    wl = random_workload(ndim, n, 0, seed=67, shape=shape, vmax_ion=0.3)
+    sp, parts = wl.species[0]
+    x = np.array(parts.x, copy=True)
+    dx = np.array(wl.grid.dx[:ndim])
+    rng = np.random.default_rng(5)
+    c0 = np.array([s // 2 for s in shape], float)
+    x[:300] = (c0 + rng.uniform(0.2, 0.8, (300, ndim))) * dx
+    # cell-major clumps: the next 3000 particles sorted by cell
+    blk = x[300:3300]
+    x[300:3300] = blk[np.lexsort(tuple(np.floor(blk[:, d] / dx[d]) for d in range(ndim)))]
+    wl = dataclasses.replace(wl, species=[(sp, dataclasses.replace(parts, x=x))])
+    s = pic.Simulation.from_workload(wl, precision=64, flags=pic.TRACK_IDS, tile=tile)
+    before = s.particles(0, ids=True)   # host loader's tile order, before the device sort
+    s.step(1)                           # ordering sort, then the push
+    after = s.particles(0, ids=True)
+    nt = tuple(-(-shape[d] // tile[d]) for d in range(ndim))
+    assert np.array_equal(after["id"], _load_order(before["cell"], before["id"], tile, nt))
+    assert s.diagnostics()["error_word"] == 0
+    s.close()
+
+
+def test_load_order_device_loader(pic):
+    """Device loads sort at once into the same order (ranks counted in the
+    load order)."""
+    import torch
+    _say("case: load order device loader 3d")
+    shape, tile = (24, 16, 16), (8, 8, 6)
+    wl = random_workload(3, 30000, 0, seed=71, shape=shape, vmax_ion=0.3)
+    sp, parts = wl.species[0]
+    dx = np.array(wl.grid.dx)
+    x = np.array(parts.x, copy=True)
+    x = x[np.lexsort(tuple(np.floor(x[:, d] / dx[d]) for d in range(3)))]   # cell-major
+    s = pic.Simulation(wl.grid, precision=32, flags=pic.TRACK_IDS, tile=tile)
+    sid = s.add_species(sp, parts.n)
+    dev = torch.device("cuda", 0)
+    s.load_particles_device(sid, torch.tensor(x, device=dev), torch.tensor(parts.u1, device=dev),
+                            delta=torch.tensor(parts.delta, device=dev),
+                            u2=torch.tensor(parts.u2, device=dev),
+                            omega_c=torch.tensor(parts.omega_c, device=dev),
+                            weight=torch.tensor(parts.weight, device=dev))
+    after = s.particles(0, ids=True)
+    cells = np.empty_like(after["cell"])
+    cells[after["id"]] = after["cell"]       # cells in load order
+    nt = tuple(-(-shape[d] // tile[d]) for d in range(3))
+    assert np.array_equal(after["id"], _load_order(cells, np.arange(parts.n), tile, nt))
+    s.close()
 
 
 def test_bragg_case_fp64_fp32(pic):
