@@ -223,30 +223,39 @@ __device__ __forceinline__ bool window(Real x0, Real x1, Window<Real>& win) {
   return true;
 }
 
-// Add into the current (accumulator type JT, which may be wider than the
-// arithmetic type): LDS patches take every term, global planes skip exact
-// zeros (fewer atomics).  An integer JT is a 64-bit fixed-point LDS patch: v * scale rounded to an
-// integer (scale a power of two chosen by the host so that every term stays
-// below 2^46 in magnitude).  Integer adds are exact, so the patch sum does
-// not depend on the order of the atomics, and 64-bit integer LDS atomics
-// issue faster than FP64 ones on gfx950.
-__device__ __forceinline__ long long to_fixed(double v, double scale) {
-  // v * scale + 1.5 * 2^52 has a unit ulp: its low mantissa bits hold the
-  // rounded integer (valid for |v * scale| < 2^51)
-  const double magic = 6755399441055744.0;
-  const double d = __builtin_fma(v, scale, magic);
-  return __builtin_bit_cast(long long, d) - __builtin_bit_cast(long long, magic);
-}
-
+// Add into a floating-point current (accumulator type JT, which may be
+// wider than the arithmetic type): LDS patches take every term, global
+// planes skip exact zeros (fewer atomics).
 template <bool GLOBAL, typename JT, typename Real>
-__device__ __forceinline__ void jadd(JT* p, Real v, Real scale) {
-  if constexpr (std::is_integral<JT>::value) {
-    atomicAdd(reinterpret_cast<unsigned long long*>(p),
-              static_cast<unsigned long long>(to_fixed((double)v, (double)scale)));
-  } else if constexpr (GLOBAL) {
+__device__ __forceinline__ void jadd(JT* p, Real v) {
+  if constexpr (GLOBAL) {
     if (v != Real(0)) unsafeAtomicAdd(p, (JT)v);
   } else {
     unsafeAtomicAdd(p, (JT)v);
+  }
+}
+
+// Add g_a X_a (+ g_b X_b with PAIR) into *p.  An integer JT is a 64-bit
+// fixed-point LDS patch: the g carry the patch scale, a power of two the
+// host chooses so that every term stays below 2^46 in magnitude.  Each
+// product is formed exactly in FP64 inside an FMA whose running sum starts
+// at 1.5 * 2^52: that sum has a unit ulp, so every FMA rounds its term to
+// an integer (to nearest) and the low mantissa bits hold the integer sum
+// of the rounded terms (valid below 2^51).  Integer adds are exact, so the
+// patch sum does not depend on the order of the atomics, and 64-bit
+// integer LDS atomics issue faster than FP64 ones on gfx950.
+template <bool GLOBAL, bool PAIR, typename JT, typename Real>
+__device__ __forceinline__ void jadd_terms(JT* p, Real ga, Real xa, Real gb, Real xb) {
+  if constexpr (std::is_integral<JT>::value) {
+    const double magic = 6755399441055744.0;
+    double t = magic;
+    if constexpr (PAIR) t = __builtin_fma((double)gb, (double)xb, t);
+    t = __builtin_fma((double)ga, (double)xa, t);
+    atomicAdd(reinterpret_cast<unsigned long long*>(p),
+              static_cast<unsigned long long>(__builtin_bit_cast(long long, t) -
+                                              __builtin_bit_cast(long long, magic)));
+  } else {
+    jadd<GLOBAL>(p, PAIR ? ga * xa + gb * xb : ga * xa);
   }
 }
 
@@ -260,6 +269,8 @@ __device__ __forceinline__ bool deposit(JT* const J[3], int base, int sy, int sz
                                         const Real x0[3], const Real x1[3], Real Q,
                                         const Real v[3], const PushConst<Real>& c) {
   const Real third = Real(1) / Real(3);
+  // the charge carries the fixed-point scale into the prefactors
+  if constexpr (std::is_integral<JT>::value) Q = Q * c.jscale;
   if constexpr (ND == 1) {
     Window<Real> wx;
     if (!window(x0[0], x1[0], wx)) return false;
@@ -272,10 +283,10 @@ __device__ __forceinline__ bool deposit(JT* const J[3], int base, int sy, int sz
       Real A = wx.S0[r] + Real(0.5) * wx.DS[r];
       if (r < 3) {
         C += wx.DS[r];
-        jadd<GLOBAL>(J[0] + o + r, fx * C, c.jscale);
+        jadd_terms<GLOBAL, false>(J[0] + o + r, fx, C, Real(0), Real(0));
       }
-      jadd<GLOBAL>(J[1] + o + r, fy * A, c.jscale);
-      jadd<GLOBAL>(J[2] + o + r, fz * A, c.jscale);
+      jadd_terms<GLOBAL, false>(J[1] + o + r, fy, A, Real(0), Real(0));
+      jadd_terms<GLOBAL, false>(J[2] + o + r, fz, A, Real(0), Real(0));
     }
   } else if constexpr (ND == 2) {
     Window<Real> wx, wy;
@@ -291,7 +302,8 @@ __device__ __forceinline__ bool deposit(JT* const J[3], int base, int sy, int sz
         Real a = fx * C;
 #pragma unroll
         for (int s = 0; s < 4; s++)
-          jadd<GLOBAL>(J[0] + o + r + s * sy, a * (wy.S0[s] + Real(0.5) * wy.DS[s]), c.jscale);
+          jadd_terms<GLOBAL, false>(J[0] + o + r + s * sy, a,
+                                    wy.S0[s] + Real(0.5) * wy.DS[s], Real(0), Real(0));
       }
     }
     // J_y = f_y C_y(s) (S0x + DSx/2)(r)
@@ -303,7 +315,8 @@ __device__ __forceinline__ bool deposit(JT* const J[3], int base, int sy, int sz
         Real a = fy * C;
 #pragma unroll
         for (int r = 0; r < 4; r++)
-          jadd<GLOBAL>(J[1] + o + r + s * sy, a * (wx.S0[r] + Real(0.5) * wx.DS[r]), c.jscale);
+          jadd_terms<GLOBAL, false>(J[1] + o + r + s * sy, a,
+                                    wx.S0[r] + Real(0.5) * wx.DS[r], Real(0), Real(0));
       }
     }
     // J_z = f_z [S0x (S0y + DSy/2) + DSx (S0y/2 + DSy/3)]
@@ -313,7 +326,8 @@ __device__ __forceinline__ bool deposit(JT* const J[3], int base, int sy, int sz
       Real by = Real(0.5) * wy.S0[s] + third * wy.DS[s];
 #pragma unroll
       for (int r = 0; r < 4; r++)
-        jadd<GLOBAL>(J[2] + o + r + s * sy, fz * (wx.S0[r] * ay + wx.DS[r] * by), c.jscale);
+        jadd_terms<GLOBAL, false>(J[2] + o + r + s * sy, fz, wx.S0[r] * ay + wx.DS[r] * by,
+                                  Real(0), Real(0));
     }
   } else {
     Window<Real> wx, wy, wz;
@@ -322,55 +336,58 @@ __device__ __forceinline__ bool deposit(JT* const J[3], int base, int sy, int sz
     const int o = base + wx.lo + wy.lo * sy + wz.lo * sz;
     // J_x = f_x C_x(r) [S0y (S0z + DSz/2) + DSy (S0z/2 + DSz/3)](s, t)
     {
-      Real fx = Q * c.jf[0];
-      Real C0 = wx.DS[0], C1 = C0 + wx.DS[1], C2 = C1 + wx.DS[2];
+      const Real fx = Q * c.jf[0];
+      const Real C0 = wx.DS[0], C1 = C0 + wx.DS[1], C2 = C1 + wx.DS[2];
+      const Real g0 = fx * C0, g1 = fx * C1, g2 = fx * C2;
 #pragma unroll
       for (int t = 0; t < 4; t++) {
         Real az = wz.S0[t] + Real(0.5) * wz.DS[t];
         Real bz = Real(0.5) * wz.S0[t] + third * wz.DS[t];
 #pragma unroll
         for (int s = 0; s < 4; s++) {
-          Real T = fx * (wy.S0[s] * az + wy.DS[s] * bz);
+          const Real X = wy.S0[s] * az + wy.DS[s] * bz;
           JT* p = J[0] + o + s * sy + t * sz;
-          jadd<GLOBAL>(p, C0 * T, c.jscale);
-          jadd<GLOBAL>(p + 1, C1 * T, c.jscale);
-          jadd<GLOBAL>(p + 2, C2 * T, c.jscale);
+          jadd_terms<GLOBAL, false>(p, g0, X, Real(0), Real(0));
+          jadd_terms<GLOBAL, false>(p + 1, g1, X, Real(0), Real(0));
+          jadd_terms<GLOBAL, false>(p + 2, g2, X, Real(0), Real(0));
         }
       }
     }
     // J_y = f_y C_y(s) [S0x (S0z + DSz/2) + DSx (S0z/2 + DSz/3)](r, t)
     {
-      Real fy = Q * c.jf[1];
-      Real C0 = wy.DS[0], C1 = C0 + wy.DS[1], C2 = C1 + wy.DS[2];
+      const Real fy = Q * c.jf[1];
+      const Real C0 = wy.DS[0], C1 = C0 + wy.DS[1], C2 = C1 + wy.DS[2];
+      const Real g0 = fy * C0, g1 = fy * C1, g2 = fy * C2;
 #pragma unroll
       for (int t = 0; t < 4; t++) {
         Real az = wz.S0[t] + Real(0.5) * wz.DS[t];
         Real bz = Real(0.5) * wz.S0[t] + third * wz.DS[t];
 #pragma unroll
         for (int r = 0; r < 4; r++) {
-          Real T = fy * (wx.S0[r] * az + wx.DS[r] * bz);
+          const Real X = wx.S0[r] * az + wx.DS[r] * bz;
           JT* p = J[1] + o + r + t * sz;
-          jadd<GLOBAL>(p, C0 * T, c.jscale);
-          jadd<GLOBAL>(p + sy, C1 * T, c.jscale);
-          jadd<GLOBAL>(p + 2 * sy, C2 * T, c.jscale);
+          jadd_terms<GLOBAL, false>(p, g0, X, Real(0), Real(0));
+          jadd_terms<GLOBAL, false>(p + sy, g1, X, Real(0), Real(0));
+          jadd_terms<GLOBAL, false>(p + 2 * sy, g2, X, Real(0), Real(0));
         }
       }
     }
     // J_z = f_z C_z(t) [S0x (S0y + DSy/2) + DSx (S0y/2 + DSy/3)](r, s)
     {
-      Real fz = Q * c.jf[2];
-      Real C0 = wz.DS[0], C1 = C0 + wz.DS[1], C2 = C1 + wz.DS[2];
+      const Real fz = Q * c.jf[2];
+      const Real C0 = wz.DS[0], C1 = C0 + wz.DS[1], C2 = C1 + wz.DS[2];
+      const Real g0 = fz * C0, g1 = fz * C1, g2 = fz * C2;
 #pragma unroll
       for (int s = 0; s < 4; s++) {
         Real ay = wy.S0[s] + Real(0.5) * wy.DS[s];
         Real by = Real(0.5) * wy.S0[s] + third * wy.DS[s];
 #pragma unroll
         for (int r = 0; r < 4; r++) {
-          Real T = fz * (wx.S0[r] * ay + wx.DS[r] * by);
+          const Real X = wx.S0[r] * ay + wx.DS[r] * by;
           JT* p = J[2] + o + r + s * sy;
-          jadd<GLOBAL>(p, C0 * T, c.jscale);
-          jadd<GLOBAL>(p + sz, C1 * T, c.jscale);
-          jadd<GLOBAL>(p + 2 * sz, C2 * T, c.jscale);
+          jadd_terms<GLOBAL, false>(p, g0, X, Real(0), Real(0));
+          jadd_terms<GLOBAL, false>(p + sz, g1, X, Real(0), Real(0));
+          jadd_terms<GLOBAL, false>(p + 2 * sz, g2, X, Real(0), Real(0));
         }
       }
     }
@@ -421,6 +438,46 @@ __device__ __forceinline__ void win3(const Real x0[3], const Real dx[3], const i
 // Bodies are given by old position and displacement (see win3).  With
 // PAIR the two bodies of an ion share the window and their terms are
 // added in registers before one add per node.
+// One current component of the 3D three-node deposit: along its axis AX the
+// running sum of DS_AX has two non-zero terms C0 = DS(0), C1 = DS(0) + DS(1)
+// (the third is the sum of the shape change, zero); across it the
+// path-averaged shape S0_B (S0_E + DS_E/2) + DS_B (S0_E/2 + DS_E/3) over
+// the transverse axes B < E.  The prefactor f and C are multiplied once
+// (g = f C), not per node.  Strides: sb, se of the nodes along B and E,
+// sa of the second node along AX.
+template <typename Real, int ND, bool GLOBAL, typename JT, bool PAIR, int AX>
+__device__ __forceinline__ void deposit3_axis(JT* Jc, int o, int sb, int se, int sa,
+                                              const Win3<Real, ND>& a, const Win3<Real, ND>& b,
+                                              Real fa, Real fb) {
+  constexpr int B = AX == 0 ? 1 : 0, E = AX == 2 ? 1 : 2;
+  const Real third = Real(1) / Real(3);
+  const Real ga0 = fa * a.DS[AX][0], ga1 = fa * (a.DS[AX][0] + a.DS[AX][1]);
+  Real gb0 = 0, gb1 = 0;
+  if constexpr (PAIR) {
+    gb0 = fb * b.DS[AX][0];
+    gb1 = fb * (b.DS[AX][0] + b.DS[AX][1]);
+  }
+#pragma unroll
+  for (int e = 0; e < 3; e++) {
+    const Real Aa = a.S0[E][e] + Real(0.5) * a.DS[E][e];
+    const Real Ba = Real(0.5) * a.S0[E][e] + third * a.DS[E][e];
+    Real Ab = 0, Bb = 0;
+    if constexpr (PAIR) {
+      Ab = b.S0[E][e] + Real(0.5) * b.DS[E][e];
+      Bb = Real(0.5) * b.S0[E][e] + third * b.DS[E][e];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+      const Real Xa = a.S0[B][k] * Aa + a.DS[B][k] * Ba;
+      Real Xb = 0;
+      if constexpr (PAIR) Xb = b.S0[B][k] * Ab + b.DS[B][k] * Bb;
+      JT* p = Jc + o + k * sb + e * se;
+      jadd_terms<GLOBAL, PAIR>(p, ga0, Xa, gb0, Xb);
+      jadd_terms<GLOBAL, PAIR>(p + sa, ga1, Xa, gb1, Xb);
+    }
+  }
+}
+
 template <typename Real, int ND, bool GLOBAL, typename JT, bool PAIR>
 __device__ __forceinline__ void deposit3(JT* const J[3], int base, int sy, int sz,
                                          const int nn[3], const Real xa0[3], const Real da[3],
@@ -428,6 +485,10 @@ __device__ __forceinline__ void deposit3(JT* const J[3], int base, int sy, int s
                                          const Real db[3], Real Qb, const Real vb[3],
                                          const PushConst<Real>& c) {
   const Real third = Real(1) / Real(3);
+  // charges carry the fixed-point scale into the prefactors
+  Real sc = Real(1);
+  if constexpr (std::is_integral<JT>::value) sc = c.jscale;
+  const Real qa = Qa * sc, qb = Qb * sc;
   Win3<Real, ND> a, b;
   win3<Real, ND>(xa0, da, nn, a);
   if constexpr (PAIR) win3<Real, ND>(xb0, db, nn, b);
@@ -435,12 +496,12 @@ __device__ __forceinline__ void deposit3(JT* const J[3], int base, int sy, int s
   if constexpr (ND > 1) o += (nn[1] - 1) * sy;
   if constexpr (ND > 2) o += (nn[2] - 1) * sz;
   if constexpr (ND == 1) {
-    Real fxa = Qa * c.jf[0], fya = Qa * va[1] * c.inv_dv, fza = Qa * va[2] * c.inv_dv;
+    Real fxa = qa * c.jf[0], fya = qa * va[1] * c.inv_dv, fza = qa * va[2] * c.inv_dv;
     Real fxb = 0, fyb = 0, fzb = 0;
     if constexpr (PAIR) {
-      fxb = Qb * c.jf[0];
-      fyb = Qb * vb[1] * c.inv_dv;
-      fzb = Qb * vb[2] * c.inv_dv;
+      fxb = qb * c.jf[0];
+      fyb = qb * vb[1] * c.inv_dv;
+      fzb = qb * vb[2] * c.inv_dv;
     }
     Real Ca = 0, Cb = 0;
 #pragma unroll
@@ -451,27 +512,27 @@ __device__ __forceinline__ void deposit3(JT* const J[3], int base, int sy, int s
       if (r < 2) {
         Ca += a.DS[0][r];
         if constexpr (PAIR) Cb += b.DS[0][r];
-        jadd<GLOBAL>(J[0] + o + r, PAIR ? fxa * Ca + fxb * Cb : fxa * Ca, c.jscale);
+        jadd_terms<GLOBAL, PAIR>(J[0] + o + r, fxa, Ca, fxb, Cb);
       }
-      jadd<GLOBAL>(J[1] + o + r, PAIR ? fya * Aa + fyb * Ab : fya * Aa, c.jscale);
-      jadd<GLOBAL>(J[2] + o + r, PAIR ? fza * Aa + fzb * Ab : fza * Aa, c.jscale);
+      jadd_terms<GLOBAL, PAIR>(J[1] + o + r, fya, Aa, fyb, Ab);
+      jadd_terms<GLOBAL, PAIR>(J[2] + o + r, fza, Aa, fzb, Ab);
     }
   } else if constexpr (ND == 2) {
-    Real fxa = Qa * c.jf[0], fya = Qa * c.jf[1], fza = Qa * va[2] * c.inv_dv;
+    Real fxa = qa * c.jf[0], fya = qa * c.jf[1], fza = qa * va[2] * c.inv_dv;
     Real fxb = 0, fyb = 0, fzb = 0;
     if constexpr (PAIR) {
-      fxb = Qb * c.jf[0];
-      fyb = Qb * c.jf[1];
-      fzb = Qb * vb[2] * c.inv_dv;
+      fxb = qb * c.jf[0];
+      fyb = qb * c.jf[1];
+      fzb = qb * vb[2] * c.inv_dv;
     }
-    Real Cxa0 = a.DS[0][0], Cxa1 = Cxa0 + a.DS[0][1];
-    Real Cya0 = a.DS[1][0], Cya1 = Cya0 + a.DS[1][1];
-    Real Cxb0 = 0, Cxb1 = 0, Cyb0 = 0, Cyb1 = 0;
+    const Real gxa0 = fxa * a.DS[0][0], gxa1 = fxa * (a.DS[0][0] + a.DS[0][1]);
+    const Real gya0 = fya * a.DS[1][0], gya1 = fya * (a.DS[1][0] + a.DS[1][1]);
+    Real gxb0 = 0, gxb1 = 0, gyb0 = 0, gyb1 = 0;
     if constexpr (PAIR) {
-      Cxb0 = b.DS[0][0];
-      Cxb1 = Cxb0 + b.DS[0][1];
-      Cyb0 = b.DS[1][0];
-      Cyb1 = Cyb0 + b.DS[1][1];
+      gxb0 = fxb * b.DS[0][0];
+      gxb1 = fxb * (b.DS[0][0] + b.DS[0][1]);
+      gyb0 = fyb * b.DS[1][0];
+      gyb1 = fyb * (b.DS[1][0] + b.DS[1][1]);
     }
 #pragma unroll
     for (int s2 = 0; s2 < 3; s2++) {
@@ -484,114 +545,31 @@ __device__ __forceinline__ void deposit3(JT* const J[3], int base, int sy, int s
       }
       // J_x = f_x C_x(r) (S0y + DSy/2)(s)
       JT* px = J[0] + o + s2 * sy;
-      jadd<GLOBAL>(px, PAIR ? fxa * Cxa0 * Aya + fxb * Cxb0 * Ayb : fxa * Cxa0 * Aya, c.jscale);
-      jadd<GLOBAL>(px + 1, PAIR ? fxa * Cxa1 * Aya + fxb * Cxb1 * Ayb : fxa * Cxa1 * Aya, c.jscale);
+      jadd_terms<GLOBAL, PAIR>(px, gxa0, Aya, gxb0, Ayb);
+      jadd_terms<GLOBAL, PAIR>(px + 1, gxa1, Aya, gxb1, Ayb);
 #pragma unroll
       for (int r = 0; r < 3; r++) {
         Real Axa = a.S0[0][r] + Real(0.5) * a.DS[0][r];
         Real Axb = 0;
         if constexpr (PAIR) Axb = b.S0[0][r] + Real(0.5) * b.DS[0][r];
         // J_y = f_y C_y(s) (S0x + DSx/2)(r), for s < 2
-        if (s2 < 2) {
-          Real cya = s2 == 0 ? Cya0 : Cya1, cyb = s2 == 0 ? Cyb0 : Cyb1;
-          jadd<GLOBAL>(J[1] + o + r + s2 * sy, PAIR ? fya * cya * Axa + fyb * cyb * Axb
-                                                     : fya * cya * Axa, c.jscale);
-        }
+        if (s2 < 2)
+          jadd_terms<GLOBAL, PAIR>(J[1] + o + r + s2 * sy, s2 == 0 ? gya0 : gya1, Axa,
+                                   s2 == 0 ? gyb0 : gyb1, Axb);
         // J_z = f_z [S0x (S0y + DSy/2) + DSx (S0y/2 + DSy/3)]
-        Real za = fza * (a.S0[0][r] * Aya + a.DS[0][r] * Bya);
-        Real zb = 0;
-        if constexpr (PAIR) zb = fzb * (b.S0[0][r] * Ayb + b.DS[0][r] * Byb);
-        jadd<GLOBAL>(J[2] + o + r + s2 * sy, PAIR ? za + zb : za, c.jscale);
+        Real Xa = a.S0[0][r] * Aya + a.DS[0][r] * Bya;
+        Real Xb = 0;
+        if constexpr (PAIR) Xb = b.S0[0][r] * Ayb + b.DS[0][r] * Byb;
+        jadd_terms<GLOBAL, PAIR>(J[2] + o + r + s2 * sy, fza, Xa, fzb, Xb);
       }
     }
   } else {
-    // J_x: running sum along x of DS_x, times [S0y (S0z + DSz/2) + DSy (S0z/2 + DSz/3)]
-    {
-      Real fa = Qa * c.jf[0], fb = PAIR ? Qb * c.jf[0] : Real(0);
-      Real Ca0 = a.DS[0][0], Ca1 = Ca0 + a.DS[0][1];
-      Real Cb0 = 0, Cb1 = 0;
-      if constexpr (PAIR) {
-        Cb0 = b.DS[0][0];
-        Cb1 = Cb0 + b.DS[0][1];
-      }
-#pragma unroll
-      for (int t = 0; t < 3; t++) {
-        Real aza = a.S0[2][t] + Real(0.5) * a.DS[2][t];
-        Real bza = Real(0.5) * a.S0[2][t] + third * a.DS[2][t];
-        Real azb = 0, bzb = 0;
-        if constexpr (PAIR) {
-          azb = b.S0[2][t] + Real(0.5) * b.DS[2][t];
-          bzb = Real(0.5) * b.S0[2][t] + third * b.DS[2][t];
-        }
-#pragma unroll
-        for (int s2 = 0; s2 < 3; s2++) {
-          Real Ta = fa * (a.S0[1][s2] * aza + a.DS[1][s2] * bza);
-          Real Tb = 0;
-          if constexpr (PAIR) Tb = fb * (b.S0[1][s2] * azb + b.DS[1][s2] * bzb);
-          JT* p = J[0] + o + s2 * sy + t * sz;
-          jadd<GLOBAL>(p, PAIR ? Ca0 * Ta + Cb0 * Tb : Ca0 * Ta, c.jscale);
-          jadd<GLOBAL>(p + 1, PAIR ? Ca1 * Ta + Cb1 * Tb : Ca1 * Ta, c.jscale);
-        }
-      }
-    }
-    // J_y: running sum along y of DS_y, times [S0x (S0z + DSz/2) + DSx (S0z/2 + DSz/3)]
-    {
-      Real fa = Qa * c.jf[1], fb = PAIR ? Qb * c.jf[1] : Real(0);
-      Real Ca0 = a.DS[1][0], Ca1 = Ca0 + a.DS[1][1];
-      Real Cb0 = 0, Cb1 = 0;
-      if constexpr (PAIR) {
-        Cb0 = b.DS[1][0];
-        Cb1 = Cb0 + b.DS[1][1];
-      }
-#pragma unroll
-      for (int t = 0; t < 3; t++) {
-        Real aza = a.S0[2][t] + Real(0.5) * a.DS[2][t];
-        Real bza = Real(0.5) * a.S0[2][t] + third * a.DS[2][t];
-        Real azb = 0, bzb = 0;
-        if constexpr (PAIR) {
-          azb = b.S0[2][t] + Real(0.5) * b.DS[2][t];
-          bzb = Real(0.5) * b.S0[2][t] + third * b.DS[2][t];
-        }
-#pragma unroll
-        for (int r = 0; r < 3; r++) {
-          Real Ta = fa * (a.S0[0][r] * aza + a.DS[0][r] * bza);
-          Real Tb = 0;
-          if constexpr (PAIR) Tb = fb * (b.S0[0][r] * azb + b.DS[0][r] * bzb);
-          JT* p = J[1] + o + r + t * sz;
-          jadd<GLOBAL>(p, PAIR ? Ca0 * Ta + Cb0 * Tb : Ca0 * Ta, c.jscale);
-          jadd<GLOBAL>(p + sy, PAIR ? Ca1 * Ta + Cb1 * Tb : Ca1 * Ta, c.jscale);
-        }
-      }
-    }
-    // J_z: running sum along z of DS_z, times [S0x (S0y + DSy/2) + DSx (S0y/2 + DSy/3)]
-    {
-      Real fa = Qa * c.jf[2], fb = PAIR ? Qb * c.jf[2] : Real(0);
-      Real Ca0 = a.DS[2][0], Ca1 = Ca0 + a.DS[2][1];
-      Real Cb0 = 0, Cb1 = 0;
-      if constexpr (PAIR) {
-        Cb0 = b.DS[2][0];
-        Cb1 = Cb0 + b.DS[2][1];
-      }
-#pragma unroll
-      for (int s2 = 0; s2 < 3; s2++) {
-        Real aya = a.S0[1][s2] + Real(0.5) * a.DS[1][s2];
-        Real bya = Real(0.5) * a.S0[1][s2] + third * a.DS[1][s2];
-        Real ayb = 0, byb = 0;
-        if constexpr (PAIR) {
-          ayb = b.S0[1][s2] + Real(0.5) * b.DS[1][s2];
-          byb = Real(0.5) * b.S0[1][s2] + third * b.DS[1][s2];
-        }
-#pragma unroll
-        for (int r = 0; r < 3; r++) {
-          Real Ta = fa * (a.S0[0][r] * aya + a.DS[0][r] * bya);
-          Real Tb = 0;
-          if constexpr (PAIR) Tb = fb * (b.S0[0][r] * ayb + b.DS[0][r] * byb);
-          JT* p = J[2] + o + r + s2 * sy;
-          jadd<GLOBAL>(p, PAIR ? Ca0 * Ta + Cb0 * Tb : Ca0 * Ta, c.jscale);
-          jadd<GLOBAL>(p + sz, PAIR ? Ca1 * Ta + Cb1 * Tb : Ca1 * Ta, c.jscale);
-        }
-      }
-    }
+    deposit3_axis<Real, ND, GLOBAL, JT, PAIR, 0>(J[0], o, sy, sz, 1, a, b, qa * c.jf[0],
+                                                 qb * c.jf[0]);
+    deposit3_axis<Real, ND, GLOBAL, JT, PAIR, 1>(J[1], o, 1, sz, sy, a, b, qa * c.jf[1],
+                                                 qb * c.jf[1]);
+    deposit3_axis<Real, ND, GLOBAL, JT, PAIR, 2>(J[2], o, 1, sy, sz, a, b, qa * c.jf[2],
+                                                 qb * c.jf[2]);
   }
 }
 
