@@ -337,7 +337,7 @@ def main():
                           f"one of the {ncol} tile-colour dispatches of a step",
                 "launch_ms": r32["ion_dispatch_ms"],
                 "algorithmic_bytes_per_launch": r32["bytes_ion_dispatch"],
-                "limiter": "VALU issue: 74 % busy, ~1770 VALU instructions per ion "
+                "limiter": "VALU issue: 77 % busy, ~1770 VALU instructions per ion "
                            "(profiles/push_tiled_3d_fp32_ionised_slab_256x128x128_counters.txt)"}
     adj = None if args.no_adjoint else run_adjoint(args)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_seconds)

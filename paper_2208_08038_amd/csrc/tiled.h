@@ -24,9 +24,10 @@ constexpr int bank_pitch(int width, int tx) {
 // LDS layout of a tile's patches.  Field components are stored in pairs
 // (Ex Ey | Ez Bx | By Bz) with the two rows of a pair side by side, which
 // fills the row pitch that the bank rule asks for (24 values for an 8-cell
-// tile row) with data instead of padding.  The three FP64 current
-// components share each row, packed: padding those rows to the bank rule
-// measured slower on the 512x256x256 slab.
+// tile row) with data instead of padding.  The three current components
+// share each row, which is padded to the bank rule for 64-bit words (40
+// words for an 8-cell tile: the 32 lanes of four 8-cell rows then cover the
+// 64 banks once per relative node of the deposit's atomics).
 struct PatchLayout {
   int F[3];    // field patch extent: T + 4 (2-node apron each side)
   int Jd[3];   // current patch extent: T + 5 (2 below, 3 above)
@@ -48,7 +49,7 @@ constexpr PatchLayout patch_layout(int tx, int ty, int tz, int nd) {
   L.fpitch = nd > 1 ? bank_pitch(2 * L.F[0], tx) : 2 * L.F[0];
   L.fplane = L.fpitch * L.F[1];
   L.fpair = L.fplane * L.F[2];
-  L.jpitch = 3 * L.Jd[0];
+  L.jpitch = nd > 1 ? bank_pitch(3 * L.Jd[0], tx) : 3 * L.Jd[0];
   L.jplane = L.jpitch * L.Jd[1];
   L.nj = L.jplane * L.Jd[2];
   return L;

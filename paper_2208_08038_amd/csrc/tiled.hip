@@ -298,7 +298,7 @@ TileGeom make_tile_geom(const GridInfo& g, const int tile[3], const int ntiles[3
   size_t limit = fixed + 32 * entry <= kTiledMaxLds / 2 ? kTiledMaxLds / 2 : kTiledMaxLds;
   if (fixed < limit) {
     size_t room = (limit - fixed) / entry;
-    t.qcap = (int)std::min<size_t>(room, kQueueMax) & ~31;
+    t.qcap = (int)std::min<size_t>(room, kQueueMax) & ~15;
   }
   return t;
 }
