@@ -314,16 +314,33 @@ __device__ __forceinline__ void velocity_adjoint(const Real n[3], const Real lv[
   for (int q = 0; q < 3; q++) ln[q] += g * lv[q] - g3 * n[q] * nl;
 }
 
-// Shapes of one body on the four-node deposit window of one dimension:
-// old (S0) and new (S1) weights and their position derivatives.
-template <typename Real>
-struct Win4 {
+// Shapes of one body on the deposit window of one dimension, NW nodes
+// from node `lo`: old (S0) and new (S1) weights and their position
+// derivatives.  NW = 3 when the body keeps its nearest node over the step
+// (the window of its shape), NW = 4 when that node moves by one.
+template <typename Real, int NW>
+struct Win {
   int lo;
-  Real S0[4], S1[4], D0[4], D1[4];
+  Real S0[NW], S1[NW], D0[NW], D1[NW];
 };
 
 template <typename Real>
-__device__ __forceinline__ bool win4(Real x0, Real x1, Win4<Real>& w) {
+__device__ __forceinline__ bool win_build(Real x0, Real x1, Win<Real, 3>& w) {
+  const Shape<Real> a = shape_at(x0, false), b = shape_at(x1, false);
+  if (a.i0 != b.i0) return false;
+  w.lo = a.i0;
+#pragma unroll
+  for (int r = 0; r < 3; r++) {
+    w.S0[r] = a.w[r];
+    w.D0[r] = a.dw[r];
+    w.S1[r] = b.w[r];
+    w.D1[r] = b.dw[r];
+  }
+  return true;
+}
+
+template <typename Real>
+__device__ __forceinline__ bool win_build(Real x0, Real x1, Win<Real, 4>& w) {
   const Shape<Real> a = shape_at(x0, false), b = shape_at(x1, false);
   const int lo = min(a.i0, b.i0);
   const int sa = a.i0 - lo, sb = b.i0 - lo;
@@ -350,185 +367,286 @@ __device__ __forceinline__ bool win4(Real x0, Real x1, Win4<Real>& w) {
   return true;
 }
 
-// Adjoint of the Esirkepov deposit of one body (charge Q, from x0 to x1,
-// velocity v for the out-of-plane components): with lJ the adjoint current,
-// Phi = sum lJ . J; returns dPhi/dx0, dPhi/dx1 (resolved dims) and
-// dPhi/dv (unresolved components).  The running sum along an axis turns
-// into a suffix sum of lJ; the path-averaged transverse shape
-// M = S0 S0'/3 + S0 S1'/6 + S1 S0'/6 + S1 S1'/3 (two transverse axes) or
-// (S0 + S1)/2 (one) is differentiated by hand.
+// Adjoint of the Esirkepov deposit of NB bodies (NB = 2: both bodies of an
+// ion on common windows, which then read the adjoint current once), body
+// b with charge Q[b] moving from x0[b] to x1[b] at velocity v[b] (for the
+// out-of-plane components), on windows of NW nodes: with lJ the adjoint
+// current, Phi = sum lJ . J; returns per body dPhi/dx0, dPhi/dx1 (resolved
+// dims) and dPhi/dv (unresolved components).  The running sum along an
+// axis (non-zero on the first NW - 1 edges of the window: the shape change
+// sums to zero) turns into a suffix sum of lJ; the path-averaged
+// transverse shape M = S0 S0'/3 + S0 S1'/6 + S1 S0'/6 + S1 S1'/3 (two
+// transverse axes) or (S0 + S1)/2 (one) is differentiated by hand.
+// Returns false if the windows do not hold every body's shapes.
+template <typename Real, int ND, int NW, int NB>
+__device__ __forceinline__ bool deposit_adjoint_w(const Real* J, int64_t jplane,
+                                                  const Where3& wh, const Real* const x0[NB],
+                                                  const Real* const x1[NB], const Real Q[NB],
+                                                  const Real* const v[NB],
+                                                  const PushConst<Real>& c, Real g0[NB][3],
+                                                  Real g1[NB][3], Real gv[NB][3]) {
+  const Real third = Real(1) / Real(3), sixth = Real(1) / Real(6);
+  const int64_t base = wh.base, sy = wh.sy;
+#pragma unroll
+  for (int b = 0; b < NB; b++)
+#pragma unroll
+    for (int d = 0; d < 3; d++) g0[b][d] = g1[b][d] = gv[b][d] = Real(0);
+  if constexpr (ND == 1) {
+    Win<Real, NW> wx[NB];
+#pragma unroll
+    for (int b = 0; b < NB; b++)
+      if (!win_build(x0[b][0], x1[b][0], wx[b]) || wx[b].lo != wx[0].lo) return false;
+    const int64_t o = base + wx[0].lo;
+    // J_x(r) = fx C(r), r < NW - 1; J_y,z(r) = fv v_{y,z} (S0 + S1)(r) / 2
+    Real L[NW];
+    L[NW - 1] = Real(0);
+    Real acc = 0;
+#pragma unroll
+    for (int r = NW - 2; r >= 0; r--) {
+      acc += J[o + r];
+      L[r] = acc;
+    }
+#pragma unroll
+    for (int r = 0; r < NW; r++) {
+      const Real ly = J[jplane + o + r], lz = J[2 * jplane + o + r];
+#pragma unroll
+      for (int b = 0; b < NB; b++) {
+        const Real fx = Q[b] * c.jf[0], fv = Q[b] * c.inv_dv;
+        const Real A = Real(0.5) * (wx[b].S0[r] + wx[b].S1[r]);
+        gv[b][1] += fv * ly * A;
+        gv[b][2] += fv * lz * A;
+        const Real t = Real(0.5) * fv * (v[b][1] * ly + v[b][2] * lz);
+        const Real dS1 = fx * L[r] + t, dS0 = -fx * L[r] + t;
+        g0[b][0] += dS0 * wx[b].D0[r];
+        g1[b][0] += dS1 * wx[b].D1[r];
+      }
+    }
+    return true;
+  } else if constexpr (ND == 2) {
+    Win<Real, NW> wx[NB], wy[NB];
+#pragma unroll
+    for (int b = 0; b < NB; b++)
+      if (!win_build(x0[b][0], x1[b][0], wx[b]) || !win_build(x0[b][1], x1[b][1], wy[b]) ||
+          wx[b].lo != wx[0].lo || wy[b].lo != wy[0].lo)
+        return false;
+    const int64_t o = base + wx[0].lo + (int64_t)wy[0].lo * sy;
+    Real fx[NB], fy[NB], fz[NB];
+    Real G0x[NB][NW], G1x[NB][NW], G0y[NB][NW], G1y[NB][NW];
+    Real Ax[NB][NW], Ay[NB][NW], DSx[NB][NW], DSy[NB][NW];
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+      fx[b] = Q[b] * c.jf[0];
+      fy[b] = Q[b] * c.jf[1];
+      fz[b] = Q[b] * v[b][2] * c.inv_dv;
+#pragma unroll
+      for (int r = 0; r < NW; r++) {
+        G0x[b][r] = G1x[b][r] = G0y[b][r] = G1y[b][r] = Real(0);
+        Ax[b][r] = Real(0.5) * (wx[b].S0[r] + wx[b].S1[r]);
+        Ay[b][r] = Real(0.5) * (wy[b].S0[r] + wy[b].S1[r]);
+        DSx[b][r] = wx[b].S1[r] - wx[b].S0[r];
+        DSy[b][r] = wy[b].S1[r] - wy[b].S0[r];
+      }
+    }
+    // J_x(r, s) = fx Cx(r) Ay(s), r < NW - 1: Lx(r, s) suffix sums along x
+#pragma unroll
+    for (int s = 0; s < NW; s++) {
+      Real acc = 0, Lx[NW];
+      Lx[NW - 1] = Real(0);
+#pragma unroll
+      for (int r = NW - 2; r >= 0; r--) {
+        acc += J[o + r + s * sy];
+        Lx[r] = acc;
+      }
+#pragma unroll
+      for (int b = 0; b < NB; b++) {
+        Real sumDL = 0;
+#pragma unroll
+        for (int r = 0; r < NW; r++) {
+          const Real t = fx[b] * Ay[b][s] * Lx[r];
+          G1x[b][r] += t;
+          G0x[b][r] -= t;
+          sumDL += DSx[b][r] * Lx[r];
+        }
+        G0y[b][s] += Real(0.5) * fx[b] * sumDL;
+        G1y[b][s] += Real(0.5) * fx[b] * sumDL;
+      }
+    }
+    // J_y(r, s) = fy Cy(s) Ax(r), s < NW - 1: Ly(r, s) suffix sums along y
+#pragma unroll
+    for (int r = 0; r < NW; r++) {
+      Real acc = 0, Ly[NW];
+      Ly[NW - 1] = Real(0);
+#pragma unroll
+      for (int s = NW - 2; s >= 0; s--) {
+        acc += J[jplane + o + r + s * sy];
+        Ly[s] = acc;
+      }
+#pragma unroll
+      for (int b = 0; b < NB; b++) {
+        Real sumDL = 0;
+#pragma unroll
+        for (int s = 0; s < NW; s++) {
+          const Real t = fy[b] * Ax[b][r] * Ly[s];
+          G1y[b][s] += t;
+          G0y[b][s] -= t;
+          sumDL += DSy[b][s] * Ly[s];
+        }
+        G0x[b][r] += Real(0.5) * fy[b] * sumDL;
+        G1x[b][r] += Real(0.5) * fy[b] * sumDL;
+      }
+    }
+    // J_z(r, s) = fz W(r, s), W = S0x S0y/3 + S0x S1y/6 + S1x S0y/6 + S1x S1y/3
+#pragma unroll
+    for (int s = 0; s < NW; s++)
+#pragma unroll
+      for (int r = 0; r < NW; r++) {
+        const Real lz = J[2 * jplane + o + r + s * sy];
+        if (lz == Real(0)) continue;
+#pragma unroll
+        for (int b = 0; b < NB; b++) {
+          const Win<Real, NW>& X = wx[b];
+          const Win<Real, NW>& Y = wy[b];
+          const Real W = third * X.S0[r] * Y.S0[s] + sixth * X.S0[r] * Y.S1[s] +
+                         sixth * X.S1[r] * Y.S0[s] + third * X.S1[r] * Y.S1[s];
+          gv[b][2] += Q[b] * c.inv_dv * lz * W;
+          const Real t = fz[b] * lz;
+          G0x[b][r] += t * (third * Y.S0[s] + sixth * Y.S1[s]);
+          G1x[b][r] += t * (sixth * Y.S0[s] + third * Y.S1[s]);
+          G0y[b][s] += t * (third * X.S0[r] + sixth * X.S1[r]);
+          G1y[b][s] += t * (sixth * X.S0[r] + third * X.S1[r]);
+        }
+      }
+#pragma unroll
+    for (int b = 0; b < NB; b++)
+#pragma unroll
+      for (int r = 0; r < NW; r++) {
+        g0[b][0] += G0x[b][r] * wx[b].D0[r];
+        g1[b][0] += G1x[b][r] * wx[b].D1[r];
+        g0[b][1] += G0y[b][r] * wy[b].D0[r];
+        g1[b][1] += G1y[b][r] * wy[b].D1[r];
+      }
+    return true;
+  } else {
+    Win<Real, NW> w[NB][3];
+#pragma unroll
+    for (int b = 0; b < NB; b++)
+#pragma unroll
+      for (int d = 0; d < 3; d++)
+        if (!win_build(x0[b][d], x1[b][d], w[b][d]) || w[b][d].lo != w[0][d].lo) return false;
+    const int64_t st[3] = {1, sy, wh.sz};
+    const int64_t o = base + w[0][0].lo + (int64_t)w[0][1].lo * sy + (int64_t)w[0][2].lo * wh.sz;
+    Real G0[NB][3][NW], G1[NB][3][NW];
+#pragma unroll
+    for (int b = 0; b < NB; b++)
+#pragma unroll
+      for (int d = 0; d < 3; d++)
+#pragma unroll
+        for (int r = 0; r < NW; r++) G0[b][d][r] = G1[b][d][r] = Real(0);
+    // J_a(i_a, i_b, i_c) = Q jf_a C_a(i_a) M(i_b, i_c), C_a the running sum of
+    // the shape change along a, (e1, e2) the transverse axes
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      const int e1 = a == 0 ? 1 : 0, e2 = a == 2 ? 1 : 2;
+      const Real* Ja = J + a * jplane;
+#pragma unroll
+      for (int s = 0; s < NW; s++)
+#pragma unroll
+        for (int t = 0; t < NW; t++) {
+          const int64_t ob = o + s * st[e1] + t * st[e2];
+          Real L[NW], acc = 0;
+          L[NW - 1] = Real(0);
+#pragma unroll
+          for (int r = NW - 2; r >= 0; r--) {
+            acc += Ja[ob + r * st[a]];
+            L[r] = acc;
+          }
+#pragma unroll
+          for (int b = 0; b < NB; b++) {
+            const Win<Real, NW>& A = w[b][a];
+            const Win<Real, NW>& B = w[b][e1];
+            const Win<Real, NW>& E = w[b][e2];
+            const Real f = Q[b] * c.jf[a];
+            const Real M = third * B.S0[s] * E.S0[t] + sixth * B.S0[s] * E.S1[t] +
+                           sixth * B.S1[s] * E.S0[t] + third * B.S1[s] * E.S1[t];
+            Real P = 0;
+#pragma unroll
+            for (int r = 0; r < NW; r++) {
+              const Real q = f * M * L[r];
+              G1[b][a][r] += q;
+              G0[b][a][r] -= q;
+              P += (A.S1[r] - A.S0[r]) * L[r];
+            }
+            P *= f;
+            G0[b][e1][s] += P * (third * E.S0[t] + sixth * E.S1[t]);
+            G1[b][e1][s] += P * (sixth * E.S0[t] + third * E.S1[t]);
+            G0[b][e2][t] += P * (third * B.S0[s] + sixth * B.S1[s]);
+            G1[b][e2][t] += P * (sixth * B.S0[s] + third * B.S1[s]);
+          }
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; b++)
+#pragma unroll
+      for (int d = 0; d < 3; d++)
+#pragma unroll
+        for (int r = 0; r < NW; r++) {
+          g0[b][d] += G0[b][d][r] * w[b][d].D0[r];
+          g1[b][d] += G1[b][d][r] * w[b][d].D1[r];
+        }
+    return true;
+  }
+}
+
+// The deposit adjoint of one body on the three-node windows when it keeps
+// its nearest node along every resolved axis (most bodies), else on four.
 template <typename Real, int ND>
 __device__ __forceinline__ bool deposit_adjoint(const Real* J, int64_t jplane, const Where3& wh,
                                                 const Real x0[3], const Real x1[3], Real Q,
                                                 const Real v[3], const PushConst<Real>& c,
                                                 Real g0[3], Real g1[3], Real gv[3]) {
-  const Real third = Real(1) / Real(3), sixth = Real(1) / Real(6);
-  const int64_t base = wh.base, sy = wh.sy;
+  bool keep = true;
 #pragma unroll
-  for (int d = 0; d < 3; d++) g0[d] = g1[d] = gv[d] = Real(0);
-  if constexpr (ND == 1) {
-    Win4<Real> wx;
-    if (!win4(x0[0], x1[0], wx)) return false;
-    const int64_t o = base + wx.lo;
-    const Real fx = Q * c.jf[0], fv = Q * c.inv_dv;
-    // J_x(r) = fx C(r), r < 3; J_y,z(r) = fv v_{y,z} (S0 + S1)(r) / 2
-    Real L[4];
-    L[3] = Real(0);
-    Real acc = 0;
+  for (int d = 0; d < ND; d++) keep = keep && floor(x0[d] + Real(0.5)) == floor(x1[d] + Real(0.5));
+  const Real* const a0[1] = {x0};
+  const Real* const a1[1] = {x1};
+  const Real* const av[1] = {v};
+  const Real q[1] = {Q};
+  Real h0[1][3], h1[1][3], hv[1][3];
+  const bool ok = keep ? deposit_adjoint_w<Real, ND, 3, 1>(J, jplane, wh, a0, a1, q, av, c, h0, h1, hv)
+                       : deposit_adjoint_w<Real, ND, 4, 1>(J, jplane, wh, a0, a1, q, av, c, h0, h1, hv);
 #pragma unroll
-    for (int r = 2; r >= 0; r--) {
-      acc += J[o + r];
-      L[r] = acc;
-    }
-#pragma unroll
-    for (int r = 0; r < 4; r++) {
-      const Real ly = J[jplane + o + r], lz = J[2 * jplane + o + r];
-      const Real A = Real(0.5) * (wx.S0[r] + wx.S1[r]);
-      gv[1] += fv * ly * A;
-      gv[2] += fv * lz * A;
-      const Real t = Real(0.5) * fv * (v[1] * ly + v[2] * lz);
-      const Real dS1 = fx * L[r] + t, dS0 = -fx * L[r] + t;
-      g0[0] += dS0 * wx.D0[r];
-      g1[0] += dS1 * wx.D1[r];
-    }
-    return true;
-  } else if constexpr (ND == 2) {
-    Win4<Real> wx, wy;
-    if (!win4(x0[0], x1[0], wx) || !win4(x0[1], x1[1], wy)) return false;
-    const int64_t o = base + wx.lo + (int64_t)wy.lo * sy;
-    const Real fx = Q * c.jf[0], fy = Q * c.jf[1], fz = Q * v[2] * c.inv_dv;
-    Real G0x[4] = {0, 0, 0, 0}, G1x[4] = {0, 0, 0, 0}, G0y[4] = {0, 0, 0, 0},
-         G1y[4] = {0, 0, 0, 0};
-    Real Ax[4], Ay[4], DSx[4], DSy[4];
-#pragma unroll
-    for (int r = 0; r < 4; r++) {
-      Ax[r] = Real(0.5) * (wx.S0[r] + wx.S1[r]);
-      Ay[r] = Real(0.5) * (wy.S0[r] + wy.S1[r]);
-      DSx[r] = wx.S1[r] - wx.S0[r];
-      DSy[r] = wy.S1[r] - wy.S0[r];
-    }
-    // J_x(r, s) = fx Cx(r) Ay(s), r < 3: Lx(r, s) suffix sums along x
-#pragma unroll
-    for (int s = 0; s < 4; s++) {
-      Real acc = 0, Lx[4];
-      Lx[3] = Real(0);
-#pragma unroll
-      for (int r = 2; r >= 0; r--) {
-        acc += J[o + r + s * sy];
-        Lx[r] = acc;
-      }
-      Real sumDL = 0;
-#pragma unroll
-      for (int r = 0; r < 4; r++) {
-        const Real t = fx * Ay[s] * Lx[r];
-        G1x[r] += t;
-        G0x[r] -= t;
-        sumDL += DSx[r] * Lx[r];
-      }
-      G0y[s] += Real(0.5) * fx * sumDL;
-      G1y[s] += Real(0.5) * fx * sumDL;
-    }
-    // J_y(r, s) = fy Cy(s) Ax(r), s < 3: Ly(r, s) suffix sums along y
-#pragma unroll
-    for (int r = 0; r < 4; r++) {
-      Real acc = 0, Ly[4];
-      Ly[3] = Real(0);
-#pragma unroll
-      for (int s = 2; s >= 0; s--) {
-        acc += J[jplane + o + r + s * sy];
-        Ly[s] = acc;
-      }
-      Real sumDL = 0;
-#pragma unroll
-      for (int s = 0; s < 4; s++) {
-        const Real t = fy * Ax[r] * Ly[s];
-        G1y[s] += t;
-        G0y[s] -= t;
-        sumDL += DSy[s] * Ly[s];
-      }
-      G0x[r] += Real(0.5) * fy * sumDL;
-      G1x[r] += Real(0.5) * fy * sumDL;
-    }
-    // J_z(r, s) = fz W(r, s), W = S0x S0y/3 + S0x S1y/6 + S1x S0y/6 + S1x S1y/3
-#pragma unroll
-    for (int s = 0; s < 4; s++)
-#pragma unroll
-      for (int r = 0; r < 4; r++) {
-        const Real lz = J[2 * jplane + o + r + s * sy];
-        if (lz == Real(0)) continue;
-        const Real W = third * wx.S0[r] * wy.S0[s] + sixth * wx.S0[r] * wy.S1[s] +
-                       sixth * wx.S1[r] * wy.S0[s] + third * wx.S1[r] * wy.S1[s];
-        gv[2] += Q * c.inv_dv * lz * W;
-        const Real t = fz * lz;
-        G0x[r] += t * (third * wy.S0[s] + sixth * wy.S1[s]);
-        G1x[r] += t * (sixth * wy.S0[s] + third * wy.S1[s]);
-        G0y[s] += t * (third * wx.S0[r] + sixth * wx.S1[r]);
-        G1y[s] += t * (sixth * wx.S0[r] + third * wx.S1[r]);
-      }
-#pragma unroll
-    for (int r = 0; r < 4; r++) {
-      g0[0] += G0x[r] * wx.D0[r];
-      g1[0] += G1x[r] * wx.D1[r];
-      g0[1] += G0y[r] * wy.D0[r];
-      g1[1] += G1y[r] * wy.D1[r];
-    }
-    return true;
-  } else {
-    Win4<Real> w[3];
-    if (!win4(x0[0], x1[0], w[0]) || !win4(x0[1], x1[1], w[1]) || !win4(x0[2], x1[2], w[2]))
-      return false;
-    const int64_t st[3] = {1, sy, wh.sz};
-    const int64_t o = base + w[0].lo + (int64_t)w[1].lo * sy + (int64_t)w[2].lo * wh.sz;
-    Real G0[3][4], G1[3][4];
-#pragma unroll
-    for (int d = 0; d < 3; d++)
-#pragma unroll
-      for (int r = 0; r < 4; r++) G0[d][r] = G1[d][r] = Real(0);
-    // J_a(i_a, i_b, i_c) = Q jf_a C_a(i_a) M(i_b, i_c), C_a the running sum of
-    // the shape change along a, (b, c) the transverse axes
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-      const int b = a == 0 ? 1 : 0, e = a == 2 ? 1 : 2;
-      const Real f = Q * c.jf[a];
-      const Real* Ja = J + a * jplane;
-#pragma unroll
-      for (int s = 0; s < 4; s++)
-#pragma unroll
-        for (int t = 0; t < 4; t++) {
-          const int64_t ob = o + s * st[b] + t * st[e];
-          Real L[4], acc = 0;
-          L[3] = Real(0);
-#pragma unroll
-          for (int r = 2; r >= 0; r--) {
-            acc += Ja[ob + r * st[a]];
-            L[r] = acc;
-          }
-          const Real M = third * w[b].S0[s] * w[e].S0[t] + sixth * w[b].S0[s] * w[e].S1[t] +
-                         sixth * w[b].S1[s] * w[e].S0[t] + third * w[b].S1[s] * w[e].S1[t];
-          Real P = 0;
-#pragma unroll
-          for (int r = 0; r < 4; r++) {
-            const Real q = f * M * L[r];
-            G1[a][r] += q;
-            G0[a][r] -= q;
-            P += (w[a].S1[r] - w[a].S0[r]) * L[r];
-          }
-          P *= f;
-          G0[b][s] += P * (third * w[e].S0[t] + sixth * w[e].S1[t]);
-          G1[b][s] += P * (sixth * w[e].S0[t] + third * w[e].S1[t]);
-          G0[e][t] += P * (third * w[b].S0[s] + sixth * w[b].S1[s]);
-          G1[e][t] += P * (sixth * w[b].S0[s] + third * w[b].S1[s]);
-        }
-    }
-#pragma unroll
-    for (int d = 0; d < 3; d++)
-#pragma unroll
-      for (int r = 0; r < 4; r++) {
-        g0[d] += G0[d][r] * w[d].D0[r];
-        g1[d] += G1[d][r] * w[d].D1[r];
-      }
-    return true;
+  for (int d = 0; d < 3; d++) {
+    g0[d] = h0[0][d];
+    g1[d] = h1[0][d];
+    gv[d] = hv[0][d];
   }
+  return ok;
+}
+
+// Both bodies of an ion at once when all four positions (old and new of
+// each body) share the nearest node along every resolved axis: the
+// three-node windows coincide and the adjoint current is read once.
+template <typename Real, int ND>
+__device__ __forceinline__ bool deposit_adjoint_pair(const Real* J, int64_t jplane,
+                                                     const Where3& wh, const Real xa0[3],
+                                                     const Real xa1[3], const Real xb0[3],
+                                                     const Real xb1[3], Real Qa, Real Qb,
+                                                     const Real va[3], const Real vb[3],
+                                                     const PushConst<Real>& c, Real g0[2][3],
+                                                     Real g1[2][3], Real gv[2][3]) {
+  bool common = true;
+#pragma unroll
+  for (int d = 0; d < ND; d++) {
+    const Real n = floor(xa0[d] + Real(0.5));
+    common = common && floor(xa1[d] + Real(0.5)) == n && floor(xb0[d] + Real(0.5)) == n &&
+             floor(xb1[d] + Real(0.5)) == n;
+  }
+  if (!common) return false;
+  const Real* const a0[2] = {xa0, xb0};
+  const Real* const a1[2] = {xa1, xb1};
+  const Real* const av[2] = {va, vb};
+  const Real q[2] = {Qa, Qb};
+  return deposit_adjoint_w<Real, ND, 3, 2>(J, jplane, wh, a0, a1, q, av, c, g0, g1, gv);
 }
 
 // Wall reflection as in the forward cycle; returns true if it reflected.
@@ -773,7 +891,28 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const Planes<Real
       }
     }
     Real l_v1[3] = {0, 0, 0}, l_v2[3] = {0, 0, 0};
-    if (c.deposit) {
+    bool paired = false;
+    if (TWO && c.deposit) {
+      const Real Q1 = st.w ? c.q1 * W : c.qw1, Q2 = st.w ? c.q2 * W : c.qw2;
+      Real h0[2][3], h1[2][3], hv[2][3];
+      paired = deposit_adjoint_pair<Real, ND>(LJ, jplane, wh, x1, y1, x2, y2, Q1, Q2, v1, v2, c,
+                                              h0, h1, hv);
+      if (paired) {
+#pragma unroll
+        for (int d = 0; d < ND; d++) {
+          l_offn[d] += h1[0][d] + h1[1][d];
+          l_off[d] += h0[0][d] + h0[1][d];
+          l_dln[d] += c.idx[d] * (c.f1 * h1[0][d] - c.f2 * h1[1][d]);
+          l_dl[d] += c.idx[d] * (c.f1 * h0[0][d] - c.f2 * h0[1][d]);
+        }
+#pragma unroll
+        for (int q = ND; q < 3; q++) {
+          l_v1[q] += hv[0][q];
+          l_v2[q] += hv[1][q];
+        }
+      }
+    }
+    if (c.deposit && !paired) {
       const Real Q1 = st.w ? c.q1 * W : c.qw1;
       Real g0[3], g1[3], gv[3];
       if (deposit_adjoint<Real, ND>(LJ, jplane, wh, x1, y1, Q1, v1, c, g0, g1, gv)) {
