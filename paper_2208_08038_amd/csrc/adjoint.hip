@@ -158,6 +158,61 @@ __device__ __forceinline__ void gather_values(const Planes<Real>& f, const Where
   B[2] = interp_value<Real, ND>(f.B(2), w, t.h[0], t.h[1], t.n[2]);
 }
 
+// True when two bodies' stencils start at the same nodes for every stagger.
+template <typename Real, int ND>
+__device__ __forceinline__ bool same_nodes(const Stencil<Real>& a, const Stencil<Real>& b) {
+  bool same = true;
+#pragma unroll
+  for (int d = 0; d < ND; d++) same = same && a.n[d].i0 == b.n[d].i0 && a.h[d].i0 == b.h[d].i0;
+  return same;
+}
+
+// Two bodies whose stencils share the nodes: one pass over the nodes
+// interpolates both.
+template <typename Real, int ND>
+__device__ __forceinline__ void interp_value2(const Real* __restrict__ F, const Where3& w,
+                                              const Shape<Real>& ax, const Shape<Real>& ay,
+                                              const Shape<Real>& az, const Shape<Real>& bx,
+                                              const Shape<Real>& by, const Shape<Real>& bz,
+                                              Real& va, Real& vb) {
+  va = vb = Real(0);
+  constexpr int NY = ND > 1 ? 3 : 1, NZ = ND > 2 ? 3 : 1;
+#pragma unroll
+  for (int t = 0; t < NZ; t++) {
+    Real ya = 0, yb = 0;
+#pragma unroll
+    for (int s = 0; s < NY; s++) {
+      const Real* row = F + w.base + ax.i0 + (ND > 1 ? (int64_t)(ay.i0 + s) * w.sy : 0) +
+                        (ND > 2 ? (int64_t)(az.i0 + t) * w.sz : 0);
+      const Real r0 = row[0], r1 = row[1], r2 = row[2];
+      ya += (ND > 1 ? ay.w[s] : Real(1)) * (ax.w[0] * r0 + ax.w[1] * r1 + ax.w[2] * r2);
+      yb += (ND > 1 ? by.w[s] : Real(1)) * (bx.w[0] * r0 + bx.w[1] * r1 + bx.w[2] * r2);
+    }
+    va += (ND > 2 ? az.w[t] : Real(1)) * ya;
+    vb += (ND > 2 ? bz.w[t] : Real(1)) * yb;
+  }
+}
+
+// E and B at both body positions of an ion (shared node reads when their
+// stencils coincide).
+template <typename Real, int ND>
+__device__ __forceinline__ void gather_values2(const Planes<Real>& f, const Where3& w,
+                                               const Real x1[3], const Real x2[3], Real E1[3],
+                                               Real B1[3], Real E2[3], Real B2[3]) {
+  const Stencil<Real> a = stencil_at<Real, ND>(x1), b = stencil_at<Real, ND>(x2);
+  if (same_nodes<Real, ND>(a, b)) {
+    interp_value2<Real, ND>(f.E(0), w, a.h[0], a.n[1], a.n[2], b.h[0], b.n[1], b.n[2], E1[0], E2[0]);
+    interp_value2<Real, ND>(f.E(1), w, a.n[0], a.h[1], a.n[2], b.n[0], b.h[1], b.n[2], E1[1], E2[1]);
+    interp_value2<Real, ND>(f.E(2), w, a.n[0], a.n[1], a.h[2], b.n[0], b.n[1], b.h[2], E1[2], E2[2]);
+    interp_value2<Real, ND>(f.B(0), w, a.n[0], a.h[1], a.h[2], b.n[0], b.h[1], b.h[2], B1[0], B2[0]);
+    interp_value2<Real, ND>(f.B(1), w, a.h[0], a.n[1], a.h[2], b.h[0], b.n[1], b.h[2], B1[1], B2[1]);
+    interp_value2<Real, ND>(f.B(2), w, a.h[0], a.h[1], a.n[2], b.h[0], b.h[1], b.n[2], B1[2], B2[2]);
+  } else {
+    gather_values<Real, ND>(f, w, x1, E1, B1);
+    gather_values<Real, ND>(f, w, x2, E2, B2);
+  }
+}
+
 // Adjoint of one interpolated component for one body (or, with two shapes,
 // for both bodies of an ion whose stencils share the nodes), in one pass
 // over its nodes: scatter lam * weight(node) and add lam * d(interp)/dx
@@ -219,13 +274,6 @@ __device__ __forceinline__ void gather_adjoint(const Planes<Real>& f, const Sink
   comp_adjoint<Real, ND, PAIR>(f.B(2), 5, k, w, a.h[0], a.h[1], a.n[2], lBa[2], b.h[0], b.h[1], b.n[2], lBb[2], lxa, lxb);
 }
 
-template <typename Real, int ND>
-__device__ __forceinline__ bool same_nodes(const Stencil<Real>& a, const Stencil<Real>& b) {
-  bool same = true;
-#pragma unroll
-  for (int d = 0; d < ND; d++) same = same && a.n[d].i0 == b.n[d].i0 && a.h[d].i0 == b.h[d].i0;
-  return same;
-}
 
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
@@ -809,8 +857,10 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const Planes<Real
 
     // ---- forward recomputation
     Real G1[3], B1[3], G2[3] = {0, 0, 0}, B2[3] = {0, 0, 0};
-    gather_values<Real, ND>(f, wh, x1, G1, B1);
-    if (TWO) gather_values<Real, ND>(f, wh, x2, G2, B2);
+    if (TWO)
+      gather_values2<Real, ND>(f, wh, x1, x2, G1, B1, G2, B2);
+    else
+      gather_values<Real, ND>(f, wh, x1, G1, B1);
     Real E1[3], E2[3] = {0, 0, 0}, um1[3], um2[3] = {0, 0, 0};
     Real r2 = 0, rq = 1, soft = 1, kf = 0;
     if (TWO) {
