@@ -114,15 +114,55 @@ void grad_release(pic_ctx* c) {
 
 namespace {
 
-// Device-to-device copies between the live state and a snapshot.
+// The pieces of one snapshot copy, moved by one kernel launch: piece
+// blockIdx.y, 16-byte chunks over a grid-stride loop (a piece's size is a
+// multiple of 4 bytes; the last chunk may be shorter).
+constexpr int kMaxPieces = 48;
+struct CopyList {
+  const uint32_t* src[kMaxPieces];
+  uint32_t* dst[kMaxPieces];
+  int64_t words[kMaxPieces];
+  int n;
+};
+
+__global__ void __launch_bounds__(256) k_copy_list(CopyList L) {
+  const int k = blockIdx.y;
+  const uint32_t* src = L.src[k];
+  uint32_t* dst = L.dst[k];
+  const int64_t nw = L.words[k];
+  const int64_t nq = (nw + 3) / 4;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += stride) {
+    const int64_t w = 4 * q;
+    if (w + 4 <= nw) {
+      *reinterpret_cast<uint4*>(dst + w) = *reinterpret_cast<const uint4*>(src + w);
+    } else {
+      for (int64_t i = w; i < nw; i++) dst[i] = src[i];
+    }
+  }
+}
+
+// Device-to-device copies between the live state and a snapshot: one
+// kernel for every piece whose addresses are 16-byte aligned and size a
+// multiple of 4 bytes, hipMemcpyAsync for any other.
 int snap_copy(pic_ctx* c, void* buf, bool save) {
   const SnapLayout& L = c->grad->lay;
   char* b = static_cast<char*>(buf);
   const size_t rs = c->rsize;
+  CopyList list{};
   auto cp = [&](void* live, size_t at, size_t bytes) -> int {
     void* dst = save ? (void*)(b + at) : live;
     const void* src = save ? (const void*)live : (const void*)(b + at);
-    HIPCHK(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->stream));
+    const bool fits = list.n < kMaxPieces && bytes % 4 == 0 &&
+                      (reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) % 16 == 0;
+    if (fits) {
+      list.src[list.n] = static_cast<const uint32_t*>(src);
+      list.dst[list.n] = static_cast<uint32_t*>(dst);
+      list.words[list.n] = (int64_t)(bytes / 4);
+      list.n++;
+    } else {
+      HIPCHK(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->stream));
+    }
     return PIC_OK;
   };
   int rc;
@@ -147,6 +187,10 @@ int snap_copy(pic_ctx* c, void* buf, bool save) {
     if (c->g.periodic[d]) continue;
     for (int t = 0; t < 2; t++)
       if ((rc = cp(c->mur_b[d][t], L.mur[d][t], face_bytes(c, d)))) return rc;
+  }
+  if (list.n > 0) {
+    hipLaunchKernelGGL(k_copy_list, dim3(256, list.n), 256, 0, c->stream, list);
+    HIPCHK(c, hipGetLastError());
   }
   return PIC_OK;
 }
