@@ -33,8 +33,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "particle-steps/sec (push+gather+deposit) and % HBM roofline, FP32 vs FP64, 1 GPU"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "push_tiled_two_body_3d_fp32_traffic.json")
-ION_KERNEL = "k_push_tiled_f32<3, true, 4, 8, 8, 6>"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "push_tiled_pair_3d_fp32_traffic.json")
+PAIR_KERNEL = "k_push_tiled_f32<3, true, 2, 4, 8, 8, 6>"
+ION_KERNEL = "k_push_tiled_f32<3, true, 1, 4, 8, 8, 6>"
 
 
 
@@ -54,16 +55,18 @@ def algorithmic_bytes(n_particles, n_cells, two_body, rsize, per_particle_wc):
     return n_particles * per_particle + n_cells * per_cell, per_particle, per_cell
 
 
-def measured_traffic(bytes_key):
-    """HBM bytes per dispatch of the ion kernel from the committed rocprofv3
-    counter summary, if it was taken on the present kernel source; else None."""
+def measured_traffic(bytes_key, kernel):
+    """HBM bytes per dispatch of the shared ion + electron kernel from the
+    committed rocprofv3 counter summary, if it was taken on the present
+    kernel source and workload; else None."""
     from paper_2208_08038_amd.profile_summary import kernel_source_hash
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_hash") != kernel_source_hash() or t.get("workload") != bytes_key:
+    if (t.get("kernel_source_hash") != kernel_source_hash() or t.get("workload") != bytes_key
+            or t.get("kernel") != kernel):
         return None
     return t.get("bytes_per_launch")
 
@@ -122,7 +125,8 @@ def run_gpu(args, precision, keep_fields=False):
 
     n = tuple(args.cells)
     sim, _, sid_i, sid_e, t_load = ionised_slab_simulation(
-        n, args.ppc, precision, pic.TIMING, args.sort_every,
+        n, args.ppc, precision, pic.TIMING | (pic.SEPARATE_SPECIES if args.separate_species else 0),
+        args.sort_every,
         args.tile if precision == 32 else args.tile64, args.chunk_particles)
     n_ion, n_el = sim.count(sid_i), sim.count(sid_e)
     print(f"[bench] fp{precision}: loaded {n_ion} ions + {n_el} electrons in {t_load:.1f} s",
@@ -136,29 +140,35 @@ def run_gpu(args, precision, keep_fields=False):
     sim.step(args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    # one timed dispatch per tile colour, species and step
+    # one timed dispatch per tile colour and step: of the shared ion +
+    # electron launch (counted for the ions), or per species
     ms_i, l_i = sim.timing(species=sid_i, reset=False)
     ms_e, l_e = sim.timing(species=sid_e, reset=True)
+    shared = l_e == 0
     diag = sim.diagnostics(check=False)
     dt = t1 - t0
     ncell = n[0] * n[1] * n[2]
     rs = 4 if precision == 32 else 8
-    ncol = l_i // args.steps  # dispatches per species push
+    ncol = l_i // args.steps  # dispatches per step (tile colours)
     bytes_i, pp_i, pc = algorithmic_bytes(n_ion, ncell, True, rs, True)
     bytes_e, pp_e, _ = algorithmic_bytes(n_el, ncell, False, rs, False)
-    # the slab fills every colour's tiles alike: each dispatch moves 1/ncol
+    # the dominant launch: the shared one moves both species' state and the
+    # cells' fields once; separately, the ion launch.  The slab fills every
+    # colour's tiles alike: each dispatch moves 1/ncol
+    bytes_main = (bytes_i + bytes_e - ncell * pc) if shared else bytes_i
     avg_i = ms_i / max(l_i, 1) / 1e3
     avg_e = ms_e / max(l_e, 1) / 1e3
     res = {
         "precision": precision, "n_ion": n_ion, "n_el": n_el, "seconds": dt,
         "ms_per_step": 1e3 * dt / args.steps,
         "value": (n_ion + n_el) * args.steps / dt,
-        "dispatches_per_push": ncol,
-        "ion_push_ms": ms_i / args.steps, "electron_push_ms": ms_e / args.steps,
-        "ion_dispatch_ms": 1e3 * avg_i, "electron_dispatch_ms": 1e3 * avg_e,
-        "ion_kernel_gbs": bytes_i / ncol / avg_i / 1e9 if avg_i > 0 else None,
-        "electron_kernel_gbs": bytes_e / ncol / avg_e / 1e9 if avg_e > 0 else None,
-        "bytes_ion_dispatch": bytes_i / ncol, "bytes_per_ion": pp_i,
+        "dispatches_per_push": ncol, "shared_launch": shared,
+        "push_ms": (ms_i + ms_e) / args.steps,
+        "dispatch_ms": 1e3 * avg_i,
+        "kernel_gbs": bytes_main / ncol / avg_i / 1e9 if avg_i > 0 else None,
+        "electron_dispatch_ms": None if shared else 1e3 * avg_e,
+        "electron_kernel_gbs": None if shared or avg_e <= 0 else bytes_e / ncol / avg_e / 1e9,
+        "bytes_dispatch": bytes_main / ncol, "bytes_per_ion": pp_i,
         "bytes_per_electron": pp_e, "bytes_per_cell": pc, "load_seconds": t_load,
         "outside_tile_last_step": diag["n_outside_tile"],
         "error_word": diag["error_word"], "field_energy": diag["field_energy"],
@@ -274,6 +284,8 @@ def main():
                     help="cells per tile of the FP64 run (default: the library's, 8x8x8)")
     ap.add_argument("--chunk-particles", type=float, default=3.4e7)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 run")
+    ap.add_argument("--separate-species", action="store_true",
+                    help="one tiled launch per species instead of one shared launch per colour")
     ap.add_argument("--fp64-only", action="store_true",
                     help="only the FP64 run (one JSON object with its numbers)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -327,18 +339,21 @@ def main():
                     "after_steps": args.warmup + args.steps}
         del f32, f64
     key = f"ionised_slab_3d {args.cells} ppc={args.ppc} fp32"
-    traffic = measured_traffic(key)
-    achieved = r32["ion_kernel_gbs"]
+    kname = PAIR_KERNEL if r32["shared_launch"] else ION_KERNEL
+    traffic = measured_traffic(key, kname)
+    achieved = r32["kernel_gbs"]
     ncol = r32["dispatches_per_push"]
+    what = ("ions then electrons of each tile" if r32["shared_launch"] else "ions of each tile")
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS if achieved else None,
                 "traffic": traffic,
-                "kernel": f"{ION_KERNEL}: ion cycle (gather + bond + Boris + move + deposit), "
+                "kernel": f"{kname}: {what} (gather + bond + Boris + move + deposit), "
                           f"one of the {ncol} tile-colour dispatches of a step",
-                "launch_ms": r32["ion_dispatch_ms"],
-                "algorithmic_bytes_per_launch": r32["bytes_ion_dispatch"],
-                "limiter": "VALU issue: 77 % busy, ~1770 VALU instructions per ion "
-                           "(profiles/push_tiled_3d_fp32_ionised_slab_256x128x128_counters.txt)"}
+                "launch_ms": r32["dispatch_ms"],
+                "algorithmic_bytes_per_launch": r32["bytes_dispatch"],
+                "limiter": "VALU issue: 75 % busy, ~2810 VALU instructions per ion and "
+                           "electron (profiles/push_tiled_3d_fp32_ionised_slab_256x128x128_"
+                           "counters.txt)"}
     adj = None if args.no_adjoint else run_adjoint(args)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_seconds)
     out = {
@@ -355,16 +370,16 @@ def main():
                    "parallelism": "1 GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "kernels": {"ion_push_ms": r32["ion_push_ms"], "electron_push_ms": r32["electron_push_ms"],
-                    "ion_dispatch_ms": r32["ion_dispatch_ms"],
+        "kernels": {"shared_launch": r32["shared_launch"], "push_ms": r32["push_ms"],
+                    "dispatch_ms": r32["dispatch_ms"], "gbs": r32["kernel_gbs"],
                     "electron_dispatch_ms": r32["electron_dispatch_ms"],
-                    "ion_gbs": r32["ion_kernel_gbs"], "electron_gbs": r32["electron_kernel_gbs"],
+                    "electron_gbs": r32["electron_kernel_gbs"],
                     "outside_tile_last_step": r32["outside_tile_last_step"]},
         "fp64": None if r64 is None else {
             "value": r64["value"], "ms_per_step": r64["ms_per_step"],
-            "ion_push_ms": r64["ion_push_ms"], "electron_push_ms": r64["electron_push_ms"],
-            "ion_kernel_gbs": r64["ion_kernel_gbs"],
-            "frac": r64["ion_kernel_gbs"] / HBM_PEAK_GBS if r64["ion_kernel_gbs"] else None},
+            "shared_launch": r64["shared_launch"], "push_ms": r64["push_ms"],
+            "dispatch_ms": r64["dispatch_ms"], "kernel_gbs": r64["kernel_gbs"],
+            "frac": r64["kernel_gbs"] / HBM_PEAK_GBS if r64["kernel_gbs"] else None},
         "fp32_vs_fp64": fp32_err,
         "adjoint": adj,
         "error_word": r32["error_word"],

@@ -65,6 +65,9 @@ typedef enum {
 #define PIC_FLAG_TIMING 16u       /* time the particle kernels with HIP events */
 #define PIC_FLAG_GLOBAL_KERNEL 32u /* advance particles from HBM with global atomics
                                       instead of the LDS-tiled kernel */
+#define PIC_FLAG_SEPARATE_SPECIES 64u /* one tiled launch per species; by default a
+                                         two-body and a point species (the only two
+                                         species) share one launch per tile colour */
 
 /* species kinds */
 #define PIC_POINT 0
@@ -247,7 +250,10 @@ int pic_read_probes(pic_ctx* ctx, double* out, int64_t* nrecorded);
    with HIP events recorded on the context stream around each dispatch.
    With the tiled kernel a species takes 2^ndim dispatches per step (one
    per tile colour), each timed on its own; the small kernel that advances
-   particles found outside their tile is not included.  species_id =
+   particles found outside their tile is not included.  When a two-body
+   and a point species share one launch per colour (the default for such a
+   pair, see PIC_FLAG_SEPARATE_SPECIES), its dispatches count for the
+   two-body species and none for the point species.  species_id =
    PIC_TIMING_ADJOINT + s selects the adjoint particle kernel of species s
    in gradient runs (one dispatch per reverse step).  Synchronises. */
 #define PIC_TIMING_ADJOINT 65536

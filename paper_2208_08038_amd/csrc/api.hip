@@ -375,7 +375,35 @@ int advance_one(pic_ctx* c, const pic::LaserDev& las, const StepOpts& o,
   pic::launch_zero<Real>(f.J[0], 3 * g.plane, c->stream);
   if (check) deposit_rho<Real>(c, c->rho0);
   if (c->tiled) HIPCHK(c, hipMemsetAsync(c->nslow + 1, 0, 63 * sizeof(uint32_t), c->stream));
-  for (size_t si = 0; si < c->sp.size(); si++) {
+  // a two-body and a point species share one tiled launch per tile colour
+  // (one field staging and one current flush per tile for both)
+  int pi = -1, pe = -1;
+  if (c->tiled && c->sp.size() == 2 && !(c->cfg.flags & PIC_FLAG_SEPARATE_SPECIES)) {
+    for (int q = 0; q < 2; q++)
+      if (c->sp[q]->d.kind == PIC_TWO_BODY && c->sp[1 - q]->d.kind == PIC_POINT) {
+        pi = q;
+        pe = 1 - q;
+      }
+  }
+  if (pi >= 0) {
+    auto& si = c->sp[pi];
+    auto& se = c->sp[pe];
+    pic::PushConst<Real> ci = push_const<Real>(c, *si), ce = push_const<Real>(c, *se);
+    ci.jscale = ce.jscale = std::min(ci.jscale, ce.jscale);  // one patch scale
+    TimedDispatch td{c, pi, false};
+    pic::DispatchHook hook;
+    if (c->cfg.flags & PIC_FLAG_TIMING) hook = {&TimedDispatch::hook, &td};
+    hipError_t e = pic::launch_push_tiled_pair<Real>(
+        g, f, species_dev<Real>(*si), ci, si->sort.tile_off, si->outside, species_dev<Real>(*se),
+        ce, se->sort.tile_off, se->outside, c->tg, c->nslow, c->nslow + 2 + pi,
+        c->nslow + 2 + pe, c->err, c->stream, hook);
+    if (e != hipSuccess)
+      return fail(c, PIC_EHIP, std::string("tiled particle kernel: ") + hipGetErrorString(e));
+    c->launches++;
+    si->steps_since_sort++;
+    se->steps_since_sort++;
+  }
+  for (size_t si = 0; si < c->sp.size() && pi < 0; si++) {
     auto& s = c->sp[si];
     TimedDispatch td{c, (int)si, false};
     if (c->tiled) {

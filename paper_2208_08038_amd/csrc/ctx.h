@@ -59,7 +59,7 @@ struct pic_ctx {
   void* mur_e[3][2] = {};
   uint32_t* err = nullptr;
   uint32_t* load_err = nullptr;
-  uint32_t* nslow = nullptr;   // [0]: list length scratch, [2 + s]: species s listed this step
+  uint32_t* nslow = nullptr;   // [0], [1]: list length scratch, [2 + s]: species s listed this step
   uint32_t* host_counts = nullptr;  // pinned: 2 slots of the per-species counts
   hipEvent_t ev_counts[2] = {nullptr, nullptr};
   int counts_pending = -1;          // slot whose copy is in flight, or -1

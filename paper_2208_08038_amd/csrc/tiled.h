@@ -90,4 +90,20 @@ hipError_t launch_push_tiled(const GridInfo& g, const FieldPtrs<Real>& f, const 
                              uint32_t* list, uint32_t* nlist, uint32_t* nlist_total,
                              uint32_t* err, hipStream_t st, DispatchHook hook = {});
 
+// A two-body species (i) and a point species (e) in one launch per tile
+// colour: each workgroup advances both species' particles of its tile out
+// of one LDS copy of the fields into one current patch (ci and ce must
+// carry the same fixed-point scale), then the outside-tile kernel of each
+// species.  nlist holds two scratch counters; total_i, total_e accumulate
+// the listed counts.  `hook` brackets each shared colour dispatch.
+template <typename Real>
+hipError_t launch_push_tiled_pair(const GridInfo& g, const FieldPtrs<Real>& f,
+                                  const SpeciesDev<Real>& si, const PushConst<Real>& ci,
+                                  const uint32_t* tile_off_i, uint32_t* list_i,
+                                  const SpeciesDev<Real>& se, const PushConst<Real>& ce,
+                                  const uint32_t* tile_off_e, uint32_t* list_e,
+                                  const TileGeom& t, uint32_t* nlist, uint32_t* total_i,
+                                  uint32_t* total_e, uint32_t* err, hipStream_t st,
+                                  DispatchHook hook = {});
+
 }  // namespace pic

@@ -75,26 +75,110 @@ struct LdsQueue {
   }
 };
 
+// One species' share of a tiled launch: its particles, constants, tile
+// offsets of its sorted order and its list of particles found outside
+// their tile (with the list's counter).
+template <typename Real>
+struct TileSpecies {
+  SpeciesDev<Real> s;
+  PushConst<Real> c;
+  const uint32_t* tile_off;
+  uint32_t* list;
+  uint32_t* nlist;
+};
+
+// 3. the particles [p0, p1) of one species in the tile; the state of a
+//    thread's next particle is loaded while it advances the present one
+//    (PREFETCH; costs the registers of one more state).  Beyond kChunk
+//    particles (a tile far more crowded than the mean) the rest is listed
+//    like particles outside the tile, which bounds the number of terms per
+//    patch node.
+template <typename Real, int ND, bool TWO, bool PREFETCH>
+__device__ __forceinline__ void tile_particles(const GridInfo& g, const TileSpecies<Real>& sp,
+                                               int64_t p0, int64_t p1, const int lo[3],
+                                               const int hi[3], const FieldPtrs<Real>& fl,
+                                               int fsy, int fsz, PatchOf<Real>* const jl[3],
+                                               int jsy, int jsz, const LdsQueue<Real, ND>& queue,
+                                               uint32_t* err) {
+  using PatchT = PatchOf<Real>;
+  const SpeciesDev<Real>& s = sp.s;
+  const PushConst<Real>& c = sp.c;
+  uint32_t* list = sp.list;
+  uint32_t* nlist = sp.nlist;
+  const int lane = threadIdx.x & 63;
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const int64_t pk = p0 + kChunk;
+  PState<Real> next;
+  if (PREFETCH && p0 + threadIdx.x < p1) load_state<Real, ND, TWO>(s, c, p0 + threadIdx.x, next);
+  for (int64_t p0w = p0; p0w < p1; p0w += blockDim.x) {
+    const int64_t p = p0w + threadIdx.x;
+    const bool valid = p < p1;
+    PState<Real> st;
+    if (PREFETCH) {
+      st = next;
+      if (p + blockDim.x < p1) load_state<Real, ND, TWO>(s, c, p + blockDim.x, next);
+    } else if (valid) {
+      load_state<Real, ND, TWO>(s, c, p, st);
+    }
+    int ci[3] = {0, 0, 0};
+    bool inside = false;
+    if (valid) {
+      decode_cell<ND>(g, st.cell, ci);
+      inside = p < pk;
+#pragma unroll
+      for (int d = 0; d < ND; d++) inside = inside && ci[d] >= lo[d] && ci[d] < hi[d];
+    }
+    // list the particles outside the tile: one atomic per wavefront
+    const bool out = valid && !inside;
+    const uint64_t m = __ballot(out);
+    if (m) {
+      uint32_t basei = 0;
+      const int leader = __ffsll((unsigned long long)m) - 1;
+      if (lane == leader) basei = atomicAdd(nlist, (uint32_t)__popcll(m));
+      basei = __shfl(basei, leader);
+      if (out) list[basei + (uint32_t)__popcll(m & below)] = (uint32_t)p;
+    }
+    if (valid && inside) {
+      int lf = (ci[0] - lo[0] + 2);
+      int lj = lf;
+      if (ND > 1) {
+        lf += (ci[1] - lo[1] + 2) * fsy;
+        lj += (ci[1] - lo[1] + 2) * jsy;
+      }
+      if (ND > 2) {
+        lf += (ci[2] - lo[2] + 2) * fsz;
+        lj += (ci[2] - lo[2] + 2) * jsz;
+      }
+      advance_particle<Real, ND, TWO, false, PatchT>(g, s, c, p, st, ci, fl, lf, fsy, fsz, jl,
+                                                     lj, jsy, jsz, err, queue);
+    }
+  }
+}
+
 // TX, TY, TZ > 0 fix the tile shape at compile time (patch strides become
 // constants, so LDS addresses fold into instruction offsets); 0 takes the
-// shape from `t`.
-template <typename Real, int ND, bool TWO, bool PREFETCH, int TX, int TY, int TZ>
+// shape from `t`.  NS = 1: species `a` (two-body if TWO) alone.  NS = 2: a
+// two-body species `a` and then a point species `b` share the tile's
+// staged fields and current patch (one staging and one flush for both);
+// both species' constants carry the same fixed-point scale.
+template <typename Real, int ND, bool TWO, int NS, int WPE, int TX, int TY, int TZ>
 __device__ __forceinline__ void tiled_body(const GridInfo& g, const FieldPtrs<Real>& f,
-                                           const SpeciesDev<Real>& s, const PushConst<Real>& c,
-                                           const TileGeom& t, const uint32_t* tile_off, int color,
-                                           uint32_t* list, uint32_t* nlist, uint32_t* err) {
+                                           const TileSpecies<Real>& a, const TileSpecies<Real>& b,
+                                           const TileGeom& t, int color, uint32_t* err) {
+  static_assert(NS == 1 || TWO, "a shared launch pairs a two-body with a point species");
   using PatchT = PatchOf<Real>;
+  const PushConst<Real>& c = a.c;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   // tile of this block within the colour
-  int b = blockIdx.x;
+  int bi = blockIdx.x;
   int tc[3] = {0, 0, 0};
-  tc[0] = 2 * (b % t.nc[0]) + (color & 1);
-  b /= t.nc[0];
+  tc[0] = 2 * (bi % t.nc[0]) + (color & 1);
+  bi /= t.nc[0];
   if (ND > 1) {
-    tc[1] = 2 * (b % t.nc[1]) + ((color >> 1) & 1);
-    b /= t.nc[1];
+    tc[1] = 2 * (bi % t.nc[1]) + ((color >> 1) & 1);
+    bi /= t.nc[1];
   }
-  if (ND > 2) tc[2] = 2 * b + ((color >> 2) & 1);
+  if (ND > 2) tc[2] = 2 * bi + ((color >> 2) & 1);
   for (int d = 0; d < ND; d++)
     if (tc[d] >= t.nt[d]) return;  // whole block leaves before any barrier
   const int TT[3] = {TX ? TX : t.T[0], TY ? TY : t.T[1], TZ ? TZ : t.T[2]};
@@ -104,7 +188,6 @@ __device__ __forceinline__ void tiled_body(const GridInfo& g, const FieldPtrs<Re
     hi[d] = min(lo[d] + TT[d], g.n[d]);
   }
   const int64_t tile = tc[0] + (int64_t)t.nt[0] * (tc[1] + (int64_t)t.nt[1] * tc[2]);
-  const int64_t p0 = tile_off[tile], p1 = tile_off[tile + 1];
 
   // LDS layout: the FP64 current patch first (8-byte aligned), then the
   // field pairs, then the deposit queue
@@ -161,60 +244,17 @@ __device__ __forceinline__ void tiled_body(const GridInfo& g, const FieldPtrs<Re
   if (threadIdx.x == 0) *queue.count = 0u;
   __syncthreads();
 
-  // 3. particles of the tile; the state of a thread's next particle is
-  //    loaded while it advances the present one (PREFETCH; costs the
-  //    registers of one more state).  Beyond kChunk particles (a tile far
-  //    more crowded than the mean) the rest is listed like particles
-  //    outside the tile, which bounds the number of terms per patch node.
   const int fsy = L.fpitch, fsz = L.fplane;
   const int jsy = L.jpitch, jsz = L.jplane;
-  const int lane = threadIdx.x & 63;
-  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  const int64_t pk = p0 + kChunk;
-  PState<Real> next;
-  if (PREFETCH && p0 + threadIdx.x < p1) load_state<Real, ND, TWO>(s, c, p0 + threadIdx.x, next);
-  for (int64_t p0w = p0; p0w < p1; p0w += blockDim.x) {
-    const int64_t p = p0w + threadIdx.x;
-    const bool valid = p < p1;
-    PState<Real> st;
-    if (PREFETCH) {
-      st = next;
-      if (p + blockDim.x < p1) load_state<Real, ND, TWO>(s, c, p + blockDim.x, next);
-    } else if (valid) {
-      load_state<Real, ND, TWO>(s, c, p, st);
-    }
-    int ci[3] = {0, 0, 0};
-    bool inside = false;
-    if (valid) {
-      decode_cell<ND>(g, st.cell, ci);
-      inside = p < pk;
-#pragma unroll
-      for (int d = 0; d < ND; d++) inside = inside && ci[d] >= lo[d] && ci[d] < hi[d];
-    }
-    // list the particles outside the tile: one atomic per wavefront
-    const bool out = valid && !inside;
-    const uint64_t m = __ballot(out);
-    if (m) {
-      uint32_t basei = 0;
-      const int leader = __ffsll((unsigned long long)m) - 1;
-      if (lane == leader) basei = atomicAdd(nlist, (uint32_t)__popcll(m));
-      basei = __shfl(basei, leader);
-      if (out) list[basei + (uint32_t)__popcll(m & below)] = (uint32_t)p;
-    }
-    if (valid && inside) {
-      int lf = (ci[0] - lo[0] + 2);
-      int lj = lf;
-      if (ND > 1) {
-        lf += (ci[1] - lo[1] + 2) * fsy;
-        lj += (ci[1] - lo[1] + 2) * jsy;
-      }
-      if (ND > 2) {
-        lf += (ci[2] - lo[2] + 2) * fsz;
-        lj += (ci[2] - lo[2] + 2) * jsz;
-      }
-      advance_particle<Real, ND, TWO, false, PatchT>(g, s, c, p, st, ci, fl, lf, fsy, fsz, jl,
-                                                     lj, jsy, jsz, err, queue);
-    }
+  constexpr bool PREFETCH_A = WPE < 4 || !TWO;
+  if constexpr (NS == 1) {
+    tile_particles<Real, ND, TWO, PREFETCH_A>(g, a, a.tile_off[tile], a.tile_off[tile + 1], lo,
+                                              hi, fl, fsy, fsz, jl, jsy, jsz, queue, err);
+  } else {
+    tile_particles<Real, ND, true, PREFETCH_A>(g, a, a.tile_off[tile], a.tile_off[tile + 1], lo,
+                                               hi, fl, fsy, fsz, jl, jsy, jsz, queue, err);
+    tile_particles<Real, ND, false, true>(g, b, b.tile_off[tile], b.tile_off[tile + 1], lo, hi,
+                                          fl, fsy, fsz, jl, jsy, jsz, queue, err);
   }
   __syncthreads();
 
@@ -258,22 +298,18 @@ __device__ __forceinline__ void tiled_body(const GridInfo& g, const FieldPtrs<Re
 // (one workgroup of 8 waves per CU: each wave may use up to 256 VGPRs);
 // an 8x8x6 tile takes under 80 KB, so two workgroups fit when each wave
 // keeps to 128 VGPRs (WPE = 4 waves per SIMD).
-template <int ND, bool TWO, int WPE, int TX, int TY, int TZ>
+template <int ND, bool TWO, int NS, int WPE, int TX, int TY, int TZ>
 __global__ void __launch_bounds__(kTiledThreads) __attribute__((amdgpu_waves_per_eu(WPE)))
-k_push_tiled_f32(GridInfo g, FieldPtrs<float> f, SpeciesDev<float> s, PushConst<float> c,
-                 TileGeom t, const uint32_t* tile_off, int color, uint32_t* list,
-                 uint32_t* nlist, uint32_t* err) {
-  tiled_body<float, ND, TWO, (WPE < 4 || !TWO), TX, TY, TZ>(g, f, s, c, t, tile_off, color, list,
-                                                            nlist, err);
+k_push_tiled_f32(GridInfo g, FieldPtrs<float> f, TileSpecies<float> a, TileSpecies<float> b,
+                 TileGeom t, int color, uint32_t* err) {
+  tiled_body<float, ND, TWO, NS, WPE, TX, TY, TZ>(g, f, a, b, t, color, err);
 }
 
-template <int ND, bool TWO, int WPE, int TX, int TY, int TZ>
+template <int ND, bool TWO, int NS, int WPE, int TX, int TY, int TZ>
 __global__ void __launch_bounds__(kTiledThreads) __attribute__((amdgpu_waves_per_eu(WPE)))
-k_push_tiled_f64(GridInfo g, FieldPtrs<double> f, SpeciesDev<double> s, PushConst<double> c,
-                 TileGeom t, const uint32_t* tile_off, int color, uint32_t* list,
-                 uint32_t* nlist, uint32_t* err) {
-  tiled_body<double, ND, TWO, (WPE < 4 || !TWO), TX, TY, TZ>(g, f, s, c, t, tile_off, color, list,
-                                                             nlist, err);
+k_push_tiled_f64(GridInfo g, FieldPtrs<double> f, TileSpecies<double> a, TileSpecies<double> b,
+                 TileGeom t, int color, uint32_t* err) {
+  tiled_body<double, ND, TWO, NS, WPE, TX, TY, TZ>(g, f, a, b, t, color, err);
 }
 
 }  // namespace
@@ -315,48 +351,46 @@ bool tiled_supported(const GridInfo& g, const TileGeom& t, size_t rsize) {
   return tiled_lds_bytes(t, rsize) <= kTiledMaxLds;
 }
 
-template <typename Real, int ND, bool TWO, int WPE, int TX, int TY, int TZ>
+template <typename Real, int ND, bool TWO, int NS, int WPE, int TX, int TY, int TZ>
 static const void* tiled_kernel() {
   if constexpr (sizeof(Real) == 4)
-    return (const void*)k_push_tiled_f32<ND, TWO, WPE, TX, TY, TZ>;
+    return (const void*)k_push_tiled_f32<ND, TWO, NS, WPE, TX, TY, TZ>;
   else
-    return (const void*)k_push_tiled_f64<ND, TWO, WPE, TX, TY, TZ>;
+    return (const void*)k_push_tiled_f64<ND, TWO, NS, WPE, TX, TY, TZ>;
 }
 
-template <typename Real, int ND, bool TWO, int WPE, int TX, int TY, int TZ>
+template <typename Real, int ND, bool TWO, int NS, int WPE, int TX, int TY, int TZ>
 static hipError_t launch_colour_wpe(const GridInfo& g, const FieldPtrs<Real>& f,
-                                    const SpeciesDev<Real>& s, const PushConst<Real>& c,
-                                    const TileGeom& t, const uint32_t* tile_off, int color,
-                                    uint32_t* list, uint32_t* nlist, uint32_t* err, size_t lds,
+                                    const TileSpecies<Real>& a, const TileSpecies<Real>& b,
+                                    const TileGeom& t, int color, uint32_t* err, size_t lds,
                                     hipStream_t st) {
   static size_t attr_lds = 0;
   if (lds > 64 * 1024 && lds > attr_lds) {
-    hipError_t e = hipFuncSetAttribute(tiled_kernel<Real, ND, TWO, WPE, TX, TY, TZ>(),
+    hipError_t e = hipFuncSetAttribute(tiled_kernel<Real, ND, TWO, NS, WPE, TX, TY, TZ>(),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     attr_lds = lds;
   }
   unsigned blocks = (unsigned)((int64_t)t.nc[0] * t.nc[1] * t.nc[2]);
   if constexpr (sizeof(Real) == 4)
-    hipLaunchKernelGGL((k_push_tiled_f32<ND, TWO, WPE, TX, TY, TZ>), dim3(blocks),
-                       dim3(kTiledThreads), lds, st, g, f, s, c, t, tile_off, color, list, nlist,
-                       err);
+    hipLaunchKernelGGL((k_push_tiled_f32<ND, TWO, NS, WPE, TX, TY, TZ>), dim3(blocks),
+                       dim3(kTiledThreads), lds, st, g, f, a, b, t, color, err);
   else
-    hipLaunchKernelGGL((k_push_tiled_f64<ND, TWO, WPE, TX, TY, TZ>), dim3(blocks),
-                       dim3(kTiledThreads), lds, st, g, f, s, c, t, tile_off, color, list, nlist,
-                       err);
+    hipLaunchKernelGGL((k_push_tiled_f64<ND, TWO, NS, WPE, TX, TY, TZ>), dim3(blocks),
+                       dim3(kTiledThreads), lds, st, g, f, a, b, t, color, err);
   return hipGetLastError();
 }
 
 // True if the 4-waves-per-SIMD build of the kernel keeps everything in
 // registers (no scratch).
-template <typename Real, int ND, bool TWO, int TX, int TY, int TZ>
+template <typename Real, int ND, bool TWO, int NS, int TX, int TY, int TZ>
 static bool wpe4_without_spill() {
   static int ok = -1;
   if (ok < 0) {
-    hipFuncAttributes a{};
-    ok = hipFuncGetAttributes(&a, tiled_kernel<Real, ND, TWO, 4, TX, TY, TZ>()) == hipSuccess &&
-                 a.localSizeBytes == 0
+    hipFuncAttributes fa{};
+    ok = hipFuncGetAttributes(&fa, tiled_kernel<Real, ND, TWO, NS, 4, TX, TY, TZ>()) ==
+                     hipSuccess &&
+                 fa.localSizeBytes == 0
              ? 1
              : 0;
   }
@@ -365,35 +399,61 @@ static bool wpe4_without_spill() {
 
 // two workgroups per CU when their LDS fits and the smaller register
 // budget needs no spills, else one with the larger register budget
-template <typename Real, int ND, bool TWO, int TX, int TY, int TZ>
+template <typename Real, int ND, bool TWO, int NS, int TX, int TY, int TZ>
 static hipError_t launch_colour_shape(const GridInfo& g, const FieldPtrs<Real>& f,
-                                      const SpeciesDev<Real>& s, const PushConst<Real>& c,
-                                      const TileGeom& t, const uint32_t* tile_off, int color,
-                                      uint32_t* list, uint32_t* nlist, uint32_t* err, size_t lds,
+                                      const TileSpecies<Real>& a, const TileSpecies<Real>& b,
+                                      const TileGeom& t, int color, uint32_t* err, size_t lds,
                                       hipStream_t st) {
-  if (2 * lds <= kTiledMaxLds && wpe4_without_spill<Real, ND, TWO, TX, TY, TZ>())
-    return launch_colour_wpe<Real, ND, TWO, 4, TX, TY, TZ>(g, f, s, c, t, tile_off, color, list,
-                                                           nlist, err, lds, st);
-  return launch_colour_wpe<Real, ND, TWO, 2, TX, TY, TZ>(g, f, s, c, t, tile_off, color, list,
-                                                         nlist, err, lds, st);
+  if (2 * lds <= kTiledMaxLds && wpe4_without_spill<Real, ND, TWO, NS, TX, TY, TZ>())
+    return launch_colour_wpe<Real, ND, TWO, NS, 4, TX, TY, TZ>(g, f, a, b, t, color, err, lds, st);
+  return launch_colour_wpe<Real, ND, TWO, NS, 2, TX, TY, TZ>(g, f, a, b, t, color, err, lds, st);
 }
 
 // the default 3D tiles (8x8x6 for FP32, 8x8x8 for FP64) have builds with
 // compile-time strides; any other shape runs the generic build
-template <typename Real, int ND, bool TWO>
+template <typename Real, int ND, bool TWO, int NS>
 static hipError_t launch_colour(const GridInfo& g, const FieldPtrs<Real>& f,
-                                const SpeciesDev<Real>& s, const PushConst<Real>& c,
-                                const TileGeom& t, const uint32_t* tile_off, int color,
-                                uint32_t* list, uint32_t* nlist, uint32_t* err, size_t lds,
+                                const TileSpecies<Real>& a, const TileSpecies<Real>& b,
+                                const TileGeom& t, int color, uint32_t* err, size_t lds,
                                 hipStream_t st) {
   if constexpr (ND == 3) {
     constexpr int TZ = sizeof(Real) == 4 ? 6 : 8;
     if (t.T[0] == 8 && t.T[1] == 8 && t.T[2] == TZ)
-      return launch_colour_shape<Real, ND, TWO, 8, 8, TZ>(g, f, s, c, t, tile_off, color, list,
-                                                          nlist, err, lds, st);
+      return launch_colour_shape<Real, ND, TWO, NS, 8, 8, TZ>(g, f, a, b, t, color, err, lds, st);
   }
-  return launch_colour_shape<Real, ND, TWO, 0, 0, 0>(g, f, s, c, t, tile_off, color, list, nlist,
-                                                     err, lds, st);
+  return launch_colour_shape<Real, ND, TWO, NS, 0, 0, 0>(g, f, a, b, t, color, err, lds, st);
+}
+
+template <typename Real, int NS>
+static hipError_t launch_colours(const GridInfo& g, const FieldPtrs<Real>& f,
+                                 const TileSpecies<Real>& a, const TileSpecies<Real>& b,
+                                 const TileGeom& t, uint32_t* err, hipStream_t st,
+                                 DispatchHook hook) {
+  const size_t lds = tiled_lds_bytes(t, sizeof(Real));
+  const bool two = NS == 2 || a.c.two_body;
+  hipError_t e = hipSuccess;
+  for (int color = 0; color < (1 << g.nd); color++) {
+    if (hook.fn) hook.fn(hook.arg, true);
+    if (two) {
+      if (g.nd == 1) e = launch_colour<Real, 1, true, NS>(g, f, a, b, t, color, err, lds, st);
+      if (g.nd == 2) e = launch_colour<Real, 2, true, NS>(g, f, a, b, t, color, err, lds, st);
+      if (g.nd == 3) e = launch_colour<Real, 3, true, NS>(g, f, a, b, t, color, err, lds, st);
+    } else if constexpr (NS == 1) {
+      if (g.nd == 1) e = launch_colour<Real, 1, false, 1>(g, f, a, b, t, color, err, lds, st);
+      if (g.nd == 2) e = launch_colour<Real, 2, false, 1>(g, f, a, b, t, color, err, lds, st);
+      if (g.nd == 3) e = launch_colour<Real, 3, false, 1>(g, f, a, b, t, color, err, lds, st);
+    }
+    if (e != hipSuccess) return e;
+    if (hook.fn) hook.fn(hook.arg, false);
+  }
+  return hipSuccess;
+}
+
+template <typename Real>
+static TileSpecies<Real> tile_species(const SpeciesDev<Real>& s, const PushConst<Real>& c,
+                                      const uint32_t* tile_off, uint32_t* list,
+                                      uint32_t* nlist) {
+  return TileSpecies<Real>{s, c, tile_off, list, nlist};
 }
 
 template <typename Real>
@@ -402,25 +462,32 @@ hipError_t launch_push_tiled(const GridInfo& g, const FieldPtrs<Real>& f, const 
                              uint32_t* list, uint32_t* nlist, uint32_t* nlist_total,
                              uint32_t* err, hipStream_t st, DispatchHook hook) {
   if (s.n == 0) return hipSuccess;
-  size_t lds = tiled_lds_bytes(t, sizeof(Real));
   hipError_t e = hipMemsetAsync(nlist, 0, sizeof(uint32_t), st);
   if (e != hipSuccess) return e;
-  int ncol = 1 << g.nd;
-  for (int color = 0; color < ncol; color++) {
-    if (hook.fn) hook.fn(hook.arg, true);
-    if (c.two_body) {
-      if (g.nd == 1) e = launch_colour<Real, 1, true>(g, f, s, c, t, tile_off, color, list, nlist, err, lds, st);
-      if (g.nd == 2) e = launch_colour<Real, 2, true>(g, f, s, c, t, tile_off, color, list, nlist, err, lds, st);
-      if (g.nd == 3) e = launch_colour<Real, 3, true>(g, f, s, c, t, tile_off, color, list, nlist, err, lds, st);
-    } else {
-      if (g.nd == 1) e = launch_colour<Real, 1, false>(g, f, s, c, t, tile_off, color, list, nlist, err, lds, st);
-      if (g.nd == 2) e = launch_colour<Real, 2, false>(g, f, s, c, t, tile_off, color, list, nlist, err, lds, st);
-      if (g.nd == 3) e = launch_colour<Real, 3, false>(g, f, s, c, t, tile_off, color, list, nlist, err, lds, st);
-    }
-    if (e != hipSuccess) return e;
-    if (hook.fn) hook.fn(hook.arg, false);
-  }
+  const TileSpecies<Real> a = tile_species(s, c, tile_off, list, nlist);
+  e = launch_colours<Real, 1>(g, f, a, a, t, err, st, hook);
+  if (e != hipSuccess) return e;
   launch_push_list<Real>(g, f, s, c, list, nlist, nlist_total, err, st);
+  return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_push_tiled_pair(const GridInfo& g, const FieldPtrs<Real>& f,
+                                  const SpeciesDev<Real>& si, const PushConst<Real>& ci,
+                                  const uint32_t* tile_off_i, uint32_t* list_i,
+                                  const SpeciesDev<Real>& se, const PushConst<Real>& ce,
+                                  const uint32_t* tile_off_e, uint32_t* list_e,
+                                  const TileGeom& t, uint32_t* nlist, uint32_t* total_i,
+                                  uint32_t* total_e, uint32_t* err, hipStream_t st,
+                                  DispatchHook hook) {
+  hipError_t e = hipMemsetAsync(nlist, 0, 2 * sizeof(uint32_t), st);
+  if (e != hipSuccess) return e;
+  const TileSpecies<Real> a = tile_species(si, ci, tile_off_i, list_i, nlist);
+  const TileSpecies<Real> b = tile_species(se, ce, tile_off_e, list_e, nlist + 1);
+  e = launch_colours<Real, 2>(g, f, a, b, t, err, st, hook);
+  if (e != hipSuccess) return e;
+  if (si.n > 0) launch_push_list<Real>(g, f, si, ci, list_i, nlist, total_i, err, st);
+  if (se.n > 0) launch_push_list<Real>(g, f, se, ce, list_e, nlist + 1, total_e, err, st);
   return hipGetLastError();
 }
 
@@ -434,5 +501,15 @@ template hipError_t launch_push_tiled<double>(const GridInfo&, const FieldPtrs<d
                                               const TileGeom&, const uint32_t*, uint32_t*,
                                               uint32_t*, uint32_t*, uint32_t*, hipStream_t,
                                              DispatchHook);
+template hipError_t launch_push_tiled_pair<float>(
+    const GridInfo&, const FieldPtrs<float>&, const SpeciesDev<float>&, const PushConst<float>&,
+    const uint32_t*, uint32_t*, const SpeciesDev<float>&, const PushConst<float>&,
+    const uint32_t*, uint32_t*, const TileGeom&, uint32_t*, uint32_t*, uint32_t*, uint32_t*,
+    hipStream_t, DispatchHook);
+template hipError_t launch_push_tiled_pair<double>(
+    const GridInfo&, const FieldPtrs<double>&, const SpeciesDev<double>&,
+    const PushConst<double>&, const uint32_t*, uint32_t*, const SpeciesDev<double>&,
+    const PushConst<double>&, const uint32_t*, uint32_t*, const TileGeom&, uint32_t*, uint32_t*,
+    uint32_t*, uint32_t*, hipStream_t, DispatchHook);
 
 }  // namespace pic

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libpic.so")
 
 PIC_OK, PIC_EINVAL, PIC_ENOMEM, PIC_EHIP, PIC_ESTATE, PIC_ERANGE, PIC_ENAN = 0, -1, -2, -3, -4, -5, -6
 FROZEN_FIELDS, NO_DEPOSIT, CHARGE_CHECK, TRACK_IDS, TIMING, GLOBAL_KERNEL = 1, 2, 4, 8, 16, 32
+SEPARATE_SPECIES = 64
 TIMING_ADJOINT = 65536  # pic_timing tag offset of the adjoint particle kernel
 ERR_NAN, ERR_RANGE = 1, 2
 

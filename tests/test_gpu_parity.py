@@ -467,8 +467,16 @@ def test_device_error_word(pic):
 def test_timing_events(pic):
     _say("case: timing")
     wl = random_workload(3, 1000, 1000, seed=80)
-    # tiled kernel: one timed dispatch per tile colour (2^3), species and step
+    # tiled kernel, ions and electrons in one launch per tile colour (2^3)
+    # and step, counted for the two-body species
     s = pic.Simulation.from_workload(wl, precision=32, flags=pic.TIMING)
+    s.step(3)
+    ms0, n0 = s.timing(species=0, reset=False)
+    ms1, n1 = s.timing(species=1, reset=False)
+    ms, n = s.timing()
+    assert n0 == 3 * 8 and n1 == 0 and n == n0 and ms == ms0 > 0
+    # one launch per species: one timed dispatch per colour, species and step
+    s = pic.Simulation.from_workload(wl, precision=32, flags=pic.TIMING | pic.SEPARATE_SPECIES)
     s.step(3)
     ms0, n0 = s.timing(species=0, reset=False)
     ms, n = s.timing()
@@ -583,6 +591,39 @@ def test_fp32_current_patch_fixed_point(pic):
     Eo, Bo, Jo = o.fields()
     Eg, Bg, Jg = s.fields()
     assert rel_l2(Eg, Eo) < 2e-5 and rel_l2(Jg, Jo) < 2e-5
+
+
+@pytest.mark.parametrize("precision,tol", [(64, 1e-13), (32, 1e-6)])
+def test_shared_launch_matches_separate(pic, precision, tol):
+    """Ions and electrons advanced in one launch per tile colour (the
+    default for a two-body and a point species) against one launch per
+    species (PIC_FLAG_SEPARATE_SPECIES): the same fields and particles up
+    to the order of the FP64 patch sums, or, for FP32 work, the fixed-point
+    quantum of the shared patch scale (which moves a few FP32 results by an
+    ulp); 3D and 2D, with particles leaving their tiles (fast electrons, no
+    sort for 4 steps)."""
+    for ndim in (3, 2):
+        _say(f"case: shared launch {ndim}d fp{precision}")
+        wl = random_workload(ndim, 1500, 1500, seed=113 + ndim, vmax_el=0.95)
+        out = []
+        for flags in (pic.TRACK_IDS, pic.TRACK_IDS | pic.SEPARATE_SPECIES):
+            s = pic.Simulation.from_workload(wl, precision=precision, flags=flags, sort_every=1000)
+            s.step(4)
+            d = s.diagnostics()
+            assert d["error_word"] == 0
+            out.append((s.fields(), [s.particles(k, ids=True) for k in range(2)],
+                        d["n_outside_tile"]))
+            s.close()
+        (fa, pa, na), (fb, pb, nb) = out
+        assert na == nb and na > 0
+        for x, y in zip(fa, fb):
+            assert rel_l2(x, y) < tol
+        for k in range(2):
+            ia, ib = np.argsort(pa[k]["id"]), np.argsort(pb[k]["id"])
+            assert np.array_equal(pa[k]["cell"][ia], pb[k]["cell"][ib])
+            for key in ("off", "u1"):
+                a_, b_ = pa[k][key][ia], pb[k][key][ib]
+                assert np.max(np.abs(a_ - b_) / np.maximum(1.0, np.abs(b_))) < tol
 
 
 def test_global_kernel_option(pic):
