@@ -192,7 +192,9 @@ pic::PushConst<Real> push_const(const pic_ctx* c, const SpeciesHost& s) {
     double fmax = c->g.nd < 3 ? 1.0 / dv : 0.0;
     for (int a = 0; a < c->g.nd; a++) fmax = std::max(fmax, c->cfg.dx[a] / (dt * dv));
     const double bound = 1.5 * qsum * fmax;
-    int e = bound > 0.0 ? (int)std::floor(46.0 - std::log2(bound)) : 0;
+    // no possible term (no weight yet): the largest scale, so that a shared
+    // patch takes its partner species' scale
+    int e = bound > 0.0 ? (int)std::floor(46.0 - std::log2(bound)) : 120;
     e = std::max(-120, std::min(120, e));
     k.jscale = (Real)std::ldexp(1.0, e);
   }

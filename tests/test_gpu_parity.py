@@ -626,6 +626,30 @@ def test_shared_launch_matches_separate(pic, precision, tol):
                 assert np.max(np.abs(a_ - b_) / np.maximum(1.0, np.abs(b_))) < tol
 
 
+def test_shared_launch_empty_partner(pic):
+    """A shared launch whose two-body species holds no particle yet (a load
+    of zero ions with per-particle weights, so no weight bounds its terms)
+    takes the electrons' patch scale: the same current as one launch per
+    species."""
+    _say("case: shared launch, empty ion species")
+    wl = random_workload(3, 0, 1200, seed=131)
+    el_sp, el = wl.species[0]
+    ion_sp = Species(TWO_BODY, 5.0, 40.0, -3.0, 3.0, weight=0.005, omega_c=2.0, a_c=0.0,
+                     nu=0.05, name="ion")
+    z3 = np.zeros((0, 3))
+    empty = Particles(x=z3, u1=z3, u2=z3, delta=z3, omega_c=np.zeros(0), weight=np.zeros(0))
+    wl = dataclasses.replace(wl, species=[(ion_sp, empty), (el_sp, el)])
+    J = []
+    for flags in (0, pic.SEPARATE_SPECIES):
+        s = pic.Simulation.from_workload(wl, precision=32, flags=flags)
+        s.step(2)
+        assert s.diagnostics()["error_word"] == 0
+        J.append(s.fields()[2])
+        s.close()
+    assert np.max(np.abs(J[0])) > 0
+    assert rel_l2(J[0], J[1]) < 1e-6
+
+
 def test_global_kernel_option(pic):
     """The HBM-gather / global-atomic kernel (PIC_FLAG_GLOBAL_KERNEL) agrees
     with the oracle too."""
