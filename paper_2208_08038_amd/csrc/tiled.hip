@@ -29,10 +29,11 @@ namespace {
 // LDS current patch: FP64 for FP64 work; for FP32 work 64-bit fixed point
 // (exact, order-independent sums, and 64-bit integer LDS atomics issue
 // faster than FP64 ones; FP32 LDS atomic adds issue slowest of all on
-// gfx950).  The per-species scale keeps a term below 2^46 (host side), so
-// 2^16 terms per node cannot overflow: a workgroup advances at most kChunk
-// particles (two bodies each) and lists any further ones for the
-// outside-tile kernel.
+// gfx950).  The per-species scale keeps a term below 2^46 (host side; a
+// shared patch takes the smaller of two species' scales), and a workgroup
+// advances at most kChunk particles of each species (listing any further
+// ones for the outside-tile kernel): at most 2^16 terms per node from the
+// two bodies of the ions and 2^15 from a point species, below 2^63.
 template <typename Real>
 using PatchOf = std::conditional_t<sizeof(Real) == 4, long long, double>;
 constexpr int64_t kChunk = 32768;
