@@ -100,7 +100,7 @@ __device__ __forceinline__ void tile_particles(const GridInfo& g, const TileSpec
                                                const int hi[3], const FieldPtrs<Real>& fl,
                                                int fsy, int fsz, PatchOf<Real>* const jl[3],
                                                int jsy, int jsz, const LdsQueue<Real, ND>& queue,
-                                               uint32_t* err) {
+                                               uint32_t* err, int tid, int nthr) {
   using PatchT = PatchOf<Real>;
   const SpeciesDev<Real>& s = sp.s;
   const PushConst<Real>& c = sp.c;
@@ -110,14 +110,14 @@ __device__ __forceinline__ void tile_particles(const GridInfo& g, const TileSpec
   const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const int64_t pk = p0 + kChunk;
   PState<Real> next;
-  if (PREFETCH && p0 + threadIdx.x < p1) load_state<Real, ND, TWO>(s, c, p0 + threadIdx.x, next);
-  for (int64_t p0w = p0; p0w < p1; p0w += blockDim.x) {
-    const int64_t p = p0w + threadIdx.x;
+  if (PREFETCH && p0 + tid < p1) load_state<Real, ND, TWO>(s, c, p0 + tid, next);
+  for (int64_t p0w = p0; p0w < p1; p0w += nthr) {
+    const int64_t p = p0w + tid;
     const bool valid = p < p1;
     PState<Real> st;
     if (PREFETCH) {
       st = next;
-      if (p + blockDim.x < p1) load_state<Real, ND, TWO>(s, c, p + blockDim.x, next);
+      if (p + nthr < p1) load_state<Real, ND, TWO>(s, c, p + nthr, next);
     } else if (valid) {
       load_state<Real, ND, TWO>(s, c, p, st);
     }
@@ -248,14 +248,27 @@ __device__ __forceinline__ void tiled_body(const GridInfo& g, const FieldPtrs<Re
   const int fsy = L.fpitch, fsz = L.fplane;
   const int jsy = L.jpitch, jsz = L.jplane;
   constexpr bool PREFETCH_A = WPE < 4 || !TWO;
+  const int64_t a0 = a.tile_off[tile], a1 = a.tile_off[tile + 1];
   if constexpr (NS == 1) {
-    tile_particles<Real, ND, TWO, PREFETCH_A>(g, a, a.tile_off[tile], a.tile_off[tile + 1], lo,
-                                              hi, fl, fsy, fsz, jl, jsy, jsz, queue, err);
+    tile_particles<Real, ND, TWO, PREFETCH_A>(g, a, a0, a1, lo, hi, fl, fsy, fsz, jl, jsy, jsz,
+                                              queue, err, threadIdx.x, blockDim.x);
   } else {
-    tile_particles<Real, ND, true, PREFETCH_A>(g, a, a.tile_off[tile], a.tile_off[tile + 1], lo,
-                                               hi, fl, fsy, fsz, jl, jsy, jsz, queue, err);
-    tile_particles<Real, ND, false, true>(g, b, b.tile_off[tile], b.tile_off[tile + 1], lo, hi,
-                                          fl, fsy, fsz, jl, jsy, jsz, queue, err);
+    // the wavefronts split between the species in proportion to their
+    // work in this tile (an ion costs about 1.7 electrons), so that the
+    // ions' arithmetic and the electrons' LDS traffic run side by side
+    const int64_t b0 = b.tile_off[tile], b1 = b.tile_off[tile + 1];
+    const int nw = (int)blockDim.x / 64;
+    const double wi = 1.7 * (double)(a1 - a0), we = (double)(b1 - b0);
+    int wa = wi + we > 0.0 ? (int)(nw * wi / (wi + we) + 0.5) : nw;
+    if (a1 > a0 && b1 > b0) wa = min(max(wa, 1), nw - 1);
+    const int split = 64 * wa;
+    if ((int)threadIdx.x < split)
+      tile_particles<Real, ND, true, PREFETCH_A>(g, a, a0, a1, lo, hi, fl, fsy, fsz, jl, jsy, jsz,
+                                                 queue, err, threadIdx.x, split);
+    else
+      tile_particles<Real, ND, false, true>(g, b, b0, b1, lo, hi, fl, fsy, fsz, jl, jsy, jsz,
+                                            queue, err, threadIdx.x - split,
+                                            (int)blockDim.x - split);
   }
   __syncthreads();
 
