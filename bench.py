@@ -343,7 +343,7 @@ def main():
     traffic = measured_traffic(key, kname)
     achieved = r32["kernel_gbs"]
     ncol = r32["dispatches_per_push"]
-    what = ("ions then electrons of each tile" if r32["shared_launch"] else "ions of each tile")
+    what = ("ions and electrons of each tile" if r32["shared_launch"] else "ions of each tile")
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS if achieved else None,
                 "traffic": traffic,

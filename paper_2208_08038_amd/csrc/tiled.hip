@@ -159,9 +159,10 @@ __device__ __forceinline__ void tile_particles(const GridInfo& g, const TileSpec
 // TX, TY, TZ > 0 fix the tile shape at compile time (patch strides become
 // constants, so LDS addresses fold into instruction offsets); 0 takes the
 // shape from `t`.  NS = 1: species `a` (two-body if TWO) alone.  NS = 2: a
-// two-body species `a` and then a point species `b` share the tile's
-// staged fields and current patch (one staging and one flush for both);
-// both species' constants carry the same fixed-point scale.
+// two-body species `a` and a point species `b` share the tile's staged
+// fields and current patch (one staging and one flush for both), each
+// advanced by its share of the workgroup's wavefronts; both species'
+// constants carry the same fixed-point scale.
 template <typename Real, int ND, bool TWO, int NS, int WPE, int TX, int TY, int TZ>
 __device__ __forceinline__ void tiled_body(const GridInfo& g, const FieldPtrs<Real>& f,
                                            const TileSpecies<Real>& a, const TileSpecies<Real>& b,
