@@ -82,7 +82,7 @@ __device__ __forceinline__ Shape<Real> unit_shape() {
 template <typename Real>
 struct Sink {
   Planes<Real> l;
-  int64_t gbase, gsy, gsz;
+  int gbase, gsy, gsz;  // 32-bit: a plane holds fewer than 2^31 values
   double* lds;
   int lbase, lsy, lsz, lplane;
   __device__ __forceinline__ void add(int comp, int ix, int iy, int iz, Real v) const {
@@ -120,7 +120,7 @@ __device__ __forceinline__ Stencil<Real> stencil_at(const Real x[3]) {
 // Node offsets and strides of one interpolation: the base index of the
 // particle's cell and the y, z strides of the array read.
 struct Where3 {
-  int64_t base, sy, sz;
+  int base, sy, sz;  // 32-bit: a plane holds fewer than 2^31 values
 };
 
 template <typename Real, int ND>
@@ -134,8 +134,8 @@ __device__ __forceinline__ Real interp_value(const Real* __restrict__ F, const W
     Real vy = 0;
 #pragma unroll
     for (int s = 0; s < NY; s++) {
-      const Real* row = F + w.base + sx.i0 + (ND > 1 ? (int64_t)(syy.i0 + s) * w.sy : 0) +
-                        (ND > 2 ? (int64_t)(szz.i0 + t) * w.sz : 0);
+      const Real* row = F + (w.base + sx.i0 + (ND > 1 ? (syy.i0 + s) * w.sy : 0) +
+                             (ND > 2 ? (szz.i0 + t) * w.sz : 0));
       const Real wy = ND > 1 ? syy.w[s] : Real(1);
       vy += wy * (sx.w[0] * row[0] + sx.w[1] * row[1] + sx.w[2] * row[2]);
     }
@@ -182,8 +182,8 @@ __device__ __forceinline__ void interp_value2(const Real* __restrict__ F, const 
     Real ya = 0, yb = 0;
 #pragma unroll
     for (int s = 0; s < NY; s++) {
-      const Real* row = F + w.base + ax.i0 + (ND > 1 ? (int64_t)(ay.i0 + s) * w.sy : 0) +
-                        (ND > 2 ? (int64_t)(az.i0 + t) * w.sz : 0);
+      const Real* row = F + (w.base + ax.i0 + (ND > 1 ? (ay.i0 + s) * w.sy : 0) +
+                             (ND > 2 ? (az.i0 + t) * w.sz : 0));
       const Real r0 = row[0], r1 = row[1], r2 = row[2];
       ya += (ND > 1 ? ay.w[s] : Real(1)) * (ax.w[0] * r0 + ax.w[1] * r1 + ax.w[2] * r2);
       yb += (ND > 1 ? by.w[s] : Real(1)) * (bx.w[0] * r0 + bx.w[1] * r1 + bx.w[2] * r2);
@@ -233,8 +233,7 @@ __device__ __forceinline__ void comp_adjoint(const Real* __restrict__ F, int com
 #pragma unroll
     for (int s = 0; s < NY; s++) {
       const int iy = ND > 1 ? ay.i0 + s : 0;
-      const Real* row = F + w.base + ax.i0 + (ND > 1 ? (int64_t)iy * w.sy : 0) +
-                        (ND > 2 ? (int64_t)iz * w.sz : 0);
+      const Real* row = F + (w.base + ax.i0 + (ND > 1 ? iy * w.sy : 0) + (ND > 2 ? iz * w.sz : 0));
       const Real r0 = row[0], r1 = row[1], r2 = row[2];
       const Real wza = ND > 2 ? az.w[t] : Real(1), wya = ND > 1 ? ay.w[s] : Real(1);
       const Real va = ax.w[0] * r0 + ax.w[1] * r1 + ax.w[2] * r2;
@@ -434,7 +433,11 @@ __device__ __forceinline__ bool deposit_adjoint_w(const Real* J, int64_t jplane,
                                                   const PushConst<Real>& c, Real g0[NB][3],
                                                   Real g1[NB][3], Real gv[NB][3]) {
   const Real third = Real(1) / Real(3), sixth = Real(1) / Real(6);
-  const int64_t base = wh.base, sy = wh.sy;
+  const int base = wh.base, sy = wh.sy;
+  // component planes by pointer (their offsets may exceed 2^31), nodes by
+  // 32-bit index
+  const Real* const J1 = J + jplane;
+  const Real* const J2 = J + 2 * jplane;
 #pragma unroll
   for (int b = 0; b < NB; b++)
 #pragma unroll
@@ -444,7 +447,7 @@ __device__ __forceinline__ bool deposit_adjoint_w(const Real* J, int64_t jplane,
 #pragma unroll
     for (int b = 0; b < NB; b++)
       if (!win_build(x0[b][0], x1[b][0], wx[b]) || wx[b].lo != wx[0].lo) return false;
-    const int64_t o = base + wx[0].lo;
+    const int o = base + wx[0].lo;
     // J_x(r) = fx C(r), r < NW - 1; J_y,z(r) = fv v_{y,z} (S0 + S1)(r) / 2
     Real L[NW];
     L[NW - 1] = Real(0);
@@ -456,7 +459,7 @@ __device__ __forceinline__ bool deposit_adjoint_w(const Real* J, int64_t jplane,
     }
 #pragma unroll
     for (int r = 0; r < NW; r++) {
-      const Real ly = J[jplane + o + r], lz = J[2 * jplane + o + r];
+      const Real ly = J1[o + r], lz = J2[o + r];
 #pragma unroll
       for (int b = 0; b < NB; b++) {
         const Real fx = Q[b] * c.jf[0], fv = Q[b] * c.inv_dv;
@@ -477,7 +480,7 @@ __device__ __forceinline__ bool deposit_adjoint_w(const Real* J, int64_t jplane,
       if (!win_build(x0[b][0], x1[b][0], wx[b]) || !win_build(x0[b][1], x1[b][1], wy[b]) ||
           wx[b].lo != wx[0].lo || wy[b].lo != wy[0].lo)
         return false;
-    const int64_t o = base + wx[0].lo + (int64_t)wy[0].lo * sy;
+    const int o = base + wx[0].lo + wy[0].lo * sy;
     Real fx[NB], fy[NB], fz[NB];
     Real G0x[NB][NW], G1x[NB][NW], G0y[NB][NW], G1y[NB][NW];
     Real Ax[NB][NW], Ay[NB][NW], DSx[NB][NW], DSy[NB][NW];
@@ -526,7 +529,7 @@ __device__ __forceinline__ bool deposit_adjoint_w(const Real* J, int64_t jplane,
       Ly[NW - 1] = Real(0);
 #pragma unroll
       for (int s = NW - 2; s >= 0; s--) {
-        acc += J[jplane + o + r + s * sy];
+        acc += J1[o + r + s * sy];
         Ly[s] = acc;
       }
 #pragma unroll
@@ -548,7 +551,7 @@ __device__ __forceinline__ bool deposit_adjoint_w(const Real* J, int64_t jplane,
     for (int s = 0; s < NW; s++)
 #pragma unroll
       for (int r = 0; r < NW; r++) {
-        const Real lz = J[2 * jplane + o + r + s * sy];
+        const Real lz = J2[o + r + s * sy];
         if (lz == Real(0)) continue;
 #pragma unroll
         for (int b = 0; b < NB; b++) {
@@ -581,8 +584,8 @@ __device__ __forceinline__ bool deposit_adjoint_w(const Real* J, int64_t jplane,
 #pragma unroll
       for (int d = 0; d < 3; d++)
         if (!win_build(x0[b][d], x1[b][d], w[b][d]) || w[b][d].lo != w[0][d].lo) return false;
-    const int64_t st[3] = {1, sy, wh.sz};
-    const int64_t o = base + w[0][0].lo + (int64_t)w[0][1].lo * sy + (int64_t)w[0][2].lo * wh.sz;
+    const int st[3] = {1, sy, wh.sz};
+    const int o = base + w[0][0].lo + w[0][1].lo * sy + w[0][2].lo * wh.sz;
     Real G0[NB][3][NW], G1[NB][3][NW];
 #pragma unroll
     for (int b = 0; b < NB; b++)
@@ -600,7 +603,7 @@ __device__ __forceinline__ bool deposit_adjoint_w(const Real* J, int64_t jplane,
       for (int s = 0; s < NW; s++)
 #pragma unroll
         for (int t = 0; t < NW; t++) {
-          const int64_t ob = o + s * st[e1] + t * st[e2];
+          const int ob = o + s * st[e1] + t * st[e2];
           Real L[NW], acc = 0;
           L[NW - 1] = Real(0);
 #pragma unroll
@@ -830,13 +833,13 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const Planes<Real
     int64_t jplane = l.plane;
     Sink<Real> k;
     k.l = l;
-    k.gbase = g.origin + ci[0] + (ND > 1 ? (int64_t)ci[1] * g.sy : 0) +
-              (ND > 2 ? (int64_t)ci[2] * g.sz : 0);
-    k.gsy = g.sy;
-    k.gsz = g.sz;
+    k.gbase = (int)(g.origin + ci[0] + (ND > 1 ? (int64_t)ci[1] * g.sy : 0) +
+                    (ND > 2 ? (int64_t)ci[2] * g.sz : 0));
+    k.gsy = (int)g.sy;
+    k.gsz = (int)g.sz;
     k.lds = nullptr;
     k.lbase = k.lsy = k.lsz = k.lplane = 0;
-    Where3 wh{k.gbase, g.sy, g.sz};
+    Where3 wh{k.gbase, (int)g.sy, (int)g.sz};
     if constexpr (IN_TILE) {
       const int cx = ci[0] - box.x0, cy = ND > 1 ? ci[1] - box.y0 : 0;
       const int cz = ND > 2 ? ci[2] - box.z0 : 0;
