@@ -190,6 +190,11 @@ __device__ __forceinline__ void tiled_body(const GridInfo& g, const FieldPtrs<Re
     hi[d] = min(lo[d] + TT[d], g.n[d]);
   }
   const int64_t tile = tc[0] + (int64_t)t.nt[0] * (tc[1] + (int64_t)t.nt[1] * tc[2]);
+  // a tile with no particle in its sorted range has nothing to stage,
+  // advance or flush (the whole block leaves before any barrier)
+  bool empty = a.tile_off[tile] == a.tile_off[tile + 1];
+  if constexpr (NS == 2) empty = empty && b.tile_off[tile] == b.tile_off[tile + 1];
+  if (empty) return;
 
   // LDS layout: the FP64 current patch first (8-byte aligned), then the
   // field pairs, then the deposit queue
