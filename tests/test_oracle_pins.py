@@ -395,6 +395,137 @@ def test_isolated_pair_invariants(oracle_built):
             assert abs(es[-10:].mean() - es[:10].mean()) < 0.01 * scale
 
 
+def test_rigid_pair_relativistic_electric(oracle_built):
+    """Bodies of equal q/m, delta = 0, u1 = u2, uniform E: the bond force
+    vanishes and each body (so the centre) follows the point-charge update
+    of Sec. 2 driven to gamma ~ 12: u^n = u^0 + n dt (q/m) E exactly, the
+    centre moves by dt u/gamma per step, and delta stays 0."""
+    g = _grid(1, (1024,), (0.5,), 0.2)
+    q1, m1, q2, m2 = 2.0, 4.0, 0.5, 1.0   # q/m = 1/2 for both bodies
+    sp = Species(TWO_BODY, q1, m1, q2, m2, weight=1.0, omega_c=1.0, a_c=0.3)
+    u0 = np.array([0.3, -0.5, 0.2])
+    x = 100.0
+    o, sid = _one_ion(g, sp, [x], u1=u0, u2=u0, delta=(0.0, 0.0, 0.0))
+    E0 = np.array([0.5, 0.2, -0.1])
+    _uniform(o, E0)
+    for n in range(1, 201):
+        o.step(1)
+        st = o.particles(sid)
+        uexp = u0 + n * g.dt * 0.5 * E0
+        for u in (st["u1"][0], st["u2"][0]):
+            assert np.allclose(u, uexp, rtol=1e-13, atol=1e-15)
+        x += g.dt * uexp[0] / math.sqrt(1.0 + uexp @ uexp)
+        xn = (st["cell"][0, 0] + st["off"][0, 0]) * g.dx[0]
+        assert abs(xn - x) < 1e-11
+        assert np.all(st["delta"][0] == 0.0)
+    assert math.sqrt(1.0 + uexp @ uexp) > 10.0
+    assert o.diagnostics()["error_word"] == 0
+
+
+def test_rigid_pair_relativistic_magnetic(oracle_built):
+    """Same rigid pair in a uniform B at gamma ~ 3: |u| is kept and u turns
+    by 2 atan(|t|) per step with t = (q dt/2m) B / gamma, as one body."""
+    g = _grid(1, (256,), (0.5,), 0.3)
+    q1, m1, q2, m2 = -3.0, 3.0, -1.0, 1.0  # q/m = -1 for both bodies
+    sp = Species(TWO_BODY, q1, m1, q2, m2, weight=1.0, omega_c=2.0, a_c=INF)
+    u0 = np.array([2.5, 0.0, 1.2])
+    o, sid = _one_ion(g, sp, [60.0], u1=u0, u2=u0, delta=(0.0, 0.0, 0.0))
+    B0 = np.array([0.0, 0.0, 1.3])
+    _uniform(o, (0, 0, 0), B0)
+    gam = math.sqrt(1 + u0 @ u0)
+    ang = 2 * math.atan(0.5 * g.dt * B0[2] / gam)
+    prev = u0
+    for _ in range(40):
+        o.step(1)
+        st = o.particles(sid)
+        u = st["u1"][0]
+        assert np.array_equal(u, st["u2"][0])
+        assert abs(np.linalg.norm(u) - np.linalg.norm(u0)) < 1e-13
+        assert abs(u[2] - u0[2]) < 1e-14
+        d = (math.atan2(u[1], u[0]) - math.atan2(prev[1], prev[0]) + math.pi) % (2 * math.pi) - math.pi
+        # q < 0, B along +z: the force on v = +x points to +y
+        assert abs(d - ang) < 1e-12
+        prev = u
+
+
+def test_pair_separation_moves_with_velocities(oracle_built):
+    """delta = 0 and no field: the bond force vanishes, the momenta are kept
+    and delta becomes dt (u1/gamma1 - u2/gamma2) after one step (Sec. 3.1
+    relative coordinate moved with the body velocities, not momenta)."""
+    g = _grid(1, (64,), (1.0,), 0.05)
+    sp = Species(TWO_BODY, 2.0, 40.0, -1.0, 1.0, weight=1.0, omega_c=3.0, a_c=0.3)
+    for u1, u2 in [((0.3, -0.1, 0.2), (2.0, 1.5, -1.0)), ((0.0, 0.0, 0.0), (-0.7, 0.0, 3.0))]:
+        o, sid = _one_ion(g, sp, [20.0], u1=u1, u2=u2, delta=(0.0, 0.0, 0.0))
+        o.step(1)
+        st = o.particles(sid)
+        a, b = np.array(u1), np.array(u2)
+        assert np.array_equal(st["u1"][0], a) and np.array_equal(st["u2"][0], b)
+        dexp = g.dt * (a / math.sqrt(1 + a @ a) - b / math.sqrt(1 + b @ b))
+        assert np.allclose(st["delta"][0], dexp, rtol=1e-14, atol=1e-17)
+
+
+def test_relativistic_pair_energy_bounded(oracle_built):
+    """No field, the electron swinging at gamma ~ 2 around a heavy nucleus in
+    a softened bond: the relativistic pair energy sum m (gamma - 1) + V stays
+    within the O(w_c dt) wobble of the staggered sampling and does not drift."""
+    re = 5.0
+    g = _grid(1, (64,), (1.0,), 0.005, re_norm=re)
+    q1, m1, q2, m2, wc = 2.0, 40.0, -1.0, 1.0, 20.0
+    a_c = ac_from_omega(q1, m1, q2, m2, wc, re)
+    assert 0.2 < a_c < 0.4
+    sp = Species(TWO_BODY, q1, m1, q2, m2, weight=1.0, omega_c=wc, a_c=0.0)
+    o, sid = _one_ion(g, sp, [30.0], u1=(0.0, 0.0, 0.0), u2=(0.0, 2.0, 0.5),
+                      delta=(0.0, 0.0, 0.0))
+
+    def energy(st):
+        u1, u2, dl = st["u1"][0], st["u2"][0], st["delta"][0]
+        k = m1 * (math.sqrt(1 + u1 @ u1) - 1) + m2 * (math.sqrt(1 + u2 @ u2) - 1)
+        return k + q1 * q2 * re / math.sqrt(dl @ dl + a_c * a_c)
+
+    e0 = energy(o.particles(sid))
+    scale = e0 - q1 * q2 * re / a_c
+    es, gmax = [], 0.0
+    for _ in range(200):
+        o.step(10)
+        st = o.particles(sid)
+        es.append(energy(st))
+        gmax = max(gmax, math.sqrt(1 + st["u2"][0] @ st["u2"][0]))
+        assert np.all(np.abs(st["delta"][0]) < 0.5)
+    es = np.array(es)
+    assert gmax > 1.8
+    # measured wobble 3.6 % of the swing energy; moving delta with the
+    # momenta instead of the velocities gives 68 %
+    assert np.max(np.abs(es - e0)) < 0.1 * scale
+    assert abs(es[-20:].mean() - es[:20].mean()) < 0.01 * scale
+
+
+@pytest.mark.parametrize("nu", [0.0, 0.4])
+def test_driven_pair_relativistic_momentum_balance(oracle_built, nu):
+    """Unequal q/m, a stretched softened bond and a strong uniform E that
+    drives the centre past gamma ~ 4: the bond force acts on the bodies as
+    equal and opposite impulses and the friction only damps the relative
+    momentum, so m1 u1 + m2 u2 grows by exactly (q1 + q2) E dt per step."""
+    g = _grid(1, (4096,), (0.5,), 0.2)
+    q1, m1, q2, m2 = 3.0, 10.0, -1.0, 1.0
+    sp = Species(TWO_BODY, q1, m1, q2, m2, weight=1.0, omega_c=6.0, a_c=0.2, nu=nu)
+    o, sid = _one_ion(g, sp, [200.0], u1=(0.2, 0.1, 0.0), u2=(-0.3, 0.4, 0.1),
+                      delta=(0.03, -0.02, 0.01))
+    E0 = np.array([0.25, 0.1, 0.0])
+    _uniform(o, E0)
+    st = o.particles(sid)
+    p0 = m1 * st["u1"][0] + m2 * st["u2"][0]
+    for n in range(1, 601):
+        o.step(1)
+        st = o.particles(sid)
+        p = m1 * st["u1"][0] + m2 * st["u2"][0]
+        pexp = p0 + n * g.dt * (q1 + q2) * E0
+        assert np.allclose(p, pexp, rtol=1e-12, atol=1e-12)
+        assert np.all(np.abs(st["delta"][0]) < 0.25)
+    uc = p / (m1 + m2)
+    assert math.sqrt(1.0 + uc @ uc) > 4.0
+    assert o.diagnostics()["error_word"] == 0
+
+
 # ------------------------------------------ Esirkepov deposit (T5, T8)
 
 def _random_state(rng, ndim, n, shape, dx, pad=0, vmax=0.8):
