@@ -117,6 +117,45 @@ def test_coupled_periodic_fp64(pic, ndim):
     assert s.diagnostics()["error_word"] == 0
 
 
+def _relativistic(wl, seed):
+    """Give every particle a random direction and gamma in [2, 8] (ion
+    centres, both bodies kept at their loaded momentum difference) or
+    [2, 20] (free electrons)."""
+    rng = np.random.default_rng(seed)
+    for sp, p in wl.species:
+        n = p.u1.shape[0]
+        d = rng.normal(size=(n, 3))
+        d /= np.linalg.norm(d, axis=1)[:, None]
+        g = rng.uniform(2.0, 8.0 if sp.kind == TWO_BODY else 20.0, n)
+        u = d * np.sqrt(g * g - 1.0)[:, None]
+        if sp.kind == TWO_BODY:
+            p.u2 = u + (p.u2 - p.u1)
+        p.u1 = u
+
+
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_relativistic_coupled(pic, ndim):
+    """15 self-consistent steps with every particle at gamma 2 - 20: FP64
+    follows the oracle to round-off, FP32 fields within its tolerance."""
+    _say(f"case: relativistic coupled ndim={ndim}")
+    wl = random_workload(ndim, 300, 300, seed=60 + ndim, weight=0.001)
+    _relativistic(wl, 70 + ndim)
+    o, s = _both(wl, pic, 64, sort_every=3)
+    o.step(15)
+    s.step(15)
+    assert o.diagnostics()["error_word"] == 0, "oracle run left the valid range"
+    assert s.diagnostics()["error_word"] == 0
+    Eo, Bo, Jo = o.fields()
+    Eg, Bg, Jg = s.fields()
+    assert rel_l2(Eg, Eo) < 1e-12 and rel_l2(Bg, Bo) < 1e-12 and rel_l2(Jg, Jo) < 1e-12
+    _compare_particles(o, s, wl, 1e-11)
+    s32 = pic.Simulation.from_workload(wl, precision=32)
+    s32.step(15)
+    assert s32.diagnostics()["error_word"] == 0
+    Eg, Bg, _ = s32.fields()
+    assert rel_l2(Eg, Eo) < 2e-5 and rel_l2(Bg, Bo) < 2e-5
+
+
 @pytest.mark.parametrize("tile", [(8, 8, 8), (8, 8, 6), (6, 8, 8), (5, 5, 5), (16, 8, 6)])
 def test_tile_shapes(pic, tile):
     """Other tile shapes (partial tiles at the upper faces, two workgroups
