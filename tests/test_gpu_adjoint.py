@@ -191,6 +191,54 @@ def test_particle_state_gradient_matches_finite_differences(pic, ndim):
         assert _rel(adj, fd) < 2e-6, (key, comp)
 
 
+@pytest.mark.parametrize("ndim", [1, 3])
+def test_particle_state_gradient_relativistic(pic, ndim):
+    """Ions drifting across the laser at gamma up to 1.56 (a common
+    transverse momentum of 0.5 - 1.2 on both bodies, so that the Jacobian
+    of v = u / gamma is far from the identity): the adjoint with respect to
+    one ion's initial u1, u2, delta and position against
+    Richardson-extrapolated central differences of the FP64 forward."""
+    _say(f"case: relativistic particle-state FD {ndim}D")
+    wl = A.small_case(ndim, a0=3e-3, thermal=2e-3, a_c=0.03)
+    sp, parts = wl.species[0]
+    rng = np.random.default_rng(11)
+    n = parts.n
+    ang = rng.uniform(0.0, 2.0 * math.pi, n)
+    mag = rng.uniform(0.5, 1.2, n)
+    uc = np.stack([0.02 * rng.normal(size=n), mag * np.cos(ang), mag * np.sin(ang)], 1)
+    wl = A.with_particles(wl, u1=parts.u1 + uc, u2=parts.u2 + uc,
+                          delta=rng.uniform(-0.01, 0.01, (n, 3)))
+    parts = wl.species[0][1]
+    sim = pic.Simulation.from_workload(wl, precision=64, flags=pic.TRACK_IDS,
+                                       max_probe_steps=wl.steps)
+    sim.grad_forward(wl.steps, 40)
+    ids = sim.particles(0, ids=True)["id"]
+    y = sim.probes()
+    w = rng.normal(size=y.shape)
+    sim.grad_backward(w)
+    gp = sim.grad_particles(0)
+    sim.close()
+    loss = _loss_w(w)
+    series = lambda x: A.gpu_series(pic, x)
+    slot = int(np.argmax(np.abs(gp["u1"]).sum(axis=1)))
+    pid = int(ids[slot])
+    gam = math.sqrt(1.0 + parts.u1[pid] @ parts.u1[pid])
+    _say(f"ion {pid} (slot {slot}), gamma {gam:.3f}")
+    assert gam > 1.1
+    for key, comp, h in (("u1", 0, 1e-6), ("u1", 1, 1e-6), ("u2", 2, 1e-6), ("delta", 1, 2e-7),
+                         ("x", 0, 1e-5)):
+        arr = {"u1": parts.u1, "u2": parts.u2, "delta": parts.delta, "x": parts.x}[key]
+
+        def make(v, arr=arr, key=key, comp=comp):
+            a = np.array(arr, dtype=np.float64, copy=True)
+            a[pid, comp] = v
+            return A.with_particles(wl, **{key: a})
+        fd = A.richardson_fd(series, loss, make, float(arr[pid, comp]), h)
+        adj = float(gp[key][slot, comp])
+        _say(f"{ndim}D d/d{key}[{comp}]: adjoint {adj:.10e}, FD {fd:.10e}, rel {_rel(adj, fd):.2e}")
+        assert _rel(adj, fd) < 2e-6, (key, comp)
+
+
 @pytest.mark.parametrize("ndim,precision", [(1, 64), (1, 32), (3, 64), (3, 32)])
 def test_gradients_against_the_oracle(pic, ndim, precision):
     """The 1D and 3D cases' gradients with respect to omega_c, nu and an
