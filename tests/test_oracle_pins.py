@@ -211,6 +211,33 @@ def test_boris_pure_magnetic_rotation(oracle_built):
         prev = u
 
 
+def test_boris_rotation_uses_half_step_gamma(oracle_built):
+    """Strong E and B together at gamma ~ 3: the magnetic part of a step
+    turns u- = u + (q dt/2m) E into u+ = u_new - (q dt/2m) E about B, keeping
+    |u-|, by 2 atan(|t|) with t = (q dt/2m) B / gamma(u-), the Lorentz factor
+    after the first half kick (not that of u; the two differ by 12 - 40 % here)."""
+    g = _grid(1, (64,), (0.5,), 0.2)
+    q, m = -1.0, 1.0
+    a = 0.5 * g.dt * q / m
+    E0 = np.array([-8.0, -4.0, 6.0])
+    B0 = np.array([0.4, 0.9, -1.1])
+    bhat = B0 / np.linalg.norm(B0)
+    for u0 in (np.array([2.0, 1.0, -1.5]), np.array([-0.5, 2.5, 0.3])):
+        o, sid = _one_point(g, q, m, [10.0], u0)
+        _uniform(o, E0, B0)
+        o.step(1)
+        un = o.particles(sid)["u1"][0]
+        um, up = u0 + a * E0, un - a * E0
+        assert abs(np.linalg.norm(up) - np.linalg.norm(um)) < 1e-13
+        assert abs(up @ bhat - um @ bhat) < 1e-13
+        pm, pp = um - (um @ bhat) * bhat, up - (up @ bhat) * bhat
+        ang = math.atan2(np.cross(pm, pp) @ bhat, pm @ pp)
+        gm, g0 = math.sqrt(1 + um @ um), math.sqrt(1 + u0 @ u0)
+        assert abs(gm / g0 - 1.0) > 0.1
+        # q < 0: the turn is positive about B
+        assert abs(ang - 2 * math.atan(abs(a) * np.linalg.norm(B0) / gm)) < 1e-12
+
+
 def test_boris_exb_drift(oracle_built):
     """Crossed E and B: a particle launched at the drift velocity E x B / B^2
     keeps it (Boris is exact for the drift in the non-relativistic limit)."""
