@@ -323,18 +323,23 @@ def test_softened_bond_equilibrium_minimises_potential(oracle_built):
     assert abs(q_r * E0 / (mr * wc ** 2) - r_eq) > 0.05 * a_c
 
 
-def test_driven_damped_oscillator_response(oracle_built):
+@pytest.mark.parametrize("nu_const,nu_per_omega", [(0.4, 0.0), (0.0, 0.2), (0.1, 0.15)])
+def test_driven_damped_oscillator_response(oracle_built, nu_const, nu_per_omega):
     """Uniform drive E0 cos(w t): after the transient, the nucleus and the
     cloud follow the Sec. 3.1 response
       r1 = [-q_c/(m_c W^2) + (m2/m_c) q_r/(m_r D)] E,
       r2 = [-q_c/(m_c W^2) - (m1/m_c) q_r/(m_r D)] E,
     with the leapfrog frequency W = (2/dt) sin(w dt/2) and
     D = w_c^2 - W^2 + i nu sin(w dt)/dt (the time-centred friction);
-    D -> w_c^2 - w^2 as dt -> 0 and nu -> 0."""
+    D -> w_c^2 - w^2 as dt -> 0 and nu -> 0.  The friction rate is a constant
+    plus a part proportional to w_c; each split gives nu = 0.4."""
     g = _grid(1, (64,), (1.0,), 0.05)
     q1, m1, q2, m2 = 4.0, 60.0, -3.0, 3.0      # charged ion, q_c = 1
-    wc, nu, w = 2.0, 0.4, 1.3
-    sp = Species(TWO_BODY, q1, m1, q2, m2, weight=1.0, omega_c=wc, a_c=INF, nu=nu)
+    wc, w = 2.0, 1.3
+    nu = nu_const + nu_per_omega * wc
+    assert abs(nu - 0.4) < 1e-15
+    sp = Species(TWO_BODY, q1, m1, q2, m2, weight=1.0, omega_c=wc, a_c=INF, nu=nu_const,
+                 nu_per_omega=nu_per_omega)
     mc, qc = m1 + m2, q1 + q2
     mr = m1 * m2 / mc
     qr = (q1 * m2 - q2 * m1) / mc
