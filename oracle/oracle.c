@@ -33,6 +33,8 @@ typedef struct {
   int kind;
   double q1, m1, q2, m2; /* real-particle charges and masses (point: q1, m1) */
   double weight, omega_c, a_c, nu, nu_per_omega;
+  int ac_derived;  /* a_c of each ion from its own omega_c (Sec. 3.1) */
+  double re_norm;  /* Coulomb constant of the bond in these units */
   int64_t n, cap;
   int32_t* cell; /* n x 3 */
   double* off;   /* n x 3 */
@@ -191,11 +193,20 @@ double or_ac_from_omega(double q1, double m1, double q2, double m2, double omega
   return cbrt(fabs(q1 * q2) * re_norm / (mr * omega_c * omega_c));
 }
 
+/* Softening length of the bond: a_c = 0 asks for a_c^3 = |q1 q2| re_norm /
+   (m_r omega_c^2) with each ion's own omega_c, because the Sec. 2 potential
+   V_M = q1 q2 / (4 pi eps0 sqrt(r^2 + a_c^2)) has one Coulomb constant for
+   every ion; a_c = +inf is the exact harmonic bond; a finite a_c > 0 is used
+   as given (and then fixes omega_c for the whole species). */
 int or_add_species(or_ctx* c, int kind, double q1, double m1, double q2, double m2,
                    double weight, double omega_c, double a_c, double nu, double nu_per_omega,
-                   int64_t capacity) {
+                   double re_norm, int64_t capacity) {
   if (!c || c->nsp >= OR_MAX_SPECIES || capacity < 0) return -1;
   if (kind != OR_POINT && kind != OR_TWO_BODY) return -1;
+  if (kind == OR_TWO_BODY) {
+    if (!(omega_c > 0.0) || isnan(a_c) || a_c < 0.0) return -1;
+    if (a_c == 0.0 && !(re_norm > 0.0)) return -1; /* a derived a_c must be positive */
+  }
   or_species* s = &c->sp[c->nsp];
   memset(s, 0, sizeof(*s));
   s->kind = kind;
@@ -208,6 +219,8 @@ int or_add_species(or_ctx* c, int kind, double q1, double m1, double q2, double 
   s->a_c = a_c;
   s->nu = nu;
   s->nu_per_omega = nu_per_omega;
+  s->ac_derived = kind == OR_TWO_BODY && a_c == 0.0;
+  s->re_norm = re_norm;
   s->cap = capacity > 0 ? capacity : 1;
   s->cell = (int32_t*)calloc((size_t)s->cap * 3, sizeof(int32_t));
   s->off = (double*)calloc((size_t)s->cap * 3, sizeof(double));
@@ -272,6 +285,13 @@ int or_load_particles(or_ctx* c, int sid, int64_t n, const double* x, const doub
   if (!c || sid < 0 || sid >= c->nsp || n < 0 || (n > 0 && (!x || !u1))) return -1;
   or_species* s = &c->sp[sid];
   if (s->n + n > s->cap) return -2;
+  if (omega_c && s->kind == OR_TWO_BODY) {
+    /* a fixed finite a_c together with omega_c fixes the Coulomb constant,
+       so the ions of such a species share one omega_c */
+    if (!s->ac_derived && !isinf(s->a_c)) return -1;
+    for (int64_t p = 0; p < n; p++)
+      if (!(omega_c[p] > 0.0)) return -1;
+  }
   if (omega_c && !s->wc) {
     if (s->n > 0) return -1;
     s->wc = (double*)calloc((size_t)s->cap, sizeof(double));
@@ -440,8 +460,12 @@ static void jadd(or_ctx* c, int a, int64_t i, int64_t j, int64_t k, double v) {
 
 /* Esirkepov (2001) charge-conserving current of one body of charge Q
    (= real charge x weight) moving from x0 to x1 (cell units, relative to
-   `cell`).  v is the body velocity, used for the components along
-   unresolved dimensions, which carry the time-averaged shape. */
+   `cell`; x0 in [0, 1), so the window -2 .. +3 holds both shapes).  v is
+   the body velocity, used for the components along unresolved dimensions,
+   which carry the time-averaged shape.  Along its own axis a component is
+   the running sum of the shape change; at the window's last node that sum
+   runs over the whole of both shapes and is zero (the body's charge is
+   conserved), so the running sums stop one node short of it. */
 static void deposit(or_ctx* c, const int32_t cell[3], const double x0[3], const double x1[3],
                     double Q, const double v[3]) {
   const or_config* g = &c->g;
@@ -463,7 +487,7 @@ static void deposit(or_ctx* c, const int32_t cell[3], const double x0[3], const 
     double acc = 0.0;
     for (int r = 0; r < NW; r++) {
       acc += DS[0][r];
-      jadd(c, 0, ci + r + RLO, 0, 0, fx * acc);
+      if (r < NW - 1) jadd(c, 0, ci + r + RLO, 0, 0, fx * acc);
       double sh = S0[0][r] + 0.5 * DS[0][r];
       jadd(c, 1, ci + r + RLO, 0, 0, Q * v[1] / dV * sh);
       jadd(c, 2, ci + r + RLO, 0, 0, Q * v[2] / dV * sh);
@@ -473,14 +497,14 @@ static void deposit(or_ctx* c, const int32_t cell[3], const double x0[3], const 
     double fy = -Q * g->dx[1] / (g->dt * dV);
     for (int s = 0; s < NW; s++) {
       double acc = 0.0;
-      for (int r = 0; r < NW; r++) {
+      for (int r = 0; r < NW - 1; r++) {
         acc += DS[0][r] * (S0[1][s] + 0.5 * DS[1][s]);
         jadd(c, 0, ci + r + RLO, cj + s + RLO, 0, fx * acc);
       }
     }
     for (int r = 0; r < NW; r++) {
       double acc = 0.0;
-      for (int s = 0; s < NW; s++) {
+      for (int s = 0; s < NW - 1; s++) {
         acc += DS[1][s] * (S0[0][r] + 0.5 * DS[0][r]);
         jadd(c, 1, ci + r + RLO, cj + s + RLO, 0, fy * acc);
       }
@@ -498,7 +522,7 @@ static void deposit(or_ctx* c, const int32_t cell[3], const double x0[3], const 
     for (int t = 0; t < NW; t++)
       for (int s = 0; s < NW; s++) {
         double acc = 0.0;
-        for (int r = 0; r < NW; r++) {
+        for (int r = 0; r < NW - 1; r++) {
           acc += DS[0][r] * (S0[1][s] * S0[2][t] + 0.5 * DS[1][s] * S0[2][t] +
                              0.5 * S0[1][s] * DS[2][t] + DS[1][s] * DS[2][t] / 3.0);
           jadd(c, 0, ci + r + RLO, cj + s + RLO, ck + t + RLO, f[0] * acc);
@@ -508,7 +532,7 @@ static void deposit(or_ctx* c, const int32_t cell[3], const double x0[3], const 
     for (int t = 0; t < NW; t++)
       for (int r = 0; r < NW; r++) {
         double acc = 0.0;
-        for (int s = 0; s < NW; s++) {
+        for (int s = 0; s < NW - 1; s++) {
           acc += DS[1][s] * (S0[0][r] * S0[2][t] + 0.5 * DS[0][r] * S0[2][t] +
                              0.5 * S0[0][r] * DS[2][t] + DS[0][r] * DS[2][t] / 3.0);
           jadd(c, 1, ci + r + RLO, cj + s + RLO, ck + t + RLO, f[1] * acc);
@@ -518,7 +542,7 @@ static void deposit(or_ctx* c, const int32_t cell[3], const double x0[3], const 
     for (int s = 0; s < NW; s++)
       for (int r = 0; r < NW; r++) {
         double acc = 0.0;
-        for (int t = 0; t < NW; t++) {
+        for (int t = 0; t < NW - 1; t++) {
           acc += DS[2][t] * (S0[0][r] * S0[1][s] + 0.5 * DS[0][r] * S0[1][s] +
                              0.5 * S0[0][r] * DS[1][s] + DS[0][r] * DS[1][s] / 3.0);
           jadd(c, 2, ci + r + RLO, cj + s + RLO, ck + t + RLO, f[2] * acc);
@@ -528,6 +552,37 @@ static void deposit(or_ctx* c, const int32_t cell[3], const double x0[3], const 
 }
 
 /* ------------------------------------------------------------------- push */
+
+/* Sec. 2: each body of a two-body ion has its own position.  A body at x
+   (cell units, relative to the centre's cell `cell`) is gathered and
+   deposited in the frame of the cell that holds it: cell + floor(x), offset
+   x - floor(x) (an exact subtraction), so its windows follow it however far
+   it is from the centre of mass. */
+static void body_frame(const or_ctx* c, const int32_t cell[3], const double x[3],
+                       int32_t bc[3], double bx[3]) {
+  for (int d = 0; d < 3; d++) {
+    if (resolved(c, d)) {
+      double k = floor(x[d]);
+      bc[d] = cell[d] + (int32_t)k;
+      bx[d] = x[d] - k;
+    } else {
+      bc[d] = 0;
+      bx[d] = 0.0;
+    }
+  }
+}
+
+/* Along an axis with walls a body must stay where every node its shape
+   reaches is interior: within one cell beyond the walls `pad` cells inside
+   the faces (the centre of mass itself stays between the walls). */
+static int body_in_range(const or_ctx* c, const int32_t cell[3], const double x[3]) {
+  for (int d = 0; d < c->nd; d++) {
+    if (periodic(c, d)) continue;
+    double X = (double)cell[d] + x[d];
+    if (!(X >= (double)(c->g.pad - 1) && X <= (double)(c->nn[d] - c->g.pad + 1))) return 0;
+  }
+  return 1;
+}
 
 /* Boris rotation and second half kick of one body (Sec. 2):
    t = (q dt / 2m) B / gamma^-, s = 2t / (1 + t^2),
@@ -593,27 +648,34 @@ static void push_two_body(or_ctx* c, or_species* s, int64_t p) {
   double wc = s->wc ? s->wc[p] : s->omega_c;
   double nu = s->nu + s->nu_per_omega * wc;
   double W = s->w ? s->w[p] : s->weight;
+  /* the ion's own softening length (Sec. 3.1 with its own omega_c) */
+  double ac = s->ac_derived ? or_ac_from_omega(q1, m1, q2, m2, wc, s->re_norm) : s->a_c;
   int32_t* cell = &s->cell[3 * p];
   double* off = &s->off[3 * p];
   double* dl = &s->delta[3 * p];
   double* u1 = &s->u1[3 * p];
   double* u2 = &s->u2[3 * p];
 
-  /* body positions r1 = r_c + (m2/m_c) r, r2 = r_c - (m1/m_c) r (Sec. 3.1) */
+  /* body positions r1 = r_c + (m2/m_c) r, r2 = r_c - (m1/m_c) r (Sec. 3.1),
+     relative to the centre's cell, and each body's own cell frame */
   double x1[3] = {0, 0, 0}, x2[3] = {0, 0, 0};
   for (int d = 0; d < nd; d++) {
     x1[d] = off[d] + f1 * dl[d] / g->dx[d];
     x2[d] = off[d] - f2 * dl[d] / g->dx[d];
   }
+  int32_t c1[3], c2[3];
+  double b1[3], b2_[3];
+  body_frame(c, cell, x1, c1, b1);
+  body_frame(c, cell, x2, c2, b2_);
   double E1[3], B1[3], E2[3], B2[3];
-  gather(c, cell, x1, E1, B1);
-  gather(c, cell, x2, E2, B2);
+  gather(c, c1, b1, E1, B1);
+  gather(c, c2, b2_, E2, B2);
 
   /* internal softened-Coulomb force on the nucleus,
      F = q1 q2 r / (4 pi eps0 (r^2 + a_c^2)^{3/2}) = -m_r w_c^2 r (1 + r^2/a_c^2)^{-3/2},
      +F on body 1 and -F on body 2, entering the push as extra E. */
   double r2 = dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2];
-  double soft = isinf(s->a_c) ? 1.0 : pow(1.0 + r2 / (s->a_c * s->a_c), -1.5);
+  double soft = isinf(ac) ? 1.0 : pow(1.0 + r2 / (ac * ac), -1.5);
   double kf = -mr * wc * wc * soft;
   for (int a = 0; a < 3; a++) {
     double F = kf * dl[a];
@@ -661,19 +723,26 @@ static void push_two_body(or_ctx* c, or_species* s, int64_t p) {
       dl[d] = -dl[d];
     }
   }
+  /* new body positions, relative to the centre's old cell and in each
+     body's old frame */
   double y1[3] = {0, 0, 0}, y2[3] = {0, 0, 0};
   for (int d = 0; d < nd; d++) {
     y1[d] = offn[d] + f1 * dl[d] / g->dx[d];
     y2[d] = offn[d] - f2 * dl[d] / g->dx[d];
   }
   if (!(g->flags & OR_NO_DEPOSIT)) {
-    deposit(c, cell, x1, y1, q1 * W, v1);
-    deposit(c, cell, x2, y2, q2 * W, v2);
+    double z1[3] = {0, 0, 0}, z2[3] = {0, 0, 0};
+    for (int d = 0; d < nd; d++) {
+      z1[d] = y1[d] - (double)(c1[d] - cell[d]);
+      z2[d] = y2[d] - (double)(c2[d] - cell[d]);
+    }
+    deposit(c, c1, b1, z1, q1 * W, v1);
+    deposit(c, c2, b2_, z2, q2 * W, v2);
   }
+  if (!body_in_range(c, cell, y1) || !body_in_range(c, cell, y2)) c->err |= OR_ERR_RANGE;
   for (int d = 0; d < nd; d++) {
     cross(c, d, &cell[d], &offn[d]);
     off[d] = offn[d];
-    if (!(fabs(dl[d]) < 0.5 * g->dx[d])) c->err |= OR_ERR_RANGE;
   }
   for (int a = 0; a < 3; a++)
     if (!isfinite(u1[a]) || !isfinite(u2[a]) || !isfinite(dl[a])) c->err |= OR_ERR_NAN;
@@ -760,10 +829,14 @@ int or_rho(or_ctx* c, double* rho) {
       if (s->kind == OR_TWO_BODY) {
         double mc = s->m1 + s->m2, f1 = s->m2 / mc, f2 = s->m1 / mc;
         const double* dl = &s->delta[3 * p];
+        int32_t bc[3];
+        double bx[3];
         for (int d = 0; d < c->nd; d++) x[d] = off[d] + f1 * dl[d] / c->g.dx[d];
-        add_rho(c, rho, cell, x, s->q1 * W);
+        body_frame(c, cell, x, bc, bx);
+        add_rho(c, rho, bc, bx, s->q1 * W);
         for (int d = 0; d < c->nd; d++) x[d] = off[d] - f2 * dl[d] / c->g.dx[d];
-        add_rho(c, rho, cell, x, s->q2 * W);
+        body_frame(c, cell, x, bc, bx);
+        add_rho(c, rho, bc, bx, s->q2 * W);
       } else {
         for (int d = 0; d < c->nd; d++) x[d] = off[d];
         add_rho(c, rho, cell, x, s->q1 * W);

@@ -85,12 +85,17 @@ typedef struct or_ctx or_ctx;
 
 or_ctx* or_create(const or_config* cfg);
 void or_destroy(or_ctx* c);
-/* returns species id >= 0, or -1 */
+/* Returns species id >= 0, or -1.  Two-body: omega_c > 0; a_c = 0 derives
+   each ion's softening length from its own omega_c,
+   a_c^3 = |q1 q2| re_norm / (m_r omega_c^2) (needs re_norm > 0); a_c = +inf
+   is the harmonic bond; a finite a_c > 0 is used as given, and such a
+   species takes no per-particle omega_c. */
 int or_add_species(or_ctx* c, int kind, double q1, double m1, double q2, double m2,
                    double weight, double omega_c, double a_c, double nu, double nu_per_omega,
-                   int64_t capacity);
+                   double re_norm, int64_t capacity);
 /* Appends n particles.  x: n*ndim physical positions (centre of mass for
-   two-body), delta: n*3 or NULL (= 0), u1: n*3, u2: n*3 or NULL.  For a
+   two-body), delta: n*3 or NULL (= 0; any size: each body has its own
+   position), u1: n*3, u2: n*3 or NULL.  For a
    two-body species with u2 == NULL, u1 is the centre-of-mass momentum per
    mass u_c and the Sec. 2 initial split is applied.  omega_c / weight:
    per-particle values or NULL (species value).  Returns 0 or <0. */

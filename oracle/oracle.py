@@ -60,7 +60,7 @@ def _load():
     lib.or_create.argtypes = [C.POINTER(_Config)]
     lib.or_destroy.argtypes = [P]
     lib.or_add_species.restype = C.c_int
-    lib.or_add_species.argtypes = [P, C.c_int] + [C.c_double] * 9 + [C.c_int64]
+    lib.or_add_species.argtypes = [P, C.c_int] + [C.c_double] * 10 + [C.c_int64]
     lib.or_load_particles.restype = C.c_int
     lib.or_load_particles.argtypes = [P, C.c_int, C.c_int64, D, D, D, D, D, D]
     lib.or_load_fields.argtypes = [P, D, D]
@@ -165,14 +165,14 @@ class Oracle:
 
     # ---------------------------------------------------------------- setup
     def add_species(self, sp, capacity: int) -> int:
-        a_c = sp.a_c
-        if sp.kind == 1 and (a_c == 0.0 or a_c is None):
-            a_c = ac_from_omega(sp.q1, sp.m1, sp.q2, sp.m2, sp.omega_c, self.grid.re_norm)
+        # a_c = 0: each ion's a_c from its own omega_c (derived in the C oracle)
+        a_c = sp.a_c if sp.a_c is not None else math.inf
         sid = self.lib.or_add_species(self.ctx, int(sp.kind), sp.q1, sp.m1, sp.q2, sp.m2,
-                                      sp.weight, sp.omega_c, a_c if a_c is not None else math.inf,
-                                      sp.nu, sp.nu_per_omega, int(capacity))
+                                      sp.weight, sp.omega_c, a_c, sp.nu, sp.nu_per_omega,
+                                      float(self.grid.re_norm), int(capacity))
         if sid < 0:
-            raise ValueError("oracle: add_species failed")
+            raise ValueError("oracle: add_species failed (omega_c <= 0, a_c < 0, or a "
+                             "derived a_c without re_norm > 0)")
         self.species.append(sp)
         return sid
 

@@ -213,6 +213,41 @@ def neutral_medium_1d(cells: int = 2048, ppc: int = 8, steps: int = 1000,
                     notes=f"{n} two-body ions, omega_c={omega_c}, omega_pb={omega_pb}")
 
 
+def ionised_medium_1d(cells: int = 2048, ppc: int = 8, steps: int = 1000,
+                      omega_pb: float = 0.9, a0: float = 1e-4, cycles: int = 10,
+                      wc_range=(1.5, 4.0), nu_per_omega: float = 0.01,
+                      probes=(32, 224), config_id: int = 13) -> Workload:
+    """1D counterpart of the ionised slab for its linear-response check:
+    cold gold ions with one free electron each (q_c = +1), every ion with
+    its own omega_c drawn uniformly from wc_range (softening length derived
+    from it), friction nu_per_omega * omega_c, free electrons at the ions'
+    density, plane wave polarised along y entering at x-min."""
+    dx = TWO_PI / 64.0
+    dt = 0.98 * dx
+    laser = Laser(a0=a0, omega=1.0, t_env=cycles * TWO_PI, pol=1)
+    grid = Grid(1, (cells, 1, 1), (dx, 1.0, 1.0), dt, (LASER, PERIODIC, PERIODIC),
+                (OPEN, PERIODIC, PERIODIC), pad=3, laser=laser,
+                re_norm=TWO_PI * R_E_M / 12.4e-9)
+    q1, m1, q2, m2 = gold_ion(78, 1.0)
+    n_ion = bound_plasma_density(q1, m1, q2, m2, omega_pb)
+    w = n_ion * dx / ppc
+    ion = Species(TWO_BODY, q1, m1, q2, m2, weight=w, omega_c=0.5 * sum(wc_range), a_c=0.0,
+                  nu_per_omega=nu_per_omega, name="Au_q1_cold")
+    pad = grid.pad
+    rng_i = rng_for(config_id, 0)
+    xi = stratified_positions(rng_i, [pad], [cells - pad], ppc, grid.dx, 1)
+    ni = xi.shape[0]
+    wci = rng_i.uniform(wc_range[0], wc_range[1], size=ni)
+    rng_e = rng_for(config_id, 1)
+    xe = stratified_positions(rng_e, [pad], [cells - pad], ppc, grid.dx, 1)
+    ele = Species(POINT, -1.0, 1.0, weight=w, name="e_cold")
+    species = [(ion, Particles(x=xi, u1=np.zeros((ni, 3)), omega_c=wci)),
+               (ele, Particles(x=xe, u1=np.zeros((xe.shape[0], 3))))]
+    return Workload("ionised_medium_1d", grid, species, steps, 64,
+                    probes=_probe_list(1, 1, list(probes)),
+                    notes=f"{ni} cold two-body ions with omega_c in {wc_range} + {ni} electrons")
+
+
 def bound_slab_1d(cells: int = 1536, x_cells=(256, 1536), ppc: int = 4, steps: int = 2200,
                   omega_c: float = 3.0, omega_pb: float = 0.9, a0: float = 1e-4,
                   cycles: int = 10, dx_per_lambda: int = 64, config_id: int = 11) -> Workload:

@@ -639,32 +639,46 @@ def test_total_current_with_per_particle_weights(oracle_built, ndim):
     frozen field: each body moves by dt v (centre by the mass-weighted
     velocity, delta by the difference), so the summed current of one step
     is sum_p w_p (q1 v1 + q2 v2) with the new velocities, for every
-    component (first moment of the charge-conserving deposit)."""
+    component (first moment of the charge-conserving deposit).  The bond
+    acts: the ions' own omega_c (and the softening lengths derived from
+    them) change the new momenta against a run with one common omega_c."""
     rng = np.random.default_rng(40 + ndim)
     shape, dx, dt = (10, 9, 8)[:ndim], (0.3, 0.25, 0.2)[:ndim], 0.05
-    g = _grid(ndim, shape, dx, dt)
+    g = _grid(ndim, shape, dx, dt, re_norm=1e-3)
     n = 60
     q1, m1, q2, m2 = 5.0, 30.0, -3.0, 3.0
-    o = Oracle(g, flags=FROZEN_FIELDS)
-    sid = o.add_species(Species(TWO_BODY, q1, m1, q2, m2, weight=0.7, omega_c=1.0, a_c=0.0,
-                                nu=0.1), n)
     w = rng.uniform(0.2, 2.0, n)
     x = rng.random((n, ndim)) * np.array(shape) * np.array(dx)
     u = rng.normal(scale=0.3, size=(n, 3))
-    o.load_particles(sid, Particles(x=x, u1=u, u2=u + rng.normal(scale=0.05, size=(n, 3)),
-                                    delta=rng.uniform(-0.05, 0.05, (n, 3)) * min(dx),
-                                    omega_c=rng.uniform(0.5, 3.0, n), weight=w))
-    o.step(1)
-    assert o.diagnostics()["error_word"] == 0
-    st = o.particles(sid)
+    u2 = u + rng.normal(scale=0.05, size=(n, 3))
+    delta = rng.uniform(-0.05, 0.05, (n, 3)) * min(dx)
+    wcs = rng.uniform(0.5, 3.0, n)
+
+    def run(omega_c):
+        o = Oracle(g, flags=FROZEN_FIELDS)
+        sid = o.add_species(Species(TWO_BODY, q1, m1, q2, m2, weight=0.7, omega_c=1.0,
+                                    a_c=0.0, nu=0.1), n)
+        o.load_particles(sid, Particles(x=x, u1=u, u2=u2, delta=delta, omega_c=omega_c,
+                                        weight=w))
+        o.step(1)
+        assert o.diagnostics()["error_word"] == 0
+        st = o.particles(sid)
+        _, _, J = o.fields()
+        o.close()
+        return st, J
+
+    st, J = run(wcs)
     v1 = st["u1"] / np.sqrt(1 + np.sum(st["u1"] ** 2, axis=1))[:, None]
     v2 = st["u2"] / np.sqrt(1 + np.sum(st["u2"] ** 2, axis=1))[:, None]
     expect = (w[:, None] * (q1 * v1 + q2 * v2)).sum(axis=0)
-    _, _, J = o.fields()
     tot = J.sum(axis=1) * float(np.prod(dx))
     assert np.allclose(tot, expect, rtol=1e-12, atol=1e-13)
     # a common weight instead of the per-particle ones is far off
     assert np.max(np.abs(tot - 0.7 * (q1 * v1 + q2 * v2).sum(axis=0))) > 1e-3
+    # the bond acts with each ion's own frequency
+    st1, _ = run(np.full(n, 1.0))
+    for k in ("u1", "u2"):
+        assert np.max(np.abs(st[k] - st1[k])) > 1e-5
 
 
 def test_esirkepov_axis_motion_and_symmetry():
