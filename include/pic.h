@@ -48,7 +48,7 @@ typedef enum {
   PIC_ENOMEM = -2,  /* allocator returned NULL or capacity exceeded */
   PIC_EHIP = -3,    /* HIP runtime error (text in pic_last_error) */
   PIC_ESTATE = -4,  /* call order misuse (e.g. particles before species) */
-  PIC_ERANGE = -5,  /* particle outside the domain or |delta_d| >= dx_d / 2 */
+  PIC_ERANGE = -5,  /* particle outside the domain, the walls or the body range */
   PIC_ENAN = -6     /* non-finite particle state */
 } pic_status;
 
@@ -75,12 +75,17 @@ typedef enum {
 
 /* Device error word bits (pic_diag.error_word).  A macro-particle whose
    state is non-finite (NAN) or outside the representable range (RANGE: an
-   offset outside [0, 1], or a two-body ion with |delta_d| >= dx_d / 2) at
-   the start of its cycle is left unchanged -- not advanced, no current --
-   and the bit is set.  One that leaves the range during its cycle (|delta_d|
-   reaching dx_d / 2, a jump of more than one node, a step out of the grid
-   along a non-periodic axis) is advanced and flagged; it stops at its next
-   cycle.  The bits stay set until the context is destroyed. */
+   offset outside [0, 1], or a body of a two-body ion more than one cell
+   beyond the particle walls along a non-periodic axis) at the start of its
+   cycle is left unchanged -- not advanced, no current -- and the bit is
+   set.  One that leaves the range during its cycle (a body past that
+   limit, a jump of more than one node, a step out of the grid along a
+   non-periodic axis) is advanced and flagged; it stops at its next cycle.
+   The bodies of a two-body ion may be any distance apart (Sec. 2: each body
+   has its own position): an ion whose bodies are half a cell or more apart
+   along a resolved axis is advanced from HBM with each body in the frame of
+   the cell that holds it.  The bits stay set until the context is
+   destroyed. */
 #define PIC_ERR_NAN 1u
 #define PIC_ERR_RANGE 2u
 
@@ -138,10 +143,14 @@ typedef struct {
    two-body: nucleus q1, m1 and combined bound electron q2 = -Z_b, m2 = Z_b
    (q1 = q_c - q2, m1 = m_c - m2); point: q1, m1 only.  weight = real
    particles per macro-particle (in units of n_c (c/omega)^ndim); it scales
-   only the deposited current, never the internal force.  omega_c is the
-   restoring frequency of Sec. 3.1; a_c the softening length
-   (0: derive a_c^3 = |q1 q2| re_norm / (m_r omega_c^2); +inf: harmonic
-   bond).  Friction on the relative momentum: nu + nu_per_omega * omega_c. */
+   only the deposited current, never the internal force.  omega_c (> 0) is
+   the restoring frequency of Sec. 3.1; a_c the softening length: 0 derives
+   a_c^3 = |q1 q2| re_norm / (m_r omega_c^2) (needs re_norm > 0), for each
+   ion from its own omega_c when the particles carry one, since the Sec. 2
+   potential has one Coulomb constant for all ions; +inf gives the harmonic
+   bond; a finite a_c > 0 is used as given, and then the species' ions
+   share its omega_c (per-particle omega_c is refused, PIC_EINVAL).
+   Friction on the relative momentum: nu + nu_per_omega * omega_c. */
 typedef struct {
   int32_t kind, reserved;
   double q1, m1, q2, m2;
@@ -160,6 +169,9 @@ typedef struct {
   int64_t n_particles;
   uint32_t error_word, reserved;
   int64_t n_outside_tile; /* particles of the last step advanced outside their tile */
+  int64_t n_far;          /* two-body ions of the last step whose bodies were half a
+                             cell or more apart (advanced from HBM, each body in the
+                             frame of its own cell) */
 } pic_diag;
 
 typedef struct pic_ctx pic_ctx;
@@ -182,11 +194,14 @@ int pic_add_species(pic_ctx* ctx, const pic_species_desc* desc, int32_t* species
           u1 is the centre-of-mass momentum per mass u_c and the bodies get
           the Sec. 2 split p1 + p2 = m_c u_c, q1 v1 + q2 v2 = 0
    u2     n x 3 or NULL
-   omega_c, weight: n values or NULL (species values)
+   omega_c, weight: n values or NULL (species values); omega_c > 0 and only
+          for a species whose a_c is derived or harmonic
    Positions are converted to (cell, offset) as xi = x/dx, cell = floor(xi),
    offset = xi - cell, then rounded to the context precision.  Particles
    are ordered by tile (stable).  PIC_ERANGE if outside the domain or the
-   walls, PIC_ENAN if non-finite, PIC_ENOMEM beyond capacity. */
+   walls, or (two-body) a body more than one cell beyond the walls along a
+   non-periodic axis; PIC_ENAN if non-finite, PIC_EINVAL for a bad omega_c,
+   PIC_ENOMEM beyond capacity. */
 int pic_load_particles(pic_ctx* ctx, int32_t species_id, int64_t n, const double* x,
                        const double* delta, const double* u1, const double* u2,
                        const double* omega_c, const double* weight);
@@ -307,6 +322,29 @@ int pic_grad_backward(pic_ctx* ctx, const double* dprobe, pic_grad* out);
    delta and u2).  HOST FP64; NULL outputs are skipped. */
 int pic_read_grad_particles(pic_ctx* ctx, int32_t species_id, double* d_x, double* d_delta,
                             double* d_u1, double* d_u2);
+
+/* Checkpoint and restart.  pic_save_state writes the whole state that
+   the following steps read -- E, B, the last step's J, the Mur history of
+   the open faces, every species' particles in their storage order with the
+   tile offsets of their last sort, per-particle omega_c and weight, load
+   ids, the sort policy's counters, the step counter and the device error
+   word -- into one HOST buffer: with host_buf NULL it only stores the size
+   needed in *bytes; otherwise *bytes is the buffer's size on entry and the
+   size written on return (PIC_EINVAL, with the size needed in *bytes, if it
+   is too small).  Synchronises.  Probes (configuration, not state) and
+   gradient runs are not saved.
+   pic_load_state puts such a buffer back into a context created with the
+   same pic_config (grid, precision, flags) and the same species (kinds,
+   charges, masses) added in the same order, each with room for the
+   state's particles; PIC_EINVAL if the buffer is not a state of such a
+   context, PIC_ENOMEM if a species' capacity is too small.  The particles
+   and fields the context held are replaced.  Run K steps, save, destroy,
+   create, load and run N - K: the same state as N steps in one run (bit
+   for bit wherever the run itself is: the FP32 fixed-point current with
+   every particle in its tile; FP64 LDS and global atomics sum in a varying
+   order).  The caller owns the buffer. */
+int pic_save_state(pic_ctx* ctx, void* host_buf, size_t* bytes);
+int pic_load_state(pic_ctx* ctx, const void* host_buf, size_t bytes);
 
 /* Text of the last error on ctx (or of the last failed pic_create if NULL). */
 const char* pic_last_error(const pic_ctx* ctx);

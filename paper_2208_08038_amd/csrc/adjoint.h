@@ -18,7 +18,9 @@ using AdjState = SpeciesDev<Real>;
 // the adjoint current (planes 6..8 of `lam`, whose planes 0..5 are the
 // adjoint E, B); updates the particle adjoint `lp` in place, adds the
 // gather's transpose into the adjoint E, B, and adds d/d(omega_c) and
-// d/d(friction rate) to dparam[0], dparam[1].
+// d/d(friction rate) to dparam[0], dparam[1].  Two-body ions whose bodies
+// are half a cell or more apart are not reversed; their number is added to
+// *dfar.
 // Tiles of the sorted particle order (cells per tile, tiles per dim).
 struct AdjTiles {
   int T[3];
@@ -36,7 +38,7 @@ size_t adjoint_lds_bytes(const GridInfo& g, const AdjTiles& tt, size_t rsize);
 template <typename Real>
 void launch_adjoint_push(const GridInfo& g, const Real* fields, const AdjState<Real>& st,
                          const PushConst<Real>& c, const AdjState<Real>& lp, Real* lam,
-                         double* dparam, const uint32_t* tile_off, const AdjTiles& tt,
-                         hipStream_t stream);
+                         double* dparam, double* dfar, const uint32_t* tile_off,
+                         const AdjTiles& tt, hipStream_t stream);
 
 }  // namespace pic

@@ -790,7 +790,7 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const Planes<Real
                                             const AdjState<Real>& lp, const Planes<Real>& l,
                                             int64_t p, const PIn<Real>& in,
                                             const TileBox<Real>& box, double& d_wc,
-                                            double& d_nu) {
+                                            double& d_nu, double& n_far) {
   do {
     // ---- stored state at the start of the step
     int ci[3] = {0, 0, 0};
@@ -811,19 +811,26 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const Planes<Real
     }
     const Real wc = in.wc;
     const Real W = in.w;
-    bool ok = true;
+    bool ok = true, near = true;
     Real x1[3] = {0, 0, 0}, x2[3] = {0, 0, 0};
 #pragma unroll
     for (int d = 0; d < ND; d++) {
       ok = ok && isfinite(off[d]) && off[d] >= Real(0) && off[d] <= Real(1);
       const Real sd = dl[d] * c.idx[d];
-      if (TWO) ok = ok && fabs(sd) < Real(0.5);
+      if (TWO) near = near && fabs(sd) < Real(0.5);
       x1[d] = off[d] + (TWO ? c.f1 * sd : Real(0));
       x2[d] = off[d] - (TWO ? c.f2 * sd : Real(0));
     }
 #pragma unroll
     for (int q = 0; q < 3; q++) ok = ok && isfinite(u1[q]) && isfinite(u2[q]) && isfinite(dl[q]);
     if (!ok) break;  // the forward cycle left it unchanged: identity
+    if (TWO && !near) {
+      // bodies half a cell or more apart: the forward took the far-body
+      // path, which this reverse cycle does not cover; counted, and the
+      // gradient run reports it
+      n_far += 1.0;
+      break;
+    }
     // where the fields, the adjoint current and the scatter live: the
     // tile's LDS copies for a particle in the tile (in 3D only the scatter,
     // the fields and adjoint current being read from the global planes),
@@ -865,11 +872,12 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const Planes<Real
     else
       gather_values<Real, ND>(f, wh, x1, G1, B1);
     Real E1[3], E2[3] = {0, 0, 0}, um1[3], um2[3] = {0, 0, 0};
-    Real r2 = 0, rq = 1, soft = 1, kf = 0;
+    Real r2 = 0, rq = 1, soft = 1, kf = 0, iac2 = 0;
     if (TWO) {
       r2 = dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2];
-      if (c.inv_ac2 != Real(0)) {
-        rq = rsq(Real(1) + r2 * c.inv_ac2);
+      iac2 = ion_inv_ac2(c, st.wc != nullptr, wc);
+      if (iac2 != Real(0)) {
+        rq = rsq(Real(1) + r2 * iac2);
         soft = rq * rq * rq;
       }
       kf = -c.mr * wc * wc * soft;
@@ -1068,12 +1076,17 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const Planes<Real
         lkf += lF * dl[q];
       }
       d_wc += (double)(lkf * Real(-2) * c.mr * wc * soft);
-      if (c.inv_ac2 != Real(0)) {
+      if (iac2 != Real(0)) {
         // soft = (1 + r2 / a_c^2)^{-3/2}
         const Real lsoft = lkf * (-c.mr * wc * wc);
-        const Real dsoft = Real(-1.5) * c.inv_ac2 * rq * rq * rq * rq * rq;
+        const Real rq5 = rq * rq * rq * rq * rq;
+        const Real dsoft = Real(-1.5) * iac2 * rq5;
 #pragma unroll
         for (int q = 0; q < 3; q++) l_dl[q] += Real(2) * dl[q] * lsoft * dsoft;
+        // a derived a_c moves with omega_c: 1/a_c^2 = ac_k omega_c^{4/3},
+        // d(1/a_c^2)/d omega_c = (4/3) (1/a_c^2) / omega_c
+        if (c.ac_k != Real(0))
+          d_wc += (double)(lsoft * (Real(-1.5) * r2 * rq5) * (Real(4) / Real(3)) * iac2 / wc);
       }
     }
     // gather
@@ -1112,21 +1125,23 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const Planes<Real
 template <typename Real, int ND, bool TWO>
 __global__ void __launch_bounds__(256)
     k_adjoint_push(GridInfo g, Planes<Real> f, AdjState<Real> st, PushConst<Real> c,
-                   AdjState<Real> lp, Planes<Real> l, double* dparam) {
+                   AdjState<Real> lp, Planes<Real> l, double* dparam, double* dfar) {
   __shared__ double sh[4];
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double d_wc = 0.0, d_nu = 0.0;
+  double d_wc = 0.0, d_nu = 0.0, n_far = 0.0;
   TileBox<Real> box{};
   if (p < st.n) {
     PIn<Real> in;
     load_in<Real, ND, TWO>(st, lp, c, p, in);
-    adjoint_one<Real, ND, TWO, false>(g, f, st, c, lp, l, p, in, box, d_wc, d_nu);
+    adjoint_one<Real, ND, TWO, false>(g, f, st, c, lp, l, p, in, box, d_wc, d_nu, n_far);
   }
   const double s_wc = block_sum<Real>(d_wc, sh);
   const double s_nu = block_sum<Real>(d_nu, sh);
+  const double s_far = block_sum<Real>(n_far, sh);
   if (threadIdx.x == 0) {
     if (s_wc != 0.0) atomicAdd(&dparam[0], s_wc);
     if (s_nu != 0.0) atomicAdd(&dparam[1], s_nu);
+    if (s_far != 0.0) atomicAdd(dfar, s_far);
   }
 }
 
@@ -1139,7 +1154,7 @@ __global__ void __launch_bounds__(256)
 template <typename Real, int ND, bool TWO>
 __global__ void __launch_bounds__(256)
     k_adjoint_tiled(GridInfo g, Planes<Real> f, AdjState<Real> st, PushConst<Real> c,
-                    AdjState<Real> lp, Planes<Real> l, double* dparam,
+                    AdjState<Real> lp, Planes<Real> l, double* dparam, double* dfar,
                     const uint32_t* tile_off, AdjTiles tt) {
   extern __shared__ double patch[];
   __shared__ double sh[4];
@@ -1174,7 +1189,7 @@ __global__ void __launch_bounds__(256)
     }
   }
   __syncthreads();
-  double d_wc = 0.0, d_nu = 0.0;
+  double d_wc = 0.0, d_nu = 0.0, n_far = 0.0;
   PIn<Real> in;
   int64_t p = p0 + threadIdx.x;
   if (p < p1) load_in<Real, ND, TWO>(st, lp, c, p, in);
@@ -1187,9 +1202,9 @@ __global__ void __launch_bounds__(256)
     const int cy = ND > 1 ? (int)((pk >> g.bits[0]) & ((1u << g.bits[1]) - 1u)) - box.y0 : 0;
     const int cz = ND > 2 ? (int)(pk >> (g.bits[0] + g.bits[1])) - box.z0 : 0;
     if (cx >= 0 && cx < box.tx && cy >= 0 && cy < box.ty && cz >= 0 && cz < box.tz)
-      adjoint_one<Real, ND, TWO, true>(g, f, st, c, lp, l, p, in, box, d_wc, d_nu);
+      adjoint_one<Real, ND, TWO, true>(g, f, st, c, lp, l, p, in, box, d_wc, d_nu, n_far);
     else
-      adjoint_one<Real, ND, TWO, false>(g, f, st, c, lp, l, p, in, box, d_wc, d_nu);
+      adjoint_one<Real, ND, TWO, false>(g, f, st, c, lp, l, p, in, box, d_wc, d_nu, n_far);
     in = nx;
   }
   __syncthreads();
@@ -1211,9 +1226,11 @@ __global__ void __launch_bounds__(256)
   }
   const double s_wc = block_sum<Real>(d_wc, sh);
   const double s_nu = block_sum<Real>(d_nu, sh);
+  const double s_far = block_sum<Real>(n_far, sh);
   if (threadIdx.x == 0) {
     if (s_wc != 0.0) atomicAdd(&dparam[0], s_wc);
     if (s_nu != 0.0) atomicAdd(&dparam[1], s_nu);
+    if (s_far != 0.0) atomicAdd(dfar, s_far);
   }
 }
 
@@ -1222,8 +1239,8 @@ __global__ void __launch_bounds__(256)
 template <typename Real>
 void launch_adjoint_push(const GridInfo& g, const Real* fields, const AdjState<Real>& st,
                          const PushConst<Real>& c, const AdjState<Real>& lp, Real* lam,
-                         double* dparam, const uint32_t* tile_off, const AdjTiles& tt,
-                         hipStream_t stream) {
+                         double* dparam, double* dfar, const uint32_t* tile_off,
+                         const AdjTiles& tt, hipStream_t stream) {
   if (st.n <= 0) return;
   const Planes<Real> f{const_cast<Real*>(fields), g.plane};
   const Planes<Real> l{lam, g.plane};
@@ -1237,7 +1254,7 @@ void launch_adjoint_push(const GridInfo& g, const Real* fields, const AdjState<R
       const void* fn = (const void*)k_adjoint_tiled<Real, ND_, TWO_>;                          \
       (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);     \
       hipLaunchKernelGGL((k_adjoint_tiled<Real, ND_, TWO_>), grid, 256, lds, stream, g, f, st,  \
-                         c, lp, l, dparam, tile_off, tt);                                      \
+                         c, lp, l, dparam, dfar, tile_off, tt);                                \
     }
     if (g.nd == 1 && two) PIC_ADJ_TILED(1, true)
     if (g.nd == 1 && !two) PIC_ADJ_TILED(1, false)
@@ -1251,7 +1268,7 @@ void launch_adjoint_push(const GridInfo& g, const Real* fields, const AdjState<R
   dim3 grid((unsigned)((st.n + 255) / 256));
 #define PIC_ADJ_GLOBAL(ND_, TWO_)                                                              \
   hipLaunchKernelGGL((k_adjoint_push<Real, ND_, TWO_>), grid, 256, 0, stream, g, f, st, c, lp, l, \
-                     dparam)
+                     dparam, dfar)
   if (g.nd == 1 && two) PIC_ADJ_GLOBAL(1, true);
   if (g.nd == 1 && !two) PIC_ADJ_GLOBAL(1, false);
   if (g.nd == 2 && two) PIC_ADJ_GLOBAL(2, true);
@@ -1278,10 +1295,11 @@ size_t adjoint_lds_bytes(const GridInfo& g, const AdjTiles& tt, size_t rsize) {
 
 template void launch_adjoint_push<float>(const GridInfo&, const float*, const AdjState<float>&,
                                          const PushConst<float>&, const AdjState<float>&, float*,
-                                         double*, const uint32_t*, const AdjTiles&, hipStream_t);
+                                         double*, double*, const uint32_t*, const AdjTiles&,
+                                         hipStream_t);
 template void launch_adjoint_push<double>(const GridInfo&, const double*, const AdjState<double>&,
                                           const PushConst<double>&, const AdjState<double>&,
-                                          double*, double*, const uint32_t*, const AdjTiles&,
-                                          hipStream_t);
+                                          double*, double*, double*, const uint32_t*,
+                                          const AdjTiles&, hipStream_t);
 
 }  // namespace pic

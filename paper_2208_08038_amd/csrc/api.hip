@@ -191,13 +191,23 @@ int load_particles_t(pic_ctx* c, SpeciesHost& s, int64_t n, const double* x, con
       } else {
         split_momentum(s.d.q1, s.d.m1, s.d.q2, s.d.m2, uu, &du1[p * 3], &du2[p * 3]);
       }
+      const double mc = s.d.m1 + s.d.m2;
       for (int a = 0; a < 3; a++) {
         double v = delta ? delta[3 * p + a] : 0.0;
         if (!std::isfinite(v)) return fail(c, PIC_ENAN, "non-finite delta");
-        if (a < nd && !(std::fabs(v) < 0.5 * c->cfg.dx[a]))
-          return fail(c, PIC_ERANGE, "|delta| must stay below half a cell");
+        // along walled axes each body stays within one cell beyond the walls
+        if (a < nd && !is_periodic(c->cfg, a)) {
+          const double X = x[p * nd + a] / c->cfg.dx[a];
+          const double X1 = X + (s.d.m2 / mc) * v / c->cfg.dx[a];
+          const double X2 = X - (s.d.m1 / mc) * v / c->cfg.dx[a];
+          const double lo = c->g.pad - 1, hi = c->g.n[a] - c->g.pad + 1;
+          if (!(X1 >= lo && X1 <= hi && X2 >= lo && X2 <= hi))
+            return fail(c, PIC_ERANGE, "a body is beyond one cell outside the particle walls");
+        }
         ddl[p * 3 + a] = v;
       }
+      if (wc && !(wc[p] > 0))
+        return fail(c, PIC_EINVAL, "per-particle omega_c must be positive");
     } else {
       for (int a = 0; a < 3; a++) du1[p * 3 + a] = uu[a];
     }
@@ -316,8 +326,13 @@ void harvest_counts(pic_ctx* c) {
   const int slot = c->counts_pending;
   c->counts_pending = -1;
   if (hipEventSynchronize(c->ev_counts[slot]) != hipSuccess) return;
-  for (size_t si = 0; si < c->sp.size(); si++)
-    c->sp[si]->listed_since_sort += (double)c->host_counts[64 * slot + si];
+  // ions listed only for their separation stay listed after a sort: they
+  // do not count toward the next one
+  for (size_t si = 0; si < c->sp.size(); si++) {
+    const uint32_t listed = c->host_counts[128 * slot + si];
+    const uint32_t far = c->host_counts[128 * slot + 64 + si];
+    c->sp[si]->listed_since_sort += (double)(listed >= far ? listed - far : 0u);
+  }
 }
 
 template <typename Real>
@@ -374,7 +389,10 @@ int advance_one(pic_ctx* c, const pic::LaserDev& las, const StepOpts& o,
   if (save) save(c, save_arg);
   pic::launch_zero<Real>(f.J[0], 3 * g.plane, c->stream);
   if (check) deposit_rho<Real>(c, c->rho0);
-  if (c->tiled) HIPCHK(c, hipMemsetAsync(c->nslow + 1, 0, 63 * sizeof(uint32_t), c->stream));
+  if (c->tiled) {
+    HIPCHK(c, hipMemsetAsync(c->nslow + 1, 0, 63 * sizeof(uint32_t), c->stream));
+    HIPCHK(c, hipMemsetAsync(c->nfar, 0, 64 * sizeof(uint32_t), c->stream));
+  }
   // a two-body and a point species share one tiled launch per tile colour
   // (one field staging and one current flush per tile for both)
   int pi = -1, pe = -1;
@@ -396,7 +414,7 @@ int advance_one(pic_ctx* c, const pic::LaserDev& las, const StepOpts& o,
     hipError_t e = pic::launch_push_tiled_pair<Real>(
         g, f, species_dev<Real>(*si), ci, si->sort.tile_off, si->outside, species_dev<Real>(*se),
         ce, se->sort.tile_off, se->outside, c->tg, c->nslow, c->nslow + 2 + pi,
-        c->nslow + 2 + pe, c->err, c->stream, hook);
+        c->nslow + 2 + pe, c->nfar + pi, c->err, c->stream, hook);
     if (e != hipSuccess)
       return fail(c, PIC_EHIP, std::string("tiled particle kernel: ") + hipGetErrorString(e));
     c->launches++;
@@ -412,7 +430,8 @@ int advance_one(pic_ctx* c, const pic::LaserDev& las, const StepOpts& o,
       hipError_t e = pic::launch_push_tiled<Real>(g, f, species_dev<Real>(*s),
                                                   push_const<Real>(c, *s), c->tg,
                                                   s->sort.tile_off, s->outside, c->nslow,
-                                                  c->nslow + 2 + si, c->err, c->stream, hook);
+                                                  c->nslow + 2 + si, c->nfar + si, c->err,
+                                                  c->stream, hook);
       if (e != hipSuccess)
         return fail(c, PIC_EHIP, std::string("tiled particle kernel: ") + hipGetErrorString(e));
     } else {
@@ -428,7 +447,10 @@ int advance_one(pic_ctx* c, const pic::LaserDev& las, const StepOpts& o,
   // the next step is enqueued
   if (c->tiled && c->sort_every == 0 && !c->sp.empty()) {
     const int slot = (int)(c->step & 1);
-    HIPCHK(c, hipMemcpyAsync(c->host_counts + 64 * slot, c->nslow + 2,
+    HIPCHK(c, hipMemcpyAsync(c->host_counts + 128 * slot, c->nslow + 2,
+                             c->sp.size() * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->host_counts + 128 * slot + 64, c->nfar,
                              c->sp.size() * sizeof(uint32_t), hipMemcpyDeviceToHost,
                              c->stream));
     HIPCHK(c, hipEventRecord(c->ev_counts[slot], c->stream));
@@ -526,13 +548,18 @@ int diagnostics_t(pic_ctx* c, pic_diag* out) {
     ke += k4[0];
     for (int a = 0; a < 3; a++) pm[a] += k4[1 + a];
   }
-  uint32_t ew = 0, nsl[kMaxSpecies] = {};
+  uint32_t ew = 0, nsl[kMaxSpecies] = {}, nfr[kMaxSpecies] = {};
   HIPCHK(c, hipMemcpyAsync(&ew, c->err, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(nsl, c->nslow + 2, kMaxSpecies * sizeof(uint32_t),
                            hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(nfr, c->nfar, kMaxSpecies * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                           c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  int64_t ns = 0;
-  for (size_t si = 0; si < c->sp.size(); si++) ns += nsl[si];
+  int64_t ns = 0, nf = 0;
+  for (size_t si = 0; si < c->sp.size(); si++) {
+    ns += nsl[si];
+    nf += nfr[si];
+  }
   out->step = c->step;
   out->time = (double)c->step * c->cfg.dt;
   out->kinetic_energy = ke;
@@ -540,6 +567,7 @@ int diagnostics_t(pic_ctx* c, pic_diag* out) {
   out->n_particles = np;
   out->error_word = ew;
   out->n_outside_tile = c->tiled ? (int64_t)ns : 0;
+  out->n_far = c->tiled ? (int64_t)nf : 0;
   if (ew & PIC_ERR_NAN) return fail(c, PIC_ENAN, "non-finite particle state on the device");
   if (ew & PIC_ERR_RANGE) return fail(c, PIC_ERANGE, "particle out of range on the device");
   return PIC_OK;
@@ -667,6 +695,17 @@ int rho_t(pic_ctx* c, double* rho) {
   return PIC_OK;
 }
 
+}  // namespace
+
+// A fixed finite a_c given with omega_c fixes the bond's Coulomb constant
+// (Sec. 2 / Sec. 3.1), so the ions of such a species share one omega_c;
+// per-particle omega_c needs a derived a_c or the harmonic bond.
+static bool own_omega_allowed(const SpeciesHost& s) {
+  return s.d.kind != PIC_TWO_BODY || s.ac_derived || std::isinf(s.a_c);
+}
+static const char* const omega_fixed_msg =
+    "per-particle omega_c needs a_c = 0 (derived per ion) or a_c = +inf (harmonic)";
+
 // allocate the optional per-particle arrays on the first load that brings them
 int prepare_optional(pic_ctx* c, SpeciesHost& s, bool want_wc, bool want_w) {
   size_t rs = c->rsize, cap = (size_t)s.cap;
@@ -688,7 +727,7 @@ int prepare_optional(pic_ctx* c, SpeciesHost& s, bool want_wc, bool want_w) {
   return PIC_OK;
 }
 
-}  // namespace
+void harvest_pending_counts(pic_ctx* c) { harvest_counts(c); }
 
 // ================================================================ C ABI
 
@@ -787,11 +826,12 @@ int pic_create(const pic_config* cfg, const pic_allocator* alloc, void* hip_stre
   c->err = static_cast<uint32_t*>(dev_alloc(c, 256));
   c->load_err = static_cast<uint32_t*>(dev_alloc(c, 256));
   c->nslow = static_cast<uint32_t*>(dev_alloc(c, 256));
+  c->nfar = static_cast<uint32_t*>(dev_alloc(c, 256));
   c->partials = static_cast<double*>(dev_alloc(c, 8 * pic::reduce_blocks() * sizeof(double)));
   c->dout = static_cast<double*>(dev_alloc(c, 32 * sizeof(double)));
   c->rho0 = static_cast<double*>(dev_alloc(c, g.plane * sizeof(double)));
   c->rho1 = static_cast<double*>(dev_alloc(c, g.plane * sizeof(double)));
-  if (!c->fields || !c->err || !c->load_err || !c->nslow || !c->partials || !c->dout || !c->rho0 || !c->rho1) {
+  if (!c->fields || !c->err || !c->load_err || !c->nslow || !c->nfar || !c->partials || !c->dout || !c->rho0 || !c->rho1) {
     dev_free_all(c);
     delete c;
     return fail(nullptr, PIC_ENOMEM, "device allocation failed");
@@ -813,6 +853,7 @@ int pic_create(const pic_config* cfg, const pic_allocator* alloc, void* hip_stre
   hipError_t e = hipMemsetAsync(c->fields, 0, 9 * g.plane * rs, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->err, 0, 256, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->nslow, 0, 256, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->nfar, 0, 256, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->dout, 0, 32 * sizeof(double), c->stream);
   for (int d = 0; d < g.nd && e == hipSuccess; d++) {
     if (g.periodic[d]) continue;
@@ -823,7 +864,7 @@ int pic_create(const pic_config* cfg, const pic_allocator* alloc, void* hip_stre
       if (e == hipSuccess) e = hipMemsetAsync(c->mur_e[d][t], 0, np * rs, c->stream);
     }
   }
-  if (e == hipSuccess) e = hipHostMalloc((void**)&c->host_counts, 2 * 64 * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->host_counts, 2 * 128 * sizeof(uint32_t));
   for (int t = 0; t < 2 && e == hipSuccess; t++) e = hipEventCreate(&c->ev_counts[t]);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
@@ -853,6 +894,8 @@ int pic_add_species(pic_ctx* c, const pic_species_desc* d, int32_t* sid) {
   if (two) {
     if (!(d->m2 > 0) || d->q2 == 0.0) return fail(c, PIC_EINVAL, "bad bound-electron charge/mass");
     if (!(d->omega_c > 0)) return fail(c, PIC_EINVAL, "omega_c must be positive");
+    if (std::isnan(d->a_c) || d->a_c < 0)
+      return fail(c, PIC_EINVAL, "a_c must be 0 (derived), positive or +inf");
     double mr = d->m1 * d->m2 / (d->m1 + d->m2);
     if (std::isinf(d->a_c))
       s.a_c = std::numeric_limits<double>::infinity();
@@ -863,6 +906,7 @@ int pic_add_species(pic_ctx* c, const pic_species_desc* d, int32_t* sid) {
       // Coulomb constant being re_norm in these units
       if (!(c->cfg.re_norm > 0)) return fail(c, PIC_EINVAL, "a_c = 0 needs re_norm > 0");
       s.a_c = std::cbrt(std::fabs(d->q1 * d->q2) * c->cfg.re_norm / (mr * d->omega_c * d->omega_c));
+      s.ac_derived = true;  // and each ion's own from its own omega_c
     }
   }
   size_t rs = c->rsize, n = (size_t)s.cap;
@@ -906,6 +950,8 @@ int pic_load_particles(pic_ctx* c, int32_t sid, int64_t n, const double* x, cons
   SpeciesHost& s = *c->sp[sid];
   if (s.n + n > s.cap) return fail(c, PIC_ENOMEM, "species capacity exceeded");
   if (n == 0) return PIC_OK;
+  if (omega_c && !own_omega_allowed(s))
+    return fail(c, PIC_EINVAL, omega_fixed_msg);
   int rc = prepare_optional(c, s, omega_c != nullptr, weight != nullptr);
   if (rc) return rc;
   if (c->prec == 32) return load_particles_t<float>(c, s, n, x, delta, u1, u2, omega_c, weight);
@@ -922,6 +968,8 @@ int pic_load_particles_device(pic_ctx* c, int32_t sid, int64_t n, const double* 
   SpeciesHost& s = *c->sp[sid];
   if (s.n + n > s.cap) return fail(c, PIC_ENOMEM, "species capacity exceeded");
   if (n == 0) return PIC_OK;
+  if (omega_c && !own_omega_allowed(s))
+    return fail(c, PIC_EINVAL, omega_fixed_msg);
   int rc = prepare_optional(c, s, omega_c != nullptr, weight != nullptr);
   if (rc) return rc;
   pic::LoadSrc src{x, delta, u1, u2, omega_c, weight, n};

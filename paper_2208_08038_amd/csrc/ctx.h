@@ -22,7 +22,8 @@ struct GradState;  // gradient run: checkpoints, adjoint arrays (grad.hip)
 
 struct SpeciesHost {
   pic_species_desc d{};
-  double a_c = 0.0;  // effective softening length (inf: harmonic)
+  double a_c = 0.0;  // softening length at the species' omega_c (inf: harmonic)
+  bool ac_derived = false;  // a_c of each ion from its own omega_c (Sec. 3.1)
   int64_t n = 0, cap = 0;
   bool has_wc = false, has_w = false;
   double max_w = 0.0;  // largest |per-particle weight| loaded (has_w)
@@ -60,7 +61,8 @@ struct pic_ctx {
   uint32_t* err = nullptr;
   uint32_t* load_err = nullptr;
   uint32_t* nslow = nullptr;   // [0], [1]: list length scratch, [2 + s]: species s listed this step
-  uint32_t* host_counts = nullptr;  // pinned: 2 slots of the per-species counts
+  uint32_t* nfar = nullptr;    // [s]: ions of species s listed this step for their separation
+  uint32_t* host_counts = nullptr;  // pinned: 2 slots of 128 (listed, then far) per-species counts
   hipEvent_t ev_counts[2] = {nullptr, nullptr};
   int counts_pending = -1;          // slot whose copy is in flight, or -1
   bool tiled = false;
@@ -172,6 +174,10 @@ pic::PushConst<Real> push_const(const pic_ctx* c, const SpeciesHost& s) {
   k.inv_q1 = (Real)(1.0 / d.q1);
   k.inv_q2 = two ? (Real)(1.0 / d.q2) : Real(0);
   k.inv_ac2 = std::isinf(s.a_c) ? Real(0) : (Real)(1.0 / (s.a_c * s.a_c));
+  // a_c^3 = C / omega_c^2 with C fixed: 1/a_c^2 = (omega_c^{4/3}) / C^{2/3}
+  k.ac_k = two && s.ac_derived
+               ? (Real)(1.0 / (s.a_c * s.a_c * std::pow(d.omega_c, 4.0 / 3.0)))
+               : Real(0);
   k.omega_c = (Real)d.omega_c;
   k.nu = (Real)d.nu;
   k.nu_per_omega = (Real)d.nu_per_omega;
@@ -225,6 +231,14 @@ inline pic::LaserDev laser_dev(const pic_ctx* c) {
   for (int k = 0; k < 64; k++) las.env[k] = k < L.n_env ? L.env[k] : 0.0;
   return las;
 }
+
+// Allocate a species' per-particle omega_c / weight arrays (and their sort
+// buffers) on the first load that brings them; fails once particles exist.
+int prepare_optional(pic_ctx* c, SpeciesHost& s, bool want_wc, bool want_w);
+
+// Add the outside-tile counts of the last enqueued step to the sort policy
+// (waits for that step's particle kernels).
+void harvest_pending_counts(pic_ctx* c);
 
 // Record a start (or stop) event of a timed particle-kernel dispatch with
 // the given tag (species index; PIC_TIMING_ADJOINT + species for the

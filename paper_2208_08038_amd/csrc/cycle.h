@@ -613,6 +613,49 @@ __device__ __forceinline__ void boris_rotate_kick(const Real um[3], Real a, cons
   out[2] = um[2] + (w0 * s1 - w1 * s0) + a * E[2];
 }
 
+// Internal force, friction and Boris push of both bodies of an ion
+// (Sec. 2).  E1, B1 and E2, B2 are the fields gathered at the bodies; the
+// softened Coulomb force F1 = -m_r w_c^2 delta (1 + |delta|^2/a_c^2)^{-3/2}
+// acts as extra E (+F/q1 on the nucleus, -F/q2 on the cloud); the friction
+// (rate nu + nu_per_omega w_c) is time-centred on the relative momentum
+// between the half kicks and keeps m1 u1 + m2 u2.  n1, n2: new momenta.
+template <typename Real>
+__device__ __forceinline__ void two_body_kick(const PushConst<Real>& c, Real wc, Real iac2,
+                                              const Real dl[3], const Real u1[3],
+                                              const Real u2[3], Real E1[3], const Real B1[3],
+                                              Real E2[3], const Real B2[3], Real n1[3],
+                                              Real n2[3]) {
+  const Real r2 = dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2];
+  Real soft = Real(1);
+  if (iac2 != Real(0)) {
+    const Real rq = rsqrt1(Real(1) + r2 * iac2);
+    soft = rq * rq * rq;
+  }
+  const Real kf = -c.mr * wc * wc * soft;
+  Real um1[3], um2[3];
+#pragma unroll
+  for (int q = 0; q < 3; q++) {
+    const Real F = kf * dl[q];
+    E1[q] += F * c.inv_q1;
+    E2[q] -= F * c.inv_q2;
+    um1[q] = u1[q] + c.a1 * E1[q];
+    um2[q] = u2[q] + c.a2 * E2[q];
+  }
+  const Real nu = c.nu + c.nu_per_omega * wc;
+  if (nu > Real(0)) {
+    const Real D = (Real(1) - nu * c.half_dt) * recip(Real(1) + nu * c.half_dt);
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+      const Real V = (c.m1 * um1[q] + c.m2 * um2[q]) * c.inv_mc;
+      const Real w = (um1[q] - um2[q]) * D;
+      um1[q] = V + c.f1 * w;
+      um2[q] = V - c.f2 * w;
+    }
+  }
+  boris_rotate_kick(um1, c.a1, E1, B1, n1);
+  boris_rotate_kick(um2, c.a2, E2, B2, n2);
+}
+
 // Reflecting walls `pad` cells inside non-periodic faces.  off: new offset
 // relative to the old cell index ci (before the crossing rule).
 template <typename Real>
@@ -713,6 +756,153 @@ __device__ __forceinline__ void load_state(const SpeciesDev<Real>& s, const Push
   st.w = s.w ? s.w[p] : Real(1);
 }
 
+// Along an axis with walls each body of an ion stays where every node its
+// shape reaches is interior: within one cell beyond the walls `pad` cells
+// inside the faces.  y: body positions relative to the cell ci.
+template <typename Real, int ND>
+__device__ __forceinline__ bool body_in_range(const GridInfo& g, const int ci[3],
+                                              const Real y[3]) {
+  bool ok = true;
+#pragma unroll
+  for (int d = 0; d < ND; d++) {
+    if (g.periodic[d]) continue;
+    const Real X = Real(ci[d]) + y[d];
+    ok = ok && X >= Real(g.pad - 1) && X <= Real(g.n[d] - g.pad + 1);
+  }
+  return ok;
+}
+
+// Frame of a body at x (cell units, relative to the centre's cell ci): the
+// cell that holds it (wrapped along periodic axes) as a storage index, and
+// the offset there (x - floor(x), exact); k is the shift floor(x).
+template <typename Real, int ND>
+__device__ __forceinline__ int body_frame(const GridInfo& g, const int ci[3], const Real x[3],
+                                          Real bx[3], int k[3]) {
+  int64_t base = g.origin;
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    bx[d] = Real(0);
+    k[d] = 0;
+  }
+#pragma unroll
+  for (int d = 0; d < ND; d++) {
+    const Real f = floor(x[d]);
+    k[d] = static_cast<int>(f);
+    bx[d] = x[d] - f;
+    int b = ci[d] + k[d];
+    if (g.periodic[d]) {
+      b %= g.n[d];
+      if (b < 0) b += g.n[d];
+    }
+    base += (int64_t)b * (d == 0 ? 1 : (d == 1 ? g.sy : g.sz));
+  }
+  return (int)base;
+}
+
+// One cycle of a two-body ion whose bodies are half a cell or more apart
+// along a resolved axis (Sec. 2: each body has its own position and
+// momentum).  Each body is gathered and deposited from HBM in the frame of
+// the cell that holds it (guard layers cover a window of any body in an
+// interior cell; global atomics for the current); the centre of mass keeps
+// the cell index, walls and crossing rule of the near path.  x1, x2: body
+// positions relative to the centre's cell.
+template <typename Real, int ND>
+__device__ __noinline__ void advance_far(const GridInfo& g, const SpeciesDev<Real>& s,
+                                         const PushConst<Real>& c, int64_t p,
+                                         const PState<Real>& st, const int ci[3],
+                                         const Real x1[3], const Real x2[3],
+                                         const FieldPtrs<Real>& f, uint32_t* err) {
+  if (!body_in_range<Real, ND>(g, ci, x1) || !body_in_range<Real, ND>(g, ci, x2)) {
+    atomicOr(err, PIC_ERR_RANGE);  // left untouched
+    return;
+  }
+  const int sy = (int)g.sy, sz = (int)g.sz;
+  Real b1[3], b2[3];
+  int k1[3], k2[3];
+  const int base1 = body_frame<Real, ND>(g, ci, x1, b1, k1);
+  const int base2 = body_frame<Real, ND>(g, ci, x2, b2, k2);
+  Real E1[3], B1[3], E2[3], B2[3];
+  gather<Real, ND>(f, base1, sy, sz, b1, E1, B1);
+  gather<Real, ND>(f, base2, sy, sz, b2, E2, B2);
+  Real u1[3], u2[3], dl[3], off[3] = {0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < 3; q++) {
+    u1[q] = st.u1[q];
+    u2[q] = st.u2[q];
+    dl[q] = st.dl[q];
+  }
+#pragma unroll
+  for (int d = 0; d < ND; d++) off[d] = st.off[d];
+  const Real wc = st.wc;
+  Real n1[3], n2[3];
+  two_body_kick(c, wc, ion_inv_ac2(c, s.wc != nullptr, wc), dl, u1, u2, E1, B1, E2, B2, n1, n2);
+  const Real ig1 = rsqrt1(Real(1) + n1[0] * n1[0] + n1[1] * n1[1] + n1[2] * n1[2]);
+  const Real ig2 = rsqrt1(Real(1) + n2[0] * n2[0] + n2[1] * n2[1] + n2[2] * n2[2]);
+  Real v1[3], v2[3];
+#pragma unroll
+  for (int q = 0; q < 3; q++) {
+    v1[q] = n1[q] * ig1;
+    v2[q] = n2[q] * ig2;
+    dl[q] = dl[q] + c.dt * (v1[q] - v2[q]);
+  }
+  Real offn[3] = {0, 0, 0};
+#pragma unroll
+  for (int d = 0; d < ND; d++) {
+    offn[d] = off[d] + c.dt * (c.m1 * v1[d] + c.m2 * v2[d]) * c.inv_mc * c.idx[d];
+    if (reflect(g.periodic[d], ci[d], g.n[d], g.pad, offn[d])) {
+      n1[d] = -n1[d];
+      n2[d] = -n2[d];
+      dl[d] = -dl[d];
+    }
+  }
+  Real y1[3] = {0, 0, 0}, y2[3] = {0, 0, 0};
+#pragma unroll
+  for (int d = 0; d < ND; d++) {
+    const Real sd = dl[d] * c.idx[d];
+    y1[d] = offn[d] + c.f1 * sd;
+    y2[d] = offn[d] - c.f2 * sd;
+  }
+  bool range_ok = body_in_range<Real, ND>(g, ci, y1) && body_in_range<Real, ND>(g, ci, y2);
+  if (c.deposit) {
+    const Real W = st.w;
+    const Real qw1 = s.w ? c.q1 * W : c.qw1;
+    const Real qw2 = s.w ? c.q2 * W : c.qw2;
+    // new positions in each body's old frame
+    Real z1[3] = {0, 0, 0}, z2[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < ND; d++) {
+      z1[d] = y1[d] - Real(k1[d]);
+      z2[d] = y2[d] - Real(k2[d]);
+    }
+    Real* const J[3] = {f.J[0], f.J[1], f.J[2]};
+    range_ok = deposit<Real, ND, true, Real>(J, base1, sy, sz, b1, z1, qw1, v1, c) && range_ok;
+    range_ok = deposit<Real, ND, true, Real>(J, base2, sy, sz, b2, z2, qw2, v2, c) && range_ok;
+  }
+  int cn[3] = {ci[0], ci[1], ci[2]};
+#pragma unroll
+  for (int d = 0; d < ND; d++) {
+    const int keep = cn[d];
+    Real o = offn[d];
+    if (cross(g.periodic[d], g.n[d], cn[d], o)) {
+      offn[d] = o;
+    } else {
+      cn[d] = keep;
+      range_ok = false;
+    }
+  }
+  if (!range_ok) atomicOr(err, PIC_ERR_RANGE);
+  if (!(finite3(n1) && finite3(n2) && finite3(dl))) atomicOr(err, PIC_ERR_NAN);
+  s.cell[p] = encode_cell<ND>(g, cn);
+#pragma unroll
+  for (int d = 0; d < ND; d++) s.off[d][p] = offn[d];
+#pragma unroll
+  for (int q = 0; q < 3; q++) {
+    s.u1[q][p] = n1[q];
+    s.u2[q][p] = n2[q];
+    s.dl[q][p] = dl[q];
+  }
+}
+
 // Advance macro-particle p through one full cycle.  Gather reads E, B
 // through `fg` at index `fbase` of the particle's cell (strides fsy, fsz);
 // the deposit adds into J at `jbase` (strides jsy, jsz).  GLOBAL selects
@@ -745,14 +935,14 @@ __device__ __forceinline__ void advance_particle(const GridInfo& g, const Specie
   // body positions (cell units, relative to the cell)
   Real x1[3] = {0, 0, 0}, x2[3] = {0, 0, 0};
   bool finite = finite3(u1) && finite3(u2) && finite3(dl);
-  bool inside = true;
+  bool inside = true, near = true;
 #pragma unroll
   for (int d = 0; d < ND; d++) {
     finite = finite && isfinite(off[d]);
     inside = inside && (off[d] >= Real(0)) && (off[d] <= Real(1));
     if constexpr (TWO) {
       Real sd = dl[d] * c.idx[d];
-      inside = inside && (fabs(sd) < Real(0.5));
+      near = near && (fabs(sd) < Real(0.5));
       x1[d] = off[d] + c.f1 * sd;
       x2[d] = off[d] - c.f2 * sd;
     } else {
@@ -764,17 +954,20 @@ __device__ __forceinline__ void advance_particle(const GridInfo& g, const Specie
     atomicOr(err, finite ? PIC_ERR_RANGE : PIC_ERR_NAN);
     return;
   }
+  if constexpr (TWO) {
+    if (!near) {
+      // bodies half a cell or more apart: each in its own cell frame, from
+      // HBM (the tiled kernel lists such ions for the HBM pass)
+      if constexpr (GLOBAL)
+        advance_far<Real, ND>(g, s, c, p, st, ci, x1, x2, fg, err);
+      else
+        atomicOr(err, PIC_ERR_RANGE);
+      return;
+    }
+  }
 
   if constexpr (TWO) {
     const Real wc = st.wc;
-    // softened Coulomb bond: F1 = -m_r w_c^2 delta (1 + |delta|^2/a_c^2)^{-3/2}
-    Real r2 = dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2];
-    Real soft = Real(1);
-    if (c.inv_ac2 != Real(0)) {
-      Real rq = rsqrt1(Real(1) + r2 * c.inv_ac2);
-      soft = rq * rq * rq;
-    }
-    const Real kf = -c.mr * wc * wc * soft;
     // one body at a time (loop not unrolled: a single copy of the gather
     // keeps the live register set small); E and B are kept per body for
     // the second half kick
@@ -798,30 +991,9 @@ __device__ __forceinline__ void advance_particle(const GridInfo& g, const Specie
       }
     }
     }
-    Real um1[3], um2[3];
-#pragma unroll
-    for (int q = 0; q < 3; q++) {
-      Real F = kf * dl[q];
-      E1[q] += F * c.inv_q1;
-      E2[q] -= F * c.inv_q2;
-      um1[q] = u1[q] + c.a1 * E1[q];
-      um2[q] = u2[q] + c.a2 * E2[q];
-    }
-    const Real nu = c.nu + c.nu_per_omega * wc;
-    if (nu > Real(0)) {
-      // time-centred friction on the relative momentum; m1 u1 + m2 u2 kept
-      Real D = (Real(1) - nu * c.half_dt) * recip(Real(1) + nu * c.half_dt);
-#pragma unroll
-      for (int q = 0; q < 3; q++) {
-        Real V = (c.m1 * um1[q] + c.m2 * um2[q]) * c.inv_mc;
-        Real w = (um1[q] - um2[q]) * D;
-        um1[q] = V + c.f1 * w;
-        um2[q] = V - c.f2 * w;
-      }
-    }
     Real n1[3], n2[3];
-    boris_rotate_kick(um1, c.a1, E1, B1, n1);
-    boris_rotate_kick(um2, c.a2, E2, B2, n2);
+    two_body_kick(c, wc, ion_inv_ac2(c, s.wc != nullptr, wc), dl, u1, u2, E1, B1, E2, B2, n1,
+                  n2);
     Real ig1 = rsqrt1(Real(1) + n1[0] * n1[0] + n1[1] * n1[1] + n1[2] * n1[2]);
     Real ig2 = rsqrt1(Real(1) + n2[0] * n2[0] + n2[1] * n2[1] + n2[2] * n2[2]);
     Real v1[3], v2[3];
@@ -842,17 +1014,18 @@ __device__ __forceinline__ void advance_particle(const GridInfo& g, const Specie
         dl[d] = -dl[d];
       }
     }
-    bool range_ok = true;
+    Real y1[3] = {0, 0, 0}, y2[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < ND; d++) {
+      Real sd = dl[d] * c.idx[d];
+      y1[d] = offn[d] + c.f1 * sd;
+      y2[d] = offn[d] - c.f2 * sd;
+    }
+    // along walled axes the bodies stay within one cell beyond the walls
+    bool range_ok = body_in_range<Real, ND>(g, ci, y1) && body_in_range<Real, ND>(g, ci, y2);
     if (c.deposit) {
       const Real qw1 = s.w ? c.q1 * W : c.qw1;
       const Real qw2 = s.w ? c.q2 * W : c.qw2;
-      Real y1[3] = {0, 0, 0}, y2[3] = {0, 0, 0};
-#pragma unroll
-      for (int d = 0; d < ND; d++) {
-        Real sd = dl[d] * c.idx[d];
-        y1[d] = offn[d] + c.f1 * sd;
-        y2[d] = offn[d] - c.f2 * sd;
-      }
       const Real* xs[4] = {x1, x2, y1, y2};
       int nn[3];
       const bool pair = common_node<Real, ND>(xs, 4, nn);
@@ -894,7 +1067,6 @@ __device__ __forceinline__ void advance_particle(const GridInfo& g, const Specie
     int cn[3] = {ci[0], ci[1], ci[2]};
 #pragma unroll
     for (int d = 0; d < ND; d++) {
-      range_ok = range_ok && (fabs(dl[d] * c.idx[d]) < Real(0.5));
       int keep = cn[d];
       Real o = offn[d];
       if (cross(g.periodic[d], g.n[d], cn[d], o)) {

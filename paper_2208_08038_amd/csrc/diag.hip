@@ -156,7 +156,9 @@ __global__ void __launch_bounds__(RB) k_kinetic(SpeciesDev<Real> s, PushConst<Re
 }
 
 // charge density at integer nodes: both bodies (or the point particle)
-// with the quadratic B-spline, FP64 atomics into a guarded FP64 plane
+// with the quadratic B-spline, FP64 atomics into a guarded FP64 plane; each
+// body in the frame of the cell that holds it (wrapped along periodic
+// axes), so bodies may be any distance from their centre of mass
 template <typename Real, int ND>
 __global__ void __launch_bounds__(256) k_rho(GridInfo g, SpeciesDev<Real> s, PushConst<Real> c,
                                              double* rho) {
@@ -167,7 +169,6 @@ __global__ void __launch_bounds__(256) k_rho(GridInfo g, SpeciesDev<Real> s, Pus
   ci[0] = packed & ((1u << g.bits[0]) - 1u);
   ci[1] = ND > 1 ? (packed >> g.bits[0]) & ((1u << g.bits[1]) - 1u) : 0;
   ci[2] = ND > 2 ? (packed >> (g.bits[0] + g.bits[1])) : 0;
-  int64_t base = g.origin + ci[0] + (int64_t)ci[1] * g.sy + (int64_t)ci[2] * g.sz;
   double dv = 1.0;
   for (int d = 0; d < ND; d++) dv *= g.dx[d];
   double W = s.w ? (double)s.w[p] : 1.0;
@@ -176,6 +177,7 @@ __global__ void __launch_bounds__(256) k_rho(GridInfo g, SpeciesDev<Real> s, Pus
     double Q = s.w ? (body == 0 ? (double)c.q1 : (double)c.q2) * W
                    : (body == 0 ? (double)c.qw1 : (double)c.qw2);
     double x[3] = {0, 0, 0};
+    int64_t base = g.origin;
     bool ok = true;
     for (int d = 0; d < ND; d++) {
       double o = s.off[d][p];
@@ -185,7 +187,18 @@ __global__ void __launch_bounds__(256) k_rho(GridInfo g, SpeciesDev<Real> s, Pus
       } else {
         x[d] = o;
       }
-      ok = ok && isfinite(x[d]) && x[d] > -1.0 && x[d] < 2.0;
+      ok = ok && isfinite(x[d]);
+      if (!ok) break;
+      const double k = floor(x[d]);
+      x[d] -= k;
+      int b = ci[d] + (int)k;
+      if (g.periodic[d]) {
+        b %= g.n[d];
+        if (b < 0) b += g.n[d];
+      }
+      // nodes b - 1 .. b + 2 must lie in the guarded storage
+      ok = ok && b >= -2 && b <= g.n[d];
+      base += (int64_t)b * (d == 0 ? 1 : (d == 1 ? g.sy : g.sz));
     }
     if (!ok) continue;
     int i0[3] = {0, 0, 0};

@@ -84,6 +84,10 @@ size_t face_bytes(const pic_ctx* c, int d) {
 
 }  // namespace
 
+// slot of the gradient buffer that counts ions the reverse cycle skipped
+// because their bodies were far apart (2 * 62 species + 64 coefficients < 255)
+constexpr int kFarSlot = 255;
+
 struct GradState {
   int64_t nsteps = 0, step0 = 0, rec0 = 0;
   int K = 0;
@@ -99,7 +103,7 @@ struct GradState {
   void* lam_mur_b[3][2] = {};     // adjoint of the Mur history of the low faces
   void* lam_mur_e[3][2] = {};     // adjoint of the saved high-face E (within a step)
   std::vector<void*> lam_sp;      // per species: adjoint offsets, delta, u1, u2
-  double* dgrad = nullptr;        // [2 * nspecies + 64]: d omega_c, d nu, d env
+  double* dgrad = nullptr;        // [2 * nspecies + 64]: d omega_c, d nu, d env; [kFarSlot]
   double* dprobe = nullptr;
   size_t dprobe_cap = 0;
   // buffers are kept for the next run when the state has the same size
@@ -462,8 +466,8 @@ int grad_backward_t(pic_ctx* c, const double* dprobe, pic_grad* out) {
         const uint32_t* toff = tiled ? s.sort.tile_off : nullptr;
         pic::launch_adjoint_push<Real>(g, fslot, snap_state<Real>(c, slot, si),
                                        push_const<Real>(c, s), lam_state<Real>(c, si),
-                                       static_cast<Real*>(G.lam_fields), G.dgrad + 2 * si, toff,
-                                       tt, c->stream);
+                                       static_cast<Real*>(G.lam_fields), G.dgrad + 2 * si,
+                                       G.dgrad + kFarSlot, toff, tt, c->stream);
         if (timed) record_event(c, PIC_TIMING_ADJOINT + (int)si, false);
       }
       // E, B guard fill at the start of the step, transposed
@@ -477,6 +481,10 @@ int grad_backward_t(pic_ctx* c, const double* dprobe, pic_grad* out) {
   HIPCHK(c, hipMemcpyAsync(dg.data(), G.dgrad, 256 * sizeof(double), hipMemcpyDeviceToHost,
                            c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (dg[kFarSlot] > 0.0)
+    return fail(c, PIC_ERANGE,
+                "the gradient run met two-body ions whose bodies are half a cell or more "
+                "apart, which its reverse cycle does not cover");
   for (size_t si = 0; si < c->sp.size(); si++) {
     const pic_species_desc& d = c->sp[si]->d;
     const double dwc = dg[2 * si], dnu = dg[2 * si + 1];

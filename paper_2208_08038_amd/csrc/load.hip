@@ -110,11 +110,20 @@ __global__ void __launch_bounds__(256) k_load(GridInfo g, LoadSrc src, SpeciesDe
       double uc[3] = {u1[0], u1[1], u1[2]};
       split_dev(sp.q1, sp.m1, sp.q2, sp.m2, uc, u1, u2);
     }
+    const double mc = sp.m1 + sp.m2;
     for (int a = 0; a < 3; a++) {
       dl[a] = src.delta ? src.delta[3 * p + a] : 0.0;
       if (!isfinite(dl[a])) bad |= PIC_ERR_NAN;
-      if (a < ND && !(fabs(dl[a]) < 0.5 * g.dx[a])) bad |= PIC_ERR_RANGE;
+      // along walled axes each body stays within one cell beyond the walls
+      if (a < ND && !g.periodic[a] && !bad) {
+        const double X = src.x[p * ND + a] / g.dx[a];
+        const double X1 = X + (sp.m2 / mc) * dl[a] / g.dx[a];
+        const double X2 = X - (sp.m1 / mc) * dl[a] / g.dx[a];
+        const double lo = g.pad - 1, hi = g.n[a] - g.pad + 1;
+        if (!(X1 >= lo && X1 <= hi && X2 >= lo && X2 <= hi)) bad |= PIC_ERR_RANGE;
+      }
     }
+    if (src.wc && !(src.wc[p] > 0.0)) bad |= PIC_ERR_RANGE;
   }
   if (bad) {
     atomicOr(err, bad);

@@ -68,7 +68,11 @@ struct PushConst {
   Real f1, f2;     // m2/mc, m1/mc: body offsets from the centre of mass
   Real mr;         // reduced mass
   Real inv_q1, inv_q2;
-  Real inv_ac2;    // 1/a_c^2, 0 for the harmonic bond
+  Real inv_ac2;    // 1/a_c^2 of the species, 0 for the harmonic bond
+  // a_c derived from omega_c (Sec. 3.1, one Coulomb constant for every
+  // ion): an ion with its own omega_c has 1/a_c^2 = ac_k * omega_c^{4/3};
+  // 0 when a_c is fixed or the bond harmonic
+  Real ac_k;
   Real omega_c, nu, nu_per_omega;
   Real qw1, qw2;   // q1 * weight, q2 * weight (species weight)
   Real weight;
@@ -81,6 +85,22 @@ struct PushConst {
   int two_body;
   int deposit;
 };
+
+// x^{4/3} for the softening length of an ion's own omega_c: FP32 through
+// the hardware base-2 logarithm and exponential (about 1 ulp each), FP64 as
+// x * cbrt(x).
+__device__ __forceinline__ float pow43(float x) {
+  return __builtin_amdgcn_exp2f(1.33333333f * __builtin_amdgcn_logf(x));
+}
+__device__ __forceinline__ double pow43(double x) { return x * cbrt(x); }
+
+// 1/a_c^2 of an ion: its own when a_c derives from omega_c and the ion
+// carries its own omega_c (Sec. 3.1 with one Coulomb constant: a_c^3
+// proportional to 1/omega_c^2), else the species value.
+template <typename Real>
+__device__ __forceinline__ Real ion_inv_ac2(const PushConst<Real>& c, bool own_wc, Real wc) {
+  return (own_wc && c.ac_k != Real(0)) ? c.ac_k * pow43(wc) : c.inv_ac2;
+}
 
 // Launchers (host).  All take the stream to launch on.
 template <typename Real>

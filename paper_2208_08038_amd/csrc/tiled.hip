@@ -86,6 +86,7 @@ struct TileSpecies {
   const uint32_t* tile_off;
   uint32_t* list;
   uint32_t* nlist;
+  uint32_t* nfar;  // two-body ions listed because their bodies are far apart
 };
 
 // 3. the particles [p0, p1) of one species in the tile; the state of a
@@ -122,15 +123,21 @@ __device__ __forceinline__ void tile_particles(const GridInfo& g, const TileSpec
       load_state<Real, ND, TWO>(s, c, p, st);
     }
     int ci[3] = {0, 0, 0};
-    bool inside = false;
+    bool inside = false, far = false;
     if (valid) {
       decode_cell<ND>(g, st.cell, ci);
       inside = p < pk;
 #pragma unroll
       for (int d = 0; d < ND; d++) inside = inside && ci[d] >= lo[d] && ci[d] < hi[d];
+      // an ion whose bodies are half a cell or more apart reaches beyond
+      // the tile's patches: the HBM pass takes it
+      if constexpr (TWO) {
+#pragma unroll
+        for (int d = 0; d < ND; d++) far = far || !(fabs(st.dl[d] * c.idx[d]) < Real(0.5));
+      }
     }
     // list the particles outside the tile: one atomic per wavefront
-    const bool out = valid && !inside;
+    const bool out = valid && (!inside || far);
     const uint64_t m = __ballot(out);
     if (m) {
       uint32_t basei = 0;
@@ -138,8 +145,12 @@ __device__ __forceinline__ void tile_particles(const GridInfo& g, const TileSpec
       if (lane == leader) basei = atomicAdd(nlist, (uint32_t)__popcll(m));
       basei = __shfl(basei, leader);
       if (out) list[basei + (uint32_t)__popcll(m & below)] = (uint32_t)p;
+      if constexpr (TWO) {
+        const uint64_t mf = __ballot(valid && far);
+        if (mf && lane == leader) atomicAdd(sp.nfar, (uint32_t)__popcll(mf));
+      }
     }
-    if (valid && inside) {
+    if (valid && inside && !far) {
       int lf = (ci[0] - lo[0] + 2);
       int lj = lf;
       if (ND > 1) {
@@ -472,19 +483,19 @@ static hipError_t launch_colours(const GridInfo& g, const FieldPtrs<Real>& f,
 template <typename Real>
 static TileSpecies<Real> tile_species(const SpeciesDev<Real>& s, const PushConst<Real>& c,
                                       const uint32_t* tile_off, uint32_t* list,
-                                      uint32_t* nlist) {
-  return TileSpecies<Real>{s, c, tile_off, list, nlist};
+                                      uint32_t* nlist, uint32_t* nfar) {
+  return TileSpecies<Real>{s, c, tile_off, list, nlist, nfar};
 }
 
 template <typename Real>
 hipError_t launch_push_tiled(const GridInfo& g, const FieldPtrs<Real>& f, const SpeciesDev<Real>& s,
                              const PushConst<Real>& c, const TileGeom& t, const uint32_t* tile_off,
                              uint32_t* list, uint32_t* nlist, uint32_t* nlist_total,
-                             uint32_t* err, hipStream_t st, DispatchHook hook) {
+                             uint32_t* nfar, uint32_t* err, hipStream_t st, DispatchHook hook) {
   if (s.n == 0) return hipSuccess;
   hipError_t e = hipMemsetAsync(nlist, 0, sizeof(uint32_t), st);
   if (e != hipSuccess) return e;
-  const TileSpecies<Real> a = tile_species(s, c, tile_off, list, nlist);
+  const TileSpecies<Real> a = tile_species(s, c, tile_off, list, nlist, nfar);
   e = launch_colours<Real, 1>(g, f, a, a, t, err, st, hook);
   if (e != hipSuccess) return e;
   launch_push_list<Real>(g, f, s, c, list, nlist, nlist_total, err, st);
@@ -498,12 +509,12 @@ hipError_t launch_push_tiled_pair(const GridInfo& g, const FieldPtrs<Real>& f,
                                   const SpeciesDev<Real>& se, const PushConst<Real>& ce,
                                   const uint32_t* tile_off_e, uint32_t* list_e,
                                   const TileGeom& t, uint32_t* nlist, uint32_t* total_i,
-                                  uint32_t* total_e, uint32_t* err, hipStream_t st,
-                                  DispatchHook hook) {
+                                  uint32_t* total_e, uint32_t* nfar_i, uint32_t* err,
+                                  hipStream_t st, DispatchHook hook) {
   hipError_t e = hipMemsetAsync(nlist, 0, 2 * sizeof(uint32_t), st);
   if (e != hipSuccess) return e;
-  const TileSpecies<Real> a = tile_species(si, ci, tile_off_i, list_i, nlist);
-  const TileSpecies<Real> b = tile_species(se, ce, tile_off_e, list_e, nlist + 1);
+  const TileSpecies<Real> a = tile_species(si, ci, tile_off_i, list_i, nlist, nfar_i);
+  const TileSpecies<Real> b = tile_species(se, ce, tile_off_e, list_e, nlist + 1, nfar_i);
   e = launch_colours<Real, 2>(g, f, a, b, t, err, st, hook);
   if (e != hipSuccess) return e;
   if (si.n > 0) launch_push_list<Real>(g, f, si, ci, list_i, nlist, total_i, err, st);
@@ -514,22 +525,22 @@ hipError_t launch_push_tiled_pair(const GridInfo& g, const FieldPtrs<Real>& f,
 template hipError_t launch_push_tiled<float>(const GridInfo&, const FieldPtrs<float>&,
                                              const SpeciesDev<float>&, const PushConst<float>&,
                                              const TileGeom&, const uint32_t*, uint32_t*,
-                                             uint32_t*, uint32_t*, uint32_t*, hipStream_t,
-                                             DispatchHook);
+                                             uint32_t*, uint32_t*, uint32_t*, uint32_t*,
+                                             hipStream_t, DispatchHook);
 template hipError_t launch_push_tiled<double>(const GridInfo&, const FieldPtrs<double>&,
                                               const SpeciesDev<double>&, const PushConst<double>&,
                                               const TileGeom&, const uint32_t*, uint32_t*,
-                                              uint32_t*, uint32_t*, uint32_t*, hipStream_t,
-                                             DispatchHook);
+                                              uint32_t*, uint32_t*, uint32_t*, uint32_t*,
+                                              hipStream_t, DispatchHook);
 template hipError_t launch_push_tiled_pair<float>(
     const GridInfo&, const FieldPtrs<float>&, const SpeciesDev<float>&, const PushConst<float>&,
     const uint32_t*, uint32_t*, const SpeciesDev<float>&, const PushConst<float>&,
     const uint32_t*, uint32_t*, const TileGeom&, uint32_t*, uint32_t*, uint32_t*, uint32_t*,
-    hipStream_t, DispatchHook);
+    uint32_t*, hipStream_t, DispatchHook);
 template hipError_t launch_push_tiled_pair<double>(
     const GridInfo&, const FieldPtrs<double>&, const SpeciesDev<double>&,
     const PushConst<double>&, const uint32_t*, uint32_t*, const SpeciesDev<double>&,
     const PushConst<double>&, const uint32_t*, uint32_t*, const TileGeom&, uint32_t*, uint32_t*,
-    uint32_t*, uint32_t*, hipStream_t, DispatchHook);
+    uint32_t*, uint32_t*, uint32_t*, hipStream_t, DispatchHook);
 
 }  // namespace pic

@@ -61,7 +61,7 @@ class PicDiag(C.Structure):
                 ("kinetic_energy", C.c_double), ("momentum", C.c_double * 3),
                 ("div_l2", C.c_double), ("div_max", C.c_double), ("rho_l2", C.c_double),
                 ("n_particles", C.c_int64), ("error_word", C.c_uint32), ("reserved", C.c_uint32),
-                ("n_outside_tile", C.c_int64)]
+                ("n_outside_tile", C.c_int64), ("n_far", C.c_int64)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -102,6 +102,8 @@ SIGNATURES = [
     ("pic_grad_forward", C.c_int, [_P, C.c_int32, C.c_int32]),
     ("pic_grad_backward", C.c_int, [_P, _D, C.POINTER(PicGrad)]),
     ("pic_read_grad_particles", C.c_int, [_P, C.c_int32, _D, _D, _D, _D]),
+    ("pic_save_state", C.c_int, [_P, _P, C.POINTER(C.c_size_t)]),
+    ("pic_load_state", C.c_int, [_P, _P, C.c_size_t]),
     ("pic_last_error", C.c_char_p, [_P]),
     ("pic_destroy", None, [_P]),
     ("pic_version", C.c_char_p, []),
@@ -313,7 +315,7 @@ class Simulation:
                 "kinetic_energy": d.kinetic_energy, "momentum": list(d.momentum),
                 "div_l2": d.div_l2, "div_max": d.div_max, "rho_l2": d.rho_l2,
                 "n_particles": d.n_particles, "error_word": d.error_word,
-                "n_outside_tile": d.n_outside_tile, "status": rc}
+                "n_outside_tile": d.n_outside_tile, "n_far": d.n_far, "status": rc}
 
     def fields(self):
         E = np.zeros((3, self.ncell))
@@ -422,6 +424,22 @@ class Simulation:
                                                      _dp(out.get("delta")), _dp(out["u1"]),
                                                      _dp(out.get("u2"))))
         return out
+
+    # ------------------------------------------------ checkpoint / restart
+    def save_state(self) -> np.ndarray:
+        """The context's state as a host byte array (pic_save_state)."""
+        n = C.c_size_t(0)
+        self._check(self.lib.pic_save_state(self.ctx, None, C.byref(n)))
+        buf = np.empty(n.value, dtype=np.uint8)
+        self._check(self.lib.pic_save_state(self.ctx, C.c_void_p(buf.ctypes.data), C.byref(n)))
+        return buf[: n.value]
+
+    def load_state(self, buf) -> None:
+        """Replace the context's state by one saved from a context of the
+        same configuration and species (pic_load_state)."""
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        self._check(self.lib.pic_load_state(self.ctx, C.c_void_p(buf.ctypes.data),
+                                            C.c_size_t(buf.size)))
 
     def timing(self, species: int = -1, reset: bool = True):
         """(total ms, dispatches) of the main particle kernel of one species

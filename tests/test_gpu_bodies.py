@@ -1,0 +1,319 @@
+"""GPU parity for the parts added on top of the first parity suite:
+
+* two-body ions whose bodies are half a cell or more apart (Sec. 2: each
+  body has its own position), advanced from HBM in their own cell frames
+  (tiled and global kernels, FP64 and FP32, periodic and walled axes);
+* each ion's softening length from its own omega_c, forward and gradient;
+* the FP64 diagnostics (field energy, kinetic energy, momentum) and the
+  Sec. 2 momentum split of charged ions at load, against the oracle.
+
+Tolerances as in the first suite: cells bit-exact, FP64 within 1e-12
+relative, FP32 fields within 2e-5 relative L2.
+"""
+import dataclasses
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from _parity import match_by_id, random_fields, rel_l2, small_grid
+from oracle import Oracle
+from oracle.oracle import CHARGE_CHECK as O_CHARGE, FROZEN_FIELDS as O_FROZEN
+from paper_2208_08038_amd.inputs import (OPEN, PERIODIC, POINT, TWO_BODY, Particles, Species,
+                                         Workload)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pic():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2208_08038_amd import pic as P
+    P.load_library()  # raises if libpic.so is missing
+    return P
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def far_workload(ndim, n_ion, n_el, seed, bc=PERIODIC, spread=2.5, shape=None):
+    """Random two-body ions with bodies up to `spread` cells apart per
+    resolved axis (most of them half a cell or more), per-ion omega_c and
+    weights with a derived softening length, and free electrons."""
+    rng = np.random.default_rng(seed)
+    shape = shape or (24, 18, 14)[:ndim]
+    dx = (0.3, 0.25, 0.2)[:ndim]
+    g = small_grid(ndim, shape, dx, bc=bc)
+    edge = 6.0 if bc == OPEN else 0.0
+    lo = np.array([edge] * ndim)
+    hi = np.array([s - edge for s in shape], float)
+    sp = Species(TWO_BODY, 5.0, 40.0, -3.0, 3.0, weight=0.005, omega_c=2.0, a_c=0.0, nu=0.05,
+                 name="ion")
+    R = (lo + (hi - lo) * rng.random((n_ion, ndim))) * np.array(dx)
+    delta = np.zeros((n_ion, 3))
+    delta[:, :ndim] = rng.uniform(-spread, spread, (n_ion, ndim)) * np.array(dx)
+    delta[:, ndim:] = rng.uniform(-0.5, 0.5, (n_ion, 3 - ndim))
+    u = rng.normal(scale=0.15, size=(n_ion, 3))
+    parts = Particles(x=R, u1=u, u2=u + rng.normal(scale=0.2, size=u.shape), delta=delta,
+                      omega_c=rng.uniform(1.0, 3.0, n_ion),
+                      weight=rng.uniform(0.5, 1.5, n_ion) * 0.005)
+    species = [(sp, parts)]
+    if n_el:
+        xe = (lo + (hi - lo) * rng.random((n_el, ndim))) * np.array(dx)
+        species.append((Species(POINT, -1.0, 1.0, weight=0.005, name="e"),
+                        Particles(x=xe, u1=rng.normal(scale=0.3, size=(n_el, 3)))))
+    return Workload(f"far{ndim}d", g, species, steps=1, precision=64)
+
+
+def _both(wl, P, precision, oflags=0, pflags=0, **kw):
+    o = Oracle.from_workload(wl, flags=oflags)
+    s = P.Simulation.from_workload(wl, precision=precision, flags=pflags | P.TRACK_IDS, **kw)
+    return o, s
+
+
+def _compare(o, s, wl, tol, exact_cells=True):
+    for sid, (sp, _) in enumerate(wl.species):
+        ref = o.particles(sid)
+        got = s.particles(sid, ids=True)
+        got = match_by_id(got, got["id"])
+        if exact_cells:
+            assert np.array_equal(ref["cell"], got["cell"]), "cell indices differ"
+        pr = ref["cell"] + ref["off"]
+        pg = got["cell"] + got["off"]
+        assert np.max(np.abs(pr - pg)) < 10 * tol
+        for k in ["u1"] + (["u2", "delta"] if sp.kind == TWO_BODY else []):
+            scale = max(np.abs(ref[k]).max(), 1e-300)
+            err = np.abs(ref[k] - got[k]).max() / scale
+            assert err < tol, f"{k}: relative error {err:.3e}"
+
+
+# ------------------------------------------------ separated bodies
+
+@pytest.mark.parametrize("ndim,bc", [(1, PERIODIC), (2, PERIODIC), (3, PERIODIC), (2, OPEN),
+                                     (3, OPEN)])
+@pytest.mark.parametrize("flags", [0, "global"])
+def test_far_bodies_one_step_fp64(pic, ndim, bc, flags):
+    """Frozen random fields, one step: ions with bodies up to 2.5 cells
+    apart (and across periodic seams) match the oracle: cells bit-exact,
+    state and J within 1e-12; the library reports them as far ions."""
+    _say(f"case: far bodies one step fp64 ndim={ndim} bc={bc} flags={flags}")
+    wl = far_workload(ndim, 60, 40, seed=200 + ndim + 10 * bc)
+    pf = pic.FROZEN_FIELDS | (pic.GLOBAL_KERNEL if flags == "global" else 0)
+    o, s = _both(wl, pic, 64, oflags=O_FROZEN | O_CHARGE, pflags=pf | pic.CHARGE_CHECK)
+    E, B = random_fields(np.random.default_rng(ndim), o.ncell)
+    o.load_fields(E, B)
+    s.load_fields(E, B)
+    o.step(1)
+    s.step(1)
+    d = s.diagnostics()
+    assert d["error_word"] == 0
+    assert o.diagnostics()["error_word"] == 0
+    if flags == 0:
+        assert d["n_far"] > 20
+    _compare(o, s, wl, 1e-12)
+    assert rel_l2(s.fields()[2], o.fields()[2]) < 1e-12
+    assert d["div_max"] < 1e-11 * d["rho_l2"]
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_far_bodies_coupled(pic, ndim):
+    """Twelve self-consistent steps with the far ions (Yee update on):
+    fields and particles against the oracle, FP64 within 1e-12 (cells
+    bit-exact) and FP32 fields within 2e-5."""
+    _say(f"case: far bodies coupled ndim={ndim}")
+    wl = far_workload(ndim, 200, 200, seed=300 + ndim)
+    o = Oracle.from_workload(wl)
+    o.step(12)
+    assert o.diagnostics()["error_word"] == 0
+    Eo, Bo, Jo = o.fields()
+    for prec, tol in ((64, 1e-12), (32, 2e-5)):
+        s = pic.Simulation.from_workload(wl, precision=prec, flags=pic.TRACK_IDS, sort_every=4)
+        s.step(12)
+        assert s.diagnostics()["error_word"] == 0
+        Eg, Bg, Jg = s.fields()
+        assert rel_l2(Eg, Eo) < tol
+        assert rel_l2(Bg, Bo) < tol
+        assert rel_l2(Jg, Jo) < (tol if prec == 64 else 1e-4)
+        if prec == 64:
+            _compare(o, s, wl, 1e-11)
+        s.close()
+
+
+def test_torn_clouds_gpu(pic):
+    """A uniform frozen E three times the softened bonds' largest restoring
+    force tears every cloud away from its nucleus: after 200 steps the bodies
+    are several cells apart, the GPU (FP64) matches the oracle and the total
+    momentum follows the impulse (q1 + q2) E dt per step."""
+    _say("case: torn clouds")
+    re = 1e-3
+    g = small_grid(2, (128, 16), (0.25, 0.25), re_norm=re)
+    g = dataclasses.replace(g, dt=0.1)
+    q1, m1, q2, m2, wc = 3.0, 60.0, -2.0, 2.0, 2.0
+    mc = m1 + m2
+    mr = m1 * m2 / mc
+    qr = (q1 * m2 - q2 * m1) / mc
+    a_c = (abs(q1 * q2) * re / (mr * wc * wc)) ** (1.0 / 3.0)
+    fmax = abs(q1 * q2) * re * 2.0 / (3.0 * math.sqrt(3.0) * a_c * a_c)
+    E0 = np.array([3.0 * fmax / qr, 0.5 * fmax / qr, 0.0])
+    rng = np.random.default_rng(9)
+    n = 64
+    x = np.column_stack([rng.uniform(40, 60, n) * 0.25, rng.uniform(0, 16, n) * 0.25])
+    wl = Workload("torn", g, [(Species(TWO_BODY, q1, m1, q2, m2, weight=0.01, omega_c=wc,
+                                       a_c=0.0), Particles(x=x, u1=np.zeros((n, 3)),
+                                                           u2=np.zeros((n, 3))))], 1)
+    o, s = _both(wl, pic, 64, oflags=O_FROZEN, pflags=pic.FROZEN_FIELDS)
+    E = np.tile(E0[:, None], (1, o.ncell))
+    o.load_fields(E, np.zeros_like(E))
+    s.load_fields(E, np.zeros_like(E))
+    p0 = np.array(s.diagnostics()["momentum"])
+    o.step(200)
+    s.step(200)
+    d = s.diagnostics()
+    assert d["error_word"] == 0 and o.diagnostics()["error_word"] == 0
+    assert d["n_far"] == n
+    _compare(o, s, wl, 1e-11)
+    st = s.particles(0)
+    assert np.min(np.abs(st["delta"][:, 0])) / 0.25 > 3.0
+    p = np.array(d["momentum"])
+    assert np.allclose(p, p0 + 200 * g.dt * (q1 + q2) * 0.01 * n * E0, rtol=1e-10)
+
+
+# ------------------------------------------------ diagnostics and loading
+
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_diagnostics_match_the_oracle(pic, ndim):
+    """Field energy, kinetic energy and momentum of the GPU's compensated
+    FP64 reductions equal the oracle's plain sums within 1e-12 relative
+    after coupled steps (FP64 state); the FP32 state's are reported within
+    1e-5."""
+    _say(f"case: diagnostics ndim={ndim}")
+    from _parity import random_workload
+    wl = random_workload(ndim, 300, 200, seed=400 + ndim)
+    o = Oracle.from_workload(wl)
+    rng = np.random.default_rng(ndim)
+    E, B = random_fields(rng, o.ncell)
+    o.load_fields(E, B)
+    o.step(5)
+    do = o.diagnostics()
+    for prec, tol in ((64, 1e-12), (32, 1e-5)):
+        s = pic.Simulation.from_workload(wl, precision=prec)
+        s.load_fields(E, B)
+        s.step(5)
+        dg = s.diagnostics()
+        for k in ("field_energy", "kinetic_energy"):
+            assert abs(dg[k] - do[k]) <= tol * abs(do[k]), (prec, k, dg[k], do[k])
+        pm = np.array(do["momentum"])
+        assert np.max(np.abs(np.array(dg["momentum"]) - pm)) <= tol * np.abs(pm).max()
+        assert dg["n_particles"] == do["n_particles"]
+        s.close()
+
+
+@pytest.mark.parametrize("loader", ["host", "device"])
+def test_charged_ion_split_matches_the_oracle(pic, loader):
+    """Charged two-body ions loaded with their centre-of-mass momentum only
+    (u2 = NULL): the library's Sec. 2 split (p1 + p2 = p_c, q1 v1 + q2 v2 = 0,
+    Newton on the host and on the device) equals the oracle's (bisection),
+    relativistic momenta included."""
+    _say(f"case: charged split {loader}")
+    import torch
+    rng = np.random.default_rng(17)
+    g = small_grid(2, (16, 12), (0.3, 0.3))
+    n = 500
+    # up to |u_c| ~ 2: beyond, the cloud of a gold ion must run at gamma in the
+    # thousands (the nucleus alone cannot carry the momentum with
+    # q1 v1 + q2 v2 = 0) and one rounding of the speed moves u2 by 1e-9
+    uc = rng.normal(size=(n, 3)) * rng.choice([1e-4, 0.05, 0.7], size=(n, 1))
+    x = rng.random((n, 2)) * [4.8, 3.6]
+    sp = Species(TWO_BODY, 79.0, 358970.0, -78.0, 78.0, weight=1.0, omega_c=2.0, a_c=math.inf)
+    wl = Workload("split", g, [(sp, Particles(x=x, u1=uc))], 1)
+    o = Oracle.from_workload(wl)
+    s = pic.Simulation(g, precision=64, flags=pic.TRACK_IDS)
+    sid = s.add_species(sp, n)
+    if loader == "host":
+        s.load_particles(sid, wl.species[0][1])
+    else:
+        dev = s.device
+        s.load_particles_device(sid, torch.tensor(x, device=dev), torch.tensor(uc, device=dev))
+    ref = o.particles(0)
+    got = s.particles(sid, ids=True)
+    got = match_by_id(got, got["id"])
+    for k in ("u1", "u2"):
+        err = np.abs(got[k] - ref[k]) / np.maximum(np.abs(ref[k]), 1e-300)
+        assert np.max(err[np.abs(ref[k]) > 0]) < 1e-12, k
+    # charged: the bodies move differently (q1 v1 + q2 v2 = 0)
+    assert np.max(np.abs(got["u1"] - got["u2"])) > 1e-3
+
+
+# ------------------------------------------------ per-ion softening: gradients
+
+def _derived_case(per_particle):
+    import _adjoint as A
+    # warm enough to be anharmonic (|delta| up to 0.15 a_c), smooth enough
+    # for finite differences
+    wl = A.small_case(1, a_c=0.0, thermal=2e-4)
+    sp, parts = wl.species[0]
+    rng = np.random.default_rng(3)
+    n = parts.n
+    wcs = rng.uniform(2.5, 3.5, n) if per_particle else None
+    parts = dataclasses.replace(parts, delta=rng.uniform(-2e-3, 2e-3, (n, 3)), omega_c=wcs)
+    return dataclasses.replace(wl, species=[(sp, parts)]), wcs
+
+
+def _adjoint_and_fd(pic, wl, make):
+    import _adjoint as A
+    s = pic.Simulation.from_workload(wl, precision=64, max_probe_steps=wl.steps)
+    s.grad_forward(wl.steps, 30)
+    w = np.random.default_rng(1).normal(size=s.probes().shape)
+    g = s.grad_backward(w)["d_omega_c"][0]
+    s.close()
+    fd = A.richardson_fd(lambda w2: A.gpu_series(pic, w2), lambda pr: float((w * pr).sum()),
+                         make, 0.0, 1e-3)
+    return g, fd
+
+
+def test_gradient_with_derived_softening_length(pic):
+    """A softening length derived from omega_c (a_c^3 proportional to
+    1/omega_c^2, Sec. 3.1) moves with it: d loss / d omega_c of the adjoint
+    includes that dependence and matches Richardson central differences of
+    the FP64 forward, for ions with their own omega_c (a common shift of
+    all of them) and for a species value; with a_c fixed at the same value
+    the derivative differs by far more than the tolerance."""
+    _say("case: gradient with derived softening")
+    import _adjoint as A
+    wl, wcs = _derived_case(True)
+    g, fd = _adjoint_and_fd(pic, wl, lambda h: A.with_particles(wl, omega_c=wcs + h))
+    assert abs(g - fd) <= 1e-6 * abs(fd), (g, fd)
+    wl, _ = _derived_case(False)
+    sp = wl.species[0][0]
+    g, fd = _adjoint_and_fd(pic, wl, lambda h: A.with_params(wl, omega_c=sp.omega_c + h))
+    assert abs(g - fd) <= 1e-6 * abs(fd), (g, fd)
+    from oracle import ac_from_omega
+    a_c = ac_from_omega(sp.q1, sp.m1, sp.q2, sp.m2, sp.omega_c, wl.grid.re_norm)
+    fixed = dataclasses.replace(wl, species=[(dataclasses.replace(sp, a_c=a_c),
+                                              wl.species[0][1])])
+    gf, fdf = _adjoint_and_fd(pic, fixed, lambda h: A.with_params(fixed, omega_c=sp.omega_c + h))
+    assert abs(gf - fdf) <= 1e-6 * abs(fdf), (gf, fdf)
+    assert abs(fdf - fd) > 1e-4 * abs(fd), (fdf, fd)
+
+
+def test_gradient_run_refuses_far_ions(pic):
+    """The reverse cycle does not cover ions whose bodies are half a cell or
+    more apart: a gradient run that meets one fails with PIC_ERANGE instead
+    of returning a wrong gradient."""
+    _say("case: gradient run with a far ion")
+    import _adjoint as A
+    wl = A.small_case(1)
+    sp, parts = wl.species[0]
+    delta = np.zeros((parts.n, 3))
+    delta[0, 0] = 0.8 * wl.grid.dx[0]
+    wl = A.with_particles(wl, delta=delta)
+    s = pic.Simulation.from_workload(wl, precision=64, max_probe_steps=wl.steps)
+    s.grad_forward(wl.steps, 30)
+    with pytest.raises(pic.PicError) as e:
+        s.grad_backward(np.ones(s.probes().shape))
+    assert e.value.code == pic.PIC_ERANGE

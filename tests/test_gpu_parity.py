@@ -469,34 +469,54 @@ def test_edge_cases(pic):
 def test_load_errors(pic):
     """Invalid inputs are rejected at load with the documented codes."""
     _say("case: load errors")
-    g = small_grid(1, (16,), (0.3,))
+    g = small_grid(1, (16,), (0.3,), bc=OPEN)
     s = pic.Simulation(g, precision=64)
     sid = s.add_species(Species(TWO_BODY, 2.0, 10.0, -1.0, 1.0, omega_c=1.0, a_c=math.inf), 4)
-    bad_u = Particles(x=np.array([[1.0]]), u1=np.array([[np.nan, 0, 0]]))
+    bad_u = Particles(x=np.array([[1.5]]), u1=np.array([[np.nan, 0, 0]]))
     with pytest.raises(pic.PicError) as e:
         s.load_particles(sid, bad_u)
     assert e.value.code == pic.PIC_ENAN
-    bad_d = Particles(x=np.array([[1.0]]), u1=np.zeros((1, 3)),
-                      delta=np.array([[0.3 * 0.5 + 1e-9, 0, 0]]))
+    # the cloud more than one cell beyond the particle wall (3 cells in)
+    bad_d = Particles(x=np.array([[3.5 * 0.3]]), u1=np.zeros((1, 3)),
+                      delta=np.array([[2.0 * 0.3, 0, 0]]))
     with pytest.raises(pic.PicError) as e:
         s.load_particles(sid, bad_d)
     assert e.value.code == pic.PIC_ERANGE
-    many = Particles(x=np.ones((5, 1)), u1=np.zeros((5, 3)))
+    # far apart but inside: accepted (each body has its own position)
+    s.load_particles(sid, Particles(x=np.array([[8.0 * 0.3]]), u1=np.zeros((1, 3)),
+                                    delta=np.array([[3.0 * 0.3, 0.7, 0]])))
+    many = Particles(x=np.ones((5, 1)) * 1.5, u1=np.zeros((5, 3)))
     with pytest.raises(pic.PicError) as e:
         s.load_particles(sid, many)
     assert e.value.code == pic.PIC_ENOMEM
+    # per-particle omega_c: positive, and not with a fixed finite a_c
+    s2 = pic.Simulation(g, precision=64)
+    fixed = s2.add_species(Species(TWO_BODY, 2.0, 10.0, -1.0, 1.0, omega_c=1.0, a_c=0.2), 4)
+    with pytest.raises(pic.PicError) as e:
+        s2.load_particles(fixed, Particles(x=np.array([[1.5]]), u1=np.zeros((1, 3)),
+                                           omega_c=np.array([1.0])))
+    assert e.value.code == pic.PIC_EINVAL
+    harm = s2.add_species(Species(TWO_BODY, 2.0, 10.0, -1.0, 1.0, omega_c=1.0, a_c=math.inf), 4)
+    with pytest.raises(pic.PicError) as e:
+        s2.load_particles(harm, Particles(x=np.array([[1.5]]), u1=np.zeros((1, 3)),
+                                          omega_c=np.array([-1.0])))
+    assert e.value.code == pic.PIC_EINVAL
+    with pytest.raises(pic.PicError) as e:
+        s2.add_species(Species(TWO_BODY, 2.0, 10.0, -1.0, 1.0, omega_c=1.0, a_c=-0.5), 1)
+    assert e.value.code == pic.PIC_EINVAL
 
 
 def test_device_error_word(pic):
-    """A bond stretched past half a cell during a step raises PIC_ERANGE at
-    the next diagnostics (set by the kernel, not by a fault)."""
+    """A cloud driven more than one cell beyond the particle wall during a
+    step raises PIC_ERANGE at the next diagnostics (set by the kernel, not
+    by a fault)."""
     _say("case: device error word")
-    g = small_grid(1, (16,), (0.3,))
+    g = small_grid(1, (16,), (0.3,), bc=OPEN)
     s = pic.Simulation(g, precision=64, flags=pic.FROZEN_FIELDS)
     sid = s.add_species(Species(TWO_BODY, 2.0, 10.0, -1.0, 1.0, omega_c=1e-6, a_c=math.inf), 1)
-    s.load_particles(sid, Particles(x=np.array([[2.0]]), u1=np.array([[0.0, 0, 0]]),
-                                    u2=np.array([[-0.99, 0, 0]]),
-                                    delta=np.array([[0.14, 0, 0]])))
+    s.load_particles(sid, Particles(x=np.array([[3.4 * 0.3]]), u1=np.array([[0.0, 0, 0]]),
+                                    u2=np.array([[-7.0, 0, 0]]),
+                                    delta=np.array([[0.0, 0, 0]])))
     s.step(3)
     d = s.diagnostics(check=False)
     assert d["status"] == pic.PIC_ERANGE
