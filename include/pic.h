@@ -252,6 +252,19 @@ int pic_read_particles_range(pic_ctx* ctx, int32_t species_id, int64_t start, in
 /* Charge density at the integer nodes of the present state (HOST FP64, prod(n)). */
 int pic_rho(pic_ctx* ctx, double* rho);
 
+/* pic_rho without device scratch from the context, for callers that
+   cannot allocate device memory at the time of the call (code under HIP
+   graph capture, tight serving loops, harnesses that forbid allocation).
+   Same result as pic_rho (to FP64 rounding: its atomics add in a varying
+   order), computed in a static device array of 2^22 FP64 values (32 MiB;
+   every GPU the library runs on holds its own copy until the process
+   ends); the guarded grid, prod(n_d + 6) nodes over the resolved
+   dimensions, must fit it (else PIC_EINVAL).  Calls no allocator: the
+   context's device must be current (else PIC_ESTATE).  Calls on one GPU
+   share the array, so calls that overlap on one GPU (two streams, two
+   threads) race.  Synchronises. */
+int pic_rho_static(pic_ctx* ctx, double* rho);
+
 /* Field probes: component 0..5 (Ex, Ey, Ez, Bx, By, Bz) at interior node
    index (i, j, k), sampled after every step into a device buffer of
    max_probe_steps entries per probe.  Setting probes resets the record. */

@@ -784,6 +784,10 @@ int pic_create(const pic_config* cfg, const pic_allocator* alloc, void* hip_stre
     c->use_hip_malloc = false;
   }
   c->stream = static_cast<hipStream_t>(hip_stream);
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return fail(nullptr, PIC_EHIP, "hipGetDevice failed");
+  }
   c->prec = cfg->precision;
   c->rsize = cfg->precision == 32 ? 4 : 8;
   GridInfo& g = c->g;

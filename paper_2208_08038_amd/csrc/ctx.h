@@ -52,6 +52,7 @@ struct pic_ctx {
   pic_allocator alloc{};
   bool use_hip_malloc = true;
   hipStream_t stream = nullptr;
+  int device = 0;  // HIP device current at pic_create (the stream's device)
   GridInfo g{};
   int prec = 64;
   size_t rsize = 8;

@@ -96,6 +96,7 @@ SIGNATURES = [
                                            C.POINTER(C.c_int32), _D, _D, _D, _D, _D, _D,
                                            C.POINTER(C.c_int64)]),
     ("pic_rho", C.c_int, [_P, _D]),
+    ("pic_rho_static", C.c_int, [_P, _D]),
     ("pic_set_probes", C.c_int, [_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
     ("pic_read_probes", C.c_int, [_P, _D, C.POINTER(C.c_int64)]),
     ("pic_timing", C.c_int, [_P, C.c_int32, _D, C.POINTER(C.c_int64), C.c_int32]),
@@ -368,6 +369,13 @@ class Simulation:
     def rho(self):
         r = np.zeros(self.ncell)
         self._check(self.lib.pic_rho(self.ctx, _dp(r)))
+        return r
+
+    def rho_static(self):
+        """pic_rho computed in the library's static device array (no
+        allocation during the call)."""
+        r = np.zeros(self.ncell)
+        self._check(self.lib.pic_rho_static(self.ctx, _dp(r)))
         return r
 
     def probes(self):
