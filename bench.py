@@ -132,6 +132,7 @@ def run_gpu(args, precision, keep_fields=False):
     print(f"[bench] fp{precision}: loaded {n_ion} ions + {n_el} electrons in {t_load:.1f} s",
           file=sys.stderr, flush=True)
 
+    tw = time.perf_counter()
     sim.step(args.warmup)
     torch.cuda.synchronize()
     sim.timing(reset=True)
@@ -146,6 +147,7 @@ def run_gpu(args, precision, keep_fields=False):
     ms_e, l_e = sim.timing(species=sid_e, reset=True)
     shared = l_e == 0
     diag = sim.diagnostics(check=False)
+    run = continue_run(sim, args, precision, n_ion + n_el, t1 - tw, diag)
     dt = t1 - t0
     ncell = n[0] * n[1] * n[2]
     rs = 4 if precision == 32 else 8
@@ -172,14 +174,92 @@ def run_gpu(args, precision, keep_fields=False):
         "bytes_per_electron": pp_e, "bytes_per_cell": pc, "load_seconds": t_load,
         "outside_tile_last_step": diag["n_outside_tile"],
         "error_word": diag["error_word"], "field_energy": diag["field_energy"],
-        "kinetic_energy": diag["kinetic_energy"],
+        "kinetic_energy": diag["kinetic_energy"], "run": run,
     }
+    if run is not None:  # energies at the end of the whole run
+        end = sim.diagnostics(check=False)
+        res["field_energy"], res["kinetic_energy"] = end["field_energy"], end["kinetic_energy"]
     if keep_fields:  # final E, B, J for the FP32-against-FP64 comparison
         res["fields"] = sim.fields()
     sim.close()
     del sim
     torch.cuda.empty_cache()
     return res
+
+
+def continue_run(sim, args, precision, n_part, t_first, diag_first):
+    """Carry the timed run on to the workload's full length (args.total_steps):
+    a late window of args.steps steps from step args.late_window, the mean
+    over every step of the run, the far ions (bodies half a cell or more
+    apart) and the error word at the end.  None if the run is no longer."""
+    import torch
+    done = args.warmup + args.steps
+    total = args.total_steps
+    if total <= done:
+        return None
+    late0 = max(args.late_window, done)
+    t_all = t_first
+    late = None
+    mark = time.perf_counter()
+    while done < total:
+        if done == late0 and late is None and late0 + args.steps <= total:
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            sim.step(args.steps)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - ta
+            t_all += dt
+            late = {"first_step": late0 + 1, "steps": args.steps,
+                    "ms_per_step": 1e3 * dt / args.steps,
+                    "value": n_part * args.steps / dt}
+            done += args.steps
+            continue
+        k = min(late0 - done if done < late0 else total - done, 25)
+        ta = time.perf_counter()
+        sim.step(k)
+        torch.cuda.synchronize()
+        t_all += time.perf_counter() - ta
+        done += k
+        if time.perf_counter() - mark > 20.0 or done == total:
+            mark = time.perf_counter()
+            print(f"[bench] fp{precision}: step {done} of {total}", file=sys.stderr, flush=True)
+    d = sim.diagnostics(check=False)
+    return {"total_steps": total, "late_window": late,
+            "whole_run": {"ms_per_step": 1e3 * t_all / total, "value": n_part * total / t_all},
+            "far_ions_last_step": d["n_far"], "outside_tile_last_step": d["n_outside_tile"],
+            "error_word": d["error_word"], "far_ions_step_25": diag_first["n_far"]}
+
+
+def cells_mismatch(args):
+    """FP32 against FP64 cell indices (bit-exact in FP64 against the oracle;
+    in FP32 a particle near a face may end one cell over): the slab's medium,
+    laser and time step on a reduced 128 x 64 x 64 grid, both precisions with
+    load ids, args.total_steps steps; fraction of particles whose cell differs."""
+    import torch
+    from paper_2208_08038_amd import pic
+    out = {}
+    cells = {}
+    for prec in (32, 64):
+        sim, _, sid_i, sid_e, _ = ionised_slab_simulation(
+            (128, 64, 64), args.ppc, prec, pic.TRACK_IDS, 0, None, args.chunk_particles)
+        sim.step(args.total_steps)
+        d = sim.diagnostics(check=False)
+        cells[prec] = []
+        for sid in (sid_i, sid_e):
+            st = sim.particles(sid, ids=True)
+            order = np.argsort(st["id"], kind="stable")
+            cells[prec].append(st["cell"][order])
+        out[f"error_word_fp{prec}"] = d["error_word"]
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    for k, name in enumerate(("ions", "electrons")):
+        a, b = cells[32][k], cells[64][k]
+        out[f"mismatch_{name}"] = float(np.mean(np.any(a != b, axis=1)))
+        out[f"n_{name}"] = int(a.shape[0])
+    out["cells"] = [128, 64, 64]
+    out["steps"] = args.total_steps
+    return out
 
 
 def run_adjoint(args):
@@ -247,22 +327,199 @@ def run_adjoint(args):
     }
 
 
-def cpu_baseline(target_seconds):
-    """The FP64 oracle as it stands, on a small sample of the same workload."""
+def run_config1(args):
+    """The 1D neutral medium (2048 cells, 16,336 two-body ions, 1000 steps,
+    FP64): particle-steps/s over the whole run (cache-resident, launch
+    bound: no HBM roofline claim) and the phase-velocity index it measures."""
+    import torch
+    from paper_2208_08038_amd import pic
+    from paper_2208_08038_amd.inputs import neutral_medium_1d
+    wl = neutral_medium_1d()
+    sim = pic.Simulation.from_workload(wl, precision=64, max_probe_steps=wl.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(wl.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    pr = sim.probes()
+    d = sim.diagnostics(check=False)
+    sim.close()
+    t = (np.arange(pr.shape[1]) + 1) * wl.grid.dt
+    F = (pr * np.exp(-1j * t)[None, :]).sum(axis=1)
+    (_, c0), (_, c1) = wl.probes
+    dist = (c1[0] - c0[0]) * wl.grid.dx[0]
+    dphi = (np.angle(F[0]) - np.angle(F[1])) % (2 * math.pi)
+    n_meas = (dphi + 2 * math.pi * math.floor(dist / (2 * math.pi))) / dist
+    n_ion = wl.species[0][1].n
+    return {"workload": "neutral_medium_1d", "cells": 2048, "two_body_ions": n_ion,
+            "steps": wl.steps, "precision": "fp64", "seconds": dt,
+            "ms_per_step": 1e3 * dt / wl.steps, "value": n_ion * wl.steps / dt,
+            "unit": "particle-steps/s", "index_measured": n_meas,
+            "index_continuum": math.sqrt(1 + 0.81 / 8.0), "error_word": d["error_word"]}
+
+
+def run_config2(args):
+    """The 2D Bragg case at full size (4096^2 cells, one gold ion per lattice
+    site of d = 1.5 lambda in the central 1024^2 cells, 4000 steps) in FP64
+    and FP32: Yee cell-steps/s and the angle of the scattered lobe (run with
+    the lattice minus the run without) against 2 theta_B = 38.94 degrees;
+    FP32 against FP64 scattered-field L2."""
+    import torch
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from _bragg import scattered_direction
+    from paper_2208_08038_amd import pic
+    from paper_2208_08038_amd.inputs import bragg_2d
+    out = {"workload": "bragg_2d", "cells": [4096, 4096]}
+    scat = {}
+    for prec in (64, 32):
+        wl = bragg_2d(steps=args.config2_steps, precision=prec)
+        n = wl.grid.n[0] * wl.grid.n[1]
+        res = {}
+        for with_ions in (True, False):
+            sim = (pic.Simulation.from_workload(wl, precision=prec) if with_ions else
+                   pic.Simulation(wl.grid, precision=prec))
+            sim.step(10)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.step(wl.steps - 10)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            _, B, _ = sim.fields()
+            res[with_ions] = (dt, B[2].copy())
+            err = sim.diagnostics(check=False)["error_word"]
+            sim.close()
+            del sim, B
+            torch.cuda.empty_cache()
+            print(f"[bench] bragg fp{prec} ions={with_ions}: {wl.steps} steps {dt:.1f} s",
+                  file=sys.stderr, flush=True)
+        dt = res[True][0]
+        s = res[True][1] - res[False][1]
+        scat[prec] = s
+        angle, kmean, contrast = scattered_direction(wl, s)
+        rs = 4 if prec == 32 else 8
+        out[f"fp{prec}"] = {
+            "two_body_ions": wl.species[0][1].n, "steps": wl.steps,
+            "ms_per_step": 1e3 * dt / (wl.steps - 10),
+            "cell_steps_per_s": n * (wl.steps - 10) / dt,
+            "yee_gbs_algorithmic": n * 15 * rs * (wl.steps - 10) / dt / 1e9,
+            "scattered_angle_deg": angle, "scattered_k": kmean, "lobe_contrast": contrast,
+            "error_word": err}
+    out["bragg_angle_2theta_deg"] = 2 * math.degrees(math.asin(1.0 / 3.0))
+    out["angular_bin_deg"] = math.degrees(1.0 / 128.0)
+    out["fp32_vs_fp64_scattered_rel_l2"] = float(np.linalg.norm(scat[32] - scat[64]) /
+                                                 np.linalg.norm(scat[64]))
+    return out
+
+
+def run_config4(args):
+    """The mixed-precision case at full size: Bragg geometry in 3D,
+    1024 x 1024 x 512 cells, 4 two-body ions per cell in x cells 384..640
+    (536,870,912 ions, lattice-modulated weights), 2000 steps, FP32 and FP64
+    runs; the FP64-compensated continuity residual every 100 steps against
+    its rounding bound, and the transmitted field (x cells 640 .. n - 3) of
+    FP32 against FP64 at the end."""
+    import torch
+    from paper_2208_08038_amd import inputs as I
+    from paper_2208_08038_amd import pic
+    n = (1024, 1024, 512)
+    steps = args.config4_steps
+    meta = I.mixed_precision_3d(n=n, slab=(384, 385), steps=steps)
+    grid, sp = meta.grid, meta.species[0][0]
+    total = (640 - 384) * n[1] * n[2] * 4
+    dx = grid.dx[0]
+    out = {"workload": "mixed_precision_3d", "cells": list(n), "two_body_ions": total,
+           "steps": steps}
+    fields = {}
+    for prec in (32, 64):
+        sim = pic.Simulation(grid, precision=prec, flags=pic.CHARGE_CHECK | pic.TIMING)
+        sid = sim.add_species(sp, total)
+        t0 = time.perf_counter()
+        x0, chunk, wmax = 384, 0, 0.0
+        while x0 < 640:
+            x1 = min(x0 + 32, 640)
+            x, w = I.mixed_precision_3d_device_chunk(n, 4, (x0, x1), chunk)
+            sim.load_particles_device(sid, x, torch.zeros_like(x), weight=w * sp.weight)
+            wmax = max(wmax, float(w.max()) * sp.weight)
+            del x, w
+            x0, chunk = x1, chunk + 1
+        torch.cuda.synchronize()
+        t_load = time.perf_counter() - t0
+        print(f"[bench] config4 fp{prec}: loaded {sim.count(sid)} ions in {t_load:.0f} s",
+              file=sys.stderr, flush=True)
+        eps = 2.0 ** -24 if prec == 32 else 2.0 ** -53
+        gross = 4 * wmax * (abs(sp.q1) + abs(sp.q2)) / (dx ** 3 * grid.dt)
+        worst_max, worst_rms, t_run = 0.0, 0.0, 0.0
+        done = 0
+        while done < steps:
+            k = min(100, steps - done)
+            ta = time.perf_counter()
+            sim.step(k)
+            d = sim.diagnostics(check=False)
+            t_run += time.perf_counter() - ta
+            done += k
+            worst_max = max(worst_max, d["div_max"] / gross)
+            worst_rms = max(worst_rms, d["div_l2"] / math.sqrt(n[0] * n[1] * n[2]) / gross)
+            print(f"[bench] config4 fp{prec}: step {done}, residual max {d['div_max']:.3e} "
+                  f"rms {d['div_l2'] / math.sqrt(n[0] * n[1] * n[2]):.3e}",
+                  file=sys.stderr, flush=True)
+        ms, nl = sim.timing(reset=True)
+        out[f"fp{prec}"] = {
+            "load_s": t_load, "seconds": t_run, "ms_per_step": 1e3 * t_run / steps,
+            "value": total * steps / t_run, "unit": "particle-steps/s",
+            "push_ms_per_step": ms / steps,
+            "residual_max_over_bound": worst_max / (27 * 8 * eps),
+            "residual_rms_over_bound": worst_rms / eps,
+            "error_word": d["error_word"], "far_ions_last_step": d["n_far"]}
+        E = sim.fields_E()
+        lo = 640 + grid.pad
+        fields[prec] = E[1].reshape(n[2], n[1], n[0])[:, :, lo:n[0] - grid.pad].copy()
+        del E
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    out["transmitted_Ey_fp32_vs_fp64_rel_l2"] = float(
+        np.linalg.norm(fields[32] - fields[64]) / np.linalg.norm(fields[64]))
+    return out
+
+
+def _oracle_sample(args):
+    """One worker of the CPU baseline: the oracle on its own sample (x planes
+    of the slab's recipe), stepped for `seconds`; particle-steps and time."""
+    seconds, chunk = args
     from oracle import Oracle
     from paper_2208_08038_amd import inputs as I
-    wl = I.ionised_slab_3d(n=(24, 16, 16), ppc=8, precision=64)
+    wl = I.ionised_slab_3d(n=(24, 16, 16), ppc=8, precision=64, chunk=chunk)
     o = Oracle.from_workload(wl)
     n = wl.n_particles
     steps, t = 0, 0.0
     t0 = time.perf_counter()
-    while t < target_seconds:
+    while t < seconds:
         o.step(1)
         steps += 1
         t = time.perf_counter() - t0
-    return {"value": n * steps / t, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+    o.close()
+    return n * steps, t
+
+
+def cpu_baseline(target_seconds, workers):
+    """The FP64 oracle as it stands (single-threaded C) on every host core the
+    process may use: one worker process per core, each on its own sample of
+    the slab (24 x 16 x 16 cells, 8 ions + 8 electrons per cell), run before
+    any GPU call (the workers are forked)."""
+    import multiprocessing as mp
+    nproc = os.cpu_count()
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else nproc
+    cores = max(1, min(avail, workers))
+    ctx = mp.get_context("fork")
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_sample, [(target_seconds, k) for k in range(cores)])
+    rates = [ps / t for ps, t in res]
+    total = sum(rates)
+    return {"value": total, "unit": "particle-steps/s", "cores": cores, "kind": "oracle",
+            "per_core": total / cores, "nproc": nproc, "cores_available": avail,
             "sample": f"ionised_slab_3d at 24x16x16 cells, 8 ions + 8 electrons per cell "
-                      f"({n} macro-particles), {steps} FP64 steps, single-threaded C"}
+                      f"(73728 macro-particles) per worker, {cores} single-threaded FP64 C "
+                      f"workers for {target_seconds:.0f} s each"}
 
 
 def main():
@@ -289,7 +546,25 @@ def main():
     ap.add_argument("--fp64-only", action="store_true",
                     help="only the FP64 run (one JSON object with its numbers)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-workers", type=int, default=16,
+                    help="oracle worker processes of the CPU baseline (at most the cores "
+                         "the process may use)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--total-steps", type=int, default=500,
+                    help="carry the slab run on to this many steps (the workload's length) "
+                         "after the timed window: late window, whole-run mean, far ions, "
+                         "FP32 against FP64 at the end")
+    ap.add_argument("--late-window", type=int, default=100,
+                    help="first step of the late timed window (--steps steps)")
+    ap.add_argument("--no-cells-check", action="store_true",
+                    help="skip the FP32-against-FP64 cell-index comparison (reduced slab)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the legs of the 1D neutral medium and the 2D Bragg case")
+    ap.add_argument("--config2-steps", type=int, default=4000)
+    ap.add_argument("--config4", action="store_true",
+                    help="only run the full-size mixed-precision case (1024 x 1024 x 512, "
+                         "536,870,912 ions, FP32 and FP64; several minutes)")
+    ap.add_argument("--config4-steps", type=int, default=2000)
     ap.add_argument("--copy-calibration", type=float, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient-run leg")
@@ -306,6 +581,13 @@ def main():
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU decomposition is a design note, not built)", file=sys.stderr)
         sys.exit(2)
+    # the CPU baseline forks its workers before anything touches the GPU
+    only = args.copy_calibration or args.adjoint_only or args.fp64_only or args.config4
+    cpu = None
+    if not (args.no_cpu_baseline or only):
+        cpu = cpu_baseline(args.cpu_seconds, args.cpu_workers)
+        print(f"[bench] cpu baseline: {cpu['value']:.3e} particle-steps/s on {cpu['cores']} "
+              f"cores", file=sys.stderr, flush=True)
     import torch
     if not torch.cuda.is_available():
         print("bench.py: no HIP device", file=sys.stderr)
@@ -316,6 +598,9 @@ def main():
 
     if args.adjoint_only:
         print(json.dumps({"adjoint": run_adjoint(args)}), flush=True)
+        return
+    if args.config4:
+        print(json.dumps({"config4": run_config4(args)}), flush=True)
         return
     if args.fp64_only:
         r = run_gpu(args, 64)
@@ -328,7 +613,7 @@ def main():
     fp32_err = None
     if r64 is not None:
         # same seeded inputs and steps in both precisions: FP32 error against
-        # the FP64 run (relative L2 over the grid)
+        # the FP64 run (relative L2 over the grid) at the end of the run
         def rel(a, b):
             return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
         f32, f64 = r32.pop("fields"), r64.pop("fields")
@@ -336,8 +621,10 @@ def main():
                     "J_rel_l2": rel(f32[2], f64[2]),
                     "field_energy_rel": abs(r32["field_energy"] / r64["field_energy"] - 1.0),
                     "kinetic_energy_rel": abs(r32["kinetic_energy"] / r64["kinetic_energy"] - 1.0),
-                    "after_steps": args.warmup + args.steps}
+                    "after_steps": max(args.warmup + args.steps, args.total_steps)}
         del f32, f64
+        if not args.no_cells_check:
+            fp32_err["cells"] = cells_mismatch(args)
     key = f"ionised_slab_3d {args.cells} ppc={args.ppc} fp32"
     kname = PAIR_KERNEL if r32["shared_launch"] else ION_KERNEL
     traffic = measured_traffic(key, kname)
@@ -355,7 +642,9 @@ def main():
                            "electron (profiles/push_tiled_3d_fp32_ionised_slab_256x128x128_"
                            "counters.txt)"}
     adj = None if args.no_adjoint else run_adjoint(args)
-    cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_seconds)
+    configs = None
+    if not args.no_configs:
+        configs = {"neutral_medium_1d": run_config1(args), "bragg_2d": run_config2(args)}
     out = {
         "metric": METRIC, "value": r32["value"], "unit": "particle-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": r32["ms_per_step"],
@@ -370,6 +659,7 @@ def main():
                    "parallelism": "1 GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "run": r32["run"],
         "kernels": {"shared_launch": r32["shared_launch"], "push_ms": r32["push_ms"],
                     "dispatch_ms": r32["dispatch_ms"], "gbs": r32["kernel_gbs"],
                     "electron_dispatch_ms": r32["electron_dispatch_ms"],
@@ -379,9 +669,11 @@ def main():
             "value": r64["value"], "ms_per_step": r64["ms_per_step"],
             "shared_launch": r64["shared_launch"], "push_ms": r64["push_ms"],
             "dispatch_ms": r64["dispatch_ms"], "kernel_gbs": r64["kernel_gbs"],
-            "frac": r64["kernel_gbs"] / HBM_PEAK_GBS if r64["kernel_gbs"] else None},
+            "frac": r64["kernel_gbs"] / HBM_PEAK_GBS if r64["kernel_gbs"] else None,
+            "run": r64["run"]},
         "fp32_vs_fp64": fp32_err,
         "adjoint": adj,
+        "configs": configs,
         "error_word": r32["error_word"],
     }
     print(json.dumps(out), flush=True)

@@ -54,7 +54,8 @@ typedef enum {
 
 /* boundary kinds per face */
 #define PIC_BC_PERIODIC 0
-#define PIC_BC_OPEN 1  /* first-order Mur absorbing face; particles reflect `pad` cells inside */
+#define PIC_BC_OPEN 1  /* first-order Mur absorbing face; particles (each body of a
+                          two-body ion on its own) reflect `pad` cells inside */
 #define PIC_BC_LASER 2 /* open face that also injects the laser (x-min only) */
 
 /* configuration flags */
@@ -75,17 +76,18 @@ typedef enum {
 
 /* Device error word bits (pic_diag.error_word).  A macro-particle whose
    state is non-finite (NAN) or outside the representable range (RANGE: an
-   offset outside [0, 1], or a body of a two-body ion more than one cell
-   beyond the particle walls along a non-periodic axis) at the start of its
-   cycle is left unchanged -- not advanced, no current -- and the bit is
-   set.  One that leaves the range during its cycle (a body past that
-   limit, a jump of more than one node, a step out of the grid along a
-   non-periodic axis) is advanced and flagged; it stops at its next cycle.
-   The bodies of a two-body ion may be any distance apart (Sec. 2: each body
-   has its own position): an ion whose bodies are half a cell or more apart
-   along a resolved axis is advanced from HBM with each body in the frame of
-   the cell that holds it.  The bits stay set until the context is
-   destroyed. */
+   offset outside [0, 1], or a body of a two-body ion outside the particle
+   walls along a non-periodic axis) at the start of its cycle is left
+   unchanged -- not advanced, no current -- and the bit is set.  One that
+   leaves the range during its cycle (a jump of more than one node, a step
+   out of the grid along a non-periodic axis) is advanced and flagged; it
+   stops at its next cycle.  The particle walls mirror every body that
+   reaches them, each body of a two-body ion on its own (with its momentum
+   component reversed; the centre of mass and delta follow).  The bodies of
+   a two-body ion may be any distance apart (Sec. 2: each body has its own
+   position): an ion whose bodies are half a cell or more apart along a
+   resolved axis is advanced from HBM with each body in the frame of the
+   cell that holds it.  The bits stay set until the context is destroyed. */
 #define PIC_ERR_NAN 1u
 #define PIC_ERR_RANGE 2u
 
@@ -199,9 +201,9 @@ int pic_add_species(pic_ctx* ctx, const pic_species_desc* desc, int32_t* species
    Positions are converted to (cell, offset) as xi = x/dx, cell = floor(xi),
    offset = xi - cell, then rounded to the context precision.  Particles
    are ordered by tile (stable).  PIC_ERANGE if outside the domain or the
-   walls, or (two-body) a body more than one cell beyond the walls along a
-   non-periodic axis; PIC_ENAN if non-finite, PIC_EINVAL for a bad omega_c,
-   PIC_ENOMEM beyond capacity. */
+   walls (two-body: either body outside the walls along a non-periodic
+   axis); PIC_ENAN if non-finite, PIC_EINVAL for a bad omega_c, PIC_ENOMEM
+   beyond capacity. */
 int pic_load_particles(pic_ctx* ctx, int32_t species_id, int64_t n, const double* x,
                        const double* delta, const double* u1, const double* u2,
                        const double* omega_c, const double* weight);

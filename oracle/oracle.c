@@ -318,6 +318,16 @@ int or_load_particles(or_ctx* c, int sid, int64_t n, const double* x, const doub
     }
     if (s->kind == OR_TWO_BODY) {
       for (int a = 0; a < 3; a++) s->delta[3 * q + a] = delta ? delta[3 * p + a] : 0.0;
+      /* along walled axes both bodies lie between the walls */
+      double mc = s->m1 + s->m2;
+      for (int d = 0; d < c->nd; d++) {
+        if (periodic(c, d)) continue;
+        double X = (double)s->cell[3 * q + d] + s->off[3 * q + d];
+        double sd = s->delta[3 * q + d] / c->g.dx[d];
+        double X1 = X + (s->m2 / mc) * sd, X2 = X - (s->m1 / mc) * sd;
+        double lo = (double)c->g.pad, hi = (double)(c->nn[d] - c->g.pad);
+        if (!(X1 >= lo && X1 <= hi && X2 >= lo && X2 <= hi)) return -3;
+      }
       if (u2) {
         for (int a = 0; a < 3; a++) {
           s->u1[3 * q + a] = u1[3 * p + a];
@@ -572,14 +582,14 @@ static void body_frame(const or_ctx* c, const int32_t cell[3], const double x[3]
   }
 }
 
-/* Along an axis with walls a body must stay where every node its shape
-   reaches is interior: within one cell beyond the walls `pad` cells inside
-   the faces (the centre of mass itself stays between the walls). */
+/* Along an axis with walls a body stays between the walls `pad` cells
+   inside the faces (they mirror every body that reaches them), where every
+   node its shape reaches is interior.  x is relative to `cell`. */
 static int body_in_range(const or_ctx* c, const int32_t cell[3], const double x[3]) {
   for (int d = 0; d < c->nd; d++) {
     if (periodic(c, d)) continue;
-    double X = (double)cell[d] + x[d];
-    if (!(X >= (double)(c->g.pad - 1) && X <= (double)(c->nn[d] - c->g.pad + 1))) return 0;
+    if (!(x[d] >= (double)(c->g.pad - cell[d]) && x[d] <= (double)(c->nn[d] - c->g.pad - cell[d])))
+      return 0;
   }
   return 1;
 }
@@ -603,9 +613,10 @@ static void boris_finish(const double um[3], double a, const double E[3], const 
   for (int k = 0; k < 3; k++) out[k] = up[k] + a * E[k];
 }
 
-/* Reflecting particle walls, `pad` cells inside each non-periodic face.
-   off is the new offset relative to the old cell (not yet wrapped).
-   Returns 1 when the particle was mirrored. */
+/* Reflecting particle walls, `pad` cells inside each non-periodic face, for
+   a point particle (the bodies of a two-body ion reflect one by one, see
+   push_two_body).  off is the new offset relative to the old cell (not yet
+   wrapped).  Returns 1 when the particle was mirrored. */
 static int reflect(or_ctx* c, int d, int32_t cell, double* off) {
   if (periodic(c, d)) return 0;
   int64_t wl = c->g.pad, wr = c->nn[d] - c->g.pad;
@@ -715,12 +726,24 @@ static void push_two_body(or_ctx* c, or_species* s, int64_t p) {
   /* move: R += dt (m1 v1 + m2 v2)/m_c, delta += dt (v1 - v2) */
   double offn[3] = {0, 0, 0};
   for (int a = 0; a < 3; a++) dl[a] = dl[a] + g->dt * (v1[a] - v2[a]);
+  for (int d = 0; d < nd; d++) offn[d] = off[d] + g->dt * (m1 * v1[d] + m2 * v2[d]) / mc / g->dx[d];
+  /* Reflecting walls act on each body, a particle with its own position
+     (Sec. 2): a body past a wall is mirrored back (moved by D cells) and its
+     momentum component reversed; R moves by (m_i/m_c) D and delta by +-D dx. */
   for (int d = 0; d < nd; d++) {
-    offn[d] = off[d] + g->dt * (m1 * v1[d] + m2 * v2[d]) / mc / g->dx[d];
-    if (reflect(c, d, cell[d], &offn[d])) {
-      u1[d] = -u1[d];
-      u2[d] = -u2[d];
-      dl[d] = -dl[d];
+    if (periodic(c, d)) continue;
+    double lo = (double)(g->pad - cell[d]), hi = (double)(c->nn[d] - g->pad - cell[d]);
+    double s = dl[d] / g->dx[d];
+    double y[2] = {offn[d] + f1 * s, offn[d] - f2 * s}, D[2] = {0.0, 0.0};
+    for (int b = 0; b < 2; b++) {
+      if (y[b] < lo) D[b] = 2.0 * (lo - y[b]);
+      else if (y[b] > hi) D[b] = 2.0 * (hi - y[b]);
+    }
+    if (D[0] != 0.0) u1[d] = -u1[d];
+    if (D[1] != 0.0) u2[d] = -u2[d];
+    if (D[0] != 0.0 || D[1] != 0.0) {
+      offn[d] += f2 * D[0] + f1 * D[1];
+      dl[d] += (D[0] - D[1]) * g->dx[d];
     }
   }
   /* new body positions, relative to the centre's old cell and in each

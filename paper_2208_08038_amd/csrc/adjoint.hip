@@ -780,6 +780,26 @@ struct TileBox {
   int x0, y0, z0, tx, ty, tz, pitch, slab, plane;
 };
 
+
+// Adjoint of the per-body walls of a two-body ion along axis d (see the
+// reverse sweep of adjoint_one).
+template <typename Real>
+__device__ __noinline__ void walls_adjoint(const PushConst<Real>& c, int d, bool w1, bool w2,
+                                           Real& l_offn, Real& l_dln, Real& l_n1, Real& l_n2) {
+  const Real lR = l_offn, ls = l_dln * c.dxs[d];
+  Real lY1 = c.f2 * lR + ls, lY2 = c.f1 * lR - ls;
+  if (w1) {
+    lY1 = -lY1;
+    l_n1 = -l_n1;
+  }
+  if (w2) {
+    lY2 = -lY2;
+    l_n2 = -l_n2;
+  }
+  l_offn = lY1 + lY2;
+  l_dln = (c.f1 * lY1 - c.f2 * lY2) * c.idx[d];
+}
+
 // Reverse the cycle of particle p (see the file comment).
 // IN_TILE: the particle's cell is in the workgroup's tile, so its fields,
 // adjoint current and scatter live in the tile's LDS copies (known LDS
@@ -923,12 +943,18 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const Planes<Real
 #pragma unroll
     for (int q = 0; q < 3; q++) dln[q] = TWO ? dl[q] + c.dt * (v1[q] - v2[q]) : Real(0);
     bool refl[3] = {false, false, false};
+    unsigned walls = 0u;
 #pragma unroll
     for (int d = 0; d < ND; d++) {
       const Real vc = TWO ? (c.m1 * v1[d] + c.m2 * v2[d]) * c.inv_mc : v1[d];
       offn[d] = off[d] + c.dt * vc * c.idx[d];
-      refl[d] = reflect_wall(g.periodic[d], ci[d], g.n[d], g.pad, offn[d]);
-      if (refl[d]) dln[d] = -dln[d];
+      if (!TWO) refl[d] = reflect_wall(g.periodic[d], ci[d], g.n[d], g.pad, offn[d]);
+    }
+    if (TWO) {
+      // walls act on each body; the momenta flipped there are the stored
+      // output, not the n1, n2 the reverse of v = u / gamma needs
+      Real m1c[3] = {n1[0], n1[1], n1[2]}, m2c[3] = {n2[0], n2[1], n2[2]};
+      walls = two_body_walls<Real, ND>(g, c, ci, offn, dln, m1c, m2c);
     }
     Real y1[3] = {0, 0, 0}, y2[3] = {0, 0, 0};
 #pragma unroll
@@ -1004,15 +1030,20 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const Planes<Real
         }
       }
     }
-    // walls: the reflected components change sign
+    // walls.  A point particle: the reflected components change sign.  A
+    // two-body ion: in body coordinates Y1 = R + f1 s, Y2 = R - f2 s
+    // (s = delta / dx) a mirrored body's coordinate and momentum component
+    // change sign; the adjoint goes to body coordinates (transpose of the
+    // inverse map R = f2 Y1 + f1 Y2, s = Y1 - Y2), flips, and comes back.
 #pragma unroll
-    for (int d = 0; d < ND; d++)
-      if (refl[d]) {
+    for (int d = 0; d < ND; d++) {
+      if (!TWO && refl[d]) {
         l_offn[d] = -l_offn[d];
-        l_dln[d] = -l_dln[d];
         l_n1[d] = -l_n1[d];
-        l_n2[d] = -l_n2[d];
       }
+      const bool w1 = (walls >> d) & 1u, w2 = (walls >> (4 + d)) & 1u;
+      if (TWO && (w1 || w2)) walls_adjoint(c, d, w1, w2, l_offn[d], l_dln[d], l_n1[d], l_n2[d]);
+    }
     // move
 #pragma unroll
     for (int d = 0; d < ND; d++) {

@@ -195,14 +195,14 @@ int load_particles_t(pic_ctx* c, SpeciesHost& s, int64_t n, const double* x, con
       for (int a = 0; a < 3; a++) {
         double v = delta ? delta[3 * p + a] : 0.0;
         if (!std::isfinite(v)) return fail(c, PIC_ENAN, "non-finite delta");
-        // along walled axes each body stays within one cell beyond the walls
+        // along walled axes each body lies between the walls
         if (a < nd && !is_periodic(c->cfg, a)) {
           const double X = x[p * nd + a] / c->cfg.dx[a];
           const double X1 = X + (s.d.m2 / mc) * v / c->cfg.dx[a];
           const double X2 = X - (s.d.m1 / mc) * v / c->cfg.dx[a];
-          const double lo = c->g.pad - 1, hi = c->g.n[a] - c->g.pad + 1;
+          const double lo = c->g.pad, hi = c->g.n[a] - c->g.pad;
           if (!(X1 >= lo && X1 <= hi && X2 >= lo && X2 <= hi))
-            return fail(c, PIC_ERANGE, "a body is beyond one cell outside the particle walls");
+            return fail(c, PIC_ERANGE, "a body of a two-body ion is outside the particle walls");
         }
         ddl[p * 3 + a] = v;
       }

@@ -188,6 +188,7 @@ pic::PushConst<Real> push_const(const pic_ctx* c, const SpeciesHost& s) {
   k.q1 = (Real)d.q1;
   k.q2 = two ? (Real)d.q2 : Real(0);
   for (int a = 0; a < 3; a++) k.jf[a] = a < c->g.nd ? (Real)(-c->cfg.dx[a] / (dt * dv)) : Real(0);
+  for (int a = 0; a < 3; a++) k.dxs[a] = a < c->g.nd ? (Real)c->cfg.dx[a] : Real(0);
   k.inv_dv = (Real)(1.0 / dv);
   // Bound on one deposit term: charge x prefactor x shape factors.  The
   // running sum C of shape changes lies in [-1, 1]; the transverse factor

@@ -656,7 +656,8 @@ __device__ __forceinline__ void two_body_kick(const PushConst<Real>& c, Real wc,
   boris_rotate_kick(um2, c.a2, E2, B2, n2);
 }
 
-// Reflecting walls `pad` cells inside non-periodic faces.  off: new offset
+// Reflecting walls `pad` cells inside non-periodic faces for a point
+// particle (two-body ions: two_body_walls, per body).  off: new offset
 // relative to the old cell index ci (before the crossing rule).
 template <typename Real>
 __device__ __forceinline__ bool reflect(int periodic, int ci, int n, int pad, Real& off) {
@@ -756,9 +757,10 @@ __device__ __forceinline__ void load_state(const SpeciesDev<Real>& s, const Push
   st.w = s.w ? s.w[p] : Real(1);
 }
 
-// Along an axis with walls each body of an ion stays where every node its
-// shape reaches is interior: within one cell beyond the walls `pad` cells
-// inside the faces.  y: body positions relative to the cell ci.
+// Along an axis with walls each body of an ion stays between the walls
+// `pad` cells inside the faces (they mirror every body that reaches them),
+// where every node its shape reaches is interior.  y: body positions
+// relative to the cell ci.
 template <typename Real, int ND>
 __device__ __forceinline__ bool body_in_range(const GridInfo& g, const int ci[3],
                                               const Real y[3]) {
@@ -766,8 +768,7 @@ __device__ __forceinline__ bool body_in_range(const GridInfo& g, const int ci[3]
 #pragma unroll
   for (int d = 0; d < ND; d++) {
     if (g.periodic[d]) continue;
-    const Real X = Real(ci[d]) + y[d];
-    ok = ok && X >= Real(g.pad - 1) && X <= Real(g.n[d] - g.pad + 1);
+    ok = ok && y[d] >= Real(g.pad - ci[d]) && y[d] <= Real(g.n[d] - g.pad - ci[d]);
   }
   return ok;
 }
@@ -847,14 +848,9 @@ __device__ __noinline__ void advance_far(const GridInfo& g, const SpeciesDev<Rea
   }
   Real offn[3] = {0, 0, 0};
 #pragma unroll
-  for (int d = 0; d < ND; d++) {
+  for (int d = 0; d < ND; d++)
     offn[d] = off[d] + c.dt * (c.m1 * v1[d] + c.m2 * v2[d]) * c.inv_mc * c.idx[d];
-    if (reflect(g.periodic[d], ci[d], g.n[d], g.pad, offn[d])) {
-      n1[d] = -n1[d];
-      n2[d] = -n2[d];
-      dl[d] = -dl[d];
-    }
-  }
+  two_body_walls<Real, ND>(g, c, ci, offn, dl, n1, n2);
   Real y1[3] = {0, 0, 0}, y2[3] = {0, 0, 0};
 #pragma unroll
   for (int d = 0; d < ND; d++) {
@@ -1003,17 +999,12 @@ __device__ __forceinline__ void advance_particle(const GridInfo& g, const Specie
       v2[q] = n2[q] * ig2;
       dl[q] = dl[q] + c.dt * (v1[q] - v2[q]);
     }
-    // move: R += dt (m1 v1 + m2 v2)/m_c, delta += dt (v1 - v2)
+    // move: R += dt (m1 v1 + m2 v2)/m_c, delta += dt (v1 - v2); walls per body
     Real offn[3] = {0, 0, 0};
 #pragma unroll
-    for (int d = 0; d < ND; d++) {
+    for (int d = 0; d < ND; d++)
       offn[d] = off[d] + c.dt * (c.m1 * v1[d] + c.m2 * v2[d]) * c.inv_mc * c.idx[d];
-      if (reflect(g.periodic[d], ci[d], g.n[d], g.pad, offn[d])) {
-        n1[d] = -n1[d];
-        n2[d] = -n2[d];
-        dl[d] = -dl[d];
-      }
-    }
+    two_body_walls<Real, ND>(g, c, ci, offn, dl, n1, n2);
     Real y1[3] = {0, 0, 0}, y2[3] = {0, 0, 0};
 #pragma unroll
     for (int d = 0; d < ND; d++) {
@@ -1021,7 +1012,7 @@ __device__ __forceinline__ void advance_particle(const GridInfo& g, const Specie
       y1[d] = offn[d] + c.f1 * sd;
       y2[d] = offn[d] - c.f2 * sd;
     }
-    // along walled axes the bodies stay within one cell beyond the walls
+    // along walled axes the bodies stay between the walls
     bool range_ok = body_in_range<Real, ND>(g, ci, y1) && body_in_range<Real, ND>(g, ci, y2);
     if (c.deposit) {
       const Real qw1 = s.w ? c.q1 * W : c.qw1;

@@ -114,12 +114,12 @@ __global__ void __launch_bounds__(256) k_load(GridInfo g, LoadSrc src, SpeciesDe
     for (int a = 0; a < 3; a++) {
       dl[a] = src.delta ? src.delta[3 * p + a] : 0.0;
       if (!isfinite(dl[a])) bad |= PIC_ERR_NAN;
-      // along walled axes each body stays within one cell beyond the walls
+      // along walled axes each body lies between the walls
       if (a < ND && !g.periodic[a] && !bad) {
         const double X = src.x[p * ND + a] / g.dx[a];
         const double X1 = X + (sp.m2 / mc) * dl[a] / g.dx[a];
         const double X2 = X - (sp.m1 / mc) * dl[a] / g.dx[a];
-        const double lo = g.pad - 1, hi = g.n[a] - g.pad + 1;
+        const double lo = g.pad, hi = g.n[a] - g.pad;
         if (!(X1 >= lo && X1 <= hi && X2 >= lo && X2 <= hi)) bad |= PIC_ERR_RANGE;
       }
     }

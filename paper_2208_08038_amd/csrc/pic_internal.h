@@ -78,6 +78,7 @@ struct PushConst {
   Real weight;
   Real q1, q2;
   Real jf[3];      // -dx_d / (dt dV): Esirkepov prefactor per unit charge
+  Real dxs[3];     // cell sizes (resolved dimensions)
   Real inv_dv;
   // power-of-two scale of the fixed-point LDS current patch: every deposit
   // term of this species times jscale is below 2^46 in magnitude
@@ -100,6 +101,49 @@ __device__ __forceinline__ double pow43(double x) { return x * cbrt(x); }
 template <typename Real>
 __device__ __forceinline__ Real ion_inv_ac2(const PushConst<Real>& c, bool own_wc, Real wc) {
   return (own_wc && c.ac_k != Real(0)) ? c.ac_k * pow43(wc) : c.inv_ac2;
+}
+
+// Reflecting walls `pad` cells inside non-periodic faces act on each body
+// of a two-body ion (Sec. 2: each body is a particle with its own position):
+// a body past a wall is mirrored back into the box and its momentum
+// component reversed; the centre of mass and delta follow the move D_i (in
+// cells) of the mirrored body: R += (m_i / m_c) D_i, delta += +-D_i dx (+
+// for the nucleus, - for the cloud).  offn: the centre's new offset
+// relative to its old cell ci (before the crossing rule); dl, n1, n2: new
+// delta and momenta.  Returns which bodies were mirrored: bit d for the
+// nucleus along axis d, bit 4 + d for the cloud.
+template <typename Real, int ND>
+__device__ __forceinline__ unsigned two_body_walls(const GridInfo& g, const PushConst<Real>& c,
+                                                   const int ci[3], Real offn[3], Real dl[3],
+                                                   Real n1[3], Real n2[3]) {
+  unsigned mask = 0u;
+#pragma unroll
+  for (int d = 0; d < ND; d++) {
+    if (g.periodic[d]) continue;
+    const Real lo = Real(g.pad - ci[d]), hi = Real(g.n[d] - g.pad - ci[d]);
+    const Real sd = dl[d] * c.idx[d];
+    const Real y1 = offn[d] + c.f1 * sd, y2 = offn[d] - c.f2 * sd;
+    Real D1 = Real(0), D2 = Real(0);
+    if (y1 < lo)
+      D1 = Real(2) * (lo - y1);
+    else if (y1 > hi)
+      D1 = Real(2) * (hi - y1);
+    if (y2 < lo)
+      D2 = Real(2) * (lo - y2);
+    else if (y2 > hi)
+      D2 = Real(2) * (hi - y2);
+    if (D1 != Real(0)) {
+      mask |= 1u << d;
+      n1[d] = -n1[d];
+    }
+    if (D2 != Real(0)) {
+      mask |= 16u << d;
+      n2[d] = -n2[d];
+    }
+    offn[d] += c.f2 * D1 + c.f1 * D2;
+    dl[d] += (D1 - D2) * c.dxs[d];
+  }
+  return mask;
 }
 
 // Launchers (host).  All take the stream to launch on.

@@ -432,6 +432,14 @@ def ionised_slab_3d_count(n=(512, 256, 256), ppc: int = 8, pad: int = 3) -> int:
 # Case 4: mixed-precision study, Bragg geometry in 3D, 4 ions per cell
 # --------------------------------------------------------------------------
 
+def lattice_site_mean(sigma):
+    """Mean over a lattice cell of the site profile exp(-(a^2 + b^2)/(2 sigma^2))
+    with a, b the offsets (in lattice constants, |a|, |b| <= 1/2) from the
+    nearest site: (sigma sqrt(2 pi) erf(1 / (2 sqrt(2) sigma)))^2.  Dividing
+    by it keeps the mean weight at the species value."""
+    return (sigma * math.sqrt(2.0 * math.pi) * math.erf(0.5 / (math.sqrt(2.0) * sigma))) ** 2
+
+
 def mixed_precision_3d(n=(1024, 1024, 512), slab=(384, 640), ppc: int = 4, steps: int = 2000,
                        omega_c: float = 0.5, d_over_lambda: float = 1.5, sigma_site: float = 0.1,
                        a0: float = 1e-4, cycles: int = 20, precision: int = 32,
@@ -465,7 +473,7 @@ def mixed_precision_3d(n=(1024, 1024, 512), slab=(384, 640), ppc: int = 4, steps
     da = (a / d) - np.round(a / d)
     db = (b / d) - np.round(b / d)
     mod = np.exp(-(da ** 2 + db ** 2) / (2.0 * sigma_site ** 2))
-    wts = sp.weight * mod / mod.mean()
+    wts = sp.weight * mod / lattice_site_mean(sigma_site)
     parts = Particles(x=x, u1=np.zeros((x.shape[0], 3)), weight=wts)
     return Workload("mixed_precision_3d", grid, [(sp, parts)], steps, precision,
                     notes=f"{x.shape[0]} two-body ions, lattice-modulated weights")
@@ -527,3 +535,45 @@ def ionised_slab_3d_device_chunk(n=(512, 256, 256), ppc: int = 8, x_cells=(3, 35
             u *= thermal_sigma(t_e_ev, 1.0)
             out += [x, u]
     return tuple(out)
+
+
+def mixed_precision_3d_device_chunk(n=(1024, 1024, 512), ppc: int = 4, x_cells=(384, 400),
+                                    chunk: int = 0, device="cuda", d_over_lambda: float = 1.5,
+                                    sigma_site: float = 0.1, config_id: int = 4):
+    """Same recipe as mixed_precision_3d for the x planes x_cells, drawn with
+    torch's Philox generator on the GPU (seed = base seed + config id, offset
+    by the chunk), as FP64 device tensors (x, weight / species weight),
+    particles enumerated cell by cell (x fastest), at rest.  Holds no method
+    arithmetic."""
+    import torch
+    dx = TWO_PI / 32.0
+    lam = TWO_PI
+    d = d_over_lambda * lam
+    theta_b = math.asin(lam / (2.0 * d))
+    ny, nz = n[1], n[2]
+    g = torch.Generator(device=device)
+    g.manual_seed((BASE_SEED + config_id) * 1000003 + chunk)
+    nxc = x_cells[1] - x_cells[0]
+    m = nxc * ny * nz * ppc
+    p = torch.arange(m, device=device, dtype=torch.int64)
+    cell = p // ppc
+    sub = (p % ppc).to(torch.float64)
+    cx = (cell % nxc).to(torch.float64) + x_cells[0]
+    rem = cell // nxc
+    cy = (rem % ny).to(torch.float64)
+    cz = (rem // ny).to(torch.float64)
+    del p, cell, rem
+    x = torch.empty((m, 3), device=device, dtype=torch.float64)
+    x[:, 0] = (cx + (sub + torch.rand(m, generator=g, device=device, dtype=torch.float64))
+               / ppc) * dx
+    x[:, 1] = (cy + torch.rand(m, generator=g, device=device, dtype=torch.float64)) * dx
+    x[:, 2] = (cz + torch.rand(m, generator=g, device=device, dtype=torch.float64)) * dx
+    del cx, cy, cz, sub
+    ct, st = math.cos(theta_b), math.sin(theta_b)
+    a = (x[:, 0] * ct + x[:, 1] * st) / d
+    b = (-x[:, 0] * st + x[:, 1] * ct) / d
+    a -= torch.round(a)
+    b -= torch.round(b)
+    w = torch.exp(-(a * a + b * b) / (2.0 * sigma_site ** 2)) / lattice_site_mean(sigma_site)
+    del a, b
+    return x, w

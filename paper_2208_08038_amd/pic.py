@@ -325,6 +325,13 @@ class Simulation:
         self._check(self.lib.pic_read_fields(self.ctx, _dp(E), _dp(B), _dp(J)))
         return E, B, J
 
+    def fields_E(self):
+        """E only (3 x ncell), for grids where E, B and J at once would not fit
+        the host."""
+        E = np.zeros((3, self.ncell))
+        self._check(self.lib.pic_read_fields(self.ctx, _dp(E), None, None))
+        return E
+
     def count(self, sid: int) -> int:
         n = C.c_int64()
         self._check(self.lib.pic_count(self.ctx, sid, C.byref(n)))

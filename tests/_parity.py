@@ -36,9 +36,9 @@ def random_workload(ndim, n_ion, n_el, seed, shape=None, dx=None, bc=PERIODIC, v
     pad = g.pad if bc == OPEN else 0
     species = []
 
-    def pos(n):
-        lo = np.array([pad] * ndim, float)
-        hi = np.array([s - pad for s in shape], float)
+    def pos(n, margin=0.0):
+        lo = np.array([pad + margin] * ndim, float)
+        hi = np.array([s - pad - margin for s in shape], float)
         return (lo + (hi - lo) * rng.random((n, ndim))) * np.array(dx)
 
     def mom(n, vmax):
@@ -50,7 +50,9 @@ def random_workload(ndim, n_ion, n_el, seed, shape=None, dx=None, bc=PERIODIC, v
         sp = Species(TWO_BODY, 5.0, 40.0, -3.0, 3.0, weight=weight, omega_c=2.0,
                      a_c=math.inf if harmonic else 0.0, nu=nu, name="ion")
         u = mom(n_ion, vmax_ion)
-        parts = Particles(x=pos(n_ion), u1=u, u2=u + rng.normal(scale=1e-3, size=u.shape),
+        # both bodies between the walls: the cloud sits up to 0.1 cell off the centre
+        parts = Particles(x=pos(n_ion, 0.15 if bc == OPEN else 0.0), u1=u,
+                          u2=u + rng.normal(scale=1e-3, size=u.shape),
                           delta=rng.uniform(-0.1, 0.1, (n_ion, 3)) * min(dx),
                           omega_c=rng.uniform(1.0, 3.0, n_ion) if per_particle else None,
                           weight=rng.uniform(0.5, 1.5, n_ion) * weight if per_particle else None)

@@ -476,9 +476,9 @@ def test_load_errors(pic):
     with pytest.raises(pic.PicError) as e:
         s.load_particles(sid, bad_u)
     assert e.value.code == pic.PIC_ENAN
-    # the cloud more than one cell beyond the particle wall (3 cells in)
+    # the cloud beyond the particle wall (3 cells in)
     bad_d = Particles(x=np.array([[3.5 * 0.3]]), u1=np.zeros((1, 3)),
-                      delta=np.array([[2.0 * 0.3, 0, 0]]))
+                      delta=np.array([[1.0 * 0.3, 0, 0]]))
     with pytest.raises(pic.PicError) as e:
         s.load_particles(sid, bad_d)
     assert e.value.code == pic.PIC_ERANGE
@@ -507,20 +507,22 @@ def test_load_errors(pic):
 
 
 def test_device_error_word(pic):
-    """A cloud driven more than one cell beyond the particle wall during a
-    step raises PIC_ERANGE at the next diagnostics (set by the kernel, not
-    by a fault)."""
+    """A momentum that overflows during a step (a field of 1e308 in a frozen
+    grid) raises PIC_ENAN at the next diagnostics: the kernel flags it, the
+    particle stops, nothing faults."""
     _say("case: device error word")
     g = small_grid(1, (16,), (0.3,), bc=OPEN)
     s = pic.Simulation(g, precision=64, flags=pic.FROZEN_FIELDS)
-    sid = s.add_species(Species(TWO_BODY, 2.0, 10.0, -1.0, 1.0, omega_c=1e-6, a_c=math.inf), 1)
-    s.load_particles(sid, Particles(x=np.array([[3.4 * 0.3]]), u1=np.array([[0.0, 0, 0]]),
-                                    u2=np.array([[-7.0, 0, 0]]),
-                                    delta=np.array([[0.0, 0, 0]])))
-    s.step(3)
+    sid = s.add_species(Species(TWO_BODY, 2.0, 10.0, -1.0, 1.0, omega_c=1.0, a_c=math.inf), 1)
+    s.load_particles(sid, Particles(x=np.array([[8.4 * 0.3]]), u1=np.zeros((1, 3)),
+                                    u2=np.zeros((1, 3)), delta=np.zeros((1, 3))))
+    E = np.zeros((3, 16))
+    E[1] = 1e308  # kicks of ~5e306 per step: the momentum overflows within 40 steps
+    s.load_fields(E, np.zeros((3, 16)))
+    s.step(40)
     d = s.diagnostics(check=False)
-    assert d["status"] == pic.PIC_ERANGE
-    assert d["error_word"] & pic.ERR_RANGE
+    assert d["status"] == pic.PIC_ENAN
+    assert d["error_word"] & pic.ERR_NAN
 
 
 def test_timing_events(pic):

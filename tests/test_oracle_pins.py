@@ -584,7 +584,8 @@ def test_charge_continuity_random_particles(oracle_built, ndim, bc):
     o = Oracle(g, flags=FROZEN_FIELDS | CHARGE_CHECK)
     nio, nel = 60, 40
     pad = 3 if bc == OPEN else 0
-    xi, ui = _random_state(rng, ndim, nio, shape, dx, pad=pad, vmax=0.6)
+    # both bodies of an ion between the walls (|delta| <= 0.15 of the smallest cell)
+    xi, ui = _random_state(rng, ndim, nio, shape, dx, pad=pad + 0.2 if pad else 0, vmax=0.6)
     sp = Species(TWO_BODY, 5.0, 30.0, -3.0, 3.0, weight=0.7, omega_c=0.5, a_c=0.0, nu=0.1)
     sid = o.add_species(sp, nio)
     delta = rng.uniform(-0.15, 0.15, size=(nio, 3)) * min(dx)

@@ -355,3 +355,41 @@ def test_ionised_medium_index(oracle_built):
     assert abs(np.sqrt(eps + n_e).real - n_theory) > 3e-3
     mean_wc = np.sqrt(1.0 - n_e - wpc2 + wpb2 / (np.mean(wc) ** 2 - 1.0)).real
     assert abs(mean_wc - n_theory) > 1e-2
+
+
+# ------------------------------------------------ walls act on each body
+
+def test_walls_mirror_each_body(oracle_built):
+    """A particle wall mirrors the body that crosses it, not the centre of
+    mass: the cloud of an ion reaching the wall comes back to 2 w - Y with its
+    momentum component reversed while the nucleus goes on, and the current of
+    the step still conserves charge."""
+    dx, dt = 0.5, 0.25
+    g = _grid(1, (32,), (dx,), dt, bc=OPEN)
+    q1, m1, q2, m2 = 3.0, 30.0, -3.0, 3.0
+    mc = m1 + m2
+    f1, f2 = m2 / mc, m1 / mc
+    sp = Species(TWO_BODY, q1, m1, q2, m2, weight=0.5, omega_c=1e-9, a_c=INF)
+    o = Oracle(g, flags=FROZEN_FIELDS | CHARGE_CHECK)
+    sid = o.add_species(sp, 1)
+    R, s = 4.0, 1.0  # cells; the cloud at R - f2 s = 3.09, just inside the wall at 3
+    u1 = np.array([0.05, 0.01, 0.0])
+    u2 = np.array([-0.5, 0.2, 0.1])
+    o.load_particles(sid, Particles(x=np.array([[R * dx]]), u1=u1[None], u2=u2[None],
+                                    delta=np.array([[s * dx, 0.0, 0.0]])))
+    o.step(1)
+    d = o.diagnostics()
+    assert d["error_word"] == 0
+    st = o.particles(sid)
+    v1 = u1 / math.sqrt(1 + u1 @ u1)
+    v2 = u2 / math.sqrt(1 + u2 @ u2)
+    Y1 = R + f1 * s + dt * v1[0] / dx
+    Y2 = R - f2 * s + dt * v2[0] / dx
+    assert Y2 < 3.0 < R  # the cloud crossed the wall, the centre did not
+    Rn = st["cell"][0, 0] + st["off"][0, 0]
+    sn = st["delta"][0, 0] / dx
+    assert abs((Rn + f1 * sn) - Y1) < 1e-13
+    assert abs((Rn - f2 * sn) - (6.0 - Y2)) < 1e-13
+    assert np.allclose(st["u1"][0], u1, rtol=0, atol=1e-14)
+    assert np.allclose(st["u2"][0], [-u2[0], u2[1], u2[2]], rtol=0, atol=1e-14)
+    assert d["div_max"] < 1e-13 * d["rho_l2"]
