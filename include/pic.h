@@ -20,9 +20,10 @@
  *  - Host arrays passed in are read during the call and never retained;
  *    the caller keeps ownership.  Host arrays passed out are written during
  *    the call (the call synchronises the stream first).
- *  - All device memory comes from the caller's allocator (pic_allocator);
- *    with a NULL allocator the library uses hipMalloc/hipFree.  Memory is
- *    released by pic_destroy.
+ *  - All device memory comes from the caller's allocator (pic_allocator,
+ *    required): the library never calls hipMalloc.  Memory is released
+ *    through the allocator's free by pic_destroy.  (Pinned host memory for
+ *    the asynchronous counter read-back is the library's own.)
  *  - Work is enqueued on the HIP stream given to pic_create.  pic_step is
  *    asynchronous; errors found on the device (non-finite state, particle
  *    out of range) surface at the next pic_diagnostics.  A context is not
@@ -179,7 +180,8 @@ typedef struct {
 typedef struct pic_ctx pic_ctx;
 
 /* Create a simulation context.  cfg: grid, time step, boundaries, laser,
-   flags.  alloc: device allocator (NULL: hipMalloc).  hip_stream: a
+   flags.  alloc: device allocator (required; NULL or a NULL member:
+   PIC_EINVAL, checked before any HIP call).  hip_stream: a
    hipStream_t (NULL: the null stream).  *out receives the context.
    Validates the CFL limit, sizes and boundary kinds (PIC_EINVAL). */
 int pic_create(const pic_config* cfg, const pic_allocator* alloc, void* hip_stream,

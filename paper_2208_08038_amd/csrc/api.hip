@@ -30,15 +30,11 @@ int fail(pic_ctx* c, int code, const std::string& msg) {
   return code;
 }
 
+// All device memory of a context comes from the caller's allocator.
 void* dev_alloc(pic_ctx* c, size_t bytes) {
   if (bytes == 0) bytes = 256;
   bytes = (bytes + 255) & ~size_t(255);
-  void* p = nullptr;
-  if (c->use_hip_malloc) {
-    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
-  } else {
-    p = c->alloc.alloc(bytes, c->alloc.user);
-  }
+  void* p = c->alloc.alloc(bytes, c->alloc.user);
   if (p) c->allocs.push_back(p);
   return p;
 }
@@ -48,10 +44,7 @@ void dev_release(pic_ctx* c, void* p) {
   auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
   if (it == c->allocs.end()) return;
   c->allocs.erase(it);
-  if (c->use_hip_malloc)
-    (void)hipFree(p);
-  else
-    c->alloc.free(p, c->alloc.user);
+  c->alloc.free(p, c->alloc.user);
 }
 
 namespace {
@@ -67,12 +60,7 @@ void release_host(pic_ctx* c) {
 }
 
 void dev_free_all(pic_ctx* c) {
-  for (void* p : c->allocs) {
-    if (c->use_hip_malloc)
-      (void)hipFree(p);
-    else
-      c->alloc.free(p, c->alloc.user);
-  }
+  for (void* p : c->allocs) c->alloc.free(p, c->alloc.user);
   c->allocs.clear();
 }
 
@@ -776,13 +764,12 @@ int pic_create(const pic_config* cfg, const pic_allocator* alloc, void* hip_stre
   }
   if (!(cfg->dt * std::sqrt(inv2) < 1.0))
     return fail(nullptr, PIC_EINVAL, "time step violates the CFL limit");
+  if (!alloc || !alloc->alloc || !alloc->free)
+    return fail(nullptr, PIC_EINVAL, "an allocator with alloc and free is required");
 
   pic_ctx* c = new pic_ctx();
   c->cfg = *cfg;
-  if (alloc && alloc->alloc && alloc->free) {
-    c->alloc = *alloc;
-    c->use_hip_malloc = false;
-  }
+  c->alloc = *alloc;
   c->stream = static_cast<hipStream_t>(hip_stream);
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;

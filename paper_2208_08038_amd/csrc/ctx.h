@@ -49,8 +49,7 @@ constexpr int kMaxSpecies = 62;
 
 struct pic_ctx {
   pic_config cfg{};
-  pic_allocator alloc{};
-  bool use_hip_malloc = true;
+  pic_allocator alloc{};  // every device allocation of the context goes through it
   hipStream_t stream = nullptr;
   int device = 0;  // HIP device current at pic_create (the stream's device)
   GridInfo g{};

@@ -80,5 +80,21 @@ def test_create_rejects_invalid_config_on_host(lib, bad):
     assert len(lib.pic_last_error(None)) > 0
 
 
+def test_create_requires_an_allocator(lib):
+    """The library allocates device memory only through the caller's
+    allocator: a valid configuration with no allocator is refused on the host,
+    before any HIP call."""
+    from paper_2208_08038_amd import pic
+    cfg = _cfg(pic)
+    ctx = C.c_void_p()
+    rc = lib.pic_create(C.byref(cfg), None, None, C.byref(ctx))
+    assert rc == pic.PIC_EINVAL
+    assert not ctx.value
+    assert b"allocator" in lib.pic_last_error(None)
+    half = pic.PicAllocator()  # alloc and free left NULL
+    rc = lib.pic_create(C.byref(cfg), C.byref(half), None, C.byref(ctx))
+    assert rc == pic.PIC_EINVAL and b"allocator" in lib.pic_last_error(None)
+
+
 def test_version_string(lib):
     assert b"gfx950" in lib.pic_version()
