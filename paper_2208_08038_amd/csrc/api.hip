@@ -451,7 +451,28 @@ int advance_one(pic_ctx* c, const pic::LaserDev& las, const StepOpts& o,
                                c->dout + 4, c->stream);
     c->residual_valid = true;
   }
-  if (!frozen) {
+  if (!frozen && c->yee_fused) {
+    pic::FieldPtrs<Real> fo = f;
+    Real* ob = static_cast<Real*>(c->fields_alt);
+    for (int a = 0; a < 3; a++) {
+      fo.E[a] = ob + a * g.plane;
+      fo.B[a] = ob + (3 + a) * g.plane;
+    }
+    Real* hin[3][2] = {};
+    Real* hout[3][2] = {};
+    for (int d = 0; d < 3; d++)
+      for (int t = 0; t < 2; t++) {
+        hin[d][t] = static_cast<Real*>(c->mur_b[d][t]);
+        hout[d][t] = static_cast<Real*>(c->mur_b_alt[d][t]);
+      }
+    hipError_t e = pic::launch_yee_fused<Real>(g, f, fo, hin, hout, las, c->step, c->stream);
+    if (e != hipSuccess)
+      return fail(c, PIC_EHIP, std::string("field step: ") + hipGetErrorString(e));
+    std::swap(c->fields, c->fields_alt);
+    for (int d = 0; d < 3; d++)
+      for (int t = 0; t < 2; t++) std::swap(c->mur_b[d][t], c->mur_b_alt[d][t]);
+    f = field_ptrs<Real>(c);
+  } else if (!frozen) {
     pic::launch_b_half<Real>(g, f, c->stream);
     pic::launch_fill_periodic<Real>(g, eb + 3, 3, c->stream);
     for (int d = 0; d < g.nd; d++)
@@ -572,8 +593,9 @@ int read_fields_t(pic_ctx* c, double* E, double* B, double* J) {
                      J, J ? J + ncell : nullptr, J ? J + 2 * ncell : nullptr};
   for (int comp = 0; comp < 9; comp++) {
     if (!outs[comp]) continue;
-    HIPCHK(c, hipMemcpy(plane.data(), static_cast<Real*>(c->fields) + comp * g.plane,
-                        g.plane * sizeof(Real), hipMemcpyDeviceToHost));
+    const Real* src = comp < 6 ? static_cast<Real*>(c->fields) + comp * g.plane
+                               : static_cast<Real*>(c->jfield) + (comp - 6) * g.plane;
+    HIPCHK(c, hipMemcpy(plane.data(), src, g.plane * sizeof(Real), hipMemcpyDeviceToHost));
     for (int k = 0; k < g.n[2]; k++)
       for (int j = 0; j < g.n[1]; j++)
         for (int i = 0; i < g.n[0]; i++)
@@ -813,7 +835,10 @@ int pic_create(const pic_config* cfg, const pic_allocator* alloc, void* hip_stre
   c->tiled = !(cfg->flags & PIC_FLAG_GLOBAL_KERNEL) && pic::tiled_supported(g, c->tg, c->rsize);
 
   size_t rs = c->rsize;
-  c->fields = dev_alloc(c, 9 * g.plane * rs);
+  c->yee_fused = g.nd <= 2;  // 3D keeps the three streaming passes
+  c->fields = dev_alloc(c, 6 * g.plane * rs);
+  c->jfield = dev_alloc(c, 3 * g.plane * rs);
+  c->fields_alt = c->yee_fused ? dev_alloc(c, 6 * g.plane * rs) : nullptr;
   c->err = static_cast<uint32_t*>(dev_alloc(c, 256));
   c->load_err = static_cast<uint32_t*>(dev_alloc(c, 256));
   c->nslow = static_cast<uint32_t*>(dev_alloc(c, 256));
@@ -822,7 +847,7 @@ int pic_create(const pic_config* cfg, const pic_allocator* alloc, void* hip_stre
   c->dout = static_cast<double*>(dev_alloc(c, 32 * sizeof(double)));
   c->rho0 = static_cast<double*>(dev_alloc(c, g.plane * sizeof(double)));
   c->rho1 = static_cast<double*>(dev_alloc(c, g.plane * sizeof(double)));
-  if (!c->fields || !c->err || !c->load_err || !c->nslow || !c->nfar || !c->partials || !c->dout || !c->rho0 || !c->rho1) {
+  if (!c->fields || !c->jfield || (c->yee_fused && !c->fields_alt) || !c->err || !c->load_err || !c->nslow || !c->nfar || !c->partials || !c->dout || !c->rho0 || !c->rho1) {
     dev_free_all(c);
     delete c;
     return fail(nullptr, PIC_ENOMEM, "device allocation failed");
@@ -834,14 +859,18 @@ int pic_create(const pic_config* cfg, const pic_allocator* alloc, void* hip_stre
     for (int t = 0; t < 2; t++) {
       c->mur_b[d][t] = dev_alloc(c, np * rs);
       c->mur_e[d][t] = dev_alloc(c, np * rs);
-      if (!c->mur_b[d][t] || !c->mur_e[d][t]) {
+      if (c->yee_fused) c->mur_b_alt[d][t] = dev_alloc(c, np * rs);
+      if (!c->mur_b[d][t] || !c->mur_e[d][t] || (c->yee_fused && !c->mur_b_alt[d][t])) {
         dev_free_all(c);
         delete c;
         return fail(nullptr, PIC_ENOMEM, "device allocation failed");
       }
     }
   }
-  hipError_t e = hipMemsetAsync(c->fields, 0, 9 * g.plane * rs, c->stream);
+  hipError_t e = hipMemsetAsync(c->fields, 0, 6 * g.plane * rs, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->jfield, 0, 3 * g.plane * rs, c->stream);
+  if (e == hipSuccess && c->fields_alt)
+    e = hipMemsetAsync(c->fields_alt, 0, 6 * g.plane * rs, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->err, 0, 256, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->nslow, 0, 256, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->nfar, 0, 256, c->stream);
@@ -853,6 +882,8 @@ int pic_create(const pic_config* cfg, const pic_allocator* alloc, void* hip_stre
     for (int t = 0; t < 2 && e == hipSuccess; t++) {
       e = hipMemsetAsync(c->mur_b[d][t], 0, np * rs, c->stream);
       if (e == hipSuccess) e = hipMemsetAsync(c->mur_e[d][t], 0, np * rs, c->stream);
+      if (e == hipSuccess && c->mur_b_alt[d][t])
+        e = hipMemsetAsync(c->mur_b_alt[d][t], 0, np * rs, c->stream);
     }
   }
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->host_counts, 2 * 128 * sizeof(uint32_t));

@@ -55,8 +55,14 @@ struct pic_ctx {
   GridInfo g{};
   int prec = 64;
   size_t rsize = 8;
-  void* fields = nullptr;  // 9 planes
+  void* fields = nullptr;      // E, B: 6 planes (the present state)
+  void* jfield = nullptr;      // J: 3 planes
+  // the one-pass field step writes E, B and the low faces' Mur history to
+  // a second set and the two sets swap roles after each step
+  bool yee_fused = false;
+  void* fields_alt = nullptr;  // 6 planes
   void* mur_b[3][2] = {};
+  void* mur_b_alt[3][2] = {};
   void* mur_e[3][2] = {};
   uint32_t* err = nullptr;
   uint32_t* load_err = nullptr;
@@ -125,10 +131,11 @@ template <typename Real>
 pic::FieldPtrs<Real> field_ptrs(const pic_ctx* c) {
   pic::FieldPtrs<Real> f;
   Real* base = static_cast<Real*>(c->fields);
+  Real* jb = static_cast<Real*>(c->jfield);
   for (int a = 0; a < 3; a++) {
     f.E[a] = base + (0 + a) * c->g.plane;
     f.B[a] = base + (3 + a) * c->g.plane;
-    f.J[a] = base + (6 + a) * c->g.plane;
+    f.J[a] = jb + a * c->g.plane;
   }
   return f;
 }

@@ -340,6 +340,272 @@ __global__ void k_mur_high_e(GridInfo g, FieldPtrs<Real> f, int d, const Real* s
   Ef[fg] = (Real)((double)save[pi] + kc * ((double)Ef[f1] - (double)Ef[fg]));
 }
 
+// ---------------------------------------------------------------------------
+// One field step in one pass over a tile of cells: B half step, E full step
+// with J, B half step, with the Mur faces (and the laser of x-min) that sit
+// between them.  The first-half B and the new E stay in LDS; E and B are read
+// from one buffer and written to the other (neighbouring tiles read this
+// tile's old values in their halos while it runs), the Mur history of the
+// low faces likewise.  Per cell it reads E, B, J and writes E, B once.
+template <typename Real, int ND>
+struct YeeTile {
+  static constexpr int TX = ND == 1 ? 512 : 64;
+  static constexpr int TY = ND == 1 ? 1 : 8;
+  // LDS regions per component, along each resolved dim: old E on
+  // [-1, T + 1], first-half B on [-1, T], new E on [0, T]
+  static constexpr int EX = TX + 3, EY = ND > 1 ? TY + 3 : 1;
+  static constexpr int BX = TX + 2, BY = ND > 1 ? TY + 2 : 1;
+  static constexpr int PX = TX + 1, PY = ND > 1 ? TY + 1 : 1;
+  static constexpr int NE = EX * EY, NB = BX * BY, NP = PX * PY;
+  static constexpr size_t lds = (size_t)3 * (NE + NB + NP) * sizeof(Real);
+};
+
+template <typename Real>
+struct MurHistory {
+  Real* in[3][2];   // B just inside each low open face after the last step's first half
+  Real* out[3][2];  // the same after this step's
+};
+
+// curl E at a B node (forward differences) and curl B at an E node
+// (backward differences), from planes with strides 1 (x) and sy (y)
+template <typename Real, int ND>
+__device__ __forceinline__ void curl_fwd(const Real* Ex, const Real* Ey, const Real* Ez, int e,
+                                         int sy, Real ix, Real iy, Real& cx, Real& cy,
+                                         Real& cz) {
+  const Real ex = Ex[e], ey = Ey[e], ez = Ez[e];
+  cx = 0;
+  cy = 0;
+  cz = 0;
+  cy -= (Ez[e + 1] - ez) * ix;
+  cz += (Ey[e + 1] - ey) * ix;
+  if (ND > 1) {
+    cx += (Ez[e + sy] - ez) * iy;
+    cz -= (Ex[e + sy] - ex) * iy;
+  }
+}
+
+template <typename Real, int ND>
+__device__ __forceinline__ void curl_bwd(const Real* Bx, const Real* By, const Real* Bz, int b,
+                                         int sy, Real ix, Real iy, Real& cx, Real& cy,
+                                         Real& cz) {
+  const Real bx = Bx[b], by = By[b], bz = Bz[b];
+  cx = 0;
+  cy = 0;
+  cz = 0;
+  cy -= (bz - Bz[b - 1]) * ix;
+  cz += (by - By[b - 1]) * ix;
+  if (ND > 1) {
+    cx += (bz - Bz[b - sy]) * iy;
+    cz -= (bx - Bx[b - sy]) * iy;
+  }
+}
+
+// 1D and 2D (the 3D field step keeps its three streaming passes, which
+// stay at the bandwidth the three-dimensional halos of one pass would
+// spend); x is dim 0, y dim 1, and the tangential components of the x and
+// y faces are (1, 2) and (0, 2).
+template <typename Real, int ND>
+__global__ void __launch_bounds__(256) k_yee_fused(GridInfo g, FieldPtrs<Real> fi,
+                                                   FieldPtrs<Real> fo, MurHistory<Real> mh,
+                                                   LaserDev L, int64_t step, Real h, Real dt,
+                                                   Real ix, Real iy) {
+  static_assert(ND == 1 || ND == 2, "one-pass field step in 1D and 2D");
+  using T = YeeTile<Real, ND>;
+  extern __shared__ __align__(16) unsigned char yee_lds[];
+  Real* sE = reinterpret_cast<Real*>(yee_lds);  // [3][NE]
+  Real* sB = sE + 3 * T::NE;                      // [3][NB]
+  Real* sP = sB + 3 * T::NB;                      // [3][NP]
+  const int ntx = (g.n[0] + T::TX - 1) / T::TX;
+  const int nty = ND > 1 ? (g.n[1] + T::TY - 1) / T::TY : 1;
+  // consecutive tiles on one XCD (workgroups go round-robin over the 8),
+  // so that neighbours' halos meet in the same L2
+  const int64_t ntiles = (int64_t)ntx * nty;
+  const int64_t b = blockIdx.x, xcd = b & 7, per = ntiles >> 3, rem = ntiles & 7;
+  const int64_t tile = xcd * per + (xcd < rem ? xcd : rem) + (b >> 3);
+  const int ox = (int)(tile % ntx) * T::TX, oy = ND > 1 ? (int)(tile / ntx) * T::TY : 0;
+  const int ex = min(T::TX, g.n[0] - ox), ey = ND > 1 ? min(T::TY, g.n[1] - oy) : 1;
+  const bool px = g.periodic[0], py = ND > 1 && g.periodic[1];
+  auto sidx = [&](int x, int y) -> int64_t {
+    return g.origin + (ox + x) + (int64_t)(oy + y) * g.sy;
+  };
+  auto eix = [](int x, int y) { return (x + 1) + (ND > 1 ? (y + 1) * T::EX : 0); };
+  auto bix = [](int x, int y) { return (x + 1) + (ND > 1 ? (y + 1) * T::BX : 0); };
+  auto pix = [](int x, int y) { return x + (ND > 1 ? y * T::PX : 0); };
+
+  // Every global load of the tile is issued before the first barrier: old
+  // E into LDS, and into registers the old B of the positions this thread
+  // advances in 2 and the J of those it advances in 3.
+  constexpr int KE = (T::NE + 255) / 256, KB = (T::NB + 255) / 256, KP = (T::NP + 255) / 256;
+  Real rb[KB][3], rj[KP][3];
+  bool vb[KB], vp[KP];
+  // 2's positions: B after the first half step on [-1, ext] (the low guard
+  // of an open face takes its Mur value from the face node, in 2)
+#pragma unroll
+  for (int k = 0; k < KB; k++) {
+    const int q = threadIdx.x + 256 * k;
+    const int x = q % T::BX - 1, y = ND > 1 ? q / T::BX - 1 : 0;
+    const bool v = q < T::NB && x <= ex && (ND < 2 || y <= ey) && (px || ox + x >= 0) &&
+                   (ND < 2 || py || oy + y >= 0);
+    vb[k] = v;
+    const int64_t si = v ? sidx(x, y) : g.origin;
+#pragma unroll
+    for (int c = 0; c < 3; c++) rb[k][c] = fi.B[c][si];
+  }
+  // 3's positions: new E on [0, ext] (the high guard of an open face takes
+  // its Mur value from the node below, in 3); J at a periodic guard is read
+  // at its interior image (the folded guards are zero)
+#pragma unroll
+  for (int k = 0; k < KP; k++) {
+    const int q = threadIdx.x + 256 * k;
+    const int x = q % T::PX, y = ND > 1 ? q / T::PX : 0;
+    int gx = ox + x, gy = oy + y;
+    bool v = q < T::NP && x <= ex && (ND < 2 || y <= ey);
+    if (gx >= g.n[0]) {
+      if (px)
+        gx -= g.n[0];
+      else
+        v = false;
+    }
+    if (ND > 1 && gy >= g.n[1]) {
+      if (py)
+        gy -= g.n[1];
+      else
+        v = false;
+    }
+    vp[k] = v;
+    const int64_t sj = v ? g.origin + gx + (int64_t)gy * g.sy : g.origin;
+#pragma unroll
+    for (int c = 0; c < 3; c++) rj[k][c] = fi.J[c][sj];
+  }
+  // 1. old E on [-1, ext + 1] (guard layers hold the periodic images)
+#pragma unroll
+  for (int k = 0; k < KE; k++) {
+    const int q = threadIdx.x + 256 * k;
+    const int x = q % T::EX - 1, y = ND > 1 ? q / T::EX - 1 : 0;
+    if (q >= T::NE || x > ex + 1 || (ND > 1 && y > ey + 1)) continue;
+    const int64_t si = sidx(x, y);
+#pragma unroll
+    for (int c = 0; c < 3; c++) sE[c * T::NE + q] = fi.E[c][si];
+  }
+  __syncthreads();
+
+  // 2. B after the first half step
+#pragma unroll
+  for (int k = 0; k < KB; k++) {
+    if (!vb[k]) continue;
+    const int q = threadIdx.x + 256 * k;
+    const int x = q % T::BX - 1, y = ND > 1 ? q / T::BX - 1 : 0;
+    Real cx, cy, cz;
+    curl_fwd<Real, ND>(sE, sE + T::NE, sE + 2 * T::NE, eix(x, y), T::EX, ix, iy, cx, cy, cz);
+    sB[q] = rb[k][0] - h * cx;
+    sB[T::NB + q] = rb[k][1] - h * cy;
+    sB[2 * T::NB + q] = rb[k][2] - h * cz;
+  }
+  __syncthreads();
+
+  // 2b. Mur on the tangential B half a cell below each open low face this
+  //     tile touches (with the incident laser B at x-min)
+  for (int d = 0; d < ND; d++) {
+    if ((d == 0 ? px : py) || (d == 0 ? ox : oy) != 0) continue;
+    // face nodes along the other dim over the B region [-1, ext]
+    const int nf = ND > 1 ? (d == 0 ? ey : ex) + 2 : 1;
+    const int na = d == 0 ? g.n[1] : g.n[0];
+    const bool pa = d == 0 ? py : px;
+    const int oa = d == 0 ? oy : ox, ea = d == 0 ? ey : ex;
+    const double dtd = g.dt, dxd = g.dx[d], kc = (dtd - dxd) / (dtd + dxd);
+    for (int q = threadIdx.x; q < 2 * nf; q += 256) {
+      const int qq = q / nf, la = ND > 1 ? q % nf - 1 : 0;
+      // the face node's coordinate along the face, in the interior range
+      // (a periodic image maps to it); the corners of two open faces are unused
+      int ga = oa + la;
+      if (ND > 1 && (ga < 0 || ga >= na)) {
+        if (!pa) continue;
+        ga = ga < 0 ? ga + na : ga - na;
+      }
+      const int comp = qq == 0 ? (d == 0 ? 1 : 0) : 2;
+      const int b1 = d == 0 ? bix(0, la) : bix(la, 0);
+      const int bg = d == 0 ? b1 - 1 : b1 - T::BX;
+      const int64_t sg = d == 0 ? g.origin - 1 + (int64_t)ga * g.sy : g.origin + ga - g.sy;
+      double ig_m = 0, ig_p = 0, i1_m = 0, i1_p = 0;
+      if (d == 0 && L.on) {
+        const double tn = (double)step * dtd;
+        ig_m = b_incident(g, L, comp, -1, ga, 0, tn - 0.5 * dtd);
+        ig_p = b_incident(g, L, comp, -1, ga, 0, tn + 0.5 * dtd);
+        i1_m = b_incident(g, L, comp, 0, ga, 0, tn - 0.5 * dtd);
+        i1_p = b_incident(g, L, comp, 0, ga, 0, tn + 0.5 * dtd);
+      }
+      const Real face = sB[comp * T::NB + b1];
+      const double s1_old = (double)mh.in[d][qq][ga] - i1_m;
+      const double sg_old = (double)fi.B[comp][sg] - ig_m;
+      const double s1_new = (double)face - i1_p;
+      const double sg_new = s1_old + kc * (s1_new - sg_old);
+      const Real v = (Real)(sg_new + ig_p);
+      sB[comp * T::NB + bg] = v;
+      if (ND < 2 || (la >= 0 && la < ea)) {  // this tile's own face nodes
+        fo.B[comp][sg] = v;
+        mh.out[d][qq][ga] = face;
+      }
+    }
+  }
+  __syncthreads();
+
+  // 3. new E
+#pragma unroll
+  for (int k = 0; k < KP; k++) {
+    if (!vp[k]) continue;
+    const int q = threadIdx.x + 256 * k;
+    const int x = q % T::PX, y = ND > 1 ? q / T::PX : 0;
+    Real cx, cy, cz;
+    curl_bwd<Real, ND>(sB, sB + T::NB, sB + 2 * T::NB, bix(x, y), T::BX, ix, iy, cx, cy, cz);
+    const int e = eix(x, y);
+    sP[q] = sE[e] + dt * (cx - rj[k][0]);
+    sP[T::NP + q] = sE[T::NE + e] + dt * (cy - rj[k][1]);
+    sP[2 * T::NP + q] = sE[2 * T::NE + e] + dt * (cz - rj[k][2]);
+  }
+  __syncthreads();
+
+  // 3b. Mur on the tangential E at the guard of each open high face
+  for (int d = 0; d < ND; d++) {
+    if ((d == 0 ? px : py) || (d == 0 ? ox + ex : oy + ey) != (d == 0 ? g.n[0] : g.n[1]))
+      continue;
+    const int nf = ND > 1 ? (d == 0 ? ey : ex) + 1 : 1;
+    const int na = d == 0 ? g.n[1] : g.n[0];
+    const bool pa = d == 0 ? py : px;
+    const int oa = d == 0 ? oy : ox, ea = d == 0 ? ey : ex;
+    const double kc = (g.dt - g.dx[d]) / (g.dt + g.dx[d]);
+    for (int q = threadIdx.x; q < 2 * nf; q += 256) {
+      const int qq = q / nf, la = ND > 1 ? q % nf : 0;
+      if (ND > 1 && !pa && oa + la >= na) continue;  // corner of two open faces (unused)
+      const int comp = qq == 0 ? (d == 0 ? 1 : 0) : 2;
+      const int xg = d == 0 ? ex : la, yg = d == 0 ? la : ey;
+      const int pg = pix(xg, yg), eg = eix(xg, yg);
+      const int p1 = d == 0 ? pg - 1 : pg - T::PX, e1 = d == 0 ? eg - 1 : eg - T::EX;
+      const Real v = (Real)((double)sE[comp * T::NE + e1] +
+                            kc * ((double)sP[comp * T::NP + p1] - (double)sE[comp * T::NE + eg]));
+      sP[comp * T::NP + pg] = v;
+      if (ND < 2 || la < ea) fo.E[comp][sidx(xg, yg)] = v;
+    }
+  }
+  __syncthreads();
+
+  // 4. B after the second half step, and the new E, on the tile's cells
+#pragma unroll
+  for (int q = threadIdx.x; q < T::TX * T::TY; q += 256) {
+    const int x = q % T::TX, y = ND > 1 ? q / T::TX : 0;
+    if (x >= ex || (ND > 1 && y >= ey)) continue;
+    const int p = pix(x, y), bb = bix(x, y);
+    Real cx, cy, cz;
+    curl_fwd<Real, ND>(sP, sP + T::NP, sP + 2 * T::NP, p, T::PX, ix, iy, cx, cy, cz);
+    const int64_t si = sidx(x, y);
+    fo.B[0][si] = sB[bb] - h * cx;
+    fo.B[1][si] = sB[T::NB + bb] - h * cy;
+    fo.B[2][si] = sB[2 * T::NB + bb] - h * cz;
+    fo.E[0][si] = sP[p];
+    fo.E[1][si] = sP[T::NP + p];
+    fo.E[2][si] = sP[2 * T::NP + p];
+  }
+}
+
 template <typename Real>
 __global__ void k_probes(GridInfo g, FieldPtrs<Real> f, int nprobe, const int* comp,
                          const int64_t* index, Real* buf, int64_t max_steps, int64_t rec) {
@@ -646,6 +912,36 @@ void launch_e_full(const GridInfo& g, const FieldPtrs<Real>& f, hipStream_t st) 
   if (g.nd == 3) hipLaunchKernelGGL((k_e_full<Real, 3>), nb, 256, 0, st, g, f, dt, ix, iy, iz);
 }
 
+template <typename Real, int ND>
+static hipError_t launch_yee_fused_nd(const GridInfo& g, const FieldPtrs<Real>& fi,
+                                      const FieldPtrs<Real>& fo, const MurHistory<Real>& mh,
+                                      const LaserDev& las, int64_t step, hipStream_t st) {
+  using T = YeeTile<Real, ND>;
+  const int64_t ntiles = (int64_t)((g.n[0] + T::TX - 1) / T::TX) *
+                         (ND > 1 ? (g.n[1] + T::TY - 1) / T::TY : 1);
+  const Real h = (Real)(0.5 * g.dt), dt = (Real)g.dt;
+  const Real ix = (Real)(1.0 / g.dx[0]);
+  const Real iy = ND > 1 ? (Real)(1.0 / g.dx[1]) : Real(0);
+  hipLaunchKernelGGL((k_yee_fused<Real, ND>), dim3((unsigned)ntiles), dim3(256), T::lds, st, g,
+                     fi, fo, mh, las, step, h, dt, ix, iy);
+  return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_yee_fused(const GridInfo& g, const FieldPtrs<Real>& fi, const FieldPtrs<Real>& fo,
+                            Real* const hist_in[3][2], Real* const hist_out[3][2],
+                            const LaserDev& las, int64_t step, hipStream_t st) {
+  MurHistory<Real> mh{};
+  for (int d = 0; d < 3; d++)
+    for (int t = 0; t < 2; t++) {
+      mh.in[d][t] = hist_in[d][t];
+      mh.out[d][t] = hist_out[d][t];
+    }
+  if (g.nd == 1) return launch_yee_fused_nd<Real, 1>(g, fi, fo, mh, las, step, st);
+  if (g.nd == 2) return launch_yee_fused_nd<Real, 2>(g, fi, fo, mh, las, step, st);
+  return hipErrorInvalidValue;
+}
+
 static int64_t face_count(const GridInfo& g, int d) {
   int a_dim = d == 0 ? 1 : 0, b_dim = d == 2 ? 1 : 2;
   return (int64_t)g.n[a_dim] * g.n[b_dim];
@@ -756,6 +1052,9 @@ void launch_probe_seed(const FieldPtrs<Real>& l, int nprobe, const int* comp,
                                       hipStream_t);                                              \
   template void launch_mur_high_e<R>(const GridInfo&, const FieldPtrs<R>&, int, const R*,        \
                                      const R*, hipStream_t);                                     \
+  template hipError_t launch_yee_fused<R>(const GridInfo&, const FieldPtrs<R>&,                 \
+                                          const FieldPtrs<R>&, R* const[3][2], R* const[3][2],   \
+                                          const LaserDev&, int64_t, hipStream_t);                \
   template void launch_probes<R>(const GridInfo&, const FieldPtrs<R>&, int, const int*,          \
                                  const int64_t*, R*, int64_t, int64_t, hipStream_t);                   \
   template void launch_b_half_adj<R>(const GridInfo&, const FieldPtrs<R>&, hipStream_t);         \

@@ -184,6 +184,17 @@ struct LaserDev {
   double env[64];
 };
 
+// One whole field step (B half, E full with J, B half, Mur faces and the
+// x-min laser) in one pass, 1D and 2D: E and B read from fi and written to fo (distinct
+// buffers; J from fi), the Mur history of the open low faces read from
+// hist_in and written to hist_out (distinct).  fo's periodic guards are left
+// stale (the next step refills them); its open-face guards get their Mur
+// values.
+template <typename Real>
+hipError_t launch_yee_fused(const GridInfo& g, const FieldPtrs<Real>& fi, const FieldPtrs<Real>& fo,
+                            Real* const hist_in[3][2], Real* const hist_out[3][2],
+                            const LaserDev& las, int64_t step, hipStream_t st);
+
 template <typename Real>
 void launch_mur_low_b(const GridInfo& g, const FieldPtrs<Real>& f, int d, Real* prev0,
                       Real* prev1, const LaserDev& las, int64_t step, hipStream_t st);

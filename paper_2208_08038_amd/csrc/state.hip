@@ -59,7 +59,8 @@ size_t face_values(const pic_ctx* c, int d) {
 void pieces_of(pic_ctx* c, std::vector<Piece>& fields, std::vector<SpeciesRecord>& recs,
                std::vector<std::vector<Piece>>& sp) {
   const size_t rs = c->rsize;
-  fields.push_back({c->fields, 9 * (size_t)c->g.plane * rs});
+  fields.push_back({c->fields, 6 * (size_t)c->g.plane * rs});
+  fields.push_back({c->jfield, 3 * (size_t)c->g.plane * rs});
   for (int d = 0; d < c->g.nd; d++) {
     if (c->g.periodic[d]) continue;
     const size_t fb = face_values(c, d) * rs;
