@@ -344,6 +344,7 @@ int sort_due(pic_ctx* c) {
   constexpr int64_t kSortMaxSteps = 64;
   if (c->sort_every == 0) harvest_counts(c);
   const bool cadence = c->sort_every > 0 && c->steps_since_sort >= c->sort_every;
+  bool sorted = false;
   for (auto& s : c->sp) {
     bool due = cadence || s->needs_sort;
     if (c->sort_every == 0)
@@ -357,9 +358,10 @@ int sort_due(pic_ctx* c) {
     s->needs_sort = false;
     s->listed_since_sort = 0.0;
     s->steps_since_sort = 0;
+    sorted = true;
   }
   if (cadence) c->steps_since_sort = 0;
-  return PIC_OK;
+  return sorted ? update_occupancy(c) : PIC_OK;
 }
 
 }  // namespace
@@ -717,6 +719,31 @@ static const char* const omega_fixed_msg =
     "per-particle omega_c needs a_c = 0 (derived per ion) or a_c = +inf (harmonic)";
 
 // allocate the optional per-particle arrays on the first load that brings them
+// After a sort: with far fewer particles than tiles of a colour (a few
+// ions in a large box), the tiled launches visit only the tiles that hold
+// particles (lists rebuilt from the sorted ranges); else every tile.
+int update_occupancy(pic_ctx* c) {
+  const int64_t per_colour = (int64_t)c->tg.nc[0] * c->tg.nc[1] * c->tg.nc[2];
+  int64_t n = 0;
+  for (auto& s : c->sp) n += s->n;
+  const bool sparse = c->tiled && c->sp.size() <= (size_t)pic::kOccSpecies && 4 * n < per_colour;
+  c->tg.occ = nullptr;
+  c->tg.occ_grid = 0;
+  if (!sparse) return PIC_OK;
+  if (!c->occ) {
+    c->occ = static_cast<uint32_t*>(dev_alloc(c, (size_t)(8 + 8 * per_colour) * 4));
+    if (!c->occ) return fail(c, PIC_ENOMEM, "device allocation failed (occupied tiles)");
+  }
+  const uint32_t* offs[pic::kOccSpecies] = {};
+  for (size_t s = 0; s < c->sp.size(); s++) offs[s] = c->sp[s]->sort.tile_off;
+  hipError_t e =
+      pic::launch_occupied_tiles(c->tg, offs, (int)c->sp.size(), c->occ, c->stream);
+  if (e != hipSuccess) return fail(c, PIC_EHIP, std::string("occupied tiles: ") + hipGetErrorString(e));
+  c->tg.occ = c->occ;
+  c->tg.occ_grid = std::max<int64_t>(n, 1);
+  return PIC_OK;
+}
+
 int prepare_optional(pic_ctx* c, SpeciesHost& s, bool want_wc, bool want_w) {
   size_t rs = c->rsize, cap = (size_t)s.cap;
   pic::AllocFn af = [c](size_t b) { return dev_alloc(c, b); };

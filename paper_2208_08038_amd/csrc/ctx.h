@@ -73,6 +73,7 @@ struct pic_ctx {
   int counts_pending = -1;          // slot whose copy is in flight, or -1
   bool tiled = false;
   pic::TileGeom tg{};
+  uint32_t* occ = nullptr;  // occupied-tile lists of sparse launches (tg.occ when in use)
   double* partials = nullptr;
   double* dout = nullptr;  // 32 doubles: [0..3] scratch, [4..6] residual, ...
   double* rho0 = nullptr;
@@ -243,6 +244,10 @@ inline pic::LaserDev laser_dev(const pic_ctx* c) {
 // Allocate a species' per-particle omega_c / weight arrays (and their sort
 // buffers) on the first load that brings them; fails once particles exist.
 int prepare_optional(pic_ctx* c, SpeciesHost& s, bool want_wc, bool want_w);
+
+// After the tile ranges changed (a sort, a restored state): choose dense or
+// sparse tiled launches and rebuild the occupied-tile lists of the latter.
+int update_occupancy(pic_ctx* c);
 
 // Add the outside-tile counts of the last enqueued step to the sort policy
 // (waits for that step's particle kernels).

@@ -332,6 +332,7 @@ int grad_forward_t(pic_ctx* c, int64_t nsteps, int K) {
   GradState& G = *c->grad;
   G.ready = false;
   // one sort now (after a load), none during the run
+  bool sorted = false;
   for (auto& s : c->sp)
     if (s->needs_sort) {
       if (pic::sort_by_tile(c->g, c->tile, c->ntiles, s->sort, s->n, c->stream, true))
@@ -339,8 +340,11 @@ int grad_forward_t(pic_ctx* c, int64_t nsteps, int K) {
       s->needs_sort = false;
       s->listed_since_sort = 0.0;
       s->steps_since_sort = 0;
+      sorted = true;
     }
-  int rc = grad_buffers(c, nsteps, K);
+  int rc = sorted ? update_occupancy(c) : PIC_OK;
+  if (rc) return rc;
+  rc = grad_buffers(c, nsteps, K);
   if (rc) return rc;
   G.nsteps = nsteps;
   G.K = K;

@@ -252,7 +252,7 @@ int pic_load_state(pic_ctx* c, const void* host_buf, size_t bytes) {
   c->steps_since_sort = h.steps_since_sort;
   c->counts_pending = -1;
   c->residual_valid = false;
-  return PIC_OK;
+  return update_occupancy(c);  // the restored tile ranges
 }
 
 }  // extern "C"

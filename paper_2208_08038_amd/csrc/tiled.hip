@@ -182,8 +182,13 @@ __device__ __forceinline__ void tiled_body(const GridInfo& g, const FieldPtrs<Re
   using PatchT = PatchOf<Real>;
   const PushConst<Real>& c = a.c;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  // tile of this block within the colour
+  // tile of this block within the colour (from the occupied list in a
+  // sparse launch)
   int bi = blockIdx.x;
+  if (t.occ) {
+    if ((uint32_t)bi >= t.occ[color]) return;
+    bi = (int)t.occ[8 + (int64_t)color * ((int64_t)t.nc[0] * t.nc[1] * t.nc[2]) + bi];
+  }
   int tc[3] = {0, 0, 0};
   tc[0] = 2 * (bi % t.nc[0]) + (color & 1);
   bi /= t.nc[0];
@@ -345,6 +350,49 @@ k_push_tiled_f64(GridInfo g, FieldPtrs<double> f, TileSpecies<double> a, TileSpe
 
 }  // namespace
 
+namespace {
+
+struct OccSpecies {
+  const uint32_t* tile_off[kOccSpecies];
+  int n;
+};
+
+// One workgroup: count and list, per colour, the tiles whose sorted range
+// is non-empty for some species.
+__global__ void __launch_bounds__(1024) k_occupied_tiles(TileGeom t, OccSpecies sp, uint32_t* occ) {
+  __shared__ uint32_t cnt[8];
+  if (threadIdx.x < 8) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t ntile = (int64_t)t.nt[0] * t.nt[1] * t.nt[2];
+  const int64_t per_colour = (int64_t)t.nc[0] * t.nc[1] * t.nc[2];
+  for (int64_t tile = threadIdx.x; tile < ntile; tile += blockDim.x) {
+    bool busy = false;
+    for (int s = 0; s < sp.n; s++) busy = busy || sp.tile_off[s][tile] != sp.tile_off[s][tile + 1];
+    if (!busy) continue;
+    const int tx = (int)(tile % t.nt[0]);
+    const int ty = (int)((tile / t.nt[0]) % t.nt[1]);
+    const int tz = (int)(tile / ((int64_t)t.nt[0] * t.nt[1]));
+    const int colour = (tx & 1) | ((ty & 1) << 1) | ((tz & 1) << 2);
+    const uint32_t bi = (uint32_t)((tx >> 1) + t.nc[0] * ((ty >> 1) + t.nc[1] * (tz >> 1)));
+    const uint32_t at = atomicAdd(&cnt[colour], 1u);
+    occ[8 + colour * per_colour + at] = bi;
+  }
+  __syncthreads();
+  if (threadIdx.x < 8) occ[threadIdx.x] = cnt[threadIdx.x];
+}
+
+}  // namespace
+
+hipError_t launch_occupied_tiles(const TileGeom& t, const uint32_t* const* tile_off, int nspecies,
+                                 uint32_t* occ, hipStream_t st) {
+  if (nspecies > kOccSpecies) return hipErrorInvalidValue;
+  OccSpecies sp{};
+  for (int s = 0; s < nspecies; s++) sp.tile_off[s] = tile_off[s];
+  sp.n = nspecies;
+  hipLaunchKernelGGL(k_occupied_tiles, dim3(1), dim3(1024), 0, st, t, sp, occ);
+  return hipGetLastError();
+}
+
 TileGeom make_tile_geom(const GridInfo& g, const int tile[3], const int ntiles[3], size_t rsize) {
   TileGeom t{};
   t.nd = g.nd;
@@ -402,7 +450,9 @@ static hipError_t launch_colour_wpe(const GridInfo& g, const FieldPtrs<Real>& f,
     if (e != hipSuccess) return e;
     attr_lds = lds;
   }
-  unsigned blocks = (unsigned)((int64_t)t.nc[0] * t.nc[1] * t.nc[2]);
+  const int64_t per_colour = (int64_t)t.nc[0] * t.nc[1] * t.nc[2];
+  unsigned blocks = (unsigned)(t.occ ? std::min<int64_t>(t.occ_grid, per_colour) : per_colour);
+  if (blocks == 0) return hipSuccess;
   if constexpr (sizeof(Real) == 4)
     hipLaunchKernelGGL((k_push_tiled_f32<ND, TWO, NS, WPE, TX, TY, TZ>), dim3(blocks),
                        dim3(kTiledThreads), lds, st, g, f, a, b, t, color, err);

@@ -117,6 +117,28 @@ def test_coupled_periodic_fp64(pic, ndim):
     assert s.diagnostics()["error_word"] == 0
 
 
+@pytest.mark.parametrize("ndim,shape,n,precision", [(2, (240, 192), 8, 64), (3, (64, 64, 48), 5, 64),
+                                                    (3, (64, 64, 48), 5, 32)])
+def test_sparse_tiles_coupled(pic, ndim, shape, n, precision):
+    """A few particles in a large box (fewer than a quarter of the tiles of
+    one colour): the tiled launches visit only the occupied tiles, listed
+    again after every sort; 12 coupled steps with fast particles crossing
+    tiles match the oracle."""
+    _say(f"case: sparse tiles ndim={ndim} fp{precision}")
+    wl = random_workload(ndim, n, n, seed=40 + ndim, shape=shape, vmax_ion=0.6, vmax_el=0.95)
+    o, s = _both(wl, pic, precision)
+    o.step(12)
+    s.step(12)
+    d = s.diagnostics()
+    assert d["error_word"] == 0
+    tol = 1e-12 if precision == 64 else 2e-5
+    Eo, Bo, Jo = o.fields()
+    Eg, Bg, Jg = s.fields()
+    assert rel_l2(Eg, Eo) < tol
+    assert rel_l2(Bg, Bo) < tol
+    _compare_particles(o, s, wl, 1e-11 if precision == 64 else 1e-4, exact_cells=precision == 64)
+
+
 def _relativistic(wl, seed):
     """Give every particle a random direction and gamma in [2, 8] (ion
     centres, both bodies kept at their loaded momentum difference) or
