@@ -415,6 +415,51 @@ def run_config2(args):
     return out
 
 
+def run_wakefield(args):
+    """The relativistic application of Sec. 3.2 at full size: a0 = 3 through
+    the pre-ionised gold lattice (4096^2 cells, crystal 2048 x 1024 cells,
+    909 ions with 30 free electrons each as 2,097,152 macro-electrons),
+    FP64 and FP32.  The paper prints no number for it: reported are the run
+    rate, the torn clouds (ions with bodies half a cell or more apart), the
+    longitudinal wake behind the pulse, and FP32 against FP64."""
+    import torch
+    from paper_2208_08038_amd import pic
+    from paper_2208_08038_amd.inputs import wakefield_crystal_2d
+    out = {"workload": "wakefield_crystal_2d", "cells": [4096, 4096]}
+    fields = {}
+    for prec in (64, 32):
+        wl = wakefield_crystal_2d(steps=args.wakefield_steps, precision=prec)
+        sim = pic.Simulation.from_workload(wl, precision=prec)
+        sim.step(10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(wl.steps - 10)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        d = sim.diagnostics()
+        E, _, _ = sim.fields()
+        nx, ny = wl.grid.n[0], wl.grid.n[1]
+        ex = E[0].reshape(ny, nx)
+        band = ex[ny // 2 - 8: ny // 2 + 8]  # E_x near the axis
+        fields[prec] = E
+        npart = wl.n_particles
+        out[f"fp{prec}"] = {
+            "ions": wl.species[0][1].n, "free_electrons": wl.species[1][1].n,
+            "steps": wl.steps, "ms_per_step": 1e3 * dt / (wl.steps - 10),
+            "particle_steps_per_s": npart * (wl.steps - 10) / dt,
+            "cell_steps_per_s": nx * ny * (wl.steps - 10) / dt,
+            "torn_ions": d["n_far"], "max_abs_ex_on_axis": float(np.abs(band).max()),
+            "max_abs_e": float(np.abs(E).max()), "error_word": d["error_word"]}
+        print(f"[bench] wakefield fp{prec}: {wl.steps} steps {dt:.1f} s", file=sys.stderr,
+              flush=True)
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    out["fp32_vs_fp64_e_rel_l2"] = float(np.linalg.norm(fields[32] - fields[64]) /
+                                         max(np.linalg.norm(fields[64]), 1e-300))
+    return out
+
+
 def run_config4(args):
     """The mixed-precision case at full size: Bragg geometry in 3D,
     1024 x 1024 x 512 cells, 4 two-body ions per cell in x cells 384..640
@@ -565,6 +610,9 @@ def main():
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the legs of the 1D neutral medium and the 2D Bragg case")
     ap.add_argument("--config2-steps", type=int, default=4000)
+    ap.add_argument("--wakefield-steps", type=int, default=4000)
+    ap.add_argument("--wakefield", action="store_true",
+                    help="run only the relativistic crystal case (FP64 and FP32) and print its JSON")
     ap.add_argument("--config2", action="store_true",
                     help="run only the 2D Bragg case (FP64 and FP32) and print its JSON")
     ap.add_argument("--config4", action="store_true",
@@ -589,7 +637,7 @@ def main():
         sys.exit(2)
     # the CPU baseline forks its workers before anything touches the GPU
     only = (args.copy_calibration or args.adjoint_only or args.fp64_only or args.config4
-            or args.config2)
+            or args.config2 or args.wakefield)
     cpu = None
     if not (args.no_cpu_baseline or only):
         cpu = cpu_baseline(args.cpu_seconds, args.cpu_workers)
@@ -611,6 +659,9 @@ def main():
         return
     if args.config2:
         print(json.dumps({"config2": run_config2(args)}), flush=True)
+        return
+    if args.wakefield:
+        print(json.dumps({"wakefield": run_wakefield(args)}), flush=True)
         return
     if args.fp64_only:
         r = run_gpu(args, 64)
@@ -654,7 +705,8 @@ def main():
     adj = None if args.no_adjoint else run_adjoint(args)
     configs = None
     if not args.no_configs:
-        configs = {"neutral_medium_1d": run_config1(args), "bragg_2d": run_config2(args)}
+        configs = {"neutral_medium_1d": run_config1(args), "bragg_2d": run_config2(args),
+                   "wakefield_crystal_2d": run_wakefield(args)}
     out = {
         "metric": METRIC, "value": r32["value"], "unit": "particle-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": r32["ms_per_step"],

@@ -719,17 +719,15 @@ static const char* const omega_fixed_msg =
     "per-particle omega_c needs a_c = 0 (derived per ion) or a_c = +inf (harmonic)";
 
 // allocate the optional per-particle arrays on the first load that brings them
-// After a sort: with far fewer particles than tiles of a colour (a few
-// ions in a large box), the tiled launches visit only the tiles that hold
-// particles (lists rebuilt from the sorted ranges); else every tile.
+// After a sort: list, per colour, the tiles that hold particles (one small
+// kernel and a read-back of the 8 counts, once per sort); when fewer than
+// half of the tiles are occupied (a few ions in a large box, a crystal in
+// part of it), the tiled launches visit only those, else every tile.
 int update_occupancy(pic_ctx* c) {
-  const int64_t per_colour = (int64_t)c->tg.nc[0] * c->tg.nc[1] * c->tg.nc[2];
-  int64_t n = 0;
-  for (auto& s : c->sp) n += s->n;
-  const bool sparse = c->tiled && c->sp.size() <= (size_t)pic::kOccSpecies && 4 * n < per_colour;
   c->tg.occ = nullptr;
-  c->tg.occ_grid = 0;
-  if (!sparse) return PIC_OK;
+  if (!c->tiled || c->sp.empty() || c->sp.size() > (size_t)pic::kOccSpecies) return PIC_OK;
+  const int64_t per_colour = (int64_t)c->tg.nc[0] * c->tg.nc[1] * c->tg.nc[2];
+  const int64_t ntile = (int64_t)c->tg.nt[0] * c->tg.nt[1] * c->tg.nt[2];
   if (!c->occ) {
     c->occ = static_cast<uint32_t*>(dev_alloc(c, (size_t)(8 + 8 * per_colour) * 4));
     if (!c->occ) return fail(c, PIC_ENOMEM, "device allocation failed (occupied tiles)");
@@ -739,8 +737,14 @@ int update_occupancy(pic_ctx* c) {
   hipError_t e =
       pic::launch_occupied_tiles(c->tg, offs, (int)c->sp.size(), c->occ, c->stream);
   if (e != hipSuccess) return fail(c, PIC_EHIP, std::string("occupied tiles: ") + hipGetErrorString(e));
+  uint32_t n[8];
+  HIPCHK(c, hipMemcpyAsync(n, c->occ, sizeof(n), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  int64_t busy = 0;
+  for (int k = 0; k < 8; k++) busy += n[k];
+  if (2 * busy >= ntile) return PIC_OK;
+  for (int k = 0; k < 8; k++) c->tg.occ_n[k] = n[k];
   c->tg.occ = c->occ;
-  c->tg.occ_grid = std::max<int64_t>(n, 1);
   return PIC_OK;
 }
 

@@ -63,17 +63,18 @@ struct TileGeom {
   PatchLayout L;  // LDS layout of the patches
   int qcap;       // LDS queue capacity for general (four-node) deposits
   int nd;         // resolved dimensions
-  // Sparse launches (far fewer particles than tiles): occ holds 8 per-colour
-  // counts, then per colour the colour-local indices of the tiles that hold
-  // particles of some species (room for nc[0] nc[1] nc[2] each); a colour
-  // dispatch runs occ_grid workgroups, those past the colour's count leave.
-  // occ = nullptr: one workgroup per tile of the colour.
+  // Sparse launches (most tiles empty): occ holds 8 per-colour counts, then
+  // per colour the colour-local indices of the tiles that hold particles of
+  // some species, in tile order (room for nc[0] nc[1] nc[2] each); the
+  // dispatch of colour c runs occ_n[c] workgroups.  occ = nullptr: one
+  // workgroup per tile of the colour.
   const uint32_t* occ = nullptr;
-  int64_t occ_grid = 0;
+  uint32_t occ_n[8] = {};
 };
 
 // Fill the occupied-tile lists of a sparse launch (TileGeom::occ) from the
-// sorted tile ranges of up to kOccSpecies species (one workgroup).
+// sorted tile ranges of up to kOccSpecies species (one workgroup; the lists
+// come out in tile order).
 constexpr int kOccSpecies = 8;
 hipError_t launch_occupied_tiles(const TileGeom& t, const uint32_t* const* tile_off, int nspecies,
                                  uint32_t* occ, hipStream_t st);

@@ -358,27 +358,55 @@ struct OccSpecies {
 };
 
 // One workgroup: count and list, per colour, the tiles whose sorted range
-// is non-empty for some species.
+// is non-empty for some species.  Rounds of 1024 consecutive tiles; within a
+// round each tile's place in its colour's list is the count of busy tiles
+// of that colour before it (wave ballots, then the waves before), so the
+// lists keep tile order.
 __global__ void __launch_bounds__(1024) k_occupied_tiles(TileGeom t, OccSpecies sp, uint32_t* occ) {
-  __shared__ uint32_t cnt[8];
-  if (threadIdx.x < 8) cnt[threadIdx.x] = 0;
+  __shared__ uint32_t base[8];
+  __shared__ uint32_t wcnt[16][8];
+  if (threadIdx.x < 8) base[threadIdx.x] = 0;
   __syncthreads();
   const int64_t ntile = (int64_t)t.nt[0] * t.nt[1] * t.nt[2];
   const int64_t per_colour = (int64_t)t.nc[0] * t.nc[1] * t.nc[2];
-  for (int64_t tile = threadIdx.x; tile < ntile; tile += blockDim.x) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t below = (uint64_t(1) << lane) - 1;
+  for (int64_t t0 = 0; t0 < ntile; t0 += 1024) {
+    const int64_t tile = t0 + threadIdx.x;
     bool busy = false;
-    for (int s = 0; s < sp.n; s++) busy = busy || sp.tile_off[s][tile] != sp.tile_off[s][tile + 1];
-    if (!busy) continue;
-    const int tx = (int)(tile % t.nt[0]);
-    const int ty = (int)((tile / t.nt[0]) % t.nt[1]);
-    const int tz = (int)(tile / ((int64_t)t.nt[0] * t.nt[1]));
-    const int colour = (tx & 1) | ((ty & 1) << 1) | ((tz & 1) << 2);
-    const uint32_t bi = (uint32_t)((tx >> 1) + t.nc[0] * ((ty >> 1) + t.nc[1] * (tz >> 1)));
-    const uint32_t at = atomicAdd(&cnt[colour], 1u);
-    occ[8 + colour * per_colour + at] = bi;
+    int colour = 0;
+    uint32_t bi = 0;
+    if (tile < ntile) {
+      for (int s = 0; s < sp.n; s++)
+        busy = busy || sp.tile_off[s][tile] != sp.tile_off[s][tile + 1];
+      const int tx = (int)(tile % t.nt[0]);
+      const int ty = (int)((tile / t.nt[0]) % t.nt[1]);
+      const int tz = (int)(tile / ((int64_t)t.nt[0] * t.nt[1]));
+      colour = (tx & 1) | ((ty & 1) << 1) | ((tz & 1) << 2);
+      bi = (uint32_t)((tx >> 1) + t.nc[0] * ((ty >> 1) + t.nc[1] * (tz >> 1)));
+    }
+    uint32_t rank = 0;
+#pragma unroll
+    for (int c = 0; c < 8; c++) {
+      const uint64_t m = __ballot(busy && colour == c);
+      if (lane == 0) wcnt[wave][c] = (uint32_t)__popcll(m);
+      if (busy && colour == c) rank = (uint32_t)__popcll(m & below);
+    }
+    __syncthreads();
+    if (busy) {
+      uint32_t at = base[colour] + rank;
+      for (int w = 0; w < wave; w++) at += wcnt[w][colour];
+      occ[8 + colour * per_colour + at] = bi;
+    }
+    __syncthreads();
+    if (threadIdx.x < 8) {
+      uint32_t add = 0;
+      for (int w = 0; w < 16; w++) add += wcnt[w][threadIdx.x];
+      base[threadIdx.x] += add;
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  if (threadIdx.x < 8) occ[threadIdx.x] = cnt[threadIdx.x];
+  if (threadIdx.x < 8) occ[threadIdx.x] = base[threadIdx.x];
 }
 
 }  // namespace
@@ -451,7 +479,7 @@ static hipError_t launch_colour_wpe(const GridInfo& g, const FieldPtrs<Real>& f,
     attr_lds = lds;
   }
   const int64_t per_colour = (int64_t)t.nc[0] * t.nc[1] * t.nc[2];
-  unsigned blocks = (unsigned)(t.occ ? std::min<int64_t>(t.occ_grid, per_colour) : per_colour);
+  unsigned blocks = (unsigned)(t.occ ? std::min<int64_t>(t.occ_n[color], per_colour) : per_colour);
   if (blocks == 0) return hipSuccess;
   if constexpr (sizeof(Real) == 4)
     hipLaunchKernelGGL((k_push_tiled_f32<ND, TWO, NS, WPE, TX, TY, TZ>), dim3(blocks),

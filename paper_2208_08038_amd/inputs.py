@@ -18,6 +18,7 @@ Workloads (the paper's cases as restated for this project):
   mixed_precision_3d  Bragg-geometry 3D slab, 4 ions per cell
   adjoint_slab        2D neutral slab crossed by a spline-envelope pulse (gradient runs)
   bound_slab_1d       medium behind a vacuum gap (Sec. 3.1 observables)
+  wakefield_crystal_2d  relativistic pulse in a pre-ionised gold lattice (Sec. 3.2, Fig. 6)
 """
 from __future__ import annotations
 
@@ -375,6 +376,65 @@ def bragg_2d(cells: int = 4096, slab: int = 1024, steps: int = 4000, d_over_lamb
     parts = Particles(x=x, u1=np.zeros((n, 3)))
     return Workload("bragg_2d", grid, [(sp, parts)], steps, precision,
                     notes=f"{n} lattice sites, d={d_over_lambda} lambda, theta_B={theta_b:.6f}")
+
+
+def wakefield_crystal_2d(cells=(4096, 4096), slab=(2048, 1024), steps: int = 4000,
+                         d_over_lambda: float = 1.5, omega_c: float = 0.5, a0: float = 3.0,
+                         cycles: int = 20, waist_lambda: float = 12.0, free_per_ion: int = 30,
+                         z_bound_neutral: int = 78, ppc_e: int = 1, t_e_ev: float = 10.0,
+                         jitter: float = 0.01, precision: int = 64,
+                         config_id: int = 6) -> Workload:
+    """The Bragg lattice of bragg_2d, longer along x, pre-ionised with
+    `free_per_ion` free electrons per ion, driven by a relativistic pulse
+    (a0 = 3): Sec. 3.2, the wakefield paragraph.  Each site's ion keeps
+    z_bound_neutral - free_per_ion bound electrons (net charge
+    +free_per_ion); the free electrons fill the crystal region uniformly
+    (ppc_e per cell, stratified, thermal at t_e_ev) with the weight that
+    makes the region neutral."""
+    nx, ny = cells
+    dx = TWO_PI / 32.0
+    dt = 0.98 * dx / math.sqrt(2.0)
+    lam = TWO_PI
+    d = d_over_lambda * lam
+    d_m = (5.9e28) ** (-1.0 / 3.0)
+    lam_m = d_m / d_over_lambda
+    re_norm = TWO_PI * R_E_M / lam_m
+    theta_b = math.asin(lam / (2.0 * d))
+    laser = Laser(a0=a0, omega=1.0, t_env=cycles * TWO_PI, waist=waist_lambda * lam,
+                  yc=0.5 * ny * dx, pol=1)
+    grid = Grid(2, (nx, ny, 1), (dx, dx, 1.0), dt, (LASER, OPEN, PERIODIC),
+                (OPEN, OPEN, PERIODIC), pad=3, laser=laser, re_norm=re_norm)
+    q1, m1, q2, m2 = gold_ion(z_bound_neutral - free_per_ion, float(free_per_ion))
+    w = 4.0 * math.pi * re_norm / d  # one column of atoms along z per site
+    ion = Species(TWO_BODY, q1, m1, q2, m2, weight=w, omega_c=omega_c, a_c=0.0,
+                  name="Au_preionised")
+    rng = rng_for(config_id, 0)
+    cx, cy = 0.5 * nx * dx, 0.5 * ny * dx
+    hx, hy = 0.5 * slab[0] * dx, 0.5 * slab[1] * dx
+    m = int(math.ceil(2.0 * max(hx, hy) * math.sqrt(2.0) / d)) + 2
+    ii, jj = np.meshgrid(np.arange(-m, m + 1), np.arange(-m, m + 1), indexing="ij")
+    a = ii.ravel() * d
+    b = jj.ravel() * d
+    ct, st = math.cos(theta_b), math.sin(theta_b)
+    xs = cx + a * ct - b * st
+    ys = cy + a * st + b * ct
+    keep = (np.abs(xs - cx) < hx) & (np.abs(ys - cy) < hy)
+    xs, ys = xs[keep], ys[keep]
+    n_ion = xs.size
+    xs = xs + rng.normal(0.0, jitter * d, n_ion)
+    ys = ys + rng.normal(0.0, jitter * d, n_ion)
+    ions = Particles(x=np.stack([xs, ys], axis=1), u1=np.zeros((n_ion, 3)))
+    rng_e = rng_for(config_id, 1)
+    lo = [int(round((cx - hx) / dx)), int(round((cy - hy) / dx))]
+    hi = [lo[0] + slab[0], lo[1] + slab[1]]
+    xe = stratified_positions(rng_e, lo, hi, ppc_e, grid.dx, 2)
+    n_e = xe.shape[0]
+    ue = rng_e.normal(0.0, thermal_sigma(t_e_ev, 1.0), size=(n_e, 3))
+    w_e = free_per_ion * n_ion * w / n_e
+    el = Species(POINT, -1.0, 1.0, weight=w_e, name="e_free")
+    return Workload("wakefield_crystal_2d", grid, [(ion, ions), (el, Particles(x=xe, u1=ue))],
+                    steps, precision,
+                    notes=f"{n_ion} sites (+{free_per_ion}), {n_e} free electrons, a0={a0}")
 
 
 # --------------------------------------------------------------------------
