@@ -184,14 +184,23 @@ __global__ void __launch_bounds__(SB) k_scatter(const uint32_t* kin, const uint3
   }
 }
 
-// Offsets of the tiles in the sorted order; the tile id is key >> tshift.
+// Offsets of the tiles in the sorted order (the tile id is key >> tshift):
+// one thread per tile boundary t in [0, ntiles], off[t] = the number of
+// keys whose tile is below t, by binary search (a run of empty tiles costs
+// nothing, unlike filling it from the particle side).
 __global__ void k_tile_off(const uint32_t* key, int64_t n, int64_t ntiles, int tshift,
                            uint32_t* off) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i > n) return;
-  int64_t lo = i == 0 ? -1 : min((int64_t)(key[i - 1] >> tshift), ntiles);
-  int64_t hi = i == n ? ntiles : min((int64_t)(key[i] >> tshift), ntiles);
-  for (int64_t t = lo + 1; t <= hi; t++) off[t] = (uint32_t)i;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > ntiles) return;
+  int64_t lo = 0, hi = n;  // first index whose tile is >= t lies in [lo, hi]
+  while (lo < hi) {
+    const int64_t mid = lo + ((hi - lo) >> 1);
+    if ((int64_t)(key[mid] >> tshift) < t)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  off[t] = (uint32_t)lo;
 }
 
 // Every attribute of element i gathered through one read of the
@@ -314,8 +323,8 @@ int sort_by_tile(const GridInfo& g, const int tile[3], const int ntiles[3], Sort
                        ntiles[1], cell, n, sb.key[0]);
     radix_sort(sb, n, tbits, kc, ic, st);
   }
-  hipLaunchKernelGGL(k_tile_off, nblk(n + 1, 256), 256, 0, st, sb.key[kc], n, sb.ntiles, tshift,
-                     sb.tile_off);
+  hipLaunchKernelGGL(k_tile_off, nblk(sb.ntiles + 1, 256), 256, 0, st, sb.key[kc], n, sb.ntiles,
+                     tshift, sb.tile_off);
   if (ic < 0) return hipGetLastError() == hipSuccess ? 0 : -1;  // a single tile: order unchanged
   const uint32_t* perm = sb.idx[ic];
   GatherSet gs{};
