@@ -29,18 +29,24 @@
 #define OR_MAX_SPECIES 8
 #define OR_PI 3.14159265358979323846
 
+#define OR_MAX_SHELL 4
+
 typedef struct {
   int kind;
   double q1, m1, q2, m2; /* real-particle charges and masses (point: q1, m1) */
+  /* multi-shell ion: nucleus (q1, m1) and nshell clouds with their own
+     charge, mass, bond frequency and softening length */
+  int nshell;
+  double qk[OR_MAX_SHELL], mk[OR_MAX_SHELL], wk[OR_MAX_SHELL], ak[OR_MAX_SHELL];
   double weight, omega_c, a_c, nu, nu_per_omega;
   int ac_derived;  /* a_c of each ion from its own omega_c (Sec. 3.1) */
   double re_norm;  /* Coulomb constant of the bond in these units */
   int64_t n, cap;
   int32_t* cell; /* n x 3 */
   double* off;   /* n x 3 */
-  double* delta; /* n x 3 */
+  double* delta; /* n x 3 (multi-shell: n x 3 nshell, shell k at 3k) */
   double* u1;    /* n x 3 */
-  double* u2;    /* n x 3 */
+  double* u2;    /* n x 3 (multi-shell: n x 3 nshell) */
   double* wc;    /* per-particle omega_c or NULL */
   double* w;     /* per-particle weight or NULL */
 } or_species;
@@ -232,6 +238,49 @@ int or_add_species(or_ctx* c, int kind, double q1, double m1, double q2, double 
   return c->nsp++;
 }
 
+/* Multi-shell ion (the extension the paper's summary names: the bound
+   electrons split into several components): a nucleus (q0, m0) and nshell
+   clouds, cloud k with charge qk[k], mass mk[k], bound to the nucleus alone
+   by the softened bond of Sec. 2 with restoring frequency wk[k] and
+   softening length ak[k] (0: derived from wk[k] with the Coulomb constant
+   re_norm, as for a two-body ion; +inf: harmonic).  Each bond's reduced
+   mass is that of its own pair, m0 mk / (m0 + mk), so one shell is exactly
+   a two-body ion. */
+int or_add_multishell(or_ctx* c, double q0, double m0, int nshell, const double* qk,
+                      const double* mk, const double* wk, const double* ak, double weight,
+                      double nu, double re_norm, int64_t capacity) {
+  if (!c || c->nsp >= OR_MAX_SPECIES || capacity < 0) return -1;
+  if (nshell < 1 || nshell > OR_MAX_SHELL || !qk || !mk || !wk || !ak) return -1;
+  if (!(m0 > 0.0) || q0 == 0.0) return -1;
+  for (int k = 0; k < nshell; k++) {
+    if (!(mk[k] > 0.0) || qk[k] == 0.0 || !(wk[k] > 0.0) || isnan(ak[k]) || ak[k] < 0.0)
+      return -1;
+    if (ak[k] == 0.0 && !(re_norm > 0.0)) return -1;
+  }
+  or_species* s = &c->sp[c->nsp];
+  memset(s, 0, sizeof(*s));
+  s->kind = OR_MULTI_SHELL;
+  s->q1 = q0;
+  s->m1 = m0;
+  s->nshell = nshell;
+  for (int k = 0; k < nshell; k++) {
+    s->qk[k] = qk[k];
+    s->mk[k] = mk[k];
+    s->wk[k] = wk[k];
+    s->ak[k] = ak[k] == 0.0 ? or_ac_from_omega(q0, m0, qk[k], mk[k], wk[k], re_norm) : ak[k];
+  }
+  s->weight = weight;
+  s->nu = nu;
+  s->re_norm = re_norm;
+  s->cap = capacity > 0 ? capacity : 1;
+  s->cell = (int32_t*)calloc((size_t)s->cap * 3, sizeof(int32_t));
+  s->off = (double*)calloc((size_t)s->cap * 3, sizeof(double));
+  s->u1 = (double*)calloc((size_t)s->cap * 3, sizeof(double));
+  s->delta = (double*)calloc((size_t)s->cap * 3 * nshell, sizeof(double));
+  s->u2 = (double*)calloc((size_t)s->cap * 3 * nshell, sizeof(double));
+  return c->nsp++;
+}
+
 /* Sec. 2 initial condition: p1 + p2 = p_c and q1 v1 + q2 v2 = 0, with
    p_i = m_i u_i and v_i = u_i / gamma_i.  Both velocities are parallel to
    u_c; v1 = alpha v2 with alpha = -q2/q1.  The speed s of body 2 solves
@@ -285,6 +334,7 @@ int or_load_particles(or_ctx* c, int sid, int64_t n, const double* x, const doub
   if (!c || sid < 0 || sid >= c->nsp || n < 0 || (n > 0 && (!x || !u1))) return -1;
   or_species* s = &c->sp[sid];
   if (s->n + n > s->cap) return -2;
+  if (s->kind == OR_MULTI_SHELL && omega_c) return -1; /* bond frequencies are per shell */
   if (omega_c && s->kind == OR_TWO_BODY) {
     /* a fixed finite a_c together with omega_c fixes the Coulomb constant,
        so the ions of such a species share one omega_c */
@@ -316,7 +366,30 @@ int or_load_particles(or_ctx* c, int sid, int64_t n, const double* x, const doub
         s->off[3 * q + d] = 0.0;
       }
     }
-    if (s->kind == OR_TWO_BODY) {
+    if (s->kind == OR_MULTI_SHELL) {
+      /* x is the centre of mass; body positions r0 = R + sum_k (m_k/M) d_k,
+         r_k = r0 - d_k; every body between the walls.  u2 == NULL: every
+         cloud moves with the nucleus. */
+      const int K = s->nshell;
+      double M = s->m1;
+      for (int k = 0; k < K; k++) M += s->mk[k];
+      for (int a = 0; a < 3 * K; a++) s->delta[3 * K * q + a] = delta ? delta[3 * K * p + a] : 0.0;
+      for (int d = 0; d < c->nd; d++) {
+        if (periodic(c, d)) continue;
+        double X0 = (double)s->cell[3 * q + d] + s->off[3 * q + d];
+        for (int k = 0; k < K; k++) X0 += (s->mk[k] / M) * s->delta[3 * K * q + 3 * k + d] / c->g.dx[d];
+        double lo = (double)c->g.pad, hi = (double)(c->nn[d] - c->g.pad);
+        if (!(X0 >= lo && X0 <= hi)) return -3;
+        for (int k = 0; k < K; k++) {
+          double Xk = X0 - s->delta[3 * K * q + 3 * k + d] / c->g.dx[d];
+          if (!(Xk >= lo && Xk <= hi)) return -3;
+        }
+      }
+      for (int a = 0; a < 3; a++) s->u1[3 * q + a] = u1[3 * p + a];
+      for (int k = 0; k < K; k++)
+        for (int a = 0; a < 3; a++)
+          s->u2[3 * K * q + 3 * k + a] = u2 ? u2[3 * K * p + 3 * k + a] : u1[3 * p + a];
+    } else if (s->kind == OR_TWO_BODY) {
       for (int a = 0; a < 3; a++) s->delta[3 * q + a] = delta ? delta[3 * p + a] : 0.0;
       /* along walled axes both bodies lie between the walls */
       double mc = s->m1 + s->m2;
@@ -385,11 +458,12 @@ int or_read_particles(or_ctx* c, int sid, int32_t* cell, double* off, double* de
   if (!c || sid < 0 || sid >= c->nsp) return -1;
   or_species* s = &c->sp[sid];
   size_t m = (size_t)s->n * 3;
+  size_t mk = m * (size_t)(s->kind == OR_MULTI_SHELL ? s->nshell : 1);
   if (cell) memcpy(cell, s->cell, m * sizeof(int32_t));
   if (off) memcpy(off, s->off, m * sizeof(double));
-  if (delta && s->delta) memcpy(delta, s->delta, m * sizeof(double));
+  if (delta && s->delta) memcpy(delta, s->delta, mk * sizeof(double));
   if (u1) memcpy(u1, s->u1, m * sizeof(double));
-  if (u2 && s->u2) memcpy(u2, s->u2, m * sizeof(double));
+  if (u2 && s->u2) memcpy(u2, s->u2, mk * sizeof(double));
   return 0;
 }
 
@@ -771,6 +845,150 @@ static void push_two_body(or_ctx* c, or_species* s, int64_t p) {
     if (!isfinite(u1[a]) || !isfinite(u2[a]) || !isfinite(dl[a])) c->err |= OR_ERR_NAN;
 }
 
+/* One step of a multi-shell ion, the two-body step of Sec. 2 with one
+   bond per shell: every body is gathered at its own position, each bond
+   adds +F_k / q0 to the nucleus' field and -F_k / q_k to cloud k's, each
+   body is Boris-pushed, the centre of mass moves with the mass-weighted
+   velocities and d_k = r0 - r_k with v0 - v_k, the walls mirror each body,
+   and each body deposits its own current.  The damping nu acts on each
+   nucleus-cloud pair in turn as on a two-body ion (pair momentum kept). */
+static void push_multishell(or_ctx* c, or_species* s, int64_t p) {
+  const or_config* g = &c->g;
+  const int nd = c->nd, K = s->nshell, nb = K + 1;
+  double W = s->w ? s->w[p] : s->weight;
+  double q[OR_MAX_SHELL + 1], m[OR_MAX_SHELL + 1];
+  q[0] = s->q1;
+  m[0] = s->m1;
+  double M = s->m1;
+  for (int k = 0; k < K; k++) {
+    q[k + 1] = s->qk[k];
+    m[k + 1] = s->mk[k];
+    M += s->mk[k];
+  }
+  int32_t* cell = &s->cell[3 * p];
+  double* off = &s->off[3 * p];
+  double* dl = &s->delta[3 * K * p]; /* shell k at dl + 3k */
+  double* u[OR_MAX_SHELL + 1];
+  u[0] = &s->u1[3 * p];
+  for (int k = 0; k < K; k++) u[k + 1] = &s->u2[3 * K * p + 3 * k];
+
+  /* body positions (cell units, relative to the centre's cell) and frames */
+  double x[OR_MAX_SHELL + 1][3];
+  memset(x, 0, sizeof(x));
+  for (int d = 0; d < nd; d++) {
+    double r0 = off[d];
+    for (int k = 0; k < K; k++) r0 += (m[k + 1] / M) * dl[3 * k + d] / g->dx[d];
+    x[0][d] = r0;
+    for (int k = 0; k < K; k++) x[k + 1][d] = r0 - dl[3 * k + d] / g->dx[d];
+  }
+  int32_t bc[OR_MAX_SHELL + 1][3];
+  double bx[OR_MAX_SHELL + 1][3], E[OR_MAX_SHELL + 1][3], B[OR_MAX_SHELL + 1][3];
+  for (int b = 0; b < nb; b++) {
+    body_frame(c, cell, x[b], bc[b], bx[b]);
+    gather(c, bc[b], bx[b], E[b], B[b]);
+  }
+  /* the bonds, as extra fields */
+  for (int k = 0; k < K; k++) {
+    const double* r = &dl[3 * k];
+    double mr = m[0] * m[k + 1] / (m[0] + m[k + 1]);
+    double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    double ak = s->ak[k];
+    double soft = isinf(ak) ? 1.0 : pow(1.0 + r2 / (ak * ak), -1.5);
+    double kf = -mr * s->wk[k] * s->wk[k] * soft;
+    for (int a = 0; a < 3; a++) {
+      double F = kf * r[a];
+      E[0][a] += F / q[0];
+      E[k + 1][a] -= F / q[k + 1];
+    }
+  }
+  double h = 0.5 * g->dt;
+  double ab[OR_MAX_SHELL + 1], um[OR_MAX_SHELL + 1][3];
+  for (int b = 0; b < nb; b++) {
+    ab[b] = h * q[b] / m[b];
+    for (int a = 0; a < 3; a++) um[b][a] = u[b][a] + ab[b] * E[b][a];
+  }
+  if (s->nu > 0.0) {
+    double D = (1.0 - s->nu * h) / (1.0 + s->nu * h);
+    for (int k = 0; k < K; k++) {
+      double mp = m[0] + m[k + 1];
+      for (int a = 0; a < 3; a++) {
+        double V = (m[0] * um[0][a] + m[k + 1] * um[k + 1][a]) / mp;
+        double w = (um[0][a] - um[k + 1][a]) * D;
+        um[0][a] = V + (m[k + 1] / mp) * w;
+        um[k + 1][a] = V - (m[0] / mp) * w;
+      }
+    }
+  }
+  double v[OR_MAX_SHELL + 1][3];
+  for (int b = 0; b < nb; b++) {
+    double nw[3];
+    boris_finish(um[b], ab[b], E[b], B[b], nw);
+    double gm = sqrt(1.0 + nw[0] * nw[0] + nw[1] * nw[1] + nw[2] * nw[2]);
+    for (int a = 0; a < 3; a++) {
+      u[b][a] = nw[a];
+      v[b][a] = nw[a] / gm;
+    }
+  }
+  /* move */
+  double offn[3] = {0, 0, 0};
+  for (int k = 0; k < K; k++)
+    for (int a = 0; a < 3; a++) dl[3 * k + a] += g->dt * (v[0][a] - v[k + 1][a]);
+  for (int d = 0; d < nd; d++) {
+    double P = 0.0;
+    for (int b = 0; b < nb; b++) P += m[b] * v[b][d];
+    offn[d] = off[d] + g->dt * P / M / g->dx[d];
+  }
+  /* walls: a body past a wall is mirrored (moved by D cells) and its
+     momentum component reversed; R moves by (m_b/M) D; the nucleus' move
+     adds D dx to every d_k, cloud k's subtracts it from d_k */
+  for (int d = 0; d < nd; d++) {
+    if (periodic(c, d)) continue;
+    double lo = (double)(g->pad - cell[d]), hi = (double)(c->nn[d] - g->pad - cell[d]);
+    double y[OR_MAX_SHELL + 1], Dm[OR_MAX_SHELL + 1];
+    double y0 = offn[d];
+    for (int k = 0; k < K; k++) y0 += (m[k + 1] / M) * dl[3 * k + d] / g->dx[d];
+    y[0] = y0;
+    for (int k = 0; k < K; k++) y[k + 1] = y0 - dl[3 * k + d] / g->dx[d];
+    for (int b = 0; b < nb; b++) {
+      Dm[b] = 0.0;
+      if (y[b] < lo) Dm[b] = 2.0 * (lo - y[b]);
+      else if (y[b] > hi) Dm[b] = 2.0 * (hi - y[b]);
+      if (Dm[b] != 0.0) {
+        u[b][d] = -u[b][d];
+        offn[d] += (m[b] / M) * Dm[b];
+      }
+    }
+    for (int k = 0; k < K; k++) dl[3 * k + d] += (Dm[0] - Dm[k + 1]) * g->dx[d];
+  }
+  /* new body positions, relative to the centre's old cell */
+  double yb[OR_MAX_SHELL + 1][3];
+  memset(yb, 0, sizeof(yb));
+  for (int d = 0; d < nd; d++) {
+    double r0 = offn[d];
+    for (int k = 0; k < K; k++) r0 += (m[k + 1] / M) * dl[3 * k + d] / g->dx[d];
+    yb[0][d] = r0;
+    for (int k = 0; k < K; k++) yb[k + 1][d] = r0 - dl[3 * k + d] / g->dx[d];
+  }
+  if (!(g->flags & OR_NO_DEPOSIT)) {
+    for (int b = 0; b < nb; b++) {
+      double z[3] = {0, 0, 0};
+      for (int d = 0; d < nd; d++) z[d] = yb[b][d] - (double)(bc[b][d] - cell[d]);
+      deposit(c, bc[b], bx[b], z, q[b] * W, v[b]);
+    }
+  }
+  for (int b = 0; b < nb; b++)
+    if (!body_in_range(c, cell, yb[b])) c->err |= OR_ERR_RANGE;
+  for (int d = 0; d < nd; d++) {
+    cross(c, d, &cell[d], &offn[d]);
+    off[d] = offn[d];
+  }
+  for (int b = 0; b < nb; b++)
+    for (int a = 0; a < 3; a++)
+      if (!isfinite(u[b][a])) c->err |= OR_ERR_NAN;
+  for (int a = 0; a < 3 * K; a++)
+    if (!isfinite(dl[a])) c->err |= OR_ERR_NAN;
+}
+
 static void push_point(or_ctx* c, or_species* s, int64_t p) {
   const or_config* g = &c->g;
   int nd = c->nd;
@@ -849,7 +1067,26 @@ int or_rho(or_ctx* c, double* rho) {
       const int32_t* cell = &s->cell[3 * p];
       const double* off = &s->off[3 * p];
       double x[3] = {0, 0, 0};
-      if (s->kind == OR_TWO_BODY) {
+      if (s->kind == OR_MULTI_SHELL) {
+        const int K = s->nshell;
+        const double* dl = &s->delta[3 * K * p];
+        double M = s->m1;
+        for (int k = 0; k < K; k++) M += s->mk[k];
+        double x0[3] = {0, 0, 0};
+        for (int d = 0; d < c->nd; d++) {
+          x0[d] = off[d];
+          for (int k = 0; k < K; k++) x0[d] += (s->mk[k] / M) * dl[3 * k + d] / c->g.dx[d];
+        }
+        int32_t bc[3];
+        double bx[3];
+        body_frame(c, cell, x0, bc, bx);
+        add_rho(c, rho, bc, bx, s->q1 * W);
+        for (int k = 0; k < K; k++) {
+          for (int d = 0; d < c->nd; d++) x[d] = x0[d] - dl[3 * k + d] / c->g.dx[d];
+          body_frame(c, cell, x, bc, bx);
+          add_rho(c, rho, bc, bx, s->qk[k] * W);
+        }
+      } else if (s->kind == OR_TWO_BODY) {
         double mc = s->m1 + s->m2, f1 = s->m2 / mc, f2 = s->m1 / mc;
         const double* dl = &s->delta[3 * p];
         int32_t bc[3];
@@ -1228,6 +1465,8 @@ int or_step(or_ctx* c, int nsteps) {
       for (int64_t p = 0; p < s->n; p++) {
         if (s->kind == OR_TWO_BODY)
           push_two_body(c, s, p);
+        else if (s->kind == OR_MULTI_SHELL)
+          push_multishell(c, s, p);
         else
           push_point(c, s, p);
       }
@@ -1276,6 +1515,13 @@ int or_diagnostics(or_ctx* c, or_diag* out) {
         double g2 = sqrt(1.0 + u2[0] * u2[0] + u2[1] * u2[1] + u2[2] * u2[2]);
         ke += W * s->m2 * (g2 - 1.0);
         for (int a = 0; a < 3; a++) pm[a] += W * s->m2 * u2[a];
+      } else if (s->kind == OR_MULTI_SHELL) {
+        for (int k = 0; k < s->nshell; k++) {
+          const double* uk = &s->u2[3 * s->nshell * p + 3 * k];
+          double gk = sqrt(1.0 + uk[0] * uk[0] + uk[1] * uk[1] + uk[2] * uk[2]);
+          ke += W * s->mk[k] * (gk - 1.0);
+          for (int a = 0; a < 3; a++) pm[a] += W * s->mk[k] * uk[a];
+        }
       }
     }
   }

@@ -40,6 +40,7 @@ extern "C" {
 
 #define OR_POINT 0
 #define OR_TWO_BODY 1
+#define OR_MULTI_SHELL 2 /* nucleus + up to 4 bound clouds, each with its own bond */
 
 /* error word bits */
 #define OR_ERR_NAN 1u
@@ -93,6 +94,16 @@ void or_destroy(or_ctx* c);
 int or_add_species(or_ctx* c, int kind, double q1, double m1, double q2, double m2,
                    double weight, double omega_c, double a_c, double nu, double nu_per_omega,
                    double re_norm, int64_t capacity);
+/* Multi-shell ion: nucleus (q0, m0) and nshell (1..4) clouds, cloud k with
+   charge qk[k], mass mk[k], bond frequency wk[k] and softening length ak[k]
+   (0: derived as for a two-body ion with the pair's reduced mass; +inf:
+   harmonic).  Particles: x = centre of mass of all bodies, delta = n*3*nshell
+   (d_k = r_nucleus - r_cloud_k, shell k at 3k), u1 = nucleus n*3, u2 =
+   clouds n*3*nshell (NULL: each cloud moves with the nucleus); no
+   per-particle omega_c.  Returns species id >= 0, or -1. */
+int or_add_multishell(or_ctx* c, double q0, double m0, int nshell, const double* qk,
+                      const double* mk, const double* wk, const double* ak, double weight,
+                      double nu, double re_norm, int64_t capacity);
 /* Appends n particles.  x: n*ndim physical positions (centre of mass for
    two-body), delta: n*3 or NULL (= 0; any size: each body has its own
    position), u1: n*3, u2: n*3 or NULL.  For a
@@ -107,7 +118,8 @@ int or_load_fields(or_ctx* c, const double* E, const double* B);
 int or_step(or_ctx* c, int nsteps);
 int or_diagnostics(or_ctx* c, or_diag* out);
 int or_read_fields(or_ctx* c, double* E, double* B, double* J);
-/* cell: n*3 int32 (per dim), off: n*3, delta/u1/u2: n*3 (may be NULL) */
+/* cell: n*3 int32 (per dim), off: n*3, delta/u1/u2: n*3, multi-shell
+   delta/u2 n*3*nshell (may be NULL) */
 int or_read_particles(or_ctx* c, int sid, int32_t* cell, double* off, double* delta,
                       double* u1, double* u2);
 int64_t or_count(or_ctx* c, int sid);

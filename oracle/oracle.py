@@ -18,6 +18,7 @@ ORACLE_LIB = os.path.join(HERE, "liboracle.so")
 FROZEN_FIELDS = 1
 NO_DEPOSIT = 2
 CHARGE_CHECK = 4
+MULTI_SHELL = 2  # species kind: nucleus + bound clouds with one bond each
 
 
 class _Config(C.Structure):
@@ -61,6 +62,9 @@ def _load():
     lib.or_destroy.argtypes = [P]
     lib.or_add_species.restype = C.c_int
     lib.or_add_species.argtypes = [P, C.c_int] + [C.c_double] * 10 + [C.c_int64]
+    lib.or_add_multishell.restype = C.c_int
+    lib.or_add_multishell.argtypes = ([P, C.c_double, C.c_double, C.c_int, D, D, D, D] +
+                                      [C.c_double] * 3 + [C.c_int64])
     lib.or_load_particles.restype = C.c_int
     lib.or_load_particles.argtypes = [P, C.c_int, C.c_int64, D, D, D, D, D, D]
     lib.or_load_fields.argtypes = [P, D, D]
@@ -165,6 +169,8 @@ class Oracle:
 
     # ---------------------------------------------------------------- setup
     def add_species(self, sp, capacity: int) -> int:
+        if int(sp.kind) == MULTI_SHELL:
+            return self._add_multishell(sp, capacity)
         # a_c = 0: each ion's a_c from its own omega_c (derived in the C oracle)
         a_c = sp.a_c if sp.a_c is not None else math.inf
         sid = self.lib.or_add_species(self.ctx, int(sp.kind), sp.q1, sp.m1, sp.q2, sp.m2,
@@ -176,12 +182,29 @@ class Oracle:
         self.species.append(sp)
         return sid
 
+    def _add_multishell(self, sp, capacity: int) -> int:
+        sh = np.asarray(sp.shells, dtype=np.float64).reshape(-1, 4)
+        qk, mk, wk, ak = (np.ascontiguousarray(sh[:, j]) for j in range(4))
+        sid = self.lib.or_add_multishell(self.ctx, sp.q1, sp.m1, int(sh.shape[0]), _dp(qk),
+                                         _dp(mk), _dp(wk), _dp(ak), sp.weight, sp.nu,
+                                         float(self.grid.re_norm), int(capacity))
+        if sid < 0:
+            raise ValueError("oracle: add_multishell failed (1..4 shells, m > 0, q != 0, "
+                             "omega_c > 0, a_c >= 0; a derived a_c needs re_norm > 0)")
+        self.species.append(sp)
+        return sid
+
+    def _nshell(self, sid: int) -> int:
+        sp = self.species[sid]
+        return len(sp.shells) if int(sp.kind) == MULTI_SHELL else 1
+
     def load_particles(self, sid: int, parts) -> None:
         n = parts.n
+        K = self._nshell(sid)
         x = _f64(parts.x, (n, self.ndim))
         u1 = _f64(parts.u1, (n, 3))
-        delta = _f64(parts.delta, (n, 3))
-        u2 = _f64(parts.u2, (n, 3))
+        delta = _f64(parts.delta, (n, 3 * K))
+        u2 = _f64(parts.u2, (n, 3 * K))
         wc = _f64(parts.omega_c, (n,))
         w = _f64(parts.weight, (n,))
         rc = self.lib.or_load_particles(self.ctx, sid, n, _dp(x), _dp(delta), _dp(u1), _dp(u2),
@@ -239,11 +262,12 @@ class Oracle:
 
     def particles(self, sid: int) -> dict:
         n = self.lib.or_count(self.ctx, sid)
+        K = self._nshell(sid)
         cell = np.zeros((n, 3), dtype=np.int32)
         off = np.zeros((n, 3))
-        delta = np.zeros((n, 3))
+        delta = np.zeros((n, 3 * K))
         u1 = np.zeros((n, 3))
-        u2 = np.zeros((n, 3))
+        u2 = np.zeros((n, 3 * K))
         self.lib.or_read_particles(self.ctx, sid, cell.ctypes.data_as(C.POINTER(C.c_int32)),
                                    _dp(off), _dp(delta), _dp(u1), _dp(u2))
         nd = self.ndim

@@ -29,7 +29,7 @@ from typing import List, Optional, Tuple
 import numpy as np
 
 PERIODIC, OPEN, LASER = 0, 1, 2
-POINT, TWO_BODY = 0, 1
+POINT, TWO_BODY, MULTI_SHELL = 0, 1, 2
 
 # physical constants (CODATA 2018)
 ME_C2_EV = 510998.95            # electron rest energy, eV
@@ -94,14 +94,17 @@ class Species:
     nu: float = 0.0
     nu_per_omega: float = 0.0
     name: str = ""
+    # MULTI_SHELL: the nucleus is (q1, m1); each shell is a bound cloud
+    # (charge, mass, omega_c, a_c) with its own bond to the nucleus
+    shells: Tuple[Tuple[float, float, float, float], ...] = ()
 
 
 @dataclass
 class Particles:
     x: np.ndarray                       # (n, ndim) positions, centre of mass for two-body
     u1: np.ndarray                      # (n, 3) momentum per mass (centre of mass if u2 is None)
-    delta: Optional[np.ndarray] = None  # (n, 3) r1 - r2
-    u2: Optional[np.ndarray] = None     # (n, 3)
+    delta: Optional[np.ndarray] = None  # (n, 3) r1 - r2; multi-shell (n, 3 K) r0 - r_k
+    u2: Optional[np.ndarray] = None     # (n, 3); multi-shell (n, 3 K) the clouds
     omega_c: Optional[np.ndarray] = None
     weight: Optional[np.ndarray] = None
 

@@ -1,0 +1,213 @@
+"""Oracle pins (CPU only) for multi-shell ions, the extension named in the
+paper's summary (several bound-electron components per ion): a nucleus and
+K clouds, each cloud bound to the nucleus alone by the Sec. 2 bond with its
+own charge, mass, omega_c and a_c.
+
+* one shell is exactly a two-body ion (coupled runs with walls, damping and
+  derived a_c agree with the two-body species to rounding);
+* the linear normal modes of a two-shell ion (the resonances of its
+  multi-resonance permittivity) are the eigenfrequencies of the coupled
+  spring system, nucleus recoil included, with the leapfrog's discrete
+  dispersion;
+* the static polarisation of each shell (the zero-frequency limit) is the
+  closed form of its own bond, harmonic and softened;
+* the momentum of a charged multi-shell ion in a uniform field grows by the
+  impulse of every body's charge; the deposit of every body keeps the charge
+  continuity.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from oracle.oracle import CHARGE_CHECK, FROZEN_FIELDS, NO_DEPOSIT
+from paper_2208_08038_amd.inputs import (MULTI_SHELL, OPEN, PERIODIC, POINT, TWO_BODY, Grid,
+                                         Particles, Species, Workload)
+
+INF = math.inf
+
+
+def _grid(ndim, n, dx, dt, bc=PERIODIC, **kw):
+    n3 = tuple(list(n) + [1] * (3 - len(n)))
+    dx3 = tuple(list(dx) + [1.0] * (3 - len(dx)))
+    bcs = tuple([bc] * ndim + [PERIODIC] * (3 - ndim))
+    return Grid(ndim, n3, dx3, dt, bcs, bcs, **kw)
+
+
+def _one_ion(o, sp, x, delta, u1=None, u2=None):
+    sid = o.add_species(sp, 1)
+    K = len(sp.shells)
+    o.load_particles(sid, Particles(x=np.atleast_2d(x), u1=np.zeros((1, 3)) if u1 is None else u1,
+                                    delta=np.asarray(delta, float).reshape(1, 3 * K),
+                                    u2=None if u2 is None else np.asarray(u2).reshape(1, 3 * K)))
+    return sid
+
+
+@pytest.mark.parametrize("bc", [PERIODIC, OPEN])
+def test_one_shell_is_a_two_body_ion(oracle_built, bc):
+    """A multi-shell species of one shell and the two-body species of the same
+    charges, masses, bond and damping follow the same coupled run (fields,
+    bodies) to rounding, with walls when the faces are open."""
+    rng = np.random.default_rng(3)
+    g = _grid(2, (24, 20), (0.3, 0.25), 0.15, bc=bc, re_norm=2e-3)
+    n = 40
+    lo = np.array([g.pad + 0.3 if bc == OPEN else 0.0] * 2)
+    hi = np.array([s - (g.pad + 0.3 if bc == OPEN else 0.0) for s in (24, 20)])
+    x = (lo + (hi - lo) * rng.random((n, 2))) * np.array([0.3, 0.25])
+    u1 = rng.normal(scale=0.1, size=(n, 3))
+    u2 = u1 + rng.normal(scale=0.05, size=(n, 3))
+    delta = rng.uniform(-0.05, 0.05, size=(n, 3))
+    q1, m1, q2, m2, wc = 5.0, 40.0, -3.0, 3.0, 2.0
+    two = Species(TWO_BODY, q1, m1, q2, m2, weight=0.01, omega_c=wc, a_c=0.0, nu=0.05)
+    ms = Species(MULTI_SHELL, q1, m1, weight=0.01, nu=0.05, shells=((q2, m2, wc, 0.0),))
+    el = Species(POINT, -1.0, 1.0, weight=0.01)
+    xe = (lo + (hi - lo) * rng.random((n, 2))) * np.array([0.3, 0.25])
+    ue = rng.normal(scale=0.3, size=(n, 3))
+    runs = []
+    for sp in (two, ms):
+        wl = Workload("shell1", g, [(sp, Particles(x=x, u1=u1, delta=delta, u2=u2)),
+                                    (el, Particles(x=xe, u1=ue))], 1)
+        o = Oracle.from_workload(wl)
+        o.step(25)
+        assert o.diagnostics()["error_word"] == 0
+        runs.append(o)
+    (E0, B0, J0), (E1, B1, J1) = runs[0].fields(), runs[1].fields()
+    for a, b in ((E0, E1), (B0, B1), (J0, J1)):
+        assert np.abs(a - b).max() <= 1e-11 * np.abs(a).max()
+    p0, p1 = runs[0].particles(0), runs[1].particles(0)
+    assert np.array_equal(p0["cell"], p1["cell"])
+    for k in ("off", "delta", "u1", "u2"):
+        assert np.abs(p0[k] - p1[k]).max() <= 1e-11 * max(np.abs(p0[k]).max(), 1.0), k
+
+
+def _shell_matrix(m0, shells):
+    """delta_k'' = -sum_j A_kj delta_j for harmonic bonds k_j = mu_j w_j^2
+    between the nucleus (m0) and cloud j (m_j), delta_j = x0 - x_j."""
+    K = len(shells)
+    kap = [m0 * m / (m0 + m) * w * w for (_, m, w, _) in shells]
+    A = np.zeros((K, K))
+    for k in range(K):
+        for j in range(K):
+            A[k, j] = kap[j] / m0 + (kap[k] / shells[k][1] if j == k else 0.0)
+    return A
+
+
+def test_normal_modes_of_a_two_shell_ion(oracle_built):
+    """A two-shell ion at rest with its clouds displaced (tiny, harmonic
+    bonds, no field) oscillates in the two normal modes of the coupled
+    system, A = eigen-problem of the nucleus with two springs: every sample
+    of d_1, d_2 is a sum of two sinusoids at the leapfrog frequencies
+    (2/dt) asin(w_m dt/2), w_m^2 the eigenvalues of A."""
+    dt = 0.05
+    g = _grid(1, (16,), (1.0,), dt)
+    m0, q0 = 30.0, 5.0
+    shells = ((-2.0, 2.0, 1.3, INF), (-3.0, 3.0, 2.9, INF))
+    sp = Species(MULTI_SHELL, q0, m0, weight=1.0, shells=shells)
+    o = Oracle(g, flags=FROZEN_FIELDS | NO_DEPOSIT)
+    o.load_fields(np.zeros((3, o.ncell)), np.zeros((3, o.ncell)))
+    d0 = np.array([[1e-6, 0, 0], [-2e-6, 0, 0]])
+    _one_ion(o, sp, [8.3], d0)
+    nsteps = 3000
+    ds = np.zeros((nsteps + 1, 2))
+    ds[0] = d0[:, 0]
+    for n in range(nsteps):
+        o.step(1)
+        ds[n + 1] = o.particles(0)["delta"][0].reshape(2, 3)[:, 0]
+    w2 = np.linalg.eigvals(_shell_matrix(m0, shells)).real
+    wt = 2.0 / dt * np.arcsin(np.sqrt(w2) * dt / 2.0)
+    t = dt * np.arange(nsteps + 1)
+    basis = np.stack([f(w * t) for w in wt for f in (np.cos, np.sin)], axis=1)
+    for k in range(2):
+        coef, *_ = np.linalg.lstsq(basis, ds[:, k], rcond=None)
+        resid = ds[:, k] - basis @ coef
+        assert np.abs(resid).max() < 1e-7 * np.abs(ds[:, k]).max(), k
+    # a model without the nucleus' recoil (clouds on a fixed centre) is off
+    w_fixed = np.array([s[2] * math.sqrt(m0 / (m0 + s[1])) for s in shells])
+    wt_f = 2.0 / dt * np.arcsin(w_fixed * dt / 2.0)
+    bad = np.stack([f(w * t) for w in wt_f for f in (np.cos, np.sin)], axis=1)
+    coef, *_ = np.linalg.lstsq(bad, ds[:, 1], rcond=None)
+    assert np.abs(ds[:, 1] - bad @ coef).max() > 1e-3 * np.abs(ds[:, 1]).max()
+
+
+@pytest.mark.parametrize("soft", [False, True])
+def test_static_polarisation_of_each_shell(oracle_built, soft):
+    """A neutral two-shell ion with damping in a static uniform field settles
+    where every cloud's bond balances its own charge, q_k E + F_k = 0: the
+    zero-frequency limit of the multi-resonance permittivity.  Harmonic:
+    d_k = -q_k E / (mu_k w_k^2); softened: mu_k w_k^2 d (1 + d^2/a_k^2)^{-3/2}
+    = |q_k E| solved for d."""
+    from scipy.optimize import brentq
+    g = _grid(1, (16,), (1.0,), 0.05)
+    m0 = 30.0
+    shells = ((-2.0, 2.0, 1.3, 0.4 if soft else INF), (-3.0, 3.0, 2.9, 0.2 if soft else INF))
+    q0 = -sum(s[0] for s in shells)
+    sp = Species(MULTI_SHELL, q0, m0, weight=1.0, nu=0.8, shells=shells)
+    o = Oracle(g, flags=FROZEN_FIELDS | NO_DEPOSIT)
+    E = np.zeros((3, o.ncell))
+    Ex = 0.01
+    E[0] = Ex
+    o.load_fields(E, np.zeros((3, o.ncell)))
+    _one_ion(o, sp, [8.0], np.zeros(6))
+    o.step(20000)
+    d = o.particles(0)["delta"][0].reshape(2, 3)[:, 0]
+    for k, (qk, mk, wk, ak) in enumerate(shells):
+        kap = m0 * mk / (m0 + mk) * wk * wk
+        if not soft:
+            want = -qk * Ex / kap
+        else:
+            f = lambda r: kap * r * (1.0 + r * r / (ak * ak)) ** -1.5 - abs(qk * Ex)
+            want = math.copysign(brentq(f, 0.0, ak * math.sqrt(2.0) * 0.999), -qk * Ex)
+        assert abs(d[k] - want) < 1e-8 * abs(want), (k, d[k], want)
+
+
+def test_charged_multishell_ion_momentum_impulse(oracle_built):
+    """A charged three-shell ion in a uniform static E (no B): the total
+    momentum sum W m u over the four bodies grows by W (q0 + sum q_k) E dt per
+    step, whatever the bonds do inside."""
+    dt = 0.1
+    g = _grid(2, (12, 12), (0.5, 0.5), dt)
+    shells = ((-2.0, 2.0, 1.1, INF), (-3.0, 3.0, 1.7, 0.3), (-1.0, 1.0, 2.3, INF))
+    q0, m0, W = 9.0, 40.0, 0.3
+    sp = Species(MULTI_SHELL, q0, m0, weight=W, shells=shells)
+    o = Oracle(g, flags=FROZEN_FIELDS | NO_DEPOSIT)
+    E = np.zeros((3, o.ncell))
+    E[0], E[1] = 0.02, -0.015
+    o.load_fields(E, np.zeros((3, o.ncell)))
+    _one_ion(o, sp, [3.0, 3.0], [0.02, 0.01, 0.0, -0.01, 0.02, 0.0, 0.0, 0.03, 0.01],
+             u1=np.array([[0.01, 0.0, 0.0]]))
+    p0 = np.array(o.diagnostics()["momentum"])
+    o.step(40)
+    p1 = np.array(o.diagnostics()["momentum"])
+    qt = q0 + sum(s[0] for s in shells)
+    want = W * qt * np.array([0.02, -0.015, 0.0]) * dt * 40
+    assert np.abs((p1 - p0) - want).max() < 1e-12 * np.abs(want).max() + 1e-15
+
+
+@pytest.mark.parametrize("bc", [PERIODIC, OPEN])
+def test_multishell_charge_continuity(oracle_built, bc):
+    """Coupled 2D run of two-shell ions (one cloud torn more than a cell from
+    its nucleus) and electrons: every body's Esirkepov current keeps
+    (rho^{n+1} - rho^n)/dt + div J = 0 to rounding."""
+    rng = np.random.default_rng(7)
+    g = _grid(2, (20, 18), (0.3, 0.3), 0.15, bc=bc, re_norm=1e-3)
+    n = 25
+    pad = g.pad + 1.5 if bc == OPEN else 0.0
+    lo, hi = np.array([pad, pad]), np.array([20 - pad, 18 - pad])
+    x = (lo + (hi - lo) * rng.random((n, 2))) * 0.3
+    delta = rng.uniform(-0.05, 0.05, size=(n, 6))
+    delta[0, 3] = 0.4  # shell 2 of ion 0 more than a cell away
+    u1 = rng.normal(scale=0.05, size=(n, 3))
+    u2 = np.repeat(u1, 2, axis=0).reshape(n, 6) + rng.normal(scale=0.05, size=(n, 6))
+    shells = ((-2.0, 2.0, 1.5, 0.0), (-4.0, 4.0, 0.7, INF))
+    sp = Species(MULTI_SHELL, 7.0, 60.0, weight=0.02, nu=0.1, shells=shells)
+    el = Species(POINT, -1.0, 1.0, weight=0.02)
+    xe = (lo + (hi - lo) * rng.random((n, 2))) * 0.3
+    wl = Workload("shells", g, [(sp, Particles(x=x, u1=u1, delta=delta, u2=u2)),
+                                (el, Particles(x=xe, u1=rng.normal(scale=0.4, size=(n, 3))))], 1)
+    o = Oracle.from_workload(wl, flags=CHARGE_CHECK)
+    o.step(15)
+    d = o.diagnostics()
+    assert d["error_word"] == 0
+    assert d["rho_l2"] > 0
+    assert d["div_l2"] < 1e-11 * d["rho_l2"]
