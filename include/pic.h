@@ -74,6 +74,8 @@ typedef enum {
 /* species kinds */
 #define PIC_POINT 0
 #define PIC_TWO_BODY 1
+#define PIC_MULTI_SHELL 2 /* nucleus + 1..PIC_MAX_SHELL bound clouds (pic_add_multishell) */
+#define PIC_MAX_SHELL 4
 
 /* Device error word bits (pic_diag.error_word).  A macro-particle whose
    state is non-finite (NAN) or outside the representable range (RANGE: an
@@ -190,6 +192,30 @@ int pic_create(const pic_config* cfg, const pic_allocator* alloc, void* hip_stre
 /* Add a species (Sec. 2 two-body macro-ion or point particle) with room for
    desc->capacity macro-particles; *species_id receives its id. */
 int pic_add_species(pic_ctx* ctx, const pic_species_desc* desc, int32_t* species_id);
+
+/* Add a multi-shell ion species: the bound electrons of an ion split into
+   several components (the extension the paper's summary names), each cloud
+   bound to the nucleus alone by the Sec. 2 bond.  desc: kind =
+   PIC_MULTI_SHELL, q1 and m1 the nucleus, weight, nu (friction on each
+   nucleus-cloud pair's relative momentum, applied pair by pair in shell
+   order, pair momentum kept), capacity; the other fields are ignored.
+   Cloud k < nshell (1..PIC_MAX_SHELL): charge shell_q[k] (!= 0), mass
+   shell_m[k] > 0, restoring frequency shell_omega[k] > 0, softening length
+   shell_ac[k] (0: derived as for a two-body ion, a^3 = |q1 q_k| re_norm /
+   (m_r,k omega_k^2) with the pair's reduced mass m_r,k = m1 m_k / (m1 +
+   m_k); +inf: harmonic; else as given).  One shell is exactly a two-body
+   ion.  Particles (pic_load_particles, host arrays only): x = centre of mass
+   of all bodies, delta n x 3 nshell (d_k = r_nucleus - r_cloud_k, shell k at
+   3k; NULL: 0), u1 the nucleus n x 3, u2 the clouds n x 3 nshell (NULL:
+   every cloud moves with the nucleus), omega_c NULL; every body between
+   the walls (PIC_ERANGE).  pic_read_particles and pic_read_particles_range
+   return delta and u2 with 3 nshell values per particle.  The species is
+   advanced from HBM, one thread per ion, every body gathered and deposited
+   in the frame of its own cell.  The device loader and gradient runs refuse
+   it (PIC_EINVAL). */
+int pic_add_multishell(pic_ctx* ctx, const pic_species_desc* desc, int32_t nshell,
+                       const double* shell_q, const double* shell_m, const double* shell_omega,
+                       const double* shell_ac, int32_t* species_id);
 
 /* Append n particles from HOST FP64 arrays:
    x      n x ndim physical positions (centre of mass r_c for two-body)

@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpic.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 SOURCES = ["api.hip", "particles.hip", "fields.hip", "diag.hip", "sort.hip", "load.hip",
-           "tiled.hip", "adjoint.hip", "grad.hip", "state.hip", "noalloc.hip"]
+           "tiled.hip", "adjoint.hip", "grad.hip", "state.hip", "noalloc.hip",
+           "shells.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

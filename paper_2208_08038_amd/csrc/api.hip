@@ -266,6 +266,127 @@ int load_particles_t(pic_ctx* c, SpeciesHost& s, int64_t n, const double* x, con
   return PIC_OK;
 }
 
+// Multi-shell load: x = centre of mass of all bodies, delta n x 3K (d_k =
+// r_nucleus - r_cloud_k), u1 the nucleus, u2 n x 3K the clouds (NULL: every
+// cloud moves with the nucleus); every body between the walls.
+template <typename Real>
+int load_shells_t(pic_ctx* c, SpeciesHost& s, int64_t n, const double* x, const double* delta,
+                  const double* u1, const double* u2, const double* w) {
+  const int nd = c->g.nd, K = s.nshell;
+  double M = s.d.m1;
+  for (int k = 0; k < K; k++) M += s.sm[k];
+  std::vector<uint32_t> cell(n);
+  std::vector<int64_t> key(n);
+  std::vector<double> off(n * 3, 0.0), du0(n * 3), ddl(n * 3 * K), duk(n * 3 * K);
+  for (int64_t p = 0; p < n; p++) {
+    int ci[3] = {0, 0, 0};
+    for (int d = 0; d < nd; d++) {
+      double xv = x[p * nd + d];
+      if (!std::isfinite(xv)) return fail(c, PIC_ENAN, "non-finite particle position");
+      double xi = xv / c->cfg.dx[d];
+      double f = std::floor(xi);
+      if (f < 0 || f >= (double)c->g.n[d])
+        return fail(c, PIC_ERANGE, "particle position outside the grid");
+      ci[d] = (int)f;
+      Real orr = (Real)(xi - f);
+      if (orr >= Real(1)) {
+        orr -= Real(1);
+        ci[d] += 1;
+        if (ci[d] >= c->g.n[d]) {
+          if (is_periodic(c->cfg, d))
+            ci[d] -= c->g.n[d];
+          else
+            return fail(c, PIC_ERANGE, "particle on the upper grid edge");
+        }
+      }
+      off[p * 3 + d] = (double)orr;
+    }
+    for (int a = 0; a < 3 * K; a++) {
+      const double v = delta ? delta[3 * K * p + a] : 0.0;
+      if (!std::isfinite(v)) return fail(c, PIC_ENAN, "non-finite delta");
+      ddl[3 * K * p + a] = v;
+    }
+    // along walled axes every body lies between the walls
+    for (int d = 0; d < nd; d++) {
+      if (is_periodic(c->cfg, d)) continue;
+      double X0 = x[p * nd + d] / c->cfg.dx[d];
+      for (int k = 0; k < K; k++) X0 += (s.sm[k] / M) * ddl[3 * K * p + 3 * k + d] / c->cfg.dx[d];
+      const double lo = c->g.pad, hi = c->g.n[d] - c->g.pad;
+      bool ok = X0 >= lo && X0 <= hi;
+      for (int k = 0; k < K; k++) {
+        const double Xk = X0 - ddl[3 * K * p + 3 * k + d] / c->cfg.dx[d];
+        ok = ok && Xk >= lo && Xk <= hi;
+      }
+      if (!ok) return fail(c, PIC_ERANGE, "a body of a multi-shell ion is outside the particle walls");
+    }
+    for (int a = 0; a < 3; a++) {
+      du0[3 * p + a] = u1[3 * p + a];
+      if (!std::isfinite(u1[3 * p + a])) return fail(c, PIC_ENAN, "non-finite momentum");
+    }
+    for (int k = 0; k < K; k++)
+      for (int a = 0; a < 3; a++) {
+        const double v = u2 ? u2[3 * K * p + 3 * k + a] : u1[3 * p + a];
+        if (!std::isfinite(v)) return fail(c, PIC_ENAN, "non-finite momentum");
+        duk[3 * K * p + 3 * k + a] = v;
+      }
+    uint32_t pk = (uint32_t)ci[0];
+    if (nd > 1) pk |= (uint32_t)ci[1] << c->g.bits[0];
+    if (nd > 2) pk |= (uint32_t)ci[2] << (c->g.bits[0] + c->g.bits[1]);
+    cell[p] = pk;
+    key[p] = (ci[0] / c->tile[0]) +
+             (int64_t)c->ntiles[0] * ((ci[1] / c->tile[1]) + (int64_t)c->ntiles[1] * (ci[2] / c->tile[2]));
+  }
+  std::vector<int64_t> perm(n);
+  {
+    int64_t nt = (int64_t)c->ntiles[0] * c->ntiles[1] * c->ntiles[2];
+    std::vector<int64_t> cnt(nt + 1, 0);
+    for (int64_t p = 0; p < n; p++) cnt[key[p] + 1]++;
+    for (int64_t t = 0; t < nt; t++) cnt[t + 1] += cnt[t];
+    for (int64_t p = 0; p < n; p++) perm[cnt[key[p]]++] = p;
+  }
+  const int64_t at = s.n;
+  std::vector<uint32_t> hc(n);
+  for (int64_t q = 0; q < n; q++) hc[q] = cell[perm[q]];
+  HIPCHK(c, hipMemcpyAsync(static_cast<uint32_t*>(s.cell) + at, hc.data(), n * sizeof(uint32_t),
+                           hipMemcpyHostToDevice, c->stream));
+  std::vector<Real> buf(n);
+  auto put = [&](void* dst, const std::vector<double>& src, int comp, int stride) -> int {
+    for (int64_t q = 0; q < n; q++) buf[q] = (Real)src[perm[q] * stride + comp];
+    int rc = upload<Real>(c, dst, buf, at);
+    if (rc) return rc;
+    return hipStreamSynchronize(c->stream) == hipSuccess ? PIC_OK
+                                                         : fail(c, PIC_EHIP, "sync failed");
+  };
+  int rc;
+  for (int d = 0; d < nd; d++)
+    if ((rc = put(s.off[d], off, d, 3))) return rc;
+  for (int a = 0; a < 3; a++)
+    if ((rc = put(s.u1[a], du0, a, 3))) return rc;
+  for (int k = 0; k < K; k++)
+    for (int a = 0; a < 3; a++) {
+      if ((rc = put(s.sdl[k][a], ddl, 3 * k + a, 3 * K))) return rc;
+      if ((rc = put(s.su2[k][a], duk, 3 * k + a, 3 * K))) return rc;
+    }
+  if (w || s.has_w) {
+    std::vector<double> tmp(n, s.d.weight);
+    if (w)
+      for (int64_t p = 0; p < n; p++) tmp[p] = w[p];
+    for (int64_t p = 0; p < n; p++) s.max_w = std::max(s.max_w, std::fabs(tmp[p]));
+    if (!s.w) return fail(c, PIC_ESTATE, "per-particle weight must come with the first load");
+    if ((rc = put(s.w, tmp, 0, 1))) return rc;
+  }
+  if (s.ids) {
+    std::vector<int64_t> ids(n);
+    for (int64_t q = 0; q < n; q++) ids[q] = at + perm[q];
+    HIPCHK(c, hipMemcpyAsync(s.ids + at, ids.data(), n * sizeof(int64_t), hipMemcpyHostToDevice,
+                             c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  s.n += n;
+  s.needs_sort = true;
+  return PIC_OK;
+}
+
 // ------------------------------------------------------------ stepping
 
 }  // namespace
@@ -326,8 +447,7 @@ void harvest_counts(pic_ctx* c) {
 template <typename Real>
 void deposit_rho(pic_ctx* c, double* rho) {
   pic::launch_zero<double>(rho, c->g.plane, c->stream);
-  for (auto& s : c->sp)
-    pic::launch_rho<Real>(c->g, species_dev<Real>(*s), push_const<Real>(c, *s), rho, c->stream);
+  for (auto& s : c->sp) launch_rho_species<Real>(c, *s, rho);
   pic::launch_fold_periodic_f64(c->g, rho, c->stream);
 }
 
@@ -414,7 +534,15 @@ int advance_one(pic_ctx* c, const pic::LaserDev& las, const StepOpts& o,
   for (size_t si = 0; si < c->sp.size() && pi < 0; si++) {
     auto& s = c->sp[si];
     TimedDispatch td{c, (int)si, false};
-    if (c->tiled) {
+    if (s->d.kind == PIC_MULTI_SHELL) {
+      // multi-shell ions advance from HBM (one thread per ion)
+      TimedDispatch::hook(&td, true);
+      hipError_t e = pic::launch_push_shells<Real>(g, f, shell_dev<Real>(*s), shell_const<Real>(c, *s),
+                                                   push_const<Real>(c, *s), c->err, c->stream);
+      TimedDispatch::hook(&td, false);
+      if (e != hipSuccess)
+        return fail(c, PIC_EHIP, std::string("multi-shell kernel: ") + hipGetErrorString(e));
+    } else if (c->tiled) {
       pic::DispatchHook hook;
       if (c->cfg.flags & PIC_FLAG_TIMING) hook = {&TimedDispatch::hook, &td};
       hipError_t e = pic::launch_push_tiled<Real>(g, f, species_dev<Real>(*s),
@@ -551,13 +679,25 @@ int diagnostics_t(pic_ctx* c, pic_diag* out) {
     const SpeciesHost& s = *sp;
     np += s.n;
     if (s.n == 0) continue;
-    pic::launch_kinetic<Real>(species_dev<Real>(s), push_const<Real>(c, s), c->partials, nb,
-                              c->dout + 0, c->stream);
-    double k4[4];
-    HIPCHK(c, hipMemcpyAsync(k4, c->dout, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    ke += k4[0];
-    for (int a = 0; a < 3; a++) pm[a] += k4[1 + a];
+    // a multi-shell ion sums as its nucleus and each cloud, each viewed as
+    // a point species of its own mass
+    const int nbody = s.d.kind == PIC_MULTI_SHELL ? 1 + s.nshell : 1;
+    for (int b = 0; b < nbody; b++) {
+      pic::SpeciesDev<Real> sd = species_dev<Real>(s);
+      pic::PushConst<Real> pc = push_const<Real>(c, s);
+      if (s.d.kind == PIC_MULTI_SHELL) {
+        pc.two_body = 0;
+        pc.m1 = (Real)(b == 0 ? s.d.m1 : s.sm[b - 1]);
+        if (b > 0)
+          for (int a = 0; a < 3; a++) sd.u1[a] = static_cast<Real*>(s.su2[b - 1][a]);
+      }
+      pic::launch_kinetic<Real>(sd, pc, c->partials, nb, c->dout + 0, c->stream);
+      double k4[4];
+      HIPCHK(c, hipMemcpyAsync(k4, c->dout, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      ke += k4[0];
+      for (int a = 0; a < 3; a++) pm[a] += k4[1 + a];
+    }
   }
   uint32_t ew = 0, nsl[kMaxSpecies] = {}, nfr[kMaxSpecies] = {};
   HIPCHK(c, hipMemcpyAsync(&ew, c->err, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
@@ -670,6 +810,10 @@ int read_particles_t(pic_ctx* c, SpeciesHost& s, int64_t start, int64_t cnt, int
     if (s.d.kind == PIC_TWO_BODY) {
       if (u2 && (rc = get(s.u2[a], u2, a, 3))) return rc;
       if (delta && (rc = get(s.dl[a], delta, a, 3))) return rc;
+    }
+    for (int k = 0; k < s.nshell; k++) {  // multi-shell: 3 nshell values per particle
+      if (u2 && (rc = get(s.su2[k][a], u2, 3 * k + a, 3 * s.nshell))) return rc;
+      if (delta && (rc = get(s.sdl[k][a], delta, 3 * k + a, 3 * s.nshell))) return rc;
     }
   }
   if (wc) {
@@ -993,6 +1137,77 @@ int pic_add_species(pic_ctx* c, const pic_species_desc* d, int32_t* sid) {
   return PIC_OK;
 }
 
+int pic_add_multishell(pic_ctx* c, const pic_species_desc* d, int32_t nshell,
+                       const double* shell_q, const double* shell_m, const double* shell_omega,
+                       const double* shell_ac, int32_t* sid) {
+  if (!c || !d || !sid || !shell_q || !shell_m || !shell_omega || !shell_ac)
+    return fail(c, PIC_EINVAL, "null argument");
+  c->version++;
+  if (d->kind != PIC_MULTI_SHELL) return fail(c, PIC_EINVAL, "bad kind (PIC_MULTI_SHELL expected)");
+  if (nshell < 1 || nshell > pic::kMaxShell)
+    return fail(c, PIC_EINVAL, "nshell must be 1 .. PIC_MAX_SHELL");
+  if ((int)c->sp.size() >= kMaxSpecies) return fail(c, PIC_EINVAL, "too many species");
+  if (d->capacity < 0 || d->capacity >= (int64_t(1) << 31))
+    return fail(c, PIC_EINVAL, "capacity must be below 2^31");
+  if (!(d->m1 > 0) || d->q1 == 0.0) return fail(c, PIC_EINVAL, "bad nucleus charge or mass");
+  if (std::isnan(d->nu) || d->nu < 0) return fail(c, PIC_EINVAL, "nu must be >= 0");
+  auto holder = std::make_unique<SpeciesHost>();
+  SpeciesHost& s = *holder;
+  s.d = *d;
+  s.d.q2 = s.d.m2 = s.d.omega_c = s.d.a_c = s.d.nu_per_omega = 0.0;
+  s.cap = std::max<int64_t>(d->capacity, 1);
+  s.nshell = nshell;
+  for (int k = 0; k < nshell; k++) {
+    if (!(shell_m[k] > 0) || shell_q[k] == 0.0 || !std::isfinite(shell_q[k]))
+      return fail(c, PIC_EINVAL, "bad cloud charge or mass");
+    if (!(shell_omega[k] > 0)) return fail(c, PIC_EINVAL, "shell omega_c must be positive");
+    if (std::isnan(shell_ac[k]) || shell_ac[k] < 0)
+      return fail(c, PIC_EINVAL, "shell a_c must be 0 (derived), positive or +inf");
+    s.sq[k] = shell_q[k];
+    s.sm[k] = shell_m[k];
+    s.sw[k] = shell_omega[k];
+    if (shell_ac[k] > 0) {
+      s.sa[k] = shell_ac[k];
+    } else {
+      // as for a two-body ion, with the nucleus-cloud pair's reduced mass
+      if (!(c->cfg.re_norm > 0)) return fail(c, PIC_EINVAL, "a_c = 0 needs re_norm > 0");
+      const double mr = d->m1 * shell_m[k] / (d->m1 + shell_m[k]);
+      s.sa[k] = std::cbrt(std::fabs(d->q1 * shell_q[k]) * c->cfg.re_norm /
+                          (mr * shell_omega[k] * shell_omega[k]));
+    }
+  }
+  size_t rs = c->rsize, n = (size_t)s.cap;
+  s.cell = dev_alloc(c, n * 4);
+  bool ok = s.cell != nullptr;
+  for (int a = 0; a < c->g.nd; a++) ok = ok && (s.off[a] = dev_alloc(c, n * rs));
+  for (int a = 0; a < 3; a++) {
+    ok = ok && (s.u1[a] = dev_alloc(c, n * rs));
+    for (int k = 0; k < nshell; k++) {
+      ok = ok && (s.sdl[k][a] = dev_alloc(c, n * rs));
+      ok = ok && (s.su2[k][a] = dev_alloc(c, n * rs));
+    }
+  }
+  if (c->cfg.flags & PIC_FLAG_TRACK_IDS)
+    ok = ok && (s.ids = static_cast<int64_t*>(dev_alloc(c, n * sizeof(int64_t))));
+  if (!ok) return fail(c, PIC_ENOMEM, "device allocation failed");
+  pic::AllocFn af = [c](size_t b) { return dev_alloc(c, b); };
+  int rc = pic::sort_alloc(c->g, c->ntiles, s.cap, af, s.sort);
+  rc = rc || pic::sort_add_attr(s.sort, &s.cell, 4, af);
+  for (int a = 0; a < c->g.nd && !rc; a++) rc = pic::sort_add_attr(s.sort, &s.off[a], rs, af);
+  for (int a = 0; a < 3 && !rc; a++) {
+    rc = pic::sort_add_attr(s.sort, &s.u1[a], rs, af);
+    for (int k = 0; k < nshell && !rc; k++) {
+      rc = pic::sort_add_attr(s.sort, &s.sdl[k][a], rs, af);
+      if (!rc) rc = pic::sort_add_attr(s.sort, &s.su2[k][a], rs, af);
+    }
+  }
+  if (s.ids && !rc) rc = pic::sort_add_attr(s.sort, reinterpret_cast<void**>(&s.ids), 8, af);
+  if (rc) return fail(c, PIC_ENOMEM, "device allocation failed (sort buffers)");
+  c->sp.push_back(std::move(holder));
+  *sid = (int32_t)(c->sp.size() - 1);
+  return PIC_OK;
+}
+
 int pic_load_particles(pic_ctx* c, int32_t sid, int64_t n, const double* x, const double* delta,
                        const double* u1, const double* u2, const double* omega_c,
                        const double* weight) {
@@ -1005,8 +1220,13 @@ int pic_load_particles(pic_ctx* c, int32_t sid, int64_t n, const double* x, cons
   if (n == 0) return PIC_OK;
   if (omega_c && !own_omega_allowed(s))
     return fail(c, PIC_EINVAL, omega_fixed_msg);
+  if (s.d.kind == PIC_MULTI_SHELL && omega_c)
+    return fail(c, PIC_EINVAL, "the bond frequencies of a multi-shell species are per shell");
   int rc = prepare_optional(c, s, omega_c != nullptr, weight != nullptr);
   if (rc) return rc;
+  if (s.d.kind == PIC_MULTI_SHELL)
+    return c->prec == 32 ? load_shells_t<float>(c, s, n, x, delta, u1, u2, weight)
+                         : load_shells_t<double>(c, s, n, x, delta, u1, u2, weight);
   if (c->prec == 32) return load_particles_t<float>(c, s, n, x, delta, u1, u2, omega_c, weight);
   return load_particles_t<double>(c, s, n, x, delta, u1, u2, omega_c, weight);
 }
@@ -1019,6 +1239,8 @@ int pic_load_particles_device(pic_ctx* c, int32_t sid, int64_t n, const double* 
   if (sid < 0 || sid >= (int32_t)c->sp.size()) return fail(c, PIC_ESTATE, "unknown species");
   if (n < 0 || (n > 0 && (!x || !u1))) return fail(c, PIC_EINVAL, "null particle arrays");
   SpeciesHost& s = *c->sp[sid];
+  if (s.d.kind == PIC_MULTI_SHELL)
+    return fail(c, PIC_EINVAL, "multi-shell species load from host arrays (pic_load_particles)");
   if (s.n + n > s.cap) return fail(c, PIC_ENOMEM, "species capacity exceeded");
   if (n == 0) return PIC_OK;
   if (omega_c && !own_omega_allowed(s))

@@ -13,6 +13,7 @@
 
 #include "pic.h"
 #include "pic_internal.h"
+#include "shells.h"
 #include "sort.h"
 #include "tiled.h"
 
@@ -34,6 +35,13 @@ struct SpeciesHost {
   void* u2[3] = {nullptr, nullptr, nullptr};
   void* wc = nullptr;
   void* w = nullptr;
+  // multi-shell ions: nshell clouds with their own charge, mass, bond
+  // frequency and softening length; d_k and u_k per cloud (dl, u2 unused)
+  int nshell = 0;
+  double sq[pic::kMaxShell] = {}, sm[pic::kMaxShell] = {}, sw[pic::kMaxShell] = {},
+         sa[pic::kMaxShell] = {};
+  void* sdl[pic::kMaxShell][3] = {};
+  void* su2[pic::kMaxShell][3] = {};
   pic::SortBuffers sort{};
   int64_t* ids = nullptr;  // device load indices (TRACK_IDS)
   uint32_t* outside = nullptr;  // particles listed as outside their tile (tiled kernel)
@@ -158,6 +166,56 @@ pic::SpeciesDev<Real> species_dev(const SpeciesHost& s) {
 }
 
 template <typename Real>
+pic::ShellDev<Real> shell_dev(const SpeciesHost& s) {
+  pic::ShellDev<Real> d{};
+  d.cell = static_cast<uint32_t*>(s.cell);
+  for (int a = 0; a < 3; a++) {
+    d.off[a] = static_cast<Real*>(s.off[a]);
+    d.u0[a] = static_cast<Real*>(s.u1[a]);
+    for (int k = 0; k < s.nshell; k++) {
+      d.dl[k][a] = static_cast<Real*>(s.sdl[k][a]);
+      d.uk[k][a] = static_cast<Real*>(s.su2[k][a]);
+    }
+  }
+  d.w = s.has_w ? static_cast<Real*>(s.w) : nullptr;
+  d.n = s.n;
+  return d;
+}
+
+template <typename Real>
+pic::ShellConst<Real> shell_const(const pic_ctx* c, const SpeciesHost& s) {
+  pic::ShellConst<Real> k{};
+  const int K = s.nshell;
+  const double dt = c->cfg.dt, m0 = s.d.m1;
+  double M = m0;
+  for (int j = 0; j < K; j++) M += s.sm[j];
+  auto body = [&](int b, double q, double m) {
+    k.q[b] = (Real)q;
+    k.inv_q[b] = (Real)(1.0 / q);
+    k.m[b] = (Real)m;
+    k.a[b] = (Real)(0.5 * dt * q / m);
+    k.fm[b] = (Real)(m / M);
+    k.qw[b] = (Real)(q * s.d.weight);
+  };
+  body(0, s.d.q1, m0);
+  for (int j = 0; j < K; j++) {
+    body(j + 1, s.sq[j], s.sm[j]);
+    const double mp = m0 + s.sm[j];
+    k.kap[j] = (Real)(m0 * s.sm[j] / mp * s.sw[j] * s.sw[j]);
+    k.iac2[j] = std::isinf(s.sa[j]) ? Real(0) : (Real)(1.0 / (s.sa[j] * s.sa[j]));
+    k.pf0[j] = (Real)(m0 / mp);
+    k.pfk[j] = (Real)(s.sm[j] / mp);
+    k.inv_mp[j] = (Real)(1.0 / mp);
+  }
+  k.inv_M = (Real)(1.0 / M);
+  const double h = 0.5 * dt, nu = s.d.nu;
+  k.D = (Real)((1.0 - nu * h) / (1.0 + nu * h));
+  k.damp = nu > 0.0 ? 1 : 0;
+  k.K = K;
+  return k;
+}
+
+template <typename Real>
 pic::PushConst<Real> push_const(const pic_ctx* c, const SpeciesHost& s) {
   pic::PushConst<Real> k{};
   const pic_species_desc& d = s.d;
@@ -216,6 +274,16 @@ pic::PushConst<Real> push_const(const pic_ctx* c, const SpeciesHost& s) {
   k.two_body = two ? 1 : 0;
   k.deposit = (c->cfg.flags & PIC_FLAG_NO_DEPOSIT) ? 0 : 1;
   return k;
+}
+
+// Charge density of one species' bodies into the FP64 plane `rho`.
+template <typename Real>
+void launch_rho_species(const pic_ctx* c, const SpeciesHost& s, double* rho) {
+  if (s.d.kind == PIC_MULTI_SHELL)
+    pic::launch_rho_shells<Real>(c->g, shell_dev<Real>(s), shell_const<Real>(c, s),
+                                 push_const<Real>(c, s), rho, c->stream);
+  else
+    pic::launch_rho<Real>(c->g, species_dev<Real>(s), push_const<Real>(c, s), rho, c->stream);
 }
 
 // Laser description for the field kernels.

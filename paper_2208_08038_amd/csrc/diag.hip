@@ -177,7 +177,6 @@ __global__ void __launch_bounds__(256) k_rho(GridInfo g, SpeciesDev<Real> s, Pus
     double Q = s.w ? (body == 0 ? (double)c.q1 : (double)c.q2) * W
                    : (body == 0 ? (double)c.qw1 : (double)c.qw2);
     double x[3] = {0, 0, 0};
-    int64_t base = g.origin;
     bool ok = true;
     for (int d = 0; d < ND; d++) {
       double o = s.off[d][p];
@@ -188,37 +187,8 @@ __global__ void __launch_bounds__(256) k_rho(GridInfo g, SpeciesDev<Real> s, Pus
         x[d] = o;
       }
       ok = ok && isfinite(x[d]);
-      if (!ok) break;
-      const double k = floor(x[d]);
-      x[d] -= k;
-      int b = ci[d] + (int)k;
-      if (g.periodic[d]) {
-        b %= g.n[d];
-        if (b < 0) b += g.n[d];
-      }
-      // nodes b - 1 .. b + 2 must lie in the guarded storage
-      ok = ok && b >= -2 && b <= g.n[d];
-      base += (int64_t)b * (d == 0 ? 1 : (d == 1 ? g.sy : g.sz));
     }
-    if (!ok) continue;
-    int i0[3] = {0, 0, 0};
-    double w[3][3] = {{1, 0, 0}, {1, 0, 0}, {1, 0, 0}};
-    for (int d = 0; d < ND; d++) {
-      double f = floor(x[d] + 0.5), dd = x[d] - f;
-      i0[d] = (int)f - 1;
-      w[d][0] = 0.5 * (0.5 - dd) * (0.5 - dd);
-      w[d][1] = 0.75 - dd * dd;
-      w[d][2] = 0.5 * (0.5 + dd) * (0.5 + dd);
-    }
-    int nz = ND > 2 ? 3 : 1, ny = ND > 1 ? 3 : 1;
-    for (int cz = 0; cz < nz; cz++)
-      for (int cy = 0; cy < ny; cy++)
-        for (int cx = 0; cx < 3; cx++) {
-          double wt = w[0][cx] * w[1][cy] * w[2][cz];
-          int64_t o = base + (i0[0] + cx) + (int64_t)(i0[1] + cy) * g.sy +
-                      (int64_t)(i0[2] + cz) * g.sz;
-          if (wt != 0.0) unsafeAtomicAdd(rho + o, Q * wt / dv);
-        }
+    if (ok) rho_add_body<ND>(g, ci, x, Q, dv, rho);
   }
 }
 

@@ -323,6 +323,9 @@ int check_grad_ok(pic_ctx* c) {
   if (c->cfg.flags & (PIC_FLAG_FROZEN_FIELDS | PIC_FLAG_NO_DEPOSIT))
     return fail(c, PIC_EINVAL, "gradient runs need the coupled step (no frozen fields, deposit on)");
   if (c->sp.size() > 64) return fail(c, PIC_EINVAL, "gradient runs support at most 64 species");
+  for (auto& s : c->sp)
+    if (s->d.kind == PIC_MULTI_SHELL)
+      return fail(c, PIC_EINVAL, "gradient runs do not take multi-shell species");
   return PIC_OK;
 }
 

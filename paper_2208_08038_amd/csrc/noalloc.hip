@@ -50,8 +50,7 @@ int rho_static_t(pic_ctx* c, double* rho, double* plane) {
   const GridInfo& g = c->g;
   // a kernel clears the plane (no memset node, should a caller capture this)
   pic::launch_zero<double>(plane, g.plane, c->stream);
-  for (auto& s : c->sp)
-    pic::launch_rho<Real>(g, species_dev<Real>(*s), push_const<Real>(c, *s), plane, c->stream);
+  for (auto& s : c->sp) launch_rho_species<Real>(c, *s, plane);
   pic::launch_fold_periodic_f64(g, plane, c->stream);
   // interior rows straight to the caller's array, one 2D copy per z layer
   const size_t nx = (size_t)g.n[0];

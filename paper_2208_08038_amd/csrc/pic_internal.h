@@ -87,6 +87,46 @@ struct PushConst {
   int deposit;
 };
 
+// Add the charge Q of one body at x (cell units, relative to the cell ci;
+// any distance) to the FP64 density rho at integer nodes with the quadratic
+// B-spline: the body is placed in the frame of the cell that holds it
+// (wrapped along periodic axes; nodes b - 1 .. b + 2 must lie in the guarded
+// storage, else nothing is added).  dv: cell volume.
+template <int ND>
+__device__ __forceinline__ void rho_add_body(const GridInfo& g, const int ci[3], const double xin[3],
+                                             double Q, double dv, double* rho) {
+  double x[3] = {0, 0, 0};
+  int64_t base = g.origin;
+  for (int d = 0; d < ND; d++) {
+    const double k = floor(xin[d]);
+    x[d] = xin[d] - k;
+    int b = ci[d] + (int)k;
+    if (g.periodic[d]) {
+      b %= g.n[d];
+      if (b < 0) b += g.n[d];
+    }
+    if (b < -2 || b > g.n[d]) return;
+    base += (int64_t)b * (d == 0 ? 1 : (d == 1 ? g.sy : g.sz));
+  }
+  int i0[3] = {0, 0, 0};
+  double w[3][3] = {{1, 0, 0}, {1, 0, 0}, {1, 0, 0}};
+  for (int d = 0; d < ND; d++) {
+    double f = floor(x[d] + 0.5), dd = x[d] - f;
+    i0[d] = (int)f - 1;
+    w[d][0] = 0.5 * (0.5 - dd) * (0.5 - dd);
+    w[d][1] = 0.75 - dd * dd;
+    w[d][2] = 0.5 * (0.5 + dd) * (0.5 + dd);
+  }
+  int nz = ND > 2 ? 3 : 1, ny = ND > 1 ? 3 : 1;
+  for (int cz = 0; cz < nz; cz++)
+    for (int cy = 0; cy < ny; cy++)
+      for (int cx = 0; cx < 3; cx++) {
+        double wt = w[0][cx] * w[1][cy] * w[2][cz];
+        int64_t o = base + (i0[0] + cx) + (int64_t)(i0[1] + cy) * g.sy + (int64_t)(i0[2] + cz) * g.sz;
+        if (wt != 0.0) unsafeAtomicAdd(rho + o, Q * wt / dv);
+      }
+}
+
 // x^{4/3} for the softening length of an ion's own omega_c: FP32 through
 // the hardware base-2 logarithm and exponential (about 1 ulp each), FP64 as
 // x * cbrt(x).

@@ -1,0 +1,317 @@
+// shells.hip -- one step of a multi-shell ion (nucleus + K clouds, one bond
+// each): the two-body step of Sec. 2 with a bond per cloud.  One thread per
+// ion from HBM: every body is gathered at its own position in the frame of
+// the cell that holds it, each bond adds +F_k / q0 to the nucleus' field
+// and -F_k / q_k to cloud k's, the optional friction acts on each
+// nucleus-cloud pair in turn (pair momentum kept), every body is
+// Boris-pushed, the centre of mass moves with the mass-weighted velocities
+// and d_k with v0 - v_k, the walls mirror each body, and each body deposits
+// its own Esirkepov current with global atomics.
+#include <hip/hip_runtime.h>
+
+#include "cycle.h"
+#include "shells.h"
+
+namespace pic {
+
+namespace {
+
+template <typename Real, int ND, int K>
+__global__ void __launch_bounds__(256) k_push_shells(GridInfo g, FieldPtrs<Real> f,
+                                                     ShellDev<Real> s, ShellConst<Real> sc,
+                                                     PushConst<Real> c, uint32_t* err) {
+  constexpr int NB = K + 1;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= s.n) return;
+  int ci[3] = {0, 0, 0};
+  decode_cell<ND>(g, s.cell[p], ci);
+  Real off[3] = {0, 0, 0}, dl[K][3], u[NB][3];
+  bool finite = true, inside = true;
+#pragma unroll
+  for (int d = 0; d < ND; d++) {
+    off[d] = s.off[d][p];
+    finite = finite && isfinite(off[d]);
+    inside = inside && off[d] >= Real(0) && off[d] <= Real(1);
+  }
+#pragma unroll
+  for (int q = 0; q < 3; q++) u[0][q] = s.u0[q][p];
+#pragma unroll
+  for (int k = 0; k < K; k++)
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+      dl[k][q] = s.dl[k][q][p];
+      u[k + 1][q] = s.uk[k][q][p];
+    }
+#pragma unroll
+  for (int b = 0; b < NB; b++) finite = finite && finite3(u[b]);
+#pragma unroll
+  for (int k = 0; k < K; k++) finite = finite && finite3(dl[k]);
+  if (!finite || !inside) {
+    atomicOr(err, finite ? PIC_ERR_RANGE : PIC_ERR_NAN);  // left untouched
+    return;
+  }
+  // body positions (cell units, relative to the centre's cell)
+  Real x[NB][3];
+#pragma unroll
+  for (int b = 0; b < NB; b++)
+#pragma unroll
+    for (int d = 0; d < 3; d++) x[b][d] = Real(0);
+#pragma unroll
+  for (int d = 0; d < ND; d++) {
+    Real r0 = off[d];
+#pragma unroll
+    for (int k = 0; k < K; k++) r0 += sc.fm[k + 1] * (dl[k][d] * c.idx[d]);
+    x[0][d] = r0;
+#pragma unroll
+    for (int k = 0; k < K; k++) x[k + 1][d] = r0 - dl[k][d] * c.idx[d];
+  }
+#pragma unroll
+  for (int b = 0; b < NB; b++)
+    if (!body_in_range<Real, ND>(g, ci, x[b])) {
+      atomicOr(err, PIC_ERR_RANGE);
+      return;
+    }
+  const int sy = (int)g.sy, sz = (int)g.sz;
+  int base[NB], kb[NB][3];
+  Real bx[NB][3], E[NB][3], B[NB][3];
+#pragma unroll
+  for (int b = 0; b < NB; b++) {
+    base[b] = body_frame<Real, ND>(g, ci, x[b], bx[b], kb[b]);
+    gather<Real, ND>(f, base[b], sy, sz, bx[b], E[b], B[b]);
+  }
+  // the bonds, as extra fields on the nucleus and on each cloud
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    const Real r2 = dl[k][0] * dl[k][0] + dl[k][1] * dl[k][1] + dl[k][2] * dl[k][2];
+    Real soft = Real(1);
+    if (sc.iac2[k] != Real(0)) {
+      const Real rq = rsqrt1(Real(1) + r2 * sc.iac2[k]);
+      soft = rq * rq * rq;
+    }
+    const Real kf = -sc.kap[k] * soft;
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+      const Real F = kf * dl[k][q];
+      E[0][q] += F * sc.inv_q[0];
+      E[k + 1][q] -= F * sc.inv_q[k + 1];
+    }
+  }
+  Real um[NB][3];
+#pragma unroll
+  for (int b = 0; b < NB; b++)
+#pragma unroll
+    for (int q = 0; q < 3; q++) um[b][q] = u[b][q] + sc.a[b] * E[b][q];
+  if (sc.damp) {
+#pragma unroll
+    for (int k = 0; k < K; k++)
+#pragma unroll
+      for (int q = 0; q < 3; q++) {
+        const Real V = (sc.m[0] * um[0][q] + sc.m[k + 1] * um[k + 1][q]) * sc.inv_mp[k];
+        const Real w = (um[0][q] - um[k + 1][q]) * sc.D;
+        um[0][q] = V + sc.pfk[k] * w;
+        um[k + 1][q] = V - sc.pf0[k] * w;
+      }
+  }
+  Real nw[NB][3], v[NB][3];
+#pragma unroll
+  for (int b = 0; b < NB; b++) {
+    boris_rotate_kick(um[b], sc.a[b], E[b], B[b], nw[b]);
+    const Real ig = rsqrt1(Real(1) + nw[b][0] * nw[b][0] + nw[b][1] * nw[b][1] + nw[b][2] * nw[b][2]);
+#pragma unroll
+    for (int q = 0; q < 3; q++) v[b][q] = nw[b][q] * ig;
+  }
+  // move
+#pragma unroll
+  for (int k = 0; k < K; k++)
+#pragma unroll
+    for (int q = 0; q < 3; q++) dl[k][q] = dl[k][q] + c.dt * (v[0][q] - v[k + 1][q]);
+  Real offn[3] = {0, 0, 0};
+#pragma unroll
+  for (int d = 0; d < ND; d++) {
+    Real P = Real(0);
+#pragma unroll
+    for (int b = 0; b < NB; b++) P += sc.m[b] * v[b][d];
+    offn[d] = off[d] + c.dt * P * sc.inv_M * c.idx[d];
+  }
+  // walls: a body past a wall is mirrored (moved by Dm cells) and its
+  // momentum component reversed; the centre moves by (m_b / M) Dm; the
+  // nucleus' move adds Dm dx to every d_k, cloud k's subtracts it from d_k
+#pragma unroll
+  for (int d = 0; d < ND; d++) {
+    if (g.periodic[d]) continue;
+    const Real lo = Real(g.pad - ci[d]), hi = Real(g.n[d] - g.pad - ci[d]);
+    Real y[NB], Dm[NB];
+    Real y0 = offn[d];
+#pragma unroll
+    for (int k = 0; k < K; k++) y0 += sc.fm[k + 1] * (dl[k][d] * c.idx[d]);
+    y[0] = y0;
+#pragma unroll
+    for (int k = 0; k < K; k++) y[k + 1] = y0 - dl[k][d] * c.idx[d];
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+      Dm[b] = Real(0);
+      if (y[b] < lo)
+        Dm[b] = Real(2) * (lo - y[b]);
+      else if (y[b] > hi)
+        Dm[b] = Real(2) * (hi - y[b]);
+      if (Dm[b] != Real(0)) {
+        nw[b][d] = -nw[b][d];
+        offn[d] += sc.fm[b] * Dm[b];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < K; k++) dl[k][d] += (Dm[0] - Dm[k + 1]) * c.dxs[d];
+  }
+  // new body positions, relative to the centre's old cell
+  Real yb[NB][3];
+#pragma unroll
+  for (int b = 0; b < NB; b++)
+#pragma unroll
+    for (int d = 0; d < 3; d++) yb[b][d] = Real(0);
+#pragma unroll
+  for (int d = 0; d < ND; d++) {
+    Real r0 = offn[d];
+#pragma unroll
+    for (int k = 0; k < K; k++) r0 += sc.fm[k + 1] * (dl[k][d] * c.idx[d]);
+    yb[0][d] = r0;
+#pragma unroll
+    for (int k = 0; k < K; k++) yb[k + 1][d] = r0 - dl[k][d] * c.idx[d];
+  }
+  bool range_ok = true;
+#pragma unroll
+  for (int b = 0; b < NB; b++) range_ok = range_ok && body_in_range<Real, ND>(g, ci, yb[b]);
+  if (c.deposit) {
+    const Real W = s.w ? s.w[p] : Real(0);
+    Real* const J[3] = {f.J[0], f.J[1], f.J[2]};
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+      Real z[3] = {0, 0, 0};
+#pragma unroll
+      for (int d = 0; d < ND; d++) z[d] = yb[b][d] - Real(kb[b][d]);
+      const Real Q = s.w ? sc.q[b] * W : sc.qw[b];
+      range_ok = deposit<Real, ND, true, Real>(J, base[b], sy, sz, bx[b], z, Q, v[b], c) && range_ok;
+    }
+  }
+  int cn[3] = {ci[0], ci[1], ci[2]};
+#pragma unroll
+  for (int d = 0; d < ND; d++) {
+    const int keep = cn[d];
+    Real o = offn[d];
+    if (cross(g.periodic[d], g.n[d], cn[d], o)) {
+      offn[d] = o;
+    } else {
+      cn[d] = keep;
+      range_ok = false;
+    }
+  }
+  if (!range_ok) atomicOr(err, PIC_ERR_RANGE);
+  bool fin = true;
+#pragma unroll
+  for (int b = 0; b < NB; b++) fin = fin && finite3(nw[b]);
+#pragma unroll
+  for (int k = 0; k < K; k++) fin = fin && finite3(dl[k]);
+  if (!fin) atomicOr(err, PIC_ERR_NAN);
+  s.cell[p] = encode_cell<ND>(g, cn);
+#pragma unroll
+  for (int d = 0; d < ND; d++) s.off[d][p] = offn[d];
+#pragma unroll
+  for (int q = 0; q < 3; q++) s.u0[q][p] = nw[0][q];
+#pragma unroll
+  for (int k = 0; k < K; k++)
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+      s.dl[k][q][p] = dl[k][q];
+      s.uk[k][q][p] = nw[k + 1][q];
+    }
+}
+
+template <typename Real, int ND, int K>
+__global__ void __launch_bounds__(256) k_rho_shells(GridInfo g, ShellDev<Real> s,
+                                                    ShellConst<Real> sc, PushConst<Real> c,
+                                                    double* rho) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= s.n) return;
+  int ci[3] = {0, 0, 0};
+  decode_cell<ND>(g, s.cell[p], ci);
+  double dv = 1.0;
+  for (int d = 0; d < ND; d++) dv *= g.dx[d];
+  const double W = s.w ? (double)s.w[p] : 0.0;
+  double x0[3] = {0, 0, 0};
+  bool ok = true;
+  for (int d = 0; d < ND; d++) {
+    x0[d] = (double)s.off[d][p];
+    for (int k = 0; k < K; k++) x0[d] += (double)sc.fm[k + 1] * ((double)s.dl[k][d][p] * (double)c.idx[d]);
+    ok = ok && isfinite(x0[d]);
+  }
+  if (!ok) return;
+  rho_add_body<ND>(g, ci, x0, s.w ? (double)sc.q[0] * W : (double)sc.qw[0], dv, rho);
+  for (int k = 0; k < K; k++) {
+    double x[3] = {0, 0, 0};
+    for (int d = 0; d < ND; d++) x[d] = x0[d] - (double)s.dl[k][d][p] * (double)c.idx[d];
+    rho_add_body<ND>(g, ci, x, s.w ? (double)sc.q[k + 1] * W : (double)sc.qw[k + 1], dv, rho);
+  }
+}
+
+template <typename Real, int ND>
+hipError_t push_nd(const GridInfo& g, const FieldPtrs<Real>& f, const ShellDev<Real>& s,
+                   const ShellConst<Real>& sc, const PushConst<Real>& c, uint32_t* err,
+                   hipStream_t st) {
+  const unsigned nb = (unsigned)((s.n + 255) / 256);
+  switch (sc.K) {
+    case 1: hipLaunchKernelGGL((k_push_shells<Real, ND, 1>), nb, 256, 0, st, g, f, s, sc, c, err); break;
+    case 2: hipLaunchKernelGGL((k_push_shells<Real, ND, 2>), nb, 256, 0, st, g, f, s, sc, c, err); break;
+    case 3: hipLaunchKernelGGL((k_push_shells<Real, ND, 3>), nb, 256, 0, st, g, f, s, sc, c, err); break;
+    case 4: hipLaunchKernelGGL((k_push_shells<Real, ND, 4>), nb, 256, 0, st, g, f, s, sc, c, err); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename Real, int ND>
+void rho_nd(const GridInfo& g, const ShellDev<Real>& s, const ShellConst<Real>& sc,
+            const PushConst<Real>& c, double* rho, hipStream_t st) {
+  const unsigned nb = (unsigned)((s.n + 255) / 256);
+  switch (sc.K) {
+    case 1: hipLaunchKernelGGL((k_rho_shells<Real, ND, 1>), nb, 256, 0, st, g, s, sc, c, rho); break;
+    case 2: hipLaunchKernelGGL((k_rho_shells<Real, ND, 2>), nb, 256, 0, st, g, s, sc, c, rho); break;
+    case 3: hipLaunchKernelGGL((k_rho_shells<Real, ND, 3>), nb, 256, 0, st, g, s, sc, c, rho); break;
+    case 4: hipLaunchKernelGGL((k_rho_shells<Real, ND, 4>), nb, 256, 0, st, g, s, sc, c, rho); break;
+    default: break;
+  }
+}
+
+}  // namespace
+
+template <typename Real>
+hipError_t launch_push_shells(const GridInfo& g, const FieldPtrs<Real>& f, const ShellDev<Real>& s,
+                              const ShellConst<Real>& sc, const PushConst<Real>& c,
+                              uint32_t* err, hipStream_t st) {
+  if (s.n == 0) return hipSuccess;
+  if (g.nd == 1) return push_nd<Real, 1>(g, f, s, sc, c, err, st);
+  if (g.nd == 2) return push_nd<Real, 2>(g, f, s, sc, c, err, st);
+  return push_nd<Real, 3>(g, f, s, sc, c, err, st);
+}
+
+template <typename Real>
+void launch_rho_shells(const GridInfo& g, const ShellDev<Real>& s, const ShellConst<Real>& sc,
+                       const PushConst<Real>& c, double* rho, hipStream_t st) {
+  if (s.n == 0) return;
+  if (g.nd == 1) rho_nd<Real, 1>(g, s, sc, c, rho, st);
+  if (g.nd == 2) rho_nd<Real, 2>(g, s, sc, c, rho, st);
+  if (g.nd == 3) rho_nd<Real, 3>(g, s, sc, c, rho, st);
+}
+
+template hipError_t launch_push_shells<float>(const GridInfo&, const FieldPtrs<float>&,
+                                              const ShellDev<float>&, const ShellConst<float>&,
+                                              const PushConst<float>&, uint32_t*, hipStream_t);
+template hipError_t launch_push_shells<double>(const GridInfo&, const FieldPtrs<double>&,
+                                               const ShellDev<double>&, const ShellConst<double>&,
+                                               const PushConst<double>&, uint32_t*, hipStream_t);
+template void launch_rho_shells<float>(const GridInfo&, const ShellDev<float>&,
+                                       const ShellConst<float>&, const PushConst<float>&, double*,
+                                       hipStream_t);
+template void launch_rho_shells<double>(const GridInfo&, const ShellDev<double>&,
+                                        const ShellConst<double>&, const PushConst<double>&,
+                                        double*, hipStream_t);
+
+}  // namespace pic

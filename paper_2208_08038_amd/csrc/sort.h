@@ -22,7 +22,8 @@
 
 namespace pic {
 
-constexpr int kMaxAttr = 24;
+constexpr int kMaxAttr = 24;      // attributes moved by one gather launch
+constexpr int kMaxSortAttr = 48;  // attributes of one species (gathered in launches of kMaxAttr)
 
 struct SortBuffers {
   uint32_t* key[2] = {nullptr, nullptr};
@@ -33,9 +34,9 @@ struct SortBuffers {
   int64_t ntiles = 0;
   int64_t cap = 0;
   int nattr = 0;
-  void** attr[kMaxAttr] = {};   // pointers to the species' attribute pointers
-  size_t elem[kMaxAttr] = {};   // element sizes
-  void* alt[kMaxAttr] = {};     // alternate buffers
+  void** attr[kMaxSortAttr] = {};   // pointers to the species' attribute pointers
+  size_t elem[kMaxSortAttr] = {};   // element sizes
+  void* alt[kMaxSortAttr] = {};     // alternate buffers
 };
 
 using AllocFn = std::function<void*(size_t)>;

@@ -7,6 +7,8 @@
 // an exclusive scan of the digit-major histogram table, and a stable
 // block scatter in which each wavefront ranks equal digits with ballots.
 // The resulting permutation gathers every attribute array in one kernel.
+#include <algorithm>
+
 #include "sort.h"
 
 namespace pic {
@@ -263,7 +265,7 @@ int sort_alloc(const GridInfo&, const int ntiles[3], int64_t cap, const AllocFn&
 }
 
 int sort_add_attr(SortBuffers& sb, void** ptr, size_t elem, const AllocFn& alloc) {
-  if (sb.nattr >= kMaxAttr) return -1;
+  if (sb.nattr >= kMaxSortAttr) return -1;
   void* a = alloc(sb.cap * elem);
   if (!a) return -1;
   sb.attr[sb.nattr] = ptr;
@@ -327,14 +329,16 @@ int sort_by_tile(const GridInfo& g, const int tile[3], const int ntiles[3], Sort
                      tshift, sb.tile_off);
   if (ic < 0) return hipGetLastError() == hipSuccess ? 0 : -1;  // a single tile: order unchanged
   const uint32_t* perm = sb.idx[ic];
-  GatherSet gs{};
-  gs.n = sb.nattr;
-  for (int a = 0; a < sb.nattr; a++) {
-    gs.src[a] = *sb.attr[a];
-    gs.dst[a] = sb.alt[a];
-    gs.wide[a] = sb.elem[a] == 8;
+  for (int a0 = 0; a0 < sb.nattr; a0 += kMaxAttr) {
+    GatherSet gs{};
+    gs.n = std::min(kMaxAttr, sb.nattr - a0);
+    for (int a = 0; a < gs.n; a++) {
+      gs.src[a] = *sb.attr[a0 + a];
+      gs.dst[a] = sb.alt[a0 + a];
+      gs.wide[a] = sb.elem[a0 + a] == 8;
+    }
+    hipLaunchKernelGGL(k_gather_all, nblk(n, 256), 256, 0, st, gs, perm, n);
   }
-  hipLaunchKernelGGL(k_gather_all, nblk(n, 256), 256, 0, st, gs, perm, n);
   for (int a = 0; a < sb.nattr; a++) {
     void* src = *sb.attr[a];
     *sb.attr[a] = sb.alt[a];

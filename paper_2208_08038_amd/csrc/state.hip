@@ -38,7 +38,7 @@ struct Header {
 };
 
 struct SpeciesRecord {
-  int32_t kind, has_wc, has_w, needs_sort, has_ids, reserved;
+  int32_t kind, has_wc, has_w, needs_sort, has_ids, nshell;
   double q1, m1, q2, m2;
   int64_t n, steps_since_sort, ntiles;
   double max_w, listed_since_sort;
@@ -76,6 +76,7 @@ void pieces_of(pic_ctx* c, std::vector<Piece>& fields, std::vector<SpeciesRecord
     r.has_w = s.has_w;
     r.needs_sort = s.needs_sort;
     r.has_ids = s.ids != nullptr;
+    r.nshell = s.nshell;
     r.q1 = s.d.q1;
     r.m1 = s.d.m1;
     r.q2 = s.d.q2;
@@ -95,6 +96,10 @@ void pieces_of(pic_ctx* c, std::vector<Piece>& fields, std::vector<SpeciesRecord
     if (two) {
       for (int a = 0; a < 3; a++) v.push_back({s.u2[a], n * rs});
       for (int a = 0; a < 3; a++) v.push_back({s.dl[a], n * rs});
+    }
+    for (int k = 0; k < s.nshell; k++) {
+      for (int a = 0; a < 3; a++) v.push_back({s.su2[k][a], n * rs});
+      for (int a = 0; a < 3; a++) v.push_back({s.sdl[k][a], n * rs});
     }
     if (s.has_wc) v.push_back({s.wc, n * rs});
     if (s.has_w) v.push_back({s.w, n * rs});
@@ -196,8 +201,9 @@ int pic_load_state(pic_ctx* c, const void* host_buf, size_t bytes) {
     std::memcpy(&recs[si], in + at, sizeof(SpeciesRecord));
     const SpeciesRecord& r = recs[si];
     SpeciesHost& s = *c->sp[si];
-    if (r.kind != s.d.kind || r.q1 != s.d.q1 || r.m1 != s.d.m1 || r.q2 != s.d.q2 ||
-        r.m2 != s.d.m2)
+    bool same = r.kind == s.d.kind && r.q1 == s.d.q1 && r.m1 == s.d.m1 && r.q2 == s.d.q2 &&
+                r.m2 == s.d.m2 && r.nshell == s.nshell;
+    if (!same)
       return fail(c, PIC_EINVAL, "species " + std::to_string(si) + " differs from the state's");
     if (r.n < 0 || r.n > s.cap)
       return fail(c, PIC_ENOMEM, "species " + std::to_string(si) + " capacity below the state's");
@@ -205,6 +211,7 @@ int pic_load_state(pic_ctx* c, const void* host_buf, size_t bytes) {
       return fail(c, PIC_EINVAL, "tiling or id tracking differs from the state's");
     const bool two = r.kind == PIC_TWO_BODY;
     size_t per = 4 + c->g.nd * c->rsize + 3 * c->rsize + (two ? 6 * c->rsize : 0) +
+                 6 * (size_t)r.nshell * c->rsize +
                  (r.has_wc ? c->rsize : 0) + (r.has_w ? c->rsize : 0) + (r.has_ids ? 8 : 0);
     at += sizeof(SpeciesRecord) + (size_t)r.n * per +
           (r.needs_sort ? 0 : ((size_t)r.ntiles + 1) * 4);

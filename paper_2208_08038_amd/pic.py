@@ -21,6 +21,7 @@ PIC_OK, PIC_EINVAL, PIC_ENOMEM, PIC_EHIP, PIC_ESTATE, PIC_ERANGE, PIC_ENAN = 0, 
 FROZEN_FIELDS, NO_DEPOSIT, CHARGE_CHECK, TRACK_IDS, TIMING, GLOBAL_KERNEL = 1, 2, 4, 8, 16, 32
 SEPARATE_SPECIES = 64
 TIMING_ADJOINT = 65536  # pic_timing tag offset of the adjoint particle kernel
+POINT, TWO_BODY, MULTI_SHELL = 0, 1, 2  # species kinds
 ERR_NAN, ERR_RANGE = 1, 2
 
 _NAMES = {PIC_EINVAL: "PIC_EINVAL", PIC_ENOMEM: "PIC_ENOMEM", PIC_EHIP: "PIC_EHIP",
@@ -83,6 +84,8 @@ class PicGrad(C.Structure):
 SIGNATURES = [
     ("pic_create", C.c_int, [C.POINTER(PicConfig), C.POINTER(PicAllocator), _P, C.POINTER(_P)]),
     ("pic_add_species", C.c_int, [_P, C.POINTER(PicSpeciesDesc), C.POINTER(C.c_int32)]),
+    ("pic_add_multishell", C.c_int, [_P, C.POINTER(PicSpeciesDesc), C.c_int32, _D, _D, _D, _D,
+                                     C.POINTER(C.c_int32)]),
     ("pic_load_particles", C.c_int, [_P, C.c_int32, C.c_int64, _D, _D, _D, _D, _D, _D]),
     ("pic_load_particles_device", C.c_int, [_P, C.c_int32, C.c_int64, _P, _P, _P, _P, _P, _P]),
     ("pic_load_fields", C.c_int, [_P, _D, _D]),
@@ -239,6 +242,16 @@ class Simulation:
 
     # ---------------------------------------------------------------- setup
     def add_species(self, sp, capacity: int) -> int:
+        if int(sp.kind) == MULTI_SHELL:
+            sh = np.asarray(sp.shells, dtype=np.float64).reshape(-1, 4)
+            cols = [np.ascontiguousarray(sh[:, j]) for j in range(4)]
+            d = PicSpeciesDesc(MULTI_SHELL, 0, sp.q1, sp.m1, 0.0, 0.0, sp.weight, 0.0, 0.0, sp.nu,
+                               0.0, int(capacity))
+            sid = C.c_int32()
+            self._check(self.lib.pic_add_multishell(self.ctx, C.byref(d), int(sh.shape[0]),
+                                                    *[_dp(v) for v in cols], C.byref(sid)))
+            self.species.append(sp)
+            return sid.value
         d = PicSpeciesDesc(int(sp.kind), 0, sp.q1, sp.m1, sp.q2, sp.m2, sp.weight, sp.omega_c,
                            sp.a_c if sp.a_c is not None else math.inf, sp.nu, sp.nu_per_omega,
                            int(capacity))
@@ -247,12 +260,17 @@ class Simulation:
         self.species.append(sp)
         return sid.value
 
+    def _nshell(self, sid: int) -> int:
+        sp = self.species[sid]
+        return len(sp.shells) if int(sp.kind) == MULTI_SHELL else 1
+
     def load_particles(self, sid: int, parts) -> None:
         n = parts.n
+        K = self._nshell(sid)
         x = _f64(parts.x, (n, self.ndim))
         u1 = _f64(parts.u1, (n, 3))
-        delta = _f64(parts.delta, (n, 3))
-        u2 = _f64(parts.u2, (n, 3))
+        delta = _f64(parts.delta, (n, 3 * K))
+        u2 = _f64(parts.u2, (n, 3 * K))
         wc = _f64(parts.omega_c, (n,))
         w = _f64(parts.weight, (n,))
         self._check(self.lib.pic_load_particles(self.ctx, sid, n, _dp(x), _dp(delta), _dp(u1),
@@ -339,11 +357,12 @@ class Simulation:
 
     def particles(self, sid: int, ids: bool = False) -> dict:
         n = self.count(sid)
+        K = self._nshell(sid)
         cell = np.zeros((n, 3), dtype=np.int32)
         off = np.zeros((n, 3))
-        delta = np.zeros((n, 3))
+        delta = np.zeros((n, 3 * K))
         u1 = np.zeros((n, 3))
-        u2 = np.zeros((n, 3))
+        u2 = np.zeros((n, 3 * K))
         idv = np.zeros(n, dtype=np.int64) if ids else None
         self._check(self.lib.pic_read_particles(
             self.ctx, sid, cell.ctypes.data_as(C.POINTER(C.c_int32)), _dp(off), _dp(delta),
@@ -358,8 +377,10 @@ class Simulation:
     def particles_range(self, sid: int, start: int, count: int, ids: bool = False) -> dict:
         """Particles start .. start+count-1 in storage order (see
         pic_read_particles_range), with omega_c and weight."""
+        K = self._nshell(sid)
         cell = np.zeros((count, 3), dtype=np.int32)
-        off, delta, u1, u2 = (np.zeros((count, 3)) for _ in range(4))
+        off, u1 = np.zeros((count, 3)), np.zeros((count, 3))
+        delta, u2 = np.zeros((count, 3 * K)), np.zeros((count, 3 * K))
         wc, w = np.zeros(count), np.zeros(count)
         idv = np.zeros(count, dtype=np.int64) if ids else None
         self._check(self.lib.pic_read_particles_range(
