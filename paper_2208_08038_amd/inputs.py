@@ -19,6 +19,7 @@ Workloads (the paper's cases as restated for this project):
   adjoint_slab        2D neutral slab crossed by a spline-envelope pulse (gradient runs)
   bound_slab_1d       medium behind a vacuum gap (Sec. 3.1 observables)
   wakefield_crystal_2d  relativistic pulse in a pre-ionised gold lattice (Sec. 3.2, Fig. 6)
+  multishell_medium_1d  medium of ions with two bound clouds each (linear response)
 """
 from __future__ import annotations
 
@@ -250,6 +251,35 @@ def ionised_medium_1d(cells: int = 2048, ppc: int = 8, steps: int = 1000,
     return Workload("ionised_medium_1d", grid, species, steps, 64,
                     probes=_probe_list(1, 1, list(probes)),
                     notes=f"{ni} cold two-body ions with omega_c in {wc_range} + {ni} electrons")
+
+
+def multishell_medium_1d(cells: int = 2048, ppc: int = 8, steps: int = 1000,
+                         nucleus=(8.0, 20.0), shells=((-5.0, 5.0, 1.6, math.inf),
+                                                      (-3.0, 3.0, 2.4, math.inf)),
+                         density: float = 0.01, nu: float = 0.02, a0: float = 1e-4,
+                         cycles: int = 10, probes=(32, 224), config_id: int = 14) -> Workload:
+    """1D medium of neutral multi-shell ions (a nucleus and two clouds with
+    their own bonds) for the linear-response check of the multi-resonance
+    permittivity: ions at rest, `density` ions per (c/omega)^3 (units of
+    n_c), friction nu on each nucleus-cloud pair, weak plane wave polarised
+    along y entering at x-min, E_y probes at two cells."""
+    dx = TWO_PI / 64.0
+    dt = 0.98 * dx
+    laser = Laser(a0=a0, omega=1.0, t_env=cycles * TWO_PI, pol=1)
+    grid = Grid(1, (cells, 1, 1), (dx, 1.0, 1.0), dt, (LASER, PERIODIC, PERIODIC),
+                (OPEN, PERIODIC, PERIODIC), pad=3, laser=laser, re_norm=1e-3)
+    w = density * dx / ppc
+    sp = Species(MULTI_SHELL, nucleus[0], nucleus[1], weight=w, nu=nu, shells=tuple(shells),
+                 name="two_shell")
+    pad = grid.pad
+    x = stratified_positions(rng_for(config_id, 0), [pad], [cells - pad], ppc, grid.dx, 1)
+    n = x.shape[0]
+    K = len(shells)
+    parts = Particles(x=x, u1=np.zeros((n, 3)), delta=np.zeros((n, 3 * K)),
+                      u2=np.zeros((n, 3 * K)))
+    return Workload("multishell_medium_1d", grid, [(sp, parts)], steps, 64,
+                    probes=_probe_list(1, 1, list(probes)),
+                    notes=f"{n} neutral two-shell ions at rest")
 
 
 def bound_slab_1d(cells: int = 1536, x_cells=(256, 1536), ppc: int = 4, steps: int = 2200,

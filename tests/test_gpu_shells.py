@@ -14,7 +14,7 @@ from _parity import match_by_id, rel_l2, small_grid
 from oracle.oracle import CHARGE_CHECK as O_CHECK
 from oracle.oracle import Oracle
 from paper_2208_08038_amd.inputs import (MULTI_SHELL, OPEN, PERIODIC, POINT, Particles, Species,
-                                         Workload)
+                                         Workload, multishell_medium_1d)
 
 pytestmark = pytest.mark.gpu
 
@@ -200,3 +200,18 @@ def test_shells_refusals(pic):
     with pytest.raises(pic.PicError) as e:
         s.add_species(bad, 10)
     assert e.value.code == pic.PIC_EINVAL
+
+
+def test_multishell_medium_probes_fp64(pic):
+    """The two-shell medium of the permittivity pin on the GPU: its E_y
+    probes follow the oracle's over the whole run (FP64)."""
+    _say("case: multi-shell medium probes")
+    wl = multishell_medium_1d()
+    o = Oracle.from_workload(wl, max_probe_steps=wl.steps)
+    o.step(wl.steps)
+    s = pic.Simulation.from_workload(wl, precision=64, max_probe_steps=wl.steps)
+    s.step(wl.steps)
+    assert s.diagnostics()["error_word"] == 0
+    po, pg = o.probes(), s.probes()
+    assert pg.shape == po.shape
+    assert np.abs(pg - po).max() < 1e-10 * np.abs(po).max()
