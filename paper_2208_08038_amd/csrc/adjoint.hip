@@ -1042,7 +1042,23 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const Planes<Real
         l_n1[d] = -l_n1[d];
       }
       const bool w1 = (walls >> d) & 1u, w2 = (walls >> (4 + d)) & 1u;
-      if (TWO && (w1 || w2)) walls_adjoint(c, d, w1, w2, l_offn[d], l_dln[d], l_n1[d], l_n2[d]);
+      if (TWO && (w1 || w2)) {
+        // FP32 builds inline this (a call would keep a copy of the kernel's
+        // constants in scratch memory for the whole kernel); the FP64 builds
+        // call walls_adjoint, as the compiler's back end rejects the
+        // inlined form there ("operand has incorrect register class")
+        if constexpr (sizeof(Real) == 4) {
+          const Real lR = l_offn[d], ls = l_dln[d] * c.dxs[d];
+          const Real s1 = w1 ? Real(-1) : Real(1), s2 = w2 ? Real(-1) : Real(1);
+          const Real lY1 = s1 * (c.f2 * lR + ls), lY2 = s2 * (c.f1 * lR - ls);
+          l_n1[d] *= s1;
+          l_n2[d] *= s2;
+          l_offn[d] = lY1 + lY2;
+          l_dln[d] = (c.f1 * lY1 - c.f2 * lY2) * c.idx[d];
+        } else {
+          walls_adjoint(c, d, w1, w2, l_offn[d], l_dln[d], l_n1[d], l_n2[d]);
+        }
+      }
     }
     // move
 #pragma unroll
