@@ -88,9 +88,9 @@ typedef enum {
    reaches them, each body of a two-body ion on its own (with its momentum
    component reversed; the centre of mass and delta follow).  The bodies of
    a two-body ion may be any distance apart (Sec. 2: each body has its own
-   position): an ion whose bodies are half a cell or more apart along a
-   resolved axis is advanced from HBM with each body in the frame of the
-   cell that holds it.  The bits stay set until the context is destroyed. */
+   position): an ion with a body outside [-1/2, 3/2) of the cell of its
+   centre of mass (cell units) along a resolved axis is advanced from HBM
+   with each body in the frame of the cell that holds it.  The bits stay set until the context is destroyed. */
 #define PIC_ERR_NAN 1u
 #define PIC_ERR_RANGE 2u
 
@@ -174,9 +174,9 @@ typedef struct {
   int64_t n_particles;
   uint32_t error_word, reserved;
   int64_t n_outside_tile; /* particles of the last step advanced outside their tile */
-  int64_t n_far;          /* two-body ions of the last step whose bodies were half a
-                             cell or more apart (advanced from HBM, each body in the
-                             frame of its own cell) */
+  int64_t n_far;          /* two-body ions of the last step with a body outside
+                             [-1/2, 3/2) of their centre's cell (advanced from HBM,
+                             each body in the frame of its own cell) */
 } pic_diag;
 
 typedef struct pic_ctx pic_ctx;

@@ -619,6 +619,18 @@ __device__ __forceinline__ void boris_rotate_kick(const Real um[3], Real a, cons
 // acts as extra E (+F/q1 on the nucleus, -F/q2 on the cloud); the friction
 // (rate nu + nu_per_omega w_c) is time-centred on the relative momentum
 // between the half kicks and keeps m1 u1 + m2 u2.  n1, n2: new momenta.
+// A body at x (cell units, relative to its ion's cell) in [-1/2, 3/2)
+// along an axis keeps its gather stencils within two nodes of the cell and
+// its deposit window (over a step of less than a cell) within two nodes
+// below and three above: the reach of a tile's field and current patches and
+// of the guard layers.  An ion with both bodies so placed is advanced in the
+// ion's cell frame (the tiled kernel or the HBM pass); bodies farther apart
+// take the far-body path, each in its own cell frame.
+template <typename Real>
+__device__ __forceinline__ bool body_near(Real x) {
+  return x >= Real(-0.5) && x < Real(1.5);
+}
+
 template <typename Real>
 __device__ __forceinline__ void two_body_kick(const PushConst<Real>& c, Real wc, Real iac2,
                                               const Real dl[3], const Real u1[3],
@@ -800,9 +812,9 @@ __device__ __forceinline__ int body_frame(const GridInfo& g, const int ci[3], co
   return (int)base;
 }
 
-// One cycle of a two-body ion whose bodies are half a cell or more apart
-// along a resolved axis (Sec. 2: each body has its own position and
-// momentum).  Each body is gathered and deposited from HBM in the frame of
+// One cycle of a two-body ion with a body outside [-1/2, 3/2) of its
+// centre's cell along a resolved axis (Sec. 2: each body has its own
+// position and momentum).  Each body is gathered and deposited from HBM in the frame of
 // the cell that holds it (guard layers cover a window of any body in an
 // interior cell; global atomics for the current); the centre of mass keeps
 // the cell index, walls and crossing rule of the near path.  x1, x2: body
@@ -938,9 +950,9 @@ __device__ __forceinline__ void advance_particle(const GridInfo& g, const Specie
     inside = inside && (off[d] >= Real(0)) && (off[d] <= Real(1));
     if constexpr (TWO) {
       Real sd = dl[d] * c.idx[d];
-      near = near && (fabs(sd) < Real(0.5));
       x1[d] = off[d] + c.f1 * sd;
       x2[d] = off[d] - c.f2 * sd;
+      near = near && body_near(x1[d]) && body_near(x2[d]);
     } else {
       x1[d] = off[d];
     }
@@ -952,8 +964,9 @@ __device__ __forceinline__ void advance_particle(const GridInfo& g, const Specie
   }
   if constexpr (TWO) {
     if (!near) {
-      // bodies half a cell or more apart: each in its own cell frame, from
-      // HBM (the tiled kernel lists such ions for the HBM pass)
+      // a body beyond the reach of the cell frame: each body in its own
+      // cell frame, from HBM (the tiled kernel lists such ions for the HBM
+      // pass)
       if constexpr (GLOBAL)
         advance_far<Real, ND>(g, s, c, p, st, ci, x1, x2, fg, err);
       else

@@ -129,11 +129,14 @@ __device__ __forceinline__ void tile_particles(const GridInfo& g, const TileSpec
       inside = p < pk;
 #pragma unroll
       for (int d = 0; d < ND; d++) inside = inside && ci[d] >= lo[d] && ci[d] < hi[d];
-      // an ion whose bodies are half a cell or more apart reaches beyond
-      // the tile's patches: the HBM pass takes it
+      // an ion with a body beyond [-1/2, 3/2) of its cell reaches beyond the
+      // tile's patches: the HBM pass takes it (each body in its own frame)
       if constexpr (TWO) {
 #pragma unroll
-        for (int d = 0; d < ND; d++) far = far || !(fabs(st.dl[d] * c.idx[d]) < Real(0.5));
+        for (int d = 0; d < ND; d++) {
+          const Real sd = st.dl[d] * c.idx[d];
+          far = far || !(body_near(st.off[d] + c.f1 * sd) && body_near(st.off[d] - c.f2 * sd));
+        }
       }
     }
     // list the particles outside the tile: one atomic per wavefront
