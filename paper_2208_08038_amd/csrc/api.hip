@@ -522,8 +522,9 @@ int advance_one(pic_ctx* c, const pic::LaserDev& las, const StepOpts& o,
     pic::DispatchHook hook;
     if (c->cfg.flags & PIC_FLAG_TIMING) hook = {&TimedDispatch::hook, &td};
     hipError_t e = pic::launch_push_tiled_pair<Real>(
-        g, f, species_dev<Real>(*si), ci, si->sort.tile_off, si->outside, species_dev<Real>(*se),
-        ce, se->sort.tile_off, se->outside, c->tg, c->nslow, c->nslow + 2 + pi,
+        g, f, species_dev<Real>(*si), ci, si->sort.tile_off, si->outside, si->sort.key[0],
+        species_dev<Real>(*se), ce, se->sort.tile_off, se->outside, c->tg, c->nslow,
+        c->nslow + 2 + pi,
         c->nslow + 2 + pe, c->nfar + pi, c->err, c->stream, hook);
     if (e != hipSuccess)
       return fail(c, PIC_EHIP, std::string("tiled particle kernel: ") + hipGetErrorString(e));
@@ -547,9 +548,9 @@ int advance_one(pic_ctx* c, const pic::LaserDev& las, const StepOpts& o,
       if (c->cfg.flags & PIC_FLAG_TIMING) hook = {&TimedDispatch::hook, &td};
       hipError_t e = pic::launch_push_tiled<Real>(g, f, species_dev<Real>(*s),
                                                   push_const<Real>(c, *s), c->tg,
-                                                  s->sort.tile_off, s->outside, c->nslow,
-                                                  c->nslow + 2 + si, c->nfar + si, c->err,
-                                                  c->stream, hook);
+                                                  s->sort.tile_off, s->outside,
+                                                  s->sort.key[0], c->nslow, c->nslow + 2 + si,
+                                                  c->nfar + si, c->err, c->stream, hook);
       if (e != hipSuccess)
         return fail(c, PIC_EHIP, std::string("tiled particle kernel: ") + hipGetErrorString(e));
     } else {

@@ -26,6 +26,8 @@ constexpr int kMaxAttr = 24;      // attributes moved by one gather launch
 constexpr int kMaxSortAttr = 48;  // attributes of one species (gathered in launches of kMaxAttr)
 
 struct SortBuffers {
+  // key[0] (cap entries) is free between sorts: the tiled kernel keeps the
+  // two-body ions it sets aside there (TileSpecies::defer)
   uint32_t* key[2] = {nullptr, nullptr};
   uint32_t* idx[2] = {nullptr, nullptr};
   uint32_t* hist = nullptr;     // 512 x blocks, digit-major

@@ -96,32 +96,35 @@ struct DispatchHook {
 
 // Launch the 2^ndim colours of the tiled kernel for one species, then the
 // kernel for the particles they listed as outside their tile (or, for
-// two-body ions, with bodies half a cell or more apart).  `list` holds room
-// for every particle of the species; `nlist` is a scratch counter;
-// `nlist_total` accumulates the listed count and `nfar` the ions listed for
-// their separation (diagnostics and the sort policy).
+// two-body ions, with a body beyond [-1/2, 3/2) of its cell).  `list` holds
+// room for every particle of the species; `defer` (two-body species; may
+// be nullptr) likewise, for the ions each tile advances after its others;
+// `nlist` is a scratch counter; `nlist_total` accumulates the listed count
+// and `nfar` the ions listed for their separation (diagnostics and the
+// sort policy).
 template <typename Real>
 hipError_t launch_push_tiled(const GridInfo& g, const FieldPtrs<Real>& f, const SpeciesDev<Real>& s,
                              const PushConst<Real>& c, const TileGeom& t, const uint32_t* tile_off,
-                             uint32_t* list, uint32_t* nlist, uint32_t* nlist_total,
-                             uint32_t* nfar, uint32_t* err, hipStream_t st,
+                             uint32_t* list, uint32_t* defer, uint32_t* nlist,
+                             uint32_t* nlist_total, uint32_t* nfar, uint32_t* err, hipStream_t st,
                              DispatchHook hook = {});
 
 // A two-body species (i) and a point species (e) in one launch per tile
 // colour: each workgroup advances both species' particles of its tile out
 // of one LDS copy of the fields into one current patch (ci and ce must
 // carry the same fixed-point scale), then the outside-tile kernel of each
-// species.  nlist holds two scratch counters; total_i, total_e accumulate
-// the listed counts, nfar_i the ions listed for their separation.  `hook`
-// brackets each shared colour dispatch.
+// species.  defer_i as `defer` above for the ions; nlist holds two scratch
+// counters; total_i, total_e accumulate the listed counts, nfar_i the ions
+// listed for their separation.  `hook` brackets each shared colour
+// dispatch.
 template <typename Real>
 hipError_t launch_push_tiled_pair(const GridInfo& g, const FieldPtrs<Real>& f,
                                   const SpeciesDev<Real>& si, const PushConst<Real>& ci,
                                   const uint32_t* tile_off_i, uint32_t* list_i,
-                                  const SpeciesDev<Real>& se, const PushConst<Real>& ce,
-                                  const uint32_t* tile_off_e, uint32_t* list_e,
-                                  const TileGeom& t, uint32_t* nlist, uint32_t* total_i,
-                                  uint32_t* total_e, uint32_t* nfar_i, uint32_t* err,
-                                  hipStream_t st, DispatchHook hook = {});
+                                  uint32_t* defer_i, const SpeciesDev<Real>& se,
+                                  const PushConst<Real>& ce, const uint32_t* tile_off_e,
+                                  uint32_t* list_e, const TileGeom& t, uint32_t* nlist,
+                                  uint32_t* total_i, uint32_t* total_e, uint32_t* nfar_i,
+                                  uint32_t* err, hipStream_t st, DispatchHook hook = {});
 
 }  // namespace pic

@@ -87,7 +87,28 @@ struct TileSpecies {
   uint32_t* list;
   uint32_t* nlist;
   uint32_t* nfar;  // two-body ions listed because their bodies are far apart
+  // two-body ions whose bodies sit on different stencils are set aside
+  // here (entry k of a tile at defer[p0 + k], p0 the tile's first sorted
+  // particle) and advanced after the others; nullptr: advanced in place
+  uint32_t* defer;
 };
+
+// Field and current patch indices of the node below the cell ci (the
+// patches start two nodes below the tile's first cell lo).
+template <int ND>
+__device__ __forceinline__ void patch_bases(const int ci[3], const int lo[3], int fsy, int fsz,
+                                            int jsy, int jsz, int& lf, int& lj) {
+  lf = ci[0] - lo[0] + 2;
+  lj = lf;
+  if (ND > 1) {
+    lf += (ci[1] - lo[1] + 2) * fsy;
+    lj += (ci[1] - lo[1] + 2) * jsy;
+  }
+  if (ND > 2) {
+    lf += (ci[2] - lo[2] + 2) * fsz;
+    lj += (ci[2] - lo[2] + 2) * jsz;
+  }
+}
 
 // 3. the particles [p0, p1) of one species in the tile; the state of a
 //    thread's next particle is loaded while it advances the present one
@@ -95,6 +116,13 @@ struct TileSpecies {
 //    particles (a tile far more crowded than the mean) the rest is listed
 //    like particles outside the tile, which bounds the number of terms per
 //    patch node.
+//    Two-body ions whose bodies sit on different stencils take the
+//    two-gather path; with sp.defer, a wavefront sets such ions aside and
+//    advances them 64 at a time (all lanes on that path together) instead
+//    of in the wavefront they were read in.  The j-th ion a wavefront sets
+//    aside is kept at the j-th position of the tile range it has read
+//    (position p0 + 64 w + (j / 64) nthr + j % 64 for its wave index w),
+//    which no other wavefront reads or writes.
 template <typename Real, int ND, bool TWO, bool PREFETCH>
 __device__ __forceinline__ void tile_particles(const GridInfo& g, const TileSpecies<Real>& sp,
                                                int64_t p0, int64_t p1, const int lo[3],
@@ -110,20 +138,38 @@ __device__ __forceinline__ void tile_particles(const GridInfo& g, const TileSpec
   const int lane = threadIdx.x & 63;
   const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const int64_t pk = p0 + kChunk;
+  // set-aside slots of this wavefront: slot j at dbase + (j / 64) nthr + j % 64
+  uint32_t* const dbase = TWO && sp.defer ? sp.defer + p0 + (tid - lane) : nullptr;
+  uint32_t dput = 0, dget = 0;  // ions set aside / taken back (same in every lane)
   PState<Real> next;
   if (PREFETCH && p0 + tid < p1) load_state<Real, ND, TWO>(s, c, p0 + tid, next);
-  for (int64_t p0w = p0; p0w < p1; p0w += nthr) {
-    const int64_t p = p0w + tid;
-    const bool valid = p < p1;
+  int64_t p0w = p0;
+  for (;;) {
+    // a full batch of set-aside ions, or the last ones once the range is read
+    const bool batch = TWO && dput > dget && (dput - dget >= 64u || p0w >= p1);
+    if (!batch && p0w >= p1) break;
+    int64_t p;
+    bool valid;
     PState<Real> st;
-    if (PREFETCH) {
-      st = next;
-      if (p + nthr < p1) load_state<Real, ND, TWO>(s, c, p + nthr, next);
-    } else if (valid) {
-      load_state<Real, ND, TWO>(s, c, p, st);
+    if (batch) {
+      const uint32_t j = dget + (uint32_t)lane;
+      valid = j < dput;
+      p = valid ? (int64_t)dbase[(int64_t)(j >> 6) * nthr + (j & 63u)] : p1;
+      if (valid) load_state<Real, ND, TWO>(s, c, p, st);
+      dget = min(dget + 64u, dput);
+    } else {
+      p = p0w + tid;
+      valid = p < p1;
+      if (PREFETCH) {
+        st = next;
+        if (p + nthr < p1) load_state<Real, ND, TWO>(s, c, p + nthr, next);
+      } else if (valid) {
+        load_state<Real, ND, TWO>(s, c, p, st);
+      }
+      p0w += nthr;
     }
     int ci[3] = {0, 0, 0};
-    bool inside = false, far = false;
+    bool inside = false, far = false, split = false;
     if (valid) {
       decode_cell<ND>(g, st.cell, ci);
       inside = p < pk;
@@ -132,14 +178,19 @@ __device__ __forceinline__ void tile_particles(const GridInfo& g, const TileSpec
       // an ion with a body beyond [-1/2, 3/2) of its cell reaches beyond the
       // tile's patches: the HBM pass takes it (each body in its own frame)
       if constexpr (TWO) {
+        Real xa[3] = {0, 0, 0}, xb[3] = {0, 0, 0};
 #pragma unroll
         for (int d = 0; d < ND; d++) {
           const Real sd = st.dl[d] * c.idx[d];
-          far = far || !(body_near(st.off[d] + c.f1 * sd) && body_near(st.off[d] - c.f2 * sd));
+          xa[d] = st.off[d] + c.f1 * sd;
+          xb[d] = st.off[d] - c.f2 * sd;
+          far = far || !(body_near(xa[d]) && body_near(xb[d]));
         }
+        split = !same_stencil<Real, ND>(xa, xb);
       }
     }
-    // list the particles outside the tile: one atomic per wavefront
+    // list the particles outside the tile: one atomic per wavefront (an ion
+    // taken back from the set-aside slots was inside and near when read)
     const bool out = valid && (!inside || far);
     const uint64_t m = __ballot(out);
     if (m) {
@@ -153,17 +204,22 @@ __device__ __forceinline__ void tile_particles(const GridInfo& g, const TileSpec
         if (mf && lane == leader) atomicAdd(sp.nfar, (uint32_t)__popcll(mf));
       }
     }
-    if (valid && inside && !far) {
-      int lf = (ci[0] - lo[0] + 2);
-      int lj = lf;
-      if (ND > 1) {
-        lf += (ci[1] - lo[1] + 2) * fsy;
-        lj += (ci[1] - lo[1] + 2) * jsy;
+    bool go = valid && inside && !far;
+    if constexpr (TWO) {
+      if (dbase && !batch) {
+        const bool aside = go && split;
+        const uint64_t md = __ballot(aside);
+        if (aside) {
+          const uint32_t j = dput + (uint32_t)__popcll(md & below);
+          dbase[(int64_t)(j >> 6) * nthr + (j & 63u)] = (uint32_t)p;
+          go = false;
+        }
+        dput += (uint32_t)__popcll(md);
       }
-      if (ND > 2) {
-        lf += (ci[2] - lo[2] + 2) * fsz;
-        lj += (ci[2] - lo[2] + 2) * jsz;
-      }
+    }
+    if (go) {
+      int lf, lj;
+      patch_bases<ND>(ci, lo, fsy, fsz, jsy, jsz, lf, lj);
       advance_particle<Real, ND, TWO, false, PatchT>(g, s, c, p, st, ci, fl, lf, fsy, fsz, jl,
                                                      lj, jsy, jsz, err, queue);
     }
@@ -564,19 +620,20 @@ static hipError_t launch_colours(const GridInfo& g, const FieldPtrs<Real>& f,
 template <typename Real>
 static TileSpecies<Real> tile_species(const SpeciesDev<Real>& s, const PushConst<Real>& c,
                                       const uint32_t* tile_off, uint32_t* list,
-                                      uint32_t* nlist, uint32_t* nfar) {
-  return TileSpecies<Real>{s, c, tile_off, list, nlist, nfar};
+                                      uint32_t* nlist, uint32_t* nfar, uint32_t* defer) {
+  return TileSpecies<Real>{s, c, tile_off, list, nlist, nfar, c.two_body ? defer : nullptr};
 }
 
 template <typename Real>
 hipError_t launch_push_tiled(const GridInfo& g, const FieldPtrs<Real>& f, const SpeciesDev<Real>& s,
                              const PushConst<Real>& c, const TileGeom& t, const uint32_t* tile_off,
-                             uint32_t* list, uint32_t* nlist, uint32_t* nlist_total,
-                             uint32_t* nfar, uint32_t* err, hipStream_t st, DispatchHook hook) {
+                             uint32_t* list, uint32_t* defer, uint32_t* nlist,
+                             uint32_t* nlist_total, uint32_t* nfar, uint32_t* err, hipStream_t st,
+                             DispatchHook hook) {
   if (s.n == 0) return hipSuccess;
   hipError_t e = hipMemsetAsync(nlist, 0, sizeof(uint32_t), st);
   if (e != hipSuccess) return e;
-  const TileSpecies<Real> a = tile_species(s, c, tile_off, list, nlist, nfar);
+  const TileSpecies<Real> a = tile_species(s, c, tile_off, list, nlist, nfar, defer);
   e = launch_colours<Real, 1>(g, f, a, a, t, err, st, hook);
   if (e != hipSuccess) return e;
   launch_push_list<Real>(g, f, s, c, list, nlist, nlist_total, err, st);
@@ -587,15 +644,16 @@ template <typename Real>
 hipError_t launch_push_tiled_pair(const GridInfo& g, const FieldPtrs<Real>& f,
                                   const SpeciesDev<Real>& si, const PushConst<Real>& ci,
                                   const uint32_t* tile_off_i, uint32_t* list_i,
-                                  const SpeciesDev<Real>& se, const PushConst<Real>& ce,
-                                  const uint32_t* tile_off_e, uint32_t* list_e,
-                                  const TileGeom& t, uint32_t* nlist, uint32_t* total_i,
-                                  uint32_t* total_e, uint32_t* nfar_i, uint32_t* err,
-                                  hipStream_t st, DispatchHook hook) {
+                                  uint32_t* defer_i, const SpeciesDev<Real>& se,
+                                  const PushConst<Real>& ce, const uint32_t* tile_off_e,
+                                  uint32_t* list_e, const TileGeom& t, uint32_t* nlist,
+                                  uint32_t* total_i, uint32_t* total_e, uint32_t* nfar_i,
+                                  uint32_t* err, hipStream_t st, DispatchHook hook) {
   hipError_t e = hipMemsetAsync(nlist, 0, 2 * sizeof(uint32_t), st);
   if (e != hipSuccess) return e;
-  const TileSpecies<Real> a = tile_species(si, ci, tile_off_i, list_i, nlist, nfar_i);
-  const TileSpecies<Real> b = tile_species(se, ce, tile_off_e, list_e, nlist + 1, nfar_i);
+  const TileSpecies<Real> a = tile_species(si, ci, tile_off_i, list_i, nlist, nfar_i, defer_i);
+  const TileSpecies<Real> b =
+      tile_species(se, ce, tile_off_e, list_e, nlist + 1, nfar_i, (uint32_t*)nullptr);
   e = launch_colours<Real, 2>(g, f, a, b, t, err, st, hook);
   if (e != hipSuccess) return e;
   if (si.n > 0) launch_push_list<Real>(g, f, si, ci, list_i, nlist, total_i, err, st);
@@ -607,20 +665,20 @@ template hipError_t launch_push_tiled<float>(const GridInfo&, const FieldPtrs<fl
                                              const SpeciesDev<float>&, const PushConst<float>&,
                                              const TileGeom&, const uint32_t*, uint32_t*,
                                              uint32_t*, uint32_t*, uint32_t*, uint32_t*,
-                                             hipStream_t, DispatchHook);
+                                             uint32_t*, hipStream_t, DispatchHook);
 template hipError_t launch_push_tiled<double>(const GridInfo&, const FieldPtrs<double>&,
                                               const SpeciesDev<double>&, const PushConst<double>&,
                                               const TileGeom&, const uint32_t*, uint32_t*,
                                               uint32_t*, uint32_t*, uint32_t*, uint32_t*,
-                                              hipStream_t, DispatchHook);
+                                              uint32_t*, hipStream_t, DispatchHook);
 template hipError_t launch_push_tiled_pair<float>(
     const GridInfo&, const FieldPtrs<float>&, const SpeciesDev<float>&, const PushConst<float>&,
-    const uint32_t*, uint32_t*, const SpeciesDev<float>&, const PushConst<float>&,
+    const uint32_t*, uint32_t*, uint32_t*, const SpeciesDev<float>&, const PushConst<float>&,
     const uint32_t*, uint32_t*, const TileGeom&, uint32_t*, uint32_t*, uint32_t*, uint32_t*,
     uint32_t*, hipStream_t, DispatchHook);
 template hipError_t launch_push_tiled_pair<double>(
     const GridInfo&, const FieldPtrs<double>&, const SpeciesDev<double>&,
-    const PushConst<double>&, const uint32_t*, uint32_t*, const SpeciesDev<double>&,
+    const PushConst<double>&, const uint32_t*, uint32_t*, uint32_t*, const SpeciesDev<double>&,
     const PushConst<double>&, const uint32_t*, uint32_t*, const TileGeom&, uint32_t*, uint32_t*,
     uint32_t*, uint32_t*, uint32_t*, hipStream_t, DispatchHook);
 
