@@ -772,15 +772,32 @@ __device__ __forceinline__ void load_state(const SpeciesDev<Real>& s, const Push
 // Along an axis with walls each body of an ion stays between the walls
 // `pad` cells inside the faces (they mirror every body that reaches them),
 // where every node its shape reaches is interior.  y: body positions
-// relative to the cell ci.
+// relative to the cell ci.  A mirrored body's position is recomputed from
+// the centre of mass and delta, so it can end a rounding error past the
+// wall (a few units in the last place of the cell-relative position, some
+// 1e-7 cell in FP32); the check allows kWallSlack cells for that (2^-16
+// in FP32, 2^-40 in FP64), far less than moves any node of the shape.
+template <typename Real>
+struct WallSlack;
+template <>
+struct WallSlack<float> {
+  static constexpr float value = 1.0f / 65536.0f;
+};
+template <>
+struct WallSlack<double> {
+  static constexpr double value = 1.0 / 1099511627776.0;  // 2^-40
+};
+
 template <typename Real, int ND>
 __device__ __forceinline__ bool body_in_range(const GridInfo& g, const int ci[3],
                                               const Real y[3]) {
+  constexpr Real kWallSlack = WallSlack<Real>::value;
   bool ok = true;
 #pragma unroll
   for (int d = 0; d < ND; d++) {
     if (g.periodic[d]) continue;
-    ok = ok && y[d] >= Real(g.pad - ci[d]) && y[d] <= Real(g.n[d] - g.pad - ci[d]);
+    ok = ok && y[d] >= Real(g.pad - ci[d]) - kWallSlack &&
+         y[d] <= Real(g.n[d] - g.pad - ci[d]) + kWallSlack;
   }
   return ok;
 }
