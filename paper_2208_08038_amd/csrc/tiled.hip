@@ -242,8 +242,18 @@ __device__ __forceinline__ void tiled_body(const GridInfo& g, const FieldPtrs<Re
   const PushConst<Real>& c = a.c;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   // tile of this block within the colour (from the occupied list in a
-  // sparse launch)
+  // sparse launch).  Workgroups go round-robin over the 8 XCDs (each with
+  // its own L2); consecutive tiles share cache lines of the field and
+  // current planes, so in FP32 each XCD takes a contiguous run of them:
+  // block b takes (b mod 8) B / 8 + min(b mod 8, B mod 8) + b / 8 of B
+  // blocks (a quarter less HBM reading on the 3D slab).  The FP64 build,
+  // with twice the particle bytes per tile, measured faster with tiles in
+  // block order.
   int bi = blockIdx.x;
+  if constexpr (sizeof(Real) == 4) {
+    const int b = blockIdx.x, nb = gridDim.x, x = b & 7;
+    bi = x * (nb >> 3) + min(x, nb & 7) + (b >> 3);
+  }
   if (t.occ) {
     if ((uint32_t)bi >= t.occ[color]) return;
     bi = (int)t.occ[8 + (int64_t)color * ((int64_t)t.nc[0] * t.nc[1] * t.nc[2]) + bi];
