@@ -34,6 +34,8 @@ sys.path.insert(0, ROOT)
 METRIC = "particle-steps/sec (push+gather+deposit) and % HBM roofline, FP32 vs FP64, 1 GPU"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "push_tiled_pair_3d_fp32_traffic.json")
+COUNTERS_FILE = os.path.join(ROOT, "profiles",
+                             "push_tiled_3d_fp32_ionised_slab_256x128x128_counters.txt")
 PAIR_KERNEL = "k_push_tiled_f32<3, true, 2, 4, 8, 8, 6>"
 ION_KERNEL = "k_push_tiled_f32<3, true, 1, 4, 8, 8, 6>"
 
@@ -69,6 +71,32 @@ def measured_traffic(bytes_key, kernel):
             or t.get("kernel") != kernel):
         return None
     return t.get("bytes_per_launch")
+
+
+def measured_limiter():
+    """The issue-rate limiter of the particle kernel from the committed
+    rocprofv3 counter summary, if it was taken on the present kernel source;
+    else None."""
+    from paper_2208_08038_amd.profile_summary import kernel_source_hash
+    try:
+        with open(COUNTERS_FILE) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    if f"# kernel source hash: {kernel_source_hash()}" not in text:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        for key in ("VALU issue", "VALU instructions per pair", "LDS per pair",
+                    "LDS bank-conflict / LDS-active cycles"):
+            if line.strip().startswith(key):
+                vals[key] = float(line.split()[-1])
+    if "VALU issue" not in vals or "VALU instructions per pair" not in vals:
+        return None
+    return (f"VALU issue: {100 * vals['VALU issue']:.0f} % of one wave instruction per CU "
+            f"per clock, {vals['VALU instructions per pair']:.0f} VALU instructions per ion "
+            f"and electron (256x128x128 slab counters, "
+            f"profiles/{os.path.basename(COUNTERS_FILE)})")
 
 
 def copy_calibration(mib):
@@ -699,9 +727,7 @@ def main():
                           f"one of the {ncol} tile-colour dispatches of a step",
                 "launch_ms": r32["dispatch_ms"],
                 "algorithmic_bytes_per_launch": r32["bytes_dispatch"],
-                "limiter": "VALU issue: 75 % busy, ~2810 VALU instructions per ion and "
-                           "electron (profiles/push_tiled_3d_fp32_ionised_slab_256x128x128_"
-                           "counters.txt)"}
+                "limiter": measured_limiter()}
     adj = None if args.no_adjoint else run_adjoint(args)
     configs = None
     if not args.no_configs:
