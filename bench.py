@@ -355,7 +355,7 @@ def run_adjoint(args):
     }
 
 
-def run_config1(args):
+def run_neutral_medium(args):
     """The 1D neutral medium (2048 cells, 16,336 two-body ions, 1000 steps,
     FP64): particle-steps/s over the whole run (cache-resident, launch
     bound: no HBM roofline claim) and the phase-velocity index it measures."""
@@ -386,7 +386,7 @@ def run_config1(args):
             "index_continuum": math.sqrt(1 + 0.81 / 8.0), "error_word": d["error_word"]}
 
 
-def run_config2(args):
+def run_bragg(args):
     """The 2D Bragg case at full size (4096^2 cells, one gold ion per lattice
     site of d = 1.5 lambda in the central 1024^2 cells, 4000 steps) in FP64
     and FP32: Yee cell-steps/s and the angle of the scattered lobe (run with
@@ -400,7 +400,7 @@ def run_config2(args):
     out = {"workload": "bragg_2d", "cells": [4096, 4096]}
     scat = {}
     for prec in (64, 32):
-        wl = bragg_2d(steps=args.config2_steps, precision=prec)
+        wl = bragg_2d(steps=args.bragg_steps, precision=prec)
         n = wl.grid.n[0] * wl.grid.n[1]
         res = {}
         for with_ions in (True, False):
@@ -488,7 +488,7 @@ def run_wakefield(args):
     return out
 
 
-def run_config4(args):
+def run_mixed_precision(args):
     """The mixed-precision case at full size: Bragg geometry in 3D,
     1024 x 1024 x 512 cells, 4 two-body ions per cell in x cells 384..640
     (536,870,912 ions, lattice-modulated weights), 2000 steps, FP32 and FP64
@@ -499,7 +499,7 @@ def run_config4(args):
     from paper_2208_08038_amd import inputs as I
     from paper_2208_08038_amd import pic
     n = (1024, 1024, 512)
-    steps = args.config4_steps
+    steps = args.mixed_precision_steps
     meta = I.mixed_precision_3d(n=n, slab=(384, 385), steps=steps)
     grid, sp = meta.grid, meta.species[0][0]
     total = (640 - 384) * n[1] * n[2] * 4
@@ -521,7 +521,7 @@ def run_config4(args):
             x0, chunk = x1, chunk + 1
         torch.cuda.synchronize()
         t_load = time.perf_counter() - t0
-        print(f"[bench] config4 fp{prec}: loaded {sim.count(sid)} ions in {t_load:.0f} s",
+        print(f"[bench] mixed_precision_3d fp{prec}: loaded {sim.count(sid)} ions in {t_load:.0f} s",
               file=sys.stderr, flush=True)
         eps = 2.0 ** -24 if prec == 32 else 2.0 ** -53
         gross = 4 * wmax * (abs(sp.q1) + abs(sp.q2)) / (dx ** 3 * grid.dt)
@@ -536,7 +536,7 @@ def run_config4(args):
             done += k
             worst_max = max(worst_max, d["div_max"] / gross)
             worst_rms = max(worst_rms, d["div_l2"] / math.sqrt(n[0] * n[1] * n[2]) / gross)
-            print(f"[bench] config4 fp{prec}: step {done}, residual max {d['div_max']:.3e} "
+            print(f"[bench] mixed_precision_3d fp{prec}: step {done}, residual max {d['div_max']:.3e} "
                   f"rms {d['div_l2'] / math.sqrt(n[0] * n[1] * n[2]):.3e}",
                   file=sys.stderr, flush=True)
         ms, nl = sim.timing(reset=True)
@@ -636,17 +636,17 @@ def main():
     ap.add_argument("--no-cells-check", action="store_true",
                     help="skip the FP32-against-FP64 cell-index comparison (reduced slab)")
     ap.add_argument("--no-configs", action="store_true",
-                    help="skip the legs of the 1D neutral medium and the 2D Bragg case")
-    ap.add_argument("--config2-steps", type=int, default=4000)
+                    help="skip the legs of the 1D neutral medium, the 2D Bragg case and the wakefield case")
+    ap.add_argument("--bragg-steps", type=int, default=4000)
     ap.add_argument("--wakefield-steps", type=int, default=4000)
     ap.add_argument("--wakefield", action="store_true",
                     help="run only the relativistic crystal case (FP64 and FP32) and print its JSON")
-    ap.add_argument("--config2", action="store_true",
+    ap.add_argument("--bragg", action="store_true",
                     help="run only the 2D Bragg case (FP64 and FP32) and print its JSON")
-    ap.add_argument("--config4", action="store_true",
+    ap.add_argument("--mixed-precision", action="store_true",
                     help="only run the full-size mixed-precision case (1024 x 1024 x 512, "
                          "536,870,912 ions, FP32 and FP64; several minutes)")
-    ap.add_argument("--config4-steps", type=int, default=2000)
+    ap.add_argument("--mixed-precision-steps", type=int, default=2000)
     ap.add_argument("--copy-calibration", type=float, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient-run leg")
@@ -664,8 +664,8 @@ def main():
               "(the multi-GPU decomposition is a design note, not built)", file=sys.stderr)
         sys.exit(2)
     # the CPU baseline forks its workers before anything touches the GPU
-    only = (args.copy_calibration or args.adjoint_only or args.fp64_only or args.config4
-            or args.config2 or args.wakefield)
+    only = (args.copy_calibration or args.adjoint_only or args.fp64_only or args.mixed_precision
+            or args.bragg or args.wakefield)
     cpu = None
     if not (args.no_cpu_baseline or only):
         cpu = cpu_baseline(args.cpu_seconds, args.cpu_workers)
@@ -682,11 +682,11 @@ def main():
     if args.adjoint_only:
         print(json.dumps({"adjoint": run_adjoint(args)}), flush=True)
         return
-    if args.config4:
-        print(json.dumps({"config4": run_config4(args)}), flush=True)
+    if args.mixed_precision:
+        print(json.dumps({"mixed_precision_3d": run_mixed_precision(args)}), flush=True)
         return
-    if args.config2:
-        print(json.dumps({"config2": run_config2(args)}), flush=True)
+    if args.bragg:
+        print(json.dumps({"bragg_2d": run_bragg(args)}), flush=True)
         return
     if args.wakefield:
         print(json.dumps({"wakefield": run_wakefield(args)}), flush=True)
@@ -731,7 +731,7 @@ def main():
     adj = None if args.no_adjoint else run_adjoint(args)
     configs = None
     if not args.no_configs:
-        configs = {"neutral_medium_1d": run_config1(args), "bragg_2d": run_config2(args),
+        configs = {"neutral_medium_1d": run_neutral_medium(args), "bragg_2d": run_bragg(args),
                    "wakefield_crystal_2d": run_wakefield(args)}
     out = {
         "metric": METRIC, "value": r32["value"], "unit": "particle-steps/s", "n_gpus": 1,

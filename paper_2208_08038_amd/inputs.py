@@ -129,9 +129,9 @@ class Workload:
         return sum(p.n for _, p in self.species)
 
 
-def rng_for(config_id: int, stream: int = 0) -> np.random.Generator:
+def rng_for(case_id: int, stream: int = 0) -> np.random.Generator:
     """Counter-based Philox stream keyed by (seed + config id, stream)."""
-    return np.random.Generator(np.random.Philox(key=[BASE_SEED + config_id, stream]))
+    return np.random.Generator(np.random.Philox(key=[BASE_SEED + case_id, stream]))
 
 
 def gold_ion(z_bound: int, q_c: float):
@@ -194,7 +194,7 @@ def _probe_list(ndim, comp, cells):
 def neutral_medium_1d(cells: int = 2048, ppc: int = 8, steps: int = 1000,
                       omega_c: float = 3.0, omega_pb: float = 0.9, a0: float = 1e-3,
                       t_ev: float = 1.0, cycles: int = 10, a_c: float = 0.0,
-                      probes=(32, 224), config_id: int = 1) -> Workload:
+                      probes=(32, 224), case_id: int = 1) -> Workload:
     dx = TWO_PI / 64.0
     dt = 0.98 * dx
     lam_m = 12.4e-9  # 0.1 keV photons, as in Sec. 3.1
@@ -206,7 +206,7 @@ def neutral_medium_1d(cells: int = 2048, ppc: int = 8, steps: int = 1000,
     n_ion = bound_plasma_density(q1, m1, q2, m2, omega_pb)
     w = n_ion * dx / ppc
     sp = Species(TWO_BODY, q1, m1, q2, m2, weight=w, omega_c=omega_c, a_c=a_c, name="Au_Zb78")
-    rng = rng_for(config_id)
+    rng = rng_for(case_id)
     pad = grid.pad
     x = stratified_positions(rng, [pad], [cells - pad], ppc, grid.dx, 1)
     n = x.shape[0]
@@ -221,7 +221,7 @@ def neutral_medium_1d(cells: int = 2048, ppc: int = 8, steps: int = 1000,
 def ionised_medium_1d(cells: int = 2048, ppc: int = 8, steps: int = 1000,
                       omega_pb: float = 0.9, a0: float = 1e-4, cycles: int = 10,
                       wc_range=(1.5, 4.0), nu_per_omega: float = 0.01,
-                      probes=(32, 224), config_id: int = 13) -> Workload:
+                      probes=(32, 224), case_id: int = 13) -> Workload:
     """1D counterpart of the ionised slab for its linear-response check:
     cold gold ions with one free electron each (q_c = +1), every ion with
     its own omega_c drawn uniformly from wc_range (softening length derived
@@ -239,11 +239,11 @@ def ionised_medium_1d(cells: int = 2048, ppc: int = 8, steps: int = 1000,
     ion = Species(TWO_BODY, q1, m1, q2, m2, weight=w, omega_c=0.5 * sum(wc_range), a_c=0.0,
                   nu_per_omega=nu_per_omega, name="Au_q1_cold")
     pad = grid.pad
-    rng_i = rng_for(config_id, 0)
+    rng_i = rng_for(case_id, 0)
     xi = stratified_positions(rng_i, [pad], [cells - pad], ppc, grid.dx, 1)
     ni = xi.shape[0]
     wci = rng_i.uniform(wc_range[0], wc_range[1], size=ni)
-    rng_e = rng_for(config_id, 1)
+    rng_e = rng_for(case_id, 1)
     xe = stratified_positions(rng_e, [pad], [cells - pad], ppc, grid.dx, 1)
     ele = Species(POINT, -1.0, 1.0, weight=w, name="e_cold")
     species = [(ion, Particles(x=xi, u1=np.zeros((ni, 3)), omega_c=wci)),
@@ -257,7 +257,7 @@ def multishell_medium_1d(cells: int = 2048, ppc: int = 8, steps: int = 1000,
                          nucleus=(8.0, 20.0), shells=((-5.0, 5.0, 1.6, math.inf),
                                                       (-3.0, 3.0, 2.4, math.inf)),
                          density: float = 0.01, nu: float = 0.02, a0: float = 1e-4,
-                         cycles: int = 10, probes=(32, 224), config_id: int = 14) -> Workload:
+                         cycles: int = 10, probes=(32, 224), case_id: int = 14) -> Workload:
     """1D medium of neutral multi-shell ions (a nucleus and two clouds with
     their own bonds) for the linear-response check of the multi-resonance
     permittivity: ions at rest, `density` ions per (c/omega)^3 (units of
@@ -272,7 +272,7 @@ def multishell_medium_1d(cells: int = 2048, ppc: int = 8, steps: int = 1000,
     sp = Species(MULTI_SHELL, nucleus[0], nucleus[1], weight=w, nu=nu, shells=tuple(shells),
                  name="two_shell")
     pad = grid.pad
-    x = stratified_positions(rng_for(config_id, 0), [pad], [cells - pad], ppc, grid.dx, 1)
+    x = stratified_positions(rng_for(case_id, 0), [pad], [cells - pad], ppc, grid.dx, 1)
     n = x.shape[0]
     K = len(shells)
     parts = Particles(x=x, u1=np.zeros((n, 3)), delta=np.zeros((n, 3 * K)),
@@ -284,7 +284,7 @@ def multishell_medium_1d(cells: int = 2048, ppc: int = 8, steps: int = 1000,
 
 def bound_slab_1d(cells: int = 1536, x_cells=(256, 1536), ppc: int = 4, steps: int = 2200,
                   omega_c: float = 3.0, omega_pb: float = 0.9, a0: float = 1e-4,
-                  cycles: int = 10, dx_per_lambda: int = 64, config_id: int = 11) -> Workload:
+                  cycles: int = 10, dx_per_lambda: int = 64, case_id: int = 11) -> Workload:
     """Neutral bound-electron medium filling x_cells (cells) after a vacuum
     gap, for the observables of Sec. 3.1 (group velocity, reflection phase):
     cold two-body gold ions (delta = 0, at rest), plane wave polarised along
@@ -301,7 +301,7 @@ def bound_slab_1d(cells: int = 1536, x_cells=(256, 1536), ppc: int = 4, steps: i
     sp = Species(TWO_BODY, q1, m1, q2, m2, weight=n_ion * dx / ppc, omega_c=omega_c,
                  a_c=math.inf, name="Au_Zb78_cold")
     lo, hi = x_cells[0], min(x_cells[1], cells - grid.pad)
-    x = stratified_positions(rng_for(config_id), [lo], [hi], ppc, grid.dx, 1)
+    x = stratified_positions(rng_for(case_id), [lo], [hi], ppc, grid.dx, 1)
     parts = Particles(x=x, u1=np.zeros((x.shape[0], 3)))
     return Workload("bound_slab_1d", grid, [(sp, parts)], steps, 64,
                     notes=f"medium cells {lo}..{hi}, omega_c={omega_c}, omega_pb={omega_pb}")
@@ -311,7 +311,7 @@ def adjoint_slab(ndim: int = 2, cells=(2048, 1024), slab=(64, 448), probe_x: int
                  ppc: int = 16, steps: int = 1024, omega_c: float = 3.0, omega_pb: float = 0.9,
                  nu: float = 0.03, a_c: float = math.inf, n_env: int = 64, cycles: float = 4.0,
                  a0: float = 1e-4, waist_frac: float = 0.3, dx_per_lambda: int = 32,
-                 config_id: int = 5) -> Workload:
+                 case_id: int = 5) -> Workload:
     """Gradient-run case: a neutral bound-electron slab (cold two-body gold
     ions, Z_b = 78, ppc per cell over x cells slab[0]..slab[1] and every y,
     z) crossed by a pulse from x-min whose temporal envelope is a cubic
@@ -353,7 +353,7 @@ def adjoint_slab(ndim: int = 2, cells=(2048, 1024), slab=(64, 448), probe_x: int
                  a_c=a_c, nu=nu, name="Au_Zb78_cold")
     lo = [slab[0]] + [0] * (ndim - 1)
     hi = [min(slab[1], nx - grid.pad)] + [ny, nz][:ndim - 1]
-    x = stratified_positions(rng_for(config_id), lo, hi, ppc, grid.dx, ndim)
+    x = stratified_positions(rng_for(case_id), lo, hi, ppc, grid.dx, ndim)
     parts = Particles(x=x, u1=np.zeros((x.shape[0], 3)))
     plane = [(j, k) for k in range(nz) for j in range(ny)]
     probes = ([(1, (probe_x, j, k)) for j, k in plane] +
@@ -370,7 +370,7 @@ def adjoint_slab(ndim: int = 2, cells=(2048, 1024), slab=(64, 448), probe_x: int
 def bragg_2d(cells: int = 4096, slab: int = 1024, steps: int = 4000, d_over_lambda: float = 1.5,
              omega_c: float = 0.5, a0: float = 1e-4, cycles: int = 20,
              waist_lambda: float = 12.0, jitter: float = 0.01, precision: int = 64,
-             weight_scale: float = 1.0, config_id: int = 2) -> Workload:
+             weight_scale: float = 1.0, case_id: int = 2) -> Workload:
     dx = TWO_PI / 32.0
     dt = 0.98 * dx / math.sqrt(2.0)
     lam = TWO_PI
@@ -390,7 +390,7 @@ def bragg_2d(cells: int = 4096, slab: int = 1024, steps: int = 4000, d_over_lamb
     # length, i.e. 4 pi re_norm / d in units of n_c (c/omega)^2
     w = weight_scale * 4.0 * math.pi * re_norm / d
     sp = Species(TWO_BODY, q1, m1, q2, m2, weight=w, omega_c=omega_c, a_c=0.0, name="Au_lattice")
-    rng = rng_for(config_id)
+    rng = rng_for(case_id)
     c0 = 0.5 * cells * dx
     half = 0.5 * slab * dx
     m = int(math.ceil(2.0 * half * math.sqrt(2.0) / d)) + 2
@@ -416,7 +416,7 @@ def wakefield_crystal_2d(cells=(4096, 4096), slab=(2048, 1024), steps: int = 400
                          cycles: int = 20, waist_lambda: float = 12.0, free_per_ion: int = 30,
                          z_bound_neutral: int = 78, ppc_e: int = 1, t_e_ev: float = 10.0,
                          jitter: float = 0.01, precision: int = 64,
-                         config_id: int = 6) -> Workload:
+                         case_id: int = 6) -> Workload:
     """The Bragg lattice of bragg_2d, longer along x, pre-ionised with
     `free_per_ion` free electrons per ion, driven by a relativistic pulse
     (a0 = 3): Sec. 3.2, the wakefield paragraph.  Each site's ion keeps
@@ -441,7 +441,7 @@ def wakefield_crystal_2d(cells=(4096, 4096), slab=(2048, 1024), steps: int = 400
     w = 4.0 * math.pi * re_norm / d  # one column of atoms along z per site
     ion = Species(TWO_BODY, q1, m1, q2, m2, weight=w, omega_c=omega_c, a_c=0.0,
                   name="Au_preionised")
-    rng = rng_for(config_id, 0)
+    rng = rng_for(case_id, 0)
     cx, cy = 0.5 * nx * dx, 0.5 * ny * dx
     hx, hy = 0.5 * slab[0] * dx, 0.5 * slab[1] * dx
     m = int(math.ceil(2.0 * max(hx, hy) * math.sqrt(2.0) / d)) + 2
@@ -457,7 +457,7 @@ def wakefield_crystal_2d(cells=(4096, 4096), slab=(2048, 1024), steps: int = 400
     xs = xs + rng.normal(0.0, jitter * d, n_ion)
     ys = ys + rng.normal(0.0, jitter * d, n_ion)
     ions = Particles(x=np.stack([xs, ys], axis=1), u1=np.zeros((n_ion, 3)))
-    rng_e = rng_for(config_id, 1)
+    rng_e = rng_for(case_id, 1)
     lo = [int(round((cx - hx) / dx)), int(round((cy - hy) / dx))]
     hi = [lo[0] + slab[0], lo[1] + slab[1]]
     xe = stratified_positions(rng_e, lo, hi, ppc_e, grid.dx, 2)
@@ -478,7 +478,7 @@ def ionised_slab_3d(n=(512, 256, 256), ppc: int = 8, steps: int = 500, precision
                     omega_pb: float = 0.9, a0: float = 0.05, waist_lambda: float = 8.0,
                     cycles: int = 10, wc_range=(1.5, 4.0), nu_per_omega: float = 0.01,
                     t_ion_ev: float = 1.0, t_e_ev: float = 10.0, electrons: bool = True,
-                    x_cells=None, chunk: int = 0, config_id: int = 3) -> Workload:
+                    x_cells=None, chunk: int = 0, case_id: int = 3) -> Workload:
     """Medium filling the box between the particle walls.  x_cells = (lo, hi)
     restricts the generated particles to those x planes (chunked loading of
     the full-size case); each chunk draws from its own Philox streams."""
@@ -500,7 +500,7 @@ def ionised_slab_3d(n=(512, 256, 256), ppc: int = 8, steps: int = 500, precision
     xlo, xhi = (grid.pad, n[0] - grid.pad) if x_cells is None else x_cells
     lo = [xlo, 0, 0]
     hi = [xhi, ny, nz]
-    rng_i = rng_for(config_id, 2 * chunk)
+    rng_i = rng_for(case_id, 2 * chunk)
     xi = stratified_positions(rng_i, lo, hi, ppc, grid.dx, 3)
     ni = xi.shape[0]
     uci = rng_i.normal(0.0, thermal_sigma(t_ion_ev, m1 + m2), size=(ni, 3))
@@ -508,7 +508,7 @@ def ionised_slab_3d(n=(512, 256, 256), ppc: int = 8, steps: int = 500, precision
     species = [(ion, Particles(x=xi, u1=uci, omega_c=wci))]
     if electrons:
         ele = Species(POINT, -1.0, 1.0, weight=w, name="e")
-        rng_e = rng_for(config_id, 2 * chunk + 1)
+        rng_e = rng_for(case_id, 2 * chunk + 1)
         xe = stratified_positions(rng_e, lo, hi, ppc, grid.dx, 3)
         ue = rng_e.normal(0.0, thermal_sigma(t_e_ev, 1.0), size=(xe.shape[0], 3))
         species.append((ele, Particles(x=xe, u1=ue)))
@@ -536,7 +536,7 @@ def lattice_site_mean(sigma):
 def mixed_precision_3d(n=(1024, 1024, 512), slab=(384, 640), ppc: int = 4, steps: int = 2000,
                        omega_c: float = 0.5, d_over_lambda: float = 1.5, sigma_site: float = 0.1,
                        a0: float = 1e-4, cycles: int = 20, precision: int = 32,
-                       config_id: int = 4) -> Workload:
+                       case_id: int = 4) -> Workload:
     dx = TWO_PI / 32.0
     dt = 0.98 * dx / math.sqrt(3.0)
     lam = TWO_PI
@@ -556,7 +556,7 @@ def mixed_precision_3d(n=(1024, 1024, 512), slab=(384, 640), ppc: int = 4, steps
     dv = dx ** 3
     sp = Species(TWO_BODY, q1, m1, q2, m2, weight=n_mean * dv / ppc, omega_c=omega_c, a_c=0.0,
                  name="Au_lattice3d")
-    rng = rng_for(config_id)
+    rng = rng_for(case_id)
     lo = [max(slab[0], grid.pad), 0, 0]
     hi = [min(slab[1], n[0] - grid.pad), n[1], n[2]]
     x = stratified_positions(rng, lo, hi, ppc, grid.dx, 3)
@@ -588,7 +588,7 @@ WORKLOADS = {
 def ionised_slab_3d_device_chunk(n=(512, 256, 256), ppc: int = 8, x_cells=(3, 35),
                                  chunk: int = 0, device="cuda", wc_range=(1.5, 4.0),
                                  t_ion_ev: float = 1.0, t_e_ev: float = 10.0,
-                                 config_id: int = 3):
+                                 case_id: int = 3):
     """Same recipe as ionised_slab_3d for the x planes x_cells, drawn with
     torch's Philox generator on the GPU (seed = base seed + config id, offset
     by the chunk), returned as FP64 device tensors:
@@ -601,7 +601,7 @@ def ionised_slab_3d_device_chunk(n=(512, 256, 256), ppc: int = 8, x_cells=(3, 35
     out = []
     for sp in range(2):
         g = torch.Generator(device=device)
-        g.manual_seed((BASE_SEED + config_id) * 1000003 + 2 * chunk + sp)
+        g.manual_seed((BASE_SEED + case_id) * 1000003 + 2 * chunk + sp)
         nxc = x_cells[1] - x_cells[0]
         m = nxc * ny * nz * ppc
         p = torch.arange(m, device=device, dtype=torch.int64)
@@ -632,7 +632,7 @@ def ionised_slab_3d_device_chunk(n=(512, 256, 256), ppc: int = 8, x_cells=(3, 35
 
 def mixed_precision_3d_device_chunk(n=(1024, 1024, 512), ppc: int = 4, x_cells=(384, 400),
                                     chunk: int = 0, device="cuda", d_over_lambda: float = 1.5,
-                                    sigma_site: float = 0.1, config_id: int = 4):
+                                    sigma_site: float = 0.1, case_id: int = 4):
     """Same recipe as mixed_precision_3d for the x planes x_cells, drawn with
     torch's Philox generator on the GPU (seed = base seed + config id, offset
     by the chunk), as FP64 device tensors (x, weight / species weight),
@@ -645,7 +645,7 @@ def mixed_precision_3d_device_chunk(n=(1024, 1024, 512), ppc: int = 4, x_cells=(
     theta_b = math.asin(lam / (2.0 * d))
     ny, nz = n[1], n[2]
     g = torch.Generator(device=device)
-    g.manual_seed((BASE_SEED + config_id) * 1000003 + chunk)
+    g.manual_seed((BASE_SEED + case_id) * 1000003 + chunk)
     nxc = x_cells[1] - x_cells[0]
     m = nxc * ny * nz * ppc
     p = torch.arange(m, device=device, dtype=torch.int64)
