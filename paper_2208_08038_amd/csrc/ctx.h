@@ -282,6 +282,14 @@ void launch_rho_species(const pic_ctx* c, const SpeciesHost& s, double* rho) {
   if (s.d.kind == PIC_MULTI_SHELL)
     pic::launch_rho_shells<Real>(c->g, shell_dev<Real>(s), shell_const<Real>(c, s),
                                  push_const<Real>(c, s), rho, c->stream);
+  else if (c->tiled && !s.needs_sort && s.sort.tile_off)
+    // sorted by tile: one LDS patch per tile (the offsets describe the
+    // storage order until the next sort, wherever the particles moved)
+    pic::launch_rho_tiled<Real>(c->g, species_dev<Real>(s), push_const<Real>(c, s),
+                                s.sort.tile_off,
+                                pic::RhoTiles{{c->tile[0], c->tile[1], c->tile[2]},
+                                              {c->ntiles[0], c->ntiles[1], c->ntiles[2]}},
+                                rho, c->stream);
   else
     pic::launch_rho<Real>(c->g, species_dev<Real>(s), push_const<Real>(c, s), rho, c->stream);
 }

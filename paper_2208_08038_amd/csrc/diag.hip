@@ -192,6 +192,101 @@ __global__ void __launch_bounds__(256) k_rho(GridInfo g, SpeciesDev<Real> s, Pus
   }
 }
 
+// Charge density of a tile-sorted species: one workgroup per tile adds the
+// bodies of its sorted range into an FP64 LDS patch covering the tile's
+// cells with two nodes around them (the nodes of every body in its cell
+// and of any body within one cell of it), then adds each non-zero patch
+// node to the plane with one global atomic.  A body whose nodes leave the
+// patch (a particle that drifted since the sort, a far body) or the
+// guarded plane's interior [-2, n + 1] goes straight to the plane as in
+// k_rho.  Same sum as k_rho up to the order of the FP64 adds.
+template <typename Real, int ND>
+__global__ void __launch_bounds__(256) k_rho_tiled(GridInfo g, SpeciesDev<Real> s,
+                                                   PushConst<Real> c, const uint32_t* tile_off,
+                                                   RhoTiles t, double* rho) {
+  extern __shared__ double patch[];
+  const int64_t tile = blockIdx.x;
+  const int64_t p0 = tile_off[tile], p1 = tile_off[tile + 1];
+  if (p0 == p1) return;  // the whole block leaves before any barrier
+  int lo[3] = {0, 0, 0}, P[3] = {1, 1, 1};
+  int64_t r = tile;
+  for (int d = 0; d < ND; d++) {
+    const int tc = (int)(r % t.nt[d]);
+    r /= t.nt[d];
+    lo[d] = tc * t.T[d] - 2;
+    P[d] = t.T[d] + 4;
+  }
+  const int np = P[0] * P[1] * P[2];
+  for (int q = threadIdx.x; q < np; q += blockDim.x) patch[q] = 0.0;
+  __syncthreads();
+  double dv = 1.0;
+  for (int d = 0; d < ND; d++) dv *= g.dx[d];
+  const int nb = c.two_body ? 2 : 1;
+  for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+    const uint32_t packed = s.cell[p];
+    int ci[3];
+    ci[0] = packed & ((1u << g.bits[0]) - 1u);
+    ci[1] = ND > 1 ? (packed >> g.bits[0]) & ((1u << g.bits[1]) - 1u) : 0;
+    ci[2] = ND > 2 ? (packed >> (g.bits[0] + g.bits[1])) : 0;
+    const double W = s.w ? (double)s.w[p] : 1.0;
+    for (int body = 0; body < nb; body++) {
+      const double Q = s.w ? (body == 0 ? (double)c.q1 : (double)c.q2) * W
+                           : (body == 0 ? (double)c.qw1 : (double)c.qw2);
+      double x[3] = {0, 0, 0};
+      bool ok = true;
+      for (int d = 0; d < ND; d++) {
+        const double o = s.off[d][p];
+        if (c.two_body) {
+          const double sd = (double)s.dl[d][p] * (double)c.idx[d];
+          x[d] = body == 0 ? o + (double)c.f1 * sd : o - (double)c.f2 * sd;
+        } else {
+          x[d] = o;
+        }
+        ok = ok && isfinite(x[d]);
+      }
+      if (!ok) continue;
+      // first of the three nodes along each axis (unwrapped node index),
+      // its index in the patch, and the weights
+      int a[3] = {0, 0, 0};
+      double w[3][3] = {{1, 0, 0}, {1, 0, 0}, {1, 0, 0}};
+      bool in = true;
+      for (int d = 0; d < ND; d++) {
+        const double k = floor(x[d]);
+        const double xf = x[d] - k;
+        const double f = floor(xf + 0.5), dd = xf - f;
+        const int n0 = ci[d] + (int)k + (int)f - 1;
+        a[d] = n0 - lo[d];
+        in = in && a[d] >= 0 && a[d] + 2 < P[d] && n0 >= -2 && n0 + 2 <= g.n[d] + 1;
+        w[d][0] = 0.5 * (0.5 - dd) * (0.5 - dd);
+        w[d][1] = 0.75 - dd * dd;
+        w[d][2] = 0.5 * (0.5 + dd) * (0.5 + dd);
+      }
+      if (!in) {
+        rho_add_body<ND>(g, ci, x, Q, dv, rho);
+        continue;
+      }
+      const double qv = Q / dv;
+      const int nz = ND > 2 ? 3 : 1, ny = ND > 1 ? 3 : 1;
+      for (int cz = 0; cz < nz; cz++)
+        for (int cy = 0; cy < ny; cy++)
+          for (int cx = 0; cx < 3; cx++) {
+            const double wt = w[0][cx] * w[1][cy] * w[2][cz];
+            const int q = (a[0] + cx) + P[0] * ((a[1] + cy) + P[1] * (a[2] + cz));
+            if (wt != 0.0) atomicAdd(patch + q, qv * wt);
+          }
+    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < np; q += blockDim.x) {
+    const double v = patch[q];
+    if (v == 0.0) continue;
+    const int i = lo[0] + q % P[0];
+    const int j = lo[1] + (q / P[0]) % P[1];
+    const int k = lo[2] + q / (P[0] * P[1]);
+    unsafeAtomicAdd(rho + g.origin + i + (int64_t)j * g.sy + (int64_t)k * g.sz, v);
+  }
+}
+
 // residual (rho1 - rho0)/dt + div J at every interior node
 template <typename Real>
 __global__ void __launch_bounds__(RB) k_residual(GridInfo g, FieldPtrs<Real> f, const double* rho0,
@@ -275,6 +370,27 @@ void launch_rho(const GridInfo& g, const SpeciesDev<Real>& s, const PushConst<Re
 }
 
 template <typename Real>
+void launch_rho_tiled(const GridInfo& g, const SpeciesDev<Real>& s, const PushConst<Real>& c,
+                      const uint32_t* tile_off, const RhoTiles& t, double* rho, hipStream_t st) {
+  if (s.n == 0) return;
+  int64_t ntiles = 1;
+  size_t lds = sizeof(double);
+  for (int d = 0; d < g.nd; d++) {
+    ntiles *= t.nt[d];
+    lds *= (size_t)(t.T[d] + 4);
+  }
+  if (g.nd == 1)
+    hipLaunchKernelGGL((k_rho_tiled<Real, 1>), dim3((unsigned)ntiles), 256, lds, st, g, s, c,
+                       tile_off, t, rho);
+  if (g.nd == 2)
+    hipLaunchKernelGGL((k_rho_tiled<Real, 2>), dim3((unsigned)ntiles), 256, lds, st, g, s, c,
+                       tile_off, t, rho);
+  if (g.nd == 3)
+    hipLaunchKernelGGL((k_rho_tiled<Real, 3>), dim3((unsigned)ntiles), 256, lds, st, g, s, c,
+                       tile_off, t, rho);
+}
+
+template <typename Real>
 void launch_residual(const GridInfo& g, const FieldPtrs<Real>& f, const double* rho0,
                      const double* rho1, double* partials, int nb, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_residual<Real>, nb, RB, 0, st, g, f, rho0, rho1, partials);
@@ -288,6 +404,8 @@ void launch_residual(const GridInfo& g, const FieldPtrs<Real>& f, const double* 
                                   double*, hipStream_t);                                        \
   template void launch_rho<R>(const GridInfo&, const SpeciesDev<R>&, const PushConst<R>&,       \
                               double*, hipStream_t);                                            \
+  template void launch_rho_tiled<R>(const GridInfo&, const SpeciesDev<R>&, const PushConst<R>&, \
+                                    const uint32_t*, const RhoTiles&, double*, hipStream_t);    \
   template void launch_residual<R>(const GridInfo&, const FieldPtrs<R>&, const double*,         \
                                    const double*, double*, int, double*, hipStream_t);
 

@@ -273,6 +273,19 @@ template <typename Real>
 void launch_rho(const GridInfo& g, const SpeciesDev<Real>& s, const PushConst<Real>& c,
                 double* rho, hipStream_t st);
 
+// Tile shape (cells) and tiles per dimension of a tile-sorted species.
+struct RhoTiles {
+  int T[3];
+  int nt[3];
+};
+
+// The charge density of launch_rho for a species sorted by tile (tile_off:
+// the ntiles + 1 offsets of its sorted order); one workgroup per tile with
+// an FP64 LDS patch of (T + 4) nodes per resolved dimension.
+template <typename Real>
+void launch_rho_tiled(const GridInfo& g, const SpeciesDev<Real>& s, const PushConst<Real>& c,
+                      const uint32_t* tile_off, const RhoTiles& t, double* rho, hipStream_t st);
+
 void launch_fold_periodic_f64(const GridInfo& g, double* rho, hipStream_t st);
 
 // FP64 compensated reductions; each writes its results into out[] (device)

@@ -92,6 +92,30 @@ def _compare(o, s, wl, tol, exact_cells=True):
             assert err < tol, f"{k}: relative error {err:.3e}"
 
 
+# ------------------------------------------------ charge density
+
+@pytest.mark.parametrize("ndim,bc", [(1, PERIODIC), (2, OPEN), (3, PERIODIC), (3, OPEN)])
+def test_rho_matches_the_oracle(pic, ndim, bc):
+    """pic_rho against the oracle's density (FP64): right after the load
+    (the particles not yet sorted by tile: one thread per particle) and
+    after six coupled steps (sorted: one LDS patch per tile, with bodies up
+    to 2.5 cells apart and particles that drifted since the sort adding
+    straight to the plane); pic_rho_static gives the same array."""
+    _say(f"case: rho ndim={ndim} bc={bc}")
+    wl = far_workload(ndim, 300, 300, 870 + ndim, bc=bc)
+    o, s = _both(wl, pic, 64)
+    ref0, got0 = o.rho(), s.rho()
+    scale = np.abs(ref0).max()
+    assert np.abs(got0 - ref0).max() < 1e-12 * scale
+    o.step(6)
+    s.step(6)
+    assert s.diagnostics()["error_word"] == 0
+    ref, got = o.rho(), s.rho()
+    assert np.abs(got - ref).max() < 1e-12 * scale
+    assert np.abs(s.rho_static() - got).max() < 1e-13 * scale
+    assert np.abs(got - ref0).max() > 1e-6 * scale  # the charges moved
+
+
 # ------------------------------------------------ separated bodies
 
 @pytest.mark.parametrize("ndim,bc", [(1, PERIODIC), (2, PERIODIC), (3, PERIODIC), (2, OPEN),
