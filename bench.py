@@ -488,6 +488,59 @@ def run_wakefield(args):
     return out
 
 
+def run_multishell(args):
+    """Multi-shell ions (Sec. 4's several bound components; a nucleus and two
+    clouds) at 256 x 128 x 128 cells, 2 ions per cell (8,192,000 ions,
+    24,576,000 bodies), FP32 and FP64: the run rate and the multi-shell
+    kernel's HIP-event time per step against its algorithmic bytes (per ion
+    the packed cell, offsets, the nucleus momentum and each cloud's
+    displacement and momentum, read and written once; per cell E and B read
+    and J written), and FP32 against FP64 fields at the end."""
+    import torch
+    from paper_2208_08038_amd import pic
+    from paper_2208_08038_amd.inputs import multishell_slab_3d
+    n = (256, 128, 128)
+    steps = args.multishell_steps
+    out = {"workload": "multishell_slab_3d", "cells": list(n), "shells": 2, "steps": steps}
+    fields = {}
+    for prec in (32, 64):
+        wl = multishell_slab_3d(n=n, steps=steps, precision=prec)
+        K = len(wl.species[0][0].shells)
+        sim = pic.Simulation.from_workload(wl, precision=prec, flags=pic.TIMING)
+        nion = sim.count(0)
+        sim.step(5)
+        torch.cuda.synchronize()
+        sim.timing(reset=True)
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ms, nl = sim.timing(species=0, reset=True)
+        rs = 4 if prec == 32 else 8
+        per_ion = 2 * (4 + 3 * rs + 3 * rs + K * 6 * rs)
+        ncell = n[0] * n[1] * n[2]
+        nbytes = nion * per_ion + ncell * 9 * rs
+        launch_ms = ms / max(nl, 1)
+        d = sim.diagnostics()
+        out[f"fp{prec}"] = {
+            "ions": nion, "ms_per_step": 1e3 * dt / steps,
+            "value": nion * steps / dt, "unit": "ion-steps/s",
+            "kernel": f"k_push_shells<{'float' if prec == 32 else 'double'}, 3, {K}>",
+            "launch_ms": launch_ms, "algorithmic_bytes_per_launch": nbytes,
+            "achieved_gbs": nbytes / (launch_ms * 1e-3) / 1e9 if launch_ms > 0 else None,
+            "frac_hbm": nbytes / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if launch_ms > 0 else None,
+            "error_word": d["error_word"], "field_energy": d["field_energy"]}
+        fields[prec] = sim.fields()[0]
+        print(f"[bench] multishell fp{prec}: {steps} steps {dt:.1f} s", file=sys.stderr,
+              flush=True)
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    out["fp32_vs_fp64_e_rel_l2"] = float(np.linalg.norm(fields[32] - fields[64]) /
+                                         max(np.linalg.norm(fields[64]), 1e-300))
+    return out
+
+
 def run_mixed_precision(args):
     """The mixed-precision case at full size: Bragg geometry in 3D,
     1024 x 1024 x 512 cells, 4 two-body ions per cell in x cells 384..640
@@ -647,6 +700,9 @@ def main():
                     help="only run the full-size mixed-precision case (1024 x 1024 x 512, "
                          "536,870,912 ions, FP32 and FP64; several minutes)")
     ap.add_argument("--mixed-precision-steps", type=int, default=2000)
+    ap.add_argument("--multishell", action="store_true",
+                    help="run only the 3D multi-shell medium (FP32 and FP64) and print its JSON")
+    ap.add_argument("--multishell-steps", type=int, default=60)
     ap.add_argument("--copy-calibration", type=float, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient-run leg")
@@ -665,7 +721,7 @@ def main():
         sys.exit(2)
     # the CPU baseline forks its workers before anything touches the GPU
     only = (args.copy_calibration or args.adjoint_only or args.fp64_only or args.mixed_precision
-            or args.bragg or args.wakefield)
+            or args.bragg or args.wakefield or args.multishell)
     cpu = None
     if not (args.no_cpu_baseline or only):
         cpu = cpu_baseline(args.cpu_seconds, args.cpu_workers)
@@ -684,6 +740,9 @@ def main():
         return
     if args.mixed_precision:
         print(json.dumps({"mixed_precision_3d": run_mixed_precision(args)}), flush=True)
+        return
+    if args.multishell:
+        print(json.dumps({"multishell_slab_3d": run_multishell(args)}), flush=True)
         return
     if args.bragg:
         print(json.dumps({"bragg_2d": run_bragg(args)}), flush=True)
@@ -732,6 +791,7 @@ def main():
     configs = None
     if not args.no_configs:
         configs = {"neutral_medium_1d": run_neutral_medium(args), "bragg_2d": run_bragg(args),
+                   "multishell_slab_3d": run_multishell(args),
                    "wakefield_crystal_2d": run_wakefield(args)}
     out = {
         "metric": METRIC, "value": r32["value"], "unit": "particle-steps/s", "n_gpus": 1,

@@ -287,7 +287,7 @@ void launch_rho_species(const pic_ctx* c, const SpeciesHost& s, double* rho) {
     // storage order until the next sort, wherever the particles moved)
     pic::launch_rho_tiled<Real>(c->g, species_dev<Real>(s), push_const<Real>(c, s),
                                 s.sort.tile_off,
-                                pic::RhoTiles{{c->tile[0], c->tile[1], c->tile[2]},
+                                pic::TileGrid{{c->tile[0], c->tile[1], c->tile[2]},
                                               {c->ntiles[0], c->ntiles[1], c->ntiles[2]}},
                                 rho, c->stream);
   else

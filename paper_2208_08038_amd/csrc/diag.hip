@@ -203,7 +203,7 @@ __global__ void __launch_bounds__(256) k_rho(GridInfo g, SpeciesDev<Real> s, Pus
 template <typename Real, int ND>
 __global__ void __launch_bounds__(256) k_rho_tiled(GridInfo g, SpeciesDev<Real> s,
                                                    PushConst<Real> c, const uint32_t* tile_off,
-                                                   RhoTiles t, double* rho) {
+                                                   TileGrid t, double* rho) {
   extern __shared__ double patch[];
   const int64_t tile = blockIdx.x;
   const int64_t p0 = tile_off[tile], p1 = tile_off[tile + 1];
@@ -371,7 +371,7 @@ void launch_rho(const GridInfo& g, const SpeciesDev<Real>& s, const PushConst<Re
 
 template <typename Real>
 void launch_rho_tiled(const GridInfo& g, const SpeciesDev<Real>& s, const PushConst<Real>& c,
-                      const uint32_t* tile_off, const RhoTiles& t, double* rho, hipStream_t st) {
+                      const uint32_t* tile_off, const TileGrid& t, double* rho, hipStream_t st) {
   if (s.n == 0) return;
   int64_t ntiles = 1;
   size_t lds = sizeof(double);
@@ -405,7 +405,7 @@ void launch_residual(const GridInfo& g, const FieldPtrs<Real>& f, const double* 
   template void launch_rho<R>(const GridInfo&, const SpeciesDev<R>&, const PushConst<R>&,       \
                               double*, hipStream_t);                                            \
   template void launch_rho_tiled<R>(const GridInfo&, const SpeciesDev<R>&, const PushConst<R>&, \
-                                    const uint32_t*, const RhoTiles&, double*, hipStream_t);    \
+                                    const uint32_t*, const TileGrid&, double*, hipStream_t);    \
   template void launch_residual<R>(const GridInfo&, const FieldPtrs<R>&, const double*,         \
                                    const double*, double*, int, double*, hipStream_t);
 

@@ -274,7 +274,7 @@ void launch_rho(const GridInfo& g, const SpeciesDev<Real>& s, const PushConst<Re
                 double* rho, hipStream_t st);
 
 // Tile shape (cells) and tiles per dimension of a tile-sorted species.
-struct RhoTiles {
+struct TileGrid {
   int T[3];
   int nt[3];
 };
@@ -284,7 +284,7 @@ struct RhoTiles {
 // an FP64 LDS patch of (T + 4) nodes per resolved dimension.
 template <typename Real>
 void launch_rho_tiled(const GridInfo& g, const SpeciesDev<Real>& s, const PushConst<Real>& c,
-                      const uint32_t* tile_off, const RhoTiles& t, double* rho, hipStream_t st);
+                      const uint32_t* tile_off, const TileGrid& t, double* rho, hipStream_t st);
 
 void launch_fold_periodic_f64(const GridInfo& g, double* rho, hipStream_t st);
 

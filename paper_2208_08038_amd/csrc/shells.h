@@ -4,7 +4,7 @@
 // extension the paper's summary names: the bound electrons of an ion in
 // several components).  Stored as the centre of mass of all bodies (cell +
 // offset), the nucleus momentum u0, and per cloud d_k = r_nucleus - r_k and
-// its momentum u_k; advanced from HBM, one thread per ion.
+// its momentum u_k; one thread per ion.
 #pragma once
 
 #include "pic_internal.h"
@@ -46,6 +46,16 @@ template <typename Real>
 hipError_t launch_push_shells(const GridInfo& g, const FieldPtrs<Real>& f, const ShellDev<Real>& s,
                               const ShellConst<Real>& sc, const PushConst<Real>& c,
                               uint32_t* err, hipStream_t st);
+
+// The same step for a species sorted by tile (tile_off: the ntiles + 1
+// offsets of its sorted order): one workgroup per tile, with an LDS
+// current patch for the bodies whose frame cell lies in the tile
+// (instantiated for FP32 work).
+template <typename Real>
+hipError_t launch_push_shells_tiled(const GridInfo& g, const FieldPtrs<Real>& f,
+                                    const ShellDev<Real>& s, const ShellConst<Real>& sc,
+                                    const PushConst<Real>& c, const uint32_t* tile_off,
+                                    const TileGrid& t, uint32_t* err, hipStream_t st);
 
 // charge density of every body (FP64 plane with guards, as launch_rho)
 template <typename Real>

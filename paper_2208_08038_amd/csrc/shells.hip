@@ -6,7 +6,11 @@
 // nucleus-cloud pair in turn (pair momentum kept), every body is
 // Boris-pushed, the centre of mass moves with the mass-weighted velocities
 // and d_k with v0 - v_k, the walls mirror each body, and each body deposits
-// its own Esirkepov current with global atomics.
+// its own Esirkepov current.  In FP32 a species sorted by tile is advanced
+// one workgroup per tile: a body whose frame cell lies in the tile deposits
+// into an FP64 LDS patch of the tile (its whole window lies there), added
+// to the current planes with one global atomic per node; other bodies, an
+// unsorted species and FP64 work deposit with global atomics.
 #include <hip/hip_runtime.h>
 
 #include "cycle.h"
@@ -16,13 +20,53 @@ namespace pic {
 
 namespace {
 
-template <typename Real, int ND, int K>
-__global__ void __launch_bounds__(256) k_push_shells(GridInfo g, FieldPtrs<Real> f,
-                                                     ShellDev<Real> s, ShellConst<Real> sc,
-                                                     PushConst<Real> c, uint32_t* err) {
+// Deposits of the global kernel: every body with global atomics.
+template <typename Real, int ND>
+struct GlobalDeposit {
+  Real* J[3];
+  int sy, sz;
+  __device__ __forceinline__ bool operator()(int base, const Real x0[3], const Real x1[3], Real Q,
+                                             const Real v[3], const int[3], const int[3],
+                                             const PushConst<Real>& c) const {
+    return deposit<Real, ND, true, Real>(J, base, sy, sz, x0, x1, Q, v, c);
+  }
+};
+
+// Deposits of the tiled kernel: a body whose frame cell (the centre's cell
+// ci shifted by k, unwrapped) lies in the tile's cells [lo, hi) adds into
+// the LDS patch, whose nodes run from lo - 2 to hi + 2 (the deposit window
+// of a body reaches two nodes below its cell and three above); any other
+// body adds to the planes with global atomics.
+template <typename Real, int ND>
+struct TileDeposit {
+  Real* J[3];
+  int sy, sz;
+  double* P[3];
+  int psy, psz;
+  int lo[3], hi[3];
+  __device__ __forceinline__ bool operator()(int base, const Real x0[3], const Real x1[3], Real Q,
+                                             const Real v[3], const int ci[3], const int k[3],
+                                             const PushConst<Real>& c) const {
+    bool in = true;
+    int jb = 0;
+#pragma unroll
+    for (int d = 0; d < ND; d++) {
+      const int cb = ci[d] + k[d];
+      in = in && cb >= lo[d] && cb < hi[d];
+      jb += (cb - lo[d] + 2) * (d == 0 ? 1 : (d == 1 ? psy : psz));
+    }
+    if (in) return deposit<Real, ND, false, double>(P, jb, psy, psz, x0, x1, Q, v, c);
+    return deposit<Real, ND, true, Real>(J, base, sy, sz, x0, x1, Q, v, c);
+  }
+};
+
+// The step of ion p; `dep` deposits each body's current.
+template <typename Real, int ND, int K, typename Dep>
+__device__ __forceinline__ void shell_ion(const GridInfo& g, const FieldPtrs<Real>& f,
+                                          const ShellDev<Real>& s, const ShellConst<Real>& sc,
+                                          const PushConst<Real>& c, uint32_t* err, int64_t p,
+                                          const Dep& dep) {
   constexpr int NB = K + 1;
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= s.n) return;
   int ci[3] = {0, 0, 0};
   decode_cell<ND>(g, s.cell[p], ci);
   Real off[3] = {0, 0, 0}, dl[K][3], u[NB][3];
@@ -182,14 +226,13 @@ __global__ void __launch_bounds__(256) k_push_shells(GridInfo g, FieldPtrs<Real>
   for (int b = 0; b < NB; b++) range_ok = range_ok && body_in_range<Real, ND>(g, ci, yb[b]);
   if (c.deposit) {
     const Real W = s.w ? s.w[p] : Real(0);
-    Real* const J[3] = {f.J[0], f.J[1], f.J[2]};
 #pragma unroll
     for (int b = 0; b < NB; b++) {
       Real z[3] = {0, 0, 0};
 #pragma unroll
       for (int d = 0; d < ND; d++) z[d] = yb[b][d] - Real(kb[b][d]);
       const Real Q = s.w ? sc.q[b] * W : sc.qw[b];
-      range_ok = deposit<Real, ND, true, Real>(J, base[b], sy, sz, bx[b], z, Q, v[b], c) && range_ok;
+      range_ok = dep(base[b], bx[b], z, Q, v[b], ci, kb[b], c) && range_ok;
     }
   }
   int cn[3] = {ci[0], ci[1], ci[2]};
@@ -223,6 +266,82 @@ __global__ void __launch_bounds__(256) k_push_shells(GridInfo g, FieldPtrs<Real>
       s.dl[k][q][p] = dl[k][q];
       s.uk[k][q][p] = nw[k + 1][q];
     }
+}
+
+template <typename Real, int ND, int K>
+__global__ void __launch_bounds__(256) k_push_shells(GridInfo g, FieldPtrs<Real> f,
+                                                     ShellDev<Real> s, ShellConst<Real> sc,
+                                                     PushConst<Real> c, uint32_t* err) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= s.n) return;
+  const GlobalDeposit<Real, ND> dep{{f.J[0], f.J[1], f.J[2]}, (int)g.sy, (int)g.sz};
+  shell_ion<Real, ND, K>(g, f, s, sc, c, err, p, dep);
+}
+
+// One workgroup per tile of the sorted order: its ions, with the LDS
+// current patch of the tile (three FP64 component blocks of (T + 5) nodes
+// per resolved dimension), then each non-zero patch node added to the
+// planes with one global atomic.
+template <typename Real, int ND, int K>
+__global__ void __launch_bounds__(256) k_push_shells_tiled(GridInfo g, FieldPtrs<Real> f,
+                                                           ShellDev<Real> s, ShellConst<Real> sc,
+                                                           PushConst<Real> c,
+                                                           const uint32_t* tile_off, TileGrid t,
+                                                           uint32_t* err) {
+  extern __shared__ double shell_patch[];
+  const int64_t tile = blockIdx.x;
+  const int64_t p0 = tile_off[tile], p1 = tile_off[tile + 1];
+  if (p0 == p1) return;  // the whole block leaves before any barrier
+  TileDeposit<Real, ND> dep;
+  int P[3] = {1, 1, 1};
+  int64_t r = tile;
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    dep.lo[d] = 0;
+    dep.hi[d] = 1;
+    if (d < ND) {
+      const int tc = (int)(r % t.nt[d]);
+      r /= t.nt[d];
+      dep.lo[d] = tc * t.T[d];
+      dep.hi[d] = min(dep.lo[d] + t.T[d], g.n[d]);
+      P[d] = t.T[d] + 5;
+    }
+  }
+  const int np = P[0] * P[1] * P[2];
+  dep.psy = P[0];
+  dep.psz = P[0] * P[1];
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    dep.J[a] = f.J[a];
+    dep.P[a] = shell_patch + (int64_t)a * np;
+  }
+  dep.sy = (int)g.sy;
+  dep.sz = (int)g.sz;
+  for (int q = threadIdx.x; q < 3 * np; q += blockDim.x) shell_patch[q] = 0.0;
+  __syncthreads();
+  for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x)
+    shell_ion<Real, ND, K>(g, f, s, sc, c, err, p, dep);
+  __syncthreads();
+  for (int q = threadIdx.x; q < np; q += blockDim.x) {
+    // patch node q is grid node lo - 2 + its position (the planes' guards
+    // reach 3 nodes out; nodes beyond are never written)
+    int gi[3] = {0, 0, 0};
+    int rem = q;
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < ND; d++) {
+      gi[d] = dep.lo[d] - 2 + rem % P[d];
+      rem /= P[d];
+      ok = ok && gi[d] >= -kGuard && gi[d] < g.n[d] + kGuard;
+    }
+    if (!ok) continue;
+    const int64_t gix = g.origin + gi[0] + (int64_t)gi[1] * g.sy + (int64_t)gi[2] * g.sz;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      const double v = dep.P[a][q];
+      if (v != 0.0) unsafeAtomicAdd(f.J[a] + gix, (Real)v);
+    }
+  }
 }
 
 template <typename Real, int ND, int K>
@@ -268,6 +387,29 @@ hipError_t push_nd(const GridInfo& g, const FieldPtrs<Real>& f, const ShellDev<R
 }
 
 template <typename Real, int ND>
+hipError_t push_tiled_nd(const GridInfo& g, const FieldPtrs<Real>& f, const ShellDev<Real>& s,
+                         const ShellConst<Real>& sc, const PushConst<Real>& c,
+                         const uint32_t* tile_off, const TileGrid& t, uint32_t* err,
+                         hipStream_t st) {
+  int64_t ntiles = 1;
+  size_t lds = 3 * sizeof(double);
+  for (int d = 0; d < ND; d++) {
+    ntiles *= t.nt[d];
+    lds *= (size_t)(t.T[d] + 5);
+  }
+  if (lds > 64 * 1024) return hipErrorInvalidValue;
+  const dim3 nb((unsigned)ntiles);
+  switch (sc.K) {
+    case 1: hipLaunchKernelGGL((k_push_shells_tiled<Real, ND, 1>), nb, 256, lds, st, g, f, s, sc, c, tile_off, t, err); break;
+    case 2: hipLaunchKernelGGL((k_push_shells_tiled<Real, ND, 2>), nb, 256, lds, st, g, f, s, sc, c, tile_off, t, err); break;
+    case 3: hipLaunchKernelGGL((k_push_shells_tiled<Real, ND, 3>), nb, 256, lds, st, g, f, s, sc, c, tile_off, t, err); break;
+    case 4: hipLaunchKernelGGL((k_push_shells_tiled<Real, ND, 4>), nb, 256, lds, st, g, f, s, sc, c, tile_off, t, err); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename Real, int ND>
 void rho_nd(const GridInfo& g, const ShellDev<Real>& s, const ShellConst<Real>& sc,
             const PushConst<Real>& c, double* rho, hipStream_t st) {
   const unsigned nb = (unsigned)((s.n + 255) / 256);
@@ -293,6 +435,17 @@ hipError_t launch_push_shells(const GridInfo& g, const FieldPtrs<Real>& f, const
 }
 
 template <typename Real>
+hipError_t launch_push_shells_tiled(const GridInfo& g, const FieldPtrs<Real>& f,
+                                    const ShellDev<Real>& s, const ShellConst<Real>& sc,
+                                    const PushConst<Real>& c, const uint32_t* tile_off,
+                                    const TileGrid& t, uint32_t* err, hipStream_t st) {
+  if (s.n == 0) return hipSuccess;
+  if (g.nd == 1) return push_tiled_nd<Real, 1>(g, f, s, sc, c, tile_off, t, err, st);
+  if (g.nd == 2) return push_tiled_nd<Real, 2>(g, f, s, sc, c, tile_off, t, err, st);
+  return push_tiled_nd<Real, 3>(g, f, s, sc, c, tile_off, t, err, st);
+}
+
+template <typename Real>
 void launch_rho_shells(const GridInfo& g, const ShellDev<Real>& s, const ShellConst<Real>& sc,
                        const PushConst<Real>& c, double* rho, hipStream_t st) {
   if (s.n == 0) return;
@@ -307,6 +460,11 @@ template hipError_t launch_push_shells<float>(const GridInfo&, const FieldPtrs<f
 template hipError_t launch_push_shells<double>(const GridInfo&, const FieldPtrs<double>&,
                                                const ShellDev<double>&, const ShellConst<double>&,
                                                const PushConst<double>&, uint32_t*, hipStream_t);
+template hipError_t launch_push_shells_tiled<float>(const GridInfo&, const FieldPtrs<float>&,
+                                                    const ShellDev<float>&,
+                                                    const ShellConst<float>&,
+                                                    const PushConst<float>&, const uint32_t*,
+                                                    const TileGrid&, uint32_t*, hipStream_t);
 template void launch_rho_shells<float>(const GridInfo&, const ShellDev<float>&,
                                        const ShellConst<float>&, const PushConst<float>&, double*,
                                        hipStream_t);

@@ -20,6 +20,7 @@ Workloads (the paper's cases as restated for this project):
   bound_slab_1d       medium behind a vacuum gap (Sec. 3.1 observables)
   wakefield_crystal_2d  relativistic pulse in a pre-ionised gold lattice (Sec. 3.2, Fig. 6)
   multishell_medium_1d  medium of ions with two bound clouds each (linear response)
+  multishell_slab_3d    3D medium of two-cloud ions (throughput of the multi-shell kernel)
 """
 from __future__ import annotations
 
@@ -130,7 +131,7 @@ class Workload:
 
 
 def rng_for(case_id: int, stream: int = 0) -> np.random.Generator:
-    """Counter-based Philox stream keyed by (seed + config id, stream)."""
+    """Counter-based Philox stream keyed by (seed + case id, stream)."""
     return np.random.Generator(np.random.Philox(key=[BASE_SEED + case_id, stream]))
 
 
@@ -280,6 +281,40 @@ def multishell_medium_1d(cells: int = 2048, ppc: int = 8, steps: int = 1000,
     return Workload("multishell_medium_1d", grid, [(sp, parts)], steps, 64,
                     probes=_probe_list(1, 1, list(probes)),
                     notes=f"{n} neutral two-shell ions at rest")
+
+
+def multishell_slab_3d(n=(256, 128, 128), ppc: int = 2, steps: int = 60,
+                       nucleus=(26.0, 55.845 * 1822.888), shells=((-8.0, 8.0, 3.0, 0.0),
+                                                                 (-18.0, 18.0, 1.2, 0.0)),
+                       density: float = 0.01, nu: float = 0.01, a0: float = 1e-3,
+                       waist_lambda: float = 8.0, cycles: int = 10, precision: int = 32,
+                       case_id: int = 15) -> Workload:
+    """Medium of neutral multi-shell ions filling the box between the
+    particle walls (the throughput case of the multi-shell kernel): an
+    iron-like nucleus with two bound clouds (8 and 18 electrons, restoring
+    frequencies 3 and 1.2, softening lengths derived from them), `ppc` ions
+    per cell at rest, `density` ions per (c/omega)^3, friction nu on each
+    nucleus-cloud pair; Gaussian laser a0 through x-min, periodic y and z."""
+    dx = TWO_PI / 24.0
+    dt = 0.98 * dx / math.sqrt(3.0)
+    lam_m = 12.4e-9
+    laser = Laser(a0=a0, omega=1.0, t_env=cycles * TWO_PI, waist=waist_lambda * TWO_PI,
+                  yc=0.5 * n[1] * dx, zc=0.5 * n[2] * dx, pol=1)
+    grid = Grid(3, tuple(n), (dx, dx, dx), dt, (LASER, PERIODIC, PERIODIC),
+                (OPEN, PERIODIC, PERIODIC), pad=3, laser=laser,
+                re_norm=TWO_PI * R_E_M / lam_m)
+    w = density * dx ** 3 / ppc
+    sp = Species(MULTI_SHELL, nucleus[0], nucleus[1], weight=w, nu=nu, shells=tuple(shells),
+                 name="two_shell_3d")
+    rng = rng_for(case_id, 0)
+    x = stratified_positions(rng, [grid.pad, 0, 0], [n[0] - grid.pad, n[1], n[2]], ppc,
+                             grid.dx, 3)
+    m = x.shape[0]
+    K = len(shells)
+    parts = Particles(x=x, u1=np.zeros((m, 3)), delta=np.zeros((m, 3 * K)),
+                      u2=np.zeros((m, 3 * K)))
+    return Workload("multishell_slab_3d", grid, [(sp, parts)], steps, precision,
+                    notes=f"{m} neutral two-shell ions at rest")
 
 
 def bound_slab_1d(cells: int = 1536, x_cells=(256, 1536), ppc: int = 4, steps: int = 2200,

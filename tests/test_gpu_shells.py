@@ -106,6 +106,25 @@ def test_shells_coupled_fp64(pic, ndim, bc):
     assert np.abs(np.array(dg["momentum"]) - pm).max() <= 1e-12 * np.abs(pm).max()
 
 
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_shells_tiled_fp32_far_clouds(pic, ndim):
+    """FP32 (one workgroup per tile with an LDS current patch once sorted)
+    against the FP64 oracle with clouds up to 2.5 smallest cell widths from
+    their nucleus on a periodic grid of several tiles: bodies in the tile's cells deposit
+    into the patch, bodies in other tiles or across a periodic face go to
+    the planes directly."""
+    _say(f"case: shells tiled fp32 far ndim={ndim}")
+    wl = shell_workload(ndim, 80, 40, seed=130 + ndim, K=2, spread=2.5)
+    o, s = _run_both(pic, wl, 32, 10)
+    assert s.diagnostics()["error_word"] == 0
+    Eo, Bo, Jo = o.fields()
+    Eg, Bg, Jg = s.fields()
+    errs = (rel_l2(Eg, Eo), rel_l2(Bg, Bo), rel_l2(Jg, Jo))
+    _say(f"fp32 tiled far ndim={ndim}: E {errs[0]:.2e} B {errs[1]:.2e} J {errs[2]:.2e}")
+    assert max(errs) < 2e-5
+    _compare(o, s, wl, 5e-5, exact_cells=False)
+
+
 @pytest.mark.parametrize("K", [1, 2, 4])
 def test_shells_count_fp32(pic, K):
     """FP32 against the FP64 oracle for 1, 2 and 4 clouds (2D, open faces)."""
