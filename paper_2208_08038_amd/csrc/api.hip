@@ -536,25 +536,19 @@ int advance_one(pic_ctx* c, const pic::LaserDev& las, const StepOpts& o,
     auto& s = c->sp[si];
     TimedDispatch td{c, (int)si, false};
     if (s->d.kind == PIC_MULTI_SHELL) {
-      // multi-shell ions: one thread per ion; in FP32 one workgroup per
-      // tile once the species is sorted by tile (LDS current patch per tile;
-      // the 3D two-cloud medium measured 4.68 -> 3.72 ms per step, while the
-      // FP64 build, which spills registers, measured 14.9 -> 16.7 ms)
+      // multi-shell ions: one thread per ion; once the species is sorted by
+      // tile, one workgroup per tile with an LDS current patch (the 3D
+      // two-cloud medium: FP32 3.72 -> 2.76 ms per step, FP64 6.75 -> 4.55)
       TimedDispatch::hook(&td, true);
-      hipError_t e = hipSuccess;
-      bool tiled_shells = false;
-      if constexpr (sizeof(Real) == 4) {
-        if (c->tiled && !s->needs_sort && s->sort.tile_off) {
-          e = pic::launch_push_shells_tiled<Real>(
-              g, f, shell_dev<Real>(*s), shell_const<Real>(c, *s), push_const<Real>(c, *s),
-              s->sort.tile_off,
-              pic::TileGrid{{c->tile[0], c->tile[1], c->tile[2]},
-                            {c->ntiles[0], c->ntiles[1], c->ntiles[2]}},
-              c->err, c->stream);
-          tiled_shells = true;
-        }
-      }
-      if (!tiled_shells)
+      hipError_t e;
+      if (c->tiled && !s->needs_sort && s->sort.tile_off)
+        e = pic::launch_push_shells_tiled<Real>(
+            g, f, shell_dev<Real>(*s), shell_const<Real>(c, *s), push_const<Real>(c, *s),
+            s->sort.tile_off,
+            pic::TileGrid{{c->tile[0], c->tile[1], c->tile[2]},
+                          {c->ntiles[0], c->ntiles[1], c->ntiles[2]}},
+            c->err, c->stream);
+      else
         e = pic::launch_push_shells<Real>(g, f, shell_dev<Real>(*s), shell_const<Real>(c, *s),
                                           push_const<Real>(c, *s), c->err, c->stream);
       TimedDispatch::hook(&td, false);

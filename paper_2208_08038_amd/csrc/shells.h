@@ -49,8 +49,7 @@ hipError_t launch_push_shells(const GridInfo& g, const FieldPtrs<Real>& f, const
 
 // The same step for a species sorted by tile (tile_off: the ntiles + 1
 // offsets of its sorted order): one workgroup per tile, with an LDS
-// current patch for the bodies whose frame cell lies in the tile
-// (instantiated for FP32 work).
+// current patch for the bodies whose frame cell lies in the tile.
 template <typename Real>
 hipError_t launch_push_shells_tiled(const GridInfo& g, const FieldPtrs<Real>& f,
                                     const ShellDev<Real>& s, const ShellConst<Real>& sc,

@@ -6,11 +6,11 @@
 // nucleus-cloud pair in turn (pair momentum kept), every body is
 // Boris-pushed, the centre of mass moves with the mass-weighted velocities
 // and d_k with v0 - v_k, the walls mirror each body, and each body deposits
-// its own Esirkepov current.  In FP32 a species sorted by tile is advanced
-// one workgroup per tile: a body whose frame cell lies in the tile deposits
-// into an FP64 LDS patch of the tile (its whole window lies there), added
-// to the current planes with one global atomic per node; other bodies, an
-// unsorted species and FP64 work deposit with global atomics.
+// its own Esirkepov current.  A species sorted by tile is advanced one
+// workgroup per tile: a body whose frame cell lies in the tile deposits into
+// an FP64 LDS patch of the tile (its whole window lies there), added to the
+// current planes with one global atomic per node; other bodies, and an
+// unsorted species, deposit with global atomics.
 #include <hip/hip_runtime.h>
 
 #include "cycle.h"
@@ -118,10 +118,32 @@ __device__ __forceinline__ void shell_ion(const GridInfo& g, const FieldPtrs<Rea
   const int sy = (int)g.sy, sz = (int)g.sz;
   int base[NB], kb[NB][3];
   Real bx[NB][3], E[NB][3], B[NB][3];
-#pragma unroll
+  // one body at a time (loop not unrolled: a single copy of the gather
+  // keeps the live register set small); its results go to their body's
+  // slots by selects
+#pragma unroll 1
   for (int b = 0; b < NB; b++) {
-    base[b] = body_frame<Real, ND>(g, ci, x[b], bx[b], kb[b]);
-    gather<Real, ND>(f, base[b], sy, sz, bx[b], E[b], B[b]);
+    Real xb[3], ob[3], Eb[3], Bb[3];
+    int kk[3];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+      xb[d] = x[0][d];
+#pragma unroll
+      for (int bb = 1; bb < NB; bb++) xb[d] = bb == b ? x[bb][d] : xb[d];
+    }
+    const int bs = body_frame<Real, ND>(g, ci, xb, ob, kk);
+    gather<Real, ND>(f, bs, sy, sz, ob, Eb, Bb);
+#pragma unroll
+    for (int bb = 0; bb < NB; bb++) {
+      base[bb] = bb == b ? bs : base[bb];
+#pragma unroll
+      for (int d = 0; d < 3; d++) {
+        bx[bb][d] = bb == b ? ob[d] : bx[bb][d];
+        kb[bb][d] = bb == b ? kk[d] : kb[bb][d];
+        E[bb][d] = bb == b ? Eb[d] : E[bb][d];
+        B[bb][d] = bb == b ? Bb[d] : B[bb][d];
+      }
+    }
   }
   // the bonds, as extra fields on the nucleus and on each cloud
 #pragma unroll
@@ -226,13 +248,37 @@ __device__ __forceinline__ void shell_ion(const GridInfo& g, const FieldPtrs<Rea
   for (int b = 0; b < NB; b++) range_ok = range_ok && body_in_range<Real, ND>(g, ci, yb[b]);
   if (c.deposit) {
     const Real W = s.w ? s.w[p] : Real(0);
-#pragma unroll
+#pragma unroll 1
     for (int b = 0; b < NB; b++) {
-      Real z[3] = {0, 0, 0};
+      // body b's quantities, picked by selects (one copy of the deposit)
+      Real ob[3], z[3] = {0, 0, 0}, vb[3];
+      int kk[3], bs = base[0];
+      Real Q = sc.qw[0], qb = sc.q[0];
 #pragma unroll
-      for (int d = 0; d < ND; d++) z[d] = yb[b][d] - Real(kb[b][d]);
-      const Real Q = s.w ? sc.q[b] * W : sc.qw[b];
-      range_ok = dep(base[b], bx[b], z, Q, v[b], ci, kb[b], c) && range_ok;
+      for (int d = 0; d < 3; d++) {
+        ob[d] = bx[0][d];
+        vb[d] = v[0][d];
+        kk[d] = kb[0][d];
+      }
+      Real yy[3] = {yb[0][0], yb[0][1], yb[0][2]};
+#pragma unroll
+      for (int bb = 1; bb < NB; bb++) {
+        const bool m = bb == b;
+        bs = m ? base[bb] : bs;
+        Q = m ? sc.qw[bb] : Q;
+        qb = m ? sc.q[bb] : qb;
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+          ob[d] = m ? bx[bb][d] : ob[d];
+          vb[d] = m ? v[bb][d] : vb[d];
+          kk[d] = m ? kb[bb][d] : kk[d];
+          yy[d] = m ? yb[bb][d] : yy[d];
+        }
+      }
+#pragma unroll
+      for (int d = 0; d < ND; d++) z[d] = yy[d] - Real(kk[d]);
+      if (s.w) Q = qb * W;
+      range_ok = dep(bs, ob, z, Q, vb, ci, kk, c) && range_ok;
     }
   }
   int cn[3] = {ci[0], ci[1], ci[2]};
@@ -465,6 +511,11 @@ template hipError_t launch_push_shells_tiled<float>(const GridInfo&, const Field
                                                     const ShellConst<float>&,
                                                     const PushConst<float>&, const uint32_t*,
                                                     const TileGrid&, uint32_t*, hipStream_t);
+template hipError_t launch_push_shells_tiled<double>(const GridInfo&, const FieldPtrs<double>&,
+                                                     const ShellDev<double>&,
+                                                     const ShellConst<double>&,
+                                                     const PushConst<double>&, const uint32_t*,
+                                                     const TileGrid&, uint32_t*, hipStream_t);
 template void launch_rho_shells<float>(const GridInfo&, const ShellDev<float>&,
                                        const ShellConst<float>&, const PushConst<float>&, double*,
                                        hipStream_t);
