@@ -837,23 +837,43 @@ __device__ __forceinline__ int body_frame(const GridInfo& g, const int ci[3], co
 // the cell index, walls and crossing rule of the near path.  x1, x2: body
 // positions relative to the centre's cell.
 template <typename Real, int ND>
-__device__ __noinline__ void advance_far(const GridInfo& g, const SpeciesDev<Real>& s,
-                                         const PushConst<Real>& c, int64_t p,
-                                         const PState<Real>& st, const int ci[3],
-                                         const Real x1[3], const Real x2[3],
-                                         const FieldPtrs<Real>& f, uint32_t* err) {
+__device__ __forceinline__ void advance_far(const GridInfo& g, const SpeciesDev<Real>& s,
+                                            const PushConst<Real>& c, int64_t p,
+                                            const PState<Real>& st, const int ci[3],
+                                            const Real x1[3], const Real x2[3],
+                                            const FieldPtrs<Real>& f, uint32_t* err) {
   if (!body_in_range<Real, ND>(g, ci, x1) || !body_in_range<Real, ND>(g, ci, x2)) {
     atomicOr(err, PIC_ERR_RANGE);  // left untouched
     return;
   }
   const int sy = (int)g.sy, sz = (int)g.sz;
   Real b1[3], b2[3];
-  int k1[3], k2[3];
-  const int base1 = body_frame<Real, ND>(g, ci, x1, b1, k1);
-  const int base2 = body_frame<Real, ND>(g, ci, x2, b2, k2);
+  int k1[3], k2[3], base1 = 0, base2 = 0;
   Real E1[3], B1[3], E2[3], B2[3];
-  gather<Real, ND>(f, base1, sy, sz, b1, E1, B1);
-  gather<Real, ND>(f, base2, sy, sz, b2, E2, B2);
+  // one body at a time (loop not unrolled: one copy of the gather keeps
+  // the registers low); results to their body by selects
+#pragma unroll 1
+  for (int body = 0; body < 2; body++) {
+    Real xb[3], ob[3], Eb[3], Bb[3];
+    int kk[3];
+#pragma unroll
+    for (int d = 0; d < 3; d++) xb[d] = body == 0 ? x1[d] : x2[d];
+    const int bs = body_frame<Real, ND>(g, ci, xb, ob, kk);
+    gather<Real, ND>(f, bs, sy, sz, ob, Eb, Bb);
+    base1 = body == 0 ? bs : base1;
+    base2 = body == 0 ? base2 : bs;
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+      b1[q] = body == 0 ? ob[q] : b1[q];
+      b2[q] = body == 0 ? b2[q] : ob[q];
+      k1[q] = body == 0 ? kk[q] : k1[q];
+      k2[q] = body == 0 ? k2[q] : kk[q];
+      E1[q] = body == 0 ? Eb[q] : E1[q];
+      B1[q] = body == 0 ? Bb[q] : B1[q];
+      E2[q] = body == 0 ? E2[q] : Eb[q];
+      B2[q] = body == 0 ? B2[q] : Bb[q];
+    }
+  }
   Real u1[3], u2[3], dl[3], off[3] = {0, 0, 0};
 #pragma unroll
   for (int q = 0; q < 3; q++) {
@@ -900,8 +920,19 @@ __device__ __noinline__ void advance_far(const GridInfo& g, const SpeciesDev<Rea
       z2[d] = y2[d] - Real(k2[d]);
     }
     Real* const J[3] = {f.J[0], f.J[1], f.J[2]};
-    range_ok = deposit<Real, ND, true, Real>(J, base1, sy, sz, b1, z1, qw1, v1, c) && range_ok;
-    range_ok = deposit<Real, ND, true, Real>(J, base2, sy, sz, b2, z2, qw2, v2, c) && range_ok;
+#pragma unroll 1
+    for (int body = 0; body < 2; body++) {
+      Real ob[3], zb[3], vb[3];
+#pragma unroll
+      for (int q = 0; q < 3; q++) {
+        ob[q] = body == 0 ? b1[q] : b2[q];
+        zb[q] = body == 0 ? z1[q] : z2[q];
+        vb[q] = body == 0 ? v1[q] : v2[q];
+      }
+      range_ok = deposit<Real, ND, true, Real>(J, body == 0 ? base1 : base2, sy, sz, ob, zb,
+                                               body == 0 ? qw1 : qw2, vb, c) &&
+                 range_ok;
+    }
   }
   int cn[3] = {ci[0], ci[1], ci[2]};
 #pragma unroll
