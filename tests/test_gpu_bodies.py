@@ -116,6 +116,50 @@ def test_rho_matches_the_oracle(pic, ndim, bc):
     assert np.abs(got - ref0).max() > 1e-6 * scale  # the charges moved
 
 
+# ------------------------------------------------ walls in FP32
+
+def test_fp32_mirrored_bodies_stay_within_rounding_of_the_wall(pic):
+    """FP32, 1D, zero frozen fields, no friction, a negligible bond: 20,000
+    ions at the x-min wall whose clouds, moving toward it, cross it by
+    1e-9..1e-5 cell in one step.  The mirrored cloud's position is
+    recomputed from the centre of mass and delta, which in FP32 can land a
+    few 1e-8 cell past the wall: the step raises no range error, and every
+    body ends within 2^-16 cell of the wall."""
+    _say("case: fp32 mirrored bodies at the wall")
+    rng = np.random.default_rng(5150)
+    n = 20000
+    g = small_grid(1, (64,), (0.3,), bc=OPEN)
+    dx, dt, lo = 0.3, g.dt, float(g.pad)
+    sp = Species(TWO_BODY, 5.0, 40.0, -3.0, 3.0, weight=1e-6, omega_c=1e-6, a_c=math.inf,
+                 nu=0.0, name="ion")
+    v2 = -0.1 / math.sqrt(1.01)  # the cloud's speed toward the wall, u = -0.1
+    step = abs(v2) * dt / dx  # cells per step
+    pen = 10.0 ** rng.uniform(-9, -5, n)
+    x2 = lo + step - pen  # cloud (cell units); one step takes it to lo - pen
+    x1 = lo + 1.0 + rng.random(n)  # nucleus
+    m1, m2 = 40.0, 3.0
+    R = (m1 * x1 + m2 * x2) / (m1 + m2)
+    delta = np.zeros((n, 3))
+    delta[:, 0] = (x1 - x2) * dx
+    u1 = np.zeros((n, 3))
+    u2 = np.zeros((n, 3))
+    u2[:, 0] = -0.1
+    wl = Workload("wall1d", g, [(sp, Particles(x=(R * dx)[:, None], u1=u1, u2=u2,
+                                               delta=delta))], steps=1, precision=32)
+    s = pic.Simulation.from_workload(wl, precision=32, flags=pic.FROZEN_FIELDS)
+    s.step(1)
+    assert s.diagnostics()["error_word"] == 0
+    p = s.particles(0)
+    xc = p["cell"][:, 0] + p["off"][:, 0]
+    f1, f2 = m2 / (m1 + m2), m1 / (m1 + m2)
+    b1 = xc + f1 * p["delta"][:, 0] / dx
+    b2 = xc - f2 * p["delta"][:, 0] / dx
+    slack = 2.0 ** -16
+    assert b1.min() >= lo - slack and b2.min() >= lo - slack
+    assert b2.max() < lo + 1e-4  # every cloud was mirrored back to just inside
+    s.close()
+
+
 # ------------------------------------------------ separated bodies
 
 @pytest.mark.parametrize("ndim,bc", [(1, PERIODIC), (2, PERIODIC), (3, PERIODIC), (2, OPEN),
