@@ -80,17 +80,41 @@ __global__ void k_rank_keys(const uint32_t* __restrict__ ck, int64_t n, uint32_t
   rk[i] = ((K / cpt) << rbits) | rank;
 }
 
+// Digit histogram of one chunk of keys.  The keys arrive nearly sorted
+// (a re-sort moves few particles), so the lanes of a wavefront mostly share
+// one digit: the lanes with equal digits are found by ballots over the
+// digit's bits and one lane adds their count (one LDS atomic per distinct
+// digit of a wavefront instead of one per key).
 __global__ void __launch_bounds__(SB) k_hist(const uint32_t* key, int64_t n, int shift,
                                              int nbits, uint32_t* hist, int nb) {
   __shared__ uint32_t h[MAXBINS];
   const int bins = 1 << nbits;
   const uint32_t mask = (uint32_t)bins - 1u;
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int d = threadIdx.x; d < bins; d += SB) h[d] = 0;
   __syncthreads();
-  int64_t base = (int64_t)blockIdx.x * CHUNK;
+  const int64_t base = (int64_t)blockIdx.x * CHUNK;
+  // every load of the chunk issued before the first is used
+  uint32_t kv[ROUNDS];
+#pragma unroll
   for (int r = 0; r < ROUNDS; r++) {
-    int64_t i = base + (int64_t)r * SB + threadIdx.x;
-    if (i < n) atomicAdd(&h[(key[i] >> shift) & mask], 1u);
+    const int64_t i = base + (int64_t)r * SB + threadIdx.x;
+    kv[r] = i < n ? key[i] : 0u;
+  }
+#pragma unroll
+  for (int r = 0; r < ROUNDS; r++) {
+    const int64_t i = base + (int64_t)r * SB + threadIdx.x;
+    const bool valid = i < n;
+    const uint32_t dig = valid ? (kv[r] >> shift) & mask : 0u;
+    uint64_t m = __ballot(valid);
+    for (int b = 0; b < nbits; b++) {
+      const bool bit = (dig >> b) & 1u;
+      const uint64_t bb = __ballot(valid && bit);
+      m &= bit ? bb : ~bb;
+    }
+    // the lowest lane of each group of equal digits adds the group's count
+    if (valid && (m & lt) == 0ull) atomicAdd(&h[dig], (uint32_t)__popcll(m));
   }
   __syncthreads();
   for (int d = threadIdx.x; d < bins; d += SB) hist[(int64_t)d * nb + blockIdx.x] = h[d];
@@ -148,14 +172,23 @@ __global__ void __launch_bounds__(SB) k_scatter(const uint32_t* kin, const uint3
   const uint32_t mask = (uint32_t)bins - 1u;
   for (int d = t; d < bins; d += SB) run[d] = offs[(int64_t)d * nb + blockIdx.x];
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  int64_t base = (int64_t)blockIdx.x * CHUNK;
+  const int64_t base = (int64_t)blockIdx.x * CHUNK;
+  // every key (and index) of the chunk loaded before the rounds start
+  uint32_t kv[ROUNDS], iv[ROUNDS];
+#pragma unroll
+  for (int r = 0; r < ROUNDS; r++) {
+    const int64_t i = base + (int64_t)r * SB + t;
+    kv[r] = i < n ? kin[i] : 0u;
+    iv[r] = i < n ? (iin ? iin[i] : (uint32_t)i) : 0u;
+  }
+#pragma unroll
   for (int r = 0; r < ROUNDS; r++) {
     for (int d = t; d < bins; d += SB)
       for (int q = 0; q < SB / 64; q++) wc[q][d] = 0;
     __syncthreads();
     int64_t i = base + (int64_t)r * SB + t;
     bool valid = i < n;
-    uint32_t key = valid ? kin[i] : 0u;
+    uint32_t key = kv[r];
     uint32_t dig = (key >> shift) & mask;
     // lanes of this wavefront with the same digit, by ballots over its bits
     uint64_t m = __ballot(valid);
@@ -180,7 +213,7 @@ __global__ void __launch_bounds__(SB) k_scatter(const uint32_t* kin, const uint3
     }
     if (valid) {
       kout[pos] = key;
-      iout[pos] = iin ? iin[i] : (uint32_t)i;
+      iout[pos] = iv[r];
     }
     __syncthreads();
   }
