@@ -541,13 +541,13 @@ int advance_one(pic_ctx* c, const pic::LaserDev& las, const StepOpts& o,
       // two-cloud medium: FP32 3.72 -> 2.76 ms per step, FP64 6.75 -> 4.55)
       TimedDispatch::hook(&td, true);
       hipError_t e;
-      if (c->tiled && !s->needs_sort && s->sort.tile_off)
+      const pic::TileGrid tgrid{{c->tile[0], c->tile[1], c->tile[2]},
+                                {c->ntiles[0], c->ntiles[1], c->ntiles[2]}};
+      if (c->tiled && !s->needs_sort && s->sort.tile_off &&
+          pic::shells_tiled_lds(g, tgrid) <= pic::kShellsTiledMaxLds)
         e = pic::launch_push_shells_tiled<Real>(
             g, f, shell_dev<Real>(*s), shell_const<Real>(c, *s), push_const<Real>(c, *s),
-            s->sort.tile_off,
-            pic::TileGrid{{c->tile[0], c->tile[1], c->tile[2]},
-                          {c->ntiles[0], c->ntiles[1], c->ntiles[2]}},
-            c->err, c->stream);
+            s->sort.tile_off, tgrid, c->err, c->stream);
       else
         e = pic::launch_push_shells<Real>(g, f, shell_dev<Real>(*s), shell_const<Real>(c, *s),
                                           push_const<Real>(c, *s), c->err, c->stream);

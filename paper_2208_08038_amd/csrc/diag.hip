@@ -369,16 +369,23 @@ void launch_rho(const GridInfo& g, const SpeciesDev<Real>& s, const PushConst<Re
   if (g.nd == 3) hipLaunchKernelGGL((k_rho<Real, 3>), nb, 256, 0, st, g, s, c, rho);
 }
 
+size_t rho_tiled_lds(const GridInfo& g, const TileGrid& t) {
+  size_t lds = sizeof(double);
+  for (int d = 0; d < g.nd; d++) lds *= (size_t)(t.T[d] + 4);
+  return lds;
+}
+
 template <typename Real>
 void launch_rho_tiled(const GridInfo& g, const SpeciesDev<Real>& s, const PushConst<Real>& c,
                       const uint32_t* tile_off, const TileGrid& t, double* rho, hipStream_t st) {
   if (s.n == 0) return;
-  int64_t ntiles = 1;
-  size_t lds = sizeof(double);
-  for (int d = 0; d < g.nd; d++) {
-    ntiles *= t.nt[d];
-    lds *= (size_t)(t.T[d] + 4);
+  if (rho_tiled_lds(g, t) > kRhoTiledMaxLds) {  // a patch this large: one thread per particle
+    launch_rho<Real>(g, s, c, rho, st);
+    return;
   }
+  int64_t ntiles = 1;
+  const size_t lds = rho_tiled_lds(g, t);
+  for (int d = 0; d < g.nd; d++) ntiles *= t.nt[d];
   if (g.nd == 1)
     hipLaunchKernelGGL((k_rho_tiled<Real, 1>), dim3((unsigned)ntiles), 256, lds, st, g, s, c,
                        tile_off, t, rho);

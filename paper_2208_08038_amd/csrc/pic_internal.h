@@ -281,7 +281,10 @@ struct TileGrid {
 
 // The charge density of launch_rho for a species sorted by tile (tile_off:
 // the ntiles + 1 offsets of its sorted order); one workgroup per tile with
-// an FP64 LDS patch of (T + 4) nodes per resolved dimension.
+// an FP64 LDS patch of (T + 4) nodes per resolved dimension (tiles whose
+// patch would exceed kRhoTiledMaxLds take launch_rho).
+constexpr size_t kRhoTiledMaxLds = 64 * 1024;
+size_t rho_tiled_lds(const GridInfo& g, const TileGrid& t);
 template <typename Real>
 void launch_rho_tiled(const GridInfo& g, const SpeciesDev<Real>& s, const PushConst<Real>& c,
                       const uint32_t* tile_off, const TileGrid& t, double* rho, hipStream_t st);

@@ -49,7 +49,10 @@ hipError_t launch_push_shells(const GridInfo& g, const FieldPtrs<Real>& f, const
 
 // The same step for a species sorted by tile (tile_off: the ntiles + 1
 // offsets of its sorted order): one workgroup per tile, with an LDS
-// current patch for the bodies whose frame cell lies in the tile.
+// current patch for the bodies whose frame cell lies in the tile; only for
+// tiles whose patch (shells_tiled_lds) fits kShellsTiledMaxLds.
+constexpr size_t kShellsTiledMaxLds = 64 * 1024;
+size_t shells_tiled_lds(const GridInfo& g, const TileGrid& t);
 template <typename Real>
 hipError_t launch_push_shells_tiled(const GridInfo& g, const FieldPtrs<Real>& f,
                                     const ShellDev<Real>& s, const ShellConst<Real>& sc,

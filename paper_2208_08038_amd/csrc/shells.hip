@@ -438,12 +438,9 @@ hipError_t push_tiled_nd(const GridInfo& g, const FieldPtrs<Real>& f, const Shel
                          const uint32_t* tile_off, const TileGrid& t, uint32_t* err,
                          hipStream_t st) {
   int64_t ntiles = 1;
-  size_t lds = 3 * sizeof(double);
-  for (int d = 0; d < ND; d++) {
-    ntiles *= t.nt[d];
-    lds *= (size_t)(t.T[d] + 5);
-  }
-  if (lds > 64 * 1024) return hipErrorInvalidValue;
+  for (int d = 0; d < ND; d++) ntiles *= t.nt[d];
+  const size_t lds = shells_tiled_lds(g, t);
+  if (lds > kShellsTiledMaxLds) return hipErrorInvalidValue;  // callers check first
   const dim3 nb((unsigned)ntiles);
   switch (sc.K) {
     case 1: hipLaunchKernelGGL((k_push_shells_tiled<Real, ND, 1>), nb, 256, lds, st, g, f, s, sc, c, tile_off, t, err); break;
@@ -478,6 +475,12 @@ hipError_t launch_push_shells(const GridInfo& g, const FieldPtrs<Real>& f, const
   if (g.nd == 1) return push_nd<Real, 1>(g, f, s, sc, c, err, st);
   if (g.nd == 2) return push_nd<Real, 2>(g, f, s, sc, c, err, st);
   return push_nd<Real, 3>(g, f, s, sc, c, err, st);
+}
+
+size_t shells_tiled_lds(const GridInfo& g, const TileGrid& t) {
+  size_t lds = 3 * sizeof(double);
+  for (int d = 0; d < g.nd; d++) lds *= (size_t)(t.T[d] + 5);
+  return lds;
 }
 
 template <typename Real>

@@ -125,6 +125,28 @@ def test_shells_tiled_fp32_far_clouds(pic, ndim):
     _compare(o, s, wl, 5e-5, exact_cells=False)
 
 
+def test_shells_large_tiles_take_the_hbm_kernel(pic):
+    """Tiles too large for the LDS of the tiled kernels (16^3 and 24^3 cells
+    in 3D FP64): the context advances every species from HBM with global
+    atomics, and a multi-shell species' step and charge density still match
+    the oracle."""
+    _say("case: shells with large tiles")
+    wl = shell_workload(3, 60, 60, seed=150, K=2)
+    for tile in ((16, 16, 16), (24, 24, 24)):
+        o = Oracle.from_workload(wl)
+        s = pic.Simulation.from_workload(wl, precision=64, flags=pic.TRACK_IDS, tile=tile)
+        o.step(6)
+        s.step(6)
+        assert s.diagnostics()["error_word"] == 0
+        Eo, Bo, Jo = o.fields()
+        Eg, Bg, Jg = s.fields()
+        assert rel_l2(Eg, Eo) < 1e-12 and rel_l2(Jg, Jo) < 1e-12
+        _compare(o, s, wl, 1e-11)
+        ro = o.rho()
+        assert np.abs(s.rho() - ro).max() < 1e-12 * np.abs(ro).max()
+        s.close()
+
+
 @pytest.mark.parametrize("K", [1, 2, 4])
 def test_shells_count_fp32(pic, K):
     """FP32 against the FP64 oracle for 1, 2 and 4 clouds (2D, open faces)."""
