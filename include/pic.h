@@ -204,15 +204,16 @@ int pic_add_species(pic_ctx* ctx, const pic_species_desc* desc, int32_t* species
    shell_ac[k] (0: derived as for a two-body ion, a^3 = |q1 q_k| re_norm /
    (m_r,k omega_k^2) with the pair's reduced mass m_r,k = m1 m_k / (m1 +
    m_k); +inf: harmonic; else as given).  One shell is exactly a two-body
-   ion.  Particles (pic_load_particles, host arrays only): x = centre of mass
-   of all bodies, delta n x 3 nshell (d_k = r_nucleus - r_cloud_k, shell k at
-   3k; NULL: 0), u1 the nucleus n x 3, u2 the clouds n x 3 nshell (NULL:
-   every cloud moves with the nucleus), omega_c NULL; every body between
-   the walls (PIC_ERANGE).  pic_read_particles and pic_read_particles_range
-   return delta and u2 with 3 nshell values per particle.  The species is
-   advanced from HBM, one thread per ion, every body gathered and deposited
-   in the frame of its own cell.  The device loader and gradient runs refuse
-   it (PIC_EINVAL). */
+   ion.  Particles (pic_load_particles or pic_load_particles_device): x =
+   centre of mass of all bodies, delta n x 3 nshell (d_k = r_nucleus -
+   r_cloud_k, shell k at 3k; NULL: 0), u1 the nucleus n x 3, u2 the clouds
+   n x 3 nshell (NULL: every cloud moves with the nucleus), omega_c NULL
+   (PIC_EINVAL otherwise); every body between the walls (PIC_ERANGE).
+   pic_read_particles and pic_read_particles_range return delta and u2 with
+   3 nshell values per particle.  The species is advanced one thread per
+   ion, every body gathered and deposited in the frame of its own cell (in
+   a tiled context, once sorted, with an LDS current patch per tile).
+   Gradient runs refuse it (PIC_EINVAL). */
 int pic_add_multishell(pic_ctx* ctx, const pic_species_desc* desc, int32_t nshell,
                        const double* shell_q, const double* shell_m, const double* shell_omega,
                        const double* shell_ac, int32_t* species_id);

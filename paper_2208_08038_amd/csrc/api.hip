@@ -1251,24 +1251,47 @@ int pic_load_particles_device(pic_ctx* c, int32_t sid, int64_t n, const double* 
   if (sid < 0 || sid >= (int32_t)c->sp.size()) return fail(c, PIC_ESTATE, "unknown species");
   if (n < 0 || (n > 0 && (!x || !u1))) return fail(c, PIC_EINVAL, "null particle arrays");
   SpeciesHost& s = *c->sp[sid];
-  if (s.d.kind == PIC_MULTI_SHELL)
-    return fail(c, PIC_EINVAL, "multi-shell species load from host arrays (pic_load_particles)");
   if (s.n + n > s.cap) return fail(c, PIC_ENOMEM, "species capacity exceeded");
   if (n == 0) return PIC_OK;
+  const bool shells = s.d.kind == PIC_MULTI_SHELL;
+  if (shells && omega_c)
+    return fail(c, PIC_EINVAL, "the bond frequencies of a multi-shell species are per shell");
   if (omega_c && !own_omega_allowed(s))
     return fail(c, PIC_EINVAL, omega_fixed_msg);
   int rc = prepare_optional(c, s, omega_c != nullptr, weight != nullptr);
   if (rc) return rc;
-  pic::LoadSrc src{x, delta, u1, u2, omega_c, weight, n};
-  pic::LoadSplit sp{s.d.q1, s.d.m1, s.d.q2, s.d.m2, s.d.omega_c, s.d.weight};
-  const bool two = s.d.kind == PIC_TWO_BODY;
   HIPCHK(c, hipMemsetAsync(c->load_err, 0, 16, c->stream));
-  if (c->prec == 32)
-    pic::launch_load<float>(c->g, src, species_dev<float>(s), s.n, s.ids, sp, two, c->load_err,
-                            c->stream);
-  else
-    pic::launch_load<double>(c->g, src, species_dev<double>(s), s.n, s.ids, sp, two, c->load_err,
-                             c->stream);
+  if (shells) {
+    pic::ShellLoad src{};
+    src.x = x;
+    src.delta = delta;
+    src.u1 = u1;
+    src.u2 = u2;
+    src.w = weight;
+    src.n = n;
+    src.weight = s.d.weight;
+    src.K = s.nshell;
+    double M = s.d.m1;
+    for (int k = 0; k < s.nshell; k++) M += s.sm[k];
+    src.fm[0] = s.d.m1 / M;
+    for (int k = 0; k < s.nshell; k++) src.fm[k + 1] = s.sm[k] / M;
+    if (c->prec == 32)
+      pic::launch_load_shells<float>(c->g, src, shell_dev<float>(s), s.n, s.ids, c->load_err,
+                                     c->stream);
+    else
+      pic::launch_load_shells<double>(c->g, src, shell_dev<double>(s), s.n, s.ids, c->load_err,
+                                      c->stream);
+  } else {
+    pic::LoadSrc src{x, delta, u1, u2, omega_c, weight, n};
+    pic::LoadSplit sp{s.d.q1, s.d.m1, s.d.q2, s.d.m2, s.d.omega_c, s.d.weight};
+    const bool two = s.d.kind == PIC_TWO_BODY;
+    if (c->prec == 32)
+      pic::launch_load<float>(c->g, src, species_dev<float>(s), s.n, s.ids, sp, two,
+                              c->load_err, c->stream);
+    else
+      pic::launch_load<double>(c->g, src, species_dev<double>(s), s.n, s.ids, sp, two,
+                               c->load_err, c->stream);
+  }
   uint32_t lw[4] = {0, 0, 0, 0};
   HIPCHK(c, hipMemcpyAsync(lw, c->load_err, 16, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));

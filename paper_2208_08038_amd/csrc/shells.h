@@ -59,6 +59,28 @@ hipError_t launch_push_shells_tiled(const GridInfo& g, const FieldPtrs<Real>& f,
                                     const PushConst<Real>& c, const uint32_t* tile_off,
                                     const TileGrid& t, uint32_t* err, hipStream_t st);
 
+// Device load of a multi-shell species (FP64 device arrays, layout as
+// pic_load_particles: x n x ndim, delta and u2 n x 3K or nullptr, u1 n x 3,
+// w n or nullptr), written at positions at .. at + n - 1 in load order.
+// fm[b]: body b's mass over the ion's (b = 0 the nucleus); weight the
+// species value for a missing w.  err as launch_load: [0] PIC_ERR_* bits,
+// bytes 8..15 the bits of the largest |weight| loaded.
+struct ShellLoad {
+  const double* x;
+  const double* delta;
+  const double* u1;
+  const double* u2;
+  const double* w;
+  int64_t n;
+  double fm[kMaxShell + 1];
+  double weight;
+  int K;
+};
+
+template <typename Real>
+void launch_load_shells(const GridInfo& g, const ShellLoad& src, const ShellDev<Real>& s,
+                        int64_t at, int64_t* ids, uint32_t* err, hipStream_t st);
+
 // charge density of every body (FP64 plane with guards, as launch_rho)
 template <typename Real>
 void launch_rho_shells(const GridInfo& g, const ShellDev<Real>& s, const ShellConst<Real>& sc,

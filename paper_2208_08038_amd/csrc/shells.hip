@@ -390,6 +390,111 @@ __global__ void __launch_bounds__(256) k_push_shells_tiled(GridInfo g, FieldPtrs
   }
 }
 
+// Device load, operation for operation as the host loader: position ->
+// (packed cell, offset in the working precision), every body between the
+// walls along walled axes, finite state.
+template <typename Real, int ND, int K>
+__global__ void __launch_bounds__(256) k_load_shells(GridInfo g, ShellLoad src, ShellDev<Real> s,
+                                                     int64_t at, int64_t* ids, uint32_t* err) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= src.n) return;
+  const int64_t q = at + p;
+  uint32_t bad = 0;
+  int ci[3] = {0, 0, 0};
+  Real offr[3] = {0, 0, 0};
+#pragma unroll
+  for (int d = 0; d < ND; d++) {
+    const double xv = src.x[p * ND + d];
+    if (!isfinite(xv)) {
+      bad |= PIC_ERR_NAN;
+      continue;
+    }
+    const double xi = xv / g.dx[d];
+    const double f = floor(xi);
+    if (f < 0.0 || f >= (double)g.n[d]) {
+      bad |= PIC_ERR_RANGE;
+      continue;
+    }
+    int cc = (int)f;
+    Real orr = (Real)(xi - f);
+    if (orr >= Real(1)) {
+      orr -= Real(1);
+      cc += 1;
+      if (cc >= g.n[d]) {
+        if (g.periodic[d])
+          cc -= g.n[d];
+        else
+          bad |= PIC_ERR_RANGE;
+      }
+    }
+    ci[d] = cc;
+    offr[d] = orr;
+  }
+  double dl[K][3];
+#pragma unroll
+  for (int k = 0; k < K; k++)
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      dl[k][a] = src.delta ? src.delta[3 * K * p + 3 * k + a] : 0.0;
+      if (!isfinite(dl[k][a])) bad |= PIC_ERR_NAN;
+    }
+  // along walled axes every body lies between the walls
+#pragma unroll
+  for (int d = 0; d < ND; d++) {
+    if (g.periodic[d] || bad) continue;
+    double X0 = src.x[p * ND + d] / g.dx[d];
+#pragma unroll
+    for (int k = 0; k < K; k++) X0 += src.fm[k + 1] * dl[k][d] / g.dx[d];
+    const double lo = g.pad, hi = g.n[d] - g.pad;
+    bool ok = X0 >= lo && X0 <= hi;
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+      const double Xk = X0 - dl[k][d] / g.dx[d];
+      ok = ok && Xk >= lo && Xk <= hi;
+    }
+    if (!ok) bad |= PIC_ERR_RANGE;
+  }
+  double u0[3], uk[K][3];
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    u0[a] = src.u1[3 * p + a];
+    if (!isfinite(u0[a])) bad |= PIC_ERR_NAN;
+  }
+#pragma unroll
+  for (int k = 0; k < K; k++)
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      uk[k][a] = src.u2 ? src.u2[3 * K * p + 3 * k + a] : u0[a];
+      if (!isfinite(uk[k][a])) bad |= PIC_ERR_NAN;
+    }
+  if (bad) {
+    atomicOr(err, bad);
+    return;
+  }
+  uint32_t pk = (uint32_t)ci[0];
+  if (ND > 1) pk |= (uint32_t)ci[1] << g.bits[0];
+  if (ND > 2) pk |= (uint32_t)ci[2] << (g.bits[0] + g.bits[1]);
+  s.cell[q] = pk;
+#pragma unroll
+  for (int d = 0; d < ND; d++) s.off[d][q] = offr[d];
+#pragma unroll
+  for (int a = 0; a < 3; a++) s.u0[a][q] = (Real)u0[a];
+#pragma unroll
+  for (int k = 0; k < K; k++)
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      s.dl[k][a][q] = (Real)dl[k][a];
+      s.uk[k][a][q] = (Real)uk[k][a];
+    }
+  if (s.w) {
+    const double w = src.w ? src.w[p] : src.weight;
+    s.w[q] = (Real)w;
+    atomicMax(reinterpret_cast<unsigned long long*>(err + 2),
+              __builtin_bit_cast(unsigned long long, fabs(w)));
+  }
+  if (ids) ids[q] = q;
+}
+
 template <typename Real, int ND, int K>
 __global__ void __launch_bounds__(256) k_rho_shells(GridInfo g, ShellDev<Real> s,
                                                     ShellConst<Real> sc, PushConst<Real> c,
@@ -494,6 +599,28 @@ hipError_t launch_push_shells_tiled(const GridInfo& g, const FieldPtrs<Real>& f,
   return push_tiled_nd<Real, 3>(g, f, s, sc, c, tile_off, t, err, st);
 }
 
+template <typename Real, int ND>
+static void load_nd(const GridInfo& g, const ShellLoad& src, const ShellDev<Real>& s, int64_t at,
+                    int64_t* ids, uint32_t* err, hipStream_t st) {
+  const unsigned nb = (unsigned)((src.n + 255) / 256);
+  switch (src.K) {
+    case 1: hipLaunchKernelGGL((k_load_shells<Real, ND, 1>), nb, 256, 0, st, g, src, s, at, ids, err); break;
+    case 2: hipLaunchKernelGGL((k_load_shells<Real, ND, 2>), nb, 256, 0, st, g, src, s, at, ids, err); break;
+    case 3: hipLaunchKernelGGL((k_load_shells<Real, ND, 3>), nb, 256, 0, st, g, src, s, at, ids, err); break;
+    case 4: hipLaunchKernelGGL((k_load_shells<Real, ND, 4>), nb, 256, 0, st, g, src, s, at, ids, err); break;
+    default: break;
+  }
+}
+
+template <typename Real>
+void launch_load_shells(const GridInfo& g, const ShellLoad& src, const ShellDev<Real>& s,
+                        int64_t at, int64_t* ids, uint32_t* err, hipStream_t st) {
+  if (src.n <= 0) return;
+  if (g.nd == 1) load_nd<Real, 1>(g, src, s, at, ids, err, st);
+  if (g.nd == 2) load_nd<Real, 2>(g, src, s, at, ids, err, st);
+  if (g.nd == 3) load_nd<Real, 3>(g, src, s, at, ids, err, st);
+}
+
 template <typename Real>
 void launch_rho_shells(const GridInfo& g, const ShellDev<Real>& s, const ShellConst<Real>& sc,
                        const PushConst<Real>& c, double* rho, hipStream_t st) {
@@ -519,6 +646,12 @@ template hipError_t launch_push_shells_tiled<double>(const GridInfo&, const Fiel
                                                      const ShellConst<double>&,
                                                      const PushConst<double>&, const uint32_t*,
                                                      const TileGrid&, uint32_t*, hipStream_t);
+template void launch_load_shells<float>(const GridInfo&, const ShellLoad&,
+                                        const ShellDev<float>&, int64_t, int64_t*, uint32_t*,
+                                        hipStream_t);
+template void launch_load_shells<double>(const GridInfo&, const ShellLoad&,
+                                         const ShellDev<double>&, int64_t, int64_t*, uint32_t*,
+                                         hipStream_t);
 template void launch_rho_shells<float>(const GridInfo&, const ShellDev<float>&,
                                        const ShellConst<float>&, const PushConst<float>&, double*,
                                        hipStream_t);

@@ -292,8 +292,9 @@ class Simulation:
             keep.append(t)
             return C.c_void_p(t.data_ptr())
 
-        args = [ptr(x, self.ndim), ptr(delta, 3), ptr(u1, 3), ptr(u2, 3), ptr(omega_c, 1),
-                ptr(weight, 1)]
+        K = self._nshell(sid)  # a multi-shell species: 3 K values of delta and u2
+        args = [ptr(x, self.ndim), ptr(delta, 3 * K), ptr(u1, 3), ptr(u2, 3 * K),
+                ptr(omega_c, 1), ptr(weight, 1)]
         torch.cuda.current_stream(self.device).synchronize()
         self._check(self.lib.pic_load_particles_device(self.ctx, sid, n, *args))
         del keep

@@ -211,9 +211,9 @@ def test_shells_restart(pic):
 
 
 def test_shells_refusals(pic):
-    """Per-particle omega_c, the device loader and gradient runs refuse a
-    multi-shell species (PIC_EINVAL); a body outside the walls is PIC_ERANGE;
-    a bad shell is refused at creation."""
+    """Per-particle omega_c (host and device loads) and gradient runs refuse
+    a multi-shell species (PIC_EINVAL); a body outside the walls is
+    PIC_ERANGE from either loader; a bad shell is refused at creation."""
     _say("case: shells refusals")
     import torch
     wl = shell_workload(2, 10, 0, seed=9, bc=OPEN)
@@ -223,16 +223,21 @@ def test_shells_refusals(pic):
     with pytest.raises(pic.PicError) as e:
         s.load_particles(sid, dataclasses.replace(parts, omega_c=np.full(parts.n, 2.0)))
     assert e.value.code == pic.PIC_EINVAL
+    dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
     with pytest.raises(pic.PicError) as e:
-        x = torch.tensor(parts.x, dtype=torch.float64, device="cuda")
-        u = torch.tensor(parts.u1, dtype=torch.float64, device="cuda")
-        s.load_particles_device(sid, x, u)
+        s.load_particles_device(sid, dev(parts.x), dev(parts.u1), delta=dev(parts.delta),
+                                u2=dev(parts.u2), omega_c=dev(np.full(parts.n, 2.0)))
     assert e.value.code == pic.PIC_EINVAL
     far = parts.delta.copy()
     far[0, 0] = 40.0 * wl.grid.dx[0]  # cloud 1 of ion 0 beyond the wall
     with pytest.raises(pic.PicError) as e:
         s.load_particles(sid, dataclasses.replace(parts, delta=far))
     assert e.value.code == pic.PIC_ERANGE
+    with pytest.raises(pic.PicError) as e:
+        s.load_particles_device(sid, dev(parts.x), dev(parts.u1), delta=dev(far),
+                                u2=dev(parts.u2))
+    assert e.value.code == pic.PIC_ERANGE
+    assert s.count(sid) == 0
     s.load_particles(sid, parts)
     with pytest.raises(pic.PicError) as e:
         s.grad_forward(4, 2)
@@ -241,6 +246,37 @@ def test_shells_refusals(pic):
     with pytest.raises(pic.PicError) as e:
         s.add_species(bad, 10)
     assert e.value.code == pic.PIC_EINVAL
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_shells_device_loader_matches_host_loader(pic, precision):
+    """The same arrays loaded from host and from device memory give the same
+    state (matched by load index: cells, offsets, displacements and
+    momenta equal), and the same fields after 8 steps (to rounding: the
+    loaders order the particles differently, so the current sums
+    differ in order)."""
+    _say(f"case: shells device loader fp{precision}")
+    import torch
+    wl = shell_workload(3, 200, 0, seed=11, K=3, bc=OPEN)
+    sp, parts = wl.species[0]
+    a = pic.Simulation(wl.grid, precision=precision, flags=pic.TRACK_IDS)
+    ia = a.add_species(sp, parts.n)
+    a.load_particles(ia, parts)
+    b = pic.Simulation(wl.grid, precision=precision, flags=pic.TRACK_IDS)
+    ib = b.add_species(sp, parts.n)
+    dev = lambda x: torch.tensor(x, dtype=torch.float64, device="cuda")
+    b.load_particles_device(ib, dev(parts.x), dev(parts.u1), delta=dev(parts.delta),
+                            u2=dev(parts.u2))
+    pa, pb = a.particles(ia, ids=True), b.particles(ib, ids=True)
+    pa, pb = match_by_id(pa, pa["id"]), match_by_id(pb, pb["id"])
+    for k in ("cell", "off", "delta", "u1", "u2"):
+        assert np.array_equal(pa[k], pb[k]), k
+    a.step(8)
+    b.step(8)
+    Ea, Ba, _ = a.fields()
+    Eb, Bb, _ = b.fields()
+    tol = 1e-12 if precision == 64 else 1e-5
+    assert rel_l2(Eb, Ea) < tol and rel_l2(Bb, Ba) < tol
 
 
 def test_multishell_medium_probes_fp64(pic):
