@@ -414,8 +414,9 @@ __device__ __forceinline__ bool win_build(Real x0, Real x1, Win<Real, 4>& w) {
   return true;
 }
 
-// Adjoint of the Esirkepov deposit of NB bodies (NB = 2: both bodies of an
-// ion on common windows, which then read the adjoint current once), body
+// Adjoint of the Esirkepov deposit of NB bodies on common windows (which
+// then read the adjoint current once; the kernels call it one body at a
+// time, which keeps their registers within two waves per SIMD), body
 // b with charge Q[b] moving from x0[b] to x1[b] at velocity v[b] (for the
 // out-of-plane components), on windows of NW nodes: with lJ the adjoint
 // current, Phi = sum lJ . J; returns per body dPhi/dx0, dPhi/dx1 (resolved
@@ -672,32 +673,6 @@ __device__ __forceinline__ bool deposit_adjoint(const Real* J, int64_t jplane, c
     gv[d] = hv[0][d];
   }
   return ok;
-}
-
-// Both bodies of an ion at once when all four positions (old and new of
-// each body) share the nearest node along every resolved axis: the
-// three-node windows coincide and the adjoint current is read once.
-template <typename Real, int ND>
-__device__ __forceinline__ bool deposit_adjoint_pair(const Real* J, int64_t jplane,
-                                                     const Where3& wh, const Real xa0[3],
-                                                     const Real xa1[3], const Real xb0[3],
-                                                     const Real xb1[3], Real Qa, Real Qb,
-                                                     const Real va[3], const Real vb[3],
-                                                     const PushConst<Real>& c, Real g0[2][3],
-                                                     Real g1[2][3], Real gv[2][3]) {
-  bool common = true;
-#pragma unroll
-  for (int d = 0; d < ND; d++) {
-    const Real n = floor(xa0[d] + Real(0.5));
-    common = common && floor(xa1[d] + Real(0.5)) == n && floor(xb0[d] + Real(0.5)) == n &&
-             floor(xb1[d] + Real(0.5)) == n;
-  }
-  if (!common) return false;
-  const Real* const a0[2] = {xa0, xb0};
-  const Real* const a1[2] = {xa1, xb1};
-  const Real* const av[2] = {va, vb};
-  const Real q[2] = {Qa, Qb};
-  return deposit_adjoint_w<Real, ND, 3, 2>(J, jplane, wh, a0, a1, q, av, c, g0, g1, gv);
 }
 
 // Wall reflection as in the forward cycle; returns true if it reflected.
@@ -978,55 +953,36 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const Planes<Real
       }
     }
     Real l_v1[3] = {0, 0, 0}, l_v2[3] = {0, 0, 0};
-    bool paired = false;
-    if (TWO && c.deposit) {
+    if (c.deposit) {
+      // one body at a time (loop not unrolled: one copy of the deposit
+      // adjoint keeps the registers low); results to their body by selects
       const Real Q1 = st.w ? c.q1 * W : c.qw1, Q2 = st.w ? c.q2 * W : c.qw2;
-      Real h0[2][3], h1[2][3], hv[2][3];
-      paired = deposit_adjoint_pair<Real, ND>(LJ, jplane, wh, x1, y1, x2, y2, Q1, Q2, v1, v2, c,
-                                              h0, h1, hv);
-      if (paired) {
+#pragma unroll 1
+      for (int body = 0; body < (TWO ? 2 : 1); body++) {
+        Real xa[3], ya[3], va[3], g0[3], g1[3], gv[3];
 #pragma unroll
-        for (int d = 0; d < ND; d++) {
-          l_offn[d] += h1[0][d] + h1[1][d];
-          l_off[d] += h0[0][d] + h0[1][d];
-          l_dln[d] += c.idx[d] * (c.f1 * h1[0][d] - c.f2 * h1[1][d]);
-          l_dl[d] += c.idx[d] * (c.f1 * h0[0][d] - c.f2 * h0[1][d]);
+        for (int q = 0; q < 3; q++) {
+          xa[q] = body == 0 ? x1[q] : x2[q];
+          ya[q] = body == 0 ? y1[q] : y2[q];
+          va[q] = body == 0 ? v1[q] : v2[q];
         }
-#pragma unroll
-        for (int q = ND; q < 3; q++) {
-          l_v1[q] += hv[0][q];
-          l_v2[q] += hv[1][q];
-        }
-      }
-    }
-    if (c.deposit && !paired) {
-      const Real Q1 = st.w ? c.q1 * W : c.qw1;
-      Real g0[3], g1[3], gv[3];
-      if (deposit_adjoint<Real, ND>(LJ, jplane, wh, x1, y1, Q1, v1, c, g0, g1, gv)) {
-#pragma unroll
-        for (int d = 0; d < ND; d++) {
-          l_offn[d] += g1[d];
-          l_off[d] += g0[d];
-          if (TWO) {
-            l_dln[d] += c.f1 * c.idx[d] * g1[d];
-            l_dl[d] += c.f1 * c.idx[d] * g0[d];
-          }
-        }
-#pragma unroll
-        for (int q = ND; q < 3; q++) l_v1[q] += gv[q];
-      }
-      if (TWO) {
-        const Real Q2 = st.w ? c.q2 * W : c.qw2;
-        if (deposit_adjoint<Real, ND>(LJ, jplane, wh, x2, y2, Q2, v2, c, g0, g1, gv)) {
+        if (deposit_adjoint<Real, ND>(LJ, jplane, wh, xa, ya, body == 0 ? Q1 : Q2, va, c, g0,
+                                      g1, gv)) {
+          const Real fs = body == 0 ? c.f1 : -c.f2;
 #pragma unroll
           for (int d = 0; d < ND; d++) {
             l_offn[d] += g1[d];
             l_off[d] += g0[d];
-            l_dln[d] -= c.f2 * c.idx[d] * g1[d];
-            l_dl[d] -= c.f2 * c.idx[d] * g0[d];
+            if (TWO) {
+              l_dln[d] += fs * c.idx[d] * g1[d];
+              l_dl[d] += fs * c.idx[d] * g0[d];
+            }
           }
 #pragma unroll
-          for (int q = ND; q < 3; q++) l_v2[q] += gv[q];
+          for (int q = ND; q < 3; q++) {
+            l_v1[q] += body == 0 ? gv[q] : Real(0);
+            l_v2[q] += body == 0 ? Real(0) : gv[q];
+          }
         }
       }
     }
@@ -1144,8 +1100,24 @@ __device__ __forceinline__ void adjoint_one(const GridInfo& g, const Planes<Real
       if (same_nodes<Real, ND>(t1, t2)) {
         gather_adjoint<Real, ND, true>(f, k, wh, t1, l_E1, l_B1, t2, l_E2, l_B2, lx1, lx2);
       } else {
-        gather_adjoint<Real, ND, false>(f, k, wh, t1, l_E1, l_B1, t1, l_E1, l_B1, lx1, lx1);
-        gather_adjoint<Real, ND, false>(f, k, wh, t2, l_E2, l_B2, t2, l_E2, l_B2, lx2, lx2);
+        // one body at a time, results to their body by selects
+#pragma unroll 1
+        for (int body = 0; body < 2; body++) {
+          Real xb[3], lE[3], lB[3], lx[3] = {0, 0, 0};
+#pragma unroll
+          for (int q = 0; q < 3; q++) {
+            xb[q] = body == 0 ? x1[q] : x2[q];
+            lE[q] = body == 0 ? l_E1[q] : l_E2[q];
+            lB[q] = body == 0 ? l_B1[q] : l_B2[q];
+          }
+          const Stencil<Real> tb = stencil_at<Real, ND>(xb);
+          gather_adjoint<Real, ND, false>(f, k, wh, tb, lE, lB, tb, lE, lB, lx, lx);
+#pragma unroll
+          for (int q = 0; q < 3; q++) {
+            lx1[q] = body == 0 ? lx[q] : lx1[q];
+            lx2[q] = body == 0 ? lx2[q] : lx[q];
+          }
+        }
       }
     } else {
       gather_adjoint<Real, ND, false>(f, k, wh, t1, l_E1, l_B1, t1, l_E1, l_B1, lx1, lx1);
@@ -1192,6 +1164,18 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// Workgroups per CU the tiled kernel is built for: two (at most 256
+// registers per lane, two waves per SIMD) where the reverse cycle fits
+// them (FP32 in 1D and 2D), else one (the 3D and FP64 cycles keep more
+// values live, and spill at 256).  At one wave per SIMD the 3D FP32 kernel
+// issues the next particle's loads before this one's arithmetic (the
+// registers of a second input set fit there; the FP64 kernels would spill).
+template <typename Real, int ND>
+struct AdjOccupancy {
+  static constexpr int kBlocks = sizeof(Real) == 4 && ND < 3 ? 2 : 1;
+  static constexpr bool kPrefetch = sizeof(Real) == 4 && ND == 3;
+};
+
 // One workgroup per tile of the sorted particle order: the gather's
 // transpose of the tile's particles accumulates in an FP64 LDS patch
 // (LDS atomics, 64-bit ones issue an order of magnitude faster than FP32
@@ -1199,7 +1183,7 @@ __global__ void __launch_bounds__(256)
 // that have left the tile since the sort scatter to the global planes
 // directly.
 template <typename Real, int ND, bool TWO>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, (AdjOccupancy<Real, ND>::kBlocks))
     k_adjoint_tiled(GridInfo g, Planes<Real> f, AdjState<Real> st, PushConst<Real> c,
                     AdjState<Real> lp, Planes<Real> l, double* dparam, double* dfar,
                     const uint32_t* tile_off, AdjTiles tt) {
@@ -1237,13 +1221,13 @@ __global__ void __launch_bounds__(256)
   }
   __syncthreads();
   double d_wc = 0.0, d_nu = 0.0, n_far = 0.0;
+  constexpr bool kPrefetch = AdjOccupancy<Real, ND>::kPrefetch;
   PIn<Real> in;
   int64_t p = p0 + threadIdx.x;
   if (p < p1) load_in<Real, ND, TWO>(st, lp, c, p, in);
   for (; p < p1; p += blockDim.x) {
-    // the next particle's loads are issued before this one's arithmetic
     PIn<Real> nx = in;
-    if (p + blockDim.x < p1) load_in<Real, ND, TWO>(st, lp, c, p + blockDim.x, nx);
+    if (kPrefetch && p + blockDim.x < p1) load_in<Real, ND, TWO>(st, lp, c, p + blockDim.x, nx);
     const uint32_t pk = in.cell;
     const int cx = (int)(pk & ((1u << g.bits[0]) - 1u)) - box.x0;
     const int cy = ND > 1 ? (int)((pk >> g.bits[0]) & ((1u << g.bits[1]) - 1u)) - box.y0 : 0;
@@ -1252,7 +1236,10 @@ __global__ void __launch_bounds__(256)
       adjoint_one<Real, ND, TWO, true>(g, f, st, c, lp, l, p, in, box, d_wc, d_nu, n_far);
     else
       adjoint_one<Real, ND, TWO, false>(g, f, st, c, lp, l, p, in, box, d_wc, d_nu, n_far);
-    in = nx;
+    if (kPrefetch)
+      in = nx;
+    else if (p + blockDim.x < p1)
+      load_in<Real, ND, TWO>(st, lp, c, p + blockDim.x, in);
   }
   __syncthreads();
   // flush: patch node (px, py, pz) is global node (x0 - 2 + px, ...)

@@ -587,8 +587,8 @@ static hipError_t launch_colour_shape(const GridInfo& g, const FieldPtrs<Real>& 
   return launch_colour_wpe<Real, ND, TWO, NS, 2, TX, TY, TZ>(g, f, a, b, t, color, err, lds, st);
 }
 
-// the default 3D tiles (8x8x6 for FP32, 8x8x8 for FP64) have builds with
-// compile-time strides; any other shape runs the generic build
+// the default tiles (3D: 8x8x6 for FP32, 8x8x8 for FP64; 2D: 12x12) have
+// builds with compile-time strides; any other shape runs the generic build
 template <typename Real, int ND, bool TWO, int NS>
 static hipError_t launch_colour(const GridInfo& g, const FieldPtrs<Real>& f,
                                 const TileSpecies<Real>& a, const TileSpecies<Real>& b,
@@ -598,6 +598,10 @@ static hipError_t launch_colour(const GridInfo& g, const FieldPtrs<Real>& f,
     constexpr int TZ = sizeof(Real) == 4 ? 6 : 8;
     if (t.T[0] == 8 && t.T[1] == 8 && t.T[2] == TZ)
       return launch_colour_shape<Real, ND, TWO, NS, 8, 8, TZ>(g, f, a, b, t, color, err, lds, st);
+  }
+  if constexpr (ND == 2) {
+    if (t.T[0] == 12 && t.T[1] == 12)
+      return launch_colour_shape<Real, ND, TWO, NS, 12, 12, 1>(g, f, a, b, t, color, err, lds, st);
   }
   return launch_colour_shape<Real, ND, TWO, NS, 0, 0, 0>(g, f, a, b, t, color, err, lds, st);
 }
