@@ -221,6 +221,34 @@ def test_open_faces_laser_walls_fp64(pic):
     _compare_particles(o, s, wl, 1e-11)
 
 
+@pytest.mark.parametrize("prec", [64, 32])
+def test_open_faces_laser_3d(pic, prec):
+    """3D box with Mur faces on x (a Gaussian laser entering at x-min) and y,
+    periodic z (the boundaries of the slab workloads, with open y faces
+    too): fields and particles follow the oracle."""
+    _say(f"case: open faces + laser 3d fp{prec}")
+    wl = random_workload(3, 300, 300, seed=37, shape=(70, 20, 40), dx=(0.2, 0.2, 0.2), bc=OPEN,
+                         vmax_el=0.9)
+    g = wl.grid
+    g.bc_lo = (LASER, OPEN, PERIODIC)
+    g.bc_hi = (OPEN, OPEN, PERIODIC)
+    g.laser = Laser(a0=0.05, omega=1.0, t_env=4 * math.pi, waist=1.5, yc=10 * 0.2,
+                    zc=20 * 0.2, pol=1)
+    o, s = _both(wl, pic, prec, sort_every=2)
+    o.step(50)
+    s.step(50)
+    assert o.diagnostics()["error_word"] == 0, "oracle run left the valid range"
+    assert s.diagnostics()["error_word"] == 0
+    Eo, Bo, _ = o.fields()
+    Eg, Bg, _ = s.fields()
+    tol = 1e-12 if prec == 64 else 2e-5
+    assert rel_l2(Eg, Eo) < tol
+    assert rel_l2(Bg, Bo) < tol
+    assert np.abs(Eo).max() > 1e-4  # the pulse is in the box
+    if prec == 64:
+        _compare_particles(o, s, wl, 1e-11)
+
+
 def test_charge_continuity_gpu(pic):
     """(rho^{n+1} - rho^n)/dt + div J = 0 on the GPU: round-off in FP64,
     reported (and small) in FP32."""
