@@ -525,7 +525,9 @@ def run_multishell(args):
         out[f"fp{prec}"] = {
             "ions": nion, "ms_per_step": 1e3 * dt / steps,
             "value": nion * steps / dt, "unit": "ion-steps/s",
-            "kernel": f"k_push_shells<{'float' if prec == 32 else 'double'}, 3, {K}>",
+            # the ions are tile-sorted at load and the tile's LDS patch fits:
+            # the per-tile kernel runs every step
+            "kernel": f"k_push_shells_tiled<{'float' if prec == 32 else 'double'}, 3, {K}>",
             "launch_ms": launch_ms, "algorithmic_bytes_per_launch": nbytes,
             "achieved_gbs": nbytes / (launch_ms * 1e-3) / 1e9 if launch_ms > 0 else None,
             "frac_hbm": nbytes / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if launch_ms > 0 else None,
