@@ -20,6 +20,26 @@ namespace pic {
 
 namespace {
 
+// Deposit of one body moving from x0 to x1 (cell units of the frame at
+// `base`): the three-node window when it keeps its nearest node, else the
+// general one.
+template <typename Real, int ND, bool GLOBAL, typename JT>
+__device__ __forceinline__ bool body_deposit(JT* const J[3], int base, int sy, int sz,
+                                             const Real x0[3], const Real x1[3], Real Q,
+                                             const Real v[3], const PushConst<Real>& c) {
+  const Real* xs[2] = {x0, x1};
+  int nn[3];
+  if (common_node<Real, ND>(xs, 2, nn)) {
+    Real d[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < ND; a++) d[a] = x1[a] - x0[a];
+    deposit3<Real, ND, GLOBAL, JT, false>(J, base, sy, sz, nn, x0, d, Q, v, x0, d, Real(0), v,
+                                          c);
+    return true;
+  }
+  return deposit<Real, ND, GLOBAL, JT>(J, base, sy, sz, x0, x1, Q, v, c);
+}
+
 // Deposits of the global kernel: every body with global atomics.
 template <typename Real, int ND>
 struct GlobalDeposit {
@@ -28,7 +48,7 @@ struct GlobalDeposit {
   __device__ __forceinline__ bool operator()(int base, const Real x0[3], const Real x1[3], Real Q,
                                              const Real v[3], const int[3], const int[3],
                                              const PushConst<Real>& c) const {
-    return deposit<Real, ND, true, Real>(J, base, sy, sz, x0, x1, Q, v, c);
+    return body_deposit<Real, ND, true, Real>(J, base, sy, sz, x0, x1, Q, v, c);
   }
 };
 
@@ -55,8 +75,8 @@ struct TileDeposit {
       in = in && cb >= lo[d] && cb < hi[d];
       jb += (cb - lo[d] + 2) * (d == 0 ? 1 : (d == 1 ? psy : psz));
     }
-    if (in) return deposit<Real, ND, false, double>(P, jb, psy, psz, x0, x1, Q, v, c);
-    return deposit<Real, ND, true, Real>(J, base, sy, sz, x0, x1, Q, v, c);
+    if (in) return body_deposit<Real, ND, false, double>(P, jb, psy, psz, x0, x1, Q, v, c);
+    return body_deposit<Real, ND, true, Real>(J, base, sy, sz, x0, x1, Q, v, c);
   }
 };
 
