@@ -5,7 +5,9 @@ so it advances sampled particles one by one: a full-grid oracle holding only
 the sampled particles, with the same fields frozen and no deposit, must move
 them exactly as the GPU moved them in its coupled step (the push of a
 particle depends only on its own state and on the fields at its nodes).
-The whole-system property checked at full size is charge continuity.
+The whole-system property checked at full size is charge continuity.  The
+2D Bragg case (4096^2 cells, 457 ions) is small enough in particles for the
+oracle to advance the whole system at its full size.
 """
 import math
 import sys
@@ -138,6 +140,76 @@ def test_full_size_sampled_particles_and_continuity(pic, precision):
     _say(f"fp{precision} continuity: div_max {d['div_max']:.3e} (bound "
          f"{27 * 8 * eps * gross:.3e}), rms {d['div_l2'] / math.sqrt(ncell):.3e} "
          f"(bound {eps * gross:.3e}), rho_l2 {d['rho_l2']:.3e}")
+    o.close()
+
+
+def _smooth_fields_2d(shape, dx, amp=0.05):
+    """E, B (3, ncell) on a 2D grid, x fastest: separable sines of a few
+    wavelengths per component."""
+    nx, ny = shape
+    i = np.arange(nx) * dx
+    j = np.arange(ny) * dx
+    Lx, Ly = nx * dx, ny * dx
+    out = []
+    for c in range(6):
+        fx = np.sin(2 * math.pi * (c + 1) * i / Lx + 0.3 * c)
+        fy = np.cos(2 * math.pi * (1 + c % 3) * j / Ly + 0.7 * c)
+        out.append((amp * (1.0 - 0.3 * (c >= 3)) * np.multiply.outer(fy, fx)).reshape(-1))
+    return np.stack(out[:3]), np.stack(out[3:])
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_full_size_bragg_case(pic, precision):
+    """The 2D Bragg case at its full size (4096^2 cells, the gold lattice of
+    the central 1024^2 cells, the x-min laser, Mur faces) in the launch
+    configuration bench.py times: from smooth fields, 12 coupled steps of the
+    whole system on the GPU and in the oracle (which starts from the state
+    the GPU holds after its load): fields and every ion."""
+    from paper_2208_08038_amd.inputs import bragg_2d
+    _say(f"case: full-size bragg 4096^2 fp{precision}")
+    steps = 12
+    wl = bragg_2d(steps=steps, precision=precision)
+    g = wl.grid
+    dx = g.dx[0]
+    E, B = _smooth_fields_2d(g.n[:2], dx)
+    if precision == 32:
+        E, B = E.astype(np.float32).astype(np.float64), B.astype(np.float32).astype(np.float64)
+    s = pic.Simulation.from_workload(wl, precision=precision, flags=pic.TRACK_IDS)
+    s.load_fields(E, B)
+    n = s.count(0)
+    st = s.particles_range(0, 0, n, ids=True)
+    order = np.argsort(st["id"])
+    sp = wl.species[0][0]
+    parts = Particles(x=(st["cell"][order] + st["off"][order]) * dx, u1=st["u1"][order],
+                      delta=st["delta"][order], u2=st["u2"][order])
+    o = Oracle(g)
+    osid = o.add_species(sp, n)
+    o.load_particles(osid, parts)
+    o.load_fields(E, B)
+    s.step(steps)
+    assert s.diagnostics()["error_word"] == 0
+    _say(f"case: full-size bragg fp{precision}: oracle, {steps} steps")
+    o.step(steps)
+    Eo, Bo, Jo = o.fields()
+    Eg, Bg, Jg = s.fields()
+    tol = 1e-12 if precision == 64 else 2e-5
+    errs = {}
+    for name, got, ref in (("E", Eg, Eo), ("B", Bg, Bo), ("J", Jg, Jo)):
+        errs[name] = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300)
+        assert errs[name] < tol, (name, errs[name])
+    r = o.particles(osid)
+    a = s.particles(0, ids=True)
+    a = {k: v[np.argsort(a["id"])] for k, v in a.items()}
+    pos_err = np.abs((r["cell"] + r["off"]) - (a["cell"] + a["off"])).max()
+    assert pos_err < (2e-6 if precision == 32 else 1e-11), pos_err
+    if precision == 64:
+        assert np.array_equal(r["cell"], a["cell"])
+    errs["u1"] = _check(r["u1"], a["u1"], tol, "u1")
+    errs["u2"] = _check(r["u2"], a["u2"], tol, "u2")
+    errs["delta"] = _check(r["delta"], a["delta"], tol, "delta")
+    _say(f"fp{precision} bragg full size: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()) +
+         f", positions {pos_err:.2e} cells")
+    s.close()
     o.close()
 
 
