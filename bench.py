@@ -543,6 +543,32 @@ def run_multishell(args):
     return out
 
 
+def mixed_precision_simulation(n, precision, flags):
+    """The mixed-precision case in HBM: (sim, species id, workload
+    description, ion count, largest weight, load seconds).  4 two-body ions
+    per cell in x cells 384..640, generated on the device in chunks of 32 x
+    planes and loaded from device memory."""
+    import torch
+    from paper_2208_08038_amd import inputs as I
+    from paper_2208_08038_amd import pic
+    meta = I.mixed_precision_3d(n=n, slab=(384, 385), steps=1)
+    grid, sp = meta.grid, meta.species[0][0]
+    total = (640 - 384) * n[1] * n[2] * 4
+    sim = pic.Simulation(grid, precision=precision, flags=flags)
+    sid = sim.add_species(sp, total)
+    t0 = time.perf_counter()
+    x0, chunk, wmax = 384, 0, 0.0
+    while x0 < 640:
+        x1 = min(x0 + 32, 640)
+        x, w = I.mixed_precision_3d_device_chunk(n, 4, (x0, x1), chunk)
+        sim.load_particles_device(sid, x, torch.zeros_like(x), weight=w * sp.weight)
+        wmax = max(wmax, float(w.max()) * sp.weight)
+        del x, w
+        x0, chunk = x1, chunk + 1
+    torch.cuda.synchronize()
+    return sim, sid, meta, total, wmax, time.perf_counter() - t0
+
+
 def run_mixed_precision(args):
     """The mixed-precision case at full size: Bragg geometry in 3D,
     1024 x 1024 x 512 cells, 4 two-body ions per cell in x cells 384..640
@@ -551,31 +577,17 @@ def run_mixed_precision(args):
     its rounding bound, and the transmitted field (x cells 640 .. n - 3) of
     FP32 against FP64 at the end."""
     import torch
-    from paper_2208_08038_amd import inputs as I
     from paper_2208_08038_amd import pic
     n = (1024, 1024, 512)
     steps = args.mixed_precision_steps
-    meta = I.mixed_precision_3d(n=n, slab=(384, 385), steps=steps)
-    grid, sp = meta.grid, meta.species[0][0]
-    total = (640 - 384) * n[1] * n[2] * 4
-    dx = grid.dx[0]
-    out = {"workload": "mixed_precision_3d", "cells": list(n), "two_body_ions": total,
-           "steps": steps}
+    out = {"workload": "mixed_precision_3d", "cells": list(n), "steps": steps}
     fields = {}
     for prec in (32, 64):
-        sim = pic.Simulation(grid, precision=prec, flags=pic.CHARGE_CHECK | pic.TIMING)
-        sid = sim.add_species(sp, total)
-        t0 = time.perf_counter()
-        x0, chunk, wmax = 384, 0, 0.0
-        while x0 < 640:
-            x1 = min(x0 + 32, 640)
-            x, w = I.mixed_precision_3d_device_chunk(n, 4, (x0, x1), chunk)
-            sim.load_particles_device(sid, x, torch.zeros_like(x), weight=w * sp.weight)
-            wmax = max(wmax, float(w.max()) * sp.weight)
-            del x, w
-            x0, chunk = x1, chunk + 1
-        torch.cuda.synchronize()
-        t_load = time.perf_counter() - t0
+        sim, sid, meta, total, wmax, t_load = mixed_precision_simulation(
+            n, prec, pic.CHARGE_CHECK | pic.TIMING)
+        grid, sp = meta.grid, meta.species[0][0]
+        dx = grid.dx[0]
+        out["two_body_ions"] = total
         print(f"[bench] mixed_precision_3d fp{prec}: loaded {sim.count(sid)} ions in {t_load:.0f} s",
               file=sys.stderr, flush=True)
         eps = 2.0 ** -24 if prec == 32 else 2.0 ** -53

@@ -6,7 +6,9 @@ the sampled particles, with the same fields frozen and no deposit, must move
 them exactly as the GPU moved them in its coupled step (the push of a
 particle depends only on its own state and on the fields at its nodes).
 The whole-system property checked at full size is charge continuity.  The
-2D Bragg case (4096^2 cells, 457 ions) is small enough in particles for the
+3D mixed-precision case (1024 x 1024 x 512 cells, 537 million ions) is
+checked the same way, each sampled range on a window of the grid.  The 2D
+Bragg case (4096^2 cells, 457 ions) is small enough in particles for the
 oracle to advance the whole system at its full size.
 """
 import math
@@ -211,6 +213,110 @@ def test_full_size_bragg_case(pic, precision):
          f", positions {pos_err:.2e} cells")
     s.close()
     o.close()
+
+
+MP_CELLS = (1024, 1024, 512)
+MP_RANGES = 12
+
+
+def _smooth_factors(shape, dx, amp=0.05):
+    """Per component c of E, B: (scale, fx, fy, fz), the separable factors
+    of _smooth_fields, so that a window of the grid takes exactly the values
+    of the whole."""
+    nx, ny, nz = shape
+    i, j, k = np.arange(nx) * dx, np.arange(ny) * dx, np.arange(nz) * dx
+    Lx, Ly, Lz = nx * dx, ny * dx, nz * dx
+    return [(amp * (1.0 - 0.3 * (c >= 3)),
+             np.sin(2 * math.pi * (c + 1) * i / Lx + 0.3 * c),
+             np.cos(2 * math.pi * (1 + c % 3) * j / Ly + 0.7 * c),
+             np.cos(2 * math.pi * (1 + c % 2) * k / Lz + 1.1 * c)) for c in range(6)]
+
+
+def _fields_from(factors, lo, shape, f32):
+    """E, B (3, ncell), x fastest, on the cells lo .. lo + shape."""
+    n = shape[0] * shape[1] * shape[2]
+    E, B = np.empty((3, n)), np.empty((3, n))
+    for c, (a, fx, fy, fz) in enumerate(factors):
+        v = a * np.multiply.outer(np.multiply.outer(fz[lo[2]:lo[2] + shape[2]],
+                                                    fy[lo[1]:lo[1] + shape[1]]),
+                                  fx[lo[0]:lo[0] + shape[0]])
+        if f32:  # the values the FP32 run holds
+            v = v.astype(np.float32).astype(np.float64)
+        (E if c < 3 else B)[c % 3] = v.reshape(-1)
+    return E, B
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_full_size_mixed_precision_case(pic, precision):
+    """The 3D mixed-precision case at its full size (1024 x 1024 x 512 cells,
+    536,870,912 two-body ions) in the launch configuration bench.py times:
+    from smooth fields, one coupled step of the whole system; sampled ranges
+    of ions against the oracle, each on a window of the grid around its
+    particles with the same field values (frozen fields, no deposit: a
+    particle's push depends only on the fields at its nodes), and the charge
+    continuity of the whole grid."""
+    import dataclasses
+
+    import bench
+    import torch
+    _say(f"case: full-size mixed precision {MP_CELLS} fp{precision}: load")
+    sim, sid, meta, total, wmax, _ = bench.mixed_precision_simulation(
+        MP_CELLS, precision, pic.TRACK_IDS | pic.CHARGE_CHECK)
+    grid, sp = meta.grid, meta.species[0][0]
+    dx = grid.dx[0]
+    factors = _smooth_factors(MP_CELLS, dx)
+    E, B = _fields_from(factors, (0, 0, 0), MP_CELLS, precision == 32)
+    sim.load_fields(E, B)
+    del E, B
+    rng = np.random.default_rng(4)
+    ranges = []
+    while len(ranges) < MP_RANGES:
+        s0 = int(rng.integers(0, total - SAMPLE_LEN))
+        b = sim.particles_range(sid, s0, SAMPLE_LEN, ids=True)
+        lo = b["cell"].min(axis=0) - 4
+        hi = b["cell"].max(axis=0) + 5
+        if np.all(lo >= 0) and np.all(hi <= np.array(MP_CELLS)):  # away from the periodic seams
+            ranges.append((s0, b, lo, hi))
+    _say(f"case: full-size mixed precision fp{precision}: one coupled step")
+    sim.step(1)
+    d = sim.diagnostics()
+    assert d["error_word"] == 0 and d["status"] == 0
+    eps = 2.0 ** -24 if precision == 32 else 2.0 ** -53
+    gross = 4 * wmax * (abs(sp.q1) + abs(sp.q2)) / (dx ** 3 * grid.dt)
+    ncell = MP_CELLS[0] * MP_CELLS[1] * MP_CELLS[2]
+    assert d["rho_l2"] > 0
+    assert d["div_max"] < 27 * 8 * eps * gross, (d, gross)
+    assert d["div_l2"] / math.sqrt(ncell) < eps * gross, (d, gross)
+    after = [sim.particles_range(sid, s0, SAMPLE_LEN, ids=True) for s0, _, _, _ in ranges]
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+
+    _say(f"case: full-size mixed precision fp{precision}: oracle windows")
+    tol = 2e-5 if precision == 32 else 1e-11
+    worst = {"position (cells)": 0.0, "u1": 0.0, "u2": 0.0, "delta": 0.0}
+    P = (0, 0, 0)  # periodic window (its seams lie beyond every stencil of its particles)
+    for (s0, b, lo, hi), a in zip(ranges, after):
+        assert np.array_equal(a["id"], b["id"]), "a step without a sort kept the storage order"
+        shape = tuple(int(v) for v in hi - lo)
+        wg = dataclasses.replace(grid, n=shape, bc_lo=P, bc_hi=P)
+        o = Oracle(wg, flags=O_FROZEN | O_NODEP)
+        parts = Particles(x=(b["cell"] - lo + b["off"]) * dx, u1=b["u1"], delta=b["delta"],
+                          u2=b["u2"], omega_c=b["omega_c"], weight=b["weight"])
+        osid = o.add_species(sp, parts.n)
+        o.load_particles(osid, parts)
+        o.load_fields(*_fields_from(factors, tuple(int(v) for v in lo), shape, precision == 32))
+        o.step(1)
+        r = o.particles(osid)
+        pos = np.abs((r["cell"] + r["off"]) - (a["cell"] - lo + a["off"])).max()
+        assert pos < (2e-6 if precision == 32 else 1e-11), f"position error {pos:.3e} cells"
+        worst["position (cells)"] = max(worst["position (cells)"], pos)
+        for key in ("u1", "u2", "delta"):
+            worst[key] = max(worst[key], _check(r[key], a[key], tol, key))
+        o.close()
+    _say(f"fp{precision} mixed precision full size ({MP_RANGES} x {SAMPLE_LEN} ions): " +
+         ", ".join(f"{k} {v:.2e}" for k, v in worst.items()) +
+         f"; continuity div_max {d['div_max']:.3e} (bound {27 * 8 * eps * gross:.3e})")
 
 
 def test_full_size_gradient_run(pic):
