@@ -170,7 +170,10 @@ __global__ void __launch_bounds__(SB) k_scatter(const uint32_t* kin, const uint3
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const int bins = 1 << nbits;
   const uint32_t mask = (uint32_t)bins - 1u;
-  for (int d = t; d < bins; d += SB) run[d] = offs[(int64_t)d * nb + blockIdx.x];
+  for (int d = t; d < bins; d += SB) {
+    run[d] = offs[(int64_t)d * nb + blockIdx.x];
+    for (int q = 0; q < SB / 64; q++) wc[q][d] = 0;
+  }
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t base = (int64_t)blockIdx.x * CHUNK;
   // every key (and index) of the chunk loaded before the rounds start
@@ -181,11 +184,15 @@ __global__ void __launch_bounds__(SB) k_scatter(const uint32_t* kin, const uint3
     kv[r] = i < n ? kin[i] : 0u;
     iv[r] = i < n ? (iin ? iin[i] : (uint32_t)i) : 0u;
   }
+  __syncthreads();
+  // Per round: the lowest lane of each group of equal digits in a wavefront
+  // (its leader) posts the group's count in wc[wave][digit]; every key's
+  // place is the digit's running offset, plus the counts of that digit in
+  // the lower wavefronts, plus its rank in its group; then the leaders add
+  // their counts to the running offsets and clear their wc entries, so a
+  // round touches only the digits it holds.
 #pragma unroll
   for (int r = 0; r < ROUNDS; r++) {
-    for (int d = t; d < bins; d += SB)
-      for (int q = 0; q < SB / 64; q++) wc[q][d] = 0;
-    __syncthreads();
     int64_t i = base + (int64_t)r * SB + t;
     bool valid = i < n;
     uint32_t key = kv[r];
@@ -197,8 +204,9 @@ __global__ void __launch_bounds__(SB) k_scatter(const uint32_t* kin, const uint3
       uint64_t bb = __ballot(valid && bit);
       m &= bit ? bb : ~bb;
     }
-    uint32_t rank = (uint32_t)__popcll(m & lt);
-    if (valid && rank == 0) wc[wave][dig] = (uint32_t)__popcll(m);
+    const uint32_t rank = (uint32_t)__popcll(m & lt), cnt = (uint32_t)__popcll(m);
+    const bool leader = valid && rank == 0;
+    if (leader) wc[wave][dig] = cnt;
     __syncthreads();
     uint32_t pos = 0;
     if (valid) {
@@ -206,10 +214,9 @@ __global__ void __launch_bounds__(SB) k_scatter(const uint32_t* kin, const uint3
       for (int q = 0; q < wave; q++) pos += wc[q][dig];
     }
     __syncthreads();
-    for (int d = t; d < bins; d += SB) {
-      uint32_t tot = 0;
-      for (int q = 0; q < SB / 64; q++) tot += wc[q][d];
-      run[d] += tot;
+    if (leader) {
+      atomicAdd(&run[dig], cnt);
+      wc[wave][dig] = 0;
     }
     if (valid) {
       kout[pos] = key;
