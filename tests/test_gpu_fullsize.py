@@ -111,6 +111,9 @@ def test_full_size_sampled_particles_and_continuity(pic, precision):
              for sid in (sid_i, sid_e)}
     species = [meta.species[0][0], meta.species[1][0]]
     sim.close()
+    del sim
+    import torch
+    torch.cuda.empty_cache()  # the next full-size case needs the memory
 
     _say(f"case: full-size fp{precision}: oracle on the sampled particles")
     o = Oracle(grid, flags=O_FROZEN | O_NODEP)
